@@ -1,0 +1,673 @@
+"""Pins of the FP64 oracle against closed forms, invariants, printed values
+and library routines (no GPU).  Every test here would fail for a plausible
+slip in the oracle: a dropped term, a wrong sign or index, a transposed
+operand."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests.helpers import f32, params, world, yaw_quat
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+H = 1.0 / 120.0
+
+PX, PY, PZ, QW, QX, QY, QZ, VX, VY, VZ, WX, WY, WZ = range(13)
+OM0, TH, THD, MU, GX, GY, SX, SY = 13, 17, 18, 19, 20, 21, 22, 23
+ACTIVE, EPSTEP, SINCE, EPISODE = range(4)
+
+
+def mk(O, spawns, prm=None, **kw):
+    p = prm or params()
+    wkw = {k: kw.pop(k) for k in list(kw) if k in ("tris", "road_xy", "road_type", "mu", "mu_ground", "agents")}
+    return O.Oracle(world(spawns, **wkw), p, **kw), p
+
+
+def zeros(n):
+    return np.zeros((n, 2), np.float32)
+
+
+def ell(p):
+    return f32(p["susp_rest"]) + f32(p["wheel_radius"])
+
+
+# ---------------------------------------------------------------- statics
+def test_static_sag(oracle_mod):
+    """After 10 s of settling from 5 cm above ride height every spring
+    carries m g / 4: compression m g / (4 k)."""
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0.3, 300, 0)])
+    f, k = o.get_state()
+    f[PZ, 0] += 0.05
+    o.set_state(f, k)
+    for _ in range(1200):
+        o.step(zeros(1), H, 1)
+    sag = f32(p["mass"]) * f32(p["gravity"]) / (4 * f32(p["susp_k"]))
+    assert abs(sag - 0.105107) < 1e-6
+    for wh in range(4):
+        hit, t, n, s, tri = o.raycast(0, wh)
+        assert hit
+        assert abs((ell(p) - t) - sag) < 1e-9
+
+
+def test_heave_recurrence(oracle_mod):
+    """Pure heave of the symmetric vehicle is the 1-DOF spring-damper under
+    semi-implicit Euler: a linear recurrence in (z, v)."""
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)])
+    f, k = o.get_state()
+    z0 = f[PZ, 0] + 0.03
+    f[PZ, 0] = z0
+    o.set_state(f, k)
+    m, g, kk, c = f32(p["mass"]), f32(p["gravity"]), f32(p["susp_k"]), f32(p["susp_c"])
+    bz = f32(p["mount"][0][2])
+    L = ell(p)
+    M = np.array([[1 - H * H * 4 * kk / m, H * (1 - H * 4 * c / m)],
+                  [-H * 4 * kk / m, 1 - H * 4 * c / m]])
+    # state (z, v): v' = v + h (4 k (L - z - bz) - 4 c v) / m - h g ; z' = z + h v'
+    b = np.array([H * H * (4 * kk * (L - bz) / m - g), H * (4 * kk * (L - bz) / m - g)])
+    s = np.array([z0, 0.0])
+    for n in range(240):
+        o.step(zeros(1), H, 1)
+        s = M @ s + b
+        f, _ = o.get_state()
+        assert abs(f[PZ, 0] - s[0]) < 1e-12, n
+        assert abs(f[VZ, 0] - s[1]) < 1e-11, n
+    assert abs(f[QX, 0]) < 1e-15 and abs(f[QY, 0]) < 1e-15
+
+
+# -------------------------------------------------------- integrator
+def test_free_fall(oracle_mod):
+    """Airborne chassis: z_n = z0 - g h^2 n (n + 1) / 2 under semi-implicit Euler."""
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)])
+    f, k = o.get_state()
+    f[PZ, 0] = 10.0
+    o.set_state(f, k)
+    g = f32(p["gravity"])
+    for n in range(1, 121):
+        o.step(zeros(1), H, 1)
+        f, _ = o.get_state()
+        assert abs(f[PZ, 0] - (10.0 - g * H * H * n * (n + 1) / 2)) < 1e-12
+
+
+def test_yaw_integration_closed_form(oracle_mod):
+    """Spin about the yaw principal axis: the first-order quaternion update
+    followed by normalisation advances yaw by exactly 2 atan(h w / 2)."""
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)])
+    f, k = o.get_state()
+    f[PZ, 0] = 50.0
+    f[WZ, 0] = 1.3
+    o.set_state(f, k)
+    for n in range(1, 200):
+        o.step(zeros(1), H, 1)
+    f, _ = o.get_state()
+    yaw = 2 * math.atan2(f[QZ, 0], f[QW, 0])
+    expect = 2 * (n) * math.atan(H * 1.3 / 2)
+    d = (yaw - expect + math.pi) % (2 * math.pi) - math.pi
+    assert abs(d) < 1e-11
+    assert abs(f[WZ, 0] - 1.3) < 1e-13 and abs(f[WX, 0]) < 1e-15
+
+
+def test_wheel_spin_up_and_brake_lock(oracle_mod):
+    """Airborne wheels: drive spins the front pair at tau h / I_w per step, the
+    rear pair stays still; the Coulomb brake stops a spinning wheel at exactly
+    zero and holds it there."""
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)])
+    f, k = o.get_state()
+    f[PZ, 0] = 100.0
+    o.set_state(f, k)
+    Iw = 0.5 * f32(p["wheel_mass"]) * f32(p["wheel_radius"]) ** 2
+    a = np.array([[1.0, 0.0]], np.float32)
+    for n in range(1, 31):
+        o.step(a, H, 1)
+        f, _ = o.get_state()
+        assert abs(f[OM0, 0] - n * H * f32(p["tau_drive"]) / Iw) < 1e-9
+        assert abs(f[OM0 + 1, 0] - f[OM0, 0]) < 1e-12
+        assert f[OM0 + 2, 0] == 0.0 and f[OM0 + 3, 0] == 0.0
+    f[OM0:OM0 + 4, 0] = 5.0
+    o.set_state(f, k)
+    a = np.array([[-0.5, 0.0]], np.float32)
+    om_f = 5.0
+    for n in range(1, 40):
+        o.step(a, H, 1)
+        f, _ = o.get_state()
+        om_f = max(0.0, om_f - H * 0.5 * f32(p["tau_brake_front"]) / Iw)
+        assert abs(f[OM0, 0] - om_f) < 1e-9
+    assert f[OM0, 0] == 0.0 and f[OM0 + 3, 0] == 0.0
+
+
+# ------------------------------------------------------------ steering
+def _steer_run(O, h_sub, T, target, prm=None):
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)], prm)
+    f, k = o.get_state()
+    f[PZ, 0] = 100.0
+    o.set_state(f, k)
+    S = int(round(H / h_sub))
+    a = np.array([[0.0, target]], np.float32)
+    th = []
+    for _ in range(int(round(T / H))):
+        o.step(a, H, S)
+        f, _ = o.get_state()
+        th.append((f[TH, 0], f[THD, 0]))
+    return np.array(th), p
+
+
+def test_steering_pd_converges_first_order(oracle_mod):
+    """The implicit PD tracks the continuous overdamped response of
+    I th'' + Kd th' + Kp th = Kp th* with first-order error in h, and
+    settles on the target."""
+    O = oracle_mod
+    tgt = f32(0.3)
+    errs = []
+    for S in (1, 2, 4):
+        th, p = _steer_run(O, H / S, 0.25, tgt)
+        I, Kp, Kd = f32(p["steer_inertia"]), f32(p["steer_kp"]), f32(p["steer_kd"])
+        disc = math.sqrt(Kd * Kd - 4 * I * Kp)
+        l1, l2 = (-Kd + disc) / (2 * I), (-Kd - disc) / (2 * I)
+        t = H * np.arange(1, len(th) + 1)
+        exact = tgt * (1 + (l2 * np.exp(l1 * t) - l1 * np.exp(l2 * t)) / (l1 - l2))
+        errs.append(np.max(np.abs(th[:, 0] - exact)))
+    assert 1.6 < errs[0] / errs[1] < 2.4 and 1.6 < errs[1] / errs[2] < 2.4
+    th, _ = _steer_run(O, H, 3.0, tgt)
+    assert abs(th[-1, 0] - tgt) < 1e-9
+
+
+def test_steering_torque_clamp(oracle_mod):
+    """With a stiff loop the clamped torque accelerates the joint at exactly
+    tau_max / I per unit time."""
+    O = oracle_mod
+    prm = params(steer_kp=1e5)
+    th, p = _steer_run(O, H, 5 * H, 0.5, prm)
+    rate = H * f32(p["steer_tau_max"]) / f32(p["steer_inertia"])
+    # two steps of full positive torque, then the loop brakes at full negative torque
+    assert abs(th[0, 1] - rate) < 1e-9 and abs(th[1, 1] - 2 * rate) < 1e-9
+    assert abs(th[2, 1] - rate) < 1e-9
+
+
+# --------------------------------------------------------------- tire
+def test_tire_free_rolling_and_locked(oracle_mod):
+    O = oracle_mod
+    p = params()
+    r = f32(p["wheel_radius"])
+    Fx, Fy, Mz, om = O.tire(p, H, 3000.0, 0.9, 10.0, 0.0, 10.0 / r, 0.0, 0.0)
+    assert abs(Fx) < 1e-9 and Fy == 0.0 and abs(om - 10.0 / r) < 1e-12
+    Fx, Fy, Mz, om = O.tire(p, H, 3000.0, f32(0.9), 20.0, 0.0, 0.0, 0.0, 1e4)
+    assert abs(Fx + f32(0.9) * 3000.0) < 1e-9 and om == 0.0
+    # lateral force opposes lateral slip; aligning moment opposes it
+    Fx, Fy, Mz, om = O.tire(p, H, 3000.0, 0.9, 10.0, 0.2, 10.0 / r, 0.0, 0.0)
+    assert Fy < 0 and Mz > 0
+    assert abs(Fy + f32(p["c_alpha"]) * 3000.0 * 0.2 / 10.0) < 1e-9
+
+
+def test_tire_implicit_equation_and_circle(oracle_mod):
+    """The spin update solves the wheel balance I (W' - W) / h = tau_d - r F_x
+    - tau_b sign(W') (a locked wheel's static brake torque within +-tau_b)
+    and the force never leaves the friction circle."""
+    O = oracle_mod
+    p = params()
+    r = f32(p["wheel_radius"])
+    Iw = 0.5 * f32(p["wheel_mass"]) * r * r
+    rng = np.random.default_rng(7)
+    for _ in range(3000):
+        Fz = rng.uniform(0, 8000)
+        mu = rng.choice([0.0, 0.1, 0.3, 0.6, 0.9, 1.2])
+        vx = rng.uniform(-30, 30) * rng.choice([1.0, 0.02])
+        vy = rng.uniform(-3, 3)
+        W = rng.uniform(-100, 100)
+        td = rng.choice([0.0, rng.uniform(0, 600.7)])
+        tb = rng.choice([0.0, rng.uniform(0, 1090.5)])
+        h = rng.choice([H, H / 4])
+        Fx, Fy, Mz, W1 = O.tire(p, h, Fz, mu, vx, vy, W, td, tb)
+        assert Fx * Fx + Fy * Fy <= (mu * Fz) ** 2 * (1 + 1e-12) + 1e-18
+        lhs = Iw * (W1 - W) / h
+        if W1 != 0.0:
+            assert abs(lhs - (td - r * Fx - tb * np.sign(W1))) < 1e-7 * (1 + abs(lhs) + tb + td)
+        else:
+            assert abs(lhs - (td - r * Fx)) <= tb * (1 + 1e-12) + 1e-7
+        assert abs(Mz + f32(p["trail"]) * Fy) < 1e-12
+
+
+@pytest.mark.parametrize("mu", [0.9, 0.6, 0.3, 0.1])
+def test_locked_wheel_stopping_distance(oracle_mod, mu):
+    """Locked-wheel stop from 20 m/s on a flat plane: the semi-implicit Euler
+    stopping distance v0^2 / (2 mu g) - v0 h / 2 within 0.5 % (pitch and
+    heave transients)."""
+    O = oracle_mod
+    prm = params(tau_brake_front=1e4, tau_brake_rear=1e4, max_episode_steps=10**6)
+    o, p = mk(O, [(0, 0, 0.0, 3000, 0)], prm, mu=mu, invincible=True)  # drift > 100 m is no crash here
+    f, k = o.get_state()
+    v0 = 20.0
+    f[VX, 0] = v0
+    f[OM0:OM0 + 4, 0] = v0 / f32(p["wheel_radius"])
+    o.set_state(f, k)
+    a = np.array([[-1.0, 0.0]], np.float32)
+    for n in range(20000):
+        o.step(a, H, 1)
+        f, _ = o.get_state()
+        if abs(f[VX, 0]) < 1e-4:
+            break
+    g, m = f32(p["gravity"]), f32(mu)
+    closed = v0 * v0 / (2 * m * g) - v0 * H / 2
+    assert abs(f[PX, 0] - closed) / closed < 5e-3
+    assert f[OM0, 0] == 0.0
+
+
+def test_steady_cornering_neutral_steer(oracle_mod):
+    """Symmetric axles with equal cornering stiffness are (nearly) neutral:
+    the steady yaw rate is v delta / L of the linear bicycle model; the
+    pneumatic trail adds a little understeer."""
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0.0, 3000, 0)])
+    f, k = o.get_state()
+    f[VX, 0] = 10.0
+    f[OM0:OM0 + 4, 0] = 10.0 / f32(p["wheel_radius"])
+    o.set_state(f, k)
+    a = np.array([[0.0, 0.02]], np.float32)
+    for _ in range(360):
+        o.step(a, H, 1)
+    f, _ = o.get_state()
+    v = math.hypot(f[VX, 0], f[VY, 0])
+    ratio = f[WZ, 0] / (v * f[TH, 0] / f32(p["wheelbase"]))
+    assert 0.95 < ratio < 1.005, ratio
+
+
+# ----------------------------------------------------------- raycast
+def test_raycast_tilted_triangle_and_ties(oracle_mod):
+    O = oracle_mod
+    # plane z = 0.2 + 0.1 x over a large triangle; the ground lies below it
+    big = 50.0
+    pts = [(-big, -big), (big, -big), (0.0, big)]
+    tri = np.array([[(x, y, 0.2 + 0.1 * x) for x, y in pts]], np.float32)
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)], tris=tri)
+    f, k = o.get_state()
+    f[PZ, 0] = 1.0
+    o.set_state(f, k)
+    hit, t, n, s, ti = o.raycast(0, 0)
+    mx = f32(p["mount"][0][0])
+    zm = 1.0 + f32(p["mount"][0][2])
+    zt = np.float64(np.float32(0.2)) + np.float64(np.float32(0.1)) * mx
+    # vertices are float32: recompute the exact plane through them
+    v = tri[0].astype(np.float64)
+    nrm = np.cross(v[1] - v[0], v[2] - v[0])
+    nrm /= np.linalg.norm(nrm)
+    m = np.array([mx, f32(p["mount"][0][1]), zm])
+    t_exact = np.dot(v[0] - m, nrm) / np.dot(np.array([0, 0, -1.0]), nrm)
+    assert hit and s == 1 and ti == 0
+    assert abs(t - t_exact) < 1e-12 and abs(zt - (zm - t)) < 1e-6
+    assert np.allclose(n, nrm * np.sign(nrm[2]), atol=1e-12)
+    # coplanar road on the ground: the road wins the tie; off the road: ground
+    tri0 = np.zeros((2, 3, 3), np.float32)
+    tri0[0, :, :2] = [(-1, -5), (5, -5), (5, 5)]
+    tri0[1, :, :2] = [(-1, -5), (5, 5), (-1, 5)]
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)], tris=tri0)
+    res = [o.raycast(0, wh) for wh in range(4)]
+    assert [r[3] for r in res] == [1, 1, 0, 0]          # rear wheels at x = -1.3 are off the road
+    assert res[0][4] in (0, 1) and res[2][4] == -1
+    assert all(r[0] for r in res)
+    assert abs(res[0][1] - res[2][1]) < 1e-12
+
+
+# ----------------------------------------------------------- contacts
+def test_circle_model_worked_example(oracle_mod):
+    g = GOLD["circle_model"]
+    r, d = oracle_mod.circle_model(params(length=g["length"], width=g["width"], wheelbase=g["wheelbase"]))
+    assert abs(r - g["r"]) <= g["tol"] and abs(d - g["d"]) <= g["tol"]
+
+
+def _two(O, p0, yaw0, p1, yaw1, **kw):
+    o, p = mk(O, [(p0[0], p0[1], yaw0, 300, 0), (p1[0], p1[1], yaw1, 300, 0)], **kw)
+    f, k = o.get_state()
+    for i, (pp, yw) in enumerate([(p0, yaw0), (p1, yaw1)]):
+        f[PX, i], f[PY, i] = pp
+        f[QW:QZ + 1, i] = yaw_quat(yw)
+    o.set_state(f, k)
+    return o, p
+
+
+def test_contact_predicate_geometry(oracle_mod):
+    """Same heading, nose to tail: the front circle of the rear car touches the
+    rear circle of the front car iff the gap is below 2 d + 2 r (quantised:
+    4546 / 1024 m).  Side by side at 2.1 m only the facing circles touch."""
+    O = oracle_mod
+    o, _ = _two(O, (0, 0), 0.0, (4.43, 0), 0.0)
+    pr = o.detect_pairs(0)
+    assert list(pr) == [0 | (1 << 8) | ((1 << (3 * 2 + 0)) << 16)]
+    o, _ = _two(O, (0, 0), 0.0, (4.45, 0), 0.0)
+    assert len(o.detect_pairs(0)) == 0
+    o, _ = _two(O, (0, 0), 0.0, (0, 2.1), 0.0)
+    pr = o.detect_pairs(0)
+    assert len(pr) == 1 and (pr[0] >> 16) == (1 | 16 | 256)
+    o, _ = _two(O, (0, 0), math.pi / 2, (0, 4.43), math.pi / 2)
+    pr = o.detect_pairs(0)
+    assert len(pr) == 1 and (pr[0] >> 16) == (1 << 6)
+    # an inactive agent takes no part
+    f, k = o.get_state()
+    k[ACTIVE, 1] = 0
+    o.set_state(f, k)
+    assert len(o.detect_pairs(0)) == 0
+
+
+def _momenta(f, p):
+    m = f32(p["mass"])
+    Izz = f32(p["inertia"][2])
+    P = m * f[[VX, VY]].sum(axis=1)
+    L = np.sum(m * (f[PX] * f[VY] - f[PY] * f[VX]) + Izz * f[WZ])
+    KE = np.sum(0.5 * m * (f[VX] ** 2 + f[VY] ** 2) + 0.5 * Izz * f[WZ] ** 2)
+    return P, L, KE
+
+
+def test_headon_collision_common_velocity(oracle_mod):
+    """Frictionless head-on impact of equal masses with e = 0 and no position
+    bias: both end at the common (zero) velocity; momentum stays zero."""
+    O = oracle_mod
+    o, p = _two(O, (-3, 0), 0.0, (3, 0), math.pi, mu=0.0, prm=params(baumgarte=0.0), invincible=True)
+    f, k = o.get_state()
+    f[VX, 0], f[VX, 1] = 5.0, -5.0
+    o.set_state(f, k)
+    hit = False
+    for n in range(60):
+        r, d, e, (rec, cnt) = o.step(zeros(2), H, 1, record_pairs=True)
+        hit |= cnt.sum() > 0
+    f, k = o.get_state()
+    assert hit and np.all(k[ACTIVE] == 1)
+    assert abs(f[VX, 0]) < 1e-9 and abs(f[VX, 1]) < 1e-9
+    assert f[PX, 1] - f[PX, 0] < 6.0     # they met and stayed together
+    P, L, KE = _momenta(f, p)
+    assert np.all(np.abs(P) < 1e-8)
+
+
+def test_glancing_collision_conserves_momentum(oracle_mod):
+    """Frictionless offset impact: planar linear momentum and angular momentum
+    about z are conserved; with no bias kinetic energy does not grow."""
+    O = oracle_mod
+    o, p = _two(O, (-3, 0), 0.0, (3, 1.2), math.pi, mu=0.0, prm=params(baumgarte=0.0), invincible=True)
+    f, k = o.get_state()
+    f[VX, 0], f[VX, 1] = 6.0, -4.0
+    f[VY, 1] = 0.5
+    o.set_state(f, k)
+    P0, L0, KE0 = _momenta(f, p)
+    contacts = 0
+    for n in range(90):
+        r, d, e, (rec, cnt) = o.step(zeros(2), H, 1, record_pairs=True)
+        contacts += int(cnt.sum())
+        f, _ = o.get_state()
+        P, L, KE = _momenta(f, p)
+        scale = f32(p["mass"]) * 10.0
+        assert np.all(np.abs(P - P0) < 1e-12 * scale)
+        assert abs(L - L0) < 1e-11 * scale * 10
+        assert KE <= KE0 * (1 + 1e-12)
+    assert contacts > 0
+    assert abs(f[WZ, 0]) > 1e-3  # the offset impact spun the cars
+
+
+def test_momentum_with_baumgarte(oracle_mod):
+    """The position bias pushes overlapping cars apart with equal and opposite
+    impulses: momentum is still conserved."""
+    O = oracle_mod
+    o, p = _two(O, (0, 0), 0.3, (1.5, 1.0), -0.4, mu=0.0, invincible=True)
+    f, k = o.get_state()
+    P0, L0, _ = _momenta(f, p)
+    for n in range(30):
+        o.step(zeros(2), H, 1)
+    f, _ = o.get_state()
+    P, L, _ = _momenta(f, p)
+    assert np.all(np.abs(P - P0) < 1e-8) and abs(L - L0) < 1e-7
+    assert np.hypot(f[PX, 1] - f[PX, 0], f[PY, 1] - f[PY, 0]) > math.hypot(1.5, 1.0) + 0.05
+
+
+# ------------------------------------------------------ events / rewards
+def _events_case(O, goal_dx=50.0, since=30, ep=0, start_dx=0.0, roll=0.0, second=None, **kw):
+    sp = [(0, 0, 0.0, goal_dx, 0)]
+    if second is not None:
+        sp.append((second, 0, 0.0, 300, 0))
+    o, p = mk(O, sp, **kw)
+    f, k = o.get_state()
+    f[PX, 0], f[PY, 0] = 0.0, 0.0
+    f[GX, 0], f[GY, 0] = goal_dx, 0.0
+    f[SX, 0] = -start_dx
+    f[QW, 0], f[QX, 0] = math.cos(roll / 2), math.sin(roll / 2)
+    k[SINCE, :] = since
+    k[EPSTEP, :] = ep
+    if second is not None:
+        f[PX, 1] = second
+        f[QW, 1], f[QX, 1] = 1.0, 0.0
+    o.set_state(f, k)
+    r, d, e = o.step(zeros(len(sp)), H, 1)
+    return o, r, d, e
+
+
+def test_event_thresholds(oracle_mod):
+    O = oracle_mod
+    G = GOLD["rewards"]
+    _, r, d, e = _events_case(O, goal_dx=2.99)
+    assert e[0] & O.EV_GOAL and r[0] == G["goal"] and d[0] == 1
+    _, r, d, e = _events_case(O, goal_dx=3.01)
+    assert e[0] == 0 and r[0] == 0 and d[0] == 0
+    _, r, d, e = _events_case(O, start_dx=100.02)
+    assert e[0] == O.EV_CRASH and r[0] == G["crash"] and d[0] == 1
+    _, r, d, e = _events_case(O, start_dx=99.9)
+    assert e[0] == 0
+    # tilt: body up-axis z below 0.15
+    _, r, d, e = _events_case(O, roll=math.acos(0.14))
+    assert e[0] & O.EV_CRASH
+    _, r, d, e = _events_case(O, roll=math.acos(0.2))
+    assert not (e[0] & O.EV_CRASH)
+
+
+def test_timeout_and_warmup(oracle_mod):
+    O = oracle_mod
+    T = GOLD["episode"]["max_episode_steps"]
+    W = GOLD["episode"]["collision_warmup"]
+    assert T == 1500 and W == 24
+    _, r, d, e = _events_case(O, ep=T - 1)
+    assert e[0] == O.EV_TIMEOUT and d[0] == 1 and r[0] == 0
+    _, r, d, e = _events_case(O, ep=T - 2)
+    assert e[0] == 0 and d[0] == 0
+    # overlapping pair: suppressed inside the warm-up, collision after it
+    _, r, d, e = _events_case(O, second=3.0, since=W - 1, mu=0.0)
+    assert not (e[0] & O.EV_COLLISION) and d[0] == 0
+    _, r, d, e = _events_case(O, second=3.0, since=W, mu=0.0)
+    assert e[0] & O.EV_COLLISION and r[0] == -6.0 and d[0] == 1
+    # precedence: goal over collision
+    _, r, d, e = _events_case(O, second=3.0, since=W, goal_dx=1.0, mu=0.0)
+    assert e[0] & O.EV_GOAL and e[0] & O.EV_COLLISION and r[0] == 45.0
+
+
+def test_park_and_reset(oracle_mod):
+    """A terminated agent is parked (inactive, zero obs, no reward); reset
+    teleports it back to a spawn entry at ride height with a new episode."""
+    O = oracle_mod
+    o, r, d, e = _events_case(O, goal_dx=1.0)
+    f, k = o.get_state()
+    assert k[ACTIVE, 0] == 0 and f[PX, 0] == 1000.0
+    r, d, e = o.step(zeros(1), H, 1)
+    assert r[0] == 0 and d[0] == 0 and e[0] == 0
+    assert np.all(o.observe()[0] == 0)
+    o.reset(np.array([1], np.uint8))
+    f, k = o.get_state()
+    assert k[ACTIVE, 0] == 1 and k[EPISODE, 0] == 1 and k[EPSTEP, 0] == 0
+    sag = f32(1500) * f32(9.81) / (4 * f32(35000))
+    assert abs(f[PZ, 0] - (ell(params()) - sag + 0.2)) < 1e-6
+
+
+def test_numeric_fault_and_nan_action(oracle_mod):
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0.0, 300, 0), (0, 10, 0.0, 300, 10)])
+    f, k = o.get_state()
+    f[VX, 1] = np.nan
+    o.set_state(f, k)
+    a = np.array([[np.nan, 0.0], [0.0, 0.0]], np.float32)
+    r, d, e = o.step(a, H, 1)
+    assert e[0] == O.EV_NAN_ACTION and d[0] == 0
+    assert e[1] & O.EV_NUMERIC and e[1] & O.EV_CRASH and d[1] == 1
+    f, k = o.get_state()
+    assert np.all(np.isfinite(f[:19]))
+
+
+# ---------------------------------------------------------- observations
+def test_knn_road_known_answer(oracle_mod):
+    O = oracle_mod
+    xs = np.arange(100, dtype=np.float32)
+    road = np.stack([xs, np.zeros_like(xs)], 1)
+    o, p = mk(O, [(50, 0, 0.0, 300, 0)], road_xy=road)
+    f, k = o.get_state()
+    f[PX, 0], f[PY, 0] = 50.0, 0.0
+    f[QW:QZ + 1, 0] = (1, 0, 0, 0)
+    o.set_state(f, k)
+    assert list(o.knn_road(0)) == list(range(18, 82))
+    obs = o.observe()[0]
+    road_feat = obs[8:8 + 192].reshape(64, 3)
+    assert np.allclose(road_feat[:, 0], (np.arange(18, 82) - 50) / 10.0, atol=1e-6)
+    assert np.allclose(road_feat[:, 2], 0.1)
+    # fewer points than slots: all of them, then zero padding
+    o, p = mk(O, [(50, 0, 0.0, 300, 0)], road_xy=road[:10])
+    assert list(o.knn_road(0)) == list(range(10)) + [-1] * 54
+    assert np.all(o.observe()[0, 8 + 30:200] == 0)
+
+
+def test_neighbours_and_ttc(oracle_mod):
+    """Nearest active neighbours in ascending distance; head-on TTC equals
+    (G - 2 d - 2 r) / closing speed, behind and separating give 1."""
+    O = oracle_mod
+    o, p = mk(O, [(0, 0, 0, 300, 0), (30, 0, math.pi, -300, 0), (-12, 0, 0, 300, 0), (0, 20, 0, 300, 0)])
+    f, k = o.get_state()
+    pos = [(0, 0, 0), (30, 0, math.pi), (-12, 0, 0), (0, 20, 0)]
+    for i, (x, y, yw) in enumerate(pos):
+        f[PX, i], f[PY, i] = x, y
+        f[QW:QZ + 1, i] = yaw_quat(yw)
+        f[VX:VZ + 1, i] = 0
+    f[VX, 0], f[VX, 1] = 5.0, -5.0
+    f[VX, 2] = -1.0
+    o.set_state(f, k)
+    assert list(o.knn_neigh(0)) == [2, 3, 1] + [-1] * 5
+    obs = o.observe()[0]
+    nb = obs[200:256].reshape(8, 7)
+    r, d = o.worlds and oracle_mod.circle_model(p)
+    ttc = (30 - 2 * d - 2 * r) / 10.0
+    assert abs(nb[2, 6] - ttc / 10.0) < 1e-6
+    assert nb[0, 6] == 1.0           # behind
+    assert nb[1, 6] == 1.0           # side, no closing
+    assert abs(nb[2, 0] - 0.3) < 1e-6 and abs(abs(nb[2, 4]) - 1.0) < 1e-6
+    assert abs(nb[2, 2] - 0.04) < 1e-7 and abs(nb[2, 3] - 0.02) < 1e-7
+    assert np.all(nb[3:] == 0)
+    # ego block: goal straight ahead at 300 m
+    assert abs(obs[0] - 3.0) < 1e-6 and abs(obs[3] - 1.0) < 1e-6 and abs(obs[5] - 0.5) < 1e-6
+    k[ACTIVE, 2] = 0
+    o.set_state(f, k)
+    assert list(o.knn_neigh(0)) == [3, 1] + [-1] * 6
+
+
+def test_obs_dimension():
+    assert 8 + 64 * 3 + 8 * 7 == 256
+
+
+# --------------------------------------------------------------- weather
+def test_friction_table(oracle_mod):
+    O = oracle_mod
+    g = GOLD["friction_table"]
+    for pav, name in enumerate(["AC", "SMA", "OGFC"]):
+        dry = O.weather_mu(1.0, 0.0, pav)
+        assert dry == 1.0
+        for h, mu in zip(g["film_mm"], g[name]):
+            # class mu equal to the pavement's dry mu reproduces its curve
+            got = O.weather_mu(g[name][0], h, pav)
+            assert abs(got - mu) <= g["tol"], (name, h, got, mu)
+    assert O.weather_mu(0.9, 1.5, 0) == 1e-3
+    assert O.weather_mu(0.9, 0.4, 0) < O.weather_mu(0.9, 0.3, 0)
+
+
+# -------------------------------------------------------------- networks
+def test_mlp_matches_torch_float64(oracle_mod):
+    """Without the bf16 rounding points the oracle's forward pass and MSE
+    gradients are those of a float64 torch MLP (library autograd)."""
+    torch = pytest.importorskip("torch")
+    O = oracle_mod
+    rng = np.random.default_rng(3)
+    sizes = [16, 24, 24, 3]
+    Ws = [(rng.standard_normal((o_, i_)) / math.sqrt(i_)).astype(np.float32) for i_, o_ in zip(sizes[:-1], sizes[1:])]
+    bs = [rng.standard_normal(o_).astype(np.float32) * 0.1 for o_ in sizes[1:]]
+    x = rng.standard_normal((37, 16)).astype(np.float32)
+    t = rng.standard_normal((37, 3)).astype(np.float32)
+    O.set_bf16(False)
+    try:
+        y = O.mlp_forward(Ws, bs, x, act="relu")
+        loss, gW, gb = O.mlp_mse_grad(Ws, bs, x, t)
+        ye = O.mlp_forward(Ws, bs, x, act="elu")
+    finally:
+        O.set_bf16(True)
+    tW = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in Ws]
+    tb = [torch.tensor(b, dtype=torch.float64, requires_grad=True) for b in bs]
+    h = torch.tensor(x, dtype=torch.float64)
+    he = h.clone()
+    for l in range(3):
+        h = torch.nn.functional.linear(h, tW[l], tb[l])
+        he = torch.nn.functional.linear(he, tW[l], tb[l])
+        if l < 2:
+            h = torch.relu(h)
+            he = torch.nn.functional.elu(he)
+    L = torch.mean((h - torch.tensor(t, dtype=torch.float64)) ** 2)
+    L.backward()
+    assert np.allclose(y, h.detach().numpy(), rtol=1e-12, atol=1e-12)
+    assert np.allclose(ye, he.detach().numpy(), rtol=1e-12, atol=1e-12)
+    assert abs(loss - L.item()) < 1e-12
+    for l in range(3):
+        assert np.allclose(gW[l], tW[l].grad.numpy(), rtol=1e-10, atol=1e-13)
+        assert np.allclose(gb[l], tb[l].grad.numpy(), rtol=1e-10, atol=1e-13)
+
+
+def test_mlp_bf16_rounding_points(oracle_mod):
+    """With rounding on, inputs, weights and hidden activations pass through
+    bf16 (torch's round-to-nearest-even cast) and accumulation stays wide."""
+    torch = pytest.importorskip("torch")
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    sizes = [32, 40, 3]
+    Ws = [(rng.standard_normal((o_, i_)) / math.sqrt(i_)).astype(np.float32) for i_, o_ in zip(sizes[:-1], sizes[1:])]
+    bs = [np.zeros(o_, np.float32) for o_ in sizes[1:]]
+    x = rng.standard_normal((11, 32)).astype(np.float32)
+    y = O.mlp_forward(Ws, bs, x, act="relu")
+    bf = lambda a: torch.tensor(a).to(torch.bfloat16).to(torch.float64)
+    h = bf(x)
+    h = torch.relu(h @ bf(Ws[0]).T + torch.tensor(bs[0], dtype=torch.float64))
+    h = h.to(torch.bfloat16).to(torch.float64)
+    h = h @ bf(Ws[1]).T
+    assert np.allclose(y, h.numpy(), rtol=1e-3, atol=1e-3)
+    O.set_bf16(False)
+    try:
+        y2 = O.mlp_forward(Ws, bs, x, act="relu")
+    finally:
+        O.set_bf16(True)
+    assert np.max(np.abs(y - y2)) > 1e-5       # the rounding points are really there
+
+
+def test_adam_matches_torch(oracle_mod):
+    torch = pytest.importorskip("torch")
+    O = oracle_mod
+    rng = np.random.default_rng(9)
+    w = rng.standard_normal(50).astype(np.float32)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    tw = torch.tensor(w.astype(np.float64), requires_grad=True)
+    opt = torch.optim.Adam([tw], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 6):
+        g = rng.standard_normal(50)
+        O.adam(w, g, m, v, step, 1e-3)
+        tw.grad = torch.tensor(g)
+        opt.step()
+        assert np.allclose(w, tw.detach().numpy(), rtol=1e-6, atol=1e-7)
+
+
+def test_policy_head_ranges(oracle_mod):
+    O = oracle_mod
+    from paper_2605_08528_amd import inputs as I
+    Ws, bs = I.mlp_params([256, 256, 256, 2], seed=1)
+    obs = np.random.default_rng(0).standard_normal((5, 256)).astype(np.float32) * 3
+    a = O.policy(Ws, bs, obs, steer_max=0.5)
+    assert np.all(np.abs(a[:, 0]) <= 1) and np.all(np.abs(a[:, 1]) <= 0.5)
+    y = O.mlp_forward(Ws, bs, obs, act="elu")
+    assert np.allclose(a[:, 0], np.tanh(y[:, 0])) and np.allclose(a[:, 1], 0.5 * np.tanh(y[:, 1]))
