@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of the batched driving-physics control step on one MI355X.
+
+A step is one pass of the whole hot path over the workload: policy MLP on
+the current observations, the fused physics step (4 substeps of steering,
+raycast suspension, tire and spin, chassis, vehicle-vehicle contact,
+integration, events, rewards, in-step respawn) and the observation gather.
+The default workload is 256 worlds with 4-32 vehicles each (4096 in total)
+on procedural road grids of 1k-20k points, dt = 1/30 s with 4 substeps.
+
+Prints one JSON line: controlled-agent steps per second (CASPS) over the
+timed steps, the dominant kernel against its roofline (per-kernel HIP events
+on the stream the kernels run on), and the FP64 CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "controlled-agent steps/s @256 worlds×16 agents; plain vs surrogate step"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+# algorithmic bytes per agent and launch ("Measurement")
+STEP_BYTES_PER_AGENT = 2 * 112 + 8 + 6        # state read + write, actions, reward/done/events
+OBS_BYTES_PER_AGENT = 1024 + 64               # observation row write + own state read
+POLICY_FLOP_PER_AGENT = 2 * (256 * 256 * 2 + 256 * 2)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(worlds, prm, dt, S, policy, seconds, max_worlds=16):
+    """The FP64 oracle on the first worlds of the workload: observe -> policy
+    -> step, timed over >= 20 control steps after 2 warm-up steps."""
+    from oracle import oracle as O
+    sub = worlds.world_slice(0, min(max_worlds, worlds.num_worlds))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    orc = O.Oracle(sub, prm, auto_reset=True, threads=threads)
+    Ws, bs = policy
+
+    def one():
+        obs = orc.observe()
+        act = O.policy(Ws, bs, obs, steer_max=prm["steer_max"]).astype(np.float32)
+        orc.step(act, dt, S)
+
+    for _ in range(2):
+        one()
+    t0 = time.perf_counter()
+    n = 0
+    while n < 20 or time.perf_counter() - t0 < seconds:
+        one()
+        n += 1
+        if time.perf_counter() - t0 > 3 * seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": orc.N * n / el, "unit": "controlled-agent steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {sub.num_worlds} worlds ({orc.N} agents) of the same workload, "
+                      f"{n} control steps (observe, policy, step), FP64 brute force"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="uneven256")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--graph-steps", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grid-cell", type=float, default=0.0)
+    ap.add_argument("--obs-waves", type=int, default=0)
+    ap.add_argument("--step-block", type=int, default=0)
+    ap.add_argument("--policy-rows", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step shards by "
+              "world across GPUs but this build measures a single GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_08528_amd import inputs as I, sf
+
+    torch.cuda.set_device(0)
+    worlds = I.workload(args.workload, seed=args.seed)
+    dt, S = I.TIMING[args.workload]
+    prm = dict(I.VEHICLE_DEFAULTS)
+    policy = I.mlp_params([256, 256, 256, 2], seed=args.seed)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = sf.Sim(worlds, prm, flags=sf.SF_AUTO_RESET, stream=stream, grid_cell=args.grid_cell,
+                     obs_waves=args.obs_waves, step_block=args.step_block,
+                     policy_rows=args.policy_rows)
+        sim.policy_load(*policy)
+        N = sim.N
+        log(f"workload {args.workload}: {worlds.num_worlds} worlds, {N} agents, "
+            f"{len(worlds.road_xy)} road points, {len(worlds.tri_verts)} triangles")
+        for _ in range(args.warmup):
+            sim.step_policy(dt, S)
+        torch.cuda.synchronize()
+
+        # ---- timed region: K policy-driven control steps, per-kernel events
+        sim.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            sim.step_policy(dt, S)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        prof = sim.profile_read()
+        sim.profile(False)
+        f, k = sim.get_state()
+        active = int(k[0].sum())
+        value = N * args.steps / (ms / 1e3)
+        log(f"eager: {ms / args.steps:.4f} ms/step, {value:.4g} CASPS, active {active}/{N}")
+
+        # ---- graph replay of the same step (context)
+        graph = None
+        if args.graph_steps > 0:
+            G = args.graph_steps
+            sim.graph_capture(G, dt, S)
+            for _ in range(2):
+                sim.graph_launch()
+            torch.cuda.synchronize()
+            reps = max(1, args.steps // G)
+            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            g0.record(stream)
+            for _ in range(reps):
+                sim.graph_launch()
+            g1.record(stream)
+            torch.cuda.synchronize()
+            gms = g0.elapsed_time(g1)
+            graph = {"casps": N * G * reps / (gms / 1e3), "ms_per_step": gms / (G * reps),
+                     "control_steps_per_graph": G, "replays": reps}
+            log(f"graph: {gms / (G * reps):.4f} ms/step, {graph['casps']:.4g} CASPS")
+
+    kernels = {}
+    for name, (tot, cnt) in prof.items():
+        if cnt:
+            kernels[name] = {"avg_us": 1e3 * tot / cnt, "launches": cnt}
+    dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
+    avg_s = kernels[dom]["avg_us"] * 1e-6
+    if dom == "policy":
+        flop = POLICY_FLOP_PER_AGENT * N
+        roof = {"bound": "mfma", "achieved": flop / avg_s / 1e12, "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "traffic": None}
+    else:
+        per = STEP_BYTES_PER_AGENT if dom == "step" else OBS_BYTES_PER_AGENT
+        roof = {"bound": "hbm", "achieved": per * N / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = {"policy": "k_policy", "step": "k_step", "obs": "k_obs"}[dom]
+    for name in kernels:
+        if name == "policy":
+            kernels[name]["tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
+        elif name in ("step", "obs"):
+            per = STEP_BYTES_PER_AGENT if name == "step" else OBS_BYTES_PER_AGENT
+            kernels[name]["algorithmic_gbs"] = per * N / (kernels[name]["avg_us"] * 1e-6) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(worlds, prm, float(np.float32(dt)), S, policy, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.4g} CASPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "controlled-agent steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {worlds.num_worlds} worlds, {N} agents "
+                        f"({int(np.diff(worlds.agent_offsets).min())}-{int(np.diff(worlds.agent_offsets).max())} per world), "
+                        f"{len(worlds.road_xy)} road points, dt {dt:.4f} s x {S} substeps, "
+                        "plain tire, policy MLP 256-256-256-2 bf16/fp32-acc",
+            "step": "policy + physics step + observation (eager launches)",
+            "active_agents": active,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "graph": graph,
+        "surrogate": None,
+        "paper_context": {"casps": 19250, "hardware": "RTX PRO 6000 Blackwell, PhysX, 256x16"},
+    }
+    print(json.dumps(out))
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,259 @@
+/*
+ * sf.h -- C ABI of the MI355X-native batched driving-physics step.
+ *
+ * The method (SceneFactory, arXiv 2605.08528, Sec. "Simulator Design" and
+ * Algorithm "SceneFactory Pipeline") runs many independent driving worlds,
+ * each holding several vehicles, and advances all of them together: every
+ * 30 Hz control tick applies the policy's actions, steps vehicle physics at
+ * 120 Hz (4 substeps), then computes rewards, terminations and resets and
+ * gathers the next observations.  This library performs that step on one
+ * gfx950 GPU with hand-written HIP kernels.
+ *
+ * Conventions shared by every call
+ *   - Every function returns sf_status; nothing throws across the ABI.  On
+ *     an error the thread-local message of sf_last_error() says why.
+ *   - Host arrays handed to sf_create are copied; the caller keeps them.
+ *   - Device pointers handed to sf_step / sf_observe / sf_reset belong to
+ *     the caller, must live on the same GPU and must stay valid until the
+ *     stream given in sf_options has passed the call.  All device work is
+ *     enqueued asynchronously on that stream (NULL = the null stream).
+ *   - A HIP runtime error turns the handle into SF_E_DEVICE; every later
+ *     call on that handle returns SF_E_BAD_STATE.
+ *   - Agent n belongs to world w iff agent_offsets[w] <= n <
+ *     agent_offsets[w+1]; world-local indices count from agent_offsets[w].
+ *   - Units SI; world frame z up with the ground plane at z = 0 (the paper
+ *     flattens every road to z = 0, Sec. "Z-flattening"); body frame x
+ *     forward, y left, z up; quaternions (w, x, y, z) rotate body -> world.
+ *   - A handle is thread-compatible, not thread-safe: one thread at a time.
+ */
+#ifndef SF_H
+#define SF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sf_sim sf_sim;
+
+typedef enum {
+    SF_OK = 0,
+    SF_E_INVALID_ARG = 1,   /* bad pointer, size, shape or value            */
+    SF_E_OUT_OF_MEMORY = 2, /* device allocation failed                     */
+    SF_E_DEVICE = 3,        /* a HIP call failed (handle is now unusable)   */
+    SF_E_BAD_STATE = 4,     /* handle unusable after an earlier device error */
+    SF_E_UNSUPPORTED = 5    /* request outside the supported limits         */
+} sf_status;
+
+/* limits */
+#define SF_MAX_AGENTS_PER_WORLD 64  /* vehicles in one world                 */
+#define SF_MAX_SURFACES 16          /* friction surfaces per world           */
+#define SF_MAX_SUBSTEPS 16          /* physics substeps per control step     */
+#define SF_MAX_ROAD_POINTS_PER_WORLD (1 << 20)
+
+/* observation layout (floats per agent), see sf_observe */
+#define SF_OBS_DIM 256
+#define SF_OBS_ROAD_K 64
+#define SF_OBS_NEIGH_K 8
+
+/* event bits of sf_observe's events array */
+#define SF_EV_GOAL 1u        /* within 3 m of the goal                      */
+#define SF_EV_COLLISION 2u   /* vehicle-vehicle overlap after the warm-up    */
+#define SF_EV_CRASH 4u       /* below ground, > 100 m drift, or tilted over  */
+#define SF_EV_TIMEOUT 8u     /* episode reached max_episode_steps            */
+#define SF_EV_NUMERIC 16u    /* non-finite state (also sets SF_EV_CRASH)     */
+#define SF_EV_NAN_ACTION 32u /* a NaN action was replaced by 0               */
+
+/* sf_options.flags */
+#define SF_INVINCIBLE 1u       /* events are reported but do not terminate   */
+#define SF_AUTO_RESET 2u       /* done agents respawn at the end of the step */
+#define SF_RECORD_CONTACTS 4u  /* keep each substep's contact-pair lists     */
+
+/* per-agent state fields, [field][agent] float32 then [ifield][agent] int32
+ * (the layout of sf_get_state / sf_set_state) */
+enum {
+    SF_F_PX, SF_F_PY, SF_F_PZ,                 /* CoM position             */
+    SF_F_QW, SF_F_QX, SF_F_QY, SF_F_QZ,        /* orientation              */
+    SF_F_VX, SF_F_VY, SF_F_VZ,                 /* CoM velocity (world)     */
+    SF_F_WX, SF_F_WY, SF_F_WZ,                 /* angular velocity (world) */
+    SF_F_OM0, SF_F_OM1, SF_F_OM2, SF_F_OM3,    /* wheel spin FL FR RL RR   */
+    SF_F_STEER, SF_F_STEER_RATE,               /* steering joint           */
+    SF_F_MU,                                   /* mean wheel friction seen */
+    SF_F_GOAL_X, SF_F_GOAL_Y, SF_F_START_X, SF_F_START_Y,
+    SF_NUM_FFIELDS
+};
+enum { SF_I_ACTIVE, SF_I_EP_STEP, SF_I_SINCE_SPAWN, SF_I_EPISODE, SF_NUM_IFIELDS };
+
+/* Vehicle and solver parameters (all vehicles share them).  sf_default_params
+ * fills the configured vehicle; zero-valued derived fields are derived. */
+typedef struct {
+    float mass;                 /* chassis mass [kg]                          */
+    float inertia[3];           /* body inertia (roll, pitch, yaw) [kg m^2]   */
+    float wheel_radius;         /* [m]                                        */
+    float wheel_mass;           /* [kg]                                       */
+    float wheel_inertia;        /* spin inertia [kg m^2]; 0 -> solid disc     */
+    float susp_k;               /* spring rate per corner [N/m]               */
+    float susp_c;               /* damper rate per corner [N s/m]             */
+    float susp_rest;            /* spring rest length [m]; ray = rest + r_w   */
+    float mount[4][3];          /* wheel mounts in the body frame FL FR RL RR */
+    float length, width, wheelbase; /* [m], the three-circle shape          */
+    float tau_drive;            /* front-wheel drive torque at +1 [N m]       */
+    float tau_brake_front;      /* brake torque per front wheel at -1 [N m]   */
+    float tau_brake_rear;       /* brake torque per rear wheel at -1 [N m]    */
+    float steer_kp, steer_kd;   /* steering PD gains (Eq. steer PD)           */
+    float steer_tau_max;        /* steering torque clamp [N m]                */
+    float steer_inertia;        /* steering joint inertia [kg m^2]            */
+    float steer_max;            /* steering target clamp [rad]                */
+    float c_kappa;              /* longitudinal slip stiffness / load         */
+    float c_alpha;              /* lateral slip stiffness / load              */
+    float v_eps;                /* slip speed floor [m/s]                     */
+    float trail;                /* pneumatic trail [m]                        */
+    float yaw_damping;          /* chassis yaw damping [N m s]                */
+    float gravity;              /* [m/s^2]                                    */
+    int32_t jacobi_iters;       /* contact solver sweeps                      */
+    float baumgarte;            /* contact position correction factor         */
+    float slop;                 /* allowed penetration [m]                    */
+} sf_vehicle_params;
+
+/* Worlds, roads and spawn tables (host arrays; copied by sf_create).
+ * CSR offsets are [num_worlds + 1] with offsets[0] = 0. */
+typedef struct {
+    int32_t num_worlds;
+    const int32_t *agent_offsets;  /* vehicles per world                      */
+    const int32_t *road_offsets;   /* road polyline points per world          */
+    const float *road_xy;          /* [P][2] world-local point positions      */
+    const uint8_t *road_type;      /* [P] polyline type code                  */
+    const int32_t *tri_offsets;    /* road mesh triangles per world           */
+    const float *tri_verts;        /* [T][3][3] vertices (x, y, z)            */
+    const uint8_t *tri_surface;    /* [T] surface id, 1..num_surfaces-1       */
+    int32_t num_surfaces;          /* surface 0 is the ground plane           */
+    const float *mu_class;         /* [W][num_surfaces] dry friction class    */
+    const float *film_mm;          /* [W] water film depth [mm] or NULL (dry) */
+    const uint8_t *pavement;       /* [W] 0 AC, 1 SMA, 2 OGFC or NULL (AC)    */
+    const int32_t *spawn_offsets;  /* spawn entries per world (>= 1 if agents)*/
+    const float *spawn;            /* [E][5] x, y, yaw, goal_x, goal_y        */
+    uint64_t seed;                 /* spawn-entry rotation seed               */
+} sf_world_desc;
+
+typedef void *(*sf_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*sf_free_fn)(void *ptr, void *ctx);
+
+typedef struct {
+    void *stream;               /* hipStream_t for all device work            */
+    sf_alloc_fn alloc;          /* device allocator (NULL -> hipMalloc)       */
+    sf_free_fn free;
+    void *alloc_ctx;
+    int32_t max_episode_steps;  /* timeout (1500 = 50 s at 30 Hz)             */
+    int32_t collision_warmup;   /* control steps without collision events    */
+    uint32_t flags;             /* SF_INVINCIBLE | SF_AUTO_RESET | ...        */
+    float grid_cell;            /* road grid cell size [m]; 0 -> default      */
+    int32_t step_block;         /* threads per world in the step; 0 -> auto   */
+    int32_t obs_waves;          /* agents (waves) per block in the obs kernel */
+    int32_t policy_rows;        /* agents per block in the policy MLP (32/64) */
+    int32_t reserved[5];
+} sf_options;
+
+/* Fill the configured vehicle / default options. */
+sf_status sf_default_params(sf_vehicle_params *p);
+sf_status sf_default_options(sf_options *o);
+
+/* Create W worlds (Algorithm "SceneFactory Pipeline", environment
+ * instantiation): copies roads and spawn tables to the device, computes the
+ * friction table (Sec. "Weather-to-Friction Module"), builds each world's
+ * road grid, spawns every agent (episode 0) and computes the first
+ * observation.  Synchronises the stream once.  *out receives the handle. */
+sf_status sf_create(const sf_world_desc *desc, const sf_vehicle_params *params,
+                    const sf_options *opts, sf_sim **out);
+sf_status sf_destroy(sf_sim *sim);
+
+/* Sizes of the handle's problem. */
+sf_status sf_info(const sf_sim *sim, int32_t *num_worlds, int32_t *num_agents,
+                  int32_t *max_agents_per_world);
+
+/* One control step (Algorithm "SceneFactory Pipeline": act, step physics,
+ * reward, reset): d_actions is [N][2] device float32, (a_long, steer):
+ * a_long in [-1, 1] drives the front wheels when positive and brakes all four
+ * when negative (Sec. "Action Space Details"); steer is the steering target
+ * in rad, clamped to +-steer_max.  dt is the control interval, split into
+ * `substeps` equal physics substeps (1..SF_MAX_SUBSTEPS).  Rewards, done
+ * flags, events and the next observation are left in the handle's output
+ * buffers (sf_observe / sf_output_ptrs). */
+sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substeps);
+
+/* Copy the last step's outputs to caller device buffers (any may be NULL):
+ * obs [N][256] float (ego 8 | 64 road points x 3 | 8 neighbours x 7, body
+ * frame, Sec. "Observation Space Details"), reward [N] float, done [N] u8,
+ * events [N] u8 (SF_EV_* bits). */
+sf_status sf_observe(sf_sim *sim, float *d_obs, float *d_reward, uint8_t *d_done,
+                     uint8_t *d_events);
+/* Device pointers of the handle's own output buffers (valid until destroy). */
+sf_status sf_output_ptrs(sf_sim *sim, float **obs, float **reward, uint8_t **done,
+                         uint8_t **events);
+
+/* Teleport reset (Sec. "Teleport-only reset"): agents whose d_mask byte is
+ * non-zero start a new episode at a spawn entry of their world at rest;
+ * their observation rows are recomputed.  d_mask is [N] device u8. */
+sf_status sf_reset(sf_sim *sim, const uint8_t *d_mask);
+
+/* State snapshot / restore through host memory (synchronous).  The layout is
+ * [SF_NUM_FFIELDS][N] float32 followed by [SF_NUM_IFIELDS][N] int32;
+ * bytes must equal sf_state_bytes(). */
+size_t sf_state_bytes(const sf_sim *sim);
+sf_status sf_get_state(sf_sim *sim, void *host_dst, size_t bytes);
+sf_status sf_set_state(sf_sim *sim, const void *host_src, size_t bytes);
+
+/* Contact pairs of one substep of the last step (needs SF_RECORD_CONTACTS):
+ * h_counts [W] pairs per world, h_pairs [W][cap] packed pairs
+ * i | j << 8 | mask << 16 (i < j world-local, mask bit 3a + b: circle a of i
+ * against circle b of j, circles 0 rear, 1 centre, 2 front), in (i, j) order.
+ * Synchronous.  cap must be >= A(A-1)/2 for the largest world. */
+sf_status sf_get_contacts(sf_sim *sim, int32_t substep, int32_t *h_counts,
+                          uint32_t *h_pairs, int32_t cap);
+
+/* Test surface: raycast every wheel on the current state.  h_out is
+ * [N][4][4] float: hit (0/1), distance t, surface id, triangle index (-1 =
+ * ground).  Synchronous. */
+sf_status sf_debug_raycast(sf_sim *sim, float *h_out);
+/* Test surface: the indices behind the last observation, [N][72] int32:
+ * 64 world-local road point indices (index order) then 8 world-local
+ * neighbour indices (nearest first), -1 where empty.  Synchronous. */
+sf_status sf_debug_obs_indices(sf_sim *sim, int32_t *h_out);
+
+/* ---- on-device policy (Algorithm "SceneFactory Pipeline": a_t = pi(o_t))
+ * A 256 -> 256 -> 256 -> 2 MLP with ELU hidden layers (Sec. "Network
+ * Architecture Details" uses ELU) and tanh outputs scaled to (a_long,
+ * steer_max * steer); bf16 inputs/weights, fp32 accumulation.
+ * h_params: float32 host array W1[256][256] b1[256] W2[256][256] b2[256]
+ * W3[2][256] b3[2] (row-major [out][in]); n must be SF_POLICY_PARAMS. */
+#define SF_POLICY_PARAMS 132098
+sf_status sf_policy_load(sf_sim *sim, const float *h_params, size_t n);
+/* Actions [N][2] (device float32) from the handle's current observation. */
+sf_status sf_policy_act(sf_sim *sim, float *d_actions);
+/* One full control step driven by the loaded policy: policy(obs) -> step
+ * -> observation (actions kept in the handle). */
+sf_status sf_step_policy(sf_sim *sim, float dt, int32_t substeps);
+
+/* ---- HIP graph of K policy-driven control steps on the handle's stream
+ * (the stream must not be the null stream).  Replays enqueue the same
+ * kernels with the same arguments; resets happen inside the step
+ * (SF_AUTO_RESET), so no host decision is needed between steps. */
+sf_status sf_graph_capture(sf_sim *sim, int32_t control_steps, float dt, int32_t substeps);
+sf_status sf_graph_launch(sf_sim *sim);
+
+/* ---- per-kernel timing of eagerly enqueued work (hipEvents on the
+ * handle's stream).  sf_profile(sim, 1) starts (and clears) the record;
+ * sf_profile_read synchronises and returns total milliseconds and launch
+ * counts per kernel: [0] policy, [1] step, [2] observation, [3] reset. */
+#define SF_PROF_KERNELS 4
+sf_status sf_profile(sf_sim *sim, int32_t enable);
+sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches);
+
+const char *sf_status_str(sf_status s);
+const char *sf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SF_H */

@@ -1,0 +1,324 @@
+// Create-time kernels: friction table, road quantisation, triangle records,
+// per-world bounding boxes and the per-world uniform road grid (counting
+// sort: count -> exclusive scan -> scatter -> per-cell order by index).
+#include "sf_dev.h"
+
+// ---------------------------------------------------------------- friction
+// Effective static mu against water film depth at 13.89 m/s for the three
+// pavements (AC, SMA, OGFC), the paper's curves of Sec. "Weather-to-Friction
+// Model Details" sampled at 0.1 mm from 0 to 0.8 mm.
+__constant__ float c_mu_curve[3][9] = {
+    {1.1048f, 1.0657f, 1.0161f, 0.9593f, 0.9039f, 0.8595f, 0.8302f, 0.8134f, 0.8044f},
+    {1.2043f, 1.1618f, 1.1078f, 1.0461f, 0.9857f, 0.9374f, 0.9056f, 0.8874f, 0.8776f},
+    {1.3368f, 1.2898f, 1.2301f, 1.1617f, 1.0948f, 1.0413f, 1.0061f, 0.9860f, 0.9753f}};
+
+// Friction after rain: the class mu scaled by the pavement curve relative
+// to its dry value; linear between samples, falling linearly to zero
+// between 0.8 mm and full hydroplaning at 1 mm; floor 1e-3 (Sec. "Weather-
+// to-Friction Module").  Computed in double: a create-time table.
+__device__ double curve_ratio(int pav, double h) {
+    const float *c = c_mu_curve[(pav >= 0 && pav < 3) ? pav : 0];
+    double v;
+    if (!(h > 0.0)) v = c[0];
+    else if (h >= 1.0) v = 0.0;
+    else if (h > 0.8) v = (double)c[8] * (1.0 - h) * 5.0;
+    else {
+        double x = h * 10.0;
+        int i = (int)floor(x);
+        if (i > 7) i = 7;
+        double a = x - i;
+        v = (double)c[i] + ((double)c[i + 1] - (double)c[i]) * a;
+    }
+    return v / (double)c[0];
+}
+
+__global__ void k_weather_mu(const float *mu_class, const float *film, const uint8_t *pav, int W,
+                             int S, float *mu) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= W * S) return;
+    int w = k / S;
+    double h = film ? (double)film[w] : 0.0;
+    double m = mu_class[k];
+    if (h > 0.0) {
+        m *= curve_ratio(pav ? pav[w] : 0, h);
+        if (m < 1e-3) m = 1e-3;
+    }
+    mu[k] = (float)m;
+}
+
+void launch_weather_mu(const float *mu_class, const float *film, const uint8_t *pav, int W, int S,
+                       float *mu_out, hipStream_t st) {
+    int n = W * S;
+    if (n == 0) return;
+    k_weather_mu<<<(n + 255) / 256, 256, 0, st>>>(mu_class, film, pav, W, S, mu_out);
+}
+
+// ------------------------------------------------------------ road points
+__global__ void k_quantise_roads(const float2 *xy, int2 *q, int P) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    float2 p = xy[k];
+    q[k] = make_int2(qpos(p.x), qpos(p.y));
+}
+
+void launch_quantise_roads(const float2 *xy, int2 *q, int P, hipStream_t st) {
+    if (P == 0) return;
+    k_quantise_roads<<<(P + 255) / 256, 256, 0, st>>>(xy, q, P);
+}
+
+// -------------------------------------------------------------- triangles
+// (v0, surface) (e1) (e2) (unit normal of e1 x e2) for Moller-Trumbore
+__global__ void k_prep_tris(const float *v, const uint8_t *surf, float4 *tri, int T) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= T) return;
+    const float *p = v + 9 * (size_t)k;
+    f3 a = mk3(p[0], p[1], p[2]);
+    f3 e1 = sub3(mk3(p[3], p[4], p[5]), a);
+    f3 e2 = sub3(mk3(p[6], p[7], p[8]), a);
+    f3 n = cross3(e1, e2);
+    float L = sqrtf(dot3(n, n));
+    n = L > 0.f ? mul3(n, 1.f / L) : mk3(0.f, 0.f, 1.f);
+    tri[4 * (size_t)k + 0] = make_float4(a.x, a.y, a.z, (float)surf[k]);
+    tri[4 * (size_t)k + 1] = make_float4(e1.x, e1.y, e1.z, 0.f);
+    tri[4 * (size_t)k + 2] = make_float4(e2.x, e2.y, e2.z, 0.f);
+    tri[4 * (size_t)k + 3] = make_float4(n.x, n.y, n.z, 0.f);
+}
+
+void launch_prep_tris(const float *verts, const uint8_t *surf, float4 *tri, int T, hipStream_t st) {
+    if (T == 0) return;
+    k_prep_tris<<<(T + 255) / 256, 256, 0, st>>>(verts, surf, tri, T);
+}
+
+// ------------------------------------------------------------ world bbox
+__global__ __launch_bounds__(256) void k_world_bbox(const int *roff, const float2 *xy,
+                                                    const int *toff, const float *verts,
+                                                    float4 *bbox) {
+    int w = blockIdx.x;
+    float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+    for (int k = roff[w] + threadIdx.x; k < roff[w + 1]; k += blockDim.x) {
+        float2 p = xy[k];
+        x0 = fminf(x0, p.x); x1 = fmaxf(x1, p.x);
+        y0 = fminf(y0, p.y); y1 = fmaxf(y1, p.y);
+    }
+    for (int k = toff[w] + threadIdx.x; k < toff[w + 1]; k += blockDim.x)
+        for (int c = 0; c < 3; ++c) {
+            float px = verts[9 * (size_t)k + 3 * c], py = verts[9 * (size_t)k + 3 * c + 1];
+            x0 = fminf(x0, px); x1 = fmaxf(x1, px);
+            y0 = fminf(y0, py); y1 = fmaxf(y1, py);
+        }
+    __shared__ float s[4][256];
+    s[0][threadIdx.x] = x0; s[1][threadIdx.x] = y0; s[2][threadIdx.x] = x1; s[3][threadIdx.x] = y1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s[0][threadIdx.x] = fminf(s[0][threadIdx.x], s[0][threadIdx.x + o]);
+            s[1][threadIdx.x] = fminf(s[1][threadIdx.x], s[1][threadIdx.x + o]);
+            s[2][threadIdx.x] = fmaxf(s[2][threadIdx.x], s[2][threadIdx.x + o]);
+            s[3][threadIdx.x] = fmaxf(s[3][threadIdx.x], s[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bbox[w] = make_float4(s[0][0], s[1][0], s[2][0], s[3][0]);
+}
+
+void launch_world_bbox(const int *roff, const float2 *xy, const int *toff, const float *verts, int W,
+                       float4 *bbox, hipStream_t st) {
+    if (W == 0) return;
+    k_world_bbox<<<W, 256, 0, st>>>(roff, xy, toff, verts, bbox);
+}
+
+// ------------------------------------------------------------------- grid
+__device__ __forceinline__ int cell_x(const GridHdr &g, float x) {
+    int c = (int)floorf((x - g.x0) * g.inv_cell);
+    return c < 0 ? 0 : (c >= g.nx ? g.nx - 1 : c);
+}
+__device__ __forceinline__ int cell_y(const GridHdr &g, float y) {
+    int c = (int)floorf((y - g.y0) * g.inv_cell);
+    return c < 0 ? 0 : (c >= g.ny ? g.ny - 1 : c);
+}
+
+// mode 0: count, mode 1: scatter through cursors
+template <int MODE>
+__global__ void k_grid_tris(DevWorld Wd, const float *verts, int T, int *cnt_or_cursor, int *items) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= T) return;
+    // world of triangle k: binary search over tri offsets
+    int lo = 0, hi = Wd.W - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (Wd.toff[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    int w = lo;
+    GridHdr g = Wd.grid[w];
+    const float *p = verts + 9 * (size_t)k;
+    float xa = fminf(p[0], fminf(p[3], p[6])), xb = fmaxf(p[0], fmaxf(p[3], p[6]));
+    float ya = fminf(p[1], fminf(p[4], p[7])), yb = fmaxf(p[1], fmaxf(p[4], p[7]));
+    int cx0 = cell_x(g, xa), cx1 = cell_x(g, xb), cy0 = cell_y(g, ya), cy1 = cell_y(g, yb);
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            int c = g.cbase + cy * g.nx + cx;
+            if (MODE == 0) atomicAdd(&cnt_or_cursor[c], 1);
+            else items[atomicAdd(&cnt_or_cursor[c], 1)] = k - Wd.toff[w];
+        }
+}
+
+template <int MODE>
+__global__ void k_grid_pts(DevWorld Wd, int P, int *cnt_or_cursor, int *items) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    int lo = 0, hi = Wd.W - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (Wd.roff[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    int w = lo;
+    GridHdr g = Wd.grid[w];
+    float2 p = Wd.road_xy[k];
+    int c = g.cbase + cell_y(g, p.y) * g.nx + cell_x(g, p.x);
+    if (MODE == 0) atomicAdd(&cnt_or_cursor[c], 1);
+    else items[atomicAdd(&cnt_or_cursor[c], 1)] = k - Wd.roff[w];
+}
+
+void launch_grid_count(const DevWorld &Wd, const float *verts, int *tri_cnt, int *pt_cnt,
+                       hipStream_t st) {
+    int T = 0, P = 0;
+    (void)hipMemcpyAsync(&T, Wd.toff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(&P, Wd.roff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    if (T) k_grid_tris<0><<<(T + 255) / 256, 256, 0, st>>>(Wd, verts, T, tri_cnt, nullptr);
+    if (P) k_grid_pts<0><<<(P + 255) / 256, 256, 0, st>>>(Wd, P, pt_cnt, nullptr);
+}
+
+void launch_grid_fill(const DevWorld &Wd, const float *verts, int *tri_cursor, int *pt_cursor,
+                      int *tri_items, int *pt_items, hipStream_t st) {
+    int T = 0, P = 0;
+    (void)hipMemcpyAsync(&T, Wd.toff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(&P, Wd.roff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    if (T) k_grid_tris<1><<<(T + 255) / 256, 256, 0, st>>>(Wd, verts, T, tri_cursor, tri_items);
+    if (P) k_grid_pts<1><<<(P + 255) / 256, 256, 0, st>>>(Wd, P, pt_cursor, pt_items);
+}
+
+// order each cell's items by index (the scatter order is not deterministic)
+__global__ void k_cell_sort(const int *start, int C, int *items) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int a = start[c], b = start[c + 1];
+    for (int i = a + 1; i < b; ++i) {
+        int v = items[i], j = i - 1;
+        while (j >= a && items[j] > v) { items[j + 1] = items[j]; --j; }
+        items[j + 1] = v;
+    }
+}
+
+__global__ void k_pack_pts(DevWorld Wd, int C, const int *pt_items, int4 *pt_cell) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    // world of cell c
+    int lo = 0, hi = Wd.W - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (Wd.grid[mid].cbase <= c) lo = mid; else hi = mid - 1;
+    }
+    int r0 = Wd.roff[lo];
+    for (int k = Wd.pt_cell_start[c]; k < Wd.pt_cell_start[c + 1]; ++k) {
+        int idx = pt_items[k];
+        int2 q = Wd.road_q[r0 + idx];
+        pt_cell[k] = make_int4(q.x, q.y, idx, 0);
+    }
+}
+
+void launch_grid_finish(const DevWorld &Wd, int C, int *tri_items, int *pt_items, int4 *pt_cell,
+                        hipStream_t st) {
+    if (C == 0) return;
+    k_cell_sort<<<(C + 255) / 256, 256, 0, st>>>(Wd.tri_cell_start, C, tri_items);
+    k_cell_sort<<<(C + 255) / 256, 256, 0, st>>>(Wd.pt_cell_start, C, pt_items);
+    k_pack_pts<<<(C + 255) / 256, 256, 0, st>>>(Wd, C, pt_items, pt_cell);
+}
+
+// ------------------------------------------------------------------- scan
+// exclusive prefix sum of n ints into out[0..n] (out[n] = total), three
+// passes: per-block scan, scan of block totals, add block offsets
+#define SCAN_BLOCK 256
+#define SCAN_ITEMS 4
+
+__device__ int block_scan_excl(int v, int *s, int &total) {
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s[wv] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+        if (k < wv) base += s[k];
+        tot += s[k];
+    }
+    __syncthreads();
+    total = tot;
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_local(const int *in, int *out, int n, int *bsum) {
+    __shared__ int s[SCAN_BLOCK / 64];
+    int base = blockIdx.x * SCAN_BLOCK * SCAN_ITEMS + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS], sum = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        sum += v[k];
+    }
+    int tot;
+    int pre = block_scan_excl(sum, s, tot);
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = pre;
+        pre += v[k];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_blocks(int *bsum, int nb, int *total_out) {
+    __shared__ int s[SCAN_BLOCK / 64];
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += SCAN_BLOCK) {
+        int k = b0 + threadIdx.x;
+        int v = k < nb ? bsum[k] : 0;
+        int tot;
+        int pre = block_scan_excl(v, s, tot);
+        if (k < nb) bsum[k] = pre + carry;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_add(int *out, int n, const int *bsum) {
+    int base = blockIdx.x * SCAN_BLOCK * SCAN_ITEMS + threadIdx.x * SCAN_ITEMS;
+    int add = bsum[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) out[base + k] += add;
+}
+
+void launch_scan(const int *in, int *out, int n, int *tmp, hipStream_t st) {
+    int per = SCAN_BLOCK * SCAN_ITEMS;
+    int nb = (n + per - 1) / per;
+    if (nb == 0) {
+        (void)hipMemsetAsync(out, 0, sizeof(int), st);
+        return;
+    }
+    k_scan_local<<<nb, SCAN_BLOCK, 0, st>>>(in, out, n, tmp);
+    k_scan_blocks<<<1, SCAN_BLOCK, 0, st>>>(tmp, nb, out + n);
+    k_scan_add<<<nb, SCAN_BLOCK, 0, st>>>(out, n, tmp);
+}
+
+// ------------------------------------------------------------ world of agent
+__global__ void k_world_of(const int *aoff, int W, int *world_of) {
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W) return;
+    for (int n = aoff[w]; n < aoff[w + 1]; ++n) world_of[n] = w;
+}
+
+void launch_world_of(const int *aoff, int W, int *world_of, hipStream_t st) {
+    if (W == 0) return;
+    k_world_of<<<(W + 255) / 256, 256, 0, st>>>(aoff, W, world_of);
+}

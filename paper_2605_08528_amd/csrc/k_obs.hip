@@ -1,0 +1,346 @@
+// Observation gather (Sec. "Observation Space Details"): one wavefront per
+// agent.  Ego block, the 64 road points with the smallest quantised
+// distance (grid-ring search, exact selection on integer keys, emitted in
+// point-index order), and the 8 nearest active neighbours with swept-circle
+// time to collision.  The row is staged in LDS and written as one coalesced
+// 1 KB store per wave.
+#include "sf_dev.h"
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ unsigned long long lane_lt() {
+    unsigned lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+    int lo = __shfl_xor((int)(unsigned)v, m, 64);
+    int hi = __shfl_xor((int)(unsigned)(v >> 32), m, 64);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// ascending bitonic sort of one u64 key per lane across the wavefront
+__device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long key) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            unsigned long long o = shfl_xor_u64(key, j);
+            bool up = (lane & k) == 0, lower = (lane & j) == 0;
+            key = (lower == up) ? (key < o ? key : o) : (key > o ? key : o);
+        }
+    return key;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        unsigned long long o = shfl_xor_u64(v, m);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        unsigned long long o = shfl_xor_u64(v, m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+#define KPL (SF_CAND_CAP / 64)  // candidate keys per lane
+
+// number of buffered keys <= x (uniform across the wave)
+__device__ __forceinline__ int count_le(const unsigned long long kv[KPL], unsigned long long x) {
+    int c = 0;
+#pragma unroll
+    for (int s = 0; s < KPL; ++s) c += __popcll(__ballot(kv[s] <= x));
+    return c;
+}
+
+// The K-th smallest key (1-based) of n >= K distinct keys held KPL per lane
+// (unused slots hold ~0): binary search on the key value.
+__device__ unsigned long long kth_smallest(const unsigned long long kv[KPL], int K) {
+    unsigned long long lo = ~0ull, hi = 0;
+#pragma unroll
+    for (int s = 0; s < KPL; ++s) {
+        lo = kv[s] < lo ? kv[s] : lo;
+        if (kv[s] != ~0ull) hi = kv[s] > hi ? kv[s] : hi;
+    }
+    lo = wave_min_u64(lo);
+    hi = wave_max_u64(hi);
+    // narrow on the distance part first (bits 20 and up), then on the index
+    unsigned long long dlo = lo >> 20, dhi = hi >> 20;
+    while (dlo < dhi) {
+        unsigned long long mid = dlo + ((dhi - dlo) >> 1);
+        if (count_le(kv, (mid << 20) | 0xFFFFFull) >= K) dhi = mid; else dlo = mid + 1;
+    }
+    unsigned long long ilo = dlo << 20, ihi = (dlo << 20) | 0xFFFFFull;
+    while (ilo < ihi) {
+        unsigned long long mid = ilo + ((ihi - ilo) >> 1);
+        if (count_le(kv, mid) >= K) ihi = mid; else ilo = mid + 1;
+    }
+    return ilo;
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
+                                                   const float *__restrict__ st,
+                                                   const int *__restrict__ ist,
+                                                   float *__restrict__ obs, int *__restrict__ dbg) {
+    __shared__ unsigned long long s_cand[WAVES][SF_CAND_CAP];
+    __shared__ float s_row[WAVES][SF_OBS_DIM];
+    __shared__ int s_sel[WAVES][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
+    // give each XCD a contiguous range of agents (neighbouring agents share a
+    // world and its road grid, which then stays in one L2)
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    const int lb = x * q + min(x, r) + (b >> 3);
+    const int N = Wd.N;
+    const int n = lb * WAVES + wv;
+    if (n >= N) return;
+    float *row = s_row[wv];
+    unsigned long long *cand = s_cand[wv];
+    float4 *dst = reinterpret_cast<float4 *>(obs + (size_t)n * SF_OBS_DIM);
+
+    if (!ist[SF_I_ACTIVE * N + n]) {
+        dst[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (dbg) dbg[(size_t)n * 72 + lane] = -1;
+        if (dbg && lane < 8) dbg[(size_t)n * 72 + 64 + lane] = -1;
+        return;
+    }
+    const int w = Wd.world_of[n];
+    const float px = st[SF_F_PX * N + n], py = st[SF_F_PY * N + n];
+    const float qw = st[SF_F_QW * N + n], qx = st[SF_F_QX * N + n];
+    const float qy = st[SF_F_QY * N + n], qz = st[SF_F_QZ * N + n];
+    float hx = 1.f - 2.f * (qy * qy + qz * qz), hy = 2.f * (qx * qy + qw * qz);
+    {
+        float L = sqrtf(hx * hx + hy * hy);
+        if (L < 1e-12f) { hx = 1.f; hy = 0.f; } else { hx /= L; hy /= L; }
+    }
+    const float vx = st[SF_F_VX * N + n], vy = st[SF_F_VY * N + n];
+    for (int k = lane; k < SF_OBS_DIM; k += 64) row[k] = 0.f;
+    wave_sync();
+
+    // ---- ego: goal in the body frame, heading error, distance, velocity, mu
+    if (lane < 8) {
+        const float gx = st[SF_F_GOAL_X * N + n] - px, gy = st[SF_F_GOAL_Y * N + n] - py;
+        const float gbx = hx * gx + hy * gy, gby = -hy * gx + hx * gy;
+        const float dist = sqrtf(gx * gx + gy * gy);
+        float e;
+        switch (lane) {
+            case 0: e = gbx / 100.f; break;
+            case 1: e = gby / 100.f; break;
+            case 2: e = dist > 0.f ? gby / dist : 0.f; break;
+            case 3: e = dist > 0.f ? gbx / dist : 1.f; break;
+            case 4: e = dist / 100.f; break;
+            case 5: e = (hx * vx + hy * vy) / 10.f; break;
+            case 6: e = (-hy * vx + hx * vy) / 10.f; break;
+            default: e = st[SF_F_MU * N + n]; break;
+        }
+        row[lane] = e;
+    }
+    const int QX = qpos(px), QY = qpos(py);
+
+    // ---- neighbours: 8 nearest other active agents of the world
+    {
+        const int a0 = Wd.aoff[w], A = Wd.aoff[w + 1] - a0;
+        unsigned long long key = ~0ull;
+        if (lane < A) {
+            const int m = a0 + lane;
+            if (m != n && ist[SF_I_ACTIVE * N + m]) {
+                long long dx = (long long)qpos(st[SF_F_PX * N + m]) - QX;
+                long long dy = (long long)qpos(st[SF_F_PY * N + m]) - QY;
+                key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 8) | (unsigned)lane;
+            }
+        }
+        key = wave_sort_u64(key);
+        int jn = key == ~0ull ? -1 : (int)(key & 0xFF);
+        if (dbg && lane < 8) dbg[(size_t)n * 72 + 64 + lane] = jn;
+        if (lane < 8 && jn >= 0) {
+            const int m = a0 + jn;
+            const float mx = st[SF_F_PX * N + m], my = st[SF_F_PY * N + m];
+            const float mqw = st[SF_F_QW * N + m], mqx = st[SF_F_QX * N + m];
+            const float mqy = st[SF_F_QY * N + m], mqz = st[SF_F_QZ * N + m];
+            float jx = 1.f - 2.f * (mqy * mqy + mqz * mqz), jy = 2.f * (mqx * mqy + mqw * mqz);
+            float L = sqrtf(jx * jx + jy * jy);
+            if (L < 1e-12f) { jx = 1.f; jy = 0.f; } else { jx /= L; jy /= L; }
+            const float dx = mx - px, dy = my - py;
+            const float bx = hx * dx + hy * dy, by = -hy * dx + hx * dy;
+            float dpsi = atan2f(hx * jy - hy * jx, hx * jx + hy * jy);
+            if (dpsi == -3.14159265358979f) dpsi = 3.14159265358979f;
+            const float mvx = st[SF_F_VX * N + m], mvy = st[SF_F_VY * N + m];
+            // swept circles, constant planar velocities; 0 if touching
+            float ttc = 10.f;
+            if (bx >= 0.f) {
+                const float dvx = mvx - vx, dvy = mvy - vy;
+                const float R2 = 4.f * P.cr * P.cr;
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c) {
+                        const float cx = (mx + (float)(c - 1) * P.cd * jx) - (px + (float)(a - 1) * P.cd * hx);
+                        const float cy = (my + (float)(c - 1) * P.cd * jy) - (py + (float)(a - 1) * P.cd * hy);
+                        const float c0 = cx * cx + cy * cy - R2;
+                        float t;
+                        if (c0 <= 0.f) t = 0.f;
+                        else {
+                            const float bq = 2.f * (cx * dvx + cy * dvy);
+                            if (bq >= 0.f) continue;
+                            const float aq = dvx * dvx + dvy * dvy;
+                            const float disc = bq * bq - 4.f * aq * c0;
+                            if (disc < 0.f) continue;
+                            t = 2.f * c0 / (-bq + sqrtf(disc));
+                        }
+                        ttc = fminf(ttc, t);
+                    }
+            }
+            float *o = row + 200 + 7 * lane;
+            o[0] = bx / 100.f;
+            o[1] = by / 100.f;
+            o[2] = P.length / 100.f;
+            o[3] = P.width / 100.f;
+            o[4] = dpsi / 3.14159265358979f;
+            o[5] = sqrtf(mvx * mvx + mvy * mvy) / 10.f;
+            o[6] = ttc / 10.f;
+        }
+    }
+
+    // ---- road: exact 64 nearest points by (quantised squared distance, index)
+    const int r0 = Wd.roff[w], PW = Wd.roff[w + 1] - r0;
+    int my_idx = 0x7fffffff;
+    if (PW > 0) {
+        const GridHdr g = Wd.grid[w];
+        int cx = (int)floorf((px - g.x0) * g.inv_cell);
+        int cy = (int)floorf((py - g.y0) * g.inv_cell);
+        cx = max(0, min(cx, g.nx - 1));
+        cy = max(0, min(cy, g.ny - 1));
+        int nc = 0;  // buffered candidates (uniform)
+        for (int rr = 0;; ++rr) {
+            // visit ring rr row by row; cells of a row segment are contiguous
+            const int ylo = max(cy - rr, 0), yhi = min(cy + rr, g.ny - 1);
+            for (int y = ylo; y <= yhi; ++y) {
+                const bool edge = (y == cy - rr) || (y == cy + rr);
+                for (int part = 0; part < 2; ++part) {
+                    int xa, xb;
+                    if (edge) {
+                        if (part) break;
+                        xa = cx - rr; xb = cx + rr;
+                    } else {
+                        xa = xb = part ? cx + rr : cx - rr;
+                        if (rr == 0 && part) break;
+                    }
+                    xa = max(xa, 0); xb = min(xb, g.nx - 1);
+                    if (xa > xb) continue;
+                    const int c0 = g.cbase + y * g.nx;
+                    const int s = Wd.pt_cell_start[c0 + xa], e = Wd.pt_cell_start[c0 + xb + 1];
+                    for (int k0 = s; k0 < e; k0 += 64) {
+                        if (nc + 64 > SF_CAND_CAP) {
+                            // keep only keys that can still be among the 64 best
+                            wave_sync();
+                            unsigned long long kv[KPL];
+#pragma unroll
+                            for (int t = 0; t < KPL; ++t) {
+                                int slot = lane + 64 * t;
+                                kv[t] = slot < nc ? cand[slot] : ~0ull;
+                            }
+                            const unsigned long long k64 = kth_smallest(kv, 64);
+                            wave_sync();
+                            int keep = 0;
+#pragma unroll
+                            for (int t = 0; t < KPL; ++t) {
+                                const bool f = kv[t] <= k64;
+                                const unsigned long long bal = __ballot(f);
+                                if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
+                                keep += __popcll(bal);
+                            }
+                            nc = keep;
+                            wave_sync();
+                        }
+                        const int k = k0 + lane;
+                        const bool has = k < e;
+                        unsigned long long key = 0;
+                        if (has) {
+                            const int4 pq = Wd.pt_cell[k];
+                            const long long dx = (long long)pq.x - QX, dy = (long long)pq.y - QY;
+                            key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 20) | (unsigned)pq.z;
+                        }
+                        const unsigned long long bal = __ballot(has);
+                        if (has) cand[nc + __popcll(bal & lane_lt())] = key;
+                        nc += __popcll(bal);
+                    }
+                }
+            }
+            // lower bound on the distance to any point outside the visited square
+            float bnd = INFINITY;
+            if (cx - rr > 0) bnd = fminf(bnd, px - (g.x0 + (float)(cx - rr) * g.cell));
+            if (cx + rr < g.nx - 1) bnd = fminf(bnd, (g.x0 + (float)(cx + rr + 1) * g.cell) - px);
+            if (cy - rr > 0) bnd = fminf(bnd, py - (g.y0 + (float)(cy - rr) * g.cell));
+            if (cy + rr < g.ny - 1) bnd = fminf(bnd, (g.y0 + (float)(cy + rr + 1) * g.cell) - py);
+            if (bnd == INFINITY) break;
+            const float tq = (bnd - 0.01f) * 1024.f;
+            if (tq > 0.f && nc >= 64) {
+                const long long th = (long long)tq;
+                const unsigned long long thr = ((unsigned long long)sat_key(th * th) << 20) | 0xFFFFFull;
+                wave_sync();
+                int cnt = 0;
+                for (int k0 = 0; k0 < nc; k0 += 64) {
+                    const int k = k0 + lane;
+                    cnt += __popcll(__ballot(k < nc && cand[k] <= thr));
+                }
+                if (cnt >= 64) break;
+            }
+        }
+        wave_sync();
+        // the 64 best among the buffered candidates, compacted into lanes
+        unsigned long long kv[KPL];
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+            int slot = lane + 64 * t;
+            kv[t] = slot < nc ? cand[slot] : ~0ull;
+        }
+        const unsigned long long kmax = nc > 64 ? kth_smallest(kv, 64) : ~0ull - 1;
+        int pos = 0;
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+            const bool f = kv[t] <= kmax;
+            const unsigned long long bal = __ballot(f);
+            const int at = pos + __popcll(bal & lane_lt());
+            if (f && at < 64) s_sel[wv][at] = (int)(kv[t] & 0xFFFFF);
+            pos += __popcll(bal);
+        }
+        wave_sync();
+        my_idx = lane < min(pos, 64) ? s_sel[wv][lane] : 0x7fffffff;
+        // point-index order: sort the member indices across lanes
+        unsigned long long sk = wave_sort_u64((unsigned long long)(unsigned)my_idx);
+        my_idx = (int)sk;
+    }
+    if (dbg) dbg[(size_t)n * 72 + lane] = my_idx == 0x7fffffff ? -1 : my_idx;
+    if (my_idx != 0x7fffffff) {
+        const float2 rp = Wd.road_xy[r0 + my_idx];
+        const float dx = rp.x - px, dy = rp.y - py;
+        float *o = row + 8 + 3 * lane;
+        o[0] = (hx * dx + hy * dy) / 10.f;
+        o[1] = (-hy * dx + hx * dy) / 10.f;
+        o[2] = (float)Wd.road_type[r0 + my_idx] / 20.f;
+    }
+    wave_sync();
+    dst[lane] = reinterpret_cast<const float4 *>(row)[lane];
+}
+
+void launch_obs(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
+                int *dbg_idx, int waves, hipStream_t s) {
+    if (Wd.N == 0) return;
+    if (waves <= 1) {
+        k_obs<1><<<Wd.N, 64, 0, s>>>(P, Wd, st, ist, obs, dbg_idx);
+    } else if (waves <= 2) {
+        k_obs<2><<<(Wd.N + 1) / 2, 128, 0, s>>>(P, Wd, st, ist, obs, dbg_idx);
+    } else {
+        k_obs<4><<<(Wd.N + 3) / 4, 256, 0, s>>>(P, Wd, st, ist, obs, dbg_idx);
+    }
+}

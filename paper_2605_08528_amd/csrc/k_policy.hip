@@ -1,0 +1,128 @@
+// Policy MLP 256 -> 256 -> 256 -> 2 on the agents' observations (the
+// on-device policy inference of Algorithm "SceneFactory Pipeline"): bf16
+// inputs and weights on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16),
+// fp32 accumulation, ELU hidden layers (Sec. "Network Architecture
+// Details" uses ELU), tanh outputs scaled to (a_long, steer_max * steer).
+//
+// One workgroup (4 waves) owns TM agents.  The observation tile is converted
+// to bf16 in LDS; each wave computes 64 output columns of a layer for all TM
+// rows; hidden activations stay in LDS (ping-pong buffers); the 2-wide head
+// is a plain fp32 dot product.
+#include "sf_dev.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define PL_IN 256
+#define PL_HID 256
+#define PL_LD (PL_HID + 8)  // padded LDS row (bf16 elements) against bank conflicts
+
+// round-to-nearest-even float -> bf16 bits
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float elu(float x) { return x > 0.f ? x : expm1f(x); }
+
+// one hidden layer: out[TM][256] = act(in[TM][256] W^T + b), bf16 in LDS
+template <int TM>
+__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
+                                            const uint16_t *__restrict__ W, const float *__restrict__ b) {
+    constexpr int RT = TM / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    f32x4 acc[RT][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kk = 0; kk < PL_IN / 32; ++kk) {
+        const int k0 = kk * 32 + kq * 8;
+        bf16x8 bfr[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int n = wv * 64 + c * 16 + r16;
+            bfr[c] = *reinterpret_cast<const bf16x8 *>(W + (size_t)n * PL_IN + k0);
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const bf16x8 afr = *reinterpret_cast<const bf16x8 *>(in + (r * 16 + r16) * PL_LD + k0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[c], acc[r][c], 0, 0, 0);
+        }
+    }
+    // lane holds D[4 * (lane / 16) + j][lane % 16] of each 16 x 16 tile
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int col = wv * 64 + c * 16 + r16;
+        const float bias = b[col];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = r * 16 + kq * 4 + j;
+                out[row * PL_LD + col] = f2bf(elu(acc[r][c][j] + bias));
+            }
+    }
+}
+
+template <int TM>
+__global__ __launch_bounds__(256) void k_policy(const float *__restrict__ obs, int N,
+                                                const uint16_t *__restrict__ W1, const float *__restrict__ b1,
+                                                const uint16_t *__restrict__ W2, const float *__restrict__ b2,
+                                                const uint16_t *__restrict__ W3, const float *__restrict__ b3,
+                                                float steer_max, float *__restrict__ act) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_a[TM * PL_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t s_b[TM * PL_LD];
+    const int r0 = blockIdx.x * TM;
+    // observation tile -> bf16 (coalesced float4 loads)
+    for (int e = threadIdx.x; e < TM * (PL_IN / 4); e += 256) {
+        const int row = e / (PL_IN / 4), c4 = e % (PL_IN / 4);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r0 + row < N) v = reinterpret_cast<const float4 *>(obs + (size_t)(r0 + row) * PL_IN)[c4];
+        uint16_t *d = s_a + row * PL_LD + 4 * c4;
+        d[0] = f2bf(v.x); d[1] = f2bf(v.y); d[2] = f2bf(v.z); d[3] = f2bf(v.w);
+    }
+    __syncthreads();
+    dense_layer<TM>(s_a, s_b, W1, b1);
+    __syncthreads();
+    dense_layer<TM>(s_b, s_a, W2, b2);
+    __syncthreads();
+    // head: 2 outputs per row, fp32 dot products over bf16 operands
+    for (int t = threadIdx.x; t < 2 * TM; t += 256) {
+        const int row = t >> 1, o = t & 1;
+        if (r0 + row >= N) continue;
+        float acc = 0.f;
+        const uint16_t *h = s_a + row * PL_LD;
+        const uint16_t *w = W3 + o * PL_HID;
+#pragma unroll 8
+        for (int k = 0; k < PL_HID; ++k) acc += bf2f(h[k]) * bf2f(w[k]);
+        const float z = tanhf(acc + b3[o]);
+        act[2 * (size_t)(r0 + row) + o] = o == 0 ? z : steer_max * z;
+    }
+}
+
+__global__ void k_to_bf16(const float *__restrict__ src, uint16_t *__restrict__ dst, int n) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = f2bf(src[k]);
+}
+
+void launch_to_bf16(const float *src, uint16_t *dst, int n, hipStream_t s) {
+    if (n > 0) k_to_bf16<<<(n + 255) / 256, 256, 0, s>>>(src, dst, n);
+}
+
+void launch_policy(const float *obs, int N, const uint16_t *W1, const float *b1, const uint16_t *W2,
+                   const float *b2, const uint16_t *W3, const float *b3, float steer_max, float *act,
+                   int tm, hipStream_t s) {
+    if (N == 0) return;
+    if (tm <= 32)
+        k_policy<32><<<(N + 31) / 32, 256, 0, s>>>(obs, N, W1, b1, W2, b2, W3, b3, steer_max, act);
+    else
+        k_policy<64><<<(N + 63) / 64, 256, 0, s>>>(obs, N, W1, b1, W2, b2, W3, b3, steer_max, act);
+}

@@ -1,0 +1,657 @@
+// The fused control-step kernel: one workgroup owns one world for all
+// substeps of a control step (contacts never cross worlds, so no grid-wide
+// synchronisation is needed).  World state lives in LDS across substeps;
+// threads map to wheels for ray/suspension/tire work, to agents for the
+// chassis, and to agent pairs for contact detection.
+#include "sf_dev.h"
+
+__device__ int g_sf_overflow;  // contact-capacity overflows (diagnostic)
+
+// ---------------------------------------------------------------- raycast
+__device__ __forceinline__ float mt_hit(const float4 *__restrict__ tri, int k, f3 m, f3 u, float ell) {
+    float4 a = tri[4 * (size_t)k], b = tri[4 * (size_t)k + 1], c = tri[4 * (size_t)k + 2];
+    f3 e1 = mk3(b.x, b.y, b.z), e2 = mk3(c.x, c.y, c.z);
+    f3 pv = cross3(u, e2);
+    float det = dot3(e1, pv);
+    if (fabsf(det) < 1e-12f) return INFINITY;
+    float inv = 1.f / det;
+    f3 tv = mk3(m.x - a.x, m.y - a.y, m.z - a.z);
+    float bu = dot3(tv, pv) * inv;
+    if (bu < 0.f || bu > 1.f) return INFINITY;
+    f3 qv = cross3(tv, e1);
+    float bv = dot3(u, qv) * inv;
+    if (bv < 0.f || bu + bv > 1.f) return INFINITY;
+    float t = dot3(e2, qv) * inv;
+    if (t < 0.f || t > ell) return INFINITY;
+    return t;
+}
+
+struct RayHit {
+    int hit, surf, tri;
+    float t;
+    f3 n;
+};
+
+// Nearest hit of the wheel ray against the ground plane z = 0 and the road
+// triangles in the grid cells the ray's footprint touches.  Hits within
+// 0.1 mm of the nearest are one surface point: a road triangle wins over the
+// ground, the lowest triangle index first.
+__device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, int w, f3 m, f3 u) {
+    const float ell = P.ell;
+    float tmin = INFINITY, tg = INFINITY;
+    if (u.z < 0.f) {
+        float t = m.z / (-u.z);
+        if (t >= 0.f && t <= ell) { tg = t; tmin = t; }
+    }
+    const int t0 = Wd.toff[w];
+    const bool any_tri = Wd.toff[w + 1] > t0;
+    int cx0 = 0, cx1 = -1, cy0 = 0, cy1 = -1;
+    GridHdr g;
+    if (any_tri) {
+        g = Wd.grid[w];
+        float ex = m.x + ell * u.x, ey = m.y + ell * u.y;
+        float xa = fminf(m.x, ex), xb = fmaxf(m.x, ex), ya = fminf(m.y, ey), yb = fmaxf(m.y, ey);
+        cx0 = (int)floorf((xa - g.x0) * g.inv_cell); cx1 = (int)floorf((xb - g.x0) * g.inv_cell);
+        cy0 = (int)floorf((ya - g.y0) * g.inv_cell); cy1 = (int)floorf((yb - g.y0) * g.inv_cell);
+        cx0 = max(0, min(cx0, g.nx - 1)); cx1 = max(0, min(cx1, g.nx - 1));
+        cy0 = max(0, min(cy0, g.ny - 1)); cy1 = max(0, min(cy1, g.ny - 1));
+        for (int cy = cy0; cy <= cy1; ++cy)
+            for (int cx = cx0; cx <= cx1; ++cx) {
+                int c = g.cbase + cy * g.nx + cx;
+                for (int k = Wd.tri_cell_start[c]; k < Wd.tri_cell_start[c + 1]; ++k)
+                    tmin = fminf(tmin, mt_hit(Wd.tri, t0 + Wd.tri_items[k], m, u, ell));
+            }
+    }
+    RayHit H;
+    H.hit = tmin < INFINITY;
+    H.tri = -1;
+    H.surf = 0;
+    H.t = tg;
+    H.n = mk3(0.f, 0.f, 1.f);
+    if (!H.hit || !any_tri) return H;
+    int best = 0x7fffffff;
+    float bt = INFINITY;
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            int c = g.cbase + cy * g.nx + cx;
+            for (int k = Wd.tri_cell_start[c]; k < Wd.tri_cell_start[c + 1]; ++k) {
+                int id = Wd.tri_items[k];
+                if (id >= best) continue;
+                float t = mt_hit(Wd.tri, t0 + id, m, u, ell);
+                if (t <= tmin + 1e-4f) { best = id; bt = t; }
+            }
+        }
+    if (best != 0x7fffffff) {
+        float4 a = Wd.tri[4 * (size_t)(t0 + best)];
+        float4 nn = Wd.tri[4 * (size_t)(t0 + best) + 3];
+        f3 n = mk3(nn.x, nn.y, nn.z);
+        if (dot3(n, u) > 0.f) n = mul3(n, -1.f);
+        H.t = bt;
+        H.n = n;
+        H.surf = (int)a.w;
+        H.tri = best;
+    }
+    return H;
+}
+
+// ------------------------------------------------------------------ tire
+// Linear-saturated tire in a friction circle with an implicit wheel-spin
+// update and Coulomb brake (closed form).  K = c_kappa Fz / max(|vx|, v_eps)
+// is the slip stiffness; the spin solve is implicit in it; forces outside
+// the circle scale onto it and the spin then integrates the saturated force.
+__device__ __forceinline__ void tire(const DevParams &P, float h, float Fz, float mu, float vx,
+                                     float vy, float om, float td, float tb, float &Fx, float &Fy,
+                                     float &om1) {
+    float D = fmaxf(fabsf(vx), P.v_eps);
+    float K = P.c_kappa * Fz / D;
+    float Fy0 = -P.c_alpha * Fz * vy / D;
+    float a = h / P.Iw;
+    float B = om + a * (td + P.rw * K * vx);
+    float Am = 1.f + a * P.rw * P.rw * K;
+    float bb = a * tb;
+    float os = B > bb ? (B - bb) / Am : (B < -bb ? (B + bb) / Am : 0.f);
+    float Fx0 = K * (P.rw * os - vx);
+    float lim = mu * Fz;
+    float F2 = Fx0 * Fx0 + Fy0 * Fy0;
+    if (F2 <= lim * lim) {
+        Fx = Fx0;
+        Fy = Fy0;
+        om1 = os;
+    } else {
+        float sc = lim / sqrtf(F2);
+        Fx = sc * Fx0;
+        Fy = sc * Fy0;
+        float Bs = om + a * (td - P.rw * Fx);
+        float mag = fmaxf(fabsf(Bs) - bb, 0.f);
+        om1 = Bs > 0.f ? mag : (Bs < 0.f ? -mag : 0.f);
+    }
+}
+
+__device__ __forceinline__ f3 inv_inertia(const DevParams &P, const float R[9], f3 x) {
+    f3 b = RTmul(R, x);
+    b.x *= P.inv_inertia[0];
+    b.y *= P.inv_inertia[1];
+    b.z *= P.inv_inertia[2];
+    return Rmul(R, b);
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    unsigned lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// (i, j), i < j, of the k-th pair in row-major order over A agents
+__device__ __forceinline__ void pair_of(int k, int A, int &i, int &j) {
+    float b = (float)(2 * A - 1);
+    int ii = (int)((b - sqrtf(b * b - 8.f * (float)k)) * 0.5f);
+    if (ii < 0) ii = 0;
+    while (ii > 0 && ii * (2 * A - ii - 1) / 2 > k) --ii;
+    while ((ii + 1) * (2 * A - ii - 2) / 2 <= k) ++ii;
+    i = ii;
+    j = k - ii * (2 * A - ii - 1) / 2 + ii + 1;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float *__restrict__ st,
+                                                int *__restrict__ ist, const float *__restrict__ act,
+                                                float h, int S, float *__restrict__ reward,
+                                                uint8_t *__restrict__ done, uint8_t *__restrict__ events,
+                                                uint32_t *__restrict__ rec, int *__restrict__ rec_cnt,
+                                                int rec_cap, const int *__restrict__ order) {
+    constexpr int NWV = BLOCK / 64;
+    const int w = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const int N = Wd.N;
+    const int a0 = Wd.aoff[w];
+    const int A = Wd.aoff[w + 1] - a0;
+    if (A <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    __shared__ float s_p[3][SF_MAXA], s_q[4][SF_MAXA], s_v[3][SF_MAXA], s_w[3][SF_MAXA];
+    __shared__ float s_R[9][SF_MAXA];
+    __shared__ float s_th[SF_MAXA], s_thd[SF_MAXA], s_taud[SF_MAXA], s_brk[SF_MAXA], s_tgt[SF_MAXA];
+    __shared__ float s_hx[SF_MAXA], s_hy[SF_MAXA], s_muo[SF_MAXA];
+    __shared__ int s_cq[6][SF_MAXA];
+    __shared__ int s_act[SF_MAXA];
+    __shared__ uint8_t s_coll[SF_MAXA], s_nan[SF_MAXA];
+    __shared__ float s_om[4 * SF_MAXA];
+    __shared__ float s_wf[6][4 * SF_MAXA];
+    __shared__ float s_wmu[4 * SF_MAXA];
+    __shared__ uint32_t s_pairs[SF_PAIR_CAP];
+    __shared__ float s_cn[2][SF_CCAP], s_cpc[3][SF_CCAP], s_cwk[SF_CCAP], s_cb[SF_CCAP];
+    __shared__ float s_clam[SF_CCAP], s_cdl[SF_CCAP];
+    __shared__ int s_cij[SF_CCAP];
+    __shared__ short s_bl[SF_MAXA][SF_BCAP];
+    __shared__ int s_bn[SF_MAXA];
+    __shared__ int s_scan[NWV];
+
+    // ---- load the world's agents; decode actions (Sec. "Action Space Details")
+    for (int i = tid; i < A; i += BLOCK) {
+        const int n = a0 + i;
+        for (int c = 0; c < 3; ++c) {
+            s_p[c][i] = st[(SF_F_PX + c) * N + n];
+            s_v[c][i] = st[(SF_F_VX + c) * N + n];
+            s_w[c][i] = st[(SF_F_WX + c) * N + n];
+        }
+        for (int c = 0; c < 4; ++c) {
+            s_q[c][i] = st[(SF_F_QW + c) * N + n];
+            s_om[4 * i + c] = st[(SF_F_OM0 + c) * N + n];
+        }
+        s_th[i] = st[SF_F_STEER * N + n];
+        s_thd[i] = st[SF_F_STEER_RATE * N + n];
+        s_muo[i] = st[SF_F_MU * N + n];
+        s_act[i] = ist[SF_I_ACTIVE * N + n];
+        float al = act[2 * (size_t)n], sa = act[2 * (size_t)n + 1];
+        uint8_t bad = 0;
+        if (al != al) { al = 0.f; bad = 1; }
+        if (sa != sa) { sa = 0.f; bad = 1; }
+        al = fminf(fmaxf(al, -1.f), 1.f);
+        s_taud[i] = al > 0.f ? al * P.tau_drive : 0.f;
+        s_brk[i] = al < 0.f ? -al : 0.f;
+        s_tgt[i] = fminf(fmaxf(sa, -P.steer_max), P.steer_max);
+        s_nan[i] = bad;
+        s_coll[i] = 0;
+    }
+    __syncthreads();
+
+    const int npc = A * (A - 1) / 2;
+    for (int sub = 0; sub < S; ++sub) {
+        const bool last = sub == S - 1;
+        // ---- A: steering PD (Eq. steer PD, implicit in the rate), rotation,
+        //      planar heading and the quantised three-circle centres
+        for (int i = tid; i < A; i += BLOCK) {
+            if (!s_act[i]) continue;
+            float th = s_th[i], thd = s_thd[i], tgt = s_tgt[i];
+            float g = h / P.Is;
+            float thd1 = (thd + g * P.kp * (tgt - th)) / (1.f + g * (P.kd + h * P.kp));
+            float tau = P.kp * (tgt - th - h * thd1) - P.kd * thd1;
+            if (fabsf(tau) > P.tau_max) {
+                tau = tau > 0.f ? P.tau_max : -P.tau_max;
+                thd1 = thd + g * tau;
+            }
+            s_th[i] = th + h * thd1;
+            s_thd[i] = thd1;
+            float R[9];
+            quat_R(s_q[0][i], s_q[1][i], s_q[2][i], s_q[3][i], R);
+            for (int c = 0; c < 9; ++c) s_R[c][i] = R[c];
+            float L = sqrtf(R[0] * R[0] + R[3] * R[3]);
+            s_hx[i] = L < 1e-12f ? 1.f : R[0] / L;
+            s_hy[i] = L < 1e-12f ? 0.f : R[3] / L;
+            long long X = qpos(s_p[0][i]), Y = qpos(s_p[1][i]);
+            long long qw = qquat(s_q[0][i]), qx = qquat(s_q[1][i]);
+            long long qy = qquat(s_q[2][i]), qz = qquat(s_q[3][i]);
+            long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);
+            long long hy = 2 * (qx * qy + qw * qz);
+            long long nh = isqrt64(hx * hx + hy * hy);
+            long long ox = 0, oy = 0;
+            if (nh > 0) { ox = (long long)P.Qd * hx / nh; oy = (long long)P.Qd * hy / nh; }
+            s_cq[0][i] = (int)(X - ox); s_cq[1][i] = (int)(Y - oy);
+            s_cq[2][i] = (int)X;        s_cq[3][i] = (int)Y;
+            s_cq[4][i] = (int)(X + ox); s_cq[5][i] = (int)(Y + oy);
+        }
+        __syncthreads();
+
+        // ---- B: overlapping circle pairs on the substep's input poses,
+        //      compacted in canonical (i, j) order (wave ballot + prefix)
+        int np = 0;
+        for (int base = 0; base < npc; base += BLOCK) {
+            const int k = base + tid;
+            int flag = 0;
+            uint32_t packed = 0;
+            if (k < npc) {
+                int i, j;
+                pair_of(k, A, i, j);
+                if (s_act[i] && s_act[j]) {
+                    uint32_t mask = 0;
+                    const long long R2 = P.Qr2;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            long long dx = (long long)s_cq[2 * a][i] - s_cq[2 * b][j];
+                            long long dy = (long long)s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
+                            if (dx * dx + dy * dy < R2) mask |= 1u << (3 * a + b);
+                        }
+                    if (mask) {
+                        flag = 1;
+                        packed = (uint32_t)i | ((uint32_t)j << 8) | (mask << 16);
+                    }
+                }
+            }
+            unsigned long long bal = __ballot(flag);
+            int pre = __popcll(bal & lanemask_lt());
+            if (lane == 0) s_scan[wave] = __popcll(bal);
+            __syncthreads();
+            int off = 0, tot = 0;
+#pragma unroll
+            for (int v = 0; v < NWV; ++v) {
+                if (v < wave) off += s_scan[v];
+                tot += s_scan[v];
+            }
+            if (flag) s_pairs[np + off + pre] = packed;
+            np += tot;
+            __syncthreads();
+        }
+        if (rec) {
+            uint32_t *dst = rec + ((size_t)sub * Wd.W + w) * rec_cap;
+            for (int k = tid; k < np && k < rec_cap; k += BLOCK) dst[k] = s_pairs[k];
+            if (tid == 0) rec_cnt[sub * Wd.W + w] = np;
+        }
+        for (int k = tid; k < np; k += BLOCK) {
+            s_coll[s_pairs[k] & 0xFF] = 1;
+            s_coll[(s_pairs[k] >> 8) & 0xFF] = 1;
+        }
+
+        // ---- C: wheels: raycast, suspension, tire, spin
+        for (int wi = tid; wi < 4 * A; wi += BLOCK) {
+            const int i = wi >> 2, wh = wi & 3;
+            float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float mu_seen = 0.f;
+            if (s_act[i]) {
+                float R[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) R[c] = s_R[c][i];
+                const f3 pos = mk3(s_p[0][i], s_p[1][i], s_p[2][i]);
+                const f3 v = mk3(s_v[0][i], s_v[1][i], s_v[2][i]);
+                const f3 om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
+                const f3 rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
+                const f3 m = add3(pos, rm);
+                const f3 u = mk3(-R[2], -R[5], -R[8]);
+                RayHit H = raycast(P, Wd, w, m, u);
+                const float Om = s_om[wi];
+                const float td = wh < 2 ? s_taud[i] : 0.f;
+                const float tb = s_brk[i] * (wh < 2 ? P.tau_bf : P.tau_br);
+                float Fx = 0.f, Fy = 0.f, om1;
+                if (H.hit) {
+                    const float mu = Wd.mu[w * Wd.S + H.surf];
+                    mu_seen = mu;
+                    // massless spring-damper along the ray
+                    const float x = P.ell - H.t;
+                    const f3 vm = add3(v, cross3(om, rm));
+                    const float xd = -dot3(H.n, vm) / (-dot3(H.n, u));
+                    const float Fz = fmaxf(P.susp_k * x + P.susp_c * xd, 0.f);
+                    const f3 rc = add3(rm, mul3(u, H.t));
+                    // tire frame: wheel heading projected on the contact plane
+                    const float dl = wh < 2 ? s_th[i] : 0.f;
+                    const f3 hw = Rmul(R, mk3(cosf(dl), sinf(dl), 0.f));
+                    f3 ex = sub3(hw, mul3(H.n, dot3(hw, H.n)));
+                    const float L = sqrtf(dot3(ex, ex));
+                    f3 ey = mk3(0.f, 0.f, 0.f);
+                    if (L > 1e-9f) {
+                        ex = mul3(ex, 1.f / L);
+                        ey = cross3(H.n, ex);
+                        const f3 vc = add3(v, cross3(om, rc));
+                        tire(P, h, Fz, mu, dot3(vc, ex), dot3(vc, ey), Om, td, tb, Fx, Fy, om1);
+                    } else {
+                        ex = mk3(0.f, 0.f, 0.f);
+                        tire(P, h, 0.f, mu, 0.f, 0.f, Om, td, tb, Fx, Fy, om1);
+                    }
+                    const f3 fw = add3(add3(mul3(H.n, Fz), mul3(ex, Fx)), mul3(ey, Fy));
+                    const f3 tq = add3(cross3(rc, fw), mul3(H.n, -P.trail * Fy));
+                    f[0] = fw.x; f[1] = fw.y; f[2] = fw.z;
+                    f[3] = tq.x; f[4] = tq.y; f[5] = tq.z;
+                } else {
+                    tire(P, h, 0.f, 0.f, 0.f, 0.f, Om, td, tb, Fx, Fy, om1);
+                }
+                s_om[wi] = om1;
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) s_wf[c][wi] = f[c];
+            s_wmu[wi] = mu_seen;
+        }
+
+        // ---- D: contact points of the compacted pairs, in list order
+        int nc = 0;
+        for (int base = 0; base < np; base += BLOCK) {
+            const int k = base + tid;
+            uint32_t pr = k < np ? s_pairs[k] : 0u;
+            int cnt = __popc(pr >> 16);
+            int x = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) s_scan[wave] = x;
+            __syncthreads();
+            int off = 0, tot = 0;
+#pragma unroll
+            for (int v = 0; v < NWV; ++v) {
+                if (v < wave) off += s_scan[v];
+                tot += s_scan[v];
+            }
+            int pos = nc + off + x - cnt;
+            if (cnt) {
+                const int i = pr & 0xFF, j = (pr >> 8) & 0xFF;
+                const uint32_t mask = pr >> 16;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        if (!(mask & (1u << (3 * a + b)))) continue;
+                        if (pos < SF_CCAP) {
+                            const float cix = s_p[0][i] + (float)(a - 1) * P.cd * s_hx[i];
+                            const float ciy = s_p[1][i] + (float)(a - 1) * P.cd * s_hy[i];
+                            const float cjx = s_p[0][j] + (float)(b - 1) * P.cd * s_hx[j];
+                            const float cjy = s_p[1][j] + (float)(b - 1) * P.cd * s_hy[j];
+                            const float dx = cjx - cix, dy = cjy - ciy;
+                            const float L = sqrtf(dx * dx + dy * dy);
+                            s_cn[0][pos] = L > 0.f ? dx / L : 1.f;
+                            s_cn[1][pos] = L > 0.f ? dy / L : 0.f;
+                            s_cpc[0][pos] = 0.5f * (cix + cjx);
+                            s_cpc[1][pos] = 0.5f * (ciy + cjy);
+                            s_cpc[2][pos] = 0.5f * (s_p[2][i] + s_p[2][j]);
+                            const float pen = 2.f * P.cr - L - P.slop;
+                            s_cb[pos] = pen > 0.f ? (P.baumgarte / h) * pen : 0.f;
+                            s_clam[pos] = 0.f;
+                            s_cij[pos] = i | (j << 8);
+                        }
+                        ++pos;
+                    }
+            }
+            nc += tot;
+            __syncthreads();
+        }
+        if (nc > SF_CCAP) {
+            if (tid == 0) atomicAdd(&g_sf_overflow, 1);
+            nc = SF_CCAP;
+        }
+        __syncthreads();
+
+        // ---- E: chassis velocities (semi-implicit Euler, explicit gyroscopic
+        //      term) and each body's contact list in list order
+        for (int i = tid; i < A; i += BLOCK) {
+            if (!s_act[i]) { s_bn[i] = 0; continue; }
+            float R[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) R[c] = s_R[c][i];
+            f3 F = mk3(0.f, 0.f, -P.mass * P.g);
+            f3 T = mk3(0.f, 0.f, -P.yaw_damping * s_w[2][i]);
+#pragma unroll
+            for (int wh = 0; wh < 4; ++wh) {
+                const int wi = 4 * i + wh;
+                F = add3(F, mk3(s_wf[0][wi], s_wf[1][wi], s_wf[2][wi]));
+                T = add3(T, mk3(s_wf[3][wi], s_wf[4][wi], s_wf[5][wi]));
+            }
+            if (last) s_muo[i] = (s_wmu[4 * i] + s_wmu[4 * i + 1] + s_wmu[4 * i + 2] + s_wmu[4 * i + 3]) * 0.25f;
+            const f3 om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
+            const f3 wb = RTmul(R, om), Tb = RTmul(R, T);
+            const f3 Lb = mk3(P.inertia[0] * wb.x, P.inertia[1] * wb.y, P.inertia[2] * wb.z);
+            const f3 gy = cross3(wb, Lb);
+            const f3 wb1 = mk3(wb.x + h * (Tb.x - gy.x) * P.inv_inertia[0],
+                               wb.y + h * (Tb.y - gy.y) * P.inv_inertia[1],
+                               wb.z + h * (Tb.z - gy.z) * P.inv_inertia[2]);
+            const f3 om1 = Rmul(R, wb1);
+            for (int c = 0; c < 3; ++c) s_v[c][i] += h * (&F.x)[c] * P.inv_mass;
+            s_w[0][i] = om1.x; s_w[1][i] = om1.y; s_w[2][i] = om1.z;
+            int cnt = 0;
+            for (int c = 0; c < nc; ++c) {
+                const int ij = s_cij[c];
+                if ((ij & 0xFF) == i || ((ij >> 8) & 0xFF) == i) {
+                    if (cnt < SF_BCAP) s_bl[i][cnt] = (short)c;
+                    ++cnt;
+                }
+            }
+            if (cnt > SF_BCAP) { atomicAdd(&g_sf_overflow, 1); cnt = SF_BCAP; }
+            s_bn[i] = cnt;
+        }
+        __syncthreads();
+
+        if (nc > 0) {
+            // ---- F: effective mass along each normal, relaxed by the larger
+            //      contact count of the two bodies
+            for (int c = tid; c < nc; c += BLOCK) {
+                const int i = s_cij[c] & 0xFF, j = (s_cij[c] >> 8) & 0xFF;
+                const f3 n = mk3(s_cn[0][c], s_cn[1][c], 0.f);
+                const f3 pc = mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]);
+                float Ri[9], Rj[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) { Ri[q] = s_R[q][i]; Rj[q] = s_R[q][j]; }
+                const f3 ri = sub3(pc, mk3(s_p[0][i], s_p[1][i], s_p[2][i]));
+                const f3 rj = sub3(pc, mk3(s_p[0][j], s_p[1][j], s_p[2][j]));
+                const f3 xi = cross3(ri, n), xj = cross3(rj, n);
+                const float keff = 2.f * P.inv_mass + dot3(xi, inv_inertia(P, Ri, xi)) +
+                                   dot3(xj, inv_inertia(P, Rj, xj));
+                const int nmax = max(s_bn[i], s_bn[j]);
+                s_cwk[c] = 1.f / ((float)nmax * keff);
+            }
+            __syncthreads();
+            // ---- G: Jacobi sweeps: every contact reads the previous sweep's
+            //      velocities; each body then sums its contacts in list order
+            for (int it = 0; it < P.jacobi_iters; ++it) {
+                for (int c = tid; c < nc; c += BLOCK) {
+                    const int i = s_cij[c] & 0xFF, j = (s_cij[c] >> 8) & 0xFF;
+                    const f3 pc = mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]);
+                    const f3 ri = sub3(pc, mk3(s_p[0][i], s_p[1][i], s_p[2][i]));
+                    const f3 rj = sub3(pc, mk3(s_p[0][j], s_p[1][j], s_p[2][j]));
+                    const f3 wi = cross3(mk3(s_w[0][i], s_w[1][i], s_w[2][i]), ri);
+                    const f3 wj = cross3(mk3(s_w[0][j], s_w[1][j], s_w[2][j]), rj);
+                    const float vn = ((s_v[0][j] + wj.x) - (s_v[0][i] + wi.x)) * s_cn[0][c] +
+                                     ((s_v[1][j] + wj.y) - (s_v[1][i] + wi.y)) * s_cn[1][c];
+                    const float lam = s_clam[c];
+                    const float lam1 = fmaxf(lam + s_cwk[c] * (-vn + s_cb[c]), 0.f);
+                    s_cdl[c] = lam1 - lam;
+                    s_clam[c] = lam1;
+                }
+                __syncthreads();
+                for (int b = tid; b < A; b += BLOCK) {
+                    const int cnt = s_bn[b];
+                    if (cnt == 0) continue;
+                    float R[9];
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) R[q] = s_R[q][b];
+                    const f3 pb = mk3(s_p[0][b], s_p[1][b], s_p[2][b]);
+                    f3 v = mk3(s_v[0][b], s_v[1][b], s_v[2][b]);
+                    f3 om = mk3(s_w[0][b], s_w[1][b], s_w[2][b]);
+                    for (int q = 0; q < cnt; ++q) {
+                        const int c = s_bl[b][q];
+                        const float sg = ((s_cij[c] >> 8) & 0xFF) == b ? 1.f : -1.f;
+                        const f3 J = mk3(sg * s_cdl[c] * s_cn[0][c], sg * s_cdl[c] * s_cn[1][c], 0.f);
+                        v = add3(v, mul3(J, P.inv_mass));
+                        const f3 r = sub3(mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]), pb);
+                        om = add3(om, inv_inertia(P, R, cross3(r, J)));
+                    }
+                    s_v[0][b] = v.x; s_v[1][b] = v.y; s_v[2][b] = v.z;
+                    s_w[0][b] = om.x; s_w[1][b] = om.y; s_w[2][b] = om.z;
+                }
+                __syncthreads();
+            }
+        }
+
+        // ---- H: positions and orientations
+        for (int i = tid; i < A; i += BLOCK) {
+            if (!s_act[i]) continue;
+            const float vx = s_v[0][i], vy = s_v[1][i], vz = s_v[2][i];
+            s_p[0][i] += h * vx;
+            s_p[1][i] += h * vy;
+            s_p[2][i] += h * vz;
+            float qw = s_q[0][i], qx = s_q[1][i], qy = s_q[2][i], qz = s_q[3][i];
+            const float wx = s_w[0][i], wy = s_w[1][i], wz = s_w[2][i];
+            const float dw = -(wx * qx + wy * qy + wz * qz);
+            const float dx = wx * qw + (wy * qz - wz * qy);
+            const float dy = wy * qw + (wz * qx - wx * qz);
+            const float dz = wz * qw + (wx * qy - wy * qx);
+            qw += 0.5f * h * dw; qx += 0.5f * h * dx; qy += 0.5f * h * dy; qz += 0.5f * h * dz;
+            const float L = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+            s_q[0][i] = qw / L; s_q[1][i] = qx / L; s_q[2][i] = qy / L; s_q[3][i] = qz / L;
+        }
+        __syncthreads();
+    }
+
+    // ---- events, reward, termination, write-back (Sec. "Reward Design Details")
+    for (int i = tid; i < A; i += BLOCK) {
+        const int n = a0 + i;
+        if (!s_act[i]) {
+            reward[n] = 0.f;
+            done[n] = 0;
+            events[n] = 0;
+            continue;
+        }
+        float dyn[SF_F_MU];
+        for (int c = 0; c < 3; ++c) {
+            dyn[SF_F_PX + c] = s_p[c][i];
+            dyn[SF_F_VX + c] = s_v[c][i];
+            dyn[SF_F_WX + c] = s_w[c][i];
+        }
+        for (int c = 0; c < 4; ++c) {
+            dyn[SF_F_QW + c] = s_q[c][i];
+            dyn[SF_F_OM0 + c] = s_om[4 * i + c];
+        }
+        dyn[SF_F_STEER] = s_th[i];
+        dyn[SF_F_STEER_RATE] = s_thd[i];
+        bool finite = true;
+        for (int c = 0; c < SF_F_MU; ++c) {
+            st[c * N + n] = dyn[c];
+            finite = finite && isfinite(dyn[c]);
+        }
+        st[SF_F_MU * N + n] = s_muo[i];
+        uint32_t ev = 0;
+        if (!finite) {
+            ev = SF_EV_CRASH | SF_EV_NUMERIC;
+        } else {
+            const long long X = qpos(dyn[SF_F_PX]), Y = qpos(dyn[SF_F_PY]), Z = qpos(dyn[SF_F_PZ]);
+            const long long gx = X - qpos(st[SF_F_GOAL_X * N + n]), gy = Y - qpos(st[SF_F_GOAL_Y * N + n]);
+            if (gx * gx + gy * gy <= 3072ll * 3072ll) ev |= SF_EV_GOAL;
+            if (s_coll[i] && ist[SF_I_SINCE_SPAWN * N + n] >= P.warmup) ev |= SF_EV_COLLISION;
+            const long long sx = X - qpos(st[SF_F_START_X * N + n]), sy = Y - qpos(st[SF_F_START_Y * N + n]);
+            bool crash = sx * sx + sy * sy > 102400ll * 102400ll || Z < 0;
+            const long long qx = qquat(dyn[SF_F_QX]), qy = qquat(dyn[SF_F_QY]);
+            crash = crash || ((1ll << 28) - 2 * (qx * qx + qy * qy) < 40265318ll);
+            if (crash) ev |= SF_EV_CRASH;
+        }
+        if (s_nan[i]) ev |= SF_EV_NAN_ACTION;
+        const int ep = ist[SF_I_EP_STEP * N + n] + 1;
+        ist[SF_I_EP_STEP * N + n] = ep;
+        ist[SF_I_SINCE_SPAWN * N + n] += 1;
+        if (ep >= P.max_ep) ev |= SF_EV_TIMEOUT;
+        const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f : 0.f;
+        const bool term = (ev & (SF_EV_GOAL | SF_EV_COLLISION | SF_EV_CRASH)) != 0;
+        const bool dn = (term && !(P.flags & SF_INVINCIBLE)) || (ev & (SF_EV_TIMEOUT | SF_EV_NUMERIC));
+        reward[n] = r;
+        done[n] = dn;
+        events[n] = (uint8_t)ev;
+        if (dn) {
+            if (P.flags & SF_AUTO_RESET) {
+                ist[SF_I_EPISODE * N + n] += 1;
+                spawn_agent(P, Wd, st, ist, N, n, w, i);
+            } else {
+                // parked off-stage at x = 1000 m at rest (Sec. "Termination and time-out")
+                st[SF_F_PX * N + n] = 1000.f;
+                st[SF_F_PY * N + n] = 0.f;
+                st[SF_F_PZ * N + n] = P.z_ride;
+                st[SF_F_QW * N + n] = 1.f;
+                st[SF_F_QX * N + n] = 0.f;
+                st[SF_F_QY * N + n] = 0.f;
+                st[SF_F_QZ * N + n] = 0.f;
+                for (int c = SF_F_VX; c <= SF_F_MU; ++c) st[c * N + n] = 0.f;
+                ist[SF_I_ACTIVE * N + n] = 0;
+            }
+        }
+    }
+}
+
+void launch_step(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act,
+                 float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
+                 int *rec_cnt, int rec_cap, const int *order, int block, hipStream_t s) {
+    if (Wd.W == 0) return;
+    if (block <= 64)
+        k_step<64><<<Wd.W, 64, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, order);
+    else if (block <= 128)
+        k_step<128><<<Wd.W, 128, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, order);
+    else
+        k_step<256><<<Wd.W, 256, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, order);
+}
+
+// ------------------------------------------------------------------ reset
+__global__ void k_reset(DevParams P, DevWorld Wd, float *st, int *ist, const uint8_t *mask, int bump) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= Wd.N) return;
+    if (mask && !mask[n]) return;
+    int w = Wd.world_of[n];
+    if (bump) ist[SF_I_EPISODE * Wd.N + n] += 1;
+    spawn_agent(P, Wd, st, ist, Wd.N, n, w, n - Wd.aoff[w]);
+}
+
+void launch_reset(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const uint8_t *mask,
+                  int bump_episode, hipStream_t s) {
+    if (Wd.N == 0) return;
+    k_reset<<<(Wd.N + 255) / 256, 256, 0, s>>>(P, Wd, st, ist, mask, bump_episode);
+}
+
+// ---------------------------------------------------------- debug raycast
+__global__ void k_debug_raycast(DevParams P, DevWorld Wd, const float *st, float *out) {
+    int wi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (wi >= 4 * Wd.N) return;
+    const int N = Wd.N, n = wi >> 2, wh = wi & 3;
+    float R[9];
+    quat_R(st[SF_F_QW * N + n], st[SF_F_QX * N + n], st[SF_F_QY * N + n], st[SF_F_QZ * N + n], R);
+    const f3 rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
+    const f3 m = add3(mk3(st[SF_F_PX * N + n], st[SF_F_PY * N + n], st[SF_F_PZ * N + n]), rm);
+    RayHit H = raycast(P, Wd, Wd.world_of[n], m, mk3(-R[2], -R[5], -R[8]));
+    out[4 * (size_t)wi + 0] = (float)H.hit;
+    out[4 * (size_t)wi + 1] = H.hit ? H.t : 0.f;
+    out[4 * (size_t)wi + 2] = (float)H.surf;
+    out[4 * (size_t)wi + 3] = (float)H.tri;
+}
+
+void launch_debug_raycast(const DevParams &P, const DevWorld &Wd, const float *st, float *out,
+                          hipStream_t s) {
+    if (Wd.N == 0) return;
+    k_debug_raycast<<<(4 * Wd.N + 255) / 256, 256, 0, s>>>(P, Wd, st, out);
+}

@@ -1,0 +1,712 @@
+// Host side of the C ABI declared in include/sf.h: argument validation,
+// device memory, create-time preparation (friction table, road grid, first
+// spawn and observation) and the enqueueing of the step kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sf_dev.h"
+
+static thread_local std::string g_err;
+
+static sf_status fail(sf_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+struct sf_sim {
+    hipStream_t stream = nullptr;
+    sf_alloc_fn alloc = nullptr;
+    sf_free_fn free_fn = nullptr;
+    void *alloc_ctx = nullptr;
+    std::vector<void *> allocs;
+    bool bad = false;
+    int W = 0, N = 0, S = 0, max_agents = 0, P = 0, T = 0, E = 0, C = 0;
+    uint32_t flags = 0;
+    int step_block = 128, obs_waves = 4;
+    DevParams P_dev{};
+    DevWorld Wd{};
+    float *st = nullptr;       // [NF][N]
+    int *ist = nullptr;        // [NI][N] (same allocation, after st)
+    float *obs = nullptr, *reward = nullptr;
+    uint8_t *done = nullptr, *events = nullptr;
+    int *order = nullptr;
+    uint32_t *rec = nullptr;
+    int *rec_cnt = nullptr;
+    int rec_cap = 0;
+    int last_substeps = 0;
+    // policy
+    int policy_rows = 64;
+    float steer_max = 0.5f;
+    float *pol_f32 = nullptr;       // float masters as loaded
+    uint16_t *pol_bf16 = nullptr;   // bf16 copies of W1, W2, W3
+    float *pol_act = nullptr;       // [N][2] actions of sf_step_policy
+    bool policy_loaded = false;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    // profiling
+    bool prof = false;
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+static hipEvent_t ev_get(sf_sim *s) {
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// bracket one enqueued kernel with events when profiling
+struct ProfScope {
+    sf_sim *s;
+    int kind;
+    hipEvent_t a = nullptr;
+    ProfScope(sf_sim *s_, int k) : s(s_), kind(k) {
+        if (s->prof) {
+            a = ev_get(s);
+            if (a) (void)hipEventRecord(a, s->stream);
+        }
+    }
+    ~ProfScope() {
+        if (s->prof && a) {
+            hipEvent_t b = ev_get(s);
+            if (b) {
+                (void)hipEventRecord(b, s->stream);
+                s->recs.push_back({kind, a, b});
+            } else {
+                s->pool.push_back(a);
+            }
+        }
+    }
+};
+
+static void *dev_alloc(sf_sim *s, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void *p = nullptr;
+    if (s->alloc) {
+        p = s->alloc(bytes, s->alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) s->allocs.push_back(p);
+    return p;
+}
+
+static void free_all(sf_sim *s) {
+    for (void *p : s->allocs) {
+        if (s->free_fn) s->free_fn(p, s->alloc_ctx);
+        else if (!s->alloc) (void)hipFree(p);
+    }
+    s->allocs.clear();
+}
+
+#define DEV(call)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            sim->bad = true;                                                             \
+            return fail(SF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+        }                                                                                \
+    } while (0)
+
+#define LAUNCHED()                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = hipGetLastError();                                                  \
+        if (e_ != hipSuccess) {                                                             \
+            sim->bad = true;                                                                \
+            return fail(SF_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+        }                                                                                   \
+    } while (0)
+
+extern "C" {
+
+const char *sf_status_str(sf_status s) {
+    switch (s) {
+        case SF_OK: return "ok";
+        case SF_E_INVALID_ARG: return "invalid argument";
+        case SF_E_OUT_OF_MEMORY: return "out of device memory";
+        case SF_E_DEVICE: return "device error";
+        case SF_E_BAD_STATE: return "handle unusable after a device error";
+        case SF_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *sf_last_error(void) { return g_err.c_str(); }
+
+sf_status sf_default_params(sf_vehicle_params *p) {
+    if (!p) return fail(SF_E_INVALID_ARG, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->mass = 1500.f;
+    p->inertia[0] = 600.f; p->inertia[1] = 2500.f; p->inertia[2] = 2800.f;
+    p->wheel_radius = 0.35f;
+    p->wheel_mass = 20.f;
+    p->wheel_inertia = 0.f;
+    p->susp_k = 35000.f;
+    p->susp_c = 4000.f;
+    p->susp_rest = 0.30f;
+    const float m[4][3] = {{1.3f, 0.8f, -0.2f}, {1.3f, -0.8f, -0.2f}, {-1.3f, 0.8f, -0.2f}, {-1.3f, -0.8f, -0.2f}};
+    std::memcpy(p->mount, m, sizeof(m));
+    p->length = 4.f; p->width = 2.f; p->wheelbase = 2.6f;
+    p->tau_drive = 600.7f; p->tau_brake_front = 1090.5f; p->tau_brake_rear = 980.7f;
+    p->steer_kp = 1839.5f; p->steer_kd = 110.5f; p->steer_tau_max = 1200.f;
+    p->steer_inertia = 0.6125f; p->steer_max = 0.5f;
+    p->c_kappa = 12.f; p->c_alpha = 10.f; p->v_eps = 1.f; p->trail = 0.03f;
+    p->yaw_damping = 0.f; p->gravity = 9.81f;
+    p->jacobi_iters = 8; p->baumgarte = 0.2f; p->slop = 0.01f;
+    return SF_OK;
+}
+
+sf_status sf_default_options(sf_options *o) {
+    if (!o) return fail(SF_E_INVALID_ARG, "options is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->max_episode_steps = 1500;
+    o->collision_warmup = 24;
+    return SF_OK;
+}
+
+static bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+static sf_status check_csr(const int32_t *off, int W, const char *name, int *total) {
+    if (!off) return fail(SF_E_INVALID_ARG, std::string(name) + " is NULL");
+    if (off[0] != 0) return fail(SF_E_INVALID_ARG, std::string(name) + "[0] must be 0");
+    for (int w = 0; w < W; ++w)
+        if (off[w + 1] < off[w]) return fail(SF_E_INVALID_ARG, std::string(name) + " must be non-decreasing");
+    *total = off[W];
+    return SF_OK;
+}
+
+sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf_options *o,
+                    sf_sim **out) {
+    if (!out) return fail(SF_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d || !p) return fail(SF_E_INVALID_ARG, "desc or params is NULL");
+    sf_options opts;
+    if (o) opts = *o; else sf_default_options(&opts);
+    const int W = d->num_worlds;
+    if (W < 0) return fail(SF_E_INVALID_ARG, "num_worlds < 0");
+    int N = 0, P = 0, T = 0, E = 0;
+    sf_status s;
+    if ((s = check_csr(d->agent_offsets, W, "agent_offsets", &N)) != SF_OK) return s;
+    if ((s = check_csr(d->road_offsets, W, "road_offsets", &P)) != SF_OK) return s;
+    if ((s = check_csr(d->tri_offsets, W, "tri_offsets", &T)) != SF_OK) return s;
+    if ((s = check_csr(d->spawn_offsets, W, "spawn_offsets", &E)) != SF_OK) return s;
+    int amax = 0;
+    for (int w = 0; w < W; ++w) {
+        int a = d->agent_offsets[w + 1] - d->agent_offsets[w];
+        amax = std::max(amax, a);
+        if (a > SF_MAX_AGENTS_PER_WORLD)
+            return fail(SF_E_UNSUPPORTED, "world " + std::to_string(w) + " has " + std::to_string(a) +
+                                              " agents (max " + std::to_string(SF_MAX_AGENTS_PER_WORLD) + ")");
+        if (a > 0 && d->spawn_offsets[w + 1] == d->spawn_offsets[w])
+            return fail(SF_E_INVALID_ARG, "world " + std::to_string(w) + " has agents but no spawn entries");
+        if (d->road_offsets[w + 1] - d->road_offsets[w] > SF_MAX_ROAD_POINTS_PER_WORLD)
+            return fail(SF_E_UNSUPPORTED, "too many road points in world " + std::to_string(w));
+    }
+    if ((P && (!d->road_xy || !d->road_type)) || (T && (!d->tri_verts || !d->tri_surface)) ||
+        (E && !d->spawn))
+        return fail(SF_E_INVALID_ARG, "road, triangle or spawn array is NULL");
+    if (d->num_surfaces < 1 || d->num_surfaces > SF_MAX_SURFACES)
+        return fail(SF_E_INVALID_ARG, "num_surfaces must be in 1..16");
+    if (W && !d->mu_class) return fail(SF_E_INVALID_ARG, "mu_class is NULL");
+    for (int k = 0; k < W * d->num_surfaces; ++k)
+        if (!(d->mu_class[k] >= 0.f) || !std::isfinite(d->mu_class[k]))
+            return fail(SF_E_INVALID_ARG, "mu_class must be finite and >= 0");
+    for (int k = 0; k < T; ++k)
+        if (d->tri_surface[k] >= d->num_surfaces)
+            return fail(SF_E_INVALID_ARG, "tri_surface out of range");
+    for (int k = 0; k < 2 * P; ++k)
+        if (!std::isfinite(d->road_xy[k])) return fail(SF_E_INVALID_ARG, "road_xy not finite");
+    for (int k = 0; k < 9 * T; ++k)
+        if (!std::isfinite(d->tri_verts[k])) return fail(SF_E_INVALID_ARG, "tri_verts not finite");
+    for (int k = 0; k < 5 * E; ++k)
+        if (!std::isfinite(d->spawn[k])) return fail(SF_E_INVALID_ARG, "spawn not finite");
+    if (!finite_pos(p->mass) || !finite_pos(p->inertia[0]) || !finite_pos(p->inertia[1]) ||
+        !finite_pos(p->inertia[2]) || !finite_pos(p->wheel_radius) || !finite_pos(p->susp_k) ||
+        !(p->susp_c >= 0.f) || !finite_pos(p->steer_inertia) || !(p->steer_max >= 0.f) ||
+        !(p->v_eps > 0.f) || !(p->gravity >= 0.f) || p->jacobi_iters < 0 || p->jacobi_iters > 64 ||
+        !(p->wheel_inertia > 0.f || p->wheel_mass > 0.f) || !finite_pos(p->length) ||
+        !finite_pos(p->width))
+        return fail(SF_E_INVALID_ARG, "vehicle parameter out of range");
+    if (opts.max_episode_steps <= 0 || opts.collision_warmup < 0)
+        return fail(SF_E_INVALID_ARG, "episode options out of range");
+    if (opts.grid_cell < 0.f || !std::isfinite(opts.grid_cell))
+        return fail(SF_E_INVALID_ARG, "grid_cell must be >= 0");
+
+    sf_sim *sim = new sf_sim();
+    sim->stream = (hipStream_t)opts.stream;
+    sim->alloc = opts.alloc;
+    sim->free_fn = opts.free;
+    sim->alloc_ctx = opts.alloc_ctx;
+    sim->W = W; sim->N = N; sim->P = P; sim->T = T; sim->E = E; sim->S = d->num_surfaces;
+    sim->max_agents = amax;
+    sim->flags = opts.flags;
+    sim->step_block = opts.step_block > 0 ? opts.step_block : (amax <= 16 ? 64 : (amax <= 32 ? 128 : 256));
+    sim->obs_waves = opts.obs_waves > 0 ? opts.obs_waves : 4;
+    sim->policy_rows = opts.policy_rows > 0 ? opts.policy_rows : 64;
+    sim->steer_max = p->steer_max;
+    hipStream_t st = sim->stream;
+
+    // ---- derived constants (double on the host, rounded once)
+    DevParams &Pd = sim->P_dev;
+    Pd.mass = p->mass;
+    Pd.inv_mass = (float)(1.0 / p->mass);
+    for (int c = 0; c < 3; ++c) {
+        Pd.inertia[c] = p->inertia[c];
+        Pd.inv_inertia[c] = (float)(1.0 / p->inertia[c]);
+    }
+    const double rw = p->wheel_radius;
+    Pd.rw = p->wheel_radius;
+    Pd.Iw = p->wheel_inertia > 0.f ? p->wheel_inertia : (float)(0.5 * (double)p->wheel_mass * rw * rw);
+    Pd.susp_k = p->susp_k;
+    Pd.susp_c = p->susp_c;
+    const double ell = (double)p->susp_rest + rw;
+    Pd.ell = (float)ell;
+    std::memcpy(Pd.mount, p->mount, sizeof(Pd.mount));
+    Pd.length = p->length;
+    Pd.width = p->width;
+    // three-circle shape (Sec. "Neighbor vehicles"): r = max(0.45, 0.55 W),
+    // d = min(WB / 2, max(0, L / 2 - 0.8 r))
+    double cr = std::max(0.45, 0.55 * (double)p->width);
+    double cd = std::min(0.5 * (double)p->wheelbase, std::max(0.0, 0.5 * (double)p->length - 0.8 * cr));
+    Pd.cr = (float)cr;
+    Pd.cd = (float)cd;
+    Pd.Qd = (int)std::nearbyint(cd * 1024.0);
+    long long qr2 = 2 * (long long)std::nearbyint(cr * 1024.0);
+    if (qr2 > 46340) { delete sim; return fail(SF_E_UNSUPPORTED, "vehicle too wide"); }
+    Pd.Qr2 = (int)(qr2 * qr2);
+    Pd.tau_drive = p->tau_drive;
+    Pd.tau_bf = p->tau_brake_front;
+    Pd.tau_br = p->tau_brake_rear;
+    Pd.kp = p->steer_kp; Pd.kd = p->steer_kd; Pd.tau_max = p->steer_tau_max;
+    Pd.Is = p->steer_inertia; Pd.steer_max = p->steer_max;
+    Pd.c_kappa = p->c_kappa; Pd.c_alpha = p->c_alpha; Pd.v_eps = p->v_eps; Pd.trail = p->trail;
+    Pd.yaw_damping = p->yaw_damping; Pd.g = p->gravity;
+    Pd.jacobi_iters = p->jacobi_iters; Pd.baumgarte = p->baumgarte; Pd.slop = p->slop;
+    Pd.max_ep = opts.max_episode_steps;
+    Pd.warmup = opts.collision_warmup;
+    Pd.flags = opts.flags;
+    // ride height of a level chassis whose four springs each carry m g / 4
+    Pd.z_ride = (float)(ell - (double)p->mass * p->gravity / (4.0 * p->susp_k) - (double)p->mount[0][2]);
+
+#define ALLOC(ptr, type, count)                                                   \
+    do {                                                                          \
+        ptr = (type *)dev_alloc(sim, sizeof(type) * (size_t)(count));             \
+        if (!ptr) {                                                               \
+            free_all(sim);                                                        \
+            delete sim;                                                           \
+            return fail(SF_E_OUT_OF_MEMORY, "device allocation of " #ptr " failed"); \
+        }                                                                         \
+    } while (0)
+#define H2D(dst, src, bytes)                                                                 \
+    do {                                                                                     \
+        if ((bytes) > 0) {                                                                   \
+            hipError_t e_ = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);      \
+            if (e_ != hipSuccess) {                                                          \
+                free_all(sim);                                                               \
+                delete sim;                                                                  \
+                return fail(SF_E_DEVICE, std::string("upload: ") + hipGetErrorString(e_));  \
+            }                                                                                \
+        }                                                                                    \
+    } while (0)
+
+    int *aoff, *roff, *toff, *soff, *world_of;
+    float2 *road_xy; int2 *road_q; uint8_t *road_type;
+    float *verts; uint8_t *tsurf; float4 *tri;
+    float *mu_class, *film = nullptr, *mu; uint8_t *pav = nullptr;
+    float *spawn;
+    GridHdr *grid;
+    float4 *bbox;
+    ALLOC(aoff, int, W + 1); ALLOC(roff, int, W + 1); ALLOC(toff, int, W + 1); ALLOC(soff, int, W + 1);
+    ALLOC(world_of, int, N);
+    ALLOC(road_xy, float2, P); ALLOC(road_q, int2, P); ALLOC(road_type, uint8_t, P);
+    ALLOC(verts, float, 9 * (size_t)T); ALLOC(tsurf, uint8_t, T); ALLOC(tri, float4, 4 * (size_t)T);
+    ALLOC(mu_class, float, (size_t)W * sim->S); ALLOC(mu, float, (size_t)W * sim->S);
+    if (d->film_mm) ALLOC(film, float, W);
+    if (d->pavement) ALLOC(pav, uint8_t, W);
+    ALLOC(spawn, float, 5 * (size_t)E);
+    ALLOC(grid, GridHdr, W);
+    ALLOC(bbox, float4, W);
+    H2D(aoff, d->agent_offsets, sizeof(int) * (W + 1));
+    H2D(roff, d->road_offsets, sizeof(int) * (W + 1));
+    H2D(toff, d->tri_offsets, sizeof(int) * (W + 1));
+    H2D(soff, d->spawn_offsets, sizeof(int) * (W + 1));
+    H2D(road_xy, d->road_xy, sizeof(float) * 2 * (size_t)P);
+    H2D(road_type, d->road_type, (size_t)P);
+    H2D(verts, d->tri_verts, sizeof(float) * 9 * (size_t)T);
+    H2D(tsurf, d->tri_surface, (size_t)T);
+    H2D(mu_class, d->mu_class, sizeof(float) * (size_t)W * sim->S);
+    if (film) H2D(film, d->film_mm, sizeof(float) * W);
+    if (pav) H2D(pav, d->pavement, (size_t)W);
+    H2D(spawn, d->spawn, sizeof(float) * 5 * (size_t)E);
+
+    DevWorld &Wd = sim->Wd;
+    Wd.W = W; Wd.N = N; Wd.S = sim->S;
+    Wd.aoff = aoff; Wd.roff = roff; Wd.toff = toff; Wd.soff = soff;
+    Wd.world_of = world_of;
+    Wd.road_xy = road_xy; Wd.road_q = road_q; Wd.road_type = road_type;
+    Wd.tri = tri; Wd.mu = mu; Wd.spawn = spawn; Wd.grid = grid;
+    Wd.seed = d->seed;
+
+    launch_weather_mu(mu_class, film, pav, W, sim->S, mu, st);
+    launch_quantise_roads(road_xy, road_q, P, st);
+    launch_prep_tris(verts, tsurf, tri, T, st);
+    launch_world_of(aoff, W, world_of, st);
+    launch_world_bbox(roff, road_xy, toff, verts, W, bbox, st);
+    LAUNCHED();
+
+    // ---- grid headers on the host from the device bounding boxes
+    std::vector<float4> hb(W);
+    if (W) DEV(hipMemcpyAsync(hb.data(), bbox, sizeof(float4) * W, hipMemcpyDeviceToHost, st));
+    DEV(hipStreamSynchronize(st));
+    const float cell0 = opts.grid_cell > 0.f ? opts.grid_cell : 4.f;
+    std::vector<GridHdr> hg(W);
+    long long C = 0;
+    for (int w = 0; w < W; ++w) {
+        GridHdr g{};
+        float4 b = hb[w];
+        if (!(b.x <= b.z) || !(b.y <= b.w)) { b = make_float4(0.f, 0.f, 0.f, 0.f); }
+        float cell = cell0;
+        const float ext = std::max(b.z - b.x, b.w - b.y);
+        if (ext / cell > 2048.f) cell = ext / 2048.f;
+        g.x0 = b.x; g.y0 = b.y; g.cell = cell; g.inv_cell = 1.f / cell;
+        g.nx = std::max(1, (int)std::ceil((b.z - b.x) * g.inv_cell));
+        g.ny = std::max(1, (int)std::ceil((b.w - b.y) * g.inv_cell));
+        g.cbase = (int)C;
+        C += (long long)g.nx * g.ny;
+        hg[w] = g;
+    }
+    if (C > (1ll << 30)) { free_all(sim); delete sim; return fail(SF_E_UNSUPPORTED, "road grid too large"); }
+    sim->C = (int)C;
+    H2D(grid, hg.data(), sizeof(GridHdr) * W);
+    int *tri_cnt, *pt_cnt, *tri_start, *pt_start, *scan_tmp, *pt_items, *tri_cursor, *pt_cursor;
+    ALLOC(tri_cnt, int, C); ALLOC(pt_cnt, int, C);
+    ALLOC(tri_start, int, C + 1); ALLOC(pt_start, int, C + 1);
+    ALLOC(scan_tmp, int, C / 1024 + 2);
+    ALLOC(tri_cursor, int, C + 1); ALLOC(pt_cursor, int, C + 1);
+    DEV(hipMemsetAsync(tri_cnt, 0, sizeof(int) * C, st));
+    DEV(hipMemsetAsync(pt_cnt, 0, sizeof(int) * C, st));
+    launch_grid_count(Wd, verts, tri_cnt, pt_cnt, st);
+    launch_scan(tri_cnt, tri_start, (int)C, scan_tmp, st);
+    launch_scan(pt_cnt, pt_start, (int)C, scan_tmp, st);
+    LAUNCHED();
+    int n_tri_items = 0;
+    DEV(hipMemcpyAsync(&n_tri_items, tri_start + C, sizeof(int), hipMemcpyDeviceToHost, st));
+    DEV(hipStreamSynchronize(st));
+    int *tri_items;
+    int4 *pt_cell;
+    ALLOC(tri_items, int, n_tri_items);
+    ALLOC(pt_items, int, P);
+    ALLOC(pt_cell, int4, P);
+    DEV(hipMemcpyAsync(tri_cursor, tri_start, sizeof(int) * (C + 1), hipMemcpyDeviceToDevice, st));
+    DEV(hipMemcpyAsync(pt_cursor, pt_start, sizeof(int) * (C + 1), hipMemcpyDeviceToDevice, st));
+    Wd.tri_cell_start = tri_start; Wd.tri_items = tri_items;
+    Wd.pt_cell_start = pt_start; Wd.pt_cell = pt_cell;
+    launch_grid_fill(Wd, verts, tri_cursor, pt_cursor, tri_items, pt_items, st);
+    launch_grid_finish(Wd, (int)C, tri_items, pt_items, pt_cell, st);
+    LAUNCHED();
+
+    // ---- state, outputs, schedule
+    const size_t nst = (size_t)SF_NUM_FFIELDS * N + (size_t)SF_NUM_IFIELDS * N;
+    float *stbuf;
+    ALLOC(stbuf, float, nst);
+    sim->st = stbuf;
+    sim->ist = reinterpret_cast<int *>(stbuf + (size_t)SF_NUM_FFIELDS * N);
+    DEV(hipMemsetAsync(stbuf, 0, sizeof(float) * nst, st));
+    ALLOC(sim->obs, float, (size_t)N * SF_OBS_DIM);
+    ALLOC(sim->reward, float, N);
+    ALLOC(sim->done, uint8_t, N);
+    ALLOC(sim->events, uint8_t, N);
+    DEV(hipMemsetAsync(sim->reward, 0, sizeof(float) * N, st));
+    DEV(hipMemsetAsync(sim->done, 0, N, st));
+    DEV(hipMemsetAsync(sim->events, 0, N, st));
+    // longest-processing-time-first world order: bigger worlds start first
+    std::vector<int> ord(W);
+    for (int w = 0; w < W; ++w) ord[w] = w;
+    auto cost = [&](int w) {
+        long long a = d->agent_offsets[w + 1] - d->agent_offsets[w];
+        return a * (8 + a);
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    ALLOC(sim->order, int, W);
+    H2D(sim->order, ord.data(), sizeof(int) * W);
+    if (opts.flags & SF_RECORD_CONTACTS) {
+        sim->rec_cap = std::max(1, amax * (amax - 1) / 2);
+        ALLOC(sim->rec, uint32_t, (size_t)SF_MAX_SUBSTEPS * W * sim->rec_cap);
+        ALLOC(sim->rec_cnt, int, (size_t)SF_MAX_SUBSTEPS * W);
+        DEV(hipMemsetAsync(sim->rec_cnt, 0, sizeof(int) * SF_MAX_SUBSTEPS * W, st));
+    }
+    launch_reset(Pd, Wd, sim->st, sim->ist, nullptr, 0, st);
+    launch_obs(Pd, Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, st);
+    LAUNCHED();
+    DEV(hipStreamSynchronize(st));
+    *out = sim;
+    return SF_OK;
+#undef ALLOC
+#undef H2D
+}
+
+sf_status sf_destroy(sf_sim *sim) {
+    if (!sim) return fail(SF_E_INVALID_ARG, "sim is NULL");
+    if (sim->stream) (void)hipStreamSynchronize(sim->stream);
+    else (void)hipDeviceSynchronize();
+    if (sim->graph_exec) (void)hipGraphExecDestroy(sim->graph_exec);
+    if (sim->graph) (void)hipGraphDestroy(sim->graph);
+    for (auto &r : sim->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : sim->pool) (void)hipEventDestroy(e);
+    free_all(sim);
+    delete sim;
+    return SF_OK;
+}
+
+sf_status sf_info(const sf_sim *sim, int32_t *W, int32_t *N, int32_t *amax) {
+    if (!sim) return fail(SF_E_INVALID_ARG, "sim is NULL");
+    if (W) *W = sim->W;
+    if (N) *N = sim->N;
+    if (amax) *amax = sim->max_agents;
+    return SF_OK;
+}
+
+#define CHECK_SIM(sim)                                                           \
+    do {                                                                         \
+        if (!(sim)) return fail(SF_E_INVALID_ARG, "sim is NULL");                \
+        if ((sim)->bad) return fail(SF_E_BAD_STATE, "handle had a device error"); \
+    } while (0)
+
+sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substeps) {
+    CHECK_SIM(sim);
+    if (substeps < 1 || substeps > SF_MAX_SUBSTEPS) return fail(SF_E_INVALID_ARG, "substeps must be 1..16");
+    if (!(dt > 0.f) || !std::isfinite(dt)) return fail(SF_E_INVALID_ARG, "dt must be finite and > 0");
+    if (sim->N > 0 && !d_actions) return fail(SF_E_INVALID_ARG, "actions is NULL");
+    const float h = dt / (float)substeps;
+    {
+        ProfScope ps(sim, 1);
+        launch_step(sim->P_dev, sim->Wd, sim->st, sim->ist, d_actions, h, substeps, sim->reward, sim->done,
+                    sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->order, sim->step_block, sim->stream);
+    }
+    {
+        ProfScope ps(sim, 2);
+        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, sim->stream);
+    }
+    LAUNCHED();
+    sim->last_substeps = substeps;
+    return SF_OK;
+}
+
+static void enqueue_policy(sf_sim *sim, float *d_act) {
+    const uint16_t *W1 = sim->pol_bf16, *W2 = W1 + 256 * 256, *W3 = W2 + 256 * 256;
+    const float *b1 = sim->pol_f32 + 256 * 256, *b2 = b1 + 256 + 256 * 256, *b3 = b2 + 256 + 2 * 256;
+    ProfScope ps(sim, 0);
+    launch_policy(sim->obs, sim->N, W1, b1, W2, b2, W3, b3, sim->steer_max, d_act, sim->policy_rows,
+                  sim->stream);
+}
+
+sf_status sf_policy_load(sf_sim *sim, const float *h, size_t n) {
+    CHECK_SIM(sim);
+    if (!h || n != SF_POLICY_PARAMS) return fail(SF_E_INVALID_ARG, "policy parameters must be 132098 floats");
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(h[k])) return fail(SF_E_INVALID_ARG, "policy parameters must be finite");
+    if (!sim->pol_f32) {
+        sim->pol_f32 = (float *)dev_alloc(sim, sizeof(float) * n);
+        sim->pol_bf16 = (uint16_t *)dev_alloc(sim, sizeof(uint16_t) * (2 * 256 * 256 + 2 * 256));
+        sim->pol_act = (float *)dev_alloc(sim, sizeof(float) * 2 * (size_t)std::max(sim->N, 1));
+        if (!sim->pol_f32 || !sim->pol_bf16 || !sim->pol_act) return fail(SF_E_OUT_OF_MEMORY, "policy buffers");
+    }
+    DEV(hipMemcpyAsync(sim->pol_f32, h, sizeof(float) * n, hipMemcpyHostToDevice, sim->stream));
+    // bf16 copies of the three weight matrices (biases stay fp32)
+    const size_t w1 = 0, w2 = 256 * 256 + 256, w3 = w2 + 256 * 256 + 256;
+    launch_to_bf16(sim->pol_f32 + w1, sim->pol_bf16, 256 * 256, sim->stream);
+    launch_to_bf16(sim->pol_f32 + w2, sim->pol_bf16 + 256 * 256, 256 * 256, sim->stream);
+    launch_to_bf16(sim->pol_f32 + w3, sim->pol_bf16 + 2 * 256 * 256, 2 * 256, sim->stream);
+    LAUNCHED();
+    DEV(hipStreamSynchronize(sim->stream));
+    sim->policy_loaded = true;
+    return SF_OK;
+}
+
+sf_status sf_policy_act(sf_sim *sim, float *d_actions) {
+    CHECK_SIM(sim);
+    if (!sim->policy_loaded) return fail(SF_E_INVALID_ARG, "no policy loaded");
+    if (sim->N > 0 && !d_actions) return fail(SF_E_INVALID_ARG, "actions is NULL");
+    enqueue_policy(sim, d_actions);
+    LAUNCHED();
+    return SF_OK;
+}
+
+sf_status sf_step_policy(sf_sim *sim, float dt, int32_t substeps) {
+    CHECK_SIM(sim);
+    if (!sim->policy_loaded) return fail(SF_E_INVALID_ARG, "no policy loaded");
+    enqueue_policy(sim, sim->pol_act);
+    LAUNCHED();
+    return sf_step(sim, sim->pol_act, dt, substeps);
+}
+
+sf_status sf_graph_capture(sf_sim *sim, int32_t K, float dt, int32_t substeps) {
+    CHECK_SIM(sim);
+    if (!sim->stream) return fail(SF_E_UNSUPPORTED, "graph capture needs a non-null stream");
+    if (!sim->policy_loaded) return fail(SF_E_INVALID_ARG, "no policy loaded");
+    if (K < 1 || K > 4096) return fail(SF_E_INVALID_ARG, "control_steps must be 1..4096");
+    if (substeps < 1 || substeps > SF_MAX_SUBSTEPS || !(dt > 0.f))
+        return fail(SF_E_INVALID_ARG, "bad dt or substeps");
+    if (sim->graph_exec) { (void)hipGraphExecDestroy(sim->graph_exec); sim->graph_exec = nullptr; }
+    if (sim->graph) { (void)hipGraphDestroy(sim->graph); sim->graph = nullptr; }
+    const bool prof = sim->prof;
+    sim->prof = false;
+    DEV(hipStreamBeginCapture(sim->stream, hipStreamCaptureModeThreadLocal));
+    sf_status st = SF_OK;
+    for (int k = 0; k < K && st == SF_OK; ++k) st = sf_step_policy(sim, dt, substeps);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(sim->stream, &g);
+    sim->prof = prof;
+    if (st != SF_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) { sim->bad = true; return fail(SF_E_DEVICE, std::string("capture: ") + hipGetErrorString(e)); }
+    sim->graph = g;
+    DEV(hipGraphInstantiate(&sim->graph_exec, g, nullptr, nullptr, 0));
+    return SF_OK;
+}
+
+sf_status sf_graph_launch(sf_sim *sim) {
+    CHECK_SIM(sim);
+    if (!sim->graph_exec) return fail(SF_E_INVALID_ARG, "no graph captured");
+    DEV(hipGraphLaunch(sim->graph_exec, sim->stream));
+    return SF_OK;
+}
+
+sf_status sf_profile(sf_sim *sim, int32_t enable) {
+    CHECK_SIM(sim);
+    DEV(hipStreamSynchronize(sim->stream));
+    for (auto &r : sim->recs) { sim->pool.push_back(r.a); sim->pool.push_back(r.b); }
+    sim->recs.clear();
+    sim->prof = enable != 0;
+    return SF_OK;
+}
+
+sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches) {
+    CHECK_SIM(sim);
+    if (!total_ms || !launches) return fail(SF_E_INVALID_ARG, "NULL output");
+    DEV(hipStreamSynchronize(sim->stream));
+    for (int k = 0; k < SF_PROF_KERNELS; ++k) { total_ms[k] = 0.0; launches[k] = 0; }
+    for (auto &r : sim->recs) {
+        float ms = 0.f;
+        DEV(hipEventElapsedTime(&ms, r.a, r.b));
+        total_ms[r.kind] += ms;
+        launches[r.kind] += 1;
+    }
+    return SF_OK;
+}
+
+sf_status sf_observe(sf_sim *sim, float *d_obs, float *d_reward, uint8_t *d_done, uint8_t *d_events) {
+    CHECK_SIM(sim);
+    const size_t N = sim->N;
+    if (N == 0) return SF_OK;
+    if (d_obs) DEV(hipMemcpyAsync(d_obs, sim->obs, sizeof(float) * N * SF_OBS_DIM, hipMemcpyDeviceToDevice, sim->stream));
+    if (d_reward) DEV(hipMemcpyAsync(d_reward, sim->reward, sizeof(float) * N, hipMemcpyDeviceToDevice, sim->stream));
+    if (d_done) DEV(hipMemcpyAsync(d_done, sim->done, N, hipMemcpyDeviceToDevice, sim->stream));
+    if (d_events) DEV(hipMemcpyAsync(d_events, sim->events, N, hipMemcpyDeviceToDevice, sim->stream));
+    return SF_OK;
+}
+
+sf_status sf_output_ptrs(sf_sim *sim, float **obs, float **reward, uint8_t **done, uint8_t **events) {
+    CHECK_SIM(sim);
+    if (obs) *obs = sim->obs;
+    if (reward) *reward = sim->reward;
+    if (done) *done = sim->done;
+    if (events) *events = sim->events;
+    return SF_OK;
+}
+
+sf_status sf_reset(sf_sim *sim, const uint8_t *d_mask) {
+    CHECK_SIM(sim);
+    if (sim->N > 0 && !d_mask) return fail(SF_E_INVALID_ARG, "mask is NULL");
+    {
+        ProfScope ps(sim, 3);
+        launch_reset(sim->P_dev, sim->Wd, sim->st, sim->ist, d_mask, 1, sim->stream);
+    }
+    {
+        ProfScope ps(sim, 2);
+        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, sim->stream);
+    }
+    LAUNCHED();
+    return SF_OK;
+}
+
+size_t sf_state_bytes(const sf_sim *sim) {
+    if (!sim) return 0;
+    return ((size_t)SF_NUM_FFIELDS + SF_NUM_IFIELDS) * 4 * (size_t)sim->N;
+}
+
+sf_status sf_get_state(sf_sim *sim, void *host_dst, size_t bytes) {
+    CHECK_SIM(sim);
+    if (!host_dst || bytes != sf_state_bytes(sim))
+        return fail(SF_E_INVALID_ARG, "host_dst NULL or bytes != sf_state_bytes");
+    if (bytes) DEV(hipMemcpyAsync(host_dst, sim->st, bytes, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    return SF_OK;
+}
+
+sf_status sf_set_state(sf_sim *sim, const void *host_src, size_t bytes) {
+    CHECK_SIM(sim);
+    if (!host_src || bytes != sf_state_bytes(sim))
+        return fail(SF_E_INVALID_ARG, "host_src NULL or bytes != sf_state_bytes");
+    if (bytes) DEV(hipMemcpyAsync(sim->st, host_src, bytes, hipMemcpyHostToDevice, sim->stream));
+    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, sim->stream);
+    LAUNCHED();
+    DEV(hipStreamSynchronize(sim->stream));
+    return SF_OK;
+}
+
+sf_status sf_get_contacts(sf_sim *sim, int32_t substep, int32_t *h_counts, uint32_t *h_pairs, int32_t cap) {
+    CHECK_SIM(sim);
+    if (!(sim->flags & SF_RECORD_CONTACTS)) return fail(SF_E_UNSUPPORTED, "created without SF_RECORD_CONTACTS");
+    if (substep < 0 || substep >= sim->last_substeps) return fail(SF_E_INVALID_ARG, "substep out of range");
+    if (!h_counts || !h_pairs || cap < sim->rec_cap) return fail(SF_E_INVALID_ARG, "bad output buffers");
+    const int W = sim->W;
+    std::vector<uint32_t> tmp((size_t)W * sim->rec_cap);
+    DEV(hipMemcpyAsync(h_counts, sim->rec_cnt + (size_t)substep * W, sizeof(int) * W, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipMemcpyAsync(tmp.data(), sim->rec + (size_t)substep * W * sim->rec_cap, sizeof(uint32_t) * tmp.size(),
+                       hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    for (int w = 0; w < W; ++w)
+        std::memcpy(h_pairs + (size_t)w * cap, tmp.data() + (size_t)w * sim->rec_cap, sizeof(uint32_t) * sim->rec_cap);
+    return SF_OK;
+}
+
+sf_status sf_debug_raycast(sf_sim *sim, float *h_out) {
+    CHECK_SIM(sim);
+    if (!h_out) return fail(SF_E_INVALID_ARG, "h_out is NULL");
+    if (sim->N == 0) return SF_OK;
+    float *buf = nullptr;
+    DEV(hipMalloc(&buf, sizeof(float) * 16 * (size_t)sim->N));
+    launch_debug_raycast(sim->P_dev, sim->Wd, sim->st, buf, sim->stream);
+    LAUNCHED();
+    DEV(hipMemcpyAsync(h_out, buf, sizeof(float) * 16 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    DEV(hipFree(buf));
+    return SF_OK;
+}
+
+sf_status sf_debug_obs_indices(sf_sim *sim, int32_t *h_out) {
+    CHECK_SIM(sim);
+    if (!h_out) return fail(SF_E_INVALID_ARG, "h_out is NULL");
+    if (sim->N == 0) return SF_OK;
+    int *buf = nullptr;
+    DEV(hipMalloc(&buf, sizeof(int) * 72 * (size_t)sim->N));
+    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, buf, sim->obs_waves, sim->stream);
+    LAUNCHED();
+    DEV(hipMemcpyAsync(h_out, buf, sizeof(int) * 72 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    DEV(hipFree(buf));
+    return SF_OK;
+}
+
+}  // extern "C"

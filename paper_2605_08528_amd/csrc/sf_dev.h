@@ -1,0 +1,183 @@
+// Device-side definitions of the batched driving-physics step (gfx950).
+//
+// Layout in HBM
+//   state   : float [SF_NUM_FFIELDS][N] and int32 [SF_NUM_IFIELDS][N]
+//             (structure of arrays: lane-contiguous loads per field)
+//   worlds  : CSR offsets [W+1] for agents, road points, triangles, spawns
+//   roads   : float2 xy [P], int2 quantised xy [P], u8 type [P]
+//   tris    : float4 [T][4] = (v0, surface) (e1, 0) (e2, 0) (unit normal, 0)
+//   grid    : per world a uniform xy grid; cells of all worlds are numbered
+//             globally (world w owns [cbase, cbase + nx*ny)); two CSR lists
+//             over cells: triangle ids, and road points packed as
+//             (quantised x, quantised y, local index) in cell order
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sf.h"
+
+#define SF_MAXA SF_MAX_AGENTS_PER_WORLD
+#define SF_CCAP 512      // contact points per world and substep
+#define SF_BCAP 32       // contact points per body and substep
+#define SF_PAIR_CAP (SF_MAXA * (SF_MAXA - 1) / 2)
+#define SF_KEY_CAP (1ll << 43)   // saturation of kNN squared distances
+#define SF_CAND_CAP 1024          // road candidates kept per agent
+
+struct GridHdr {
+    float x0, y0, cell, inv_cell;
+    int nx, ny, cbase, pad;
+};
+
+// Constants of the step (derived on the host at create, passed by value).
+struct DevParams {
+    float mass, inv_mass;
+    float inertia[3], inv_inertia[3];
+    float rw, Iw, susp_k, susp_c, ell;
+    float mount[4][3];
+    float length, width, cr, cd;
+    int Qd, Qr2;                   // quantised circle offset, (2 Qp(r))^2 (fits int32)
+    float tau_drive, tau_bf, tau_br;
+    float kp, kd, tau_max, Is, steer_max;
+    float c_kappa, c_alpha, v_eps, trail, yaw_damping, g;
+    int jacobi_iters;
+    float baumgarte, slop;
+    int max_ep, warmup;
+    unsigned flags;
+    float z_ride;
+};
+
+struct DevWorld {
+    int W, N, S;
+    const int *aoff, *roff, *toff, *soff;
+    const int *world_of;                 // [N]
+    const float2 *road_xy;               // [P]
+    const int2 *road_q;                  // [P]
+    const uint8_t *road_type;            // [P]
+    const float4 *tri;                   // [T][4]
+    const float *mu;                     // [W][S]
+    const float *spawn;                  // [E][5]
+    const GridHdr *grid;                 // [W]
+    const int *tri_cell_start;           // [C+1]
+    const int *tri_items;                // world-local triangle ids
+    const int *pt_cell_start;            // [C+1]
+    const int4 *pt_cell;                 // (qx, qy, local idx, 0) in cell order
+    unsigned long long seed;
+};
+
+// ------------------------------------------------------------ quantisers
+// positions in units of 2^-10 m, nearest-even, saturating at 2^29
+__device__ __forceinline__ int qpos(float x) {
+    float y = x * 1024.0f;
+    if (y != y) return 0;
+    if (y >= 536870912.0f) return 536870912;
+    if (y <= -536870912.0f) return -536870912;
+    return (int)rintf(y);
+}
+// quaternion components in units of 2^-14
+__device__ __forceinline__ int qquat(float x) {
+    float y = x * 16384.0f;
+    if (y != y) return 0;
+    if (y >= 32768.0f) return 32768;
+    if (y <= -32768.0f) return -32768;
+    return (int)rintf(y);
+}
+// floor(sqrt(v)) for 0 <= v < 2^62: a double estimate corrected by integers
+__device__ __forceinline__ long long isqrt64(long long v) {
+    long long r = (long long)sqrt((double)v);
+    while (r > 0 && r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014)
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ long long sat_key(long long d2) {
+    return d2 < SF_KEY_CAP ? d2 : SF_KEY_CAP - 1;
+}
+
+// ------------------------------------------------------------ small math
+struct f3 { float x, y, z; };
+__device__ __forceinline__ f3 mk3(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 add3(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 sub3(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 mul3(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross3(f3 a, f3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+// rotation matrix (row major) of a unit quaternion (w, x, y, z)
+__device__ __forceinline__ void quat_R(float w, float x, float y, float z, float R[9]) {
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+}
+__device__ __forceinline__ f3 Rmul(const float R[9], f3 a) {
+    return {R[0] * a.x + R[1] * a.y + R[2] * a.z, R[3] * a.x + R[4] * a.y + R[5] * a.z,
+            R[6] * a.x + R[7] * a.y + R[8] * a.z};
+}
+__device__ __forceinline__ f3 RTmul(const float R[9], f3 a) {
+    return {R[0] * a.x + R[3] * a.y + R[6] * a.z, R[1] * a.x + R[4] * a.y + R[7] * a.z,
+            R[2] * a.x + R[5] * a.y + R[8] * a.z};
+}
+
+// Spawn of agent n (world w, world-local slot j) for its current episode:
+// the world's spawn entries rotated by SplitMix64(seed ^ w << 32 ^ episode).
+__device__ __forceinline__ void spawn_agent(const DevParams &P, const DevWorld &Wd, float *st,
+                                            int *ist, int N, int n, int w, int j) {
+    int s0 = Wd.soff[w], M = Wd.soff[w + 1] - s0;
+    unsigned long long e = (unsigned long long)(unsigned)ist[SF_I_EPISODE * N + n];
+    unsigned long long key = Wd.seed ^ ((unsigned long long)(unsigned)w << 32) ^ e;
+    int off = (int)(splitmix64(key) % (unsigned long long)M);
+    const float *sp = Wd.spawn + 5 * (size_t)(s0 + (j + off) % M);
+    float yaw = sp[2];
+    st[SF_F_PX * N + n] = sp[0];
+    st[SF_F_PY * N + n] = sp[1];
+    st[SF_F_PZ * N + n] = P.z_ride;
+    st[SF_F_QW * N + n] = cosf(0.5f * yaw);
+    st[SF_F_QX * N + n] = 0.f;
+    st[SF_F_QY * N + n] = 0.f;
+    st[SF_F_QZ * N + n] = sinf(0.5f * yaw);
+    for (int c = SF_F_VX; c <= SF_F_MU; ++c) st[c * N + n] = 0.f;
+    st[SF_F_GOAL_X * N + n] = sp[3];
+    st[SF_F_GOAL_Y * N + n] = sp[4];
+    st[SF_F_START_X * N + n] = sp[0];
+    st[SF_F_START_Y * N + n] = sp[1];
+    ist[SF_I_ACTIVE * N + n] = 1;
+    ist[SF_I_EP_STEP * N + n] = 0;
+    ist[SF_I_SINCE_SPAWN * N + n] = 0;
+}
+
+// kernel launchers (defined in the .hip files)
+void launch_weather_mu(const float *mu_class, const float *film, const uint8_t *pav, int W, int S,
+                       float *mu_out, hipStream_t st);
+void launch_quantise_roads(const float2 *xy, int2 *q, int P, hipStream_t st);
+void launch_prep_tris(const float *verts, const uint8_t *surf, float4 *tri, int T, hipStream_t st);
+void launch_world_bbox(const int *roff, const float2 *xy, const int *toff, const float *verts, int W,
+                       float4 *bbox, hipStream_t st);
+void launch_grid_count(const DevWorld &Wd, const float *verts, int *tri_cnt, int *pt_cnt,
+                       hipStream_t st);
+void launch_grid_fill(const DevWorld &Wd, const float *verts, int *tri_cursor, int *pt_cursor,
+                      int *tri_items, int *pt_items, hipStream_t st);
+void launch_grid_finish(const DevWorld &Wd, int C, int *tri_items, int *pt_items, int4 *pt_cell,
+                        hipStream_t st);
+void launch_scan(const int *in, int *out, int n, int *tmp, hipStream_t st);  // exclusive, out[n]
+void launch_world_of(const int *aoff, int W, int *world_of, hipStream_t st);
+void launch_reset(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const uint8_t *mask,
+                  int bump_episode, hipStream_t s);
+void launch_step(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act,
+                 float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
+                 int *rec_cnt, int rec_cap, const int *order, int block, hipStream_t s);
+void launch_obs(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
+                int *dbg_idx, int waves, hipStream_t s);
+void launch_to_bf16(const float *src, uint16_t *dst, int n, hipStream_t s);
+void launch_policy(const float *obs, int N, const uint16_t *W1, const float *b1, const uint16_t *W2,
+                   const float *b2, const uint16_t *W3, const float *b3, float steer_max, float *act,
+                   int tm, hipStream_t s);
+void launch_debug_raycast(const DevParams &P, const DevWorld &Wd, const float *st, float *out,
+                          hipStream_t s);

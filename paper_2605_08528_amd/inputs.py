@@ -202,9 +202,18 @@ def _spawn_table(rng, lanes, count, min_sep, headway=None, max_tries=20000, min_
     (never past its end), hence always >= 3 m from the start."""
     out = []
 
-    def ok(p):
+    def ok(p, d):
+        # same lane: at least min_sep apart; parallel neighbouring lanes:
+        # 3 m (lanes are 3.5 m apart, wider than two circle radii); crossing
+        # lanes: 4.6 m, enough that no two vehicle circles overlap
         for e in out:
-            if (e[0] - p[0]) ** 2 + (e[1] - p[1]) ** 2 < min_sep ** 2:
+            dx, dy = e[0] - p[0], e[1] - p[1]
+            dist = math.hypot(dx, dy)
+            ex, ey = math.cos(e[2]), math.sin(e[2])
+            parallel = abs(ex * d[0] + ey * d[1]) > 0.99
+            lateral = abs(d[0] * dy - d[1] * dx)
+            need = (min_sep if lateral < 1.0 else 3.0) if parallel else 4.6
+            if dist < need:
                 return False
         return True
 
@@ -223,7 +232,7 @@ def _spawn_table(rng, lanes, count, min_sep, headway=None, max_tries=20000, min_
             s = rng.uniform(0.5, headway[1])
             while lane[2] - s >= 10.0:
                 p = lane[0] + s * lane[1]
-                if ok(p):
+                if ok(p, lane[1]):
                     out.append(entry(lane, s))
                     if len(out) >= count:
                         return np.array(out, np.float32)
@@ -244,7 +253,7 @@ def _spawn_table(rng, lanes, count, min_sep, headway=None, max_tries=20000, min_
             continue
         s = rng.uniform(0.0, lane[2] - 10.0)
         p = lane[0] + s * lane[1]
-        if ok(p):
+        if ok(p, lane[1]):
             out.append(entry(lane, s))
     return np.array(out, np.float32)
 
@@ -352,7 +361,7 @@ def intersections(num_worlds=64, agents=8, seed=0, headway=None, min_sep=8.0,
         road = _intersection(rng)
         roads.append(road)
         if headway is not None:
-            spawns.append(_spawn_table(rng, road.lanes, agents, 5.0, headway=headway))
+            spawns.append(_spawn_table(rng, road.lanes, agents, headway[0], headway=headway))
         else:
             spawns.append(_spawn_table(rng, road.lanes, spawn_factor * agents, min_sep))
         film.append(0.8 * rng.uniform(0.0, 1.0) if rain else 0.0)

@@ -1,0 +1,328 @@
+"""ctypes binding of ``libsf.so`` (the C ABI in ``include/sf.h``).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory (tensors passed
+as raw pointers) and the stream.  Loading fails loudly when the library has
+not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsf.so")
+
+SF_INVINCIBLE, SF_AUTO_RESET, SF_RECORD_CONTACTS = 1, 2, 4
+EV_GOAL, EV_COLLISION, EV_CRASH, EV_TIMEOUT, EV_NUMERIC, EV_NAN_ACTION = 1, 2, 4, 8, 16, 32
+NF, NI, OBS_DIM = 24, 4, 256
+FIELDS = ["px", "py", "pz", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
+          "om0", "om1", "om2", "om3", "steer", "steer_rate", "mu", "goal_x", "goal_y",
+          "start_x", "start_y"]
+IFIELDS = ["active", "ep_step", "since_spawn", "episode"]
+
+
+class VehicleParams(C.Structure):
+    _fields_ = [
+        ("mass", C.c_float), ("inertia", C.c_float * 3),
+        ("wheel_radius", C.c_float), ("wheel_mass", C.c_float), ("wheel_inertia", C.c_float),
+        ("susp_k", C.c_float), ("susp_c", C.c_float), ("susp_rest", C.c_float),
+        ("mount", (C.c_float * 3) * 4),
+        ("length", C.c_float), ("width", C.c_float), ("wheelbase", C.c_float),
+        ("tau_drive", C.c_float), ("tau_brake_front", C.c_float), ("tau_brake_rear", C.c_float),
+        ("steer_kp", C.c_float), ("steer_kd", C.c_float), ("steer_tau_max", C.c_float),
+        ("steer_inertia", C.c_float), ("steer_max", C.c_float),
+        ("c_kappa", C.c_float), ("c_alpha", C.c_float), ("v_eps", C.c_float),
+        ("trail", C.c_float), ("yaw_damping", C.c_float), ("gravity", C.c_float),
+        ("jacobi_iters", C.c_int32), ("baumgarte", C.c_float), ("slop", C.c_float),
+    ]
+
+
+class WorldDesc(C.Structure):
+    _fields_ = [
+        ("num_worlds", C.c_int32),
+        ("agent_offsets", C.c_void_p),
+        ("road_offsets", C.c_void_p), ("road_xy", C.c_void_p), ("road_type", C.c_void_p),
+        ("tri_offsets", C.c_void_p), ("tri_verts", C.c_void_p), ("tri_surface", C.c_void_p),
+        ("num_surfaces", C.c_int32), ("mu_class", C.c_void_p),
+        ("film_mm", C.c_void_p), ("pavement", C.c_void_p),
+        ("spawn_offsets", C.c_void_p), ("spawn", C.c_void_p),
+        ("seed", C.c_uint64),
+    ]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
+        ("max_episode_steps", C.c_int32), ("collision_warmup", C.c_int32),
+        ("flags", C.c_uint32), ("grid_cell", C.c_float),
+        ("step_block", C.c_int32), ("obs_waves", C.c_int32), ("policy_rows", C.c_int32),
+        ("reserved", C.c_int32 * 5),
+    ]
+
+
+class SFError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libsf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SFError(f"{LIB_PATH} is missing: build it with paper_2605_08528_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, st = C.c_void_p, C.c_int32, C.c_int
+        L.sf_default_params.argtypes = [C.POINTER(VehicleParams)]
+        L.sf_default_options.argtypes = [C.POINTER(Options)]
+        L.sf_create.argtypes = [C.POINTER(WorldDesc), C.POINTER(VehicleParams), C.POINTER(Options),
+                                C.POINTER(vp)]
+        L.sf_destroy.argtypes = [vp]
+        L.sf_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.sf_step.argtypes = [vp, vp, C.c_float, i32]
+        L.sf_observe.argtypes = [vp, vp, vp, vp, vp]
+        L.sf_output_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+        L.sf_reset.argtypes = [vp, vp]
+        L.sf_state_bytes.argtypes = [vp]
+        L.sf_state_bytes.restype = C.c_size_t
+        L.sf_get_state.argtypes = [vp, vp, C.c_size_t]
+        L.sf_set_state.argtypes = [vp, vp, C.c_size_t]
+        L.sf_get_contacts.argtypes = [vp, i32, vp, vp, i32]
+        L.sf_debug_raycast.argtypes = [vp, vp]
+        L.sf_debug_obs_indices.argtypes = [vp, vp]
+        L.sf_policy_load.argtypes = [vp, vp, C.c_size_t]
+        L.sf_policy_act.argtypes = [vp, vp]
+        L.sf_step_policy.argtypes = [vp, C.c_float, i32]
+        L.sf_graph_capture.argtypes = [vp, i32, C.c_float, i32]
+        L.sf_graph_launch.argtypes = [vp]
+        L.sf_profile.argtypes = [vp, i32]
+        L.sf_profile_read.argtypes = [vp, vp, vp]
+        L.sf_status_str.argtypes = [st]
+        L.sf_status_str.restype = C.c_char_p
+        L.sf_last_error.restype = C.c_char_p
+        for name in ("sf_default_params", "sf_default_options", "sf_create", "sf_destroy", "sf_info",
+                     "sf_step", "sf_observe", "sf_output_ptrs", "sf_reset", "sf_get_state",
+                     "sf_set_state", "sf_get_contacts", "sf_debug_raycast", "sf_debug_obs_indices",
+                     "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
+                     "sf_graph_launch", "sf_profile", "sf_profile_read"):
+            getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != 0:
+        L = lib()
+        raise SFError(f"{what}: {L.sf_status_str(status).decode()} ({L.sf_last_error().decode()})")
+
+
+def make_params(prm: dict) -> VehicleParams:
+    p = VehicleParams()
+    for name, _ in VehicleParams._fields_:
+        v = prm[name]
+        if name == "inertia":
+            for k in range(3):
+                p.inertia[k] = v[k]
+        elif name == "mount":
+            for r in range(4):
+                for c in range(3):
+                    p.mount[r][c] = v[r][c]
+        else:
+            setattr(p, name, v)
+    return p
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _tptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Sim:
+    """One handle of W worlds on the current torch CUDA device."""
+
+    def __init__(self, worlds, params: dict, flags: int = 0, stream=None, grid_cell: float = 0.0,
+                 step_block: int = 0, obs_waves: int = 0, policy_rows: int = 0,
+                 torch_alloc: bool = True):
+        import torch
+        L = lib()
+        self.torch = torch
+        self.worlds = worlds
+        self.params = dict(params)
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return _ptr(a)
+
+        d = WorldDesc()
+        d.num_worlds = worlds.num_worlds
+        d.agent_offsets = arr(worlds.agent_offsets, np.int32)
+        d.road_offsets = arr(worlds.road_offsets, np.int32)
+        d.road_xy = arr(worlds.road_xy, np.float32)
+        d.road_type = arr(worlds.road_type, np.uint8)
+        d.tri_offsets = arr(worlds.tri_offsets, np.int32)
+        d.tri_verts = arr(worlds.tri_verts, np.float32)
+        d.tri_surface = arr(worlds.tri_surface, np.uint8)
+        d.num_surfaces = worlds.num_surfaces
+        d.mu_class = arr(worlds.mu_class, np.float32)
+        d.film_mm = arr(worlds.film_mm, np.float32)
+        d.pavement = arr(worlds.pavement, np.uint8)
+        d.spawn_offsets = arr(worlds.spawn_offsets, np.int32)
+        d.spawn = arr(worlds.spawn, np.float32)
+        d.seed = int(worlds.seed)
+        o = Options()
+        check(L.sf_default_options(C.byref(o)), "sf_default_options")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        o.stream = C.c_void_p(self.stream.cuda_stream)
+        o.max_episode_steps = int(params.get("max_episode_steps", 1500))
+        o.collision_warmup = int(params.get("collision_warmup", 24))
+        o.flags = int(flags)
+        o.grid_cell = float(grid_cell)
+        o.step_block = int(step_block)
+        o.obs_waves = int(obs_waves)
+        o.policy_rows = int(policy_rows)
+        # device memory from torch's caching allocator
+        self._blocks = {}
+        if torch_alloc:
+            dev = torch.device("cuda", torch.cuda.current_device())
+
+            def _alloc(nbytes, ctx):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+                self._blocks[t.data_ptr()] = t
+                return t.data_ptr()
+
+            def _free(ptr, ctx):
+                self._blocks.pop(ptr, None)
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+            o.alloc = self._alloc_cb
+            o.free = self._free_cb
+        h = C.c_void_p()
+        check(L.sf_create(C.byref(d), C.byref(make_params(params)), C.byref(o), C.byref(h)), "sf_create")
+        self.h = h
+        W, N, A = C.c_int32(), C.c_int32(), C.c_int32()
+        check(L.sf_info(h, C.byref(W), C.byref(N), C.byref(A)), "sf_info")
+        self.W, self.N, self.max_agents = W.value, N.value, A.value
+        self.flags = flags
+        ob, rw, dn, ev = C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p()
+        check(L.sf_output_ptrs(h, C.byref(ob), C.byref(rw), C.byref(dn), C.byref(ev)), "sf_output_ptrs")
+        self._out_ptrs = (ob.value, rw.value, dn.value, ev.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib().sf_destroy(self.h), "sf_destroy")
+            self.h = None
+            self._blocks.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # calls ---------------------------------------------------------------
+    def step(self, actions, dt: float, substeps: int) -> None:
+        """actions: float32 CUDA tensor [N, 2] (a_long, steer)."""
+        t = self.torch
+        assert actions.is_cuda and actions.dtype == t.float32 and actions.is_contiguous()
+        assert tuple(actions.shape) == (self.N, 2)
+        check(lib().sf_step(self.h, _tptr(actions), C.c_float(dt), int(substeps)), "sf_step")
+
+    def observe(self):
+        """(obs [N,256] f32, reward [N] f32, done [N] u8, events [N] u8) CUDA tensors."""
+        t = self.torch
+        dev = t.device("cuda", t.cuda.current_device())
+        obs = t.empty((self.N, OBS_DIM), dtype=t.float32, device=dev)
+        rew = t.empty(self.N, dtype=t.float32, device=dev)
+        done = t.empty(self.N, dtype=t.uint8, device=dev)
+        ev = t.empty(self.N, dtype=t.uint8, device=dev)
+        check(lib().sf_observe(self.h, _tptr(obs), _tptr(rew), _tptr(done), _tptr(ev)), "sf_observe")
+        return obs, rew, done, ev
+
+    def reset(self, mask) -> None:
+        """mask: uint8 CUDA tensor [N]."""
+        assert mask.is_cuda and mask.dtype == self.torch.uint8 and mask.numel() == self.N
+        check(lib().sf_reset(self.h, _tptr(mask.contiguous())), "sf_reset")
+
+    def state_bytes(self) -> int:
+        return int(lib().sf_state_bytes(self.h))
+
+    def get_state(self):
+        """(f [24, N] float32, k [4, N] int32) host copies."""
+        buf = np.zeros(self.state_bytes() // 4, np.float32)
+        check(lib().sf_get_state(self.h, _ptr(buf), buf.nbytes), "sf_get_state")
+        f = buf[:NF * self.N].reshape(NF, self.N).copy()
+        k = buf[NF * self.N:].view(np.int32).reshape(NI, self.N).copy()
+        return f, k
+
+    def set_state(self, f, k) -> None:
+        f = np.ascontiguousarray(f, np.float32).reshape(NF, self.N)
+        k = np.ascontiguousarray(k, np.int32).reshape(NI, self.N)
+        buf = np.concatenate([f.ravel(), k.ravel().view(np.float32)])
+        check(lib().sf_set_state(self.h, _ptr(buf), buf.nbytes), "sf_set_state")
+
+    def contacts(self, substep: int):
+        """(counts [W] int32, pairs [W, cap] uint32) of one substep of the last step."""
+        cap = max(1, self.max_agents * (self.max_agents - 1) // 2)
+        cnt = np.zeros(self.W, np.int32)
+        pairs = np.zeros((self.W, cap), np.uint32)
+        check(lib().sf_get_contacts(self.h, int(substep), _ptr(cnt), _ptr(pairs), cap), "sf_get_contacts")
+        return cnt, pairs
+
+    def debug_raycast(self):
+        out = np.zeros((self.N, 4, 4), np.float32)
+        check(lib().sf_debug_raycast(self.h, _ptr(out)), "sf_debug_raycast")
+        return out
+
+    def debug_obs_indices(self):
+        out = np.zeros((self.N, 72), np.int32)
+        check(lib().sf_debug_obs_indices(self.h, _ptr(out)), "sf_debug_obs_indices")
+        return out
+
+    # policy, graphs, profiling ------------------------------------------
+    def policy_load(self, Ws, bs) -> None:
+        """Float32 masters of the 256-256-256-2 policy (W as [out, in])."""
+        flat = np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(),
+                                               np.asarray(b, np.float32).ravel()])
+                               for W, b in zip(Ws, bs)])
+        check(lib().sf_policy_load(self.h, _ptr(flat), flat.size), "sf_policy_load")
+
+    def policy_act(self):
+        t = self.torch
+        a = t.empty((self.N, 2), dtype=t.float32, device=t.device("cuda", t.cuda.current_device()))
+        check(lib().sf_policy_act(self.h, _tptr(a)), "sf_policy_act")
+        return a
+
+    def step_policy(self, dt: float, substeps: int) -> None:
+        check(lib().sf_step_policy(self.h, C.c_float(dt), int(substeps)), "sf_step_policy")
+
+    def graph_capture(self, control_steps: int, dt: float, substeps: int) -> None:
+        check(lib().sf_graph_capture(self.h, int(control_steps), C.c_float(dt), int(substeps)),
+              "sf_graph_capture")
+
+    def graph_launch(self) -> None:
+        check(lib().sf_graph_launch(self.h), "sf_graph_launch")
+
+    def profile(self, enable: bool) -> None:
+        check(lib().sf_profile(self.h, int(bool(enable))), "sf_profile")
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches)} for policy, step, obs, reset."""
+        ms = np.zeros(4, np.float64)
+        n = np.zeros(4, np.int32)
+        check(lib().sf_profile_read(self.h, _ptr(ms), _ptr(n)), "sf_profile_read")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(("policy", "step", "obs", "reset"))}
