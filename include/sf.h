@@ -152,7 +152,8 @@ typedef struct {
     int32_t step_block;         /* threads per world in the step; 0 -> auto   */
     int32_t obs_waves;          /* agents (waves) per block in the obs kernel */
     int32_t policy_rows;        /* agents per block in the policy MLP (32/64) */
-    int32_t reserved[5];
+    float tri_cell;             /* triangle grid cell size [m]; 0 -> default  */
+    int32_t reserved[4];
 } sf_options;
 
 /* Fill the configured vehicle / default options. */

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libsf.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SF_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + os.path.join(os.path.dirname(HERE), "include"),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
 

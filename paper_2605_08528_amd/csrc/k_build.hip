@@ -149,7 +149,7 @@ __global__ void k_grid_tris(DevWorld Wd, const float *verts, int T, int *cnt_or_
         if (Wd.toff[mid] <= k) lo = mid; else hi = mid - 1;
     }
     int w = lo;
-    GridHdr g = Wd.grid[w];
+    GridHdr g = Wd.tgrid[w];
     const float *p = verts + 9 * (size_t)k;
     float xa = fminf(p[0], fminf(p[3], p[6])), xb = fmaxf(p[0], fmaxf(p[3], p[6]));
     float ya = fminf(p[1], fminf(p[4], p[7])), yb = fmaxf(p[1], fmaxf(p[4], p[7]));
@@ -179,22 +179,14 @@ __global__ void k_grid_pts(DevWorld Wd, int P, int *cnt_or_cursor, int *items) {
     else items[atomicAdd(&cnt_or_cursor[c], 1)] = k - Wd.roff[w];
 }
 
-void launch_grid_count(const DevWorld &Wd, const float *verts, int *tri_cnt, int *pt_cnt,
-                       hipStream_t st) {
-    int T = 0, P = 0;
-    (void)hipMemcpyAsync(&T, Wd.toff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
-    (void)hipMemcpyAsync(&P, Wd.roff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
-    (void)hipStreamSynchronize(st);
+void launch_grid_count(const DevWorld &Wd, const float *verts, int T, int P, int *tri_cnt,
+                       int *pt_cnt, hipStream_t st) {
     if (T) k_grid_tris<0><<<(T + 255) / 256, 256, 0, st>>>(Wd, verts, T, tri_cnt, nullptr);
     if (P) k_grid_pts<0><<<(P + 255) / 256, 256, 0, st>>>(Wd, P, pt_cnt, nullptr);
 }
 
-void launch_grid_fill(const DevWorld &Wd, const float *verts, int *tri_cursor, int *pt_cursor,
-                      int *tri_items, int *pt_items, hipStream_t st) {
-    int T = 0, P = 0;
-    (void)hipMemcpyAsync(&T, Wd.toff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
-    (void)hipMemcpyAsync(&P, Wd.roff + Wd.W, sizeof(int), hipMemcpyDeviceToHost, st);
-    (void)hipStreamSynchronize(st);
+void launch_grid_fill(const DevWorld &Wd, const float *verts, int T, int P, int *tri_cursor,
+                      int *pt_cursor, int *tri_items, int *pt_items, hipStream_t st) {
     if (T) k_grid_tris<1><<<(T + 255) / 256, 256, 0, st>>>(Wd, verts, T, tri_cursor, tri_items);
     if (P) k_grid_pts<1><<<(P + 255) / 256, 256, 0, st>>>(Wd, P, pt_cursor, pt_items);
 }
@@ -211,16 +203,19 @@ __global__ void k_cell_sort(const int *start, int C, int *items) {
     }
 }
 
+__device__ __forceinline__ int world_of_cell(const GridHdr *grid, int W, int c) {
+    int lo = 0, hi = W - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (grid[mid].cbase <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ void k_pack_pts(DevWorld Wd, int C, const int *pt_items, int4 *pt_cell) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
-    // world of cell c
-    int lo = 0, hi = Wd.W - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (Wd.grid[mid].cbase <= c) lo = mid; else hi = mid - 1;
-    }
-    int r0 = Wd.roff[lo];
+    const int r0 = Wd.roff[world_of_cell(Wd.grid, Wd.W, c)];
     for (int k = Wd.pt_cell_start[c]; k < Wd.pt_cell_start[c + 1]; ++k) {
         int idx = pt_items[k];
         int2 q = Wd.road_q[r0 + idx];
@@ -228,12 +223,69 @@ __global__ void k_pack_pts(DevWorld Wd, int C, const int *pt_items, int4 *pt_cel
     }
 }
 
-void launch_grid_finish(const DevWorld &Wd, int C, int *tri_items, int *pt_items, int4 *pt_cell,
-                        hipStream_t st) {
-    if (C == 0) return;
-    k_cell_sort<<<(C + 255) / 256, 256, 0, st>>>(Wd.tri_cell_start, C, tri_items);
-    k_cell_sort<<<(C + 255) / 256, 256, 0, st>>>(Wd.pt_cell_start, C, pt_items);
-    k_pack_pts<<<(C + 255) / 256, 256, 0, st>>>(Wd, C, pt_items, pt_cell);
+// triangle records copied into cell order: a ray then reads contiguous
+// candidates with no id -> record indirection
+__global__ void k_pack_tris(DevWorld Wd, int C, const int *tri_items, float4 *rec) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int t0 = Wd.toff[world_of_cell(Wd.tgrid, Wd.W, c)];
+    for (int k = Wd.tri_cell_start[c]; k < Wd.tri_cell_start[c + 1]; ++k) {
+        const int id = tri_items[k];
+        const float4 a = Wd.tri[4 * (size_t)(t0 + id)];
+        const float4 b = Wd.tri[4 * (size_t)(t0 + id) + 1];
+        const float4 e = Wd.tri[4 * (size_t)(t0 + id) + 2];
+        rec[3 * (size_t)k] = make_float4(a.x, a.y, a.z, __int_as_float(id));
+        rec[3 * (size_t)k + 1] = make_float4(b.x, b.y, b.z, a.w);
+        rec[3 * (size_t)k + 2] = make_float4(e.x, e.y, e.z, 0.f);
+    }
+}
+
+// Chebyshev distance (in cells) from every point cell to the nearest cell
+// holding road points: relaxation d = min(d, d(neighbour) + 1) until it
+// settles (values only decrease and stay upper bounds, so in-place updates
+// are safe).  The kNN search skips the rings closer than this distance.
+__global__ __launch_bounds__(256) void k_occ(DevWorld Wd, int *occ) {
+    const int w = blockIdx.x;
+    const GridHdr g = Wd.grid[w];
+    const int n = g.nx * g.ny;
+    int *d = occ + g.cbase;
+    for (int c = threadIdx.x; c < n; c += blockDim.x)
+        d[c] = Wd.pt_cell_start[g.cbase + c + 1] > Wd.pt_cell_start[g.cbase + c] ? 0 : (1 << 20);
+    __shared__ int changed;
+    for (int it = 0; it < g.nx + g.ny + 2; ++it) {
+        __syncthreads();
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            const int x = c % g.nx, y = c / g.nx;
+            int m = d[c];
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xx = x + dx, yy = y + dy;
+                    if ((dx | dy) == 0 || xx < 0 || yy < 0 || xx >= g.nx || yy >= g.ny) continue;
+                    m = min(m, __atomic_load_n(&d[yy * g.nx + xx], __ATOMIC_RELAXED) + 1);
+                }
+            if (m < d[c]) {
+                __atomic_store_n(&d[c], m, __ATOMIC_RELAXED);
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        if (!changed) break;
+    }
+}
+
+void launch_grid_finish(const DevWorld &Wd, int CT, int CP, int *tri_items, int *pt_items,
+                        float4 *tri_rec, int4 *pt_cell, int *pt_occ, hipStream_t st) {
+    if (CT) {
+        k_cell_sort<<<(CT + 255) / 256, 256, 0, st>>>(Wd.tri_cell_start, CT, tri_items);
+        k_pack_tris<<<(CT + 255) / 256, 256, 0, st>>>(Wd, CT, tri_items, tri_rec);
+    }
+    if (CP) {
+        k_cell_sort<<<(CP + 255) / 256, 256, 0, st>>>(Wd.pt_cell_start, CP, pt_items);
+        k_pack_pts<<<(CP + 255) / 256, 256, 0, st>>>(Wd, CP, pt_items, pt_cell);
+    }
+    if (Wd.W) k_occ<<<Wd.W, 256, 0, st>>>(Wd, pt_occ);
 }
 
 // ------------------------------------------------------------------- scan

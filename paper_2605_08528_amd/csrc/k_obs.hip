@@ -55,35 +55,47 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 
 #define KPL (SF_CAND_CAP / 64)  // candidate keys per lane
 
-// number of buffered keys <= x (uniform across the wave)
-__device__ __forceinline__ int count_le(const unsigned long long kv[KPL], unsigned long long x) {
+// number of buffered keys <= x among the first `slots` register slots
+__device__ __forceinline__ int count_le(const unsigned long long kv[KPL], unsigned long long x, int slots) {
     int c = 0;
 #pragma unroll
-    for (int s = 0; s < KPL; ++s) c += __popcll(__ballot(kv[s] <= x));
+    for (int s = 0; s < KPL; ++s)
+        if (s < slots) c += __popcll(__ballot(kv[s] <= x));
     return c;
 }
 
-// The K-th smallest key (1-based) of n >= K distinct keys held KPL per lane
-// (unused slots hold ~0): binary search on the key value.
-__device__ unsigned long long kth_smallest(const unsigned long long kv[KPL], int K) {
+// The K-th smallest key (1-based) of n >= K distinct keys held in the first
+// `slots` register slots of the wave (unused entries hold ~0): binary search
+// on the distance part, then on the index only when distances tie.
+__device__ unsigned long long kth_smallest(const unsigned long long kv[KPL], int K, int slots) {
     unsigned long long lo = ~0ull, hi = 0;
 #pragma unroll
     for (int s = 0; s < KPL; ++s) {
+        if (s >= slots) break;
         lo = kv[s] < lo ? kv[s] : lo;
         if (kv[s] != ~0ull) hi = kv[s] > hi ? kv[s] : hi;
     }
     lo = wave_min_u64(lo);
     hi = wave_max_u64(hi);
-    // narrow on the distance part first (bits 20 and up), then on the index
     unsigned long long dlo = lo >> 20, dhi = hi >> 20;
     while (dlo < dhi) {
-        unsigned long long mid = dlo + ((dhi - dlo) >> 1);
-        if (count_le(kv, (mid << 20) | 0xFFFFFull) >= K) dhi = mid; else dlo = mid + 1;
+        const unsigned long long mid = dlo + ((dhi - dlo) >> 1);
+        if (count_le(kv, (mid << 20) | 0xFFFFFull, slots) >= K) dhi = mid; else dlo = mid + 1;
     }
-    unsigned long long ilo = dlo << 20, ihi = (dlo << 20) | 0xFFFFFull;
+    // keys with distance < dlo number below K; if exactly K have distance
+    // <= dlo, the K-th key is the largest of them
+    const unsigned long long top = (dlo << 20) | 0xFFFFFull;
+    if (count_le(kv, top, slots) == K) {
+        unsigned long long m = 0;
+#pragma unroll
+        for (int s = 0; s < KPL; ++s)
+            if (s < slots && kv[s] <= top) m = kv[s] > m ? kv[s] : m;
+        return wave_max_u64(m);
+    }
+    unsigned long long ilo = dlo << 20, ihi = top;
     while (ilo < ihi) {
-        unsigned long long mid = ilo + ((ihi - ilo) >> 1);
-        if (count_le(kv, mid) >= K) ihi = mid; else ilo = mid + 1;
+        const unsigned long long mid = ilo + ((ihi - ilo) >> 1);
+        if (count_le(kv, mid, slots) >= K) ihi = mid; else ilo = mid + 1;
     }
     return ilo;
 }
@@ -96,6 +108,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
     __shared__ unsigned long long s_cand[WAVES][SF_CAND_CAP];
     __shared__ float s_row[WAVES][SF_OBS_DIM];
     __shared__ int s_sel[WAVES][64];
+    __shared__ int s_segs[WAVES][64], s_segp[WAVES][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
     // give each XCD a contiguous range of agents (neighbouring agents share a
@@ -221,60 +234,103 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
         cx = max(0, min(cx, g.nx - 1));
         cy = max(0, min(cy, g.ny - 1));
         int nc = 0;  // buffered candidates (uniform)
-        for (int rr = 0;; ++rr) {
-            // visit ring rr row by row; cells of a row segment are contiguous
-            const int ylo = max(cy - rr, 0), yhi = min(cy + rr, g.ny - 1);
-            for (int y = ylo; y <= yhi; ++y) {
-                const bool edge = (y == cy - rr) || (y == cy + rr);
-                for (int part = 0; part < 2; ++part) {
-                    int xa, xb;
-                    if (edge) {
-                        if (part) break;
-                        xa = cx - rr; xb = cx + rr;
-                    } else {
-                        xa = xb = part ? cx + rr : cx - rr;
-                        if (rr == 0 && part) break;
+        // rings closer than the distance to the nearest non-empty cell hold
+        // no points: start there
+        int rr = Wd.pt_occ[g.cbase + cy * g.nx + cx];
+        rr = min(rr, max(g.nx, g.ny));
+        for (;; ++rr) {
+            // the ring's cells as contiguous row segments (top row, bottom
+            // row, single cells of the left and right columns), one segment
+            // per lane, their points flattened across the wave
+            const int nseg = rr == 0 ? 1 : 4 * rr;
+            for (int sb = 0; sb < nseg; sb += 64) {
+                const int j = sb + lane;
+                int s = 0, e = 0;
+                if (j < nseg) {
+                    int y, xa, xb;
+                    if (rr == 0) { y = cy; xa = xb = cx; }
+                    else if (j == 0) { y = cy - rr; xa = cx - rr; xb = cx + rr; }
+                    else if (j == 1) { y = cy + rr; xa = cx - rr; xb = cx + rr; }
+                    else {
+                        const int qq = j - 2;
+                        y = cy - rr + 1 + (qq >> 1);
+                        xa = xb = (qq & 1) ? cx + rr : cx - rr;
                     }
-                    xa = max(xa, 0); xb = min(xb, g.nx - 1);
-                    if (xa > xb) continue;
-                    const int c0 = g.cbase + y * g.nx;
-                    const int s = Wd.pt_cell_start[c0 + xa], e = Wd.pt_cell_start[c0 + xb + 1];
-                    for (int k0 = s; k0 < e; k0 += 64) {
-                        if (nc + 64 > SF_CAND_CAP) {
-                            // keep only keys that can still be among the 64 best
-                            wave_sync();
-                            unsigned long long kv[KPL];
+                    xa = max(xa, 0);
+                    xb = min(xb, g.nx - 1);
+                    if (y >= 0 && y < g.ny && xa <= xb) {
+                        const int c0 = g.cbase + y * g.nx;
+                        s = Wd.pt_cell_start[c0 + xa];
+                        e = Wd.pt_cell_start[c0 + xb + 1];
+                    }
+                }
+                const int len = e - s;
+                int incl = len;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y2 = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += y2;
+                }
+                const int total = __shfl(incl, 63, 64);
+                s_segs[wv][lane] = s;
+                s_segp[wv][lane] = incl - len;
+                wave_sync();
+                // batches of up to 8 points per lane: all loads of a batch are
+                // issued before any key is appended
+                for (int f0 = 0; f0 < total; f0 += 512) {
+                    const int nslot = min(8, (total - f0 + 63) >> 6);
+                    if (nc + 64 * nslot > SF_CAND_CAP) {
+                        // keep only keys that can still be among the 64 best
+                        wave_sync();
+                        unsigned long long kv[KPL];
 #pragma unroll
-                            for (int t = 0; t < KPL; ++t) {
-                                int slot = lane + 64 * t;
-                                kv[t] = slot < nc ? cand[slot] : ~0ull;
-                            }
-                            const unsigned long long k64 = kth_smallest(kv, 64);
-                            wave_sync();
-                            int keep = 0;
-#pragma unroll
-                            for (int t = 0; t < KPL; ++t) {
-                                const bool f = kv[t] <= k64;
-                                const unsigned long long bal = __ballot(f);
-                                if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
-                                keep += __popcll(bal);
-                            }
-                            nc = keep;
-                            wave_sync();
+                        for (int t = 0; t < KPL; ++t) {
+                            int slot = lane + 64 * t;
+                            kv[t] = slot < nc ? cand[slot] : ~0ull;
                         }
-                        const int k = k0 + lane;
-                        const bool has = k < e;
+                        const unsigned long long k64 = kth_smallest(kv, 64, (nc + 63) >> 6);
+                        wave_sync();
+                        int keep = 0;
+#pragma unroll
+                        for (int t = 0; t < KPL; ++t) {
+                            const bool f = kv[t] <= k64;
+                            const unsigned long long bal = __ballot(f);
+                            if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
+                            keep += __popcll(bal);
+                        }
+                        nc = keep;
+                        wave_sync();
+                    }
+                    int4 pq[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int f = f0 + 64 * t + lane;
+                        pq[t] = make_int4(0, 0, 0, -1);
+                        if (t < nslot && f < total) {
+                            // the segment holding flat index f: the last one
+                            // whose prefix is <= f (it is never empty)
+                            int lo = 0, hi = min(63, nseg - 1 - sb);
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (s_segp[wv][mid] <= f) lo = mid; else hi = mid - 1;
+                            }
+                            pq[t] = Wd.pt_cell[s_segs[wv][lo] + (f - s_segp[wv][lo])];
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        if (t >= nslot) break;
+                        const bool has = pq[t].w == 0;
                         unsigned long long key = 0;
                         if (has) {
-                            const int4 pq = Wd.pt_cell[k];
-                            const long long dx = (long long)pq.x - QX, dy = (long long)pq.y - QY;
-                            key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 20) | (unsigned)pq.z;
+                            const long long dx = (long long)pq[t].x - QX, dy = (long long)pq[t].y - QY;
+                            key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 20) | (unsigned)pq[t].z;
                         }
                         const unsigned long long bal = __ballot(has);
                         if (has) cand[nc + __popcll(bal & lane_lt())] = key;
                         nc += __popcll(bal);
                     }
                 }
+                wave_sync();
             }
             // lower bound on the distance to any point outside the visited square
             float bnd = INFINITY;
@@ -304,7 +360,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
             int slot = lane + 64 * t;
             kv[t] = slot < nc ? cand[slot] : ~0ull;
         }
-        const unsigned long long kmax = nc > 64 ? kth_smallest(kv, 64) : ~0ull - 1;
+        const unsigned long long kmax = nc > 64 ? kth_smallest(kv, 64, (nc + 63) >> 6) : ~0ull - 1;
         int pos = 0;
 #pragma unroll
         for (int t = 0; t < KPL; ++t) {

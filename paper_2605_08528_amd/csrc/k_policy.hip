@@ -40,14 +40,22 @@ __device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ in, uin
     for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+    // weight fragments of the next k-step are fetched before the current
+    // step's matrix instructions issue (register double buffering)
+    bf16x8 bnx[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        bnx[c] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(wv * 64 + c * 16 + r16) * PL_IN + kq * 8);
+#pragma unroll
     for (int kk = 0; kk < PL_IN / 32; ++kk) {
         const int k0 = kk * 32 + kq * 8;
         bf16x8 bfr[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int n = wv * 64 + c * 16 + r16;
-            bfr[c] = *reinterpret_cast<const bf16x8 *>(W + (size_t)n * PL_IN + k0);
+        for (int c = 0; c < 4; ++c) bfr[c] = bnx[c];
+        if (kk + 1 < PL_IN / 32) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                bnx[c] = *reinterpret_cast<const bf16x8 *>(W + (size_t)(wv * 64 + c * 16 + r16) * PL_IN + k0 + 32);
         }
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
@@ -121,7 +129,9 @@ void launch_policy(const float *obs, int N, const uint16_t *W1, const float *b1,
                    const float *b2, const uint16_t *W3, const float *b3, float steer_max, float *act,
                    int tm, hipStream_t s) {
     if (N == 0) return;
-    if (tm <= 32)
+    if (tm <= 16)
+        k_policy<16><<<(N + 15) / 16, 256, 0, s>>>(obs, N, W1, b1, W2, b2, W3, b3, steer_max, act);
+    else if (tm <= 32)
         k_policy<32><<<(N + 31) / 32, 256, 0, s>>>(obs, N, W1, b1, W2, b2, W3, b3, steer_max, act);
     else
         k_policy<64><<<(N + 63) / 64, 256, 0, s>>>(obs, N, W1, b1, W2, b2, W3, b3, steer_max, act);

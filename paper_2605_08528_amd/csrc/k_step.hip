@@ -8,20 +8,20 @@
 __device__ int g_sf_overflow;  // contact-capacity overflows (diagnostic)
 
 // ---------------------------------------------------------------- raycast
-__device__ __forceinline__ float mt_hit(const float4 *__restrict__ tri, int k, f3 m, f3 u, float ell) {
-    float4 a = tri[4 * (size_t)k], b = tri[4 * (size_t)k + 1], c = tri[4 * (size_t)k + 2];
-    f3 e1 = mk3(b.x, b.y, b.z), e2 = mk3(c.x, c.y, c.z);
-    f3 pv = cross3(u, e2);
-    float det = dot3(e1, pv);
+__device__ __forceinline__ float mt_rec(const float4 &a, const float4 &b, const float4 &c, f3 m, f3 u,
+                                        float ell) {
+    const f3 e1 = mk3(b.x, b.y, b.z), e2 = mk3(c.x, c.y, c.z);
+    const f3 pv = cross3(u, e2);
+    const float det = dot3(e1, pv);
     if (fabsf(det) < 1e-12f) return INFINITY;
-    float inv = 1.f / det;
-    f3 tv = mk3(m.x - a.x, m.y - a.y, m.z - a.z);
-    float bu = dot3(tv, pv) * inv;
+    const float inv = 1.f / det;
+    const f3 tv = mk3(m.x - a.x, m.y - a.y, m.z - a.z);
+    const float bu = dot3(tv, pv) * inv;
     if (bu < 0.f || bu > 1.f) return INFINITY;
-    f3 qv = cross3(tv, e1);
-    float bv = dot3(u, qv) * inv;
+    const f3 qv = cross3(tv, e1);
+    const float bv = dot3(u, qv) * inv;
     if (bv < 0.f || bu + bv > 1.f) return INFINITY;
-    float t = dot3(e2, qv) * inv;
+    const float t = dot3(e2, qv) * inv;
     if (t < 0.f || t > ell) return INFINITY;
     return t;
 }
@@ -33,62 +33,92 @@ struct RayHit {
 };
 
 // Nearest hit of the wheel ray against the ground plane z = 0 and the road
-// triangles in the grid cells the ray's footprint touches.  Hits within
-// 0.1 mm of the nearest are one surface point: a road triangle wins over the
-// ground, the lowest triangle index first.
+// triangles of the triangle-grid cells under the ray's footprint.  Hits
+// within 0.1 mm of the nearest are one surface point: a road triangle wins
+// over the ground, the lowest triangle index first.  One pass keeps up to 4
+// distinct triangle hits in registers; more (stacked geometry) triggers a
+// second pass that applies the same rule.
 __device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, int w, f3 m, f3 u) {
     const float ell = P.ell;
     float tmin = INFINITY, tg = INFINITY;
     if (u.z < 0.f) {
-        float t = m.z / (-u.z);
+        const float t = m.z / (-u.z);
         if (t >= 0.f && t <= ell) { tg = t; tmin = t; }
     }
-    const int t0 = Wd.toff[w];
-    const bool any_tri = Wd.toff[w + 1] > t0;
-    int cx0 = 0, cx1 = -1, cy0 = 0, cy1 = -1;
-    GridHdr g;
-    if (any_tri) {
-        g = Wd.grid[w];
-        float ex = m.x + ell * u.x, ey = m.y + ell * u.y;
-        float xa = fminf(m.x, ex), xb = fmaxf(m.x, ex), ya = fminf(m.y, ey), yb = fmaxf(m.y, ey);
-        cx0 = (int)floorf((xa - g.x0) * g.inv_cell); cx1 = (int)floorf((xb - g.x0) * g.inv_cell);
-        cy0 = (int)floorf((ya - g.y0) * g.inv_cell); cy1 = (int)floorf((yb - g.y0) * g.inv_cell);
-        cx0 = max(0, min(cx0, g.nx - 1)); cx1 = max(0, min(cx1, g.nx - 1));
-        cy0 = max(0, min(cy0, g.ny - 1)); cy1 = max(0, min(cy1, g.ny - 1));
-        for (int cy = cy0; cy <= cy1; ++cy)
-            for (int cx = cx0; cx <= cx1; ++cx) {
-                int c = g.cbase + cy * g.nx + cx;
-                for (int k = Wd.tri_cell_start[c]; k < Wd.tri_cell_start[c + 1]; ++k)
-                    tmin = fminf(tmin, mt_hit(Wd.tri, t0 + Wd.tri_items[k], m, u, ell));
-            }
-    }
     RayHit H;
-    H.hit = tmin < INFINITY;
     H.tri = -1;
     H.surf = 0;
     H.t = tg;
     H.n = mk3(0.f, 0.f, 1.f);
-    if (!H.hit || !any_tri) return H;
-    int best = 0x7fffffff;
-    float bt = INFINITY;
-    for (int cy = cy0; cy <= cy1; ++cy)
-        for (int cx = cx0; cx <= cx1; ++cx) {
-            int c = g.cbase + cy * g.nx + cx;
-            for (int k = Wd.tri_cell_start[c]; k < Wd.tri_cell_start[c + 1]; ++k) {
-                int id = Wd.tri_items[k];
-                if (id >= best) continue;
-                float t = mt_hit(Wd.tri, t0 + id, m, u, ell);
-                if (t <= tmin + 1e-4f) { best = id; bt = t; }
+    const bool any_tri = Wd.toff[w + 1] > Wd.toff[w];
+    if (!any_tri) {
+        H.hit = tmin < INFINITY;
+        return H;
+    }
+    const GridHdr g = Wd.tgrid[w];
+    const float ex = m.x + ell * u.x, ey = m.y + ell * u.y;
+    int cx0 = (int)floorf((fminf(m.x, ex) - g.x0) * g.inv_cell);
+    int cx1 = (int)floorf((fmaxf(m.x, ex) - g.x0) * g.inv_cell);
+    int cy0 = (int)floorf((fminf(m.y, ey) - g.y0) * g.inv_cell);
+    int cy1 = (int)floorf((fmaxf(m.y, ey) - g.y0) * g.inv_cell);
+    cx0 = max(0, min(cx0, g.nx - 1)); cx1 = max(0, min(cx1, g.nx - 1));
+    cy0 = max(0, min(cy0, g.ny - 1)); cy1 = max(0, min(cy1, g.ny - 1));
+    int nh = 0;
+    float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
+    int i0 = -1, i1 = -1, i2 = -1, i3 = -1, k0 = -1, k1 = -1, k2 = -1, k3 = -1;
+    for (int cy = cy0; cy <= cy1; ++cy) {
+        const int c0 = g.cbase + cy * g.nx;
+        const int s = Wd.tri_cell_start[c0 + cx0], e = Wd.tri_cell_start[c0 + cx1 + 1];
+        for (int k = s; k < e; ++k) {
+            const float4 a = Wd.tri_rec[3 * (size_t)k], b = Wd.tri_rec[3 * (size_t)k + 1],
+                         c = Wd.tri_rec[3 * (size_t)k + 2];
+            const float t = mt_rec(a, b, c, m, u, ell);
+            if (t < INFINITY) {
+                const int id = __float_as_int(a.w);
+                tmin = fminf(tmin, t);
+                if (id == i0 || id == i1 || id == i2 || id == i3) continue;
+                if (nh == 0) { t0 = t; i0 = id; k0 = k; }
+                else if (nh == 1) { t1 = t; i1 = id; k1 = k; }
+                else if (nh == 2) { t2 = t; i2 = id; k2 = k; }
+                else if (nh == 3) { t3 = t; i3 = id; k3 = k; }
+                ++nh;
             }
         }
-    if (best != 0x7fffffff) {
-        float4 a = Wd.tri[4 * (size_t)(t0 + best)];
-        float4 nn = Wd.tri[4 * (size_t)(t0 + best) + 3];
-        f3 n = mk3(nn.x, nn.y, nn.z);
+    }
+    H.hit = tmin < INFINITY;
+    if (!H.hit || nh == 0) return H;
+    int best = 0x7fffffff, bk = -1;
+    float bt = 0.f;
+    const float lim = tmin + 1e-4f;
+    if (nh <= 4) {
+        if (t0 <= lim && i0 < best) { best = i0; bt = t0; bk = k0; }
+        if (nh > 1 && t1 <= lim && i1 < best) { best = i1; bt = t1; bk = k1; }
+        if (nh > 2 && t2 <= lim && i2 < best) { best = i2; bt = t2; bk = k2; }
+        if (nh > 3 && t3 <= lim && i3 < best) { best = i3; bt = t3; bk = k3; }
+    } else {
+        // more than 4 distinct triangles under one ray: apply the rule in a
+        // second pass over the same cells
+        for (int cy = cy0; cy <= cy1; ++cy) {
+            const int c0 = g.cbase + cy * g.nx;
+            const int s = Wd.tri_cell_start[c0 + cx0], e = Wd.tri_cell_start[c0 + cx1 + 1];
+            for (int k = s; k < e; ++k) {
+                const float4 a = Wd.tri_rec[3 * (size_t)k];
+                const int id = __float_as_int(a.w);
+                if (id >= best) continue;
+                const float t = mt_rec(a, Wd.tri_rec[3 * (size_t)k + 1], Wd.tri_rec[3 * (size_t)k + 2], m, u, ell);
+                if (t <= lim) { best = id; bt = t; bk = k; }
+            }
+        }
+    }
+    if (bk >= 0) {
+        const float4 b = Wd.tri_rec[3 * (size_t)bk + 1], c = Wd.tri_rec[3 * (size_t)bk + 2];
+        f3 n = cross3(mk3(b.x, b.y, b.z), mk3(c.x, c.y, c.z));
+        const float L = sqrtf(dot3(n, n));
+        n = L > 0.f ? mul3(n, 1.f / L) : mk3(0.f, 0.f, 1.f);
         if (dot3(n, u) > 0.f) n = mul3(n, -1.f);
         H.t = bt;
         H.n = n;
-        H.surf = (int)a.w;
+        H.surf = (int)b.w;
         H.tri = best;
     }
     return H;
@@ -183,6 +213,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float 
     __shared__ short s_bl[SF_MAXA][SF_BCAP];
     __shared__ int s_bn[SF_MAXA];
     __shared__ int s_scan[NWV];
+    __shared__ int s_np;
 
     // ---- load the world's agents; decode actions (Sec. "Action Space Details")
     for (int i = tid; i < A; i += BLOCK) {
@@ -250,59 +281,56 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float 
         }
         __syncthreads();
 
-        // ---- B: overlapping circle pairs on the substep's input poses,
-        //      compacted in canonical (i, j) order (wave ballot + prefix)
-        int np = 0;
-        for (int base = 0; base < npc; base += BLOCK) {
-            const int k = base + tid;
-            int flag = 0;
-            uint32_t packed = 0;
-            if (k < npc) {
-                int i, j;
-                pair_of(k, A, i, j);
-                if (s_act[i] && s_act[j]) {
-                    uint32_t mask = 0;
-                    const long long R2 = P.Qr2;
+        // ---- B (last wave): overlapping circle pairs on the substep's input
+        //      poses, compacted in canonical (i, j) order with wave ballots.
+        // ---- C (the other waves; every thread when the block is one wave):
+        //      wheels: raycast, suspension, tire, spin.  B and C overlap.
+        const bool pair_wave = NWV == 1 || wave == NWV - 1;
+        if (pair_wave) {
+            int np_w = 0;
+            for (int base = 0; base < npc; base += 64) {
+                const int k = base + lane;
+                int flag = 0;
+                uint32_t packed = 0;
+                if (k < npc) {
+                    int i, j;
+                    pair_of(k, A, i, j);
+                    if (s_act[i] && s_act[j]) {
+                        uint32_t mask = 0;
+                        const long long R2 = P.Qr2;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
+                        for (int a = 0; a < 3; ++a)
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) {
-                            long long dx = (long long)s_cq[2 * a][i] - s_cq[2 * b][j];
-                            long long dy = (long long)s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
-                            if (dx * dx + dy * dy < R2) mask |= 1u << (3 * a + b);
+                            for (int b = 0; b < 3; ++b) {
+                                const long long dx = (long long)s_cq[2 * a][i] - s_cq[2 * b][j];
+                                const long long dy = (long long)s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
+                                if (dx * dx + dy * dy < R2) mask |= 1u << (3 * a + b);
+                            }
+                        if (mask) {
+                            flag = 1;
+                            packed = (uint32_t)i | ((uint32_t)j << 8) | (mask << 16);
                         }
-                    if (mask) {
-                        flag = 1;
-                        packed = (uint32_t)i | ((uint32_t)j << 8) | (mask << 16);
                     }
                 }
+                const unsigned long long bal = __ballot(flag);
+                if (flag) s_pairs[np_w + __popcll(bal & lanemask_lt())] = packed;
+                np_w += __popcll(bal);
             }
-            unsigned long long bal = __ballot(flag);
-            int pre = __popcll(bal & lanemask_lt());
-            if (lane == 0) s_scan[wave] = __popcll(bal);
-            __syncthreads();
-            int off = 0, tot = 0;
-#pragma unroll
-            for (int v = 0; v < NWV; ++v) {
-                if (v < wave) off += s_scan[v];
-                tot += s_scan[v];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (rec) {
+                uint32_t *dst = rec + ((size_t)sub * Wd.W + w) * rec_cap;
+                for (int k = lane; k < np_w && k < rec_cap; k += 64) dst[k] = s_pairs[k];
+                if (lane == 0) rec_cnt[sub * Wd.W + w] = np_w;
             }
-            if (flag) s_pairs[np + off + pre] = packed;
-            np += tot;
-            __syncthreads();
+            for (int k = lane; k < np_w; k += 64) {
+                s_coll[s_pairs[k] & 0xFF] = 1;
+                s_coll[(s_pairs[k] >> 8) & 0xFF] = 1;
+            }
+            if (lane == 0) s_np = np_w;
         }
-        if (rec) {
-            uint32_t *dst = rec + ((size_t)sub * Wd.W + w) * rec_cap;
-            for (int k = tid; k < np && k < rec_cap; k += BLOCK) dst[k] = s_pairs[k];
-            if (tid == 0) rec_cnt[sub * Wd.W + w] = np;
-        }
-        for (int k = tid; k < np; k += BLOCK) {
-            s_coll[s_pairs[k] & 0xFF] = 1;
-            s_coll[(s_pairs[k] >> 8) & 0xFF] = 1;
-        }
-
-        // ---- C: wheels: raycast, suspension, tire, spin
-        for (int wi = tid; wi < 4 * A; wi += BLOCK) {
+        const int wheel_threads = NWV == 1 ? BLOCK : BLOCK - 64;
+        for (int wi = tid; tid < wheel_threads && wi < 4 * A; wi += wheel_threads) {
             const int i = wi >> 2, wh = wi & 3;
             float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float mu_seen = 0.f;
@@ -359,6 +387,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float 
             s_wmu[wi] = mu_seen;
         }
 
+        __syncthreads();
+        const int np = s_np;
         // ---- D: contact points of the compacted pairs, in list order
         int nc = 0;
         for (int base = 0; base < np; base += BLOCK) {
@@ -610,12 +640,15 @@ void launch_step(const DevParams &P, const DevWorld &Wd, float *st, int *ist, co
                  float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
                  int *rec_cnt, int rec_cap, const int *order, int block, hipStream_t s) {
     if (Wd.W == 0) return;
-    if (block <= 64)
-        k_step<64><<<Wd.W, 64, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, order);
-    else if (block <= 128)
-        k_step<128><<<Wd.W, 128, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, order);
-    else
-        k_step<256><<<Wd.W, 256, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, order);
+#define SF_STEP_LAUNCH(B)                                                                                \
+    k_step<B><<<Wd.W, B, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, \
+                                 order)
+    if (block <= 64) SF_STEP_LAUNCH(64);
+    else if (block <= 128) SF_STEP_LAUNCH(128);
+    else if (block <= 192) SF_STEP_LAUNCH(192);
+    else if (block <= 256) SF_STEP_LAUNCH(256);
+    else SF_STEP_LAUNCH(320);
+#undef SF_STEP_LAUNCH
 }
 
 // ------------------------------------------------------------------ reset

@@ -240,8 +240,9 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
         return fail(SF_E_INVALID_ARG, "vehicle parameter out of range");
     if (opts.max_episode_steps <= 0 || opts.collision_warmup < 0)
         return fail(SF_E_INVALID_ARG, "episode options out of range");
-    if (opts.grid_cell < 0.f || !std::isfinite(opts.grid_cell))
-        return fail(SF_E_INVALID_ARG, "grid_cell must be >= 0");
+    if (opts.grid_cell < 0.f || !std::isfinite(opts.grid_cell) || opts.tri_cell < 0.f ||
+        !std::isfinite(opts.tri_cell))
+        return fail(SF_E_INVALID_ARG, "grid_cell and tri_cell must be >= 0");
 
     sf_sim *sim = new sf_sim();
     sim->stream = (hipStream_t)opts.stream;
@@ -251,9 +252,11 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     sim->W = W; sim->N = N; sim->P = P; sim->T = T; sim->E = E; sim->S = d->num_surfaces;
     sim->max_agents = amax;
     sim->flags = opts.flags;
-    sim->step_block = opts.step_block > 0 ? opts.step_block : (amax <= 16 ? 64 : (amax <= 32 ? 128 : 256));
+    // one thread per wheel plus one wave for contact-pair detection
+    sim->step_block = opts.step_block > 0 ? opts.step_block
+                                          : std::min(320, 64 * ((4 * std::max(amax, 1) + 63) / 64) + 64);
     sim->obs_waves = opts.obs_waves > 0 ? opts.obs_waves : 4;
-    sim->policy_rows = opts.policy_rows > 0 ? opts.policy_rows : 64;
+    sim->policy_rows = opts.policy_rows > 0 ? opts.policy_rows : 16;
     sim->steer_max = p->steer_max;
     hipStream_t st = sim->stream;
 
@@ -365,55 +368,71 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     launch_world_bbox(roff, road_xy, toff, verts, W, bbox, st);
     LAUNCHED();
 
-    // ---- grid headers on the host from the device bounding boxes
+    // ---- grid headers on the host from the device bounding boxes: a road
+    // point grid (kNN) and a finer triangle grid (raycast)
     std::vector<float4> hb(W);
     if (W) DEV(hipMemcpyAsync(hb.data(), bbox, sizeof(float4) * W, hipMemcpyDeviceToHost, st));
     DEV(hipStreamSynchronize(st));
-    const float cell0 = opts.grid_cell > 0.f ? opts.grid_cell : 4.f;
-    std::vector<GridHdr> hg(W);
-    long long C = 0;
-    for (int w = 0; w < W; ++w) {
-        GridHdr g{};
-        float4 b = hb[w];
-        if (!(b.x <= b.z) || !(b.y <= b.w)) { b = make_float4(0.f, 0.f, 0.f, 0.f); }
-        float cell = cell0;
-        const float ext = std::max(b.z - b.x, b.w - b.y);
-        if (ext / cell > 2048.f) cell = ext / 2048.f;
-        g.x0 = b.x; g.y0 = b.y; g.cell = cell; g.inv_cell = 1.f / cell;
-        g.nx = std::max(1, (int)std::ceil((b.z - b.x) * g.inv_cell));
-        g.ny = std::max(1, (int)std::ceil((b.w - b.y) * g.inv_cell));
-        g.cbase = (int)C;
-        C += (long long)g.nx * g.ny;
-        hg[w] = g;
+    auto headers = [&](float cell0, std::vector<GridHdr> &hg) {
+        long long C = 0;
+        hg.resize(W);
+        for (int w = 0; w < W; ++w) {
+            GridHdr g{};
+            float4 b = hb[w];
+            if (!(b.x <= b.z) || !(b.y <= b.w)) b = make_float4(0.f, 0.f, 0.f, 0.f);
+            float cell = cell0;
+            const float ext = std::max(b.z - b.x, b.w - b.y);
+            if (ext / cell > 2048.f) cell = ext / 2048.f;
+            g.x0 = b.x; g.y0 = b.y; g.cell = cell; g.inv_cell = 1.f / cell;
+            g.nx = std::max(1, (int)std::ceil((b.z - b.x) * g.inv_cell));
+            g.ny = std::max(1, (int)std::ceil((b.w - b.y) * g.inv_cell));
+            g.cbase = (int)C;
+            C += (long long)g.nx * g.ny;
+            hg[w] = g;
+        }
+        return C;
+    };
+    std::vector<GridHdr> hgp, hgt;
+    const long long CP = headers(opts.grid_cell > 0.f ? opts.grid_cell : 8.f, hgp);
+    const long long CT = headers(opts.tri_cell > 0.f ? opts.tri_cell : 0.5f, hgt);
+    if (CP > (1ll << 30) || CT > (1ll << 30)) {
+        free_all(sim); delete sim;
+        return fail(SF_E_UNSUPPORTED, "road grid too large");
     }
-    if (C > (1ll << 30)) { free_all(sim); delete sim; return fail(SF_E_UNSUPPORTED, "road grid too large"); }
-    sim->C = (int)C;
-    H2D(grid, hg.data(), sizeof(GridHdr) * W);
-    int *tri_cnt, *pt_cnt, *tri_start, *pt_start, *scan_tmp, *pt_items, *tri_cursor, *pt_cursor;
-    ALLOC(tri_cnt, int, C); ALLOC(pt_cnt, int, C);
-    ALLOC(tri_start, int, C + 1); ALLOC(pt_start, int, C + 1);
-    ALLOC(scan_tmp, int, C / 1024 + 2);
-    ALLOC(tri_cursor, int, C + 1); ALLOC(pt_cursor, int, C + 1);
-    DEV(hipMemsetAsync(tri_cnt, 0, sizeof(int) * C, st));
-    DEV(hipMemsetAsync(pt_cnt, 0, sizeof(int) * C, st));
-    launch_grid_count(Wd, verts, tri_cnt, pt_cnt, st);
-    launch_scan(tri_cnt, tri_start, (int)C, scan_tmp, st);
-    launch_scan(pt_cnt, pt_start, (int)C, scan_tmp, st);
+    sim->C = (int)CP;
+    GridHdr *tgrid;
+    ALLOC(tgrid, GridHdr, W);
+    H2D(grid, hgp.data(), sizeof(GridHdr) * W);
+    H2D(tgrid, hgt.data(), sizeof(GridHdr) * W);
+    Wd.tgrid = tgrid;
+    int *tri_cnt, *pt_cnt, *tri_start, *pt_start, *scan_tmp, *pt_items, *tri_cursor, *pt_cursor, *pt_occ;
+    ALLOC(tri_cnt, int, CT); ALLOC(pt_cnt, int, CP);
+    ALLOC(tri_start, int, CT + 1); ALLOC(pt_start, int, CP + 1);
+    ALLOC(scan_tmp, int, std::max(CT, CP) / 1024 + 2);
+    ALLOC(tri_cursor, int, CT + 1); ALLOC(pt_cursor, int, CP + 1);
+    ALLOC(pt_occ, int, CP);
+    DEV(hipMemsetAsync(tri_cnt, 0, sizeof(int) * CT, st));
+    DEV(hipMemsetAsync(pt_cnt, 0, sizeof(int) * CP, st));
+    launch_grid_count(Wd, verts, T, P, tri_cnt, pt_cnt, st);
+    launch_scan(tri_cnt, tri_start, (int)CT, scan_tmp, st);
+    launch_scan(pt_cnt, pt_start, (int)CP, scan_tmp, st);
     LAUNCHED();
     int n_tri_items = 0;
-    DEV(hipMemcpyAsync(&n_tri_items, tri_start + C, sizeof(int), hipMemcpyDeviceToHost, st));
+    DEV(hipMemcpyAsync(&n_tri_items, tri_start + CT, sizeof(int), hipMemcpyDeviceToHost, st));
     DEV(hipStreamSynchronize(st));
     int *tri_items;
     int4 *pt_cell;
+    float4 *tri_rec;
     ALLOC(tri_items, int, n_tri_items);
+    ALLOC(tri_rec, float4, 3 * (size_t)n_tri_items);
     ALLOC(pt_items, int, P);
     ALLOC(pt_cell, int4, P);
-    DEV(hipMemcpyAsync(tri_cursor, tri_start, sizeof(int) * (C + 1), hipMemcpyDeviceToDevice, st));
-    DEV(hipMemcpyAsync(pt_cursor, pt_start, sizeof(int) * (C + 1), hipMemcpyDeviceToDevice, st));
-    Wd.tri_cell_start = tri_start; Wd.tri_items = tri_items;
-    Wd.pt_cell_start = pt_start; Wd.pt_cell = pt_cell;
-    launch_grid_fill(Wd, verts, tri_cursor, pt_cursor, tri_items, pt_items, st);
-    launch_grid_finish(Wd, (int)C, tri_items, pt_items, pt_cell, st);
+    DEV(hipMemcpyAsync(tri_cursor, tri_start, sizeof(int) * (CT + 1), hipMemcpyDeviceToDevice, st));
+    DEV(hipMemcpyAsync(pt_cursor, pt_start, sizeof(int) * (CP + 1), hipMemcpyDeviceToDevice, st));
+    Wd.tri_cell_start = tri_start; Wd.tri_rec = tri_rec;
+    Wd.pt_cell_start = pt_start; Wd.pt_cell = pt_cell; Wd.pt_occ = pt_occ;
+    launch_grid_fill(Wd, verts, T, P, tri_cursor, pt_cursor, tri_items, pt_items, st);
+    launch_grid_finish(Wd, (int)CT, (int)CP, tri_items, pt_items, tri_rec, pt_cell, pt_occ, st);
     LAUNCHED();
 
     // ---- state, outputs, schedule

@@ -6,15 +6,18 @@
 //   worlds  : CSR offsets [W+1] for agents, road points, triangles, spawns
 //   roads   : float2 xy [P], int2 quantised xy [P], u8 type [P]
 //   tris    : float4 [T][4] = (v0, surface) (e1, 0) (e2, 0) (unit normal, 0)
-//   grid    : per world a uniform xy grid; cells of all worlds are numbered
-//             globally (world w owns [cbase, cbase + nx*ny)); two CSR lists
-//             over cells: triangle ids, and road points packed as
-//             (quantised x, quantised y, local index) in cell order
+//   grids   : per world two uniform xy grids (road points; triangles, finer);
+//             cells of all worlds are numbered globally (world w owns
+//             [cbase, cbase + nx*ny)); CSR over cells with the items stored
+//             contiguously in cell order: road points as (quantised x,
+//             quantised y, local index), triangles as full records (so a ray
+//             reads its candidates without an indirection); plus, per point
+//             cell, the Chebyshev distance to the nearest non-empty cell
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/sf.h"
+#include "sf.h"
 
 #define SF_MAXA SF_MAX_AGENTS_PER_WORLD
 #define SF_CCAP 512      // contact points per world and substep
@@ -56,11 +59,13 @@ struct DevWorld {
     const float4 *tri;                   // [T][4]
     const float *mu;                     // [W][S]
     const float *spawn;                  // [E][5]
-    const GridHdr *grid;                 // [W]
-    const int *tri_cell_start;           // [C+1]
-    const int *tri_items;                // world-local triangle ids
-    const int *pt_cell_start;            // [C+1]
+    const GridHdr *grid;                 // [W] road-point grid
+    const GridHdr *tgrid;                // [W] triangle grid (its own cell size)
+    const int *tri_cell_start;           // [CT+1]
+    const float4 *tri_rec;               // [items][3] (v0, id bits) (e1, surface) (e2, 0), cell order
+    const int *pt_cell_start;            // [CP+1]
     const int4 *pt_cell;                 // (qx, qy, local idx, 0) in cell order
+    const int *pt_occ;                   // [CP] Chebyshev distance to the nearest non-empty cell
     unsigned long long seed;
 };
 
@@ -160,12 +165,12 @@ void launch_quantise_roads(const float2 *xy, int2 *q, int P, hipStream_t st);
 void launch_prep_tris(const float *verts, const uint8_t *surf, float4 *tri, int T, hipStream_t st);
 void launch_world_bbox(const int *roff, const float2 *xy, const int *toff, const float *verts, int W,
                        float4 *bbox, hipStream_t st);
-void launch_grid_count(const DevWorld &Wd, const float *verts, int *tri_cnt, int *pt_cnt,
-                       hipStream_t st);
-void launch_grid_fill(const DevWorld &Wd, const float *verts, int *tri_cursor, int *pt_cursor,
-                      int *tri_items, int *pt_items, hipStream_t st);
-void launch_grid_finish(const DevWorld &Wd, int C, int *tri_items, int *pt_items, int4 *pt_cell,
-                        hipStream_t st);
+void launch_grid_count(const DevWorld &Wd, const float *verts, int T, int P, int *tri_cnt,
+                       int *pt_cnt, hipStream_t st);
+void launch_grid_fill(const DevWorld &Wd, const float *verts, int T, int P, int *tri_cursor,
+                      int *pt_cursor, int *tri_items, int *pt_items, hipStream_t st);
+void launch_grid_finish(const DevWorld &Wd, int CT, int CP, int *tri_items, int *pt_items,
+                        float4 *tri_rec, int4 *pt_cell, int *pt_occ, hipStream_t st);
 void launch_scan(const int *in, int *out, int n, int *tmp, hipStream_t st);  // exclusive, out[n]
 void launch_world_of(const int *aoff, int W, int *world_of, hipStream_t st);
 void launch_reset(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const uint8_t *mask,

@@ -63,7 +63,7 @@ class Options(C.Structure):
         ("max_episode_steps", C.c_int32), ("collision_warmup", C.c_int32),
         ("flags", C.c_uint32), ("grid_cell", C.c_float),
         ("step_block", C.c_int32), ("obs_waves", C.c_int32), ("policy_rows", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("tri_cell", C.c_float), ("reserved", C.c_int32 * 4),
     ]
 
 
@@ -154,7 +154,7 @@ class Sim:
 
     def __init__(self, worlds, params: dict, flags: int = 0, stream=None, grid_cell: float = 0.0,
                  step_block: int = 0, obs_waves: int = 0, policy_rows: int = 0,
-                 torch_alloc: bool = True):
+                 tri_cell: float = 0.0, torch_alloc: bool = True):
         import torch
         L = lib()
         self.torch = torch
@@ -194,6 +194,7 @@ class Sim:
         o.step_block = int(step_block)
         o.obs_waves = int(obs_waves)
         o.policy_rows = int(policy_rows)
+        o.tri_cell = float(tri_cell)
         # device memory from torch's caching allocator
         self._blocks = {}
         if torch_alloc:

@@ -437,7 +437,7 @@ def test_policy_mfma_matches_oracle(O, torch):
     bf16 rounding points: relative error per output norm <= 1e-2."""
     w = I.intersections(40, 8, seed=13)      # 320 agents: several 64-row tiles + a ragged tail
     from paper_2605_08528_amd import sf
-    for rows in (32, 64):
+    for rows in (16, 32, 64):
         sim = sf.Sim(w, mkparams(), policy_rows=rows)
         Ws, bs = I.mlp_params([256, 256, 256, 2], seed=5)
         bs = [np.random.default_rng(9).standard_normal(b.shape).astype(np.float32) * 0.1 for b in bs]
@@ -497,3 +497,23 @@ def test_bitwise_determinism(O, torch):
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("block", [64, 128, 192, 256, 320])
+def test_step_block_sizes(O, torch, block):
+    """Every workgroup shape of the step kernel (one wave doing both pairs and
+    wheels, or a pair wave beside wheel waves) gives the same lockstep result."""
+    w = I.intersections(4, 32, seed=16, headway=(6.0, 10.0))
+    prm = mkparams(collision_warmup=0)
+
+    def closing(f, k):
+        rng = np.random.default_rng(3)
+        spd = rng.uniform(-4.0, 14.0, f.shape[1]).astype(np.float32)
+        hx = 1 - 2 * (f[5] ** 2 + f[6] ** 2)
+        hy = 2 * (f[4] * f[5] + f[3] * f[6])
+        f[7], f[8] = spd * hx, spd * hy
+        f[13:17] = spd / 0.35
+
+    worst, n_pairs = lockstep(O, torch, w, 30, 1.0 / 120.0, 1, prm=prm, flags=1, init=closing,
+                              step_block=block)
+    assert n_pairs > 0
