@@ -251,6 +251,86 @@ sf_status sf_graph_launch(sf_sim *sim);
 sf_status sf_profile(sf_sim *sim, int32_t enable);
 sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches);
 
+/* ---- learned tire surrogate.
+ * The paper replaces a validated but expensive vehicle model (its teacher)
+ * by a cheaper one fitted to the teacher's trajectories (Sec. "Vehicle
+ * Asset Generation and System Identification").  The same idea is applied
+ * here to the per-wheel tire: a 16 -> 128 -> 128 -> 128 -> 3 ReLU network
+ * (bf16 operands, fp32 accumulation) is fitted to samples of the plain tire
+ * model and, when enabled, computes (F_x, F_y, M_z) inside the step.
+ *
+ * Domain: a loaded wheel (F_z > 0) with a tire frame and |v_x| >= 3 m/s.
+ * Inputs, each rounded to float: slip ratio (r Omega - v_x) / max(|v_x|,
+ * v_eps), slip angle atan(v_y / max(|v_x|, v_eps)), F_z / 4000, mu,
+ * r Omega / 30, camber asin(axle . n), v_x / 30, v_y / 5, steer angle,
+ * compression / 0.2, compression rate / 2, tau_drive / tau_drive_max,
+ * tau_brake / tau_brake_front, body roll atan2(R21, R22), pitch asin(-R20),
+ * yaw rate / 2.  Outputs (F_x, F_y, M_z / trail) / (mu F_z).
+ * A wheel uses the network only if every input lies inside the training
+ * envelope [lo, hi] and the prediction passes two residual checks (force
+ * inside 1.02 mu F_z, and F_x along the slip when |slip ratio| > 0.02);
+ * otherwise, and outside the domain, the plain tire model runs.  Wheel spin
+ * takes the implicit Coulomb-brake update with the network's F_x.
+ *
+ * Parameter block (SF_SUR_PARAMS floats): W1[128][16] b1[128] W2[128][128]
+ * b2[128] W3[128][128] b3[128] W4[3][128] b4[3], row-major [out][in].
+ * A training sample is SF_SUR_SAMPLE floats: 16 inputs, 3 targets (the
+ * plain model's outputs in the units above) and a validity flag (1 or 0). */
+#define SF_SUR_INPUTS 16
+#define SF_SUR_PARAMS 35587
+#define SF_SUR_SAMPLE 20
+
+/* Log a training sample for every wheel of every substep into a device
+ * ring of `capacity` samples (capacity 0 stops logging and frees the ring).
+ * Slot of agent n, wheel k, substep s of the c-th logged step:
+ * (c * S * 4N + s * 4N + 4n + k) mod capacity (S = that step's substeps);
+ * wheels outside the domain leave a sample flagged invalid.  capacity must
+ * be at most 2^28.  A HIP graph captured while logging replays the same
+ * slots. */
+sf_status sf_sur_log(sf_sim *sim, int64_t capacity);
+/* Copy the ring's valid samples, in slot order, to d_out [max_out][20]
+ * (device); *n_valid receives the number of valid samples (which may exceed
+ * max_out: then only the first max_out are written).  Synchronises. */
+sf_status sf_sur_collect(sf_sim *sim, float *d_out, int64_t max_out, int64_t *n_valid);
+
+typedef struct {
+    int32_t steps;            /* Adam steps (>= 0) */
+    int32_t batch;            /* samples per step, a multiple of 64 drawn with
+                                 replacement; 0 = the whole set in order
+                                 (at most 262144 samples) */
+    float lr, beta1, beta2, eps;   /* Adam (Kingma and Ba 2015) */
+    uint64_t seed;            /* minibatch draws */
+    uint64_t init_seed;       /* nonzero: fresh He-normal weights, zero biases
+                                 and moments before training */
+    int32_t set_envelope;     /* nonzero: envelope := per-input min / max of
+                                 the training set */
+} sf_sur_train_opts;
+
+/* Train on d_data [M][20] (device, valid samples) with the batch-mean
+ * squared error over the three outputs; *loss_out (may be NULL) receives
+ * the last step's loss.  Enqueued on the handle's stream; synchronises. */
+sf_status sf_sur_train(sf_sim *sim, const float *d_data, int64_t M, const sf_sur_train_opts *opts,
+                       float *loss_out);
+/* Gradient of that loss over all M samples (at most 262144) at the current
+ * parameters: h_grad [SF_SUR_PARAMS] (parameter block layout), *h_loss. */
+sf_status sf_sur_gradient(sf_sim *sim, const float *d_data, int64_t M, float *h_grad, float *h_loss);
+/* Network outputs d_pred [M][3] (device) for the inputs of d_data [M][20]. */
+sf_status sf_sur_predict(sf_sim *sim, const float *d_data, int64_t M, float *d_pred);
+/* Relative force error of the network on d_data [M][20]: per sample
+ * |(dF_x, dF_y)| / max(|(F_x, F_y)|, 0.05) in units of mu F_z against the
+ * stored targets; mean and 95th percentile.  Synchronises. */
+sf_status sf_sur_evaluate(sf_sim *sim, const float *d_data, int64_t M, float *h_mean, float *h_p95);
+/* Load (h_params, h_lo, h_hi: 35587, 16, 16 host floats) or read back the
+ * network and its envelope.  Loading clears the Adam moments. */
+sf_status sf_sur_set(sf_sim *sim, const float *h_params, const float *h_lo, const float *h_hi);
+sf_status sf_sur_get(sf_sim *sim, float *h_params, float *h_lo, float *h_hi);
+/* Use the network in later steps (on != 0) or the plain model only. */
+sf_status sf_sur_enable(sf_sim *sim, int32_t on);
+/* Domain wheel-substeps since the last reset of the counters that used the
+ * network (out[0]) or fell back (out[1]); reset != 0 clears them after
+ * reading.  Synchronises. */
+sf_status sf_sur_counts(sf_sim *sim, uint64_t *out, int32_t reset);
+
 const char *sf_status_str(sf_status s);
 const char *sf_last_error(void);
 

@@ -21,6 +21,9 @@ FIELDS = ["px", "py", "pz", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy"
           "om0", "om1", "om2", "om3", "th", "thd", "mu", "gx", "gy", "sx", "sy"]
 IFIELDS = ["active", "ep_step", "since", "episode"]
 EV_GOAL, EV_COLLISION, EV_CRASH, EV_TIMEOUT, EV_NUMERIC, EV_NAN_ACTION = 1, 2, 4, 8, 16, 32
+SUR_IN, SUR_HID, SAMPLE = 16, 128, 20
+SUR_SIZES = [16, 128, 128, 128, 3]
+SUR_PARAMS = 16 * 128 + 128 + 2 * (128 * 128 + 128) + 3 * 128 + 3
 
 
 def build(verbose: bool = False) -> str:
@@ -103,6 +106,9 @@ def lib():
         L.or_adam.argtypes = [ip, vp, vp, vp, vp, ip, C.c_double, C.c_double, C.c_double, C.c_double]
         L.or_tire.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 8 + [dp] * 4
         L.or_set_threads.argtypes = [ip]
+        L.or_set_surrogate.argtypes = [vp, vp, vp, vp, ip]
+        L.or_surrogate_counts.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
+        L.or_record_samples.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -247,6 +253,28 @@ class Oracle:
     def reset(self, mask):
         m = np.ascontiguousarray(mask, np.uint8)
         lib().or_reset(self.h, _ptr(m))
+
+    def set_surrogate(self, params, env_lo, env_hi, enable=True):
+        self._sur = [np.ascontiguousarray(params, np.float32), np.ascontiguousarray(env_lo, np.float32),
+                     np.ascontiguousarray(env_hi, np.float32)]
+        lib().or_set_surrogate(self.h, *[_ptr(a) for a in self._sur], int(enable))
+
+    def surrogate_counts(self):
+        u, f = C.c_longlong(), C.c_longlong()
+        lib().or_surrogate_counts(self.h, C.byref(u), C.byref(f))
+        return u.value, f.value
+
+    def record_samples(self, on=True):
+        """Start recording the last substep's per-wheel surrogate samples."""
+        if on:
+            self._rec = np.zeros((self.N, 4, SAMPLE), np.float32)
+            lib().or_record_samples(self.h, _ptr(self._rec))
+        else:
+            lib().or_record_samples(self.h, None)
+            self._rec = None
+
+    def samples(self):
+        return self._rec.copy()
 
     def detect_pairs(self, world):
         a = int(self.worlds.agent_offsets[world + 1] - self.worlds.agent_offsets[world])

@@ -47,6 +47,12 @@ struct or_sim {
     int32_t *k;      /* [OR_NK][N] */
     /* derived constants */
     double Iw, ell, cr, cd, z_ride;
+    /* learned tire surrogate (optional) */
+    int sur_on;
+    float *sur;                 /* flat parameters, OR_SUR_PARAMS floats */
+    float env_lo[OR_SUR_IN], env_hi[OR_SUR_IN];
+    long long sur_used, sur_fallback;
+    float *sample_rec;          /* [N][4][OR_SAMPLE] of the last substep, or NULL */
 };
 
 #define F(s, fld, i) ((s)->f[(size_t)(fld) * (s)->N + (i)])
@@ -218,6 +224,7 @@ void or_destroy(or_sim *s) {
     free(s->aoff); free(s->roff); free(s->toff); free(s->soff);
     free(s->road_xy); free(s->road_type); free(s->tri); free(s->tri_surf);
     free(s->mu); free(s->spawn); free(s->world_of); free(s->f); free(s->k);
+    free(s->sur);
     free(s);
 }
 
@@ -364,6 +371,30 @@ int or_raycast(const or_sim *s, int i, int wh, double *t, double *n, int *surf, 
     for (int c = 0; c < 3; ++c) { m[c] = p[c] + rm[c]; u[c] = -R[c][2]; }
     return raycast(s, s->world_of[i], m, u, t, n, surf, tri);
 }
+
+/* ------------------------------------------------------- tire surrogate */
+/* Inputs of the learned tire model for one wheel, each scaled to order one:
+ * slip ratio, slip angle, load, friction, rim speed, camber, then the
+ * longitudinal and lateral contact speeds, the wheel's steer angle, spring
+ * compression and rate, drive and brake torque fractions, body roll and
+ * pitch and yaw rate.  Rounded to float (the form in which both the logged
+ * training samples and the inference inputs exist). */
+static void sur_features(const or_sim *s, double Fz, double mu, double vx, double vy, double Om,
+                         double td, double tb, double x, double xd, double delta, double gamma,
+                         double R[3][3], const double *om, float *f) {
+    const or_params *p = &s->p;
+    double D = fabs(vx) > p->v_eps ? fabs(vx) : p->v_eps;
+    double pitch_s = -R[2][0];
+    if (pitch_s > 1.0) pitch_s = 1.0;
+    if (pitch_s < -1.0) pitch_s = -1.0;
+    double v[OR_SUR_IN] = {
+        (p->wheel_radius * Om - vx) / D, atan(vy / D), Fz / 4000.0, mu, p->wheel_radius * Om / 30.0,
+        gamma, vx / 30.0, vy / 5.0, delta, x / 0.2, xd / 2.0, td / p->tau_drive,
+        tb / p->tau_brake_front, atan2(R[2][1], R[2][2]), asin(pitch_s), om[2] / 2.0};
+    for (int k = 0; k < OR_SUR_IN; ++k) f[k] = (float)v[k];
+}
+
+static void sur_forward(const or_sim *s, const float *f, double *y);
 
 /* ---------------------------------------------------------------- tire */
 /* Linear-saturated tire inside the friction circle with an implicit wheel
@@ -564,7 +595,66 @@ static void substep_world(or_sim *s, int w, const float *actions, double h,
                     cross3(om, rc, wc);
                     for (int c = 0; c < 3; ++c) vc[c] = v[c] + wc[c];
                     double vx = dot3(vc, ex), vy = dot3(vc, ey);
-                    or_tire(p, h, Fz, mu, vx, vy, Omega, td, tb, &Fx, &Fy, &Mz, &om_new);
+                    int used = 0;
+                    float feat[OR_SUR_IN];
+                    int in_domain = Fz > 0.0 && fabs(vx) >= 3.0;
+                    if (in_domain && (s->sur_on || s->sample_rec)) {
+                        double ab[3] = {-sin(dl), cos(dl), 0.0}, axle[3];
+                        matvec(R, ab, axle);
+                        double g = dot3(axle, n);
+                        if (g > 1.0) g = 1.0;
+                        if (g < -1.0) g = -1.0;
+                        sur_features(s, Fz, mu, vx, vy, Omega, td, tb, x, xd, dl, asin(g), R, om, feat);
+                    }
+                    if (in_domain && s->sur_on) {
+                        int inside = 1;
+                        for (int q = 0; q < OR_SUR_IN; ++q)
+                            if (!(feat[q] >= s->env_lo[q] && feat[q] <= s->env_hi[q])) inside = 0;
+                        if (inside) {
+                            double y[3];
+                            sur_forward(s, feat, y);
+                            double lim = mu * Fz;
+                            double Fxs = lim * y[0], Fys = lim * y[1];
+                            double kap = (p->wheel_radius * Omega - vx) / fabs(vx);
+                            /* physical residual checks: inside the friction
+                             * circle (2 % slack) and force along the slip */
+                            if (sqrt(Fxs * Fxs + Fys * Fys) <= 1.02 * lim &&
+                                (fabs(kap) <= 0.02 || ((Fxs > 0.0) == (kap > 0.0)))) {
+                                double a = h / s->Iw, Bs = Omega + a * (td - p->wheel_radius * Fxs);
+                                double mag = fabs(Bs) - a * tb;
+                                if (mag < 0.0) mag = 0.0;
+                                Fx = Fxs;
+                                Fy = Fys;
+                                Mz = p->trail * lim * y[2];
+                                om_new = Bs > 0 ? mag : (Bs < 0 ? -mag : 0.0);
+                                used = 1;
+                            }
+                        }
+                    }
+                    if (!used) or_tire(p, h, Fz, mu, vx, vy, Omega, td, tb, &Fx, &Fy, &Mz, &om_new);
+                    if (s->sur_on && in_domain) {
+                        /* worlds run on several threads */
+                        if (used) {
+#pragma omp atomic
+                            s->sur_used++;
+                        } else {
+#pragma omp atomic
+                            s->sur_fallback++;
+                        }
+                    }
+                    if (s->sample_rec && last) {
+                        float *r = s->sample_rec + ((size_t)i * NW + wh) * OR_SAMPLE;
+                        for (int q = 0; q < OR_SAMPLE; ++q) r[q] = 0.0f;
+                        if (in_domain) {
+                            double Fxp, Fyp, Mzp, omp, lim = mu * Fz;
+                            or_tire(p, h, Fz, mu, vx, vy, Omega, td, tb, &Fxp, &Fyp, &Mzp, &omp);
+                            for (int q = 0; q < OR_SUR_IN; ++q) r[q] = feat[q];
+                            r[OR_SUR_IN] = (float)(lim > 0 ? Fxp / lim : 0.0);
+                            r[OR_SUR_IN + 1] = (float)(lim > 0 ? Fyp / lim : 0.0);
+                            r[OR_SUR_IN + 2] = (float)(lim > 0 ? Mzp / (p->trail * lim) : 0.0);
+                            r[OR_SUR_IN + 3] = 1.0f;
+                        }
+                    }
                     tire = 1;
                 }
                 if (!tire) or_tire(p, h, 0.0, mu, 0.0, 0.0, Omega, td, tb, &Fx, &Fy, &Mz, &om_new);
@@ -749,6 +839,8 @@ void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
     double h = dt / S;
     const or_params *p = &s->p;
     int W = s->W;
+    /* a wheel without a tire frame in the last substep records nothing */
+    if (s->sample_rec) memset(s->sample_rec, 0, sizeof(float) * (size_t)s->N * NW * OR_SAMPLE);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int w = 0; w < W; ++w) {
         int a0 = s->aoff[w], a1 = s->aoff[w + 1], A = a1 - a0;
@@ -1039,6 +1131,37 @@ double or_mlp_mse_grad(int L, const int *sz, const float *const *W, const float 
     free(d0); free(d1);
     return loss;
 }
+
+/* surrogate forward in FP64 with the bf16 rounding points */
+static void sur_forward(const or_sim *s, const float *f, double *y) {
+    int sz[5] = {OR_SUR_IN, OR_SUR_HID, OR_SUR_HID, OR_SUR_HID, 3};
+    const float *Wp[4], *bp[4];
+    const float *q = s->sur;
+    for (int l = 0; l < 4; ++l) {
+        Wp[l] = q;
+        q += sz[l] * sz[l + 1];
+        bp[l] = q;
+        q += sz[l + 1];
+    }
+    or_mlp_forward(4, sz, Wp, bp, 1, 1, f, y);
+}
+
+void or_set_surrogate(or_sim *s, const float *params, const float *env_lo, const float *env_hi,
+                      int enable) {
+    if (!s->sur) s->sur = (float *)malloc(sizeof(float) * OR_SUR_PARAMS);
+    if (params) memcpy(s->sur, params, sizeof(float) * OR_SUR_PARAMS);
+    if (env_lo) memcpy(s->env_lo, env_lo, sizeof(float) * OR_SUR_IN);
+    if (env_hi) memcpy(s->env_hi, env_hi, sizeof(float) * OR_SUR_IN);
+    s->sur_on = enable;
+    s->sur_used = s->sur_fallback = 0;
+}
+
+void or_surrogate_counts(const or_sim *s, long long *used, long long *fallback) {
+    *used = s->sur_used;
+    *fallback = s->sur_fallback;
+}
+
+void or_record_samples(or_sim *s, float *rec) { s->sample_rec = rec; }
 
 /* Adam (Kingma and Ba 2015) with bias correction */
 void or_adam(int n, float *w, const double *g, double *m, double *v, int step, double lr,

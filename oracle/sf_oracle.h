@@ -39,6 +39,10 @@ enum { OR_ACTIVE, OR_EPSTEP, OR_SINCE, OR_EPISODE, OR_NK };
 #define OR_EV_NUMERIC 16u
 #define OR_EV_NAN_ACTION 32u
 
+#define OR_SUR_IN 16
+#define OR_SUR_HID 128
+#define OR_SUR_PARAMS (16 * 128 + 128 + 2 * (128 * 128 + 128) + 3 * 128 + 3)
+#define OR_SAMPLE (OR_SUR_IN + 4) /* features, 3 targets, valid flag */
 #define OR_OBS_DIM 256
 #define OR_ROAD_K 64
 #define OR_NEIGH_K 8
@@ -141,6 +145,20 @@ void or_adam(int n, float *w, const double *g, double *m, double *v,
 void or_tire(const or_params *p, double h, double Fz, double mu, double vx,
              double vy, double omega, double tau_d, double tau_b, double *Fx,
              double *Fy, double *Mz, double *omega_new);
+
+/* Learned tire surrogate inside the step: flat parameters W1[128][16] b1
+ * W2[128][128] b2 W3[128][128] b3 W4[3][128] b4 (ReLU hidden, outputs
+ * (F_x, F_y, M_z / trail) / (mu F_z)); a wheel uses it when it carries load,
+ * |v_x| >= 3 m/s, its inputs lie inside [env_lo, env_hi] and the output
+ * passes the friction-circle (2 %) and slip-direction checks; otherwise the
+ * plain tire model. */
+void or_set_surrogate(or_sim *s, const float *params, const float *env_lo, const float *env_hi,
+                      int enable);
+void or_surrogate_counts(const or_sim *s, long long *used, long long *fallback);
+/* Record, for the last substep of each step, every wheel's surrogate inputs
+ * and plain-model targets: rec [N][4][OR_SAMPLE] (valid flag last; zeros
+ * outside the surrogate's domain).  NULL stops recording. */
+void or_record_samples(or_sim *s, float *rec);
 
 void or_set_threads(int n);
 

@@ -6,11 +6,6 @@
 // 1 KB store per wave.
 #include "sf_dev.h"
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 __device__ __forceinline__ unsigned long long lane_lt() {
     unsigned lane = threadIdx.x & 63;
     return lane ? (~0ull >> (64 - lane)) : 0ull;

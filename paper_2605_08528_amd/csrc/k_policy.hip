@@ -17,15 +17,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #define PL_HID 256
 #define PL_LD (PL_HID + 8)  // padded LDS row (bf16 elements) against bank conflicts
 
-// round-to-nearest-even float -> bf16 bits
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
 __device__ __forceinline__ float elu(float x) { return x > 0.f ? x : expm1f(x); }
 
 // one hidden layer: out[TM][256] = act(in[TM][256] W^T + b), bf16 in LDS

@@ -165,6 +165,61 @@ __device__ __forceinline__ f3 inv_inertia(const DevParams &P, const float R[9], 
     return Rmul(R, b);
 }
 
+// ------------------------------------------------------ surrogate inference
+#define SUR_LD 136  // row stride (bf16) of a wave's activation tile
+
+__device__ __forceinline__ void sur_store(const f32x4 (&acc)[4][8], uint16_t *buf, const float *bias) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int col = c * 16 + r16;
+        const float b = bias[col];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) buf[(r * 16 + kq * 4 + j) * SUR_LD + col] = f2bf(fmaxf(acc[r][c][j] + b, 0.f));
+    }
+}
+
+// The learned tire model on the 64 wheels of one wave (row = lane): bf16
+// inputs and weights on the matrix cores, fp32 accumulation, each layer
+// computed into registers and written back over its input tile.  Lanes
+// outside the model's domain run with zero inputs and ignore the result.
+__device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool inside, const DevSur &Su,
+                             float (&y)[3]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) buf[lane * SUR_LD + q] = (q < SF_SUR_IN && inside) ? f2bf(feat[q]) : (uint16_t)0;
+    wave_sync();
+    f32x4 acc[4][8];
+    zero_acc(acc);
+    mfma_nt<4, 8, 1>(acc, [&](int r, int k0) { return ld8(buf + r * SUR_LD + k0); },
+                     [&](int c, int k0) { return k0 < SF_SUR_IN ? ld8(Su.Wb + SF_SURB_W1 + c * SF_SUR_IN + k0) : zero8(); });
+    wave_sync();
+    sur_store(acc, buf, Su.P + SF_SUR_B1);
+    wave_sync();
+    zero_acc(acc);
+    mfma_nt<4, 8, 4>(acc, [&](int r, int k0) { return ld8(buf + r * SUR_LD + k0); },
+                     [&](int c, int k0) { return ld8(Su.Wb + SF_SURB_W2 + c * SF_SUR_HID + k0); });
+    wave_sync();
+    sur_store(acc, buf, Su.P + SF_SUR_B2);
+    wave_sync();
+    zero_acc(acc);
+    mfma_nt<4, 8, 4>(acc, [&](int r, int k0) { return ld8(buf + r * SUR_LD + k0); },
+                     [&](int c, int k0) { return ld8(Su.Wb + SF_SURB_W3 + c * SF_SUR_HID + k0); });
+    wave_sync();
+    sur_store(acc, buf, Su.P + SF_SUR_B3);
+    wave_sync();
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        float a = Su.P[SF_SUR_B4 + o];
+        for (int k = 0; k < SF_SUR_HID; ++k)
+            a += bf2f(buf[lane * SUR_LD + k]) * bf2f(Su.Wb[SF_SURB_W4 + o * SF_SUR_HID + k]);
+        y[o] = a;
+    }
+    wave_sync();
+}
+
 __device__ __forceinline__ unsigned long long lanemask_lt() {
     unsigned lane = threadIdx.x & 63;
     return lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -181,8 +236,8 @@ __device__ __forceinline__ void pair_of(int k, int A, int &i, int &j) {
     j = k - ii * (2 * A - ii - 1) / 2 + ii + 1;
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float *__restrict__ st,
+template <int BLOCK, bool SUR>
+__global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur Su, float *__restrict__ st,
                                                 int *__restrict__ ist, const float *__restrict__ act,
                                                 float h, int S, float *__restrict__ reward,
                                                 uint8_t *__restrict__ done, uint8_t *__restrict__ events,
@@ -214,6 +269,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float 
     __shared__ int s_bn[SF_MAXA];
     __shared__ int s_scan[NWV];
     __shared__ int s_np;
+    constexpr int NSW = NWV == 1 ? 1 : NWV - 1;  // waves that run wheels
+    __shared__ __attribute__((aligned(16))) uint16_t s_sur[SUR ? NSW * 64 * SUR_LD : 8];
 
     // ---- load the world's agents; decode actions (Sec. "Action Space Details")
     for (int i = tid; i < A; i += BLOCK) {
@@ -330,61 +387,165 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float 
             if (lane == 0) s_np = np_w;
         }
         const int wheel_threads = NWV == 1 ? BLOCK : BLOCK - 64;
-        for (int wi = tid; tid < wheel_threads && wi < 4 * A; wi += wheel_threads) {
-            const int i = wi >> 2, wh = wi & 3;
-            float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            float mu_seen = 0.f;
-            if (s_act[i]) {
+        if (tid < wheel_threads) {
+            // the loop bound is the same for every lane of a wave (the
+            // surrogate's matrix products need the whole wave)
+            for (int base = 0; base < 4 * A; base += wheel_threads) {
+                const int wi = base + tid;
+                const bool valid = wi < 4 * A;
+                const int i = valid ? (wi >> 2) : 0, wh = wi & 3;
+                const bool live = valid && s_act[i];
+                float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float mu_seen = 0.f;
                 float R[9];
+                f3 v = mk3(0.f, 0.f, 0.f), om = v, rm = v, u = v, n = v, rc = v, ex = v, ey = v;
+                float Om = 0.f, td = 0.f, tb = 0.f, mu = 0.f, Fz = 0.f, vx = 0.f, vy = 0.f, x = 0.f, xd = 0.f, dl = 0.f;
+                bool hit = false, frame = false;
+                if (live) {
 #pragma unroll
-                for (int c = 0; c < 9; ++c) R[c] = s_R[c][i];
-                const f3 pos = mk3(s_p[0][i], s_p[1][i], s_p[2][i]);
-                const f3 v = mk3(s_v[0][i], s_v[1][i], s_v[2][i]);
-                const f3 om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
-                const f3 rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
-                const f3 m = add3(pos, rm);
-                const f3 u = mk3(-R[2], -R[5], -R[8]);
-                RayHit H = raycast(P, Wd, w, m, u);
-                const float Om = s_om[wi];
-                const float td = wh < 2 ? s_taud[i] : 0.f;
-                const float tb = s_brk[i] * (wh < 2 ? P.tau_bf : P.tau_br);
-                float Fx = 0.f, Fy = 0.f, om1;
-                if (H.hit) {
-                    const float mu = Wd.mu[w * Wd.S + H.surf];
-                    mu_seen = mu;
-                    // massless spring-damper along the ray
-                    const float x = P.ell - H.t;
-                    const f3 vm = add3(v, cross3(om, rm));
-                    const float xd = -dot3(H.n, vm) / (-dot3(H.n, u));
-                    const float Fz = fmaxf(P.susp_k * x + P.susp_c * xd, 0.f);
-                    const f3 rc = add3(rm, mul3(u, H.t));
-                    // tire frame: wheel heading projected on the contact plane
-                    const float dl = wh < 2 ? s_th[i] : 0.f;
-                    const f3 hw = Rmul(R, mk3(cosf(dl), sinf(dl), 0.f));
-                    f3 ex = sub3(hw, mul3(H.n, dot3(hw, H.n)));
-                    const float L = sqrtf(dot3(ex, ex));
-                    f3 ey = mk3(0.f, 0.f, 0.f);
-                    if (L > 1e-9f) {
-                        ex = mul3(ex, 1.f / L);
-                        ey = cross3(H.n, ex);
-                        const f3 vc = add3(v, cross3(om, rc));
-                        tire(P, h, Fz, mu, dot3(vc, ex), dot3(vc, ey), Om, td, tb, Fx, Fy, om1);
-                    } else {
-                        ex = mk3(0.f, 0.f, 0.f);
-                        tire(P, h, 0.f, mu, 0.f, 0.f, Om, td, tb, Fx, Fy, om1);
+                    for (int c = 0; c < 9; ++c) R[c] = s_R[c][i];
+                    const f3 pos = mk3(s_p[0][i], s_p[1][i], s_p[2][i]);
+                    v = mk3(s_v[0][i], s_v[1][i], s_v[2][i]);
+                    om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
+                    rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
+                    u = mk3(-R[2], -R[5], -R[8]);
+                    const RayHit H = raycast(P, Wd, w, add3(pos, rm), u);
+                    Om = s_om[wi];
+                    td = wh < 2 ? s_taud[i] : 0.f;
+                    tb = s_brk[i] * (wh < 2 ? P.tau_bf : P.tau_br);
+                    hit = H.hit;
+                    if (hit) {
+                        n = H.n;
+                        mu = Wd.mu[w * Wd.S + H.surf];
+                        mu_seen = mu;
+                        // massless spring-damper along the ray
+                        x = P.ell - H.t;
+                        const f3 vm = add3(v, cross3(om, rm));
+                        xd = -dot3(n, vm) / (-dot3(n, u));
+                        Fz = fmaxf(P.susp_k * x + P.susp_c * xd, 0.f);
+                        rc = add3(rm, mul3(u, H.t));
+                        // tire frame: wheel heading projected on the contact plane
+                        dl = wh < 2 ? s_th[i] : 0.f;
+                        const f3 hw = Rmul(R, mk3(cosf(dl), sinf(dl), 0.f));
+                        ex = sub3(hw, mul3(n, dot3(hw, n)));
+                        const float L = sqrtf(dot3(ex, ex));
+                        if (L > 1e-9f) {
+                            frame = true;
+                            ex = mul3(ex, 1.f / L);
+                            ey = cross3(n, ex);
+                            const f3 vc = add3(v, cross3(om, rc));
+                            vx = dot3(vc, ex);
+                            vy = dot3(vc, ey);
+                        } else {
+                            ex = mk3(0.f, 0.f, 0.f);
+                        }
                     }
-                    const f3 fw = add3(add3(mul3(H.n, Fz), mul3(ex, Fx)), mul3(ey, Fy));
-                    const f3 tq = add3(cross3(rc, fw), mul3(H.n, -P.trail * Fy));
-                    f[0] = fw.x; f[1] = fw.y; f[2] = fw.z;
-                    f[3] = tq.x; f[4] = tq.y; f[5] = tq.z;
-                } else {
-                    tire(P, h, 0.f, 0.f, 0.f, 0.f, Om, td, tb, Fx, Fy, om1);
                 }
-                s_om[wi] = om1;
-            }
+                // the surrogate's domain: a loaded wheel at |v_x| >= 3 m/s
+                const bool dom = frame && Fz > 0.f && fabsf(vx) >= 3.f;
+                float feat[SF_SUR_IN];
+                if (SUR || Su.log) {
+                    if (dom) {
+                        const float D = fmaxf(fabsf(vx), P.v_eps);
+                        const f3 axle = Rmul(R, mk3(-sinf(dl), cosf(dl), 0.f));
+                        feat[0] = (P.rw * Om - vx) / D;
+                        feat[1] = atanf(vy / D);
+                        feat[2] = Fz / 4000.f;
+                        feat[3] = mu;
+                        feat[4] = P.rw * Om / 30.f;
+                        feat[5] = asinf(fminf(fmaxf(dot3(axle, n), -1.f), 1.f));
+                        feat[6] = vx / 30.f;
+                        feat[7] = vy / 5.f;
+                        feat[8] = dl;
+                        feat[9] = x / 0.2f;
+                        feat[10] = xd / 2.f;
+                        feat[11] = td / P.tau_drive;
+                        feat[12] = tb / P.tau_bf;
+                        feat[13] = atan2f(R[7], R[8]);
+                        feat[14] = asinf(fminf(fmaxf(-R[6], -1.f), 1.f));
+                        feat[15] = om.z / 2.f;
+                    } else {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) s_wf[c][wi] = f[c];
-            s_wmu[wi] = mu_seen;
+                        for (int q = 0; q < SF_SUR_IN; ++q) feat[q] = 0.f;
+                    }
+                }
+                // ---- learned tire model for the wave's wheels, if enabled
+                bool use = false;
+                float Fxs = 0.f, Fys = 0.f, Mzs = 0.f;
+                if (SUR) {
+                    bool inside = dom;
+#pragma unroll
+                    for (int q = 0; q < SF_SUR_IN; ++q) inside = inside && feat[q] >= Su.lo[q] && feat[q] <= Su.hi[q];
+                    if (__ballot(inside)) {
+                        float y[3];
+                        sur_mlp_wave(s_sur + wave * 64 * SUR_LD, feat, inside, Su, y);
+                        if (inside) {
+                            const float lim = mu * Fz;
+                            Fxs = lim * y[0];
+                            Fys = lim * y[1];
+                            Mzs = P.trail * lim * y[2];
+                            const float kap = (P.rw * Om - vx) / fabsf(vx);
+                            // residual checks: inside the friction circle (2 %
+                            // slack) and longitudinal force along the slip
+                            use = sqrtf(Fxs * Fxs + Fys * Fys) <= 1.02f * lim &&
+                                  (fabsf(kap) <= 0.02f || ((Fxs > 0.f) == (kap > 0.f)));
+                        }
+                    }
+                    // one counter update per wave, not per wheel
+                    const unsigned long long bu = __ballot(dom && use), bf = __ballot(dom && !use);
+                    if (lane == 0 && bu) atomicAdd(Su.counts, (unsigned long long)__popcll(bu));
+                    if (lane == 0 && bf) atomicAdd(Su.counts + 1, (unsigned long long)__popcll(bf));
+                }
+                if (live) {
+                    float Fx = 0.f, Fy = 0.f, Mz = 0.f, om1;
+                    if (frame) {
+                        if (use) {
+                            Fx = Fxs;
+                            Fy = Fys;
+                            Mz = Mzs;
+                            const float a = h / P.Iw, Bs = Om + a * (td - P.rw * Fx);
+                            const float mag = fmaxf(fabsf(Bs) - a * tb, 0.f);
+                            om1 = Bs > 0.f ? mag : (Bs < 0.f ? -mag : 0.f);
+                        } else {
+                            tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fx, Fy, om1);
+                            Mz = -P.trail * Fy;
+                        }
+                    } else {
+                        // airborne wheel or no usable tire frame: no load
+                        tire(P, h, 0.f, hit ? mu : 0.f, 0.f, 0.f, Om, td, tb, Fx, Fy, om1);
+                    }
+                    if (hit) {
+                        const f3 fw = add3(add3(mul3(n, Fz), mul3(ex, Fx)), mul3(ey, Fy));
+                        const f3 tq = add3(cross3(rc, fw), mul3(n, Mz));
+                        f[0] = fw.x; f[1] = fw.y; f[2] = fw.z;
+                        f[3] = tq.x; f[4] = tq.y; f[5] = tq.z;
+                    }
+                    s_om[wi] = om1;
+                }
+                // ---- training samples: inputs and the plain model's outputs
+                if (Su.log && valid) {
+                    const long long slot = (Su.log_base + (long long)sub * 4 * N + 4ll * (a0 + i) + wh) % Su.log_cap;
+                    float *dst = Su.log + slot * SF_SUR_SAMPLE;
+                    if (dom) {
+                        float Fxp, Fyp, omp;
+                        tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fxp, Fyp, omp);
+                        const float lim = mu * Fz;
+#pragma unroll
+                        for (int q = 0; q < SF_SUR_IN; ++q) dst[q] = feat[q];
+                        dst[SF_SUR_IN] = lim > 0.f ? Fxp / lim : 0.f;
+                        dst[SF_SUR_IN + 1] = lim > 0.f ? Fyp / lim : 0.f;
+                        dst[SF_SUR_IN + 2] = lim > 0.f ? -Fyp / lim : 0.f;
+                        dst[SF_SUR_IN + 3] = 1.f;
+                    } else {
+                        dst[SF_SUR_IN + 3] = 0.f;
+                    }
+                }
+                if (valid) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) s_wf[c][wi] = f[c];
+                    s_wmu[wi] = mu_seen;
+                }
+            }
         }
 
         __syncthreads();
@@ -636,13 +797,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, float 
     }
 }
 
-void launch_step(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act,
-                 float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
+void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
+                 const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
                  int *rec_cnt, int rec_cap, const int *order, int block, hipStream_t s) {
     if (Wd.W == 0) return;
-#define SF_STEP_LAUNCH(B)                                                                                \
-    k_step<B><<<Wd.W, B, 0, s>>>(P, Wd, st, ist, act, h, S, reward, done, events, rec, rec_cnt, rec_cap, \
-                                 order)
+#define SF_STEP_LAUNCH(B)                                                                                     \
+    do {                                                                                                      \
+        if (use_sur)                                                                                          \
+            k_step<B, true><<<Wd.W, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,      \
+                                               rec_cnt, rec_cap, order);                                      \
+        else                                                                                                  \
+            k_step<B, false><<<Wd.W, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,     \
+                                                rec_cnt, rec_cap, order);                                     \
+    } while (0)
     if (block <= 64) SF_STEP_LAUNCH(64);
     else if (block <= 128) SF_STEP_LAUNCH(128);
     else if (block <= 192) SF_STEP_LAUNCH(192);

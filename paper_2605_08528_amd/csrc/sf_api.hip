@@ -2,7 +2,9 @@
 // device memory, create-time preparation (friction table, road grid, first
 // spawn and observation) and the enqueueing of the step kernels.
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -11,6 +13,9 @@
 #include "sf_dev.h"
 
 static thread_local std::string g_err;
+
+// largest number of 64-sample tiles in one surrogate gradient
+#define SUR_MAX_TILES 4096
 
 static sf_status fail(sf_status s, const std::string &msg) {
     g_err = msg;
@@ -45,6 +50,21 @@ struct sf_sim {
     uint16_t *pol_bf16 = nullptr;   // bf16 copies of W1, W2, W3
     float *pol_act = nullptr;       // [N][2] actions of sf_step_policy
     bool policy_loaded = false;
+    // learned tire surrogate
+    float *sur_P = nullptr, *sur_m = nullptr, *sur_v = nullptr, *sur_gsum = nullptr;
+    uint16_t *sur_Wb = nullptr;
+    unsigned long long *sur_counts = nullptr;
+    float *sur_loss = nullptr, *sur_env = nullptr;   // per-tile losses; envelope partials + lo/hi
+    float sur_lo[SF_SUR_IN] = {}, sur_hi[SF_SUR_IN] = {};
+    bool sur_ready = false, sur_on = false;
+    long long sur_t = 0;                             // Adam steps taken
+    float *sur_log = nullptr;
+    long long sur_log_cap = 0, sur_log_base = 0;
+    int *sur_flag = nullptr, *sur_pos = nullptr, *sur_scan = nullptr;
+    float *sur_grad = nullptr;
+    long long sur_grad_tiles = 0;
+    float *sur_pred = nullptr, *sur_err = nullptr;
+    long long sur_pred_cap = 0;
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -100,6 +120,15 @@ static void *dev_alloc(sf_sim *s, size_t bytes) {
     }
     if (p) s->allocs.push_back(p);
     return p;
+}
+
+static void dev_free(sf_sim *s, void *p) {
+    if (!p) return;
+    auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
+    if (it == s->allocs.end()) return;
+    s->allocs.erase(it);
+    if (s->free_fn) s->free_fn(p, s->alloc_ctx);
+    else if (!s->alloc) (void)hipFree(p);
 }
 
 static void free_all(sf_sim *s) {
@@ -510,8 +539,20 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
     const float h = dt / (float)substeps;
     {
         ProfScope ps(sim, 1);
-        launch_step(sim->P_dev, sim->Wd, sim->st, sim->ist, d_actions, h, substeps, sim->reward, sim->done,
-                    sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->order, sim->step_block, sim->stream);
+        DevSur Su{};
+        Su.Wb = sim->sur_Wb;
+        Su.P = sim->sur_P;
+        std::memcpy(Su.lo, sim->sur_lo, sizeof(Su.lo));
+        std::memcpy(Su.hi, sim->sur_hi, sizeof(Su.hi));
+        Su.counts = sim->sur_counts;
+        Su.log = sim->sur_log;
+        Su.log_cap = sim->sur_log_cap;
+        Su.log_base = sim->sur_log_base;
+        launch_step(sim->P_dev, sim->Wd, Su, sim->sur_on, sim->st, sim->ist, d_actions, h, substeps, sim->reward,
+                    sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->order, sim->step_block,
+                    sim->stream);
+        if (sim->sur_log)
+            sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;
     }
     {
         ProfScope ps(sim, 2);
@@ -621,6 +662,263 @@ sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches) {
         total_ms[r.kind] += ms;
         launches[r.kind] += 1;
     }
+    return SF_OK;
+}
+
+// ------------------------------------------------------ learned tire surrogate
+static sf_status sur_alloc(sf_sim *sim) {
+    if (sim->sur_P) return SF_OK;
+    sim->sur_P = (float *)dev_alloc(sim, sizeof(float) * SF_SUR_PARAMS);
+    sim->sur_m = (float *)dev_alloc(sim, sizeof(float) * SF_SUR_PARAMS);
+    sim->sur_v = (float *)dev_alloc(sim, sizeof(float) * SF_SUR_PARAMS);
+    sim->sur_gsum = (float *)dev_alloc(sim, sizeof(float) * SF_SUR_PARAMS);
+    sim->sur_Wb = (uint16_t *)dev_alloc(sim, sizeof(uint16_t) * SF_SURB_TOTAL);
+    sim->sur_counts = (unsigned long long *)dev_alloc(sim, 2 * sizeof(unsigned long long));
+    sim->sur_loss = (float *)dev_alloc(sim, sizeof(float) * SUR_MAX_TILES);
+    sim->sur_env = (float *)dev_alloc(sim, sizeof(float) * (64 * SF_SUR_IN * 2 + 2 * SF_SUR_IN));
+    if (!sim->sur_P || !sim->sur_m || !sim->sur_v || !sim->sur_gsum || !sim->sur_Wb || !sim->sur_counts ||
+        !sim->sur_loss || !sim->sur_env)
+        return fail(SF_E_OUT_OF_MEMORY, "surrogate buffers");
+    DEV(hipMemsetAsync(sim->sur_m, 0, sizeof(float) * SF_SUR_PARAMS, sim->stream));
+    DEV(hipMemsetAsync(sim->sur_v, 0, sizeof(float) * SF_SUR_PARAMS, sim->stream));
+    DEV(hipMemsetAsync(sim->sur_counts, 0, 2 * sizeof(unsigned long long), sim->stream));
+    return SF_OK;
+}
+
+static sf_status sur_grad_buf(sf_sim *sim, long long tiles) {
+    if (tiles <= sim->sur_grad_tiles) return SF_OK;
+    DEV(hipStreamSynchronize(sim->stream));
+    dev_free(sim, sim->sur_grad);
+    sim->sur_grad_tiles = 0;
+    sim->sur_grad = (float *)dev_alloc(sim, sizeof(float) * SF_SUR_PARAMS * (size_t)tiles);
+    if (!sim->sur_grad) return fail(SF_E_OUT_OF_MEMORY, "surrogate gradient tiles");
+    sim->sur_grad_tiles = tiles;
+    return SF_OK;
+}
+
+static sf_status sur_pred_buf(sf_sim *sim, long long M) {
+    if (M <= sim->sur_pred_cap) return SF_OK;
+    DEV(hipStreamSynchronize(sim->stream));
+    dev_free(sim, sim->sur_pred);
+    dev_free(sim, sim->sur_err);
+    sim->sur_pred_cap = 0;
+    sim->sur_pred = (float *)dev_alloc(sim, sizeof(float) * 3 * (size_t)M);
+    sim->sur_err = (float *)dev_alloc(sim, sizeof(float) * (size_t)M);
+    if (!sim->sur_pred || !sim->sur_err) return fail(SF_E_OUT_OF_MEMORY, "surrogate predictions");
+    sim->sur_pred_cap = M;
+    return SF_OK;
+}
+
+sf_status sf_sur_log(sf_sim *sim, int64_t capacity) {
+    CHECK_SIM(sim);
+    if (capacity < 0 || capacity > (1ll << 28)) return fail(SF_E_INVALID_ARG, "capacity must be in 0..2^28");
+    DEV(hipStreamSynchronize(sim->stream));
+    dev_free(sim, sim->sur_log);
+    dev_free(sim, sim->sur_flag);
+    dev_free(sim, sim->sur_pos);
+    dev_free(sim, sim->sur_scan);
+    sim->sur_log = nullptr; sim->sur_flag = sim->sur_pos = sim->sur_scan = nullptr;
+    sim->sur_log_cap = sim->sur_log_base = 0;
+    if (capacity == 0) return SF_OK;
+    sim->sur_log = (float *)dev_alloc(sim, sizeof(float) * SF_SUR_SAMPLE * (size_t)capacity);
+    sim->sur_flag = (int *)dev_alloc(sim, sizeof(int) * (size_t)capacity);
+    sim->sur_pos = (int *)dev_alloc(sim, sizeof(int) * ((size_t)capacity + 1));
+    sim->sur_scan = (int *)dev_alloc(sim, sizeof(int) * ((size_t)capacity / 1024 + 2));
+    if (!sim->sur_log || !sim->sur_flag || !sim->sur_pos || !sim->sur_scan)
+        return fail(SF_E_OUT_OF_MEMORY, "sample ring");
+    DEV(hipMemsetAsync(sim->sur_log, 0, sizeof(float) * SF_SUR_SAMPLE * (size_t)capacity, sim->stream));
+    sim->sur_log_cap = capacity;
+    return SF_OK;
+}
+
+sf_status sf_sur_collect(sf_sim *sim, float *d_out, int64_t max_out, int64_t *n_valid) {
+    CHECK_SIM(sim);
+    if (!sim->sur_log) return fail(SF_E_INVALID_ARG, "no sample ring (sf_sur_log)");
+    if (!n_valid || max_out < 0 || (max_out > 0 && !d_out)) return fail(SF_E_INVALID_ARG, "bad output");
+    const int n = (int)sim->sur_log_cap;
+    launch_sur_collect(sim->sur_log, n, sim->sur_flag, sim->sur_pos, sim->sur_scan, d_out,
+                       (int)std::min<int64_t>(max_out, INT32_MAX), sim->stream);
+    LAUNCHED();
+    int tot = 0;
+    DEV(hipMemcpyAsync(&tot, sim->sur_pos + n, sizeof(int), hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    *n_valid = tot;
+    return SF_OK;
+}
+
+static sf_status sur_check_data(const float *d, int64_t M, int64_t max_m) {
+    if (M < 1 || M > max_m) return fail(SF_E_INVALID_ARG, "sample count out of range (1.." + std::to_string(max_m) + ")");
+    if (!d) return fail(SF_E_INVALID_ARG, "data is NULL");
+    return SF_OK;
+}
+
+sf_status sf_sur_train(sf_sim *sim, const float *d_data, int64_t M, const sf_sur_train_opts *o, float *loss_out) {
+    CHECK_SIM(sim);
+    if (!o) return fail(SF_E_INVALID_ARG, "opts is NULL");
+    sf_status r;
+    if ((r = sur_check_data(d_data, M, INT32_MAX)) != SF_OK) return r;
+    if (o->steps < 0 || o->batch < 0 || o->batch % 64 || o->batch > 64 * SUR_MAX_TILES)
+        return fail(SF_E_INVALID_ARG, "steps >= 0 and batch a multiple of 64 up to 262144 required");
+    if (o->batch == 0 && M > 64ll * SUR_MAX_TILES)
+        return fail(SF_E_INVALID_ARG, "full-batch training takes at most 262144 samples");
+    if (!(o->lr > 0.f) || !std::isfinite(o->lr) || !(o->beta1 >= 0.f && o->beta1 < 1.f) ||
+        !(o->beta2 >= 0.f && o->beta2 < 1.f) || !(o->eps > 0.f))
+        return fail(SF_E_INVALID_ARG, "bad Adam hyper-parameters");
+    if (!sim->sur_ready && !o->init_seed) return fail(SF_E_INVALID_ARG, "no parameters: give init_seed or sf_sur_set");
+    if ((r = sur_alloc(sim)) != SF_OK) return r;
+    hipStream_t st = sim->stream;
+    if (o->init_seed) {
+        launch_sur_init(sim->sur_P, o->init_seed, st);
+        launch_sur_pack(sim->sur_P, sim->sur_Wb, st);
+        DEV(hipMemsetAsync(sim->sur_m, 0, sizeof(float) * SF_SUR_PARAMS, st));
+        DEV(hipMemsetAsync(sim->sur_v, 0, sizeof(float) * SF_SUR_PARAMS, st));
+        sim->sur_t = 0;
+    }
+    if (o->set_envelope) {
+        float *lo = sim->sur_env + 64 * SF_SUR_IN * 2, *hi = lo + SF_SUR_IN;
+        launch_sur_envelope(d_data, (int)M, sim->sur_env, lo, hi, st);
+        DEV(hipMemcpyAsync(sim->sur_lo, lo, sizeof(sim->sur_lo), hipMemcpyDeviceToHost, st));
+        DEV(hipMemcpyAsync(sim->sur_hi, hi, sizeof(sim->sur_hi), hipMemcpyDeviceToHost, st));
+    }
+    const long long tiles = o->batch ? o->batch / 64 : (M + 63) / 64;
+    if ((r = sur_grad_buf(sim, tiles)) != SF_OK) return r;
+    for (int k = 0; k < o->steps; ++k) {
+        if (o->batch == 0) {
+            launch_sur_grad_seq(d_data, (int)M, sim->sur_P, sim->sur_Wb, sim->sur_grad, sim->sur_loss, st);
+        } else {
+            // per-step draw key (never 0, which would mean "rows in order")
+            unsigned long long key = o->seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(sim->sur_t + 1);
+            key ^= key >> 31;
+            key *= 0xBF58476D1CE4E5B9ull;
+            key ^= key >> 29;
+            if (!key) key = 1;
+            launch_sur_grad(d_data, (int)M, sim->sur_P, sim->sur_Wb, key, (int)tiles, sim->sur_grad, sim->sur_loss, st);
+        }
+        sim->sur_t += 1;
+        const double c1 = 1.0 / (1.0 - std::pow((double)o->beta1, (double)sim->sur_t));
+        const double c2 = 1.0 / (1.0 - std::pow((double)o->beta2, (double)sim->sur_t));
+        launch_sur_adam(sim->sur_P, sim->sur_m, sim->sur_v, sim->sur_grad, (int)tiles, o->lr, o->beta1, o->beta2,
+                        o->eps, (float)c1, (float)c2, sim->sur_Wb, st);
+        LAUNCHED();
+    }
+    std::vector<float> tl(tiles);
+    if (o->steps > 0) DEV(hipMemcpyAsync(tl.data(), sim->sur_loss, sizeof(float) * tiles, hipMemcpyDeviceToHost, st));
+    DEV(hipStreamSynchronize(st));
+    sim->sur_ready = true;
+    if (loss_out) {
+        double L = 0.0;
+        for (float x : tl) L += x;
+        *loss_out = o->steps > 0 ? (float)L : NAN;
+    }
+    return SF_OK;
+}
+
+sf_status sf_sur_gradient(sf_sim *sim, const float *d_data, int64_t M, float *h_grad, float *h_loss) {
+    CHECK_SIM(sim);
+    sf_status r;
+    if ((r = sur_check_data(d_data, M, 64ll * SUR_MAX_TILES)) != SF_OK) return r;
+    if (!h_grad || !h_loss) return fail(SF_E_INVALID_ARG, "NULL output");
+    if (!sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    const long long tiles = (M + 63) / 64;
+    if ((r = sur_grad_buf(sim, tiles)) != SF_OK) return r;
+    launch_sur_grad_seq(d_data, (int)M, sim->sur_P, sim->sur_Wb, sim->sur_grad, sim->sur_loss, sim->stream);
+    launch_sur_reduce(sim->sur_grad, (int)tiles, sim->sur_gsum, sim->stream);
+    LAUNCHED();
+    std::vector<float> tl(tiles);
+    DEV(hipMemcpyAsync(h_grad, sim->sur_gsum, sizeof(float) * SF_SUR_PARAMS, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipMemcpyAsync(tl.data(), sim->sur_loss, sizeof(float) * tiles, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    double L = 0.0;
+    for (float x : tl) L += x;
+    *h_loss = (float)L;
+    return SF_OK;
+}
+
+sf_status sf_sur_predict(sf_sim *sim, const float *d_data, int64_t M, float *d_pred) {
+    CHECK_SIM(sim);
+    sf_status r;
+    if ((r = sur_check_data(d_data, M, INT32_MAX)) != SF_OK) return r;
+    if (!d_pred) return fail(SF_E_INVALID_ARG, "d_pred is NULL");
+    if (!sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    launch_sur_eval(d_data, (int)M, sim->sur_P, sim->sur_Wb, d_pred, sim->stream);
+    LAUNCHED();
+    return SF_OK;
+}
+
+sf_status sf_sur_evaluate(sf_sim *sim, const float *d_data, int64_t M, float *h_mean, float *h_p95) {
+    CHECK_SIM(sim);
+    sf_status r;
+    if ((r = sur_check_data(d_data, M, 1ll << 28)) != SF_OK) return r;
+    if (!h_mean || !h_p95) return fail(SF_E_INVALID_ARG, "NULL output");
+    if (!sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    if ((r = sur_pred_buf(sim, M)) != SF_OK) return r;
+    launch_sur_eval(d_data, (int)M, sim->sur_P, sim->sur_Wb, sim->sur_pred, sim->stream);
+    launch_sur_errors(d_data, (int)M, sim->sur_pred, sim->sur_err, sim->stream);
+    LAUNCHED();
+    std::vector<float> e(M);
+    DEV(hipMemcpyAsync(e.data(), sim->sur_err, sizeof(float) * M, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    double sum = 0.0;
+    for (float x : e) sum += x;
+    *h_mean = (float)(sum / (double)M);
+    const size_t k = std::min<size_t>((size_t)M - 1, (size_t)std::ceil(0.95 * (double)M) - 1);
+    std::nth_element(e.begin(), e.begin() + k, e.end());
+    *h_p95 = e[k];
+    return SF_OK;
+}
+
+sf_status sf_sur_set(sf_sim *sim, const float *h_params, const float *h_lo, const float *h_hi) {
+    CHECK_SIM(sim);
+    if (!h_params || !h_lo || !h_hi) return fail(SF_E_INVALID_ARG, "NULL input");
+    for (int k = 0; k < SF_SUR_PARAMS; ++k)
+        if (!std::isfinite(h_params[k])) return fail(SF_E_INVALID_ARG, "surrogate parameters must be finite");
+    for (int k = 0; k < SF_SUR_IN; ++k)
+        if (!(h_lo[k] <= h_hi[k])) return fail(SF_E_INVALID_ARG, "envelope needs lo <= hi");
+    sf_status r;
+    if ((r = sur_alloc(sim)) != SF_OK) return r;
+    DEV(hipMemcpyAsync(sim->sur_P, h_params, sizeof(float) * SF_SUR_PARAMS, hipMemcpyHostToDevice, sim->stream));
+    DEV(hipMemsetAsync(sim->sur_m, 0, sizeof(float) * SF_SUR_PARAMS, sim->stream));
+    DEV(hipMemsetAsync(sim->sur_v, 0, sizeof(float) * SF_SUR_PARAMS, sim->stream));
+    launch_sur_pack(sim->sur_P, sim->sur_Wb, sim->stream);
+    LAUNCHED();
+    DEV(hipStreamSynchronize(sim->stream));
+    std::memcpy(sim->sur_lo, h_lo, sizeof(sim->sur_lo));
+    std::memcpy(sim->sur_hi, h_hi, sizeof(sim->sur_hi));
+    sim->sur_t = 0;
+    sim->sur_ready = true;
+    return SF_OK;
+}
+
+sf_status sf_sur_get(sf_sim *sim, float *h_params, float *h_lo, float *h_hi) {
+    CHECK_SIM(sim);
+    if (!sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    if (h_params) {
+        DEV(hipMemcpyAsync(h_params, sim->sur_P, sizeof(float) * SF_SUR_PARAMS, hipMemcpyDeviceToHost, sim->stream));
+        DEV(hipStreamSynchronize(sim->stream));
+    }
+    if (h_lo) std::memcpy(h_lo, sim->sur_lo, sizeof(sim->sur_lo));
+    if (h_hi) std::memcpy(h_hi, sim->sur_hi, sizeof(sim->sur_hi));
+    return SF_OK;
+}
+
+sf_status sf_sur_enable(sf_sim *sim, int32_t on) {
+    CHECK_SIM(sim);
+    if (on && !sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    sim->sur_on = on != 0;
+    return SF_OK;
+}
+
+sf_status sf_sur_counts(sf_sim *sim, uint64_t *out, int32_t reset) {
+    CHECK_SIM(sim);
+    if (!out) return fail(SF_E_INVALID_ARG, "out is NULL");
+    out[0] = out[1] = 0;
+    if (!sim->sur_counts) return SF_OK;
+    unsigned long long c[2];
+    DEV(hipMemcpyAsync(c, sim->sur_counts, sizeof(c), hipMemcpyDeviceToHost, sim->stream));
+    if (reset) DEV(hipMemsetAsync(sim->sur_counts, 0, sizeof(c), sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    out[0] = c[0];
+    out[1] = c[1];
     return SF_OK;
 }
 

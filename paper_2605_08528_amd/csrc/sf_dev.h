@@ -26,6 +26,40 @@
 #define SF_KEY_CAP (1ll << 43)   // saturation of kNN squared distances
 #define SF_CAND_CAP 1024          // road candidates kept per agent
 
+// learned tire surrogate: 16 -> 128 -> 128 -> 128 -> 3, flat fp32 parameters
+// W1[128][16] b1 W2[128][128] b2 W3[128][128] b3 W4[3][128] b4
+#define SF_SUR_IN 16
+#define SF_SUR_HID 128
+#define SF_SUR_SAMPLE 20  // 16 inputs, 3 targets, valid flag
+#define SF_SUR_W1 0
+#define SF_SUR_B1 2048
+#define SF_SUR_W2 2176
+#define SF_SUR_B2 18560
+#define SF_SUR_W3 18688
+#define SF_SUR_B3 35072
+#define SF_SUR_W4 35200
+#define SF_SUR_B4 35584
+#define SF_SUR_PARAMS 35587
+// bf16 weight copies: row-major W1 W2 W3 W4, then transposed W2 and W3
+#define SF_SURB_W1 0
+#define SF_SURB_W2 2048
+#define SF_SURB_W3 18432
+#define SF_SURB_W4 34816
+#define SF_SURB_W2T 35200
+#define SF_SURB_W3T 51584
+#define SF_SURB_TOTAL 67968
+
+// learned surrogate inside the step (inference + fallback) and the log of
+// training samples the plain step writes
+struct DevSur {
+    const uint16_t *Wb;            // bf16 weight copies (SF_SURB_* layout)
+    const float *P;                // fp32 parameters (biases read from here)
+    float lo[SF_SUR_IN], hi[SF_SUR_IN];  // input envelope of the training set
+    unsigned long long *counts;    // [2] wheels on the surrogate / on the fallback
+    float *log;                    // [log_cap][SF_SUR_SAMPLE] ring, or null
+    long long log_cap, log_base;
+};
+
 struct GridHdr {
     float x0, y0, cell, inv_cell;
     int nx, ny, cbase, pad;
@@ -102,6 +136,64 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
     return z ^ (z >> 31);
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+    return z;
+}
+
+template <int RT, int CT>
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[RT][CT]) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// acc (RT x CT tiles of 16 x 16) += A B^T over KS k-steps of 32 on the
+// matrix cores (v_mfma_f32_16x16x32_bf16): fa(row, k0) / fb(col, k0) return
+// the 8 consecutive-k bf16 values lane (row | col) = lane % 16,
+// k0 = 32 ks + 8 (lane / 16) needs; the lane then holds
+// acc[r][c][j] = C[16 r + 4 (lane / 16) + j][16 c + lane % 16]
+template <int RT, int CT, int KS, class FA, class FB>
+__device__ __forceinline__ void mfma_nt(f32x4 (&acc)[RT][CT], FA fa, FB fb) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k0 = ks * 32 + kq * 8;
+        bf16x8 b[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[c] = fb(c * 16 + r16, k0);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const bf16x8 a = fa(r * 16 + r16, k0);
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[c], acc[r][c], 0, 0, 0);
+        }
+    }
+}
+
+// make one lane's LDS writes visible to the other lanes of its wave
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// round-to-nearest-even float -> bf16 bits, and back
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
 __device__ __forceinline__ long long sat_key(long long d2) {
     return d2 < SF_KEY_CAP ? d2 : SF_KEY_CAP - 1;
 }
@@ -175,14 +267,28 @@ void launch_scan(const int *in, int *out, int n, int *tmp, hipStream_t st);  // 
 void launch_world_of(const int *aoff, int W, int *world_of, hipStream_t st);
 void launch_reset(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const uint8_t *mask,
                   int bump_episode, hipStream_t s);
-void launch_step(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act,
-                 float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
+void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
+                 const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
                  int *rec_cnt, int rec_cap, const int *order, int block, hipStream_t s);
+void launch_sur_reduce(const float *grad, int tiles, float *out, hipStream_t s);
+void launch_sur_grad_seq(const float *data, int M, const float *P, const uint16_t *Wb, float *grad, float *loss,
+                         hipStream_t s);
 void launch_obs(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
                 int *dbg_idx, int waves, hipStream_t s);
 void launch_to_bf16(const float *src, uint16_t *dst, int n, hipStream_t s);
 void launch_policy(const float *obs, int N, const uint16_t *W1, const float *b1, const uint16_t *W2,
                    const float *b2, const uint16_t *W3, const float *b3, float steer_max, float *act,
                    int tm, hipStream_t s);
+void launch_sur_collect(const float *log, int n, int *flag, int *pos, int *scan_tmp, float *out, int max_out,
+                        hipStream_t s);
+void launch_sur_envelope(const float *x, int M, float *part, float *lo, float *hi, hipStream_t s);
+void launch_sur_init(float *P, unsigned long long seed, hipStream_t s);
+void launch_sur_pack(const float *P, uint16_t *Wb, hipStream_t s);
+void launch_sur_grad(const float *data, int M, const float *P, const uint16_t *Wb, unsigned long long seed,
+                     int tiles, float *grad, float *loss, hipStream_t s);
+void launch_sur_eval(const float *data, int M, const float *P, const uint16_t *Wb, float *pred, hipStream_t s);
+void launch_sur_adam(float *P, float *m, float *v, const float *grad, int tiles, float lr, float b1, float b2,
+                     float eps, float c1, float c2, uint16_t *Wb, hipStream_t s);
+void launch_sur_errors(const float *data, int M, const float *pred, float *err, hipStream_t s);
 void launch_debug_raycast(const DevParams &P, const DevWorld &Wd, const float *st, float *out,
                           hipStream_t s);

@@ -67,6 +67,20 @@ class Options(C.Structure):
     ]
 
 
+SUR_INPUTS, SUR_PARAMS, SUR_SAMPLE = 16, 35587, 20
+# piecewise-constant Adam learning rates (lr, steps) used to fit the tire
+# network; 40k steps of 8192 samples take about 3 s on one MI355X
+SUR_SCHEDULE = ((2e-3, 15000), (1e-3, 10000), (3e-4, 10000), (1e-4, 5000))
+
+
+class SurTrainOpts(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int32), ("batch", C.c_int32),
+        ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+        ("seed", C.c_uint64), ("init_seed", C.c_uint64), ("set_envelope", C.c_int32),
+    ]
+
+
 class SFError(RuntimeError):
     pass
 
@@ -106,6 +120,16 @@ def lib():
         L.sf_graph_launch.argtypes = [vp]
         L.sf_profile.argtypes = [vp, i32]
         L.sf_profile_read.argtypes = [vp, vp, vp]
+        L.sf_sur_log.argtypes = [vp, C.c_int64]
+        L.sf_sur_collect.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.sf_sur_train.argtypes = [vp, vp, C.c_int64, C.POINTER(SurTrainOpts), C.POINTER(C.c_float)]
+        L.sf_sur_gradient.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(C.c_float)]
+        L.sf_sur_predict.argtypes = [vp, vp, C.c_int64, vp]
+        L.sf_sur_evaluate.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.sf_sur_set.argtypes = [vp, vp, vp, vp]
+        L.sf_sur_get.argtypes = [vp, vp, vp, vp]
+        L.sf_sur_enable.argtypes = [vp, i32]
+        L.sf_sur_counts.argtypes = [vp, vp, i32]
         L.sf_status_str.argtypes = [st]
         L.sf_status_str.restype = C.c_char_p
         L.sf_last_error.restype = C.c_char_p
@@ -113,7 +137,9 @@ def lib():
                      "sf_step", "sf_observe", "sf_output_ptrs", "sf_reset", "sf_get_state",
                      "sf_set_state", "sf_get_contacts", "sf_debug_raycast", "sf_debug_obs_indices",
                      "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
-                     "sf_graph_launch", "sf_profile", "sf_profile_read"):
+                     "sf_graph_launch", "sf_profile", "sf_profile_read", "sf_sur_log", "sf_sur_collect",
+                     "sf_sur_train", "sf_sur_gradient", "sf_sur_predict", "sf_sur_evaluate", "sf_sur_set",
+                     "sf_sur_get", "sf_sur_enable", "sf_sur_counts"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -327,3 +353,73 @@ class Sim:
         n = np.zeros(4, np.int32)
         check(lib().sf_profile_read(self.h, _ptr(ms), _ptr(n)), "sf_profile_read")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(("policy", "step", "obs", "reset"))}
+
+    # learned tire surrogate --------------------------------------------
+    def sur_log(self, capacity: int) -> None:
+        check(lib().sf_sur_log(self.h, int(capacity)), "sf_sur_log")
+
+    def sur_collect(self, max_out: int):
+        """Valid logged samples as a [n, 20] device tensor (n <= max_out)."""
+        t = self.torch
+        out = t.empty((max(int(max_out), 1), SUR_SAMPLE), dtype=t.float32,
+                      device=t.device("cuda", t.cuda.current_device()))
+        n = C.c_int64()
+        check(lib().sf_sur_collect(self.h, _tptr(out), int(max_out), C.byref(n)), "sf_sur_collect")
+        return out[:min(n.value, int(max_out))], n.value
+
+    def sur_train(self, data, steps: int, batch: int = 4096, lr: float = 1e-3, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-8, seed: int = 1, init_seed: int = 0,
+                  set_envelope: bool = False) -> float:
+        o = SurTrainOpts(int(steps), int(batch), lr, beta1, beta2, eps, int(seed), int(init_seed),
+                         int(bool(set_envelope)))
+        loss = C.c_float()
+        check(lib().sf_sur_train(self.h, _tptr(data), data.shape[0], C.byref(o), C.byref(loss)),
+              "sf_sur_train")
+        return loss.value
+
+    def sur_fit(self, data, schedule=SUR_SCHEDULE, batch: int = 8192, init_seed: int = 1) -> float:
+        """Fresh network and envelope from ``data``, then the Adam phases of
+        ``schedule``; returns the last minibatch loss."""
+        self.sur_train(data, steps=0, init_seed=init_seed, set_envelope=True)
+        loss = float("nan")
+        for k, (lr, n) in enumerate(schedule):
+            loss = self.sur_train(data, steps=n, batch=batch, lr=lr, seed=k + 1)
+        return loss
+
+    def sur_gradient(self, data):
+        g = np.zeros(SUR_PARAMS, np.float32)
+        loss = C.c_float()
+        check(lib().sf_sur_gradient(self.h, _tptr(data), data.shape[0], _ptr(g), C.byref(loss)),
+              "sf_sur_gradient")
+        return loss.value, g
+
+    def sur_predict(self, data):
+        t = self.torch
+        out = t.empty((data.shape[0], 3), dtype=t.float32, device=data.device)
+        check(lib().sf_sur_predict(self.h, _tptr(data), data.shape[0], _tptr(out)), "sf_sur_predict")
+        return out
+
+    def sur_evaluate(self, data):
+        m, p = C.c_float(), C.c_float()
+        check(lib().sf_sur_evaluate(self.h, _tptr(data), data.shape[0], C.byref(m), C.byref(p)),
+              "sf_sur_evaluate")
+        return m.value, p.value
+
+    def sur_set(self, params, lo, hi) -> None:
+        self._sur_keep = [np.ascontiguousarray(a, np.float32) for a in (params, lo, hi)]
+        check(lib().sf_sur_set(self.h, *[_ptr(a) for a in self._sur_keep]), "sf_sur_set")
+
+    def sur_get(self):
+        p = np.zeros(SUR_PARAMS, np.float32)
+        lo = np.zeros(SUR_INPUTS, np.float32)
+        hi = np.zeros(SUR_INPUTS, np.float32)
+        check(lib().sf_sur_get(self.h, _ptr(p), _ptr(lo), _ptr(hi)), "sf_sur_get")
+        return p, lo, hi
+
+    def sur_enable(self, on: bool) -> None:
+        check(lib().sf_sur_enable(self.h, int(bool(on))), "sf_sur_enable")
+
+    def sur_counts(self, reset: bool = False):
+        out = np.zeros(2, np.uint64)
+        check(lib().sf_sur_counts(self.h, _ptr(out), int(bool(reset))), "sf_sur_counts")
+        return int(out[0]), int(out[1])

@@ -114,3 +114,41 @@ def test_calls_on_null_handle(L):
     assert L.sf_observe(None, None, None, None, None) == 1
     assert L.sf_destroy(None) == 1
     assert L.sf_state_bytes(None) == 0
+    for name in ("sf_sur_log", "sf_sur_enable"):
+        assert getattr(L, name)(None, 0) == 1
+    assert L.sf_sur_counts(None, None, 0) == 1
+    assert L.sf_sur_set(None, None, None, None) == 1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the C compiler's sizes and
+    field offsets (a C program built from include/sf.h prints them)."""
+    import shutil
+    import subprocess
+    from paper_2605_08528_amd import sf
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"sf_vehicle_params": sf.VehicleParams, "sf_world_desc": sf.WorldDesc,
+               "sf_options": sf.Options, "sf_sur_train_opts": sf.SurTrainOpts}
+    header_fields = {
+        "sf_vehicle_params": ["mass", "inertia", "wheel_radius", "mount", "jacobi_iters", "slop"],
+        "sf_world_desc": ["num_worlds", "agent_offsets", "num_surfaces", "spawn", "seed"],
+        "sf_options": ["stream", "alloc", "max_episode_steps", "flags", "tri_cell", "reserved"],
+        "sf_sur_train_opts": ["steps", "batch", "lr", "eps", "seed", "init_seed", "set_envelope"],
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sf.h"', "int main(void) {"]
+    for s, fields in header_fields.items():
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f in fields:
+            lines.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for s, cls in structs.items():
+        assert int(got[s]) == C.sizeof(cls), s
+        for f in header_fields[s]:
+            assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
