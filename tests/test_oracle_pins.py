@@ -671,3 +671,147 @@ def test_policy_head_ranges(oracle_mod):
     assert np.all(np.abs(a[:, 0]) <= 1) and np.all(np.abs(a[:, 1]) <= 0.5)
     y = O.mlp_forward(Ws, bs, obs, act="elu")
     assert np.allclose(a[:, 0], np.tanh(y[:, 0])) and np.allclose(a[:, 1], 0.5 * np.tanh(y[:, 1]))
+
+
+# ------------------------------------------------- learned tire surrogate
+SUR_PARAMS = 16 * 128 + 128 + 2 * (128 * 128 + 128) + 3 * 128 + 3
+WIDE = (np.full(16, -1e30, np.float32), np.full(16, 1e30, np.float32))
+
+
+def _settled(O, yaw=0.3, mu=0.9, **kw):
+    """A vehicle settled at rest for 10 s (every spring at m g / 4)."""
+    o, p = mk(O, [(0, 0, yaw, 300, 0)], mu=mu, invincible=True, **kw)
+    for _ in range(1200):
+        o.step(zeros(1), H, 1)
+    return o, p
+
+
+def _drive(o, yaw, vx, vy, wz, spin, steer=0.0):
+    f, k = o.get_state()
+    c, s = math.cos(yaw), math.sin(yaw)
+    f[VX, 0], f[VY, 0], f[VZ, 0] = c * vx - s * vy, s * vx + c * vy, 0.0
+    f[WX, 0] = f[WY, 0] = 0.0
+    f[WZ, 0] = wz
+    f[OM0:OM0 + 4, 0] = spin
+    f[TH, 0], f[THD, 0] = steer, 0.0
+    o.set_state(f, k)
+    return f
+
+
+def test_surrogate_features_closed_form(oracle_mod):
+    """Level body driving at (v_x, v_y) with yaw rate w_z, steered front
+    wheels, half throttle: each wheel's inputs are the rigid-body contact
+    kinematics in the wheel frame; the stored targets are the plain tire
+    model's outputs for exactly those kinematics over mu F_z."""
+    O = oracle_mod
+    yaw, vx, vy, wz, th = 0.3, 10.0, 0.5, 0.4, 0.1
+    o, p = _settled(O, yaw)
+    r = f32(p["wheel_radius"])
+    _drive(o, yaw, vx, vy, wz, vx / r, steer=th)
+    o.record_samples(True)
+    o.step(np.array([[0.5, th]], np.float32), H, 1)
+    rec = o.samples()[0]
+    mg4 = f32(p["mass"]) * f32(p["gravity"]) / 4
+    sag = mg4 / f32(p["susp_k"])
+    for wh in range(4):
+        xm, ym = p["mount"][wh][0], p["mount"][wh][1]
+        d = th if wh < 2 else 0.0
+        # contact-point velocity in the body frame, then in the wheel frame
+        bx, by = vx - wz * ym, vy + wz * xm
+        wx_, wy_ = math.cos(d) * bx + math.sin(d) * by, -math.sin(d) * bx + math.cos(d) * by
+        D = max(abs(wx_), p["v_eps"])
+        td = 0.5 * p["tau_drive"] if wh < 2 else 0.0
+        want = [(r * (vx / r) - wx_) / D, math.atan(wy_ / D), mg4 / 4000.0, 0.9, vx / 30.0, 0.0,
+                wx_ / 30.0, wy_ / 5.0, d, sag / 0.2, 0.0, td / p["tau_drive"], 0.0, 0.0, 0.0, wz / 2.0]
+        assert rec[wh, 19] == 1.0
+        assert np.allclose(rec[wh, :16], want, rtol=2e-6, atol=2e-6), (wh, rec[wh, :16], want)
+        Fx, Fy, Mz, _ = O.tire(p, H, mg4, 0.9, wx_, wy_, vx / r, td, 0.0)
+        lim = 0.9 * mg4
+        assert np.allclose(rec[wh, 16:19], [Fx / lim, Fy / lim, Mz / (p["trail"] * lim)], atol=2e-6)
+    assert rec[0, 0] != rec[1, 0] and rec[0, 7] != rec[2, 7]   # wheels are told apart
+
+
+def test_surrogate_features_attitude(oracle_mod):
+    """Rolled and pitched body: the roll, pitch and camber inputs are the
+    body's Euler angles and asin(axle . n) of the tilted axle."""
+    O = oracle_mod
+    o, p = _settled(O, 0.0)
+    roll, pitch = 0.03, -0.02
+    f, k = o.get_state()
+    cr, sr, cp, sp = math.cos(roll / 2), math.sin(roll / 2), math.cos(pitch / 2), math.sin(pitch / 2)
+    f[QW:QZ + 1, 0] = [cr * cp, sr * cp, cr * sp, -sr * sp]     # R = Ry(pitch) Rx(roll)
+    o.set_state(f, k)
+    _drive(o, 0.0, 8.0, 0.0, 0.0, 8.0 / f32(p["wheel_radius"]))
+    o.record_samples(True)
+    o.step(zeros(1), H, 1)
+    rec = o.samples()[0]
+    loaded = rec[:, 19] == 1.0
+    assert loaded.sum() >= 2
+    for wh in np.nonzero(loaded)[0]:
+        assert abs(rec[wh, 13] - roll) < 1e-6 and abs(rec[wh, 14] - pitch) < 1e-6
+        assert abs(rec[wh, 5] - math.asin(math.cos(pitch) * math.sin(roll))) < 1e-6
+
+
+def _net(b4):
+    P = np.zeros(SUR_PARAMS, np.float32)
+    P[-3:] = b4
+    return P
+
+
+def test_surrogate_constant_network_closed_form(oracle_mod):
+    """A network that always answers (c, 0, 0): every wheel of a straight,
+    free-rolling vehicle pushes c mu F_z forward, so after one substep the
+    speed grows by h c mu g and each wheel's spin drops by h r c mu F_z / I_w
+    (implicit spin update with the network's force, no drive or brake)."""
+    O = oracle_mod
+    yaw, v, c, mu = 0.3, 10.0, 0.2, 0.6
+    o, p = _settled(O, yaw, mu=mu)
+    r = f32(p["wheel_radius"])
+    _drive(o, yaw, v, 0.0, 0.0, v / r)
+    o.set_surrogate(_net([c, 0.0, 0.0]), *WIDE, True)
+    o.step(zeros(1), H, 1)
+    f, _ = o.get_state()
+    g, m = f32(p["gravity"]), f32(p["mass"])
+    Iw = 0.5 * f32(p["wheel_mass"]) * r * r
+    speed = math.hypot(f[VX, 0], f[VY, 0])
+    assert abs(speed - (v + H * c * mu * g)) < 1e-9
+    assert abs(math.atan2(f[VY, 0], f[VX, 0]) - yaw) < 1e-9
+    for wh in range(4):
+        # F_z is m g / 4 to the settling accuracy (~1e-7 relative)
+        assert abs(f[OM0 + wh, 0] - (v / r - H * r * c * mu * m * g / 4 / Iw)) < 1e-6
+    assert o.surrogate_counts() == (4, 0)
+
+
+def _one_step(O, net, env, spin_ratio=1.0, enable=True):
+    o, p = _settled(O, 0.3)
+    r = f32(p["wheel_radius"])
+    _drive(o, 0.3, 10.0, 0.0, 0.0, spin_ratio * 10.0 / r)
+    if net is not None:
+        o.set_surrogate(net, *env, enable)
+    o.step(zeros(1), H, 1)
+    return o.get_state()[0], (o.surrogate_counts() if net is not None else None)
+
+
+def test_surrogate_fallback_rules(oracle_mod):
+    """A prediction outside 1.02 mu F_z, an input outside the envelope, or a
+    longitudinal force against a slip above 2 % hands the wheel back to the
+    plain model: the step is then exactly the plain step."""
+    O = oracle_mod
+    plain, _ = _one_step(O, None, None)
+    f, cnt = _one_step(O, _net([1.5, 0.0, 0.0]), WIDE)
+    assert cnt == (0, 4) and np.array_equal(f, plain)
+    f, cnt = _one_step(O, _net([0.1, 1.0, 0.0]), WIDE)            # |F| = 1.005 mu F_z: inside the slack
+    assert cnt == (4, 0) and not np.array_equal(f, plain)
+    lo, hi = WIDE[0].copy(), WIDE[1].copy()
+    hi[4] = 0.2                                                    # r Omega / 30 = 0.333 is outside
+    f, cnt = _one_step(O, _net([0.1, 0.0, 0.0]), (lo, hi))
+    assert cnt == (0, 4) and np.array_equal(f, plain)
+    # slip ratio +5 %: a braking prediction is rejected, a driving one kept
+    plain5, _ = _one_step(O, None, None, spin_ratio=1.05)
+    f, cnt = _one_step(O, _net([-0.1, 0.0, 0.0]), WIDE, spin_ratio=1.05)
+    assert cnt == (0, 4) and np.array_equal(f, plain5)
+    f, cnt = _one_step(O, _net([0.1, 0.0, 0.0]), WIDE, spin_ratio=1.05)
+    assert cnt == (4, 0)
+    # disabled: counts stay at zero and the step is the plain one
+    f, cnt = _one_step(O, _net([0.1, 0.0, 0.0]), WIDE, enable=False)
+    assert cnt == (0, 0) and np.array_equal(f, plain)
