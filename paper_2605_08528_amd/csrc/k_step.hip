@@ -166,58 +166,117 @@ __device__ __forceinline__ f3 inv_inertia(const DevParams &P, const float R[9], 
 }
 
 // ------------------------------------------------------ surrogate inference
-#define SUR_LD 136  // row stride (bf16) of a wave's activation tile
+#define SUR_LD 136    // row stride (bf16) of a wave's activation tile
+#define SUR_ROWS 32   // rows per pass: half a wave's wheels
+// LDS copy of the network: bf16 weights in padded rows (conflict-free
+// fragment reads; W1's inputs 16..31 are zero so the first layer is one
+// 32-deep product), then fp32 biases b1 b2 b3 b4
+#define SURW_LD1 40
+#define SURW_W2 (128 * SURW_LD1)
+#define SURW_W3 (SURW_W2 + 128 * SUR_LD)
+#define SURW_W4 (SURW_W3 + 128 * SUR_LD)
+#define SURW_BF16 (SURW_W4 + 3 * SUR_LD)
+#define SURW_NB (3 * 128 + 4)
 
-__device__ __forceinline__ void sur_store(const f32x4 (&acc)[4][8], uint16_t *buf, const float *bias) {
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// One hidden layer for the tile's 32 rows, written back over its input.
+// The product is taken transposed, out^T = W in^T (weights as the row
+// operand), so that each lane ends up with four consecutive outputs of one
+// row: bias, ReLU, one packed bf16 conversion and one 8-byte store.
+template <int KS>
+__device__ __forceinline__ void sur_layer32(uint16_t *buf, const uint16_t *W, int ldw, const float *bias) {
     const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+    f32x4 acc[8][2];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int col = c * 16 + r16;
-        const float b = bias[col];
+    for (int n = 0; n < 8; ++n) acc[n][0] = acc[n][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k0 = ks * 32 + kq * 8;
+        const bf16x8 x0 = ld8(buf + r16 * SUR_LD + k0), x1 = ld8(buf + (16 + r16) * SUR_LD + k0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) buf[(r * 16 + kq * 4 + j) * SUR_LD + col] = f2bf(fmaxf(acc[r][c][j] + b, 0.f));
+        for (int n = 0; n < 8; ++n) {
+            const bf16x8 w = ld8(W + (n * 16 + r16) * ldw + k0);
+            acc[n][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x0, acc[n][0], 0, 0, 0);
+            acc[n][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x1, acc[n][1], 0, 0, 0);
+        }
     }
+    wave_sync();
+    // lane holds out[row 16 t + lane % 16][16 n + 4 (lane / 16) + j]
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const float4 bb = *reinterpret_cast<const float4 *>(bias + n * 16 + kq * 4);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            bf16x4 o;
+            o[0] = (__bf16)fmaxf(acc[n][t][0] + bb.x, 0.f);
+            o[1] = (__bf16)fmaxf(acc[n][t][1] + bb.y, 0.f);
+            o[2] = (__bf16)fmaxf(acc[n][t][2] + bb.z, 0.f);
+            o[3] = (__bf16)fmaxf(acc[n][t][3] + bb.w, 0.f);
+            *reinterpret_cast<bf16x4 *>(buf + (t * 16 + r16) * SUR_LD + n * 16 + kq * 4) = o;
+        }
+    }
+    wave_sync();
 }
 
-// The learned tire model on the 64 wheels of one wave (row = lane): bf16
-// inputs and weights on the matrix cores, fp32 accumulation, each layer
-// computed into registers and written back over its input tile.  Lanes
-// outside the model's domain run with zero inputs and ignore the result.
-__device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool inside, const DevSur &Su,
-                             float (&y)[3]) {
-    const int lane = threadIdx.x & 63;
+// The learned tire model on the 64 wheels of one wave, in two passes of 32
+// rows (a pass is skipped when none of its wheels is inside the envelope):
+// bf16 inputs and weights on the matrix cores, fp32 accumulation.  The
+// 3-wide output layer is a product against W4 padded to 16 rows; its fp32
+// results go to the row's padding columns, where the row's lane reads them.
+// Lanes outside the domain run with zero inputs and ignore y.
+__device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool inside, const uint16_t *Wl,
+                             const float *bl, float (&y)[3]) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4, row = lane & 31;
+    const unsigned long long any = __ballot(inside);
+    y[0] = y[1] = y[2] = 0.f;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        if (!(half ? (any >> 32) : (any & 0xFFFFFFFFull))) continue;
+        if ((lane >> 5) == half) {
+            bf16x8 v0, v1;
 #pragma unroll
-    for (int q = 0; q < 32; ++q) buf[lane * SUR_LD + q] = (q < SF_SUR_IN && inside) ? f2bf(feat[q]) : (uint16_t)0;
-    wave_sync();
-    f32x4 acc[4][8];
-    zero_acc(acc);
-    mfma_nt<4, 8, 1>(acc, [&](int r, int k0) { return ld8(buf + r * SUR_LD + k0); },
-                     [&](int c, int k0) { return k0 < SF_SUR_IN ? ld8(Su.Wb + SF_SURB_W1 + c * SF_SUR_IN + k0) : zero8(); });
-    wave_sync();
-    sur_store(acc, buf, Su.P + SF_SUR_B1);
-    wave_sync();
-    zero_acc(acc);
-    mfma_nt<4, 8, 4>(acc, [&](int r, int k0) { return ld8(buf + r * SUR_LD + k0); },
-                     [&](int c, int k0) { return ld8(Su.Wb + SF_SURB_W2 + c * SF_SUR_HID + k0); });
-    wave_sync();
-    sur_store(acc, buf, Su.P + SF_SUR_B2);
-    wave_sync();
-    zero_acc(acc);
-    mfma_nt<4, 8, 4>(acc, [&](int r, int k0) { return ld8(buf + r * SUR_LD + k0); },
-                     [&](int c, int k0) { return ld8(Su.Wb + SF_SURB_W3 + c * SF_SUR_HID + k0); });
-    wave_sync();
-    sur_store(acc, buf, Su.P + SF_SUR_B3);
-    wave_sync();
+            for (int q = 0; q < 8; ++q) {
+                v0[q] = (__bf16)(inside ? feat[q] : 0.f);
+                v1[q] = (__bf16)(inside ? feat[8 + q] : 0.f);
+            }
+            bf16x8 *d = reinterpret_cast<bf16x8 *>(buf + row * SUR_LD);
+            d[0] = v0;
+            d[1] = v1;
+            d[2] = zero8();
+            d[3] = zero8();
+        }
+        wave_sync();
+        sur_layer32<1>(buf, Wl, SURW_LD1, bl);
+        sur_layer32<4>(buf, Wl + SURW_W2, SUR_LD, bl + 128);
+        sur_layer32<4>(buf, Wl + SURW_W3, SUR_LD, bl + 256);
+        f32x4 o0 = f32x4{0.f, 0.f, 0.f, 0.f}, o1 = o0;
 #pragma unroll
-    for (int o = 0; o < 3; ++o) {
-        float a = Su.P[SF_SUR_B4 + o];
-        for (int k = 0; k < SF_SUR_HID; ++k)
-            a += bf2f(buf[lane * SUR_LD + k]) * bf2f(Su.Wb[SF_SURB_W4 + o * SF_SUR_HID + k]);
-        y[o] = a;
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k0 = ks * 32 + kq * 8;
+            const bf16x8 w = ld8(Wl + SURW_W4 + (r16 < 3 ? r16 : 0) * SUR_LD + k0);
+            const bf16x8 wz = r16 < 3 ? w : zero8();
+            o0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(buf + r16 * SUR_LD + k0), wz, o0, 0, 0, 0);
+            o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(buf + (16 + r16) * SUR_LD + k0), wz, o1, 0, 0, 0);
+        }
+        wave_sync();
+        if (r16 < 3) {
+            const float b4 = bl[384 + r16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                reinterpret_cast<float *>(buf + (kq * 4 + j) * SUR_LD + 128)[r16] = o0[j] + b4;
+                reinterpret_cast<float *>(buf + (16 + kq * 4 + j) * SUR_LD + 128)[r16] = o1[j] + b4;
+            }
+        }
+        wave_sync();
+        if ((lane >> 5) == half) {
+            const float *yo = reinterpret_cast<const float *>(buf + row * SUR_LD + 128);
+            y[0] = yo[0];
+            y[1] = yo[1];
+            y[2] = yo[2];
+        }
+        wave_sync();
     }
-    wave_sync();
 }
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
@@ -270,7 +329,42 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ int s_scan[NWV];
     __shared__ int s_np;
     constexpr int NSW = NWV == 1 ? 1 : NWV - 1;  // waves that run wheels
-    __shared__ __attribute__((aligned(16))) uint16_t s_sur[SUR ? NSW * 64 * SUR_LD : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t s_sur[SUR ? NSW * SUR_ROWS * SUR_LD : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t s_surw[SUR ? SURW_BF16 : 8];
+    __shared__ __attribute__((aligned(16))) float s_surb[SUR ? SURW_NB : 4];
+
+    if (SUR) {
+        // the network's weights and biases, once per block for all substeps
+        for (int e = tid; e < 128 * 4 + 2 * 128 * 16 + 3 * 16; e += BLOCK) {
+            const uint16_t *src;
+            uint16_t *dst;
+            if (e < 512) {
+                // W1 rows: 16 inputs then 16 zeros
+                dst = s_surw + (e >> 2) * SURW_LD1 + (e & 3) * 8;
+                if ((e & 3) >= 2) {
+                    *reinterpret_cast<uint4 *>(dst) = make_uint4(0u, 0u, 0u, 0u);
+                    continue;
+                }
+                src = Su.Wb + SF_SURB_W1 + (e >> 2) * SF_SUR_IN + (e & 3) * 8;
+            } else if (e < 512 + 2048) {
+                const int q = e - 512;
+                src = Su.Wb + SF_SURB_W2 + (q >> 4) * SF_SUR_HID + (q & 15) * 8;
+                dst = s_surw + SURW_W2 + (q >> 4) * SUR_LD + (q & 15) * 8;
+            } else if (e < 512 + 4096) {
+                const int q = e - 512 - 2048;
+                src = Su.Wb + SF_SURB_W3 + (q >> 4) * SF_SUR_HID + (q & 15) * 8;
+                dst = s_surw + SURW_W3 + (q >> 4) * SUR_LD + (q & 15) * 8;
+            } else {
+                const int q = e - 512 - 4096;
+                src = Su.Wb + SF_SURB_W4 + (q >> 4) * SF_SUR_HID + (q & 15) * 8;
+                dst = s_surw + SURW_W4 + (q >> 4) * SUR_LD + (q & 15) * 8;
+            }
+            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+        }
+        for (int e = tid; e < SURW_NB; e += BLOCK)
+            s_surb[e] = e < 128 ? Su.P[SF_SUR_B1 + e] : e < 256 ? Su.P[SF_SUR_B2 + e - 128]
+                      : e < 384 ? Su.P[SF_SUR_B3 + e - 256] : e < 387 ? Su.P[SF_SUR_B4 + e - 384] : 0.f;
+    }
 
     // ---- load the world's agents; decode actions (Sec. "Action Space Details")
     for (int i = tid; i < A; i += BLOCK) {
@@ -478,7 +572,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     for (int q = 0; q < SF_SUR_IN; ++q) inside = inside && feat[q] >= Su.lo[q] && feat[q] <= Su.hi[q];
                     if (__ballot(inside)) {
                         float y[3];
-                        sur_mlp_wave(s_sur + wave * 64 * SUR_LD, feat, inside, Su, y);
+                        sur_mlp_wave(s_sur + wave * SUR_ROWS * SUR_LD, feat, inside, s_surw, s_surb, y);
                         if (inside) {
                             const float lim = mu * Fz;
                             Fxs = lim * y[0];
@@ -801,6 +895,8 @@ void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool 
                  const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
                  int *rec_cnt, int rec_cap, const int *order, int block, hipStream_t s) {
     if (Wd.W == 0) return;
+    // the network's LDS copy leaves room for at most three wheel waves
+    if (use_sur && block > 256) block = 256;
 #define SF_STEP_LAUNCH(B)                                                                                     \
     do {                                                                                                      \
         if (use_sur)                                                                                          \
@@ -813,8 +909,10 @@ void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool 
     if (block <= 64) SF_STEP_LAUNCH(64);
     else if (block <= 128) SF_STEP_LAUNCH(128);
     else if (block <= 192) SF_STEP_LAUNCH(192);
-    else if (block <= 256) SF_STEP_LAUNCH(256);
-    else SF_STEP_LAUNCH(320);
+    else if (block <= 256 || use_sur) SF_STEP_LAUNCH(256);
+    else
+        k_step<320, false><<<Wd.W, 320, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec, rec_cnt,
+                                                rec_cap, order);
 #undef SF_STEP_LAUNCH
 }
 
