@@ -49,6 +49,9 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 #define KPL (SF_CAND_CAP / 64)  // candidate keys per lane
+// points loaded per lane and batch: after a prune (64 kept) a full batch
+// still fits the candidate buffer
+#define BATCH ((SF_CAND_CAP - 64) / 64 < 8 ? (SF_CAND_CAP - 64) / 64 : 8)
 
 // number of buffered keys <= x among the first `slots` register slots
 __device__ __forceinline__ int count_le(const unsigned long long kv[KPL], unsigned long long x, int slots) {
@@ -96,7 +99,7 @@ __device__ unsigned long long kth_smallest(const unsigned long long kv[KPL], int
 }
 
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
+__global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
                                                    const float *__restrict__ st,
                                                    const int *__restrict__ ist,
                                                    float *__restrict__ obs, int *__restrict__ dbg) {
@@ -229,6 +232,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
         cx = max(0, min(cx, g.nx - 1));
         cy = max(0, min(cy, g.ny - 1));
         int nc = 0;  // buffered candidates (uniform)
+        // once 64 candidates are known: the largest of the 64 best so far.
+        // A point with a larger key can no longer be selected, and a cell
+        // farther than that distance (plus a margin for the quantisation of
+        // positions) need not be read at all.
+        unsigned long long kthr = ~0ull;
+        float rcull = INFINITY;
         // rings closer than the distance to the nearest non-empty cell hold
         // no points: start there
         int rr = Wd.pt_occ[g.cbase + cy * g.nx + cx];
@@ -254,9 +263,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
                     xa = max(xa, 0);
                     xb = min(xb, g.nx - 1);
                     if (y >= 0 && y < g.ny && xa <= xb) {
-                        const int c0 = g.cbase + y * g.nx;
-                        s = Wd.pt_cell_start[c0 + xa];
-                        e = Wd.pt_cell_start[c0 + xb + 1];
+                        // distance from the agent to the segment's rectangle
+                        const float rx0 = g.x0 + (float)xa * g.cell, rx1 = g.x0 + (float)(xb + 1) * g.cell;
+                        const float ry0 = g.y0 + (float)y * g.cell, ry1 = ry0 + g.cell;
+                        const float ddx = fmaxf(fmaxf(rx0 - px, px - rx1), 0.f);
+                        const float ddy = fmaxf(fmaxf(ry0 - py, py - ry1), 0.f);
+                        if (ddx * ddx + ddy * ddy <= rcull * rcull) {
+                            const int c0 = g.cbase + y * g.nx;
+                            s = Wd.pt_cell_start[c0 + xa];
+                            e = Wd.pt_cell_start[c0 + xb + 1];
+                        }
                     }
                 }
                 const int len = e - s;
@@ -266,13 +282,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
                     if (lane >= o) incl += y2;
                 }
                 const int total = __shfl(incl, 63, 64);
+                if (total == 0) continue;
                 s_segs[wv][lane] = s;
                 s_segp[wv][lane] = incl - len;
                 wave_sync();
-                // batches of up to 8 points per lane: all loads of a batch are
-                // issued before any key is appended
-                for (int f0 = 0; f0 < total; f0 += 512) {
-                    const int nslot = min(8, (total - f0 + 63) >> 6);
+                // batches of up to BATCH points per lane: all loads of a batch
+                // are issued before any key is appended
+                for (int f0 = 0; f0 < total; f0 += 64 * BATCH) {
+                    const int nslot = min(BATCH, (total - f0 + 63) >> 6);
                     if (nc + 64 * nslot > SF_CAND_CAP) {
                         // keep only keys that can still be among the 64 best
                         wave_sync();
@@ -282,12 +299,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
                             int slot = lane + 64 * t;
                             kv[t] = slot < nc ? cand[slot] : ~0ull;
                         }
-                        const unsigned long long k64 = kth_smallest(kv, 64, (nc + 63) >> 6);
+                        kthr = kth_smallest(kv, 64, (nc + 63) >> 6);
                         wave_sync();
                         int keep = 0;
 #pragma unroll
                         for (int t = 0; t < KPL; ++t) {
-                            const bool f = kv[t] <= k64;
+                            const bool f = kv[t] <= kthr;
                             const unsigned long long bal = __ballot(f);
                             if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
                             keep += __popcll(bal);
@@ -295,9 +312,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
                         nc = keep;
                         wave_sync();
                     }
-                    int4 pq[8];
+                    int4 pq[BATCH];
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) {
+                    for (int t = 0; t < BATCH; ++t) {
                         const int f = f0 + 64 * t + lane;
                         pq[t] = make_int4(0, 0, 0, -1);
                         if (t < nslot && f < total) {
@@ -312,20 +329,49 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
                         }
                     }
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) {
+                    for (int t = 0; t < BATCH; ++t) {
                         if (t >= nslot) break;
-                        const bool has = pq[t].w == 0;
-                        unsigned long long key = 0;
-                        if (has) {
+                        unsigned long long key = ~0ull;
+                        if (pq[t].w == 0) {
                             const long long dx = (long long)pq[t].x - QX, dy = (long long)pq[t].y - QY;
                             key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 20) | (unsigned)pq[t].z;
                         }
+                        const bool has = key < kthr;
                         const unsigned long long bal = __ballot(has);
                         if (has) cand[nc + __popcll(bal & lane_lt())] = key;
                         nc += __popcll(bal);
                     }
                 }
                 wave_sync();
+            }
+            // with 64 or more candidates: keep the 64 best, which sets the
+            // selection threshold and the cell-culling radius
+            if (nc >= 64) {
+                unsigned long long kv[KPL];
+#pragma unroll
+                for (int t = 0; t < KPL; ++t) {
+                    int slot = lane + 64 * t;
+                    kv[t] = slot < nc ? cand[slot] : ~0ull;
+                }
+                if (nc == 64) {
+                    kthr = wave_max_u64(kv[0]);
+                } else {
+                    kthr = kth_smallest(kv, 64, (nc + 63) >> 6);
+                    wave_sync();
+                    int keep = 0;
+#pragma unroll
+                    for (int t = 0; t < KPL; ++t) {
+                        const bool f = kv[t] <= kthr;
+                        const unsigned long long bal = __ballot(f);
+                        if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
+                        keep += __popcll(bal);
+                    }
+                    nc = keep;
+                    wave_sync();
+                }
+                // squared distance of the 64th point, back in metres; the
+                // margin covers the quantisation of both positions
+                rcull = sqrtf((float)(kthr >> 20) * (1.f / 1048576.f)) + 0.01f;
             }
             // lower bound on the distance to any point outside the visited square
             float bnd = INFINITY;
@@ -334,18 +380,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_obs(DevParams P, DevWorld Wd,
             if (cy - rr > 0) bnd = fminf(bnd, py - (g.y0 + (float)(cy - rr) * g.cell));
             if (cy + rr < g.ny - 1) bnd = fminf(bnd, (g.y0 + (float)(cy + rr + 1) * g.cell) - py);
             if (bnd == INFINITY) break;
-            const float tq = (bnd - 0.01f) * 1024.f;
-            if (tq > 0.f && nc >= 64) {
-                const long long th = (long long)tq;
-                const unsigned long long thr = ((unsigned long long)sat_key(th * th) << 20) | 0xFFFFFull;
-                wave_sync();
-                int cnt = 0;
-                for (int k0 = 0; k0 < nc; k0 += 64) {
-                    const int k = k0 + lane;
-                    cnt += __popcll(__ballot(k < nc && cand[k] <= thr));
-                }
-                if (cnt >= 64) break;
-            }
+            // every unvisited point is farther than the 64th candidate
+            if (nc >= 64 && bnd > rcull) break;
         }
         wave_sync();
         // the 64 best among the buffered candidates, compacted into lanes

@@ -24,7 +24,7 @@
 #define SF_BCAP 32       // contact points per body and substep
 #define SF_PAIR_CAP (SF_MAXA * (SF_MAXA - 1) / 2)
 #define SF_KEY_CAP (1ll << 43)   // saturation of kNN squared distances
-#define SF_CAND_CAP 1024          // road candidates kept per agent
+#define SF_CAND_CAP 512           // road candidates kept per agent
 
 // learned tire surrogate: 16 -> 128 -> 128 -> 128 -> 3, flat fp32 parameters
 // W1[128][16] b1 W2[128][128] b2 W3[128][128] b3 W4[3][128] b4
