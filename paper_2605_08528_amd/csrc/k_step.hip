@@ -38,7 +38,7 @@ struct RayHit {
 // over the ground, the lowest triangle index first.  One pass keeps up to 4
 // distinct triangle hits in registers; more (stacked geometry) triggers a
 // second pass that applies the same rule.
-__device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, int w, f3 m, f3 u) {
+__device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, const GridHdr &g, bool any_tri, f3 m, f3 u) {
     const float ell = P.ell;
     float tmin = INFINITY, tg = INFINITY;
     if (u.z < 0.f) {
@@ -50,12 +50,10 @@ __device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, int w, f3 m, f
     H.surf = 0;
     H.t = tg;
     H.n = mk3(0.f, 0.f, 1.f);
-    const bool any_tri = Wd.toff[w + 1] > Wd.toff[w];
     if (!any_tri) {
         H.hit = tmin < INFINITY;
         return H;
     }
-    const GridHdr g = Wd.tgrid[w];
     const float ex = m.x + ell * u.x, ey = m.y + ell * u.y;
     int cx0 = (int)floorf((fminf(m.x, ex) - g.x0) * g.inv_cell);
     int cx1 = (int)floorf((fmaxf(m.x, ex) - g.x0) * g.inv_cell);
@@ -69,19 +67,32 @@ __device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, int w, f3 m, f
     for (int cy = cy0; cy <= cy1; ++cy) {
         const int c0 = g.cbase + cy * g.nx;
         const int s = Wd.tri_cell_start[c0 + cx0], e = Wd.tri_cell_start[c0 + cx1 + 1];
-        for (int k = s; k < e; ++k) {
-            const float4 a = Wd.tri_rec[3 * (size_t)k], b = Wd.tri_rec[3 * (size_t)k + 1],
-                         c = Wd.tri_rec[3 * (size_t)k + 2];
-            const float t = mt_rec(a, b, c, m, u, ell);
-            if (t < INFINITY) {
-                const int id = __float_as_int(a.w);
-                tmin = fminf(tmin, t);
-                if (id == i0 || id == i1 || id == i2 || id == i3) continue;
-                if (nh == 0) { t0 = t; i0 = id; k0 = k; }
-                else if (nh == 1) { t1 = t; i1 = id; k1 = k; }
-                else if (nh == 2) { t2 = t; i2 = id; k2 = k; }
-                else if (nh == 3) { t3 = t; i3 = id; k3 = k; }
-                ++nh;
+        // records in groups of 4: all loads of a group are in flight together
+        for (int kb = s; kb < e; kb += 4) {
+            float4 ra[4], rb[4], rc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (kb + q < e) {
+                    ra[q] = Wd.tri_rec[3 * (size_t)(kb + q)];
+                    rb[q] = Wd.tri_rec[3 * (size_t)(kb + q) + 1];
+                    rc[q] = Wd.tri_rec[3 * (size_t)(kb + q) + 2];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (kb + q >= e) break;
+                const int k = kb + q;
+                const float t = mt_rec(ra[q], rb[q], rc[q], m, u, ell);
+                if (t < INFINITY) {
+                    const int id = __float_as_int(ra[q].w);
+                    tmin = fminf(tmin, t);
+                    if (id == i0 || id == i1 || id == i2 || id == i3) continue;
+                    if (nh == 0) { t0 = t; i0 = id; k0 = k; }
+                    else if (nh == 1) { t1 = t; i1 = id; k1 = k; }
+                    else if (nh == 2) { t2 = t; i2 = id; k2 = k; }
+                    else if (nh == 3) { t3 = t; i3 = id; k3 = k; }
+                    ++nh;
+                }
             }
         }
     }
@@ -325,6 +336,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ float s_clam[SF_CCAP], s_cdl[SF_CCAP];
     __shared__ int s_cij[SF_CCAP];
     __shared__ short s_bl[SF_MAXA][SF_BCAP];
+    __shared__ float s_iw[6][SF_MAXA];   // world-frame inverse inertia (xx xy xz yy yz zz)
+    __shared__ GridHdr s_tgrid;          // the world's triangle grid
+    __shared__ bool s_anytri;
     __shared__ int s_bn[SF_MAXA];
     __shared__ int s_scan[NWV];
     __shared__ int s_np;
@@ -366,6 +380,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                       : e < 384 ? Su.P[SF_SUR_B3 + e - 256] : e < 387 ? Su.P[SF_SUR_B4 + e - 384] : 0.f;
     }
 
+    if (tid == 0) {
+        s_tgrid = Wd.tgrid[w];
+        s_anytri = Wd.toff[w + 1] > Wd.toff[w];
+    }
     // ---- load the world's agents; decode actions (Sec. "Action Space Details")
     for (int i = tid; i < A; i += BLOCK) {
         const int n = a0 + i;
@@ -425,7 +443,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
             long long hy = 2 * (qx * qy + qw * qz);
             long long nh = isqrt64(hx * hx + hy * hy);
             long long ox = 0, oy = 0;
-            if (nh > 0) { ox = (long long)P.Qd * hx / nh; oy = (long long)P.Qd * hy / nh; }
+            // |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to
+            // the exact integer quotient (cheaper than 64-bit division)
+            if (nh > 0) {
+                ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);
+                oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);
+            }
             s_cq[0][i] = (int)(X - ox); s_cq[1][i] = (int)(Y - oy);
             s_cq[2][i] = (int)X;        s_cq[3][i] = (int)Y;
             s_cq[4][i] = (int)(X + ox); s_cq[5][i] = (int)(Y + oy);
@@ -438,6 +461,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
         //      wheels: raycast, suspension, tire, spin.  B and C overlap.
         const bool pair_wave = NWV == 1 || wave == NWV - 1;
         if (pair_wave) {
+            const int pair_bound = (int)sqrtf((float)P.Qr2) + 2 + 2 * P.Qd;
             int np_w = 0;
             for (int base = 0; base < npc; base += 64) {
                 const int k = base + lane;
@@ -446,16 +470,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 if (k < npc) {
                     int i, j;
                     pair_of(k, A, i, j);
-                    if (s_act[i] && s_act[j]) {
+                    // centres farther apart than 2 (r + d) on either axis
+                    // cannot overlap; past that test every offset is below
+                    // 2^13 units and the squares fit 32-bit integers
+                    const int dX = s_cq[2][i] - s_cq[2][j], dY = s_cq[3][i] - s_cq[3][j];
+                    if (s_act[i] && s_act[j] && abs(dX) < pair_bound && abs(dY) < pair_bound) {
                         uint32_t mask = 0;
-                        const long long R2 = P.Qr2;
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
 #pragma unroll
                             for (int b = 0; b < 3; ++b) {
-                                const long long dx = (long long)s_cq[2 * a][i] - s_cq[2 * b][j];
-                                const long long dy = (long long)s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
-                                if (dx * dx + dy * dy < R2) mask |= 1u << (3 * a + b);
+                                const int dx = s_cq[2 * a][i] - s_cq[2 * b][j];
+                                const int dy = s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
+                                if (dx * dx + dy * dy < P.Qr2) mask |= 1u << (3 * a + b);
                             }
                         if (mask) {
                             flag = 1;
@@ -503,7 +530,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
                     rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
                     u = mk3(-R[2], -R[5], -R[8]);
-                    const RayHit H = raycast(P, Wd, w, add3(pos, rm), u);
+                    const RayHit H = raycast(P, Wd, s_tgrid, s_anytri, add3(pos, rm), u);
                     Om = s_om[wi];
                     td = wh < 2 ? s_taud[i] : 0.f;
                     tb = s_brk[i] * (wh < 2 ? P.tau_bf : P.tau_br);
@@ -725,6 +752,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
             const f3 om1 = Rmul(R, wb1);
             for (int c = 0; c < 3; ++c) s_v[c][i] += h * (&F.x)[c] * P.inv_mass;
             s_w[0][i] = om1.x; s_w[1][i] = om1.y; s_w[2][i] = om1.z;
+            // R diag(1/I) R^T, for the contact solve
+            {
+                const float a0 = P.inv_inertia[0], a1 = P.inv_inertia[1], a2 = P.inv_inertia[2];
+                s_iw[0][i] = R[0] * R[0] * a0 + R[1] * R[1] * a1 + R[2] * R[2] * a2;
+                s_iw[1][i] = R[0] * R[3] * a0 + R[1] * R[4] * a1 + R[2] * R[5] * a2;
+                s_iw[2][i] = R[0] * R[6] * a0 + R[1] * R[7] * a1 + R[2] * R[8] * a2;
+                s_iw[3][i] = R[3] * R[3] * a0 + R[4] * R[4] * a1 + R[5] * R[5] * a2;
+                s_iw[4][i] = R[3] * R[6] * a0 + R[4] * R[7] * a1 + R[5] * R[8] * a2;
+                s_iw[5][i] = R[6] * R[6] * a0 + R[7] * R[7] * a1 + R[8] * R[8] * a2;
+            }
             int cnt = 0;
             for (int c = 0; c < nc; ++c) {
                 const int ij = s_cij[c];
@@ -778,22 +815,27 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 for (int b = tid; b < A; b += BLOCK) {
                     const int cnt = s_bn[b];
                     if (cnt == 0) continue;
-                    float R[9];
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) R[q] = s_R[q][b];
-                    const f3 pb = mk3(s_p[0][b], s_p[1][b], s_p[2][b]);
-                    f3 v = mk3(s_v[0][b], s_v[1][b], s_v[2][b]);
-                    f3 om = mk3(s_w[0][b], s_w[1][b], s_w[2][b]);
+                    const float pbx = s_p[0][b], pby = s_p[1][b], pbz = s_p[2][b];
+                    // impulse and its moment summed in list order, then one
+                    // application of 1/m and the world inverse inertia
+                    float jx = 0.f, jy = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
+#pragma unroll 4
                     for (int q = 0; q < cnt; ++q) {
                         const int c = s_bl[b][q];
-                        const float sg = ((s_cij[c] >> 8) & 0xFF) == b ? 1.f : -1.f;
-                        const f3 J = mk3(sg * s_cdl[c] * s_cn[0][c], sg * s_cdl[c] * s_cn[1][c], 0.f);
-                        v = add3(v, mul3(J, P.inv_mass));
-                        const f3 r = sub3(mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]), pb);
-                        om = add3(om, inv_inertia(P, R, cross3(r, J)));
+                        const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? s_cdl[c] : -s_cdl[c];
+                        const float Jx = dl * s_cn[0][c], Jy = dl * s_cn[1][c];
+                        const float rx = s_cpc[0][c] - pbx, ry = s_cpc[1][c] - pby, rz = s_cpc[2][c] - pbz;
+                        jx += Jx;
+                        jy += Jy;
+                        tx -= rz * Jy;
+                        ty += rz * Jx;
+                        tz += rx * Jy - ry * Jx;
                     }
-                    s_v[0][b] = v.x; s_v[1][b] = v.y; s_v[2][b] = v.z;
-                    s_w[0][b] = om.x; s_w[1][b] = om.y; s_w[2][b] = om.z;
+                    s_v[0][b] += jx * P.inv_mass;
+                    s_v[1][b] += jy * P.inv_mass;
+                    s_w[0][b] += s_iw[0][b] * tx + s_iw[1][b] * ty + s_iw[2][b] * tz;
+                    s_w[1][b] += s_iw[1][b] * tx + s_iw[3][b] * ty + s_iw[4][b] * tz;
+                    s_w[2][b] += s_iw[2][b] * tx + s_iw[4][b] * ty + s_iw[5][b] * tz;
                 }
                 __syncthreads();
             }
@@ -941,7 +983,8 @@ __global__ void k_debug_raycast(DevParams P, DevWorld Wd, const float *st, float
     quat_R(st[SF_F_QW * N + n], st[SF_F_QX * N + n], st[SF_F_QY * N + n], st[SF_F_QZ * N + n], R);
     const f3 rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
     const f3 m = add3(mk3(st[SF_F_PX * N + n], st[SF_F_PY * N + n], st[SF_F_PZ * N + n]), rm);
-    RayHit H = raycast(P, Wd, Wd.world_of[n], m, mk3(-R[2], -R[5], -R[8]));
+    const int w = Wd.world_of[n];
+    RayHit H = raycast(P, Wd, Wd.tgrid[w], Wd.toff[w + 1] > Wd.toff[w], m, mk3(-R[2], -R[5], -R[8]));
     out[4 * (size_t)wi + 0] = (float)H.hit;
     out[4 * (size_t)wi + 1] = H.hit ? H.t : 0.f;
     out[4 * (size_t)wi + 2] = (float)H.surf;
