@@ -153,7 +153,10 @@ typedef struct {
     int32_t obs_waves;          /* agents (waves) per block in the obs kernel */
     int32_t policy_rows;        /* agents per block in the policy MLP (32/64) */
     float tri_cell;             /* triangle grid cell size [m]; 0 -> default  */
-    int32_t reserved[4];
+    int32_t step_grid;          /* persistent step: this many workgroups
+                                   pull worlds (largest first) from a queue;
+                                   0 (or >= worlds) -> one workgroup per world */
+    int32_t reserved[3];
 } sf_options;
 
 /* Fill the configured vehicle / default options. */
@@ -330,6 +333,32 @@ sf_status sf_sur_enable(sf_sim *sim, int32_t on);
  * network (out[0]) or fell back (out[1]); reset != 0 clears them after
  * reading.  Synchronises. */
 sf_status sf_sur_counts(sf_sim *sim, uint64_t *out, int32_t reset);
+
+/* ---- launch shapes and their autotuner.
+ * The paper measures throughput per configuration (Sec. "Throughput
+ * Analysis Details"); here the launch shapes of the three kernels of a
+ * control step are chosen by measuring them on the handle's own workload. */
+typedef struct {
+    int32_t step_block;   /* threads per world in the step (64..320)            */
+    int32_t step_grid;    /* 0, or the workgroups of a persistent step (queue)  */
+    int32_t obs_waves;    /* agents per workgroup in the observation (1, 2, 4)  */
+    int32_t policy_rows;  /* agents per workgroup in the policy (16, 32, 64)    */
+    float step_us, obs_us, policy_us;  /* measured mean durations (0 if cached) */
+} sf_tuning;
+
+sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out);
+/* Apply launch shapes (the timing fields are ignored); invalid values are
+ * rejected and nothing changes. */
+sf_status sf_set_tuning(sf_sim *sim, const sf_tuning *t);
+/* Time every candidate shape of the step, observation and policy kernels
+ * over `steps` control steps driven by the loaded policy (zero actions if
+ * none), each from the same snapshot of the state, which is restored at the
+ * end; keep the fastest of each kernel.  With cache_path (a text file, one
+ * line per workload signature: worlds, agents, largest world, road points,
+ * triangles, substeps, device), a line for this workload is applied without
+ * measuring, and a new result is added.  Synchronises. */
+sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, const char *cache_path,
+                      sf_tuning *out);
 
 const char *sf_status_str(sf_status s);
 const char *sf_last_error(void);

@@ -312,13 +312,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                                                 float h, int S, float *__restrict__ reward,
                                                 uint8_t *__restrict__ done, uint8_t *__restrict__ events,
                                                 uint32_t *__restrict__ rec, int *__restrict__ rec_cnt,
-                                                int rec_cap, const int *__restrict__ order) {
+                                                int rec_cap, const int *__restrict__ order,
+                                                int *__restrict__ queue) {
     constexpr int NWV = BLOCK / 64;
-    const int w = order ? order[blockIdx.x] : (int)blockIdx.x;
     const int N = Wd.N;
-    const int a0 = Wd.aoff[w];
-    const int A = Wd.aoff[w + 1] - a0;
-    if (A <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     __shared__ float s_p[3][SF_MAXA], s_q[4][SF_MAXA], s_v[3][SF_MAXA], s_w[3][SF_MAXA];
@@ -380,581 +377,609 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                       : e < 384 ? Su.P[SF_SUR_B3 + e - 256] : e < 387 ? Su.P[SF_SUR_B4 + e - 384] : 0.f;
     }
 
-    if (tid == 0) {
-        s_tgrid = Wd.tgrid[w];
-        s_anytri = Wd.toff[w + 1] > Wd.toff[w];
-    }
-    // ---- load the world's agents; decode actions (Sec. "Action Space Details")
-    for (int i = tid; i < A; i += BLOCK) {
-        const int n = a0 + i;
-        for (int c = 0; c < 3; ++c) {
-            s_p[c][i] = st[(SF_F_PX + c) * N + n];
-            s_v[c][i] = st[(SF_F_VX + c) * N + n];
-            s_w[c][i] = st[(SF_F_WX + c) * N + n];
-        }
-        for (int c = 0; c < 4; ++c) {
-            s_q[c][i] = st[(SF_F_QW + c) * N + n];
-            s_om[4 * i + c] = st[(SF_F_OM0 + c) * N + n];
-        }
-        s_th[i] = st[SF_F_STEER * N + n];
-        s_thd[i] = st[SF_F_STEER_RATE * N + n];
-        s_muo[i] = st[SF_F_MU * N + n];
-        s_act[i] = ist[SF_I_ACTIVE * N + n];
-        float al = act[2 * (size_t)n], sa = act[2 * (size_t)n + 1];
-        uint8_t bad = 0;
-        if (al != al) { al = 0.f; bad = 1; }
-        if (sa != sa) { sa = 0.f; bad = 1; }
-        al = fminf(fmaxf(al, -1.f), 1.f);
-        s_taud[i] = al > 0.f ? al * P.tau_drive : 0.f;
-        s_brk[i] = al < 0.f ? -al : 0.f;
-        s_tgt[i] = fminf(fmaxf(sa, -P.steer_max), P.steer_max);
-        s_nan[i] = bad;
-        s_coll[i] = 0;
-    }
-    __syncthreads();
-
-    const int npc = A * (A - 1) / 2;
-    for (int sub = 0; sub < S; ++sub) {
-        const bool last = sub == S - 1;
-        // ---- A: steering PD (Eq. steer PD, implicit in the rate), rotation,
-        //      planar heading and the quantised three-circle centres
-        for (int i = tid; i < A; i += BLOCK) {
-            if (!s_act[i]) continue;
-            float th = s_th[i], thd = s_thd[i], tgt = s_tgt[i];
-            float g = h / P.Is;
-            float thd1 = (thd + g * P.kp * (tgt - th)) / (1.f + g * (P.kd + h * P.kp));
-            float tau = P.kp * (tgt - th - h * thd1) - P.kd * thd1;
-            if (fabsf(tau) > P.tau_max) {
-                tau = tau > 0.f ? P.tau_max : -P.tau_max;
-                thd1 = thd + g * tau;
+    // Worlds in longest-first order.  Without a queue, block b takes world
+    // order[b]; with one (a persistent grid smaller than W), a block that
+    // finishes a world takes the next unclaimed one from an atomic counter.
+    __shared__ int s_item;
+    int item = blockIdx.x;
+    while (item < Wd.W) {
+        do {
+            const int w = order ? order[item] : item;
+            const int a0 = Wd.aoff[w];
+            const int A = Wd.aoff[w + 1] - a0;
+            if (A <= 0) break;
+            if (tid == 0) {
+                s_tgrid = Wd.tgrid[w];
+                s_anytri = Wd.toff[w + 1] > Wd.toff[w];
             }
-            s_th[i] = th + h * thd1;
-            s_thd[i] = thd1;
-            float R[9];
-            quat_R(s_q[0][i], s_q[1][i], s_q[2][i], s_q[3][i], R);
-            for (int c = 0; c < 9; ++c) s_R[c][i] = R[c];
-            float L = sqrtf(R[0] * R[0] + R[3] * R[3]);
-            s_hx[i] = L < 1e-12f ? 1.f : R[0] / L;
-            s_hy[i] = L < 1e-12f ? 0.f : R[3] / L;
-            long long X = qpos(s_p[0][i]), Y = qpos(s_p[1][i]);
-            long long qw = qquat(s_q[0][i]), qx = qquat(s_q[1][i]);
-            long long qy = qquat(s_q[2][i]), qz = qquat(s_q[3][i]);
-            long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);
-            long long hy = 2 * (qx * qy + qw * qz);
-            long long nh = isqrt64(hx * hx + hy * hy);
-            long long ox = 0, oy = 0;
-            // |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to
-            // the exact integer quotient (cheaper than 64-bit division)
-            if (nh > 0) {
-                ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);
-                oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);
+            // ---- load the world's agents; decode actions (Sec. "Action Space Details")
+            for (int i = tid; i < A; i += BLOCK) {
+                const int n = a0 + i;
+                for (int c = 0; c < 3; ++c) {
+                    s_p[c][i] = st[(SF_F_PX + c) * N + n];
+                    s_v[c][i] = st[(SF_F_VX + c) * N + n];
+                    s_w[c][i] = st[(SF_F_WX + c) * N + n];
+                }
+                for (int c = 0; c < 4; ++c) {
+                    s_q[c][i] = st[(SF_F_QW + c) * N + n];
+                    s_om[4 * i + c] = st[(SF_F_OM0 + c) * N + n];
+                }
+                s_th[i] = st[SF_F_STEER * N + n];
+                s_thd[i] = st[SF_F_STEER_RATE * N + n];
+                s_muo[i] = st[SF_F_MU * N + n];
+                s_act[i] = ist[SF_I_ACTIVE * N + n];
+                float al = act[2 * (size_t)n], sa = act[2 * (size_t)n + 1];
+                uint8_t bad = 0;
+                if (al != al) { al = 0.f; bad = 1; }
+                if (sa != sa) { sa = 0.f; bad = 1; }
+                al = fminf(fmaxf(al, -1.f), 1.f);
+                s_taud[i] = al > 0.f ? al * P.tau_drive : 0.f;
+                s_brk[i] = al < 0.f ? -al : 0.f;
+                s_tgt[i] = fminf(fmaxf(sa, -P.steer_max), P.steer_max);
+                s_nan[i] = bad;
+                s_coll[i] = 0;
             }
-            s_cq[0][i] = (int)(X - ox); s_cq[1][i] = (int)(Y - oy);
-            s_cq[2][i] = (int)X;        s_cq[3][i] = (int)Y;
-            s_cq[4][i] = (int)(X + ox); s_cq[5][i] = (int)(Y + oy);
-        }
-        __syncthreads();
+            __syncthreads();
 
-        // ---- B (last wave): overlapping circle pairs on the substep's input
-        //      poses, compacted in canonical (i, j) order with wave ballots.
-        // ---- C (the other waves; every thread when the block is one wave):
-        //      wheels: raycast, suspension, tire, spin.  B and C overlap.
-        const bool pair_wave = NWV == 1 || wave == NWV - 1;
-        if (pair_wave) {
-            const int pair_bound = (int)sqrtf((float)P.Qr2) + 2 + 2 * P.Qd;
-            int np_w = 0;
-            for (int base = 0; base < npc; base += 64) {
-                const int k = base + lane;
-                int flag = 0;
-                uint32_t packed = 0;
-                if (k < npc) {
-                    int i, j;
-                    pair_of(k, A, i, j);
-                    // centres farther apart than 2 (r + d) on either axis
-                    // cannot overlap; past that test every offset is below
-                    // 2^13 units and the squares fit 32-bit integers
-                    const int dX = s_cq[2][i] - s_cq[2][j], dY = s_cq[3][i] - s_cq[3][j];
-                    if (s_act[i] && s_act[j] && abs(dX) < pair_bound && abs(dY) < pair_bound) {
-                        uint32_t mask = 0;
+            const int npc = A * (A - 1) / 2;
+            for (int sub = 0; sub < S; ++sub) {
+                const bool last = sub == S - 1;
+                // ---- A: steering PD (Eq. steer PD, implicit in the rate), rotation,
+                //      planar heading and the quantised three-circle centres
+                for (int i = tid; i < A; i += BLOCK) {
+                    if (!s_act[i]) continue;
+                    float th = s_th[i], thd = s_thd[i], tgt = s_tgt[i];
+                    float g = h / P.Is;
+                    float thd1 = (thd + g * P.kp * (tgt - th)) / (1.f + g * (P.kd + h * P.kp));
+                    float tau = P.kp * (tgt - th - h * thd1) - P.kd * thd1;
+                    if (fabsf(tau) > P.tau_max) {
+                        tau = tau > 0.f ? P.tau_max : -P.tau_max;
+                        thd1 = thd + g * tau;
+                    }
+                    s_th[i] = th + h * thd1;
+                    s_thd[i] = thd1;
+                    float R[9];
+                    quat_R(s_q[0][i], s_q[1][i], s_q[2][i], s_q[3][i], R);
+                    for (int c = 0; c < 9; ++c) s_R[c][i] = R[c];
+                    float L = sqrtf(R[0] * R[0] + R[3] * R[3]);
+                    s_hx[i] = L < 1e-12f ? 1.f : R[0] / L;
+                    s_hy[i] = L < 1e-12f ? 0.f : R[3] / L;
+                    long long X = qpos(s_p[0][i]), Y = qpos(s_p[1][i]);
+                    long long qw = qquat(s_q[0][i]), qx = qquat(s_q[1][i]);
+                    long long qy = qquat(s_q[2][i]), qz = qquat(s_q[3][i]);
+                    long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);
+                    long long hy = 2 * (qx * qy + qw * qz);
+                    long long nh = isqrt64(hx * hx + hy * hy);
+                    long long ox = 0, oy = 0;
+                    // |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to
+                    // the exact integer quotient (cheaper than 64-bit division)
+                    if (nh > 0) {
+                        ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);
+                        oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);
+                    }
+                    s_cq[0][i] = (int)(X - ox); s_cq[1][i] = (int)(Y - oy);
+                    s_cq[2][i] = (int)X;        s_cq[3][i] = (int)Y;
+                    s_cq[4][i] = (int)(X + ox); s_cq[5][i] = (int)(Y + oy);
+                }
+                __syncthreads();
+
+                // ---- B (last wave): overlapping circle pairs on the substep's input
+                //      poses, compacted in canonical (i, j) order with wave ballots.
+                // ---- C (the other waves; every thread when the block is one wave):
+                //      wheels: raycast, suspension, tire, spin.  B and C overlap.
+                const bool pair_wave = NWV == 1 || wave == NWV - 1;
+                if (pair_wave) {
+                    const int pair_bound = (int)sqrtf((float)P.Qr2) + 2 + 2 * P.Qd;
+                    int np_w = 0;
+                    for (int base = 0; base < npc; base += 64) {
+                        const int k = base + lane;
+                        int flag = 0;
+                        uint32_t packed = 0;
+                        if (k < npc) {
+                            int i, j;
+                            pair_of(k, A, i, j);
+                            // centres farther apart than 2 (r + d) on either axis
+                            // cannot overlap; past that test every offset is below
+                            // 2^13 units and the squares fit 32-bit integers
+                            const int dX = s_cq[2][i] - s_cq[2][j], dY = s_cq[3][i] - s_cq[3][j];
+                            if (s_act[i] && s_act[j] && abs(dX) < pair_bound && abs(dY) < pair_bound) {
+                                uint32_t mask = 0;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a)
+                                for (int a = 0; a < 3; ++a)
 #pragma unroll
-                            for (int b = 0; b < 3; ++b) {
-                                const int dx = s_cq[2 * a][i] - s_cq[2 * b][j];
-                                const int dy = s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
-                                if (dx * dx + dy * dy < P.Qr2) mask |= 1u << (3 * a + b);
+                                    for (int b = 0; b < 3; ++b) {
+                                        const int dx = s_cq[2 * a][i] - s_cq[2 * b][j];
+                                        const int dy = s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
+                                        if (dx * dx + dy * dy < P.Qr2) mask |= 1u << (3 * a + b);
+                                    }
+                                if (mask) {
+                                    flag = 1;
+                                    packed = (uint32_t)i | ((uint32_t)j << 8) | (mask << 16);
+                                }
                             }
-                        if (mask) {
-                            flag = 1;
-                            packed = (uint32_t)i | ((uint32_t)j << 8) | (mask << 16);
+                        }
+                        const unsigned long long bal = __ballot(flag);
+                        if (flag) s_pairs[np_w + __popcll(bal & lanemask_lt())] = packed;
+                        np_w += __popcll(bal);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    if (rec) {
+                        uint32_t *dst = rec + ((size_t)sub * Wd.W + w) * rec_cap;
+                        for (int k = lane; k < np_w && k < rec_cap; k += 64) dst[k] = s_pairs[k];
+                        if (lane == 0) rec_cnt[sub * Wd.W + w] = np_w;
+                    }
+                    for (int k = lane; k < np_w; k += 64) {
+                        s_coll[s_pairs[k] & 0xFF] = 1;
+                        s_coll[(s_pairs[k] >> 8) & 0xFF] = 1;
+                    }
+                    if (lane == 0) s_np = np_w;
+                }
+                const int wheel_threads = NWV == 1 ? BLOCK : BLOCK - 64;
+                if (tid < wheel_threads) {
+                    // the loop bound is the same for every lane of a wave (the
+                    // surrogate's matrix products need the whole wave)
+                    for (int base = 0; base < 4 * A; base += wheel_threads) {
+                        const int wi = base + tid;
+                        const bool valid = wi < 4 * A;
+                        const int i = valid ? (wi >> 2) : 0, wh = wi & 3;
+                        const bool live = valid && s_act[i];
+                        float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                        float mu_seen = 0.f;
+                        float R[9];
+                        f3 v = mk3(0.f, 0.f, 0.f), om = v, rm = v, u = v, n = v, rc = v, ex = v, ey = v;
+                        float Om = 0.f, td = 0.f, tb = 0.f, mu = 0.f, Fz = 0.f, vx = 0.f, vy = 0.f, x = 0.f, xd = 0.f, dl = 0.f;
+                        bool hit = false, frame = false;
+                        if (live) {
+#pragma unroll
+                            for (int c = 0; c < 9; ++c) R[c] = s_R[c][i];
+                            const f3 pos = mk3(s_p[0][i], s_p[1][i], s_p[2][i]);
+                            v = mk3(s_v[0][i], s_v[1][i], s_v[2][i]);
+                            om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
+                            rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
+                            u = mk3(-R[2], -R[5], -R[8]);
+                            const RayHit H = raycast(P, Wd, s_tgrid, s_anytri, add3(pos, rm), u);
+                            Om = s_om[wi];
+                            td = wh < 2 ? s_taud[i] : 0.f;
+                            tb = s_brk[i] * (wh < 2 ? P.tau_bf : P.tau_br);
+                            hit = H.hit;
+                            if (hit) {
+                                n = H.n;
+                                mu = Wd.mu[w * Wd.S + H.surf];
+                                mu_seen = mu;
+                                // massless spring-damper along the ray
+                                x = P.ell - H.t;
+                                const f3 vm = add3(v, cross3(om, rm));
+                                xd = -dot3(n, vm) / (-dot3(n, u));
+                                Fz = fmaxf(P.susp_k * x + P.susp_c * xd, 0.f);
+                                rc = add3(rm, mul3(u, H.t));
+                                // tire frame: wheel heading projected on the contact plane
+                                dl = wh < 2 ? s_th[i] : 0.f;
+                                const f3 hw = Rmul(R, mk3(cosf(dl), sinf(dl), 0.f));
+                                ex = sub3(hw, mul3(n, dot3(hw, n)));
+                                const float L = sqrtf(dot3(ex, ex));
+                                if (L > 1e-9f) {
+                                    frame = true;
+                                    ex = mul3(ex, 1.f / L);
+                                    ey = cross3(n, ex);
+                                    const f3 vc = add3(v, cross3(om, rc));
+                                    vx = dot3(vc, ex);
+                                    vy = dot3(vc, ey);
+                                } else {
+                                    ex = mk3(0.f, 0.f, 0.f);
+                                }
+                            }
+                        }
+                        // the surrogate's domain: a loaded wheel at |v_x| >= 3 m/s
+                        const bool dom = frame && Fz > 0.f && fabsf(vx) >= 3.f;
+                        float feat[SF_SUR_IN];
+                        if (SUR || Su.log) {
+                            if (dom) {
+                                const float D = fmaxf(fabsf(vx), P.v_eps);
+                                const f3 axle = Rmul(R, mk3(-sinf(dl), cosf(dl), 0.f));
+                                feat[0] = (P.rw * Om - vx) / D;
+                                feat[1] = atanf(vy / D);
+                                feat[2] = Fz / 4000.f;
+                                feat[3] = mu;
+                                feat[4] = P.rw * Om / 30.f;
+                                feat[5] = asinf(fminf(fmaxf(dot3(axle, n), -1.f), 1.f));
+                                feat[6] = vx / 30.f;
+                                feat[7] = vy / 5.f;
+                                feat[8] = dl;
+                                feat[9] = x / 0.2f;
+                                feat[10] = xd / 2.f;
+                                feat[11] = td / P.tau_drive;
+                                feat[12] = tb / P.tau_bf;
+                                feat[13] = atan2f(R[7], R[8]);
+                                feat[14] = asinf(fminf(fmaxf(-R[6], -1.f), 1.f));
+                                feat[15] = om.z / 2.f;
+                            } else {
+#pragma unroll
+                                for (int q = 0; q < SF_SUR_IN; ++q) feat[q] = 0.f;
+                            }
+                        }
+                        // ---- learned tire model for the wave's wheels, if enabled
+                        bool use = false;
+                        float Fxs = 0.f, Fys = 0.f, Mzs = 0.f;
+                        if (SUR) {
+                            bool inside = dom;
+#pragma unroll
+                            for (int q = 0; q < SF_SUR_IN; ++q) inside = inside && feat[q] >= Su.lo[q] && feat[q] <= Su.hi[q];
+                            if (__ballot(inside)) {
+                                float y[3];
+                                sur_mlp_wave(s_sur + wave * SUR_ROWS * SUR_LD, feat, inside, s_surw, s_surb, y);
+                                if (inside) {
+                                    const float lim = mu * Fz;
+                                    Fxs = lim * y[0];
+                                    Fys = lim * y[1];
+                                    Mzs = P.trail * lim * y[2];
+                                    const float kap = (P.rw * Om - vx) / fabsf(vx);
+                                    // residual checks: inside the friction circle (2 %
+                                    // slack) and longitudinal force along the slip
+                                    use = sqrtf(Fxs * Fxs + Fys * Fys) <= 1.02f * lim &&
+                                          (fabsf(kap) <= 0.02f || ((Fxs > 0.f) == (kap > 0.f)));
+                                }
+                            }
+                            // one counter update per wave, not per wheel
+                            const unsigned long long bu = __ballot(dom && use), bf = __ballot(dom && !use);
+                            if (lane == 0 && bu) atomicAdd(Su.counts, (unsigned long long)__popcll(bu));
+                            if (lane == 0 && bf) atomicAdd(Su.counts + 1, (unsigned long long)__popcll(bf));
+                        }
+                        if (live) {
+                            float Fx = 0.f, Fy = 0.f, Mz = 0.f, om1;
+                            if (frame) {
+                                if (use) {
+                                    Fx = Fxs;
+                                    Fy = Fys;
+                                    Mz = Mzs;
+                                    const float a = h / P.Iw, Bs = Om + a * (td - P.rw * Fx);
+                                    const float mag = fmaxf(fabsf(Bs) - a * tb, 0.f);
+                                    om1 = Bs > 0.f ? mag : (Bs < 0.f ? -mag : 0.f);
+                                } else {
+                                    tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fx, Fy, om1);
+                                    Mz = -P.trail * Fy;
+                                }
+                            } else {
+                                // airborne wheel or no usable tire frame: no load
+                                tire(P, h, 0.f, hit ? mu : 0.f, 0.f, 0.f, Om, td, tb, Fx, Fy, om1);
+                            }
+                            if (hit) {
+                                const f3 fw = add3(add3(mul3(n, Fz), mul3(ex, Fx)), mul3(ey, Fy));
+                                const f3 tq = add3(cross3(rc, fw), mul3(n, Mz));
+                                f[0] = fw.x; f[1] = fw.y; f[2] = fw.z;
+                                f[3] = tq.x; f[4] = tq.y; f[5] = tq.z;
+                            }
+                            s_om[wi] = om1;
+                        }
+                        // ---- training samples: inputs and the plain model's outputs
+                        if (Su.log && valid) {
+                            const long long slot = (Su.log_base + (long long)sub * 4 * N + 4ll * (a0 + i) + wh) % Su.log_cap;
+                            float *dst = Su.log + slot * SF_SUR_SAMPLE;
+                            if (dom) {
+                                float Fxp, Fyp, omp;
+                                tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fxp, Fyp, omp);
+                                const float lim = mu * Fz;
+#pragma unroll
+                                for (int q = 0; q < SF_SUR_IN; ++q) dst[q] = feat[q];
+                                dst[SF_SUR_IN] = lim > 0.f ? Fxp / lim : 0.f;
+                                dst[SF_SUR_IN + 1] = lim > 0.f ? Fyp / lim : 0.f;
+                                dst[SF_SUR_IN + 2] = lim > 0.f ? -Fyp / lim : 0.f;
+                                dst[SF_SUR_IN + 3] = 1.f;
+                            } else {
+                                dst[SF_SUR_IN + 3] = 0.f;
+                            }
+                        }
+                        if (valid) {
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) s_wf[c][wi] = f[c];
+                            s_wmu[wi] = mu_seen;
                         }
                     }
                 }
-                const unsigned long long bal = __ballot(flag);
-                if (flag) s_pairs[np_w + __popcll(bal & lanemask_lt())] = packed;
-                np_w += __popcll(bal);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (rec) {
-                uint32_t *dst = rec + ((size_t)sub * Wd.W + w) * rec_cap;
-                for (int k = lane; k < np_w && k < rec_cap; k += 64) dst[k] = s_pairs[k];
-                if (lane == 0) rec_cnt[sub * Wd.W + w] = np_w;
-            }
-            for (int k = lane; k < np_w; k += 64) {
-                s_coll[s_pairs[k] & 0xFF] = 1;
-                s_coll[(s_pairs[k] >> 8) & 0xFF] = 1;
-            }
-            if (lane == 0) s_np = np_w;
-        }
-        const int wheel_threads = NWV == 1 ? BLOCK : BLOCK - 64;
-        if (tid < wheel_threads) {
-            // the loop bound is the same for every lane of a wave (the
-            // surrogate's matrix products need the whole wave)
-            for (int base = 0; base < 4 * A; base += wheel_threads) {
-                const int wi = base + tid;
-                const bool valid = wi < 4 * A;
-                const int i = valid ? (wi >> 2) : 0, wh = wi & 3;
-                const bool live = valid && s_act[i];
-                float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                float mu_seen = 0.f;
-                float R[9];
-                f3 v = mk3(0.f, 0.f, 0.f), om = v, rm = v, u = v, n = v, rc = v, ex = v, ey = v;
-                float Om = 0.f, td = 0.f, tb = 0.f, mu = 0.f, Fz = 0.f, vx = 0.f, vy = 0.f, x = 0.f, xd = 0.f, dl = 0.f;
-                bool hit = false, frame = false;
-                if (live) {
+
+                __syncthreads();
+                const int np = s_np;
+                // ---- D: contact points of the compacted pairs, in list order
+                int nc = 0;
+                for (int base = 0; base < np; base += BLOCK) {
+                    const int k = base + tid;
+                    uint32_t pr = k < np ? s_pairs[k] : 0u;
+                    int cnt = __popc(pr >> 16);
+                    int x = cnt;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        int y = __shfl_up(x, o, 64);
+                        if (lane >= o) x += y;
+                    }
+                    if (lane == 63) s_scan[wave] = x;
+                    __syncthreads();
+                    int off = 0, tot = 0;
+#pragma unroll
+                    for (int v = 0; v < NWV; ++v) {
+                        if (v < wave) off += s_scan[v];
+                        tot += s_scan[v];
+                    }
+                    int pos = nc + off + x - cnt;
+                    if (cnt) {
+                        const int i = pr & 0xFF, j = (pr >> 8) & 0xFF;
+                        const uint32_t mask = pr >> 16;
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) {
+                                if (!(mask & (1u << (3 * a + b)))) continue;
+                                if (pos < SF_CCAP) {
+                                    const float cix = s_p[0][i] + (float)(a - 1) * P.cd * s_hx[i];
+                                    const float ciy = s_p[1][i] + (float)(a - 1) * P.cd * s_hy[i];
+                                    const float cjx = s_p[0][j] + (float)(b - 1) * P.cd * s_hx[j];
+                                    const float cjy = s_p[1][j] + (float)(b - 1) * P.cd * s_hy[j];
+                                    const float dx = cjx - cix, dy = cjy - ciy;
+                                    const float L = sqrtf(dx * dx + dy * dy);
+                                    s_cn[0][pos] = L > 0.f ? dx / L : 1.f;
+                                    s_cn[1][pos] = L > 0.f ? dy / L : 0.f;
+                                    s_cpc[0][pos] = 0.5f * (cix + cjx);
+                                    s_cpc[1][pos] = 0.5f * (ciy + cjy);
+                                    s_cpc[2][pos] = 0.5f * (s_p[2][i] + s_p[2][j]);
+                                    const float pen = 2.f * P.cr - L - P.slop;
+                                    s_cb[pos] = pen > 0.f ? (P.baumgarte / h) * pen : 0.f;
+                                    s_clam[pos] = 0.f;
+                                    s_cij[pos] = i | (j << 8);
+                                }
+                                ++pos;
+                            }
+                    }
+                    nc += tot;
+                    __syncthreads();
+                }
+                if (nc > SF_CCAP) {
+                    if (tid == 0) atomicAdd(&g_sf_overflow, 1);
+                    nc = SF_CCAP;
+                }
+                __syncthreads();
+
+                // ---- E: chassis velocities (semi-implicit Euler, explicit gyroscopic
+                //      term) and each body's contact list in list order
+                for (int i = tid; i < A; i += BLOCK) {
+                    if (!s_act[i]) { s_bn[i] = 0; continue; }
+                    float R[9];
 #pragma unroll
                     for (int c = 0; c < 9; ++c) R[c] = s_R[c][i];
-                    const f3 pos = mk3(s_p[0][i], s_p[1][i], s_p[2][i]);
-                    v = mk3(s_v[0][i], s_v[1][i], s_v[2][i]);
-                    om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
-                    rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
-                    u = mk3(-R[2], -R[5], -R[8]);
-                    const RayHit H = raycast(P, Wd, s_tgrid, s_anytri, add3(pos, rm), u);
-                    Om = s_om[wi];
-                    td = wh < 2 ? s_taud[i] : 0.f;
-                    tb = s_brk[i] * (wh < 2 ? P.tau_bf : P.tau_br);
-                    hit = H.hit;
-                    if (hit) {
-                        n = H.n;
-                        mu = Wd.mu[w * Wd.S + H.surf];
-                        mu_seen = mu;
-                        // massless spring-damper along the ray
-                        x = P.ell - H.t;
-                        const f3 vm = add3(v, cross3(om, rm));
-                        xd = -dot3(n, vm) / (-dot3(n, u));
-                        Fz = fmaxf(P.susp_k * x + P.susp_c * xd, 0.f);
-                        rc = add3(rm, mul3(u, H.t));
-                        // tire frame: wheel heading projected on the contact plane
-                        dl = wh < 2 ? s_th[i] : 0.f;
-                        const f3 hw = Rmul(R, mk3(cosf(dl), sinf(dl), 0.f));
-                        ex = sub3(hw, mul3(n, dot3(hw, n)));
-                        const float L = sqrtf(dot3(ex, ex));
-                        if (L > 1e-9f) {
-                            frame = true;
-                            ex = mul3(ex, 1.f / L);
-                            ey = cross3(n, ex);
-                            const f3 vc = add3(v, cross3(om, rc));
-                            vx = dot3(vc, ex);
-                            vy = dot3(vc, ey);
-                        } else {
-                            ex = mk3(0.f, 0.f, 0.f);
+                    f3 F = mk3(0.f, 0.f, -P.mass * P.g);
+                    f3 T = mk3(0.f, 0.f, -P.yaw_damping * s_w[2][i]);
+#pragma unroll
+                    for (int wh = 0; wh < 4; ++wh) {
+                        const int wi = 4 * i + wh;
+                        F = add3(F, mk3(s_wf[0][wi], s_wf[1][wi], s_wf[2][wi]));
+                        T = add3(T, mk3(s_wf[3][wi], s_wf[4][wi], s_wf[5][wi]));
+                    }
+                    if (last) s_muo[i] = (s_wmu[4 * i] + s_wmu[4 * i + 1] + s_wmu[4 * i + 2] + s_wmu[4 * i + 3]) * 0.25f;
+                    const f3 om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
+                    const f3 wb = RTmul(R, om), Tb = RTmul(R, T);
+                    const f3 Lb = mk3(P.inertia[0] * wb.x, P.inertia[1] * wb.y, P.inertia[2] * wb.z);
+                    const f3 gy = cross3(wb, Lb);
+                    const f3 wb1 = mk3(wb.x + h * (Tb.x - gy.x) * P.inv_inertia[0],
+                                       wb.y + h * (Tb.y - gy.y) * P.inv_inertia[1],
+                                       wb.z + h * (Tb.z - gy.z) * P.inv_inertia[2]);
+                    const f3 om1 = Rmul(R, wb1);
+                    for (int c = 0; c < 3; ++c) s_v[c][i] += h * (&F.x)[c] * P.inv_mass;
+                    s_w[0][i] = om1.x; s_w[1][i] = om1.y; s_w[2][i] = om1.z;
+                    // R diag(1/I) R^T, for the contact solve
+                    {
+                        const float a0 = P.inv_inertia[0], a1 = P.inv_inertia[1], a2 = P.inv_inertia[2];
+                        s_iw[0][i] = R[0] * R[0] * a0 + R[1] * R[1] * a1 + R[2] * R[2] * a2;
+                        s_iw[1][i] = R[0] * R[3] * a0 + R[1] * R[4] * a1 + R[2] * R[5] * a2;
+                        s_iw[2][i] = R[0] * R[6] * a0 + R[1] * R[7] * a1 + R[2] * R[8] * a2;
+                        s_iw[3][i] = R[3] * R[3] * a0 + R[4] * R[4] * a1 + R[5] * R[5] * a2;
+                        s_iw[4][i] = R[3] * R[6] * a0 + R[4] * R[7] * a1 + R[5] * R[8] * a2;
+                        s_iw[5][i] = R[6] * R[6] * a0 + R[7] * R[7] * a1 + R[8] * R[8] * a2;
+                    }
+                    int cnt = 0;
+                    for (int c = 0; c < nc; ++c) {
+                        const int ij = s_cij[c];
+                        if ((ij & 0xFF) == i || ((ij >> 8) & 0xFF) == i) {
+                            if (cnt < SF_BCAP) s_bl[i][cnt] = (short)c;
+                            ++cnt;
                         }
                     }
-                }
-                // the surrogate's domain: a loaded wheel at |v_x| >= 3 m/s
-                const bool dom = frame && Fz > 0.f && fabsf(vx) >= 3.f;
-                float feat[SF_SUR_IN];
-                if (SUR || Su.log) {
-                    if (dom) {
-                        const float D = fmaxf(fabsf(vx), P.v_eps);
-                        const f3 axle = Rmul(R, mk3(-sinf(dl), cosf(dl), 0.f));
-                        feat[0] = (P.rw * Om - vx) / D;
-                        feat[1] = atanf(vy / D);
-                        feat[2] = Fz / 4000.f;
-                        feat[3] = mu;
-                        feat[4] = P.rw * Om / 30.f;
-                        feat[5] = asinf(fminf(fmaxf(dot3(axle, n), -1.f), 1.f));
-                        feat[6] = vx / 30.f;
-                        feat[7] = vy / 5.f;
-                        feat[8] = dl;
-                        feat[9] = x / 0.2f;
-                        feat[10] = xd / 2.f;
-                        feat[11] = td / P.tau_drive;
-                        feat[12] = tb / P.tau_bf;
-                        feat[13] = atan2f(R[7], R[8]);
-                        feat[14] = asinf(fminf(fmaxf(-R[6], -1.f), 1.f));
-                        feat[15] = om.z / 2.f;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < SF_SUR_IN; ++q) feat[q] = 0.f;
-                    }
-                }
-                // ---- learned tire model for the wave's wheels, if enabled
-                bool use = false;
-                float Fxs = 0.f, Fys = 0.f, Mzs = 0.f;
-                if (SUR) {
-                    bool inside = dom;
-#pragma unroll
-                    for (int q = 0; q < SF_SUR_IN; ++q) inside = inside && feat[q] >= Su.lo[q] && feat[q] <= Su.hi[q];
-                    if (__ballot(inside)) {
-                        float y[3];
-                        sur_mlp_wave(s_sur + wave * SUR_ROWS * SUR_LD, feat, inside, s_surw, s_surb, y);
-                        if (inside) {
-                            const float lim = mu * Fz;
-                            Fxs = lim * y[0];
-                            Fys = lim * y[1];
-                            Mzs = P.trail * lim * y[2];
-                            const float kap = (P.rw * Om - vx) / fabsf(vx);
-                            // residual checks: inside the friction circle (2 %
-                            // slack) and longitudinal force along the slip
-                            use = sqrtf(Fxs * Fxs + Fys * Fys) <= 1.02f * lim &&
-                                  (fabsf(kap) <= 0.02f || ((Fxs > 0.f) == (kap > 0.f)));
-                        }
-                    }
-                    // one counter update per wave, not per wheel
-                    const unsigned long long bu = __ballot(dom && use), bf = __ballot(dom && !use);
-                    if (lane == 0 && bu) atomicAdd(Su.counts, (unsigned long long)__popcll(bu));
-                    if (lane == 0 && bf) atomicAdd(Su.counts + 1, (unsigned long long)__popcll(bf));
-                }
-                if (live) {
-                    float Fx = 0.f, Fy = 0.f, Mz = 0.f, om1;
-                    if (frame) {
-                        if (use) {
-                            Fx = Fxs;
-                            Fy = Fys;
-                            Mz = Mzs;
-                            const float a = h / P.Iw, Bs = Om + a * (td - P.rw * Fx);
-                            const float mag = fmaxf(fabsf(Bs) - a * tb, 0.f);
-                            om1 = Bs > 0.f ? mag : (Bs < 0.f ? -mag : 0.f);
-                        } else {
-                            tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fx, Fy, om1);
-                            Mz = -P.trail * Fy;
-                        }
-                    } else {
-                        // airborne wheel or no usable tire frame: no load
-                        tire(P, h, 0.f, hit ? mu : 0.f, 0.f, 0.f, Om, td, tb, Fx, Fy, om1);
-                    }
-                    if (hit) {
-                        const f3 fw = add3(add3(mul3(n, Fz), mul3(ex, Fx)), mul3(ey, Fy));
-                        const f3 tq = add3(cross3(rc, fw), mul3(n, Mz));
-                        f[0] = fw.x; f[1] = fw.y; f[2] = fw.z;
-                        f[3] = tq.x; f[4] = tq.y; f[5] = tq.z;
-                    }
-                    s_om[wi] = om1;
-                }
-                // ---- training samples: inputs and the plain model's outputs
-                if (Su.log && valid) {
-                    const long long slot = (Su.log_base + (long long)sub * 4 * N + 4ll * (a0 + i) + wh) % Su.log_cap;
-                    float *dst = Su.log + slot * SF_SUR_SAMPLE;
-                    if (dom) {
-                        float Fxp, Fyp, omp;
-                        tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fxp, Fyp, omp);
-                        const float lim = mu * Fz;
-#pragma unroll
-                        for (int q = 0; q < SF_SUR_IN; ++q) dst[q] = feat[q];
-                        dst[SF_SUR_IN] = lim > 0.f ? Fxp / lim : 0.f;
-                        dst[SF_SUR_IN + 1] = lim > 0.f ? Fyp / lim : 0.f;
-                        dst[SF_SUR_IN + 2] = lim > 0.f ? -Fyp / lim : 0.f;
-                        dst[SF_SUR_IN + 3] = 1.f;
-                    } else {
-                        dst[SF_SUR_IN + 3] = 0.f;
-                    }
-                }
-                if (valid) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) s_wf[c][wi] = f[c];
-                    s_wmu[wi] = mu_seen;
-                }
-            }
-        }
-
-        __syncthreads();
-        const int np = s_np;
-        // ---- D: contact points of the compacted pairs, in list order
-        int nc = 0;
-        for (int base = 0; base < np; base += BLOCK) {
-            const int k = base + tid;
-            uint32_t pr = k < np ? s_pairs[k] : 0u;
-            int cnt = __popc(pr >> 16);
-            int x = cnt;
-            for (int o = 1; o < 64; o <<= 1) {
-                int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            if (lane == 63) s_scan[wave] = x;
-            __syncthreads();
-            int off = 0, tot = 0;
-#pragma unroll
-            for (int v = 0; v < NWV; ++v) {
-                if (v < wave) off += s_scan[v];
-                tot += s_scan[v];
-            }
-            int pos = nc + off + x - cnt;
-            if (cnt) {
-                const int i = pr & 0xFF, j = (pr >> 8) & 0xFF;
-                const uint32_t mask = pr >> 16;
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) {
-                        if (!(mask & (1u << (3 * a + b)))) continue;
-                        if (pos < SF_CCAP) {
-                            const float cix = s_p[0][i] + (float)(a - 1) * P.cd * s_hx[i];
-                            const float ciy = s_p[1][i] + (float)(a - 1) * P.cd * s_hy[i];
-                            const float cjx = s_p[0][j] + (float)(b - 1) * P.cd * s_hx[j];
-                            const float cjy = s_p[1][j] + (float)(b - 1) * P.cd * s_hy[j];
-                            const float dx = cjx - cix, dy = cjy - ciy;
-                            const float L = sqrtf(dx * dx + dy * dy);
-                            s_cn[0][pos] = L > 0.f ? dx / L : 1.f;
-                            s_cn[1][pos] = L > 0.f ? dy / L : 0.f;
-                            s_cpc[0][pos] = 0.5f * (cix + cjx);
-                            s_cpc[1][pos] = 0.5f * (ciy + cjy);
-                            s_cpc[2][pos] = 0.5f * (s_p[2][i] + s_p[2][j]);
-                            const float pen = 2.f * P.cr - L - P.slop;
-                            s_cb[pos] = pen > 0.f ? (P.baumgarte / h) * pen : 0.f;
-                            s_clam[pos] = 0.f;
-                            s_cij[pos] = i | (j << 8);
-                        }
-                        ++pos;
-                    }
-            }
-            nc += tot;
-            __syncthreads();
-        }
-        if (nc > SF_CCAP) {
-            if (tid == 0) atomicAdd(&g_sf_overflow, 1);
-            nc = SF_CCAP;
-        }
-        __syncthreads();
-
-        // ---- E: chassis velocities (semi-implicit Euler, explicit gyroscopic
-        //      term) and each body's contact list in list order
-        for (int i = tid; i < A; i += BLOCK) {
-            if (!s_act[i]) { s_bn[i] = 0; continue; }
-            float R[9];
-#pragma unroll
-            for (int c = 0; c < 9; ++c) R[c] = s_R[c][i];
-            f3 F = mk3(0.f, 0.f, -P.mass * P.g);
-            f3 T = mk3(0.f, 0.f, -P.yaw_damping * s_w[2][i]);
-#pragma unroll
-            for (int wh = 0; wh < 4; ++wh) {
-                const int wi = 4 * i + wh;
-                F = add3(F, mk3(s_wf[0][wi], s_wf[1][wi], s_wf[2][wi]));
-                T = add3(T, mk3(s_wf[3][wi], s_wf[4][wi], s_wf[5][wi]));
-            }
-            if (last) s_muo[i] = (s_wmu[4 * i] + s_wmu[4 * i + 1] + s_wmu[4 * i + 2] + s_wmu[4 * i + 3]) * 0.25f;
-            const f3 om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
-            const f3 wb = RTmul(R, om), Tb = RTmul(R, T);
-            const f3 Lb = mk3(P.inertia[0] * wb.x, P.inertia[1] * wb.y, P.inertia[2] * wb.z);
-            const f3 gy = cross3(wb, Lb);
-            const f3 wb1 = mk3(wb.x + h * (Tb.x - gy.x) * P.inv_inertia[0],
-                               wb.y + h * (Tb.y - gy.y) * P.inv_inertia[1],
-                               wb.z + h * (Tb.z - gy.z) * P.inv_inertia[2]);
-            const f3 om1 = Rmul(R, wb1);
-            for (int c = 0; c < 3; ++c) s_v[c][i] += h * (&F.x)[c] * P.inv_mass;
-            s_w[0][i] = om1.x; s_w[1][i] = om1.y; s_w[2][i] = om1.z;
-            // R diag(1/I) R^T, for the contact solve
-            {
-                const float a0 = P.inv_inertia[0], a1 = P.inv_inertia[1], a2 = P.inv_inertia[2];
-                s_iw[0][i] = R[0] * R[0] * a0 + R[1] * R[1] * a1 + R[2] * R[2] * a2;
-                s_iw[1][i] = R[0] * R[3] * a0 + R[1] * R[4] * a1 + R[2] * R[5] * a2;
-                s_iw[2][i] = R[0] * R[6] * a0 + R[1] * R[7] * a1 + R[2] * R[8] * a2;
-                s_iw[3][i] = R[3] * R[3] * a0 + R[4] * R[4] * a1 + R[5] * R[5] * a2;
-                s_iw[4][i] = R[3] * R[6] * a0 + R[4] * R[7] * a1 + R[5] * R[8] * a2;
-                s_iw[5][i] = R[6] * R[6] * a0 + R[7] * R[7] * a1 + R[8] * R[8] * a2;
-            }
-            int cnt = 0;
-            for (int c = 0; c < nc; ++c) {
-                const int ij = s_cij[c];
-                if ((ij & 0xFF) == i || ((ij >> 8) & 0xFF) == i) {
-                    if (cnt < SF_BCAP) s_bl[i][cnt] = (short)c;
-                    ++cnt;
-                }
-            }
-            if (cnt > SF_BCAP) { atomicAdd(&g_sf_overflow, 1); cnt = SF_BCAP; }
-            s_bn[i] = cnt;
-        }
-        __syncthreads();
-
-        if (nc > 0) {
-            // ---- F: effective mass along each normal, relaxed by the larger
-            //      contact count of the two bodies
-            for (int c = tid; c < nc; c += BLOCK) {
-                const int i = s_cij[c] & 0xFF, j = (s_cij[c] >> 8) & 0xFF;
-                const f3 n = mk3(s_cn[0][c], s_cn[1][c], 0.f);
-                const f3 pc = mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]);
-                float Ri[9], Rj[9];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) { Ri[q] = s_R[q][i]; Rj[q] = s_R[q][j]; }
-                const f3 ri = sub3(pc, mk3(s_p[0][i], s_p[1][i], s_p[2][i]));
-                const f3 rj = sub3(pc, mk3(s_p[0][j], s_p[1][j], s_p[2][j]));
-                const f3 xi = cross3(ri, n), xj = cross3(rj, n);
-                const float keff = 2.f * P.inv_mass + dot3(xi, inv_inertia(P, Ri, xi)) +
-                                   dot3(xj, inv_inertia(P, Rj, xj));
-                const int nmax = max(s_bn[i], s_bn[j]);
-                s_cwk[c] = 1.f / ((float)nmax * keff);
-            }
-            __syncthreads();
-            // ---- G: Jacobi sweeps: every contact reads the previous sweep's
-            //      velocities; each body then sums its contacts in list order
-            for (int it = 0; it < P.jacobi_iters; ++it) {
-                for (int c = tid; c < nc; c += BLOCK) {
-                    const int i = s_cij[c] & 0xFF, j = (s_cij[c] >> 8) & 0xFF;
-                    const f3 pc = mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]);
-                    const f3 ri = sub3(pc, mk3(s_p[0][i], s_p[1][i], s_p[2][i]));
-                    const f3 rj = sub3(pc, mk3(s_p[0][j], s_p[1][j], s_p[2][j]));
-                    const f3 wi = cross3(mk3(s_w[0][i], s_w[1][i], s_w[2][i]), ri);
-                    const f3 wj = cross3(mk3(s_w[0][j], s_w[1][j], s_w[2][j]), rj);
-                    const float vn = ((s_v[0][j] + wj.x) - (s_v[0][i] + wi.x)) * s_cn[0][c] +
-                                     ((s_v[1][j] + wj.y) - (s_v[1][i] + wi.y)) * s_cn[1][c];
-                    const float lam = s_clam[c];
-                    const float lam1 = fmaxf(lam + s_cwk[c] * (-vn + s_cb[c]), 0.f);
-                    s_cdl[c] = lam1 - lam;
-                    s_clam[c] = lam1;
+                    if (cnt > SF_BCAP) { atomicAdd(&g_sf_overflow, 1); cnt = SF_BCAP; }
+                    s_bn[i] = cnt;
                 }
                 __syncthreads();
-                for (int b = tid; b < A; b += BLOCK) {
-                    const int cnt = s_bn[b];
-                    if (cnt == 0) continue;
-                    const float pbx = s_p[0][b], pby = s_p[1][b], pbz = s_p[2][b];
-                    // impulse and its moment summed in list order, then one
-                    // application of 1/m and the world inverse inertia
-                    float jx = 0.f, jy = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
+
+                if (nc > 0) {
+                    // ---- F: effective mass along each normal, relaxed by the larger
+                    //      contact count of the two bodies
+                    for (int c = tid; c < nc; c += BLOCK) {
+                        const int i = s_cij[c] & 0xFF, j = (s_cij[c] >> 8) & 0xFF;
+                        const f3 n = mk3(s_cn[0][c], s_cn[1][c], 0.f);
+                        const f3 pc = mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]);
+                        float Ri[9], Rj[9];
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) { Ri[q] = s_R[q][i]; Rj[q] = s_R[q][j]; }
+                        const f3 ri = sub3(pc, mk3(s_p[0][i], s_p[1][i], s_p[2][i]));
+                        const f3 rj = sub3(pc, mk3(s_p[0][j], s_p[1][j], s_p[2][j]));
+                        const f3 xi = cross3(ri, n), xj = cross3(rj, n);
+                        const float keff = 2.f * P.inv_mass + dot3(xi, inv_inertia(P, Ri, xi)) +
+                                           dot3(xj, inv_inertia(P, Rj, xj));
+                        const int nmax = max(s_bn[i], s_bn[j]);
+                        s_cwk[c] = 1.f / ((float)nmax * keff);
+                    }
+                    __syncthreads();
+                    // ---- G: Jacobi sweeps: every contact reads the previous sweep's
+                    //      velocities; each body then sums its contacts in list order
+                    for (int it = 0; it < P.jacobi_iters; ++it) {
+                        for (int c = tid; c < nc; c += BLOCK) {
+                            const int i = s_cij[c] & 0xFF, j = (s_cij[c] >> 8) & 0xFF;
+                            const f3 pc = mk3(s_cpc[0][c], s_cpc[1][c], s_cpc[2][c]);
+                            const f3 ri = sub3(pc, mk3(s_p[0][i], s_p[1][i], s_p[2][i]));
+                            const f3 rj = sub3(pc, mk3(s_p[0][j], s_p[1][j], s_p[2][j]));
+                            const f3 wi = cross3(mk3(s_w[0][i], s_w[1][i], s_w[2][i]), ri);
+                            const f3 wj = cross3(mk3(s_w[0][j], s_w[1][j], s_w[2][j]), rj);
+                            const float vn = ((s_v[0][j] + wj.x) - (s_v[0][i] + wi.x)) * s_cn[0][c] +
+                                             ((s_v[1][j] + wj.y) - (s_v[1][i] + wi.y)) * s_cn[1][c];
+                            const float lam = s_clam[c];
+                            const float lam1 = fmaxf(lam + s_cwk[c] * (-vn + s_cb[c]), 0.f);
+                            s_cdl[c] = lam1 - lam;
+                            s_clam[c] = lam1;
+                        }
+                        __syncthreads();
+                        for (int b = tid; b < A; b += BLOCK) {
+                            const int cnt = s_bn[b];
+                            if (cnt == 0) continue;
+                            const float pbx = s_p[0][b], pby = s_p[1][b], pbz = s_p[2][b];
+                            // impulse and its moment summed in list order, then one
+                            // application of 1/m and the world inverse inertia
+                            float jx = 0.f, jy = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
 #pragma unroll 4
-                    for (int q = 0; q < cnt; ++q) {
-                        const int c = s_bl[b][q];
-                        const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? s_cdl[c] : -s_cdl[c];
-                        const float Jx = dl * s_cn[0][c], Jy = dl * s_cn[1][c];
-                        const float rx = s_cpc[0][c] - pbx, ry = s_cpc[1][c] - pby, rz = s_cpc[2][c] - pbz;
-                        jx += Jx;
-                        jy += Jy;
-                        tx -= rz * Jy;
-                        ty += rz * Jx;
-                        tz += rx * Jy - ry * Jx;
+                            for (int q = 0; q < cnt; ++q) {
+                                const int c = s_bl[b][q];
+                                const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? s_cdl[c] : -s_cdl[c];
+                                const float Jx = dl * s_cn[0][c], Jy = dl * s_cn[1][c];
+                                const float rx = s_cpc[0][c] - pbx, ry = s_cpc[1][c] - pby, rz = s_cpc[2][c] - pbz;
+                                jx += Jx;
+                                jy += Jy;
+                                tx -= rz * Jy;
+                                ty += rz * Jx;
+                                tz += rx * Jy - ry * Jx;
+                            }
+                            s_v[0][b] += jx * P.inv_mass;
+                            s_v[1][b] += jy * P.inv_mass;
+                            s_w[0][b] += s_iw[0][b] * tx + s_iw[1][b] * ty + s_iw[2][b] * tz;
+                            s_w[1][b] += s_iw[1][b] * tx + s_iw[3][b] * ty + s_iw[4][b] * tz;
+                            s_w[2][b] += s_iw[2][b] * tx + s_iw[4][b] * ty + s_iw[5][b] * tz;
+                        }
+                        __syncthreads();
                     }
-                    s_v[0][b] += jx * P.inv_mass;
-                    s_v[1][b] += jy * P.inv_mass;
-                    s_w[0][b] += s_iw[0][b] * tx + s_iw[1][b] * ty + s_iw[2][b] * tz;
-                    s_w[1][b] += s_iw[1][b] * tx + s_iw[3][b] * ty + s_iw[4][b] * tz;
-                    s_w[2][b] += s_iw[2][b] * tx + s_iw[4][b] * ty + s_iw[5][b] * tz;
+                }
+
+                // ---- H: positions and orientations
+                for (int i = tid; i < A; i += BLOCK) {
+                    if (!s_act[i]) continue;
+                    const float vx = s_v[0][i], vy = s_v[1][i], vz = s_v[2][i];
+                    s_p[0][i] += h * vx;
+                    s_p[1][i] += h * vy;
+                    s_p[2][i] += h * vz;
+                    float qw = s_q[0][i], qx = s_q[1][i], qy = s_q[2][i], qz = s_q[3][i];
+                    const float wx = s_w[0][i], wy = s_w[1][i], wz = s_w[2][i];
+                    const float dw = -(wx * qx + wy * qy + wz * qz);
+                    const float dx = wx * qw + (wy * qz - wz * qy);
+                    const float dy = wy * qw + (wz * qx - wx * qz);
+                    const float dz = wz * qw + (wx * qy - wy * qx);
+                    qw += 0.5f * h * dw; qx += 0.5f * h * dx; qy += 0.5f * h * dy; qz += 0.5f * h * dz;
+                    const float L = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+                    s_q[0][i] = qw / L; s_q[1][i] = qx / L; s_q[2][i] = qy / L; s_q[3][i] = qz / L;
                 }
                 __syncthreads();
             }
-        }
 
-        // ---- H: positions and orientations
-        for (int i = tid; i < A; i += BLOCK) {
-            if (!s_act[i]) continue;
-            const float vx = s_v[0][i], vy = s_v[1][i], vz = s_v[2][i];
-            s_p[0][i] += h * vx;
-            s_p[1][i] += h * vy;
-            s_p[2][i] += h * vz;
-            float qw = s_q[0][i], qx = s_q[1][i], qy = s_q[2][i], qz = s_q[3][i];
-            const float wx = s_w[0][i], wy = s_w[1][i], wz = s_w[2][i];
-            const float dw = -(wx * qx + wy * qy + wz * qz);
-            const float dx = wx * qw + (wy * qz - wz * qy);
-            const float dy = wy * qw + (wz * qx - wx * qz);
-            const float dz = wz * qw + (wx * qy - wy * qx);
-            qw += 0.5f * h * dw; qx += 0.5f * h * dx; qy += 0.5f * h * dy; qz += 0.5f * h * dz;
-            const float L = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-            s_q[0][i] = qw / L; s_q[1][i] = qx / L; s_q[2][i] = qy / L; s_q[3][i] = qz / L;
-        }
-        __syncthreads();
-    }
-
-    // ---- events, reward, termination, write-back (Sec. "Reward Design Details")
-    for (int i = tid; i < A; i += BLOCK) {
-        const int n = a0 + i;
-        if (!s_act[i]) {
-            reward[n] = 0.f;
-            done[n] = 0;
-            events[n] = 0;
-            continue;
-        }
-        float dyn[SF_F_MU];
-        for (int c = 0; c < 3; ++c) {
-            dyn[SF_F_PX + c] = s_p[c][i];
-            dyn[SF_F_VX + c] = s_v[c][i];
-            dyn[SF_F_WX + c] = s_w[c][i];
-        }
-        for (int c = 0; c < 4; ++c) {
-            dyn[SF_F_QW + c] = s_q[c][i];
-            dyn[SF_F_OM0 + c] = s_om[4 * i + c];
-        }
-        dyn[SF_F_STEER] = s_th[i];
-        dyn[SF_F_STEER_RATE] = s_thd[i];
-        bool finite = true;
-        for (int c = 0; c < SF_F_MU; ++c) {
-            st[c * N + n] = dyn[c];
-            finite = finite && isfinite(dyn[c]);
-        }
-        st[SF_F_MU * N + n] = s_muo[i];
-        uint32_t ev = 0;
-        if (!finite) {
-            ev = SF_EV_CRASH | SF_EV_NUMERIC;
-        } else {
-            const long long X = qpos(dyn[SF_F_PX]), Y = qpos(dyn[SF_F_PY]), Z = qpos(dyn[SF_F_PZ]);
-            const long long gx = X - qpos(st[SF_F_GOAL_X * N + n]), gy = Y - qpos(st[SF_F_GOAL_Y * N + n]);
-            if (gx * gx + gy * gy <= 3072ll * 3072ll) ev |= SF_EV_GOAL;
-            if (s_coll[i] && ist[SF_I_SINCE_SPAWN * N + n] >= P.warmup) ev |= SF_EV_COLLISION;
-            const long long sx = X - qpos(st[SF_F_START_X * N + n]), sy = Y - qpos(st[SF_F_START_Y * N + n]);
-            bool crash = sx * sx + sy * sy > 102400ll * 102400ll || Z < 0;
-            const long long qx = qquat(dyn[SF_F_QX]), qy = qquat(dyn[SF_F_QY]);
-            crash = crash || ((1ll << 28) - 2 * (qx * qx + qy * qy) < 40265318ll);
-            if (crash) ev |= SF_EV_CRASH;
-        }
-        if (s_nan[i]) ev |= SF_EV_NAN_ACTION;
-        const int ep = ist[SF_I_EP_STEP * N + n] + 1;
-        ist[SF_I_EP_STEP * N + n] = ep;
-        ist[SF_I_SINCE_SPAWN * N + n] += 1;
-        if (ep >= P.max_ep) ev |= SF_EV_TIMEOUT;
-        const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f : 0.f;
-        const bool term = (ev & (SF_EV_GOAL | SF_EV_COLLISION | SF_EV_CRASH)) != 0;
-        const bool dn = (term && !(P.flags & SF_INVINCIBLE)) || (ev & (SF_EV_TIMEOUT | SF_EV_NUMERIC));
-        reward[n] = r;
-        done[n] = dn;
-        events[n] = (uint8_t)ev;
-        if (dn) {
-            if (P.flags & SF_AUTO_RESET) {
-                ist[SF_I_EPISODE * N + n] += 1;
-                spawn_agent(P, Wd, st, ist, N, n, w, i);
-            } else {
-                // parked off-stage at x = 1000 m at rest (Sec. "Termination and time-out")
-                st[SF_F_PX * N + n] = 1000.f;
-                st[SF_F_PY * N + n] = 0.f;
-                st[SF_F_PZ * N + n] = P.z_ride;
-                st[SF_F_QW * N + n] = 1.f;
-                st[SF_F_QX * N + n] = 0.f;
-                st[SF_F_QY * N + n] = 0.f;
-                st[SF_F_QZ * N + n] = 0.f;
-                for (int c = SF_F_VX; c <= SF_F_MU; ++c) st[c * N + n] = 0.f;
-                ist[SF_I_ACTIVE * N + n] = 0;
+            // ---- events, reward, termination, write-back (Sec. "Reward Design Details")
+            for (int i = tid; i < A; i += BLOCK) {
+                const int n = a0 + i;
+                if (!s_act[i]) {
+                    reward[n] = 0.f;
+                    done[n] = 0;
+                    events[n] = 0;
+                    continue;
+                }
+                float dyn[SF_F_MU];
+                for (int c = 0; c < 3; ++c) {
+                    dyn[SF_F_PX + c] = s_p[c][i];
+                    dyn[SF_F_VX + c] = s_v[c][i];
+                    dyn[SF_F_WX + c] = s_w[c][i];
+                }
+                for (int c = 0; c < 4; ++c) {
+                    dyn[SF_F_QW + c] = s_q[c][i];
+                    dyn[SF_F_OM0 + c] = s_om[4 * i + c];
+                }
+                dyn[SF_F_STEER] = s_th[i];
+                dyn[SF_F_STEER_RATE] = s_thd[i];
+                bool finite = true;
+                for (int c = 0; c < SF_F_MU; ++c) {
+                    st[c * N + n] = dyn[c];
+                    finite = finite && isfinite(dyn[c]);
+                }
+                st[SF_F_MU * N + n] = s_muo[i];
+                uint32_t ev = 0;
+                if (!finite) {
+                    ev = SF_EV_CRASH | SF_EV_NUMERIC;
+                } else {
+                    const long long X = qpos(dyn[SF_F_PX]), Y = qpos(dyn[SF_F_PY]), Z = qpos(dyn[SF_F_PZ]);
+                    const long long gx = X - qpos(st[SF_F_GOAL_X * N + n]), gy = Y - qpos(st[SF_F_GOAL_Y * N + n]);
+                    if (gx * gx + gy * gy <= 3072ll * 3072ll) ev |= SF_EV_GOAL;
+                    if (s_coll[i] && ist[SF_I_SINCE_SPAWN * N + n] >= P.warmup) ev |= SF_EV_COLLISION;
+                    const long long sx = X - qpos(st[SF_F_START_X * N + n]), sy = Y - qpos(st[SF_F_START_Y * N + n]);
+                    bool crash = sx * sx + sy * sy > 102400ll * 102400ll || Z < 0;
+                    const long long qx = qquat(dyn[SF_F_QX]), qy = qquat(dyn[SF_F_QY]);
+                    crash = crash || ((1ll << 28) - 2 * (qx * qx + qy * qy) < 40265318ll);
+                    if (crash) ev |= SF_EV_CRASH;
+                }
+                if (s_nan[i]) ev |= SF_EV_NAN_ACTION;
+                const int ep = ist[SF_I_EP_STEP * N + n] + 1;
+                ist[SF_I_EP_STEP * N + n] = ep;
+                ist[SF_I_SINCE_SPAWN * N + n] += 1;
+                if (ep >= P.max_ep) ev |= SF_EV_TIMEOUT;
+                const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f : 0.f;
+                const bool term = (ev & (SF_EV_GOAL | SF_EV_COLLISION | SF_EV_CRASH)) != 0;
+                const bool dn = (term && !(P.flags & SF_INVINCIBLE)) || (ev & (SF_EV_TIMEOUT | SF_EV_NUMERIC));
+                reward[n] = r;
+                done[n] = dn;
+                events[n] = (uint8_t)ev;
+                if (dn) {
+                    if (P.flags & SF_AUTO_RESET) {
+                        ist[SF_I_EPISODE * N + n] += 1;
+                        spawn_agent(P, Wd, st, ist, N, n, w, i);
+                    } else {
+                        // parked off-stage at x = 1000 m at rest (Sec. "Termination and time-out")
+                        st[SF_F_PX * N + n] = 1000.f;
+                        st[SF_F_PY * N + n] = 0.f;
+                        st[SF_F_PZ * N + n] = P.z_ride;
+                        st[SF_F_QW * N + n] = 1.f;
+                        st[SF_F_QX * N + n] = 0.f;
+                        st[SF_F_QY * N + n] = 0.f;
+                        st[SF_F_QZ * N + n] = 0.f;
+                        for (int c = SF_F_VX; c <= SF_F_MU; ++c) st[c * N + n] = 0.f;
+                        ist[SF_I_ACTIVE * N + n] = 0;
+                    }
+                }
             }
-        }
+        } while (0);
+        if (!queue) break;
+        __syncthreads();   // the world's LDS is no longer read
+        if (tid == 0) s_item = atomicAdd(queue, 1) + (int)gridDim.x;
+        __syncthreads();
+        item = s_item;
+    }
+    // the last block out re-arms the queue for the next launch
+    if (queue && tid == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
+        queue[0] = 0;
+        queue[1] = 0;
     }
 }
 
 void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
                  const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
-                 int *rec_cnt, int rec_cap, const int *order, int block, hipStream_t s) {
+                 int *rec_cnt, int rec_cap, const int *order, int block, int grid, int *queue, hipStream_t s) {
     if (Wd.W == 0) return;
+    // a persistent grid pulls worlds from the queue; a full grid needs none
+    if (grid <= 0 || grid >= Wd.W) {
+        grid = Wd.W;
+        queue = nullptr;
+    }
     // the network's LDS copy leaves room for at most three wheel waves
     if (use_sur && block > 256) block = 256;
 #define SF_STEP_LAUNCH(B)                                                                                     \
     do {                                                                                                      \
         if (use_sur)                                                                                          \
-            k_step<B, true><<<Wd.W, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,      \
-                                               rec_cnt, rec_cap, order);                                      \
+            k_step<B, true><<<grid, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,       \
+                                               rec_cnt, rec_cap, order, queue);                               \
         else                                                                                                  \
-            k_step<B, false><<<Wd.W, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,     \
-                                                rec_cnt, rec_cap, order);                                     \
+            k_step<B, false><<<grid, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,      \
+                                                rec_cnt, rec_cap, order, queue);                              \
     } while (0)
     if (block <= 64) SF_STEP_LAUNCH(64);
     else if (block <= 128) SF_STEP_LAUNCH(128);
     else if (block <= 192) SF_STEP_LAUNCH(192);
     else if (block <= 256 || use_sur) SF_STEP_LAUNCH(256);
     else
-        k_step<320, false><<<Wd.W, 320, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec, rec_cnt,
-                                                rec_cap, order);
+        k_step<320, false><<<grid, 320, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec, rec_cnt,
+                                                rec_cap, order, queue);
 #undef SF_STEP_LAUNCH
 }
 

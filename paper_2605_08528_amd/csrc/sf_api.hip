@@ -32,6 +32,8 @@ struct sf_sim {
     int W = 0, N = 0, S = 0, max_agents = 0, P = 0, T = 0, E = 0, C = 0;
     uint32_t flags = 0;
     int step_block = 128, obs_waves = 4;
+    int step_grid = 0, cus = 256;  // persistent step: workgroups (0: one per world); compute units
+    int *queue = nullptr;          // [2] world counter and finished-workgroup counter
     DevParams P_dev{};
     DevWorld Wd{};
     float *st = nullptr;       // [NF][N]
@@ -272,6 +274,9 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     if (opts.grid_cell < 0.f || !std::isfinite(opts.grid_cell) || opts.tri_cell < 0.f ||
         !std::isfinite(opts.tri_cell))
         return fail(SF_E_INVALID_ARG, "grid_cell and tri_cell must be >= 0");
+    if (opts.step_block < 0 || opts.step_block > 320 || opts.step_grid < 0 ||
+        opts.obs_waves < 0 || opts.obs_waves > 4 || opts.policy_rows < 0 || opts.policy_rows > 64)
+        return fail(SF_E_INVALID_ARG, "launch shape out of range");
 
     sf_sim *sim = new sf_sim();
     sim->stream = (hipStream_t)opts.stream;
@@ -286,6 +291,13 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
                                           : std::min(320, 64 * ((4 * std::max(amax, 1) + 63) / 64) + 64);
     sim->obs_waves = opts.obs_waves > 0 ? opts.obs_waves : 4;
     sim->policy_rows = opts.policy_rows > 0 ? opts.policy_rows : 16;
+    sim->step_grid = opts.step_grid;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&sim->cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (sim->cus <= 0) sim->cus = 256;
+    }
     sim->steer_max = p->steer_max;
     hipStream_t st = sim->stream;
 
@@ -488,6 +500,8 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost(a) > cost(b); });
     ALLOC(sim->order, int, W);
     H2D(sim->order, ord.data(), sizeof(int) * W);
+    ALLOC(sim->queue, int, 2);
+    DEV(hipMemsetAsync(sim->queue, 0, 2 * sizeof(int), st));
     if (opts.flags & SF_RECORD_CONTACTS) {
         sim->rec_cap = std::max(1, amax * (amax - 1) / 2);
         ALLOC(sim->rec, uint32_t, (size_t)SF_MAX_SUBSTEPS * W * sim->rec_cap);
@@ -550,7 +564,7 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         Su.log_base = sim->sur_log_base;
         launch_step(sim->P_dev, sim->Wd, Su, sim->sur_on, sim->st, sim->ist, d_actions, h, substeps, sim->reward,
                     sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->order, sim->step_block,
-                    sim->stream);
+                    sim->step_grid, sim->queue, sim->stream);
         if (sim->sur_log)
             sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;
     }
@@ -1023,6 +1037,182 @@ sf_status sf_debug_obs_indices(sf_sim *sim, int32_t *h_out) {
     DEV(hipMemcpyAsync(h_out, buf, sizeof(int) * 72 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream));
     DEV(hipStreamSynchronize(sim->stream));
     DEV(hipFree(buf));
+    return SF_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+static const int k_step_blocks[] = {64, 128, 192, 256, 320};
+
+static bool tuning_ok(const sf_tuning &t) {
+    bool blk = false;
+    for (int b : k_step_blocks) blk = blk || t.step_block == b;
+    return blk && t.step_grid >= 0 &&
+           (t.obs_waves == 1 || t.obs_waves == 2 || t.obs_waves == 4) &&
+           (t.policy_rows == 16 || t.policy_rows == 32 || t.policy_rows == 64);
+}
+
+static void tuning_apply(sf_sim *sim, const sf_tuning &t) {
+    sim->step_block = t.step_block;
+    sim->step_grid = t.step_grid;
+    sim->obs_waves = t.obs_waves;
+    sim->policy_rows = t.policy_rows;
+}
+
+sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out) {
+    CHECK_SIM(sim);
+    if (!out) return fail(SF_E_INVALID_ARG, "out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->step_block = sim->step_block;
+    out->step_grid = sim->step_grid;
+    out->obs_waves = sim->obs_waves;
+    out->policy_rows = sim->policy_rows;
+    return SF_OK;
+}
+
+sf_status sf_set_tuning(sf_sim *sim, const sf_tuning *t) {
+    CHECK_SIM(sim);
+    if (!t || !tuning_ok(*t))
+        return fail(SF_E_INVALID_ARG, "step_block in {64,128,192,256,320}, step_grid >= 0, obs_waves 1/2/4, "
+                                      "policy_rows 16/32/64");
+    tuning_apply(sim, *t);
+    return SF_OK;
+}
+
+sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, const char *cache_path,
+                      sf_tuning *out) {
+    CHECK_SIM(sim);
+    if (!out) return fail(SF_E_INVALID_ARG, "out is NULL");
+    if (substeps < 1 || substeps > SF_MAX_SUBSTEPS || !(dt > 0.f) || !std::isfinite(dt))
+        return fail(SF_E_INVALID_ARG, "bad dt or substeps");
+    if (steps < 1 || steps > 10000) return fail(SF_E_INVALID_ARG, "steps must be 1..10000");
+    sf_get_tuning(sim, out);
+    if (sim->N == 0) return SF_OK;
+    // the workload's signature
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    DEV(hipGetDevice(&dev));
+    DEV(hipGetDeviceProperties(&prop, dev));
+    char sig[256];
+    std::snprintf(sig, sizeof(sig), "W%d N%d A%d P%d T%d S%d %s/%dcu", sim->W, sim->N, sim->max_agents, sim->P,
+                  sim->T, (int)substeps, prop.gcnArchName, sim->cus);
+    std::vector<std::string> lines;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char buf[512];
+            while (std::fgets(buf, sizeof(buf), f)) {
+                std::string l(buf);
+                while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+                if (l.empty()) continue;
+                const size_t bar = l.find(" | ");
+                if (bar != std::string::npos && l.compare(0, bar, sig) == 0) {
+                    sf_tuning t{};
+                    if (std::sscanf(l.c_str() + bar + 3, "%d %d %d %d", &t.step_block, &t.step_grid, &t.obs_waves,
+                                    &t.policy_rows) == 4 &&
+                        tuning_ok(t)) {
+                        std::fclose(f);
+                        tuning_apply(sim, t);
+                        *out = t;
+                        return SF_OK;
+                    }
+                    continue;  // a malformed entry is replaced
+                }
+                lines.push_back(l);
+            }
+            std::fclose(f);
+        }
+    }
+    // snapshot of state and step outputs; trials start from it
+    const size_t sb = sf_state_bytes(sim), N = sim->N;
+    char *snap = (char *)dev_alloc(sim, sb + 6 * N);
+    float *zero_act = sim->policy_loaded ? nullptr : (float *)dev_alloc(sim, sizeof(float) * 2 * N);
+    if (!snap || (!sim->policy_loaded && !zero_act)) return fail(SF_E_OUT_OF_MEMORY, "autotune snapshot");
+    hipStream_t st = sim->stream;
+    DEV(hipMemcpyAsync(snap, sim->st, sb, hipMemcpyDeviceToDevice, st));
+    DEV(hipMemcpyAsync(snap + sb, sim->reward, 4 * N, hipMemcpyDeviceToDevice, st));
+    DEV(hipMemcpyAsync(snap + sb + 4 * N, sim->done, N, hipMemcpyDeviceToDevice, st));
+    DEV(hipMemcpyAsync(snap + sb + 5 * N, sim->events, N, hipMemcpyDeviceToDevice, st));
+    if (zero_act) DEV(hipMemsetAsync(zero_act, 0, sizeof(float) * 2 * N, st));
+    float *log_keep = sim->sur_log;
+    sim->sur_log = nullptr;  // trials write no training samples
+    const bool prof_keep = sim->prof;
+    auto restore = [&]() -> sf_status {
+        DEV(hipMemcpyAsync(sim->st, snap, sb, hipMemcpyDeviceToDevice, st));
+        DEV(hipMemcpyAsync(sim->reward, snap + sb, 4 * N, hipMemcpyDeviceToDevice, st));
+        DEV(hipMemcpyAsync(sim->done, snap + sb + 4 * N, N, hipMemcpyDeviceToDevice, st));
+        DEV(hipMemcpyAsync(sim->events, snap + sb + 5 * N, N, hipMemcpyDeviceToDevice, st));
+        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, st);
+        LAUNCHED();
+        return SF_OK;
+    };
+    // mean durations [policy, step, obs] of `steps` control steps of shape t
+    auto trial = [&](const sf_tuning &t, double *ms) -> sf_status {
+        tuning_apply(sim, t);
+        sf_status r;
+        if ((r = restore()) != SF_OK) return r;
+        if ((r = sf_profile(sim, 1)) != SF_OK) return r;
+        for (int k = 0; k < steps; ++k) {
+            r = zero_act ? sf_step(sim, zero_act, dt, substeps) : sf_step_policy(sim, dt, substeps);
+            if (r != SF_OK) return r;
+        }
+        double tot[SF_PROF_KERNELS];
+        int32_t cnt[SF_PROF_KERNELS];
+        if ((r = sf_profile_read(sim, tot, cnt)) != SF_OK) return r;
+        for (int k = 0; k < 3; ++k) ms[k] = cnt[k] ? tot[k] / cnt[k] : 0.0;
+        return sf_profile(sim, 0);
+    };
+    sf_tuning best = *out;
+    double ms[3], best_ms[3] = {1e30, 1e30, 1e30};
+    sf_status r = SF_OK;
+    // step shapes (a persistent grid matters only when it is smaller than W)
+    for (int b : k_step_blocks) {
+        for (int g : {0, 1, 2, 4}) {
+            if (g > 0 && g * sim->cus >= sim->W) continue;
+            sf_tuning t = best;
+            t.step_block = b;
+            t.step_grid = g * sim->cus;
+            if ((r = trial(t, ms)) != SF_OK) break;
+            if (ms[1] < best_ms[1]) { best_ms[1] = ms[1]; best.step_block = b; best.step_grid = t.step_grid; }
+        }
+        if (r != SF_OK) break;
+    }
+    for (int wv : {1, 2, 4}) {
+        if (r != SF_OK) break;
+        sf_tuning t = best;
+        t.obs_waves = wv;
+        if ((r = trial(t, ms)) != SF_OK) break;
+        if (ms[2] < best_ms[2]) { best_ms[2] = ms[2]; best.obs_waves = wv; }
+    }
+    for (int rows : {16, 32, 64}) {
+        if (r != SF_OK || !sim->policy_loaded) break;
+        sf_tuning t = best;
+        t.policy_rows = rows;
+        if ((r = trial(t, ms)) != SF_OK) break;
+        if (ms[0] < best_ms[0]) { best_ms[0] = ms[0]; best.policy_rows = rows; }
+    }
+    sim->sur_log = log_keep;
+    sim->prof = prof_keep;
+    tuning_apply(sim, best);
+    if (r == SF_OK) r = restore();
+    if (r == SF_OK) {
+        DEV(hipStreamSynchronize(st));
+        dev_free(sim, snap);
+        dev_free(sim, zero_act);
+    }
+    if (r != SF_OK) return r;
+    best.step_us = (float)(1e3 * best_ms[1]);
+    best.obs_us = (float)(1e3 * best_ms[2]);
+    best.policy_us = sim->policy_loaded ? (float)(1e3 * best_ms[0]) : 0.f;
+    *out = best;
+    if (cache_path) {
+        char line[512];
+        std::snprintf(line, sizeof(line), "%s | %d %d %d %d", sig, best.step_block, best.step_grid, best.obs_waves,
+                      best.policy_rows);
+        lines.push_back(line);
+        FILE *f = std::fopen(cache_path, "w");
+        if (!f) return fail(SF_E_INVALID_ARG, std::string("cannot write ") + cache_path);
+        for (auto &l : lines) std::fprintf(f, "%s\n", l.c_str());
+        std::fclose(f);
+    }
     return SF_OK;
 }
 

@@ -63,7 +63,7 @@ class Options(C.Structure):
         ("max_episode_steps", C.c_int32), ("collision_warmup", C.c_int32),
         ("flags", C.c_uint32), ("grid_cell", C.c_float),
         ("step_block", C.c_int32), ("obs_waves", C.c_int32), ("policy_rows", C.c_int32),
-        ("tri_cell", C.c_float), ("reserved", C.c_int32 * 4),
+        ("tri_cell", C.c_float), ("step_grid", C.c_int32), ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -79,6 +79,15 @@ class SurTrainOpts(C.Structure):
         ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
         ("seed", C.c_uint64), ("init_seed", C.c_uint64), ("set_envelope", C.c_int32),
     ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("step_block", C.c_int32), ("step_grid", C.c_int32), ("obs_waves", C.c_int32),
+                ("policy_rows", C.c_int32), ("step_us", C.c_float), ("obs_us", C.c_float),
+                ("policy_us", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SFError(RuntimeError):
@@ -130,6 +139,9 @@ def lib():
         L.sf_sur_get.argtypes = [vp, vp, vp, vp]
         L.sf_sur_enable.argtypes = [vp, i32]
         L.sf_sur_counts.argtypes = [vp, vp, i32]
+        L.sf_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.sf_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.sf_autotune.argtypes = [vp, C.c_float, i32, i32, C.c_char_p, C.POINTER(Tuning)]
         L.sf_status_str.argtypes = [st]
         L.sf_status_str.restype = C.c_char_p
         L.sf_last_error.restype = C.c_char_p
@@ -139,7 +151,8 @@ def lib():
                      "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
                      "sf_graph_launch", "sf_profile", "sf_profile_read", "sf_sur_log", "sf_sur_collect",
                      "sf_sur_train", "sf_sur_gradient", "sf_sur_predict", "sf_sur_evaluate", "sf_sur_set",
-                     "sf_sur_get", "sf_sur_enable", "sf_sur_counts"):
+                     "sf_sur_get", "sf_sur_enable", "sf_sur_counts", "sf_get_tuning", "sf_set_tuning",
+                     "sf_autotune"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -180,7 +193,7 @@ class Sim:
 
     def __init__(self, worlds, params: dict, flags: int = 0, stream=None, grid_cell: float = 0.0,
                  step_block: int = 0, obs_waves: int = 0, policy_rows: int = 0,
-                 tri_cell: float = 0.0, torch_alloc: bool = True):
+                 tri_cell: float = 0.0, step_grid: int = 0, torch_alloc: bool = True):
         import torch
         L = lib()
         self.torch = torch
@@ -221,6 +234,7 @@ class Sim:
         o.obs_waves = int(obs_waves)
         o.policy_rows = int(policy_rows)
         o.tri_cell = float(tri_cell)
+        o.step_grid = int(step_grid)
         # device memory from torch's caching allocator
         self._blocks = {}
         if torch_alloc:
@@ -423,3 +437,20 @@ class Sim:
         out = np.zeros(2, np.uint64)
         check(lib().sf_sur_counts(self.h, _ptr(out), int(bool(reset))), "sf_sur_counts")
         return int(out[0]), int(out[1])
+
+    # launch shapes ------------------------------------------------------
+    def tuning(self) -> dict:
+        t = Tuning()
+        check(lib().sf_get_tuning(self.h, C.byref(t)), "sf_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, step_block: int, step_grid: int, obs_waves: int, policy_rows: int) -> None:
+        t = Tuning(int(step_block), int(step_grid), int(obs_waves), int(policy_rows), 0.0, 0.0, 0.0)
+        check(lib().sf_set_tuning(self.h, C.byref(t)), "sf_set_tuning")
+
+    def autotune(self, dt: float, substeps: int, steps: int = 20, cache_path: str | None = None) -> dict:
+        t = Tuning()
+        path = cache_path.encode() if cache_path else None
+        check(lib().sf_autotune(self.h, C.c_float(dt), int(substeps), int(steps), path, C.byref(t)),
+              "sf_autotune")
+        return t.as_dict()

@@ -118,6 +118,8 @@ def test_calls_on_null_handle(L):
         assert getattr(L, name)(None, 0) == 1
     assert L.sf_sur_counts(None, None, 0) == 1
     assert L.sf_sur_set(None, None, None, None) == 1
+    assert L.sf_get_tuning(None, None) == 1 and L.sf_set_tuning(None, None) == 1
+    assert L.sf_autotune(None, C.c_float(0.1), 1, 1, None, None) == 1
 
 
 def test_struct_layouts_match_the_header(tmp_path):
@@ -130,12 +132,13 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"sf_vehicle_params": sf.VehicleParams, "sf_world_desc": sf.WorldDesc,
-               "sf_options": sf.Options, "sf_sur_train_opts": sf.SurTrainOpts}
+               "sf_options": sf.Options, "sf_sur_train_opts": sf.SurTrainOpts, "sf_tuning": sf.Tuning}
     header_fields = {
         "sf_vehicle_params": ["mass", "inertia", "wheel_radius", "mount", "jacobi_iters", "slop"],
         "sf_world_desc": ["num_worlds", "agent_offsets", "num_surfaces", "spawn", "seed"],
-        "sf_options": ["stream", "alloc", "max_episode_steps", "flags", "tri_cell", "reserved"],
+        "sf_options": ["stream", "alloc", "max_episode_steps", "flags", "tri_cell", "step_grid", "reserved"],
         "sf_sur_train_opts": ["steps", "batch", "lr", "eps", "seed", "init_seed", "set_envelope"],
+        "sf_tuning": ["step_block", "step_grid", "obs_waves", "policy_rows", "step_us", "policy_us"],
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sf.h"', "int main(void) {"]
     for s, fields in header_fields.items():
