@@ -52,16 +52,18 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, n_agents: int):
+def recorded_traffic(kernel: str, launch_name: str, n_agents: int):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     record (scaled by the copy-kernel calibration), or None when the kernel
-    source changed since the counters were taken or the shape differs."""
+    source changed since the counters were taken, or the launch shape or the
+    workload size differs."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     k = rec.get("kernels", {}).get(kernel)
-    if not k or k.get("source_hash") != kernel_source_hash(kernel) or k.get("agents") != n_agents:
+    if (not k or k.get("source_hash") != kernel_source_hash(kernel) or k.get("agents") != n_agents
+            or k.get("launch") != launch_name):
         return None
     return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
 
@@ -94,6 +96,31 @@ def cpu_baseline(worlds, prm, dt, S, policy, seconds, max_worlds=16):
             "kind": "oracle",
             "sample": f"first {sub.num_worlds} worlds ({orc.N} agents) of the same workload, "
                       f"{n} control steps (observe, policy, step), FP64 brute force"}
+
+
+def trajectory_error(sim, torch, sf, dt, S, steps):
+    """Position difference between the plain and the network step after
+    `steps` control steps from the same state under the same seeded
+    open-loop actions, over agents that neither run reset."""
+    from paper_2605_08528_amd import inputs as I
+    f0, k0 = sim.get_state()
+    acts = [torch.from_numpy(I.actions(7, t, sim.N)).cuda() for t in range(steps)]
+    ends = []
+    for on in (False, True):
+        sim.set_state(f0, k0)
+        sim.sur_enable(on)
+        for a in acts:
+            sim.step(a, dt, S)
+        torch.cuda.synchronize()
+        ends.append(sim.get_state())
+    sim.sur_enable(False)
+    sim.set_state(f0, k0)
+    (fa, ka), (fb, kb) = ends
+    same = (ka[3] == k0[3]) & (kb[3] == k0[3]) & (k0[0] == 1)   # same episode, active at the start
+    d = np.hypot(fa[0] - fb[0], fa[1] - fb[1])[same]
+    moved = np.hypot(fa[0] - f0[0], fa[1] - f0[1])[same]
+    return {"agents": int(same.sum()), "mean_m": float(d.mean()), "p95_m": float(np.percentile(d, 95)),
+            "max_m": float(d.max()), "mean_path_m": float(moved.mean())}
 
 
 def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
@@ -144,6 +171,7 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     used, fb = sim.sur_counts(reset=True)
     sim.sur_enable(False)
     casps = N * steps / (ms / 1e3)
+    traj = trajectory_error(sim, torch, sf, dt, S, 200)
     log(f"surrogate step: {ms / steps:.4f} ms/step, {casps:.4g} CASPS, network on "
         f"{used / max(1, used + fb):.3f} of in-domain wheel-substeps")
     return {
@@ -153,6 +181,7 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
         "force_error_mean": err_mean, "force_error_p95": err_p95, "force_error_untrained": untrained[0],
         "train_samples": int(split), "test_samples": int(M - split), "adam_steps": n_adam,
         "batch": 8192, "train_seconds": t_train, "last_loss": loss,
+        "trajectory_error_200": traj,
         "note": "force error = |d(Fx,Fy)| / max(|(Fx,Fy)|, 0.05 mu Fz) against the plain tire model "
                 "on held-out samples (the last 10% of the logged steps)",
     }
@@ -174,6 +203,8 @@ def main():
     ap.add_argument("--obs-waves", type=int, default=0)
     ap.add_argument("--step-block", type=int, default=0)
     ap.add_argument("--policy-rows", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step shards by "
@@ -200,6 +231,11 @@ def main():
         for _ in range(args.warmup):
             sim.step_policy(dt, S)
         torch.cuda.synchronize()
+        # launch shapes measured on this workload (state restored afterwards)
+        tuning = sim.tuning()
+        if not args.no_autotune:
+            tuning = sim.autotune(dt, S, steps=args.tune_steps)
+            log(f"autotuned: {tuning}")
 
         # ---- timed region: K policy-driven control steps, per-kernel events
         sim.profile(True)
@@ -259,8 +295,12 @@ def main():
         roof = {"bound": "hbm", "achieved": per * N / avg_s / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = {"policy": "k_policy", "step": "k_step", "obs": "k_obs"}[dom]
-    roof["traffic"] = recorded_traffic(roof["kernel"], N)
+    launch = {"policy": f"k_policy<{tuning['policy_rows']}>",
+              "step": f"k_step<{tuning['step_block']}, false>",
+              "obs": f"k_obs<{tuning['obs_waves']}>"}
+    roof["kernel"] = launch[dom]
+    roof["traffic"] = recorded_traffic({"policy": "k_policy", "step": "k_step", "obs": "k_obs"}[dom],
+                                       launch[dom], N)
     for name in kernels:
         if name == "policy":
             kernels[name]["tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
@@ -293,6 +333,7 @@ def main():
                         "plain tire, policy MLP 256-256-256-2 bf16/fp32-acc",
             "step": "policy + physics step + observation (eager launches)",
             "active_agents": active,
+            "launch_shapes": {k: tuning[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows")},
         },
         "roofline": roof,
         "cpu_baseline": cpu,

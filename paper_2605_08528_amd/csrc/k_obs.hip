@@ -98,11 +98,107 @@ __device__ unsigned long long kth_smallest(const unsigned long long kv[KPL], int
     return ilo;
 }
 
+// Keep the 64 smallest of nc > 64 distinct buffered keys (nc == 64: keep
+// all); returns the largest kept key.
+__device__ unsigned long long keep64(unsigned long long *cand, int &nc) {
+    const int lane = threadIdx.x & 63;
+    wave_sync();
+    unsigned long long kv[KPL];
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+        const int slot = lane + 64 * t;
+        kv[t] = slot < nc ? cand[slot] : ~0ull;
+    }
+    if (nc == 64) return wave_max_u64(kv[0]);
+    const unsigned long long k64 = kth_smallest(kv, 64, (nc + 63) >> 6);
+    wave_sync();
+    int keep = 0;
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+        const bool f = kv[t] <= k64;
+        const unsigned long long bal = __ballot(f);
+        if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
+        keep += __popcll(bal);
+    }
+    nc = keep;
+    wave_sync();
+    return k64;
+}
+
+// the smallest key above every point closer than r metres (quantised)
+__device__ __forceinline__ unsigned long long hint_key(float r) {
+    const double rq = (double)r * 1024.0 + 1.0;
+    return ((unsigned long long)sat_key((long long)(rq * rq) + 1) << 20) | 0xFFFFFull;
+}
+
+// Append to the candidate buffer the keys below kthr of every point of the
+// segments seg(j, s, e), j < nseg (each lane fills the point range [s, e) of
+// its segment, or leaves it empty), flattened across the wave and loaded in
+// batches of BATCH points per lane; a full buffer is first cut to its 64
+// best, which also lowers kthr.
+template <class SEG>
+__device__ __forceinline__ void gather(int nseg, SEG seg, const int4 *__restrict__ pts, int QX, int QY,
+                                       unsigned long long *cand, int *segs, int *segp, int &nc,
+                                       unsigned long long &kthr) {
+    const int lane = threadIdx.x & 63;
+    for (int sb = 0; sb < nseg; sb += 64) {
+        int s = 0, e = 0;
+        if (sb + lane < nseg) seg(sb + lane, s, e);
+        const int len = e - s;
+        int incl = len;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y2 = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y2;
+        }
+        const int total = __shfl(incl, 63, 64);
+        if (total == 0) continue;
+        segs[lane] = s;
+        segp[lane] = incl - len;
+        wave_sync();
+        // all loads of a batch are issued before any key is appended
+        for (int f0 = 0; f0 < total; f0 += 64 * BATCH) {
+            const int nslot = min(BATCH, (total - f0 + 63) >> 6);
+            if (nc + 64 * nslot > SF_CAND_CAP) kthr = keep64(cand, nc);
+            int4 pq[BATCH];
+#pragma unroll
+            for (int t = 0; t < BATCH; ++t) {
+                const int f = f0 + 64 * t + lane;
+                pq[t] = make_int4(0, 0, 0, -1);
+                if (t < nslot && f < total) {
+                    // the segment holding flat index f: the last one whose
+                    // prefix is <= f (it is never empty)
+                    int lo = 0, hi = min(63, nseg - 1 - sb);
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (segp[mid] <= f) lo = mid; else hi = mid - 1;
+                    }
+                    pq[t] = pts[segs[lo] + (f - segp[lo])];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < BATCH; ++t) {
+                if (t >= nslot) break;
+                unsigned long long key = ~0ull;
+                if (pq[t].w == 0) {
+                    const long long dx = (long long)pq[t].x - QX, dy = (long long)pq[t].y - QY;
+                    key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 20) | (unsigned)pq[t].z;
+                }
+                const bool has = key < kthr;
+                const unsigned long long bal = __ballot(has);
+                if (has) cand[nc + __popcll(bal & lane_lt())] = key;
+                nc += __popcll(bal);
+            }
+        }
+        wave_sync();
+    }
+}
+
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
                                                    const float *__restrict__ st,
                                                    const int *__restrict__ ist,
-                                                   float *__restrict__ obs, int *__restrict__ dbg) {
+                                                   float *__restrict__ obs, int *__restrict__ dbg,
+                                                   float4 *__restrict__ hint) {
     __shared__ unsigned long long s_cand[WAVES][SF_CAND_CAP];
     __shared__ float s_row[WAVES][SF_OBS_DIM];
     __shared__ int s_sel[WAVES][64];
@@ -121,28 +217,49 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
     unsigned long long *cand = s_cand[wv];
     float4 *dst = reinterpret_cast<float4 *>(obs + (size_t)n * SF_OBS_DIM);
 
-    if (!ist[SF_I_ACTIVE * N + n]) {
+    // the loads that depend only on the agent go out together, then the
+    // world's (each group is one memory round trip)
+    const int active = ist[SF_I_ACTIVE * N + n];
+    const int w = Wd.world_of[n];
+    const float px = st[SF_F_PX * N + n], py = st[SF_F_PY * N + n];
+    const float qw = st[SF_F_QW * N + n], qx = st[SF_F_QX * N + n];
+    const float qy = st[SF_F_QY * N + n], qz = st[SF_F_QZ * N + n];
+    const float vx = st[SF_F_VX * N + n], vy = st[SF_F_VY * N + n];
+    const float goal_x = st[SF_F_GOAL_X * N + n], goal_y = st[SF_F_GOAL_Y * N + n];
+    const float mu_seen = st[SF_F_MU * N + n];
+    const float4 hv = hint[n];
+    const int a0 = Wd.aoff[w], A = Wd.aoff[w + 1] - a0;
+    const int r0 = Wd.roff[w], PW = Wd.roff[w + 1] - r0;
+    const GridHdr g = Wd.grid[w];
+    if (!active) {
         dst[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (dbg) dbg[(size_t)n * 72 + lane] = -1;
         if (dbg && lane < 8) dbg[(size_t)n * 72 + 64 + lane] = -1;
         return;
     }
-    const int w = Wd.world_of[n];
-    const float px = st[SF_F_PX * N + n], py = st[SF_F_PY * N + n];
-    const float qw = st[SF_F_QW * N + n], qx = st[SF_F_QX * N + n];
-    const float qy = st[SF_F_QY * N + n], qz = st[SF_F_QZ * N + n];
+    // the agent's road-grid cell and the first ring that holds points
+    int cx = (int)floorf((px - g.x0) * g.inv_cell);
+    int cy = (int)floorf((py - g.y0) * g.inv_cell);
+    cx = max(0, min(cx, g.nx - 1));
+    cy = max(0, min(cy, g.ny - 1));
+    const int rr_first = PW > 0 ? Wd.pt_occ[g.cbase + cy * g.nx + cx] : 0;
     float hx = 1.f - 2.f * (qy * qy + qz * qz), hy = 2.f * (qx * qy + qw * qz);
     {
         float L = sqrtf(hx * hx + hy * hy);
         if (L < 1e-12f) { hx = 1.f; hy = 0.f; } else { hx /= L; hy /= L; }
     }
-    const float vx = st[SF_F_VX * N + n], vy = st[SF_F_VY * N + n];
+    // The 64th road distance of this agent's previous observation, grown by
+    // the distance moved since, bounds this one (triangle inequality), so
+    // cells and points beyond it are skipped from the start.  No bound yet:
+    // not a number.
+    const float rhint = hv.z == hv.z ? hv.z + sqrtf((px - hv.x) * (px - hv.x) + (py - hv.y) * (py - hv.y)) + 0.01f
+                                     : INFINITY;
     for (int k = lane; k < SF_OBS_DIM; k += 64) row[k] = 0.f;
     wave_sync();
 
     // ---- ego: goal in the body frame, heading error, distance, velocity, mu
     if (lane < 8) {
-        const float gx = st[SF_F_GOAL_X * N + n] - px, gy = st[SF_F_GOAL_Y * N + n] - py;
+        const float gx = goal_x - px, gy = goal_y - py;
         const float gbx = hx * gx + hy * gy, gby = -hy * gx + hx * gy;
         const float dist = sqrtf(gx * gx + gy * gy);
         float e;
@@ -154,7 +271,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
             case 4: e = dist / 100.f; break;
             case 5: e = (hx * vx + hy * vy) / 10.f; break;
             case 6: e = (-hy * vx + hx * vy) / 10.f; break;
-            default: e = st[SF_F_MU * N + n]; break;
+            default: e = mu_seen; break;
         }
         row[lane] = e;
     }
@@ -162,7 +279,6 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
 
     // ---- neighbours: 8 nearest other active agents of the world
     {
-        const int a0 = Wd.aoff[w], A = Wd.aoff[w + 1] - a0;
         unsigned long long key = ~0ull;
         if (lane < A) {
             const int m = a0 + lane;
@@ -223,14 +339,8 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
     }
 
     // ---- road: exact 64 nearest points by (quantised squared distance, index)
-    const int r0 = Wd.roff[w], PW = Wd.roff[w + 1] - r0;
     int my_idx = 0x7fffffff;
     if (PW > 0) {
-        const GridHdr g = Wd.grid[w];
-        int cx = (int)floorf((px - g.x0) * g.inv_cell);
-        int cy = (int)floorf((py - g.y0) * g.inv_cell);
-        cx = max(0, min(cx, g.nx - 1));
-        cy = max(0, min(cy, g.ny - 1));
         int nc = 0;  // buffered candidates (uniform)
         // once 64 candidates are known: the largest of the 64 best so far.
         // A point with a larger key can no longer be selected, and a cell
@@ -238,141 +348,73 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
         // positions) need not be read at all.
         unsigned long long kthr = ~0ull;
         float rcull = INFINITY;
+        const int4 *__restrict__ pts = Wd.pt_cell;
+        // keep the 64 best of nc >= 64 candidates; set the threshold and radius
+        auto settle = [&]() {
+            kthr = keep64(cand, nc);
+            // squared distance of the 64th point, back in metres; the margin
+            // covers the quantisation of both positions
+            rcull = sqrtf((float)(kthr >> 20) * (1.f / 1048576.f)) + 0.01f;
+        };
+        bool found = false;
+        if (rhint <= 16.f * g.cell) {
+            // one pass over the rows of cells that meet the disk of radius
+            // rhint (which holds the 64 nearest): per row, the cells the
+            // widest chord of the disk in that row spans
+            kthr = hint_key(rhint);
+            const int k = (int)(rhint * g.inv_cell) + 1;
+            gather(2 * k + 1, [&](int j, int &s, int &e) {
+                const int y = cy - k + j;
+                if (y < 0 || y >= g.ny) return;
+                const float ry0 = g.y0 + (float)y * g.cell, ry1 = ry0 + g.cell;
+                const float ddy = fmaxf(fmaxf(ry0 - py, py - ry1), 0.f);
+                if (ddy > rhint) return;
+                const float hw = sqrtf(rhint * rhint - ddy * ddy) + 1e-3f;
+                const int xa = max((int)floorf((px - hw - g.x0) * g.inv_cell), 0);
+                const int xb = min((int)floorf((px + hw - g.x0) * g.inv_cell), g.nx - 1);
+                if (xa > xb) return;
+                const int c0 = g.cbase + y * g.nx;
+                s = Wd.pt_cell_start[c0 + xa];
+                e = Wd.pt_cell_start[c0 + xb + 1];
+            }, pts, QX, QY, cand, s_segs[wv], s_segp[wv], nc, kthr);
+            if (nc >= 64) {
+                settle();
+                found = true;
+            } else {
+                nc = 0;  // not a bound after all: search from scratch
+                kthr = ~0ull;
+            }
+        }
         // rings closer than the distance to the nearest non-empty cell hold
         // no points: start there
-        int rr = Wd.pt_occ[g.cbase + cy * g.nx + cx];
-        rr = min(rr, max(g.nx, g.ny));
-        for (;; ++rr) {
+        for (int rr = min(rr_first, max(g.nx, g.ny)); !found; ++rr) {
             // the ring's cells as contiguous row segments (top row, bottom
             // row, single cells of the left and right columns), one segment
             // per lane, their points flattened across the wave
-            const int nseg = rr == 0 ? 1 : 4 * rr;
-            for (int sb = 0; sb < nseg; sb += 64) {
-                const int j = sb + lane;
-                int s = 0, e = 0;
-                if (j < nseg) {
-                    int y, xa, xb;
-                    if (rr == 0) { y = cy; xa = xb = cx; }
-                    else if (j == 0) { y = cy - rr; xa = cx - rr; xb = cx + rr; }
-                    else if (j == 1) { y = cy + rr; xa = cx - rr; xb = cx + rr; }
-                    else {
-                        const int qq = j - 2;
-                        y = cy - rr + 1 + (qq >> 1);
-                        xa = xb = (qq & 1) ? cx + rr : cx - rr;
-                    }
-                    xa = max(xa, 0);
-                    xb = min(xb, g.nx - 1);
-                    if (y >= 0 && y < g.ny && xa <= xb) {
-                        // distance from the agent to the segment's rectangle
-                        const float rx0 = g.x0 + (float)xa * g.cell, rx1 = g.x0 + (float)(xb + 1) * g.cell;
-                        const float ry0 = g.y0 + (float)y * g.cell, ry1 = ry0 + g.cell;
-                        const float ddx = fmaxf(fmaxf(rx0 - px, px - rx1), 0.f);
-                        const float ddy = fmaxf(fmaxf(ry0 - py, py - ry1), 0.f);
-                        if (ddx * ddx + ddy * ddy <= rcull * rcull) {
-                            const int c0 = g.cbase + y * g.nx;
-                            s = Wd.pt_cell_start[c0 + xa];
-                            e = Wd.pt_cell_start[c0 + xb + 1];
-                        }
-                    }
+            gather(rr == 0 ? 1 : 4 * rr, [&](int j, int &s, int &e) {
+                int y, xa, xb;
+                if (rr == 0) { y = cy; xa = xb = cx; }
+                else if (j == 0) { y = cy - rr; xa = cx - rr; xb = cx + rr; }
+                else if (j == 1) { y = cy + rr; xa = cx - rr; xb = cx + rr; }
+                else {
+                    const int qq = j - 2;
+                    y = cy - rr + 1 + (qq >> 1);
+                    xa = xb = (qq & 1) ? cx + rr : cx - rr;
                 }
-                const int len = e - s;
-                int incl = len;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y2 = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += y2;
-                }
-                const int total = __shfl(incl, 63, 64);
-                if (total == 0) continue;
-                s_segs[wv][lane] = s;
-                s_segp[wv][lane] = incl - len;
-                wave_sync();
-                // batches of up to BATCH points per lane: all loads of a batch
-                // are issued before any key is appended
-                for (int f0 = 0; f0 < total; f0 += 64 * BATCH) {
-                    const int nslot = min(BATCH, (total - f0 + 63) >> 6);
-                    if (nc + 64 * nslot > SF_CAND_CAP) {
-                        // keep only keys that can still be among the 64 best
-                        wave_sync();
-                        unsigned long long kv[KPL];
-#pragma unroll
-                        for (int t = 0; t < KPL; ++t) {
-                            int slot = lane + 64 * t;
-                            kv[t] = slot < nc ? cand[slot] : ~0ull;
-                        }
-                        kthr = kth_smallest(kv, 64, (nc + 63) >> 6);
-                        wave_sync();
-                        int keep = 0;
-#pragma unroll
-                        for (int t = 0; t < KPL; ++t) {
-                            const bool f = kv[t] <= kthr;
-                            const unsigned long long bal = __ballot(f);
-                            if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
-                            keep += __popcll(bal);
-                        }
-                        nc = keep;
-                        wave_sync();
-                    }
-                    int4 pq[BATCH];
-#pragma unroll
-                    for (int t = 0; t < BATCH; ++t) {
-                        const int f = f0 + 64 * t + lane;
-                        pq[t] = make_int4(0, 0, 0, -1);
-                        if (t < nslot && f < total) {
-                            // the segment holding flat index f: the last one
-                            // whose prefix is <= f (it is never empty)
-                            int lo = 0, hi = min(63, nseg - 1 - sb);
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (s_segp[wv][mid] <= f) lo = mid; else hi = mid - 1;
-                            }
-                            pq[t] = Wd.pt_cell[s_segs[wv][lo] + (f - s_segp[wv][lo])];
-                        }
-                    }
-#pragma unroll
-                    for (int t = 0; t < BATCH; ++t) {
-                        if (t >= nslot) break;
-                        unsigned long long key = ~0ull;
-                        if (pq[t].w == 0) {
-                            const long long dx = (long long)pq[t].x - QX, dy = (long long)pq[t].y - QY;
-                            key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 20) | (unsigned)pq[t].z;
-                        }
-                        const bool has = key < kthr;
-                        const unsigned long long bal = __ballot(has);
-                        if (has) cand[nc + __popcll(bal & lane_lt())] = key;
-                        nc += __popcll(bal);
-                    }
-                }
-                wave_sync();
-            }
-            // with 64 or more candidates: keep the 64 best, which sets the
-            // selection threshold and the cell-culling radius
-            if (nc >= 64) {
-                unsigned long long kv[KPL];
-#pragma unroll
-                for (int t = 0; t < KPL; ++t) {
-                    int slot = lane + 64 * t;
-                    kv[t] = slot < nc ? cand[slot] : ~0ull;
-                }
-                if (nc == 64) {
-                    kthr = wave_max_u64(kv[0]);
-                } else {
-                    kthr = kth_smallest(kv, 64, (nc + 63) >> 6);
-                    wave_sync();
-                    int keep = 0;
-#pragma unroll
-                    for (int t = 0; t < KPL; ++t) {
-                        const bool f = kv[t] <= kthr;
-                        const unsigned long long bal = __ballot(f);
-                        if (f) cand[keep + __popcll(bal & lane_lt())] = kv[t];
-                        keep += __popcll(bal);
-                    }
-                    nc = keep;
-                    wave_sync();
-                }
-                // squared distance of the 64th point, back in metres; the
-                // margin covers the quantisation of both positions
-                rcull = sqrtf((float)(kthr >> 20) * (1.f / 1048576.f)) + 0.01f;
-            }
+                xa = max(xa, 0);
+                xb = min(xb, g.nx - 1);
+                if (y < 0 || y >= g.ny || xa > xb) return;
+                // distance from the agent to the segment's rectangle
+                const float rx0 = g.x0 + (float)xa * g.cell, rx1 = g.x0 + (float)(xb + 1) * g.cell;
+                const float ry0 = g.y0 + (float)y * g.cell, ry1 = ry0 + g.cell;
+                const float ddx = fmaxf(fmaxf(rx0 - px, px - rx1), 0.f);
+                const float ddy = fmaxf(fmaxf(ry0 - py, py - ry1), 0.f);
+                if (ddx * ddx + ddy * ddy > rcull * rcull) return;
+                const int c0 = g.cbase + y * g.nx;
+                s = Wd.pt_cell_start[c0 + xa];
+                e = Wd.pt_cell_start[c0 + xb + 1];
+            }, pts, QX, QY, cand, s_segs[wv], s_segp[wv], nc, kthr);
+            if (nc >= 64) settle();
             // lower bound on the distance to any point outside the visited square
             float bnd = INFINITY;
             if (cx - rr > 0) bnd = fminf(bnd, px - (g.x0 + (float)(cx - rr) * g.cell));
@@ -403,6 +445,8 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
         }
         wave_sync();
         my_idx = lane < min(pos, 64) ? s_sel[wv][lane] : 0x7fffffff;
+        if (lane == 0)
+            hint[n] = make_float4(px, py, nc >= 64 ? sqrtf((float)(kthr >> 20) * (1.f / 1048576.f)) : NAN, 0.f);
         // point-index order: sort the member indices across lanes
         unsigned long long sk = wave_sort_u64((unsigned long long)(unsigned)my_idx);
         my_idx = (int)sk;
@@ -421,13 +465,23 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
 }
 
 void launch_obs(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
-                int *dbg_idx, int waves, hipStream_t s) {
+                int *dbg_idx, float4 *hint, int waves, hipStream_t s) {
     if (Wd.N == 0) return;
     if (waves <= 1) {
-        k_obs<1><<<Wd.N, 64, 0, s>>>(P, Wd, st, ist, obs, dbg_idx);
+        k_obs<1><<<Wd.N, 64, 0, s>>>(P, Wd, st, ist, obs, dbg_idx, hint);
     } else if (waves <= 2) {
-        k_obs<2><<<(Wd.N + 1) / 2, 128, 0, s>>>(P, Wd, st, ist, obs, dbg_idx);
+        k_obs<2><<<(Wd.N + 1) / 2, 128, 0, s>>>(P, Wd, st, ist, obs, dbg_idx, hint);
     } else {
-        k_obs<4><<<(Wd.N + 3) / 4, 256, 0, s>>>(P, Wd, st, ist, obs, dbg_idx);
+        k_obs<4><<<(Wd.N + 3) / 4, 256, 0, s>>>(P, Wd, st, ist, obs, dbg_idx, hint);
     }
+}
+
+// no bound known yet for any agent
+__global__ void k_hint_clear(float4 *hint, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) hint[k] = make_float4(0.f, 0.f, NAN, 0.f);
+}
+
+void launch_hint_clear(float4 *hint, int n, hipStream_t s) {
+    if (n > 0) k_hint_clear<<<(n + 255) / 256, 256, 0, s>>>(hint, n);
 }

@@ -335,6 +335,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ short s_bl[SF_MAXA][SF_BCAP];
     __shared__ float s_iw[6][SF_MAXA];   // world-frame inverse inertia (xx xy xz yy yz zz)
     __shared__ GridHdr s_tgrid;          // the world's triangle grid
+    __shared__ float s_mu[SF_MAX_SURFACES];  // the world's friction per surface
     __shared__ bool s_anytri;
     __shared__ int s_bn[SF_MAXA];
     __shared__ int s_scan[NWV];
@@ -392,6 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 s_tgrid = Wd.tgrid[w];
                 s_anytri = Wd.toff[w + 1] > Wd.toff[w];
             }
+            if (tid < Wd.S) s_mu[tid] = Wd.mu[w * Wd.S + tid];
             // ---- load the world's agents; decode actions (Sec. "Action Space Details")
             for (int i = tid; i < A; i += BLOCK) {
                 const int n = a0 + i;
@@ -545,7 +547,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             hit = H.hit;
                             if (hit) {
                                 n = H.n;
-                                mu = Wd.mu[w * Wd.S + H.surf];
+                                mu = s_mu[H.surf];
                                 mu_seen = mu;
                                 // massless spring-damper along the ray
                                 x = P.ell - H.t;

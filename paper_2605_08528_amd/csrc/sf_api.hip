@@ -34,6 +34,7 @@ struct sf_sim {
     int step_block = 128, obs_waves = 4;
     int step_grid = 0, cus = 256;  // persistent step: workgroups (0: one per world); compute units
     int *queue = nullptr;          // [2] world counter and finished-workgroup counter
+    float4 *hint = nullptr;        // [N] last observation's position and 64th road distance
     DevParams P_dev{};
     DevWorld Wd{};
     float *st = nullptr;       // [NF][N]
@@ -509,7 +510,9 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
         DEV(hipMemsetAsync(sim->rec_cnt, 0, sizeof(int) * SF_MAX_SUBSTEPS * W, st));
     }
     launch_reset(Pd, Wd, sim->st, sim->ist, nullptr, 0, st);
-    launch_obs(Pd, Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, st);
+    ALLOC(sim->hint, float4, std::max(N, 1));
+    launch_hint_clear(sim->hint, N, st);
+    launch_obs(Pd, Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, st);
     LAUNCHED();
     DEV(hipStreamSynchronize(st));
     *out = sim;
@@ -570,7 +573,7 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
     }
     {
         ProfScope ps(sim, 2);
-        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, sim->stream);
+        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, sim->stream);
     }
     LAUNCHED();
     sim->last_substeps = substeps;
@@ -965,7 +968,7 @@ sf_status sf_reset(sf_sim *sim, const uint8_t *d_mask) {
     }
     {
         ProfScope ps(sim, 2);
-        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, sim->stream);
+        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, sim->stream);
     }
     LAUNCHED();
     return SF_OK;
@@ -990,7 +993,7 @@ sf_status sf_set_state(sf_sim *sim, const void *host_src, size_t bytes) {
     if (!host_src || bytes != sf_state_bytes(sim))
         return fail(SF_E_INVALID_ARG, "host_src NULL or bytes != sf_state_bytes");
     if (bytes) DEV(hipMemcpyAsync(sim->st, host_src, bytes, hipMemcpyHostToDevice, sim->stream));
-    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, sim->stream);
+    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, sim->stream);
     LAUNCHED();
     DEV(hipStreamSynchronize(sim->stream));
     return SF_OK;
@@ -1032,7 +1035,7 @@ sf_status sf_debug_obs_indices(sf_sim *sim, int32_t *h_out) {
     if (sim->N == 0) return SF_OK;
     int *buf = nullptr;
     DEV(hipMalloc(&buf, sizeof(int) * 72 * (size_t)sim->N));
-    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, buf, sim->obs_waves, sim->stream);
+    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, buf, sim->hint, sim->obs_waves, sim->stream);
     LAUNCHED();
     DEV(hipMemcpyAsync(h_out, buf, sizeof(int) * 72 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream));
     DEV(hipStreamSynchronize(sim->stream));
@@ -1140,7 +1143,7 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
         DEV(hipMemcpyAsync(sim->reward, snap + sb, 4 * N, hipMemcpyDeviceToDevice, st));
         DEV(hipMemcpyAsync(sim->done, snap + sb + 4 * N, N, hipMemcpyDeviceToDevice, st));
         DEV(hipMemcpyAsync(sim->events, snap + sb + 5 * N, N, hipMemcpyDeviceToDevice, st));
-        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->obs_waves, st);
+        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, st);
         LAUNCHED();
         return SF_OK;
     };
