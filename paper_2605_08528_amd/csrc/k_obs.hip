@@ -279,23 +279,37 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
 
     // ---- neighbours: 8 nearest other active agents of the world
     {
+        // lane l holds agent a0 + l of the world (all of its planar state,
+        // so that the 8 nearest need no second round of loads)
         unsigned long long key = ~0ull;
+        float ox = 0.f, oy = 0.f, oqw = 1.f, oqx = 0.f, oqy = 0.f, oqz = 0.f, ovx = 0.f, ovy = 0.f;
         if (lane < A) {
             const int m = a0 + lane;
-            if (m != n && ist[SF_I_ACTIVE * N + m]) {
-                long long dx = (long long)qpos(st[SF_F_PX * N + m]) - QX;
-                long long dy = (long long)qpos(st[SF_F_PY * N + m]) - QY;
+            const int act_m = ist[SF_I_ACTIVE * N + m];
+            ox = st[SF_F_PX * N + m];
+            oy = st[SF_F_PY * N + m];
+            oqw = st[SF_F_QW * N + m];
+            oqx = st[SF_F_QX * N + m];
+            oqy = st[SF_F_QY * N + m];
+            oqz = st[SF_F_QZ * N + m];
+            ovx = st[SF_F_VX * N + m];
+            ovy = st[SF_F_VY * N + m];
+            if (m != n && act_m) {
+                long long dx = (long long)qpos(ox) - QX;
+                long long dy = (long long)qpos(oy) - QY;
                 key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 8) | (unsigned)lane;
             }
         }
         key = wave_sort_u64(key);
         int jn = key == ~0ull ? -1 : (int)(key & 0xFF);
         if (dbg && lane < 8) dbg[(size_t)n * 72 + 64 + lane] = jn;
+        // the state of the neighbour of rank `lane`, from lane jn
+        const int src = jn < 0 ? 0 : jn;
+        const float mx = __shfl(ox, src, 64), my = __shfl(oy, src, 64);
+        const float mqw = __shfl(oqw, src, 64), mqx = __shfl(oqx, src, 64);
+        const float mqy = __shfl(oqy, src, 64), mqz = __shfl(oqz, src, 64);
+        const float mvx = __shfl(ovx, src, 64), mvy = __shfl(ovy, src, 64);
         if (lane < 8 && jn >= 0) {
-            const int m = a0 + jn;
-            const float mx = st[SF_F_PX * N + m], my = st[SF_F_PY * N + m];
-            const float mqw = st[SF_F_QW * N + m], mqx = st[SF_F_QX * N + m];
-            const float mqy = st[SF_F_QY * N + m], mqz = st[SF_F_QZ * N + m];
             float jx = 1.f - 2.f * (mqy * mqy + mqz * mqz), jy = 2.f * (mqx * mqy + mqw * mqz);
             float L = sqrtf(jx * jx + jy * jy);
             if (L < 1e-12f) { jx = 1.f; jy = 0.f; } else { jx /= L; jy /= L; }
@@ -303,7 +317,6 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
             const float bx = hx * dx + hy * dy, by = -hy * dx + hx * dy;
             float dpsi = atan2f(hx * jy - hy * jx, hx * jx + hy * jy);
             if (dpsi == -3.14159265358979f) dpsi = 3.14159265358979f;
-            const float mvx = st[SF_F_VX * N + m], mvy = st[SF_F_VY * N + m];
             // swept circles, constant planar velocities; 0 if touching
             float ttc = 10.f;
             if (bx >= 0.f) {
