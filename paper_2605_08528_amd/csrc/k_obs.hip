@@ -252,8 +252,8 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
     // the distance moved since, bounds this one (triangle inequality), so
     // cells and points beyond it are skipped from the start.  No bound yet:
     // not a number.
-    const float rhint = hv.z == hv.z ? hv.z + sqrtf((px - hv.x) * (px - hv.x) + (py - hv.y) * (py - hv.y)) + 0.01f
-                                     : INFINITY;
+    const float moved = sqrtf((px - hv.x) * (px - hv.x) + (py - hv.y) * (py - hv.y));
+    const float rhint = hv.z == hv.z ? hv.z + moved + 0.01f : INFINITY;
     for (int k = lane; k < SF_OBS_DIM; k += 64) row[k] = 0.f;
     wave_sync();
 
@@ -370,7 +370,9 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
             rcull = sqrtf((float)(kthr >> 20) * (1.f / 1048576.f)) + 0.01f;
         };
         bool found = false;
-        if (rhint <= 16.f * g.cell) {
+        // a bound stays tight while the agent moves little; after a
+        // teleport (respawn, set state) the ring search is cheaper
+        if (rhint <= 64.f * g.cell && moved <= 2.f * g.cell) {
             // one pass over the rows of cells that meet the disk of radius
             // rhint (which holds the 64 nearest): per row, the cells the
             // widest chord of the disk in that row spans
