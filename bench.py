@@ -204,7 +204,7 @@ def main():
     ap.add_argument("--step-block", type=int, default=0)
     ap.add_argument("--policy-rows", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tune-steps", type=int, default=10)
+    ap.add_argument("--tune-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step shards by "

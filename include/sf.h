@@ -343,7 +343,7 @@ typedef struct {
     int32_t step_grid;    /* 0, or the workgroups of a persistent step (queue)  */
     int32_t obs_waves;    /* agents per workgroup in the observation (1, 2, 4)  */
     int32_t policy_rows;  /* agents per workgroup in the policy (16, 32, 64)    */
-    float step_us, obs_us, policy_us;  /* measured mean durations (0 if cached) */
+    float step_us, obs_us, policy_us;  /* measured median durations (0 if cached) */
 } sf_tuning;
 
 sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out);
@@ -352,8 +352,9 @@ sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out);
 sf_status sf_set_tuning(sf_sim *sim, const sf_tuning *t);
 /* Time every candidate shape of the step, observation and policy kernels
  * over `steps` control steps driven by the loaded policy (zero actions if
- * none), each from the same snapshot of the state, which is restored at the
- * end; keep the fastest of each kernel.  With cache_path (a text file, one
+ * none; two untimed steps first), each from the same snapshot of the state,
+ * which is restored at the end; keep the shape with the smallest median
+ * duration for each kernel.  With cache_path (a text file, one
  * line per workload signature: worlds, agents, largest world, road points,
  * triangles, substeps, device), a line for this workload is applied without
  * measuring, and a new result is added.  Synchronises. */

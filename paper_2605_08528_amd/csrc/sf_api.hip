@@ -1147,20 +1147,29 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
         LAUNCHED();
         return SF_OK;
     };
-    // mean durations [policy, step, obs] of `steps` control steps of shape t
+    // median durations [policy, step, obs] over `steps` control steps of
+    // shape t, after two untimed steps
     auto trial = [&](const sf_tuning &t, double *ms) -> sf_status {
         tuning_apply(sim, t);
         sf_status r;
         if ((r = restore()) != SF_OK) return r;
-        if ((r = sf_profile(sim, 1)) != SF_OK) return r;
-        for (int k = 0; k < steps; ++k) {
+        for (int k = 0; k < steps + 2; ++k) {
+            if (k == 2 && (r = sf_profile(sim, 1)) != SF_OK) return r;
             r = zero_act ? sf_step(sim, zero_act, dt, substeps) : sf_step_policy(sim, dt, substeps);
             if (r != SF_OK) return r;
         }
-        double tot[SF_PROF_KERNELS];
-        int32_t cnt[SF_PROF_KERNELS];
-        if ((r = sf_profile_read(sim, tot, cnt)) != SF_OK) return r;
-        for (int k = 0; k < 3; ++k) ms[k] = cnt[k] ? tot[k] / cnt[k] : 0.0;
+        DEV(hipStreamSynchronize(st));
+        std::vector<float> per[3];
+        for (auto &rec : sim->recs) {
+            float e = 0.f;
+            DEV(hipEventElapsedTime(&e, rec.a, rec.b));
+            if (rec.kind < 3) per[rec.kind].push_back(e);
+        }
+        for (int k = 0; k < 3; ++k) {
+            if (per[k].empty()) { ms[k] = 0.0; continue; }
+            std::nth_element(per[k].begin(), per[k].begin() + per[k].size() / 2, per[k].end());
+            ms[k] = per[k][per[k].size() / 2];
+        }
         return sf_profile(sim, 0);
     };
     sf_tuning best = *out;
