@@ -61,9 +61,9 @@ def recorded_traffic(kernel: str, launch_name: str, n_agents: int):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    k = rec.get("kernels", {}).get(kernel)
-    if (not k or k.get("source_hash") != kernel_source_hash(kernel) or k.get("agents") != n_agents
-            or k.get("launch") != launch_name):
+    k = rec.get("launches", {}).get(launch_name)
+    if not k or k.get("kernel") != kernel or k.get("source_hash") != kernel_source_hash(kernel) \
+            or k.get("agents") != n_agents:
         return None
     return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
 
