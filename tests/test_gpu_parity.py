@@ -387,7 +387,7 @@ def test_nan_actions_and_numeric_faults(O, torch):
 
 
 # ---------------------------------------------------- full-size sampling
-def sampled_full_size(O, torch, name, shapes, n_sample=6, surrogate=None):
+def sampled_full_size(O, torch, name, shapes, n_sample=6, surrogate=None, init=None):
     """A workload at full size in a given launch shape: sampled worlds re-run
     on the oracle from the GPU state (state, events, integer state, kNN
     membership and order, observation rows)."""
@@ -395,6 +395,10 @@ def sampled_full_size(O, torch, name, shapes, n_sample=6, surrogate=None):
     w = I.workload(name)
     dt, S = I.TIMING[name]
     sim = sf.Sim(w, mkparams(), flags=sf.SF_AUTO_RESET, **shapes)
+    if init is not None:
+        f0, k0 = sim.get_state()
+        init(f0, k0)
+        sim.set_state(f0, k0)
     if surrogate is not None:
         sim.sur_set(*surrogate)
         sim.sur_enable(True)

@@ -329,3 +329,28 @@ def test_fallback_is_the_plain_step(torch, trained):
         assert used == 0 and fb > 0
         for a, b in zip(got, ref):
             assert np.array_equal(a, b)
+
+
+def test_cross1024x16_surrogate_full_size_sampled(O, torch):
+    """The learned-tire step at full size (1024 worlds x 16 vehicles, the
+    configuration the network is meant for): a network trained on samples of
+    this workload, then sampled worlds re-run on the oracle with the same
+    network from the GPU state."""
+    from paper_2605_08528_amd import sf
+    from tests.test_gpu_parity import sampled_full_size
+    w = I.workload("cross1024x16")
+    sim = sf.Sim(w, mkparams(), flags=sf.SF_AUTO_RESET)
+    f, k = sim.get_state()
+    moving(seed=9)(f, k)
+    sim.set_state(f, k)
+    sim.sur_log(1 << 22)
+    for step in range(12):
+        a = I.actions(13, step, sim.N)
+        a[:, 0] = 0.5 * a[:, 0] + 0.3
+        sim.step(cuda(torch, a), 1.0 / 60.0, 4)
+    data, n = sim.sur_collect(1 << 22)
+    sim.sur_fit(data[: min(n, 1 << 22)])
+    P, lo, hi = sim.sur_get()
+    sim.close()
+    sampled_full_size(O, torch, "cross1024x16", {"step_grid": 512}, n_sample=4, surrogate=(P, lo, hi),
+                      init=moving(seed=10))
