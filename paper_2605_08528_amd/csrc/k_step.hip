@@ -822,30 +822,44 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             s_clam[c] = lam1;
                         }
                         __syncthreads();
-                        for (int b = tid; b < A; b += BLOCK) {
-                            const int cnt = s_bn[b];
-                            if (cnt == 0) continue;
-                            const float pbx = s_p[0][b], pby = s_p[1][b], pbz = s_p[2][b];
-                            // impulse and its moment summed in list order, then one
-                            // application of 1/m and the world inverse inertia
+                        // four lanes per body split its contacts (q = g, g + 4, ...),
+                        // then add their partial sums in a fixed butterfly order;
+                        // one application of 1/m and the world inverse inertia
+                        for (int e0 = 0; e0 < 4 * A; e0 += BLOCK) {
+                            const int e = e0 + tid, b = e >> 2, g = e & 3;
                             float jx = 0.f, jy = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
-#pragma unroll 4
-                            for (int q = 0; q < cnt; ++q) {
-                                const int c = s_bl[b][q];
-                                const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? s_cdl[c] : -s_cdl[c];
-                                const float Jx = dl * s_cn[0][c], Jy = dl * s_cn[1][c];
-                                const float rx = s_cpc[0][c] - pbx, ry = s_cpc[1][c] - pby, rz = s_cpc[2][c] - pbz;
-                                jx += Jx;
-                                jy += Jy;
-                                tx -= rz * Jy;
-                                ty += rz * Jx;
-                                tz += rx * Jy - ry * Jx;
+                            const int cnt = b < A ? s_bn[b] : 0;
+                            if (cnt > 0) {
+                                const float pbx = s_p[0][b], pby = s_p[1][b], pbz = s_p[2][b];
+#pragma unroll 2
+                                for (int q = g; q < cnt; q += 4) {
+                                    const int c = s_bl[b][q];
+                                    const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? s_cdl[c] : -s_cdl[c];
+                                    const float Jx = dl * s_cn[0][c], Jy = dl * s_cn[1][c];
+                                    const float rx = s_cpc[0][c] - pbx, ry = s_cpc[1][c] - pby,
+                                                rz = s_cpc[2][c] - pbz;
+                                    jx += Jx;
+                                    jy += Jy;
+                                    tx -= rz * Jy;
+                                    ty += rz * Jx;
+                                    tz += rx * Jy - ry * Jx;
+                                }
                             }
-                            s_v[0][b] += jx * P.inv_mass;
-                            s_v[1][b] += jy * P.inv_mass;
-                            s_w[0][b] += s_iw[0][b] * tx + s_iw[1][b] * ty + s_iw[2][b] * tz;
-                            s_w[1][b] += s_iw[1][b] * tx + s_iw[3][b] * ty + s_iw[4][b] * tz;
-                            s_w[2][b] += s_iw[2][b] * tx + s_iw[4][b] * ty + s_iw[5][b] * tz;
+#pragma unroll
+                            for (int m = 2; m > 0; m >>= 1) {
+                                jx += __shfl_xor(jx, m, 64);
+                                jy += __shfl_xor(jy, m, 64);
+                                tx += __shfl_xor(tx, m, 64);
+                                ty += __shfl_xor(ty, m, 64);
+                                tz += __shfl_xor(tz, m, 64);
+                            }
+                            if (cnt > 0 && g == 0) {
+                                s_v[0][b] += jx * P.inv_mass;
+                                s_v[1][b] += jy * P.inv_mass;
+                                s_w[0][b] += s_iw[0][b] * tx + s_iw[1][b] * ty + s_iw[2][b] * tz;
+                                s_w[1][b] += s_iw[1][b] * tx + s_iw[3][b] * ty + s_iw[4][b] * tz;
+                                s_w[2][b] += s_iw[2][b] * tx + s_iw[4][b] * ty + s_iw[5][b] * tz;
+                            }
                         }
                         __syncthreads();
                     }
