@@ -306,6 +306,46 @@ __device__ __forceinline__ void pair_of(int k, int A, int &i, int &j) {
     j = k - ii * (2 * A - ii - 1) / 2 + ii + 1;
 }
 
+// ---- A: steering PD (Eq. steer PD, implicit in the rate), rotation, planar
+//      heading and the quantised three-circle centres of active agent i
+//      (run for the first substep after the load, and for each later one
+//      right after the previous substep's integration, by the same thread)
+#define SF_PHASE_A(i)                                                                \
+    do {                                                                             \
+        float th = s_th[i], thd = s_thd[i], tgt = s_tgt[i];                          \
+        float g = h / P.Is;                                                          \
+        float thd1 = (thd + g * P.kp * (tgt - th)) / (1.f + g * (P.kd + h * P.kp));  \
+        float tau = P.kp * (tgt - th - h * thd1) - P.kd * thd1;                      \
+        if (fabsf(tau) > P.tau_max) {                                                \
+            tau = tau > 0.f ? P.tau_max : -P.tau_max;                                \
+            thd1 = thd + g * tau;                                                    \
+        }                                                                            \
+        s_th[i] = th + h * thd1;                                                     \
+        s_thd[i] = thd1;                                                             \
+        float R[9];                                                                  \
+        quat_R(s_q[0][i], s_q[1][i], s_q[2][i], s_q[3][i], R);                       \
+        for (int c = 0; c < 9; ++c) s_R[c][i] = R[c];                                \
+        float L = sqrtf(R[0] * R[0] + R[3] * R[3]);                                  \
+        s_hx[i] = L < 1e-12f ? 1.f : R[0] / L;                                       \
+        s_hy[i] = L < 1e-12f ? 0.f : R[3] / L;                                       \
+        long long X = qpos(s_p[0][i]), Y = qpos(s_p[1][i]);                          \
+        long long qw = qquat(s_q[0][i]), qx = qquat(s_q[1][i]);                      \
+        long long qy = qquat(s_q[2][i]), qz = qquat(s_q[3][i]);                      \
+        long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);                        \
+        long long hy = 2 * (qx * qy + qw * qz);                                      \
+        long long nh = isqrt64(hx * hx + hy * hy);                                   \
+        long long ox = 0, oy = 0;                                                    \
+        /* |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to */        \
+        /* the exact integer quotient (cheaper than 64-bit division) */              \
+        if (nh > 0) {                                                                \
+            ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);           \
+            oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);           \
+        }                                                                            \
+        s_cq[0][i] = (int)(X - ox); s_cq[1][i] = (int)(Y - oy);                      \
+        s_cq[2][i] = (int)X;        s_cq[3][i] = (int)Y;                             \
+        s_cq[4][i] = (int)(X + ox); s_cq[5][i] = (int)(Y + oy);                      \
+    } while (0)
+
 template <int BLOCK, bool SUR>
 __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur Su, float *__restrict__ st,
                                                 int *__restrict__ ist, const float *__restrict__ act,
@@ -426,44 +466,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
             const int npc = A * (A - 1) / 2;
             for (int sub = 0; sub < S; ++sub) {
                 const bool last = sub == S - 1;
-                // ---- A: steering PD (Eq. steer PD, implicit in the rate), rotation,
-                //      planar heading and the quantised three-circle centres
-                for (int i = tid; i < A; i += BLOCK) {
-                    if (!s_act[i]) continue;
-                    float th = s_th[i], thd = s_thd[i], tgt = s_tgt[i];
-                    float g = h / P.Is;
-                    float thd1 = (thd + g * P.kp * (tgt - th)) / (1.f + g * (P.kd + h * P.kp));
-                    float tau = P.kp * (tgt - th - h * thd1) - P.kd * thd1;
-                    if (fabsf(tau) > P.tau_max) {
-                        tau = tau > 0.f ? P.tau_max : -P.tau_max;
-                        thd1 = thd + g * tau;
-                    }
-                    s_th[i] = th + h * thd1;
-                    s_thd[i] = thd1;
-                    float R[9];
-                    quat_R(s_q[0][i], s_q[1][i], s_q[2][i], s_q[3][i], R);
-                    for (int c = 0; c < 9; ++c) s_R[c][i] = R[c];
-                    float L = sqrtf(R[0] * R[0] + R[3] * R[3]);
-                    s_hx[i] = L < 1e-12f ? 1.f : R[0] / L;
-                    s_hy[i] = L < 1e-12f ? 0.f : R[3] / L;
-                    long long X = qpos(s_p[0][i]), Y = qpos(s_p[1][i]);
-                    long long qw = qquat(s_q[0][i]), qx = qquat(s_q[1][i]);
-                    long long qy = qquat(s_q[2][i]), qz = qquat(s_q[3][i]);
-                    long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);
-                    long long hy = 2 * (qx * qy + qw * qz);
-                    long long nh = isqrt64(hx * hx + hy * hy);
-                    long long ox = 0, oy = 0;
-                    // |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to
-                    // the exact integer quotient (cheaper than 64-bit division)
-                    if (nh > 0) {
-                        ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);
-                        oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);
-                    }
-                    s_cq[0][i] = (int)(X - ox); s_cq[1][i] = (int)(Y - oy);
-                    s_cq[2][i] = (int)X;        s_cq[3][i] = (int)Y;
-                    s_cq[4][i] = (int)(X + ox); s_cq[5][i] = (int)(Y + oy);
+                if (sub == 0) {
+                    for (int i = tid; i < A; i += BLOCK)
+                        if (s_act[i]) SF_PHASE_A(i);
+                    __syncthreads();
                 }
-                __syncthreads();
 
                 // ---- B (last wave): overlapping circle pairs on the substep's input
                 //      poses, compacted in canonical (i, j) order with wave ballots.
@@ -881,6 +888,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     qw += 0.5f * h * dw; qx += 0.5f * h * dx; qy += 0.5f * h * dy; qz += 0.5f * h * dz;
                     const float L = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
                     s_q[0][i] = qw / L; s_q[1][i] = qx / L; s_q[2][i] = qy / L; s_q[3][i] = qz / L;
+                    if (!last) SF_PHASE_A(i);
                 }
                 __syncthreads();
             }
@@ -968,6 +976,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
         queue[1] = 0;
     }
 }
+
+#undef SF_PHASE_A
 
 void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
                  const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
