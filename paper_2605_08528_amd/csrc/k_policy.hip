@@ -137,18 +137,21 @@ __global__ __launch_bounds__(256) void k_policy(const float *__restrict__ obs, i
 #define PL_WLD (PL_IN + 8)  // padded weight row (bf16)
 
 __device__ __forceinline__ void stage_weights(const uint16_t *__restrict__ W, uint16_t *__restrict__ sw) {
-    // 256 rows x 32 chunks of 8 bf16; thread t copies chunks t, t + 256, ...
+    // 256 rows x 32 chunks of 8 bf16; thread t copies chunks t, t + 256, ...,
+    // starting at a 4 KB offset of its own per block, so that the blocks'
+    // copies do not all hit the same memory lines at once
+    const int rot = (int)(blockIdx.x & 31) * 256;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         uint4 v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int c = threadIdx.x + 256 * (16 * b + q);
+            const int c = (threadIdx.x + 256 * (16 * b + q) + rot) & 8191;
             v[q] = reinterpret_cast<const uint4 *>(W)[c];
         }
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int c = threadIdx.x + 256 * (16 * b + q);
+            const int c = (threadIdx.x + 256 * (16 * b + q) + rot) & 8191;
             *reinterpret_cast<uint4 *>(sw + (c >> 5) * PL_WLD + (c & 31) * 8) = v[q];
         }
     }

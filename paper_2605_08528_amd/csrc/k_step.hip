@@ -386,8 +386,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ __attribute__((aligned(16))) float s_surb[SUR ? SURW_NB : 4];
 
     if (SUR) {
-        // the network's weights and biases, once per block for all substeps
-        for (int e = tid; e < 128 * 4 + 2 * 128 * 16 + 3 * 16; e += BLOCK) {
+        // the network's weights and biases, once per block for all substeps;
+        // each block starts at its own offset so that the blocks' copies do
+        // not all hit the same memory lines at once
+        constexpr int NCH = 128 * 4 + 2 * 128 * 16 + 3 * 16;
+        const int rot = (int)(blockIdx.x % 64) * 64;
+        for (int e0 = tid; e0 < NCH; e0 += BLOCK) {
+            const int e = e0 + rot < NCH ? e0 + rot : e0 + rot - NCH;
             const uint16_t *src;
             uint16_t *dst;
             if (e < 512) {
