@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 METRIC = "controlled-agent steps/s @256 worlds×16 agents; plain vs surrogate step"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
-# algorithmic bytes per agent and launch ("Measurement")
+# algorithmic bytes per agent and launch: state read + write, actions and
+# outputs for the step; the observation row and the state it reads
 STEP_BYTES_PER_AGENT = 2 * 112 + 8 + 6        # state read + write, actions, reward/done/events
 OBS_BYTES_PER_AGENT = 1024 + 64               # observation row write + own state read
 POLICY_FLOP_PER_AGENT = 2 * (256 * 256 * 2 + 256 * 2)
@@ -207,8 +208,8 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step shards by "
-              "world across GPUs but this build measures a single GPU", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step would shard by "
+              "world across GPUs, and only the single-GPU step is implemented and measured", file=sys.stderr)
         sys.exit(2)
 
     import torch
