@@ -296,7 +296,7 @@ def main():
         roof = {"bound": "hbm", "achieved": per * N / avg_s / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    launch = {"policy": f"k_policy<{tuning['policy_rows']}>",
+    launch = {"policy": "k_policy_lds<16>" if tuning["policy_rows"] <= 16 else f"k_policy<{tuning['policy_rows']}>",
               "step": f"k_step<{tuning['step_block']}, false>",
               "obs": f"k_obs<{tuning['obs_waves']}>"}
     roof["kernel"] = launch[dom]
