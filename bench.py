@@ -298,7 +298,7 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     launch = {"policy": "k_policy_lds<16>" if tuning["policy_rows"] <= 16 else f"k_policy<{tuning['policy_rows']}>",
               "step": f"k_step<{tuning['step_block']}, false>",
-              "obs": f"k_obs<{tuning['obs_waves']}>"}
+              "obs": "k_obs_policy" if tuning["obs_waves"] == 16 else f"k_obs<{tuning['obs_waves']}>"}
     roof["kernel"] = launch[dom]
     roof["traffic"] = recorded_traffic({"policy": "k_policy", "step": "k_step", "obs": "k_obs"}[dom],
                                        launch[dom], N)
@@ -332,7 +332,8 @@ def main():
                         f"({int(np.diff(worlds.agent_offsets).min())}-{int(np.diff(worlds.agent_offsets).max())} per world), "
                         f"{len(worlds.road_xy)} road points, dt {dt:.4f} s x {S} substeps, "
                         "plain tire, policy MLP 256-256-256-2 bf16/fp32-acc",
-            "step": "policy + physics step + observation (eager launches)",
+            "step": ("physics step + observation with the next actions in the same kernel (eager launches)"
+                     if tuning["obs_waves"] == 16 else "policy + physics step + observation (eager launches)"),
             "active_agents": active,
             "launch_shapes": {k: tuning[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows")},
         },

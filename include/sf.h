@@ -150,7 +150,9 @@ typedef struct {
     uint32_t flags;             /* SF_INVINCIBLE | SF_AUTO_RESET | ...        */
     float grid_cell;            /* road grid cell size [m]; 0 -> default      */
     int32_t step_block;         /* threads per world in the step; 0 -> auto   */
-    int32_t obs_waves;          /* agents (waves) per block in the obs kernel */
+    int32_t obs_waves;          /* agents (waves) per block in the obs kernel;
+                                   16: with a loaded policy, the observation
+                                   kernel also computes the next actions     */
     int32_t policy_rows;        /* agents per block in the policy MLP (32/64) */
     float tri_cell;             /* triangle grid cell size [m]; 0 -> default  */
     int32_t step_grid;          /* persistent step: this many workgroups
@@ -233,16 +235,24 @@ sf_status sf_debug_obs_indices(sf_sim *sim, int32_t *h_out);
  * W3[2][256] b3[2] (row-major [out][in]); n must be SF_POLICY_PARAMS. */
 #define SF_POLICY_PARAMS 132098
 sf_status sf_policy_load(sf_sim *sim, const float *h_params, size_t n);
-/* Actions [N][2] (device float32) from the handle's current observation. */
+/* Actions [N][2] (device float32) from the handle's current observation.
+ * When the fused observation kernel (obs_waves = 16) already computed them,
+ * they are copied from the handle instead of evaluating the network again. */
 sf_status sf_policy_act(sf_sim *sim, float *d_actions);
 /* One full control step driven by the loaded policy: policy(obs) -> step
- * -> observation (actions kept in the handle). */
+ * -> observation (actions kept in the handle).  With obs_waves = 16 the
+ * observation kernel also computes the next step's actions, and the policy
+ * launch is skipped while they are current.  Loading a policy drops a
+ * captured graph (capture again). */
 sf_status sf_step_policy(sf_sim *sim, float dt, int32_t substeps);
 
 /* ---- HIP graph of K policy-driven control steps on the handle's stream
  * (the stream must not be the null stream).  Replays enqueue the same
  * kernels with the same arguments; resets happen inside the step
- * (SF_AUTO_RESET), so no host decision is needed between steps. */
+ * (SF_AUTO_RESET), so no host decision is needed between steps.  With
+ * obs_waves = 16 the capture enqueues the first step's policy evaluation
+ * (outside the graph) when the actions are not current, and a replay does
+ * the same when a later change of state or launch shape left them stale. */
 sf_status sf_graph_capture(sf_sim *sim, int32_t control_steps, float dt, int32_t substeps);
 sf_status sf_graph_launch(sf_sim *sim);
 
@@ -341,9 +351,12 @@ sf_status sf_sur_counts(sf_sim *sim, uint64_t *out, int32_t reset);
 typedef struct {
     int32_t step_block;   /* threads per world in the step (64..320)            */
     int32_t step_grid;    /* 0, or the workgroups of a persistent step (queue)  */
-    int32_t obs_waves;    /* agents per workgroup in the observation (1, 2, 4)  */
+    int32_t obs_waves;    /* agents per workgroup in the observation (1, 2, 4),
+                             or 16: observation and policy in one kernel        */
     int32_t policy_rows;  /* agents per workgroup in the policy (16, 32, 64)    */
-    float step_us, obs_us, policy_us;  /* measured median durations (0 if cached) */
+    float step_us, obs_us, policy_us;  /* measured median durations (0 if cached;
+                                          policy_us 0 when the observation
+                                          kernel computes the actions)       */
 } sf_tuning;
 
 sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out);

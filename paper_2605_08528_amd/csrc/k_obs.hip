@@ -193,28 +193,25 @@ __device__ __forceinline__ void gather(int nseg, SEG seg, const int4 *__restrict
     }
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
-                                                   const float *__restrict__ st,
-                                                   const int *__restrict__ ist,
-                                                   float *__restrict__ obs, int *__restrict__ dbg,
-                                                   float4 *__restrict__ hint) {
-    __shared__ unsigned long long s_cand[WAVES][SF_CAND_CAP];
-    __shared__ float s_row[WAVES][SF_OBS_DIM];
-    __shared__ int s_sel[WAVES][64];
-    __shared__ int s_segs[WAVES][64], s_segp[WAVES][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
-    // give each XCD a contiguous range of agents (neighbouring agents share a
-    // world and its road grid, which then stays in one L2)
+// XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
+// give each XCD a contiguous range of agents (neighbouring agents share a
+// world and its road grid, which then stays in one L2).  First agent of the
+// block for `waves` agents per block.
+__device__ __forceinline__ int xcd_agent(int waves) {
     const int nb = gridDim.x, b = blockIdx.x;
     const int q = nb >> 3, r = nb & 7, x = b & 7;
-    const int lb = x * q + min(x, r) + (b >> 3);
+    return (x * q + min(x, r) + (b >> 3)) * waves;
+}
+
+// One agent's observation row (one wave): written to obs and left in the
+// wave's LDS row; returns false for an inactive agent (row of zeros in
+// memory, LDS row untouched).
+__device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *__restrict__ st,
+                          const int *__restrict__ ist, float *__restrict__ obs, int *__restrict__ dbg,
+                          float4 *__restrict__ hint, int n, unsigned long long *cand, float *row, int *sel,
+                          int *segs, int *segp) {
+    const int lane = threadIdx.x & 63;
     const int N = Wd.N;
-    const int n = lb * WAVES + wv;
-    if (n >= N) return;
-    float *row = s_row[wv];
-    unsigned long long *cand = s_cand[wv];
     float4 *dst = reinterpret_cast<float4 *>(obs + (size_t)n * SF_OBS_DIM);
 
     // the loads that depend only on the agent go out together, then the
@@ -235,7 +232,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
         dst[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (dbg) dbg[(size_t)n * 72 + lane] = -1;
         if (dbg && lane < 8) dbg[(size_t)n * 72 + 64 + lane] = -1;
-        return;
+        return false;
     }
     // the agent's road-grid cell and the first ring that holds points
     int cx = (int)floorf((px - g.x0) * g.inv_cell);
@@ -391,7 +388,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
                 const int c0 = g.cbase + y * g.nx;
                 s = Wd.pt_cell_start[c0 + xa];
                 e = Wd.pt_cell_start[c0 + xb + 1];
-            }, pts, QX, QY, cand, s_segs[wv], s_segp[wv], nc, kthr);
+            }, pts, QX, QY, cand, segs, segp, nc, kthr);
             if (nc >= 64) {
                 settle();
                 found = true;
@@ -428,7 +425,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
                 const int c0 = g.cbase + y * g.nx;
                 s = Wd.pt_cell_start[c0 + xa];
                 e = Wd.pt_cell_start[c0 + xb + 1];
-            }, pts, QX, QY, cand, s_segs[wv], s_segp[wv], nc, kthr);
+            }, pts, QX, QY, cand, segs, segp, nc, kthr);
             if (nc >= 64) settle();
             // lower bound on the distance to any point outside the visited square
             float bnd = INFINITY;
@@ -455,11 +452,11 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
             const bool f = kv[t] <= kmax;
             const unsigned long long bal = __ballot(f);
             const int at = pos + __popcll(bal & lane_lt());
-            if (f && at < 64) s_sel[wv][at] = (int)(kv[t] & 0xFFFFF);
+            if (f && at < 64) sel[at] = (int)(kv[t] & 0xFFFFF);
             pos += __popcll(bal);
         }
         wave_sync();
-        my_idx = lane < min(pos, 64) ? s_sel[wv][lane] : 0x7fffffff;
+        my_idx = lane < min(pos, 64) ? sel[lane] : 0x7fffffff;
         if (lane == 0)
             hint[n] = make_float4(px, py, nc >= 64 ? sqrtf((float)(kthr >> 20) * (1.f / 1048576.f)) : NAN, 0.f);
         // point-index order: sort the member indices across lanes
@@ -477,6 +474,114 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
     }
     wave_sync();
     dst[lane] = reinterpret_cast<const float4 *>(row)[lane];
+    return true;
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd, const float *__restrict__ st,
+                                                   const int *__restrict__ ist, float *__restrict__ obs,
+                                                   int *__restrict__ dbg, float4 *__restrict__ hint) {
+    __shared__ unsigned long long s_cand[WAVES][SF_CAND_CAP];
+    __shared__ float s_row[WAVES][SF_OBS_DIM];
+    __shared__ int s_sel[WAVES][64];
+    __shared__ int s_segs[WAVES][64], s_segp[WAVES][64];
+    const int wv = threadIdx.x >> 6;
+    const int n = xcd_agent(WAVES) + wv;
+    if (n >= Wd.N) return;
+    obs_agent(P, Wd, st, ist, obs, dbg, hint, n, s_cand[wv], s_row[wv], s_sel[wv], s_segs[wv], s_segp[wv]);
+}
+
+// The observation of 16 agents (one wave each) followed by the policy MLP on
+// their rows (the network of k_policy.hip: 256 -> 256 -> 256 -> 2, ELU,
+// tanh head; bf16 operands, fp32 accumulation), so that the next control
+// step's actions are ready when the observation is: the policy's own launch
+// and its re-read of the observations disappear, and a workgroup whose
+// agents were quick runs its network while others still search.  Wave w
+// computes output columns [16 w, 16 w + 16) of each hidden layer with weight
+// fragments from L2, one k-step ahead.
+#define OP_LD (SF_OBS_DIM + 8)  // padded bf16 activation row
+
+__device__ __forceinline__ float elu_fast(float x) {
+    if (x > 0.f) return x;
+    if (x > -0.25f) return x * (1.f + x * (0.5f + x * (1.f / 6.f + x * (1.f / 24.f))));
+    return __expf(x) - 1.f;
+}
+
+__device__ __forceinline__ void op_layer(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
+                                         const uint16_t *__restrict__ W, const float *__restrict__ b) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *wrow = W + (size_t)(wv * 16 + r16) * SF_OBS_DIM + kq * 8;
+    bf16x8 bn = *reinterpret_cast<const bf16x8 *>(wrow);
+#pragma unroll
+    for (int kk = 0; kk < SF_OBS_DIM / 32; ++kk) {
+        const bf16x8 bf = bn;
+        if (kk + 1 < SF_OBS_DIM / 32) bn = *reinterpret_cast<const bf16x8 *>(wrow + 32 * (kk + 1));
+        const bf16x8 af = *reinterpret_cast<const bf16x8 *>(in + r16 * OP_LD + kk * 32 + kq * 8);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc, 0, 0, 0);
+    }
+    const int col = wv * 16 + r16;
+    const float bias = b[col];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[(kq * 4 + j) * OP_LD + col] = f2bf(elu_fast(acc[j] + bias));
+}
+
+__global__ __launch_bounds__(1024) void k_obs_policy(DevParams P, DevWorld Wd, const float *__restrict__ st,
+                                                     const int *__restrict__ ist, float *__restrict__ obs,
+                                                     float4 *__restrict__ hint, const uint16_t *__restrict__ W1,
+                                                     const float *__restrict__ b1, const uint16_t *__restrict__ W2,
+                                                     const float *__restrict__ b2, const uint16_t *__restrict__ W3,
+                                                     const float *__restrict__ b3, float steer_max,
+                                                     float *__restrict__ act) {
+    __shared__ unsigned long long s_cand[16][SF_CAND_CAP];
+    __shared__ float s_row[16][SF_OBS_DIM];
+    __shared__ int s_sel[16][64];
+    __shared__ int s_segs[16][64], s_segp[16][64];
+    __shared__ __attribute__((aligned(16))) uint16_t s_pa[16 * OP_LD], s_pb[16 * OP_LD];
+    __shared__ uint16_t s_w3[2 * SF_OBS_DIM];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n0 = xcd_agent(16), n = n0 + wv;
+    if (threadIdx.x < 2 * SF_OBS_DIM) s_w3[threadIdx.x] = W3[threadIdx.x];
+    bool ok = false;
+    if (n < Wd.N)
+        ok = obs_agent(P, Wd, st, ist, obs, nullptr, hint, n, s_cand[wv], s_row[wv], s_sel[wv], s_segs[wv],
+                       s_segp[wv]);
+    // the row as bf16 (zeros for an inactive agent or past the end)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = 4 * lane + q;
+        s_pa[wv * OP_LD + c] = f2bf(ok ? s_row[wv][c] : 0.f);
+    }
+    __syncthreads();
+    op_layer(s_pa, s_pb, W1, b1);
+    __syncthreads();
+    op_layer(s_pb, s_pa, W2, b2);
+    __syncthreads();
+    // head: 32 outputs, each split over 32 lanes and summed in a fixed
+    // butterfly order
+    {
+        const int out = threadIdx.x >> 5, part = threadIdx.x & 31;
+        const int row = out >> 1, o = out & 1;
+        const uint16_t *h = s_pa + row * OP_LD + part * 8;
+        const uint16_t *w = s_w3 + o * SF_OBS_DIM + part * 8;
+        float a = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a += bf2f(h[k]) * bf2f(w[k]);
+#pragma unroll
+        for (int m = 16; m > 0; m >>= 1) a += __shfl_xor(a, m, 64);
+        if (part == 0 && n0 + row < Wd.N) {
+            const float z = tanhf(a + b3[o]);
+            act[2 * (size_t)(n0 + row) + o] = o == 0 ? z : steer_max * z;
+        }
+    }
+}
+
+void launch_obs_policy(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
+                       float4 *hint, const uint16_t *W1, const float *b1, const uint16_t *W2, const float *b2,
+                       const uint16_t *W3, const float *b3, float steer_max, float *act, hipStream_t s) {
+    if (Wd.N == 0) return;
+    k_obs_policy<<<(Wd.N + 15) / 16, 1024, 0, s>>>(P, Wd, st, ist, obs, hint, W1, b1, W2, b2, W3, b3, steer_max,
+                                                   act);
 }
 
 void launch_obs(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,

@@ -53,6 +53,9 @@ struct sf_sim {
     uint16_t *pol_bf16 = nullptr;   // bf16 copies of W1, W2, W3
     float *pol_act = nullptr;       // [N][2] actions of sf_step_policy
     bool policy_loaded = false;
+    bool act_valid = false;         // pol_act = policy(obs) of the current state
+    bool graph_act_in = false;      // the captured graph starts from valid pol_act
+    bool graph_act_out = false;     // ... and leaves it valid
     // learned tire surrogate
     float *sur_P = nullptr, *sur_m = nullptr, *sur_v = nullptr, *sur_gsum = nullptr;
     uint16_t *sur_Wb = nullptr;
@@ -276,7 +279,9 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
         !std::isfinite(opts.tri_cell))
         return fail(SF_E_INVALID_ARG, "grid_cell and tri_cell must be >= 0");
     if (opts.step_block < 0 || opts.step_block > 320 || opts.step_grid < 0 ||
-        opts.obs_waves < 0 || opts.obs_waves > 4 || opts.policy_rows < 0 || opts.policy_rows > 64)
+        (opts.obs_waves != 0 && opts.obs_waves != 1 && opts.obs_waves != 2 && opts.obs_waves != 4 &&
+         opts.obs_waves != 16) ||
+        opts.policy_rows < 0 || opts.policy_rows > 64)
         return fail(SF_E_INVALID_ARG, "launch shape out of range");
 
     sf_sim *sim = new sf_sim();
@@ -512,7 +517,8 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     launch_reset(Pd, Wd, sim->st, sim->ist, nullptr, 0, st);
     ALLOC(sim->hint, float4, std::max(N, 1));
     launch_hint_clear(sim->hint, N, st);
-    launch_obs(Pd, Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, st);
+    launch_obs(Pd, Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves == 16 ? 4 : sim->obs_waves,
+               st);
     LAUNCHED();
     DEV(hipStreamSynchronize(st));
     *out = sim;
@@ -548,6 +554,23 @@ sf_status sf_info(const sf_sim *sim, int32_t *W, int32_t *N, int32_t *amax) {
         if ((sim)->bad) return fail(SF_E_BAD_STATE, "handle had a device error"); \
     } while (0)
 
+// The observation of the current state; with a loaded policy and 16 agents
+// per workgroup, the fused kernel also leaves the next actions in pol_act.
+static void enqueue_obs(sf_sim *sim) {
+    ProfScope ps(sim, 2);
+    if (sim->policy_loaded && sim->obs_waves == 16) {
+        const uint16_t *W1 = sim->pol_bf16, *W2 = W1 + 256 * 256, *W3 = W2 + 256 * 256;
+        const float *b1 = sim->pol_f32 + 256 * 256, *b2 = b1 + 256 + 256 * 256, *b3 = b2 + 256 + 2 * 256;
+        launch_obs_policy(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, sim->hint, W1, b1, W2, b2, W3, b3,
+                          sim->steer_max, sim->pol_act, sim->stream);
+        sim->act_valid = true;
+    } else {
+        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint,
+                   sim->obs_waves == 16 ? 4 : sim->obs_waves, sim->stream);
+        sim->act_valid = false;
+    }
+}
+
 sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substeps) {
     CHECK_SIM(sim);
     if (substeps < 1 || substeps > SF_MAX_SUBSTEPS) return fail(SF_E_INVALID_ARG, "substeps must be 1..16");
@@ -571,10 +594,7 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         if (sim->sur_log)
             sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;
     }
-    {
-        ProfScope ps(sim, 2);
-        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, sim->stream);
-    }
+    enqueue_obs(sim);
     LAUNCHED();
     sim->last_substeps = substeps;
     return SF_OK;
@@ -608,6 +628,10 @@ sf_status sf_policy_load(sf_sim *sim, const float *h, size_t n) {
     LAUNCHED();
     DEV(hipStreamSynchronize(sim->stream));
     sim->policy_loaded = true;
+    sim->act_valid = false;
+    // a captured graph may start from actions of the previous network
+    if (sim->graph_exec) { (void)hipGraphExecDestroy(sim->graph_exec); sim->graph_exec = nullptr; }
+    if (sim->graph) { (void)hipGraphDestroy(sim->graph); sim->graph = nullptr; }
     return SF_OK;
 }
 
@@ -615,6 +639,12 @@ sf_status sf_policy_act(sf_sim *sim, float *d_actions) {
     CHECK_SIM(sim);
     if (!sim->policy_loaded) return fail(SF_E_INVALID_ARG, "no policy loaded");
     if (sim->N > 0 && !d_actions) return fail(SF_E_INVALID_ARG, "actions is NULL");
+    if (sim->act_valid) {
+        if (sim->N > 0)
+            DEV(hipMemcpyAsync(d_actions, sim->pol_act, sizeof(float) * 2 * sim->N, hipMemcpyDeviceToDevice,
+                               sim->stream));
+        return SF_OK;
+    }
     enqueue_policy(sim, d_actions);
     LAUNCHED();
     return SF_OK;
@@ -623,8 +653,11 @@ sf_status sf_policy_act(sf_sim *sim, float *d_actions) {
 sf_status sf_step_policy(sf_sim *sim, float dt, int32_t substeps) {
     CHECK_SIM(sim);
     if (!sim->policy_loaded) return fail(SF_E_INVALID_ARG, "no policy loaded");
-    enqueue_policy(sim, sim->pol_act);
-    LAUNCHED();
+    // the fused observation of the previous call may have left the actions
+    if (!sim->act_valid) {
+        enqueue_policy(sim, sim->pol_act);
+        LAUNCHED();
+    }
     return sf_step(sim, sim->pol_act, dt, substeps);
 }
 
@@ -639,6 +672,15 @@ sf_status sf_graph_capture(sf_sim *sim, int32_t K, float dt, int32_t substeps) {
     if (sim->graph) { (void)hipGraphDestroy(sim->graph); sim->graph = nullptr; }
     const bool prof = sim->prof;
     sim->prof = false;
+    // with the fused observation the actions of every later step come from
+    // it; the first one is computed now, outside the graph, so that replays
+    // follow the same launches as eager steps
+    if (sim->obs_waves == 16 && !sim->act_valid) {
+        enqueue_policy(sim, sim->pol_act);
+        LAUNCHED();
+        sim->act_valid = true;
+    }
+    const bool act_in = sim->act_valid;
     DEV(hipStreamBeginCapture(sim->stream, hipStreamCaptureModeThreadLocal));
     sf_status st = SF_OK;
     for (int k = 0; k < K && st == SF_OK; ++k) st = sf_step_policy(sim, dt, substeps);
@@ -648,6 +690,9 @@ sf_status sf_graph_capture(sf_sim *sim, int32_t K, float dt, int32_t substeps) {
     if (st != SF_OK) { if (g) (void)hipGraphDestroy(g); return st; }
     if (e != hipSuccess) { sim->bad = true; return fail(SF_E_DEVICE, std::string("capture: ") + hipGetErrorString(e)); }
     sim->graph = g;
+    sim->graph_act_in = act_in;
+    sim->graph_act_out = sim->act_valid;
+    sim->act_valid = act_in;  // nothing ran yet
     DEV(hipGraphInstantiate(&sim->graph_exec, g, nullptr, nullptr, 0));
     return SF_OK;
 }
@@ -655,7 +700,13 @@ sf_status sf_graph_capture(sf_sim *sim, int32_t K, float dt, int32_t substeps) {
 sf_status sf_graph_launch(sf_sim *sim) {
     CHECK_SIM(sim);
     if (!sim->graph_exec) return fail(SF_E_INVALID_ARG, "no graph captured");
+    // a graph that begins without a policy launch needs the current actions
+    if (sim->graph_act_in && !sim->act_valid) {
+        enqueue_policy(sim, sim->pol_act);
+        LAUNCHED();
+    }
     DEV(hipGraphLaunch(sim->graph_exec, sim->stream));
+    sim->act_valid = sim->graph_act_out;
     return SF_OK;
 }
 
@@ -966,10 +1017,7 @@ sf_status sf_reset(sf_sim *sim, const uint8_t *d_mask) {
         ProfScope ps(sim, 3);
         launch_reset(sim->P_dev, sim->Wd, sim->st, sim->ist, d_mask, 1, sim->stream);
     }
-    {
-        ProfScope ps(sim, 2);
-        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, sim->stream);
-    }
+    enqueue_obs(sim);
     LAUNCHED();
     return SF_OK;
 }
@@ -993,7 +1041,7 @@ sf_status sf_set_state(sf_sim *sim, const void *host_src, size_t bytes) {
     if (!host_src || bytes != sf_state_bytes(sim))
         return fail(SF_E_INVALID_ARG, "host_src NULL or bytes != sf_state_bytes");
     if (bytes) DEV(hipMemcpyAsync(sim->st, host_src, bytes, hipMemcpyHostToDevice, sim->stream));
-    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, sim->stream);
+    enqueue_obs(sim);
     LAUNCHED();
     DEV(hipStreamSynchronize(sim->stream));
     return SF_OK;
@@ -1035,7 +1083,8 @@ sf_status sf_debug_obs_indices(sf_sim *sim, int32_t *h_out) {
     if (sim->N == 0) return SF_OK;
     int *buf = nullptr;
     DEV(hipMalloc(&buf, sizeof(int) * 72 * (size_t)sim->N));
-    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, buf, sim->hint, sim->obs_waves, sim->stream);
+    launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, buf, sim->hint,
+               sim->obs_waves == 16 ? 4 : sim->obs_waves, sim->stream);
     LAUNCHED();
     DEV(hipMemcpyAsync(h_out, buf, sizeof(int) * 72 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream));
     DEV(hipStreamSynchronize(sim->stream));
@@ -1050,7 +1099,7 @@ static bool tuning_ok(const sf_tuning &t) {
     bool blk = false;
     for (int b : k_step_blocks) blk = blk || t.step_block == b;
     return blk && t.step_grid >= 0 &&
-           (t.obs_waves == 1 || t.obs_waves == 2 || t.obs_waves == 4) &&
+           (t.obs_waves == 1 || t.obs_waves == 2 || t.obs_waves == 4 || t.obs_waves == 16) &&
            (t.policy_rows == 16 || t.policy_rows == 32 || t.policy_rows == 64);
 }
 
@@ -1075,7 +1124,7 @@ sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out) {
 sf_status sf_set_tuning(sf_sim *sim, const sf_tuning *t) {
     CHECK_SIM(sim);
     if (!t || !tuning_ok(*t))
-        return fail(SF_E_INVALID_ARG, "step_block in {64,128,192,256,320}, step_grid >= 0, obs_waves 1/2/4, "
+        return fail(SF_E_INVALID_ARG, "step_block in {64,128,192,256,320}, step_grid >= 0, obs_waves 1/2/4/16, "
                                       "policy_rows 16/32/64");
     tuning_apply(sim, *t);
     return SF_OK;
@@ -1143,7 +1192,7 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
         DEV(hipMemcpyAsync(sim->reward, snap + sb, 4 * N, hipMemcpyDeviceToDevice, st));
         DEV(hipMemcpyAsync(sim->done, snap + sb + 4 * N, N, hipMemcpyDeviceToDevice, st));
         DEV(hipMemcpyAsync(sim->events, snap + sb + 5 * N, N, hipMemcpyDeviceToDevice, st));
-        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint, sim->obs_waves, st);
+        enqueue_obs(sim);
         LAUNCHED();
         return SF_OK;
     };
@@ -1187,20 +1236,28 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
         }
         if (r != SF_OK) break;
     }
-    for (int wv : {1, 2, 4}) {
-        if (r != SF_OK) break;
-        sf_tuning t = best;
-        t.obs_waves = wv;
-        if ((r = trial(t, ms)) != SF_OK) break;
-        if (ms[2] < best_ms[2]) { best_ms[2] = ms[2]; best.obs_waves = wv; }
-    }
+    // policy tiles first (with a plain observation), then the observation
+    // shapes, each scored with the policy time it leaves per step (none when
+    // the fused kernel computes the actions)
     for (int rows : {16, 32, 64}) {
         if (r != SF_OK || !sim->policy_loaded) break;
         sf_tuning t = best;
         t.policy_rows = rows;
+        if (t.obs_waves == 16) t.obs_waves = 4;
         if ((r = trial(t, ms)) != SF_OK) break;
         if (ms[0] < best_ms[0]) { best_ms[0] = ms[0]; best.policy_rows = rows; }
     }
+    double best_op = 1e30;
+    for (int wv : {1, 2, 4, 16}) {
+        if (r != SF_OK) break;
+        if (wv == 16 && !sim->policy_loaded) continue;
+        sf_tuning t = best;
+        t.obs_waves = wv;
+        if ((r = trial(t, ms)) != SF_OK) break;
+        const double op = ms[2] + (wv == 16 ? 0.0 : (sim->policy_loaded ? best_ms[0] : 0.0));
+        if (op < best_op) { best_op = op; best_ms[2] = ms[2]; best.obs_waves = wv; }
+    }
+    if (best.obs_waves == 16) best_ms[0] = 0.0;
     sim->sur_log = log_keep;
     sim->prof = prof_keep;
     tuning_apply(sim, best);

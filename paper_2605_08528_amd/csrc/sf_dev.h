@@ -272,6 +272,9 @@ void launch_sur_grad_seq(const float *data, int M, const float *P, const uint16_
 void launch_obs(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
                 int *dbg_idx, float4 *hint, int waves, hipStream_t s);
 void launch_hint_clear(float4 *hint, int n, hipStream_t s);
+void launch_obs_policy(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
+                       float4 *hint, const uint16_t *W1, const float *b1, const uint16_t *W2, const float *b2,
+                       const uint16_t *W3, const float *b3, float steer_max, float *act, hipStream_t s);
 void launch_to_bf16(const float *src, uint16_t *dst, int n, hipStream_t s);
 void launch_policy(const float *obs, int N, const uint16_t *W1, const float *b1, const uint16_t *W2,
                    const float *b2, const uint16_t *W3, const float *b3, float steer_max, float *act,

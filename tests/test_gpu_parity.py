@@ -464,8 +464,9 @@ def test_policy_mfma_matches_oracle(O, torch):
     bf16 rounding points: relative error per output norm <= 1e-2."""
     w = I.intersections(40, 8, seed=13)      # 320 agents: several 64-row tiles + a ragged tail
     from paper_2605_08528_amd import sf
-    for rows in (16, 32, 64):
-        sim = sf.Sim(w, mkparams(), policy_rows=rows)
+    # 16: one kernel computes the observation and the actions
+    for rows, waves in ((16, 0), (32, 0), (64, 0), (16, 16)):
+        sim = sf.Sim(w, mkparams(), policy_rows=rows, obs_waves=waves)
         Ws, bs = I.mlp_params([256, 256, 256, 2], seed=5)
         bs = [np.random.default_rng(9).standard_normal(b.shape).astype(np.float32) * 0.1 for b in bs]
         sim.policy_load(Ws, bs)
@@ -475,21 +476,22 @@ def test_policy_mfma_matches_oracle(O, torch):
         a_g = sim.policy_act().cpu().numpy().astype(np.float64)
         a_o = O.policy(Ws, bs, obs.cpu().numpy(), steer_max=0.5)
         rel = np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)
-        print("policy rows", rows, "relative error", rel, "max abs", np.abs(a_g - a_o).max())
+        print("policy rows", rows, "obs waves", waves, "relative error", rel, "max abs", np.abs(a_g - a_o).max())
         assert rel <= 1e-2
         assert np.abs(a_g[:, 1]).max() <= 0.5 + 1e-6
         sim.close()
 
 
 # ------------------------------------------------------ graphs, determinism
-def test_graph_replay_matches_eager(O, torch):
+@pytest.mark.parametrize("obs_waves", [0, 16])
+def test_graph_replay_matches_eager(O, torch, obs_waves):
     from paper_2605_08528_amd import sf
     w = I.uneven_manhattan(16, agents=(4, 32), points=(1000, 5000), seed=14, mean_agents=16)
     Ws, bs = I.mlp_params([256, 256, 256, 2], seed=6)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        a = sf.Sim(w, mkparams(max_episode_steps=9), flags=sf.SF_AUTO_RESET, stream=stream)
-        b = sf.Sim(w, mkparams(max_episode_steps=9), flags=sf.SF_AUTO_RESET, stream=stream)
+        a = sf.Sim(w, mkparams(max_episode_steps=9), flags=sf.SF_AUTO_RESET, stream=stream, obs_waves=obs_waves)
+        b = sf.Sim(w, mkparams(max_episode_steps=9), flags=sf.SF_AUTO_RESET, stream=stream, obs_waves=obs_waves)
         a.policy_load(Ws, bs)
         b.policy_load(Ws, bs)
         b.graph_capture(5, 1.0 / 30.0, 4)
@@ -544,3 +546,73 @@ def test_step_block_sizes(O, torch, block):
     worst, n_pairs = lockstep(O, torch, w, 30, 1.0 / 120.0, 1, prm=prm, flags=1, init=closing,
                               step_block=block)
     assert n_pairs > 0
+
+
+def test_fused_policy_follows_state_changes(O, torch):
+    """The actions left by the fused observation kernel track every change of
+    state (step, reset, set_state, a newly loaded network, a change of launch
+    shape) and equal a fresh evaluation of the network on the observation."""
+    from paper_2605_08528_amd import sf
+    w = I.intersections(12, 24, seed=21)
+    Ws, bs = I.mlp_params([256, 256, 256, 2], seed=7)
+    W2s, b2s = I.mlp_params([256, 256, 256, 2], seed=8)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        fused = sf.Sim(w, mkparams(max_episode_steps=7), flags=sf.SF_AUTO_RESET, stream=stream, obs_waves=16)
+        plain = sf.Sim(w, mkparams(max_episode_steps=7), flags=sf.SF_AUTO_RESET, stream=stream, obs_waves=4)
+        for s_ in (fused, plain):
+            s_.policy_load(Ws, bs)
+
+        def check(tag):
+            torch.cuda.synchronize()
+            o_f, o_p = fused.observe()[0], plain.observe()[0]
+            assert torch.equal(o_f, o_p), tag
+            a_f = fused.policy_act().cpu().numpy().astype(np.float64)
+            a_p = plain.policy_act().cpu().numpy().astype(np.float64)
+            rel = np.linalg.norm(a_f - a_p) / max(np.linalg.norm(a_p), 1e-30)
+            assert rel <= 1e-2, (tag, rel)
+            return a_f, a_p
+
+        for step in range(4):
+            a = cuda(torch, I.actions(21, step, fused.N))
+            fused.step(a, 1.0 / 30.0, 4)
+            plain.step(a, 1.0 / 30.0, 4)
+            check(("step", step))
+        mask = np.zeros(fused.N, np.uint8)
+        mask[::3] = 1
+        fused.reset(cuda(torch, mask))
+        plain.reset(cuda(torch, mask))
+        check("reset")
+        f, k = plain.get_state()
+        f[7] *= 0.5
+        fused.set_state(f, k)
+        plain.set_state(f, k)
+        check("set_state")
+        fused.policy_load(W2s, b2s)
+        plain.policy_load(W2s, b2s)
+        check("reload")
+        a = cuda(torch, I.actions(21, 5, fused.N))
+        fused.step(a, 1.0 / 30.0, 4)
+        plain.step(a, 1.0 / 30.0, 4)
+        a_f, _ = check("step after reload")
+        a_o = O.policy(W2s, b2s, plain.observe()[0].cpu().numpy(), steer_max=0.5)
+        assert np.linalg.norm(a_f - a_o) / np.linalg.norm(a_o) <= 1e-2
+        # a captured graph that starts from the fused actions, replayed after
+        # the launch shape changed to the plain observation
+        fused.step_policy(1.0 / 30.0, 4)
+        fused.graph_capture(3, 1.0 / 30.0, 4)
+        t = fused.tuning()
+        fused.set_tuning(t["step_block"], t["step_grid"], 4, t["policy_rows"])
+        fused.step(cuda(torch, I.actions(21, 9, fused.N)), 1.0 / 30.0, 4)
+        f_ref, k_ref = fused.get_state()
+        plain.set_state(f_ref, k_ref)
+        fused.graph_launch()
+        for _ in range(3):
+            plain.step_policy(1.0 / 30.0, 4)
+        torch.cuda.synchronize()
+        ff, kf = fused.get_state()
+        fp, kp = plain.get_state()
+        assert np.array_equal(kf, kp)
+        assert np.abs(ff - fp).max() <= 1e-3 * max(1.0, np.abs(fp).max())
+        fused.close()
+        plain.close()

@@ -80,9 +80,11 @@ def test_autotune_restores_state_and_caches(torch, tmp_path):
         f1, k1 = sim.get_state()
         obs1 = sim.observe()[0].cpu().numpy()
         assert np.array_equal(f0, f1) and np.array_equal(k0, k1) and np.array_equal(obs0, obs1)
-        assert t["step_block"] in (64, 128, 192, 256, 320) and t["obs_waves"] in (1, 2, 4)
+        assert t["step_block"] in (64, 128, 192, 256, 320) and t["obs_waves"] in (1, 2, 4, 16)
         assert t["policy_rows"] in (16, 32, 64) and t["step_grid"] >= 0
-        assert t["step_us"] > 0 and t["obs_us"] > 0 and t["policy_us"] > 0
+        assert t["step_us"] > 0 and t["obs_us"] > 0
+        # the fused observation leaves no policy launch to time
+        assert (t["policy_us"] > 0) != (t["obs_waves"] == 16)
         assert sim.tuning()["step_block"] == t["step_block"]
         print("autotuned shapes", t)
         # the chosen shapes step on as usual
