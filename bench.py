@@ -34,6 +34,15 @@ BF16_PEAK_TFLOPS = 2500.0
 STEP_BYTES_PER_AGENT = 2 * 112 + 8 + 6        # state read + write, actions, reward/done/events
 OBS_BYTES_PER_AGENT = 1024 + 64               # observation row write + own state read
 POLICY_FLOP_PER_AGENT = 2 * (256 * 256 * 2 + 256 * 2)
+POLICY_WEIGHT_BYTES = 132098 * 2              # bf16 copies of the three layers read once per launch
+ACT_BYTES_PER_AGENT = 8                       # two float actions written
+
+
+def obs_bytes(n_agents: int, fused: bool) -> int:
+    """Algorithmic bytes of one observation launch; the kernel that also
+    evaluates the policy reads the network once and writes the actions."""
+    b = OBS_BYTES_PER_AGENT * n_agents
+    return b + (POLICY_WEIGHT_BYTES + ACT_BYTES_PER_AGENT * n_agents if fused else 0)
 
 
 def log(*a):
@@ -292,8 +301,8 @@ def main():
         roof = {"bound": "mfma", "achieved": flop / avg_s / 1e12, "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "traffic": None}
     else:
-        per = STEP_BYTES_PER_AGENT if dom == "step" else OBS_BYTES_PER_AGENT
-        roof = {"bound": "hbm", "achieved": per * N / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+        nbytes = STEP_BYTES_PER_AGENT * N if dom == "step" else obs_bytes(N, tuning["obs_waves"] == 16)
+        roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"]
     launch = {"policy": "k_policy_lds<16>" if tuning["policy_rows"] <= 16 else f"k_policy<{tuning['policy_rows']}>",
@@ -306,8 +315,10 @@ def main():
         if name == "policy":
             kernels[name]["tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
         elif name in ("step", "obs"):
-            per = STEP_BYTES_PER_AGENT if name == "step" else OBS_BYTES_PER_AGENT
-            kernels[name]["algorithmic_gbs"] = per * N / (kernels[name]["avg_us"] * 1e-6) / 1e9
+            nbytes = STEP_BYTES_PER_AGENT * N if name == "step" else obs_bytes(N, tuning["obs_waves"] == 16)
+            kernels[name]["algorithmic_gbs"] = nbytes / (kernels[name]["avg_us"] * 1e-6) / 1e9
+            if name == "obs" and tuning["obs_waves"] == 16:
+                kernels[name]["policy_tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
 
     cpu = None
     if not args.no_cpu_baseline:
