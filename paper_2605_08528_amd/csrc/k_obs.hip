@@ -497,9 +497,12 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
 // step's actions are ready when the observation is: the policy's own launch
 // and its re-read of the observations disappear, and a workgroup whose
 // agents were quick runs its network while others still search.  Wave w
-// computes output columns [16 w, 16 w + 16) of each hidden layer with weight
-// fragments from L2, one k-step ahead.
+// computes output columns [16 w, 16 w + 16) of each hidden layer; as soon
+// as its observation is done (its registers free again) it issues the loads
+// of all its weight fragments for both layers, which then arrive while the
+// workgroup waits for its slowest agent.
 #define OP_LD (SF_OBS_DIM + 8)  // padded bf16 activation row
+#define OP_KS (SF_OBS_DIM / 32)  // k-steps of 32 per layer
 
 __device__ __forceinline__ float elu_fast(float x) {
     if (x > 0.f) return x;
@@ -507,18 +510,22 @@ __device__ __forceinline__ float elu_fast(float x) {
     return __expf(x) - 1.f;
 }
 
+// this lane's B fragments of wave w's 16 columns, all k-steps
+__device__ __forceinline__ void op_fetch(const uint16_t *__restrict__ W, bf16x8 (&f)[OP_KS]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+    const uint16_t *wrow = W + (size_t)(wv * 16 + r16) * SF_OBS_DIM + kq * 8;
+#pragma unroll
+    for (int kk = 0; kk < OP_KS; ++kk) f[kk] = *reinterpret_cast<const bf16x8 *>(wrow + 32 * kk);
+}
+
 __device__ __forceinline__ void op_layer(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
-                                         const uint16_t *__restrict__ W, const float *__restrict__ b) {
+                                         const bf16x8 (&f)[OP_KS], const float *__restrict__ b) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-    const uint16_t *wrow = W + (size_t)(wv * 16 + r16) * SF_OBS_DIM + kq * 8;
-    bf16x8 bn = *reinterpret_cast<const bf16x8 *>(wrow);
 #pragma unroll
-    for (int kk = 0; kk < SF_OBS_DIM / 32; ++kk) {
-        const bf16x8 bf = bn;
-        if (kk + 1 < SF_OBS_DIM / 32) bn = *reinterpret_cast<const bf16x8 *>(wrow + 32 * (kk + 1));
+    for (int kk = 0; kk < OP_KS; ++kk) {
         const bf16x8 af = *reinterpret_cast<const bf16x8 *>(in + r16 * OP_LD + kk * 32 + kq * 8);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, f[kk], acc, 0, 0, 0);
     }
     const int col = wv * 16 + r16;
     const float bias = b[col];
@@ -546,6 +553,9 @@ __global__ __launch_bounds__(1024) void k_obs_policy(DevParams P, DevWorld Wd, c
     if (n < Wd.N)
         ok = obs_agent(P, Wd, st, ist, obs, nullptr, hint, n, s_cand[wv], s_row[wv], s_sel[wv], s_segs[wv],
                        s_segp[wv]);
+    bf16x8 f1[OP_KS], f2[OP_KS];
+    op_fetch(W1, f1);
+    op_fetch(W2, f2);
     // the row as bf16 (zeros for an inactive agent or past the end)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -553,9 +563,9 @@ __global__ __launch_bounds__(1024) void k_obs_policy(DevParams P, DevWorld Wd, c
         s_pa[wv * OP_LD + c] = f2bf(ok ? s_row[wv][c] : 0.f);
     }
     __syncthreads();
-    op_layer(s_pa, s_pb, W1, b1);
+    op_layer(s_pa, s_pb, f1, b1);
     __syncthreads();
-    op_layer(s_pb, s_pa, W2, b2);
+    op_layer(s_pb, s_pa, f2, b2);
     __syncthreads();
     // head: 32 outputs, each split over 32 lanes and summed in a fixed
     // butterfly order
