@@ -8,6 +8,16 @@
 __device__ int g_sf_overflow;  // contact-capacity overflows (diagnostic)
 
 // ---------------------------------------------------------------- raycast
+// body-frame mount point of wheel wh: selects between the four (uniform)
+// parameter entries rather than an indexed read of the argument block,
+// which would be a memory round trip on every substep
+__device__ __forceinline__ f3 mount_of(const DevParams &P, int wh) {
+    const float x = wh == 0 ? P.mount[0][0] : wh == 1 ? P.mount[1][0] : wh == 2 ? P.mount[2][0] : P.mount[3][0];
+    const float y = wh == 0 ? P.mount[0][1] : wh == 1 ? P.mount[1][1] : wh == 2 ? P.mount[2][1] : P.mount[3][1];
+    const float z = wh == 0 ? P.mount[0][2] : wh == 1 ? P.mount[1][2] : wh == 2 ? P.mount[2][2] : P.mount[3][2];
+    return mk3(x, y, z);
+}
+
 __device__ __forceinline__ float mt_rec(const float4 &a, const float4 &b, const float4 &c, f3 m, f3 u,
                                         float ell) {
     const f3 e1 = mk3(b.x, b.y, b.z), e2 = mk3(c.x, c.y, c.z);
@@ -32,18 +42,38 @@ struct RayHit {
     f3 n;
 };
 
+// record hit (t, id) of record k: the nearest distance so far and up to 4
+// distinct triangle hits, in separate registers (an indexed array here
+// would be placed in scratch memory)
+#define RAY_HIT(t_, id_, k_)                                                        \
+    do {                                                                            \
+        tmin = fminf(tmin, (t_));                                                   \
+        const int idh = (id_);                                                      \
+        if (idh != i0 && idh != i1 && idh != i2 && idh != i3) {                     \
+            if (nh == 0) { t0 = (t_); i0 = idh; k0 = (k_); }                        \
+            else if (nh == 1) { t1 = (t_); i1 = idh; k1 = (k_); }                   \
+            else if (nh == 2) { t2 = (t_); i2 = idh; k2 = (k_); }                   \
+            else if (nh == 3) { t3 = (t_); i3 = idh; k3 = (k_); }                   \
+            ++nh;                                                                   \
+        }                                                                           \
+    } while (0)
+
 // Nearest hit of the wheel ray against the ground plane z = 0 and the road
 // triangles of the triangle-grid cells under the ray's footprint.  Hits
 // within 0.1 mm of the nearest are one surface point: a road triangle wins
 // over the ground, the lowest triangle index first.  One pass keeps up to 4
 // distinct triangle hits in registers; more (stacked geometry) triggers a
-// second pass that applies the same rule.
-__device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, const GridHdr &g, bool any_tri, f3 m, f3 u) {
+// second pass that applies the same rule.  The record ranges of two cell
+// rows are fetched together and their records tested in batches of 8 whose
+// loads are all in flight at once (the rule does not depend on the order in
+// which records are visited).
+__device__ __forceinline__ RayHit raycast(const DevParams &P, const DevWorld &Wd, const GridHdr &g, bool any_tri,
+                                        f3 m, f3 u) {
     const float ell = P.ell;
-    float tmin = INFINITY, tg = INFINITY;
+    float tg = INFINITY;
     if (u.z < 0.f) {
         const float t = m.z / (-u.z);
-        if (t >= 0.f && t <= ell) { tg = t; tmin = t; }
+        if (t >= 0.f && t <= ell) tg = t;
     }
     RayHit H;
     H.tri = -1;
@@ -51,7 +81,7 @@ __device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, const GridHdr 
     H.t = tg;
     H.n = mk3(0.f, 0.f, 1.f);
     if (!any_tri) {
-        H.hit = tmin < INFINITY;
+        H.hit = tg < INFINITY;
         return H;
     }
     const float ex = m.x + ell * u.x, ey = m.y + ell * u.y;
@@ -61,38 +91,32 @@ __device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, const GridHdr 
     int cy1 = (int)floorf((fmaxf(m.y, ey) - g.y0) * g.inv_cell);
     cx0 = max(0, min(cx0, g.nx - 1)); cx1 = max(0, min(cx1, g.nx - 1));
     cy0 = max(0, min(cy0, g.ny - 1)); cy1 = max(0, min(cy1, g.ny - 1));
-    int nh = 0;
-    float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
-    int i0 = -1, i1 = -1, i2 = -1, i3 = -1, k0 = -1, k1 = -1, k2 = -1, k3 = -1;
-    for (int cy = cy0; cy <= cy1; ++cy) {
-        const int c0 = g.cbase + cy * g.nx;
-        const int s = Wd.tri_cell_start[c0 + cx0], e = Wd.tri_cell_start[c0 + cx1 + 1];
-        // records in groups of 4: all loads of a group are in flight together
-        for (int kb = s; kb < e; kb += 4) {
-            float4 ra[4], rb[4], rc[4];
+    float tmin = tg, t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
+    int nh = 0, i0 = -1, i1 = -1, i2 = -1, i3 = -1, k0 = -1, k1 = -1, k2 = -1, k3 = -1;
+    // two cell rows at a time (the second empty unless the footprint spans it)
+    for (int cy = cy0; cy <= cy1; cy += 2) {
+        const int ca = g.cbase + cy * g.nx, cb = g.cbase + min(cy + 1, g.ny - 1) * g.nx;
+        const int sA = Wd.tri_cell_start[ca + cx0], eA = Wd.tri_cell_start[ca + cx1 + 1];
+        const int sB = Wd.tri_cell_start[cb + cx0], eB = Wd.tri_cell_start[cb + cx1 + 1];
+        const int nA = eA - sA, nAB = nA + (cy < cy1 ? eB - sB : 0);
+        for (int rb = 0; rb < nAB; rb += 8) {
+            float4 ra[8], rbv[8], rc[8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (kb + q < e) {
-                    ra[q] = Wd.tri_rec[3 * (size_t)(kb + q)];
-                    rb[q] = Wd.tri_rec[3 * (size_t)(kb + q) + 1];
-                    rc[q] = Wd.tri_rec[3 * (size_t)(kb + q) + 2];
+            for (int q = 0; q < 8; ++q) {
+                const int r = rb + q;
+                if (r < nAB) {
+                    const size_t k = (size_t)(r < nA ? sA + r : sB + (r - nA));
+                    ra[q] = Wd.tri_rec[3 * k];
+                    rbv[q] = Wd.tri_rec[3 * k + 1];
+                    rc[q] = Wd.tri_rec[3 * k + 2];
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (kb + q >= e) break;
-                const int k = kb + q;
-                const float t = mt_rec(ra[q], rb[q], rc[q], m, u, ell);
-                if (t < INFINITY) {
-                    const int id = __float_as_int(ra[q].w);
-                    tmin = fminf(tmin, t);
-                    if (id == i0 || id == i1 || id == i2 || id == i3) continue;
-                    if (nh == 0) { t0 = t; i0 = id; k0 = k; }
-                    else if (nh == 1) { t1 = t; i1 = id; k1 = k; }
-                    else if (nh == 2) { t2 = t; i2 = id; k2 = k; }
-                    else if (nh == 3) { t3 = t; i3 = id; k3 = k; }
-                    ++nh;
-                }
+            for (int q = 0; q < 8; ++q) {
+                const int r = rb + q;
+                if (r >= nAB) break;
+                const float t = mt_rec(ra[q], rbv[q], rc[q], m, u, ell);
+                if (t < INFINITY) RAY_HIT(t, __float_as_int(ra[q].w), r < nA ? sA + r : sB + (r - nA));
             }
         }
     }
@@ -134,6 +158,7 @@ __device__ RayHit raycast(const DevParams &P, const DevWorld &Wd, const GridHdr 
     }
     return H;
 }
+#undef RAY_HIT
 
 // ------------------------------------------------------------------ tire
 // Linear-saturated tire in a friction circle with an implicit wheel-spin
@@ -550,7 +575,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             const f3 pos = mk3(s_p[0][i], s_p[1][i], s_p[2][i]);
                             v = mk3(s_v[0][i], s_v[1][i], s_v[2][i]);
                             om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
-                            rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
+                            rm = Rmul(R, mount_of(P, wh));
                             u = mk3(-R[2], -R[5], -R[8]);
                             const RayHit H = raycast(P, Wd, s_tgrid, s_anytri, add3(pos, rm), u);
                             Om = s_om[wi];
@@ -1037,7 +1062,7 @@ __global__ void k_debug_raycast(DevParams P, DevWorld Wd, const float *st, float
     const int N = Wd.N, n = wi >> 2, wh = wi & 3;
     float R[9];
     quat_R(st[SF_F_QW * N + n], st[SF_F_QX * N + n], st[SF_F_QY * N + n], st[SF_F_QZ * N + n], R);
-    const f3 rm = Rmul(R, mk3(P.mount[wh][0], P.mount[wh][1], P.mount[wh][2]));
+    const f3 rm = Rmul(R, mount_of(P, wh));
     const f3 m = add3(mk3(st[SF_F_PX * N + n], st[SF_F_PY * N + n], st[SF_F_PZ * N + n]), rm);
     const int w = Wd.world_of[n];
     RayHit H = raycast(P, Wd, Wd.tgrid[w], Wd.toff[w + 1] > Wd.toff[w], m, mk3(-R[2], -R[5], -R[8]));
