@@ -4,14 +4,18 @@
 A step is one pass of the whole hot path over the workload: policy MLP on
 the current observations, the fused physics step (4 substeps of steering,
 raycast suspension, tire and spin, chassis, vehicle-vehicle contact,
-integration, events, rewards, in-step respawn) and the observation gather.
-The default workload is 256 worlds with 4-32 vehicles each (4096 in total)
-on procedural road grids of 1k-20k points, dt = 1/30 s with 4 substeps.
+integration, events, rewards, in-step respawn) and the observation gather
+(which, in the autotuner's usual pick, also evaluates the policy for the
+next step).  The default workload is 256 worlds with 4-32 vehicles each
+(4096 in total) on procedural road grids of 1k-20k points, dt = 1/30 s with
+4 substeps.
 
 Prints one JSON line: controlled-agent steps per second (CASPS) over the
-timed steps, the dominant kernel against its roofline (per-kernel HIP events
-on the stream the kernels run on), and the FP64 CPU oracle's rate on a
-bounded sample of the same workload.
+timed steps, run as replays of captured graphs of up to 16 control steps and
+averaged over three seeded workloads; the dominant kernel against its
+roofline (per-kernel HIP events on the stream the kernels run on, from a
+profiled eager pass over the same number of steps); and the FP64 CPU
+oracle's rate on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -197,6 +201,98 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     }
 
 
+def graph_len(steps: int) -> int:
+    """Control steps per captured graph: the largest divisor of the timed
+    step count up to 16, so that whole replays cover exactly that count."""
+    return max(d for d in range(1, 17) if steps % d == 0)
+
+
+def copy_bandwidth(torch, stream) -> float:
+    """HBM bandwidth of a plain device-to-device copy (1 GiB read + 1 GiB
+    written per copy), GB/s: the practical ceiling beside the 8 TB/s spec."""
+    with torch.cuda.stream(stream):
+        x = torch.empty(256 * 2 ** 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            y.copy_(x)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gbs = 10 * 2 * x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return gbs
+
+
+def measure(args, seed, torch, sf, I, stream, keep=False):
+    """One seeded workload: warm-up, autotuned launch shapes, a profiled eager
+    pass over the timed step count (per-kernel HIP events on the handle's
+    stream), then the timed region: the same number of policy-driven control
+    steps as replays of a captured graph."""
+    worlds = I.workload(args.workload, seed=seed)
+    dt, S = I.TIMING[args.workload]
+    prm = dict(I.VEHICLE_DEFAULTS)
+    policy = I.mlp_params([256, 256, 256, 2], seed=seed)
+    K = args.steps
+    with torch.cuda.stream(stream):
+        sim = sf.Sim(worlds, prm, flags=sf.SF_AUTO_RESET, stream=stream, grid_cell=args.grid_cell,
+                     obs_waves=args.obs_waves, step_block=args.step_block,
+                     policy_rows=args.policy_rows)
+        sim.policy_load(*policy)
+        N = sim.N
+        log(f"seed {seed}: {args.workload}: {worlds.num_worlds} worlds, {N} agents, "
+            f"{len(worlds.road_xy)} road points, {len(worlds.tri_verts)} triangles")
+        for _ in range(args.warmup):
+            sim.step_policy(dt, S)
+        torch.cuda.synchronize()
+        tuning = sim.tuning()
+        if not args.no_autotune:
+            tuning = sim.autotune(dt, S, steps=args.tune_steps)
+            log(f"autotuned: {tuning}")
+
+        # profiled eager pass: per-kernel HIP events around every launch
+        sim.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(K):
+            sim.step_policy(dt, S)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        eager_ms = e0.elapsed_time(e1)
+        prof = sim.profile_read()
+        sim.profile(False)
+
+        # ---- timed region: K control steps as replays of a G-step graph
+        G = graph_len(K)
+        sim.graph_capture(G, dt, S)
+        for _ in range(2):
+            sim.graph_launch()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(K // G):
+            sim.graph_launch()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        ms = g0.elapsed_time(g1)
+        f, k = sim.get_state()
+        active = int(k[0].sum())
+    r = {"seed": seed, "casps": N * K / (ms / 1e3), "ms_per_step": ms / K, "graph_steps": G,
+         "eager_casps": N * K / (eager_ms / 1e3), "eager_ms_per_step": eager_ms / K, "active": active,
+         "N": N, "tuning": tuning, "prof": prof, "worlds": worlds, "prm": prm, "policy": policy,
+         "dt": dt, "S": S}
+    log(f"seed {seed}: graph {r['ms_per_step']:.4f} ms/step ({G}-step graphs), {r['casps']:.4g} CASPS; "
+        f"eager {r['eager_ms_per_step']:.4f} ms/step; active {active}/{N}")
+    if keep:
+        r["sim"] = sim
+    else:
+        sim.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,7 +300,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1500)
     ap.add_argument("--workload", default="uneven256")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--graph-steps", type=int, default=16)
+    ap.add_argument("--seeds", type=int, default=3, help="seeded workloads averaged (seed, seed+1, ...)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -220,73 +316,29 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step would shard by "
               "world across GPUs, and only the single-GPU step is implemented and measured", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.seeds < 1:
+        print("--steps and --seeds must be >= 1", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     from paper_2605_08528_amd import inputs as I, sf
 
     torch.cuda.set_device(0)
-    worlds = I.workload(args.workload, seed=args.seed)
-    dt, S = I.TIMING[args.workload]
-    prm = dict(I.VEHICLE_DEFAULTS)
-    policy = I.mlp_params([256, 256, 256, 2], seed=args.seed)
     stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        sim = sf.Sim(worlds, prm, flags=sf.SF_AUTO_RESET, stream=stream, grid_cell=args.grid_cell,
-                     obs_waves=args.obs_waves, step_block=args.step_block,
-                     policy_rows=args.policy_rows)
-        sim.policy_load(*policy)
-        N = sim.N
-        log(f"workload {args.workload}: {worlds.num_worlds} worlds, {N} agents, "
-            f"{len(worlds.road_xy)} road points, {len(worlds.tri_verts)} triangles")
-        for _ in range(args.warmup):
-            sim.step_policy(dt, S)
-        torch.cuda.synchronize()
-        # launch shapes measured on this workload (state restored afterwards)
-        tuning = sim.tuning()
-        if not args.no_autotune:
-            tuning = sim.autotune(dt, S, steps=args.tune_steps)
-            log(f"autotuned: {tuning}")
+    copy_gbs = copy_bandwidth(torch, stream)
+    log(f"device-to-device copy: {copy_gbs:.0f} GB/s")
+    runs = [measure(args, args.seed + i, torch, sf, I, stream, keep=(i == 0)) for i in range(args.seeds)]
+    r0 = runs[0]
+    sim, N, tuning, prof = r0["sim"], r0["N"], r0["tuning"], r0["prof"]
+    worlds, prm, policy, dt, S = r0["worlds"], r0["prm"], r0["policy"], r0["dt"], r0["S"]
+    vals = np.array([r["casps"] for r in runs])
+    value = float(vals.mean())
+    ms = float(np.mean([r["ms_per_step"] for r in runs]))
 
-        # ---- timed region: K policy-driven control steps, per-kernel events
-        sim.profile(True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            sim.step_policy(dt, S)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        prof = sim.profile_read()
-        sim.profile(False)
-        f, k = sim.get_state()
-        active = int(k[0].sum())
-        value = N * args.steps / (ms / 1e3)
-        log(f"eager: {ms / args.steps:.4f} ms/step, {value:.4g} CASPS, active {active}/{N}")
-
-        # ---- graph replay of the same step (context)
-        graph = None
-        if args.graph_steps > 0:
-            G = args.graph_steps
-            sim.graph_capture(G, dt, S)
-            for _ in range(2):
-                sim.graph_launch()
-            torch.cuda.synchronize()
-            reps = max(1, args.steps // G)
-            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            g0.record(stream)
-            for _ in range(reps):
-                sim.graph_launch()
-            g1.record(stream)
-            torch.cuda.synchronize()
-            gms = g0.elapsed_time(g1)
-            graph = {"casps": N * G * reps / (gms / 1e3), "ms_per_step": gms / (G * reps),
-                     "control_steps_per_graph": G, "replays": reps}
-            log(f"graph: {gms / (G * reps):.4f} ms/step, {graph['casps']:.4g} CASPS")
-
-        # ---- the same control step with the learned tire model inside
-        sur = None
-        if not args.no_surrogate:
+    # ---- the same control step with the learned tire model inside (seed 0)
+    sur = None
+    if not args.no_surrogate:
+        with torch.cuda.stream(stream):
             sur = surrogate_leg(sim, torch, sf, stream, dt, S, args.steps, min(args.warmup, 300),
                                 args.sur_log_steps)
 
@@ -296,28 +348,31 @@ def main():
             kernels[name] = {"avg_us": 1e3 * tot / cnt, "launches": cnt}
     dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
     avg_s = kernels[dom]["avg_us"] * 1e-6
+    fused = tuning["obs_waves"] == 16
     if dom == "policy":
         flop = POLICY_FLOP_PER_AGENT * N
         roof = {"bound": "mfma", "achieved": flop / avg_s / 1e12, "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "traffic": None}
     else:
-        nbytes = STEP_BYTES_PER_AGENT * N if dom == "step" else obs_bytes(N, tuning["obs_waves"] == 16)
+        nbytes = STEP_BYTES_PER_AGENT * N if dom == "step" else obs_bytes(N, fused)
         roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "traffic": None}
+                "unit": "GB/s", "traffic": None, "measured_copy_gbs": copy_gbs}
     roof["frac"] = roof["achieved"] / roof["peak"]
     launch = {"policy": "k_policy_lds<16>" if tuning["policy_rows"] <= 16 else f"k_policy<{tuning['policy_rows']}>",
               "step": f"k_step<{tuning['step_block']}, false>",
-              "obs": "k_obs_policy" if tuning["obs_waves"] == 16 else f"k_obs<{tuning['obs_waves']}>"}
+              "obs": "k_obs_policy" if fused else f"k_obs<{tuning['obs_waves']}>"}
     roof["kernel"] = launch[dom]
     roof["traffic"] = recorded_traffic({"policy": "k_policy", "step": "k_step", "obs": "k_obs"}[dom],
                                        launch[dom], N)
+    roof["timing"] = ("mean HIP-event duration of the kernel over a profiled eager pass of the same "
+                      "control steps, seed %d" % args.seed)
     for name in kernels:
         if name == "policy":
             kernels[name]["tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
         elif name in ("step", "obs"):
-            nbytes = STEP_BYTES_PER_AGENT * N if name == "step" else obs_bytes(N, tuning["obs_waves"] == 16)
+            nbytes = STEP_BYTES_PER_AGENT * N if name == "step" else obs_bytes(N, fused)
             kernels[name]["algorithmic_gbs"] = nbytes / (kernels[name]["avg_us"] * 1e-6) / 1e9
-            if name == "obs" and tuning["obs_waves"] == 16:
+            if name == "obs" and fused:
                 kernels[name]["policy_tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
 
     cpu = None
@@ -332,7 +387,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -343,15 +398,24 @@ def main():
                         f"({int(np.diff(worlds.agent_offsets).min())}-{int(np.diff(worlds.agent_offsets).max())} per world), "
                         f"{len(worlds.road_xy)} road points, dt {dt:.4f} s x {S} substeps, "
                         "plain tire, policy MLP 256-256-256-2 bf16/fp32-acc",
-            "step": ("physics step + observation with the next actions in the same kernel (eager launches)"
-                     if tuning["obs_waves"] == 16 else "policy + physics step + observation (eager launches)"),
-            "active_agents": active,
+            "step": ("physics step + observation with the next actions in the same kernel"
+                     if fused else "policy + physics step + observation"),
+            "timed": f"{args.steps} control steps as replays of {r0['graph_steps']}-step hipGraphs, "
+                     f"mean over seeds {[r['seed'] for r in runs]}",
+            "active_agents": r0["active"],
             "launch_shapes": {k: tuning[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows")},
         },
+        "value_stdev": float(vals.std(ddof=1)) if len(runs) > 1 else 0.0,
+        "seeds": [{"seed": r["seed"], "casps": r["casps"], "ms_per_step": r["ms_per_step"],
+                   "eager_casps": r["eager_casps"],
+                   "launch_shapes": {k: r["tuning"][k] for k in ("step_block", "step_grid", "obs_waves",
+                                                                  "policy_rows")}} for r in runs],
+        "eager": {"casps": float(np.mean([r["eager_casps"] for r in runs])),
+                  "ms_per_step": float(np.mean([r["eager_ms_per_step"] for r in runs])),
+                  "note": "one launch per kernel from the host, per-kernel events on"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels,
-        "graph": graph,
         "surrogate": sur,
         "paper_context": {"casps": 19250, "hardware": "RTX PRO 6000 Blackwell, PhysX, 256x16"},
     }
