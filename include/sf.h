@@ -357,17 +357,23 @@ typedef struct {
     float step_us, obs_us, policy_us;  /* measured median durations (0 if cached;
                                           policy_us 0 when the observation
                                           kernel computes the actions)       */
+    float grid_cell;      /* road-point grid cell (m), 0.25..1000; 0 = keep     */
+    float tri_cell;       /* triangle grid cell (m), 0.05..100; 0 = keep        */
 } sf_tuning;
 
 sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out);
 /* Apply launch shapes (the timing fields are ignored); invalid values are
- * rejected and nothing changes. */
+ * rejected and nothing changes.  Other cell sizes rebuild the grids on the
+ * handle's stream (synchronising, dropping a captured graph); the kNN and
+ * ray results do not depend on them. */
 sf_status sf_set_tuning(sf_sim *sim, const sf_tuning *t);
 /* Time every candidate shape of the step, observation and policy kernels
  * over `steps` control steps driven by the loaded policy (zero actions if
  * none; two untimed steps first), each from the same snapshot of the state,
  * which is restored at the end; keep the shape with the smallest median
- * duration for each kernel.  With cache_path (a text file, one
+ * duration for each kernel.  Then the grid cells: road-point cells of 4, 8
+ * and 16 m scored by the observation, triangle cells of 0.5 and 1 m by the
+ * step (each a rebuild of the grids; a captured graph is dropped).  With cache_path (a text file, one
  * line per workload signature: worlds, agents, largest world, road points,
  * triangles, substeps, device), a line for this workload is applied without
  * measuring, and a new result is added.  Synchronises. */

@@ -18,20 +18,28 @@ __device__ __forceinline__ f3 mount_of(const DevParams &P, int wh) {
     return mk3(x, y, z);
 }
 
+// Ray-triangle test (Moller-Trumbore) on a packed record: v0, edges e1 and
+// e2.  Every product-sum is an explicit fused multiply-add and the compiler
+// may fuse nothing else, so a call rounds the same wherever it is inlined
+// (the records of a ray sit at layout-dependent places in its batch).
 __device__ __forceinline__ float mt_rec(const float4 &a, const float4 &b, const float4 &c, f3 m, f3 u,
                                         float ell) {
-    const f3 e1 = mk3(b.x, b.y, b.z), e2 = mk3(c.x, c.y, c.z);
-    const f3 pv = cross3(u, e2);
-    const float det = dot3(e1, pv);
+#pragma clang fp contract(off)
+    const float pvx = fmaf(u.y, c.z, -(u.z * c.y));
+    const float pvy = fmaf(u.z, c.x, -(u.x * c.z));
+    const float pvz = fmaf(u.x, c.y, -(u.y * c.x));
+    const float det = fmaf(b.x, pvx, fmaf(b.y, pvy, b.z * pvz));
     if (fabsf(det) < 1e-12f) return INFINITY;
     const float inv = 1.f / det;
-    const f3 tv = mk3(m.x - a.x, m.y - a.y, m.z - a.z);
-    const float bu = dot3(tv, pv) * inv;
+    const float tx = m.x - a.x, ty = m.y - a.y, tz = m.z - a.z;
+    const float bu = fmaf(tx, pvx, fmaf(ty, pvy, tz * pvz)) * inv;
     if (bu < 0.f || bu > 1.f) return INFINITY;
-    const f3 qv = cross3(tv, e1);
-    const float bv = dot3(u, qv) * inv;
+    const float qx = fmaf(ty, b.z, -(tz * b.y));
+    const float qy = fmaf(tz, b.x, -(tx * b.z));
+    const float qz = fmaf(tx, b.y, -(ty * b.x));
+    const float bv = fmaf(u.x, qx, fmaf(u.y, qy, u.z * qz)) * inv;
     if (bv < 0.f || bu + bv > 1.f) return INFINITY;
-    const float t = dot3(e2, qv) * inv;
+    const float t = fmaf(c.x, qx, fmaf(c.y, qy, c.z * qz)) * inv;
     if (t < 0.f || t > ell) return INFINITY;
     return t;
 }

@@ -35,6 +35,12 @@ struct sf_sim {
     int step_grid = 0, cus = 256;  // persistent step: workgroups (0: one per world); compute units
     int *queue = nullptr;          // [2] world counter and finished-workgroup counter
     float4 *hint = nullptr;        // [N] last observation's position and 64th road distance
+    // grids: the road-point grid (observation kNN) and the triangle grid
+    // (wheel rays) with their requested cell sizes, rebuilt when these change
+    float grid_cell = 8.f, tri_cell = 0.5f;
+    const float *verts = nullptr;  // [T][3][3] triangle vertices
+    const float4 *bbox = nullptr;  // [W] road bounding boxes
+    std::vector<void *> grid_bufs;
     DevParams P_dev{};
     DevWorld Wd{};
     float *st = nullptr;       // [NF][N]
@@ -221,6 +227,109 @@ static sf_status check_csr(const int32_t *off, int W, const char *name, int *tot
     return SF_OK;
 }
 
+// The two uniform grids of every world, cells of all worlds numbered
+// globally: road points (the observation's kNN) and road triangles (the
+// wheel rays), counted, scanned, filled and sorted per cell on the device
+// from the worlds' bounding boxes.  A rebuild (other cell sizes) replaces
+// the previous grids once the new ones exist; results of the kNN and of the
+// rays do not depend on the cell sizes, only their cost does.
+static sf_status build_grids(sf_sim *sim, float grid_cell, float tri_cell) {
+    const int W = sim->W, P = sim->P, T = sim->T;
+    hipStream_t st = sim->stream;
+    std::vector<void *> keep, tmp;
+    bool oom = false;
+    auto alloc = [&](std::vector<void *> &list, size_t bytes) -> void * {
+        void *p = dev_alloc(sim, bytes);
+        if (p) list.push_back(p);
+        else oom = true;
+        return p;
+    };
+    auto drop = [&]() {
+        for (void *p : keep) dev_free(sim, p);
+        for (void *p : tmp) dev_free(sim, p);
+    };
+    std::vector<float4> hb(W);
+    if (W) DEV(hipMemcpyAsync(hb.data(), sim->bbox, sizeof(float4) * W, hipMemcpyDeviceToHost, st));
+    DEV(hipStreamSynchronize(st));
+    auto headers = [&](float cell0, std::vector<GridHdr> &hg) {
+        long long C = 0;
+        hg.resize(W);
+        for (int w = 0; w < W; ++w) {
+            GridHdr g{};
+            float4 b = hb[w];
+            if (!(b.x <= b.z) || !(b.y <= b.w)) b = make_float4(0.f, 0.f, 0.f, 0.f);
+            float cell = cell0;
+            const float ext = std::max(b.z - b.x, b.w - b.y);
+            if (ext / cell > 2048.f) cell = ext / 2048.f;
+            g.x0 = b.x; g.y0 = b.y; g.cell = cell; g.inv_cell = 1.f / cell;
+            g.nx = std::max(1, (int)std::ceil((b.z - b.x) * g.inv_cell));
+            g.ny = std::max(1, (int)std::ceil((b.w - b.y) * g.inv_cell));
+            g.cbase = (int)C;
+            C += (long long)g.nx * g.ny;
+            hg[w] = g;
+        }
+        return C;
+    };
+    std::vector<GridHdr> hgp, hgt;
+    const long long CP = headers(grid_cell, hgp);
+    const long long CT = headers(tri_cell, hgt);
+    if (CP > (1ll << 30) || CT > (1ll << 30)) return fail(SF_E_UNSUPPORTED, "road grid too large");
+    DevWorld Wn = sim->Wd;
+    GridHdr *grid = (GridHdr *)alloc(keep, sizeof(GridHdr) * std::max(W, 1));
+    GridHdr *tgrid = (GridHdr *)alloc(keep, sizeof(GridHdr) * std::max(W, 1));
+    int *tri_start = (int *)alloc(keep, sizeof(int) * (CT + 1));
+    int *pt_start = (int *)alloc(keep, sizeof(int) * (CP + 1));
+    int *pt_occ = (int *)alloc(keep, sizeof(int) * std::max(CP, 1ll));
+    int4 *pt_cell = (int4 *)alloc(keep, sizeof(int4) * std::max(P, 1));
+    int *tri_cnt = (int *)alloc(tmp, sizeof(int) * CT), *pt_cnt = (int *)alloc(tmp, sizeof(int) * CP);
+    int *scan_tmp = (int *)alloc(tmp, sizeof(int) * (std::max(CT, CP) / 1024 + 2));
+    int *tri_cursor = (int *)alloc(tmp, sizeof(int) * (CT + 1));
+    int *pt_cursor = (int *)alloc(tmp, sizeof(int) * (CP + 1));
+    int *pt_items = (int *)alloc(tmp, sizeof(int) * std::max(P, 1));
+    if (oom) {
+        drop();
+        return fail(SF_E_OUT_OF_MEMORY, "grid allocation failed");
+    }
+    DEV(hipMemcpyAsync(grid, hgp.data(), sizeof(GridHdr) * W, hipMemcpyHostToDevice, st));
+    DEV(hipMemcpyAsync(tgrid, hgt.data(), sizeof(GridHdr) * W, hipMemcpyHostToDevice, st));
+    Wn.grid = grid;
+    Wn.tgrid = tgrid;
+    DEV(hipMemsetAsync(tri_cnt, 0, sizeof(int) * CT, st));
+    DEV(hipMemsetAsync(pt_cnt, 0, sizeof(int) * CP, st));
+    launch_grid_count(Wn, sim->verts, T, P, tri_cnt, pt_cnt, st);
+    launch_scan(tri_cnt, tri_start, (int)CT, scan_tmp, st);
+    launch_scan(pt_cnt, pt_start, (int)CP, scan_tmp, st);
+    LAUNCHED();
+    int n_tri_items = 0;
+    DEV(hipMemcpyAsync(&n_tri_items, tri_start + CT, sizeof(int), hipMemcpyDeviceToHost, st));
+    DEV(hipStreamSynchronize(st));
+    int *tri_items = (int *)alloc(tmp, sizeof(int) * std::max(n_tri_items, 1));
+    float4 *tri_rec = (float4 *)alloc(keep, sizeof(float4) * 3 * (size_t)std::max(n_tri_items, 1));
+    if (oom) {
+        drop();
+        return fail(SF_E_OUT_OF_MEMORY, "grid allocation failed");
+    }
+    DEV(hipMemcpyAsync(tri_cursor, tri_start, sizeof(int) * (CT + 1), hipMemcpyDeviceToDevice, st));
+    DEV(hipMemcpyAsync(pt_cursor, pt_start, sizeof(int) * (CP + 1), hipMemcpyDeviceToDevice, st));
+    Wn.tri_cell_start = tri_start; Wn.tri_rec = tri_rec;
+    Wn.pt_cell_start = pt_start; Wn.pt_cell = pt_cell; Wn.pt_occ = pt_occ;
+    launch_grid_fill(Wn, sim->verts, T, P, tri_cursor, pt_cursor, tri_items, pt_items, st);
+    launch_grid_finish(Wn, (int)CT, (int)CP, tri_items, pt_items, tri_rec, pt_cell, pt_occ, st);
+    LAUNCHED();
+    DEV(hipStreamSynchronize(st));
+    for (void *p : tmp) dev_free(sim, p);
+    for (void *p : sim->grid_bufs) dev_free(sim, p);
+    sim->grid_bufs = keep;
+    sim->Wd = Wn;
+    sim->C = (int)CP;
+    sim->grid_cell = grid_cell;
+    sim->tri_cell = tri_cell;
+    // a captured graph holds the previous grids
+    if (sim->graph_exec) { (void)hipGraphExecDestroy(sim->graph_exec); sim->graph_exec = nullptr; }
+    if (sim->graph) { (void)hipGraphDestroy(sim->graph); sim->graph = nullptr; }
+    return SF_OK;
+}
+
 sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf_options *o,
                     sf_sim **out) {
     if (!out) return fail(SF_E_INVALID_ARG, "out is NULL");
@@ -375,7 +484,6 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     float *verts; uint8_t *tsurf; float4 *tri;
     float *mu_class, *film = nullptr, *mu; uint8_t *pav = nullptr;
     float *spawn;
-    GridHdr *grid;
     float4 *bbox;
     ALLOC(aoff, int, W + 1); ALLOC(roff, int, W + 1); ALLOC(toff, int, W + 1); ALLOC(soff, int, W + 1);
     ALLOC(world_of, int, N);
@@ -385,7 +493,6 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     if (d->film_mm) ALLOC(film, float, W);
     if (d->pavement) ALLOC(pav, uint8_t, W);
     ALLOC(spawn, float, 5 * (size_t)E);
-    ALLOC(grid, GridHdr, W);
     ALLOC(bbox, float4, W);
     H2D(aoff, d->agent_offsets, sizeof(int) * (W + 1));
     H2D(roff, d->road_offsets, sizeof(int) * (W + 1));
@@ -405,7 +512,7 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     Wd.aoff = aoff; Wd.roff = roff; Wd.toff = toff; Wd.soff = soff;
     Wd.world_of = world_of;
     Wd.road_xy = road_xy; Wd.road_q = road_q; Wd.road_type = road_type;
-    Wd.tri = tri; Wd.mu = mu; Wd.spawn = spawn; Wd.grid = grid;
+    Wd.tri = tri; Wd.mu = mu; Wd.spawn = spawn;
     Wd.seed = d->seed;
 
     launch_weather_mu(mu_class, film, pav, W, sim->S, mu, st);
@@ -415,72 +522,17 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     launch_world_bbox(roff, road_xy, toff, verts, W, bbox, st);
     LAUNCHED();
 
-    // ---- grid headers on the host from the device bounding boxes: a road
-    // point grid (kNN) and a finer triangle grid (raycast)
-    std::vector<float4> hb(W);
-    if (W) DEV(hipMemcpyAsync(hb.data(), bbox, sizeof(float4) * W, hipMemcpyDeviceToHost, st));
-    DEV(hipStreamSynchronize(st));
-    auto headers = [&](float cell0, std::vector<GridHdr> &hg) {
-        long long C = 0;
-        hg.resize(W);
-        for (int w = 0; w < W; ++w) {
-            GridHdr g{};
-            float4 b = hb[w];
-            if (!(b.x <= b.z) || !(b.y <= b.w)) b = make_float4(0.f, 0.f, 0.f, 0.f);
-            float cell = cell0;
-            const float ext = std::max(b.z - b.x, b.w - b.y);
-            if (ext / cell > 2048.f) cell = ext / 2048.f;
-            g.x0 = b.x; g.y0 = b.y; g.cell = cell; g.inv_cell = 1.f / cell;
-            g.nx = std::max(1, (int)std::ceil((b.z - b.x) * g.inv_cell));
-            g.ny = std::max(1, (int)std::ceil((b.w - b.y) * g.inv_cell));
-            g.cbase = (int)C;
-            C += (long long)g.nx * g.ny;
-            hg[w] = g;
+    sim->verts = verts;
+    sim->bbox = bbox;
+    {
+        const sf_status r = build_grids(sim, opts.grid_cell > 0.f ? opts.grid_cell : 8.f,
+                                        opts.tri_cell > 0.f ? opts.tri_cell : 0.5f);
+        if (r != SF_OK) {
+            free_all(sim);
+            delete sim;
+            return r;
         }
-        return C;
-    };
-    std::vector<GridHdr> hgp, hgt;
-    const long long CP = headers(opts.grid_cell > 0.f ? opts.grid_cell : 8.f, hgp);
-    const long long CT = headers(opts.tri_cell > 0.f ? opts.tri_cell : 0.5f, hgt);
-    if (CP > (1ll << 30) || CT > (1ll << 30)) {
-        free_all(sim); delete sim;
-        return fail(SF_E_UNSUPPORTED, "road grid too large");
     }
-    sim->C = (int)CP;
-    GridHdr *tgrid;
-    ALLOC(tgrid, GridHdr, W);
-    H2D(grid, hgp.data(), sizeof(GridHdr) * W);
-    H2D(tgrid, hgt.data(), sizeof(GridHdr) * W);
-    Wd.tgrid = tgrid;
-    int *tri_cnt, *pt_cnt, *tri_start, *pt_start, *scan_tmp, *pt_items, *tri_cursor, *pt_cursor, *pt_occ;
-    ALLOC(tri_cnt, int, CT); ALLOC(pt_cnt, int, CP);
-    ALLOC(tri_start, int, CT + 1); ALLOC(pt_start, int, CP + 1);
-    ALLOC(scan_tmp, int, std::max(CT, CP) / 1024 + 2);
-    ALLOC(tri_cursor, int, CT + 1); ALLOC(pt_cursor, int, CP + 1);
-    ALLOC(pt_occ, int, CP);
-    DEV(hipMemsetAsync(tri_cnt, 0, sizeof(int) * CT, st));
-    DEV(hipMemsetAsync(pt_cnt, 0, sizeof(int) * CP, st));
-    launch_grid_count(Wd, verts, T, P, tri_cnt, pt_cnt, st);
-    launch_scan(tri_cnt, tri_start, (int)CT, scan_tmp, st);
-    launch_scan(pt_cnt, pt_start, (int)CP, scan_tmp, st);
-    LAUNCHED();
-    int n_tri_items = 0;
-    DEV(hipMemcpyAsync(&n_tri_items, tri_start + CT, sizeof(int), hipMemcpyDeviceToHost, st));
-    DEV(hipStreamSynchronize(st));
-    int *tri_items;
-    int4 *pt_cell;
-    float4 *tri_rec;
-    ALLOC(tri_items, int, n_tri_items);
-    ALLOC(tri_rec, float4, 3 * (size_t)n_tri_items);
-    ALLOC(pt_items, int, P);
-    ALLOC(pt_cell, int4, P);
-    DEV(hipMemcpyAsync(tri_cursor, tri_start, sizeof(int) * (CT + 1), hipMemcpyDeviceToDevice, st));
-    DEV(hipMemcpyAsync(pt_cursor, pt_start, sizeof(int) * (CP + 1), hipMemcpyDeviceToDevice, st));
-    Wd.tri_cell_start = tri_start; Wd.tri_rec = tri_rec;
-    Wd.pt_cell_start = pt_start; Wd.pt_cell = pt_cell; Wd.pt_occ = pt_occ;
-    launch_grid_fill(Wd, verts, T, P, tri_cursor, pt_cursor, tri_items, pt_items, st);
-    launch_grid_finish(Wd, (int)CT, (int)CP, tri_items, pt_items, tri_rec, pt_cell, pt_occ, st);
-    LAUNCHED();
 
     // ---- state, outputs, schedule
     const size_t nst = (size_t)SF_NUM_FFIELDS * N + (size_t)SF_NUM_IFIELDS * N;
@@ -1098,16 +1150,23 @@ static const int k_step_blocks[] = {64, 128, 192, 256, 320};
 static bool tuning_ok(const sf_tuning &t) {
     bool blk = false;
     for (int b : k_step_blocks) blk = blk || t.step_block == b;
+    // cell sizes: 0 keeps the current grids
+    const bool gc = t.grid_cell == 0.f || (t.grid_cell >= 0.25f && t.grid_cell <= 1000.f);
+    const bool tc = t.tri_cell == 0.f || (t.tri_cell >= 0.05f && t.tri_cell <= 100.f);
     return blk && t.step_grid >= 0 &&
            (t.obs_waves == 1 || t.obs_waves == 2 || t.obs_waves == 4 || t.obs_waves == 16) &&
-           (t.policy_rows == 16 || t.policy_rows == 32 || t.policy_rows == 64);
+           (t.policy_rows == 16 || t.policy_rows == 32 || t.policy_rows == 64) && gc && tc;
 }
 
-static void tuning_apply(sf_sim *sim, const sf_tuning &t) {
+static sf_status tuning_apply(sf_sim *sim, const sf_tuning &t) {
     sim->step_block = t.step_block;
     sim->step_grid = t.step_grid;
     sim->obs_waves = t.obs_waves;
     sim->policy_rows = t.policy_rows;
+    const float gc = t.grid_cell > 0.f ? t.grid_cell : sim->grid_cell;
+    const float tc = t.tri_cell > 0.f ? t.tri_cell : sim->tri_cell;
+    if (gc != sim->grid_cell || tc != sim->tri_cell) return build_grids(sim, gc, tc);
+    return SF_OK;
 }
 
 sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out) {
@@ -1118,6 +1177,8 @@ sf_status sf_get_tuning(sf_sim *sim, sf_tuning *out) {
     out->step_grid = sim->step_grid;
     out->obs_waves = sim->obs_waves;
     out->policy_rows = sim->policy_rows;
+    out->grid_cell = sim->grid_cell;
+    out->tri_cell = sim->tri_cell;
     return SF_OK;
 }
 
@@ -1125,9 +1186,8 @@ sf_status sf_set_tuning(sf_sim *sim, const sf_tuning *t) {
     CHECK_SIM(sim);
     if (!t || !tuning_ok(*t))
         return fail(SF_E_INVALID_ARG, "step_block in {64,128,192,256,320}, step_grid >= 0, obs_waves 1/2/4/16, "
-                                      "policy_rows 16/32/64");
-    tuning_apply(sim, *t);
-    return SF_OK;
+                                      "policy_rows 16/32/64, grid_cell 0 or 0.25..1000 m, tri_cell 0 or 0.05..100 m");
+    return tuning_apply(sim, *t);
 }
 
 sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, const char *cache_path,
@@ -1158,13 +1218,14 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
                 const size_t bar = l.find(" | ");
                 if (bar != std::string::npos && l.compare(0, bar, sig) == 0) {
                     sf_tuning t{};
-                    if (std::sscanf(l.c_str() + bar + 3, "%d %d %d %d", &t.step_block, &t.step_grid, &t.obs_waves,
-                                    &t.policy_rows) == 4 &&
-                        tuning_ok(t)) {
+                    const int got = std::sscanf(l.c_str() + bar + 3, "%d %d %d %d %f %f", &t.step_block,
+                                                &t.step_grid, &t.obs_waves, &t.policy_rows, &t.grid_cell,
+                                                &t.tri_cell);
+                    if ((got == 4 || got == 6) && tuning_ok(t)) {
                         std::fclose(f);
-                        tuning_apply(sim, t);
-                        *out = t;
-                        return SF_OK;
+                        const sf_status ra = tuning_apply(sim, t);
+                        if (ra != SF_OK) return ra;
+                        return sf_get_tuning(sim, out);
                     }
                     continue;  // a malformed entry is replaced
                 }
@@ -1199,8 +1260,8 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
     // median durations [policy, step, obs] over `steps` control steps of
     // shape t, after two untimed steps
     auto trial = [&](const sf_tuning &t, double *ms) -> sf_status {
-        tuning_apply(sim, t);
-        sf_status r;
+        sf_status r = tuning_apply(sim, t);
+        if (r != SF_OK) return r;
         if ((r = restore()) != SF_OK) return r;
         for (int k = 0; k < steps + 2; ++k) {
             if (k == 2 && (r = sf_profile(sim, 1)) != SF_OK) return r;
@@ -1258,9 +1319,27 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
         if (op < best_op) { best_op = op; best_ms[2] = ms[2]; best.obs_waves = wv; }
     }
     if (best.obs_waves == 16) best_ms[0] = 0.0;
+    // grid cells: the road-point grid scored by the observation, the
+    // triangle grid by the step (the current sizes were measured above)
+    for (float gc : {4.f, 8.f, 16.f}) {
+        if (r != SF_OK) break;
+        if (gc == best.grid_cell) continue;
+        sf_tuning t = best;
+        t.grid_cell = gc;
+        if ((r = trial(t, ms)) != SF_OK) break;
+        if (ms[2] < best_ms[2]) { best_ms[2] = ms[2]; best.grid_cell = gc; }
+    }
+    for (float tc : {0.5f, 1.f}) {
+        if (r != SF_OK) break;
+        if (tc == best.tri_cell) continue;
+        sf_tuning t = best;
+        t.tri_cell = tc;
+        if ((r = trial(t, ms)) != SF_OK) break;
+        if (ms[1] < best_ms[1]) { best_ms[1] = ms[1]; best.tri_cell = tc; }
+    }
     sim->sur_log = log_keep;
     sim->prof = prof_keep;
-    tuning_apply(sim, best);
+    if (r == SF_OK) r = tuning_apply(sim, best);
     if (r == SF_OK) r = restore();
     if (r == SF_OK) {
         DEV(hipStreamSynchronize(st));
@@ -1274,8 +1353,8 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
     *out = best;
     if (cache_path) {
         char line[512];
-        std::snprintf(line, sizeof(line), "%s | %d %d %d %d", sig, best.step_block, best.step_grid, best.obs_waves,
-                      best.policy_rows);
+        std::snprintf(line, sizeof(line), "%s | %d %d %d %d %g %g", sig, best.step_block, best.step_grid,
+                      best.obs_waves, best.policy_rows, best.grid_cell, best.tri_cell);
         lines.push_back(line);
         FILE *f = std::fopen(cache_path, "w");
         if (!f) return fail(SF_E_INVALID_ARG, std::string("cannot write ") + cache_path);

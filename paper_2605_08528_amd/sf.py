@@ -84,7 +84,7 @@ class SurTrainOpts(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("step_block", C.c_int32), ("step_grid", C.c_int32), ("obs_waves", C.c_int32),
                 ("policy_rows", C.c_int32), ("step_us", C.c_float), ("obs_us", C.c_float),
-                ("policy_us", C.c_float)]
+                ("policy_us", C.c_float), ("grid_cell", C.c_float), ("tri_cell", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -444,8 +444,11 @@ class Sim:
         check(lib().sf_get_tuning(self.h, C.byref(t)), "sf_get_tuning")
         return t.as_dict()
 
-    def set_tuning(self, step_block: int, step_grid: int, obs_waves: int, policy_rows: int) -> None:
-        t = Tuning(int(step_block), int(step_grid), int(obs_waves), int(policy_rows), 0.0, 0.0, 0.0)
+    def set_tuning(self, step_block: int, step_grid: int, obs_waves: int, policy_rows: int,
+                   grid_cell: float = 0.0, tri_cell: float = 0.0) -> None:
+        """Launch shapes; cell sizes of 0 keep the current grids, others rebuild them."""
+        t = Tuning(int(step_block), int(step_grid), int(obs_waves), int(policy_rows), 0.0, 0.0, 0.0,
+                   float(grid_cell), float(tri_cell))
         check(lib().sf_set_tuning(self.h, C.byref(t)), "sf_set_tuning")
 
     def autotune(self, dt: float, substeps: int, steps: int = 20, cache_path: str | None = None) -> dict:

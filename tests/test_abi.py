@@ -138,7 +138,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         "sf_world_desc": ["num_worlds", "agent_offsets", "num_surfaces", "spawn", "seed"],
         "sf_options": ["stream", "alloc", "max_episode_steps", "flags", "tri_cell", "step_grid", "reserved"],
         "sf_sur_train_opts": ["steps", "batch", "lr", "eps", "seed", "init_seed", "set_envelope"],
-        "sf_tuning": ["step_block", "step_grid", "obs_waves", "policy_rows", "step_us", "policy_us"],
+        "sf_tuning": ["step_block", "step_grid", "obs_waves", "policy_rows", "step_us", "policy_us", "grid_cell",
+                      "tri_cell"],
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sf.h"', "int main(void) {"]
     for s, fields in header_fields.items():

@@ -183,9 +183,12 @@ def test_freerun_plane_200_steps(O, torch):
 
 
 # -------------------------------------------------------------- raycast
-def test_raycast_grid_vs_brute_force(O, torch):
+@pytest.mark.parametrize("tri_cell", [0.5, 0.25, 1.0, 3.0])
+def test_raycast_grid_vs_brute_force(O, torch, tri_cell):
+    """Wheel rays through the triangle grid equal the oracle's brute force
+    over all triangles, at several cell sizes of the grid."""
     w = I.intersections(16, 8, seed=5)
-    sim, orc = make_pair(O, torch, w)
+    sim, orc = make_pair(O, torch, w, tri_cell=tri_cell)
     f, k = sim.get_state()
     rng = np.random.default_rng(0)
     # lift, tilt and shift the cars so that rays hit, miss and cross cells

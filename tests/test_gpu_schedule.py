@@ -82,6 +82,7 @@ def test_autotune_restores_state_and_caches(torch, tmp_path):
         assert np.array_equal(f0, f1) and np.array_equal(k0, k1) and np.array_equal(obs0, obs1)
         assert t["step_block"] in (64, 128, 192, 256, 320) and t["obs_waves"] in (1, 2, 4, 16)
         assert t["policy_rows"] in (16, 32, 64) and t["step_grid"] >= 0
+        assert t["grid_cell"] in (4.0, 8.0, 16.0) and t["tri_cell"] in (0.5, 1.0)
         assert t["step_us"] > 0 and t["obs_us"] > 0
         # the fused observation leaves no policy launch to time
         assert (t["policy_us"] > 0) != (t["obs_waves"] == 16)
@@ -94,9 +95,51 @@ def test_autotune_restores_state_and_caches(torch, tmp_path):
         assert len(lines) == 1 and lines[0].startswith("W256 N4096")
         sim2 = sf.Sim(w, mkparams(), flags=sf.SF_AUTO_RESET, stream=stream)
         t2 = sim2.autotune(dt, S, steps=4, cache_path=cache)
-        assert {k: t2[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows")} == \
-               {k: t[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows")}
+        keys = ("step_block", "step_grid", "obs_waves", "policy_rows", "grid_cell", "tri_cell")
+        assert {k: t2[k] for k in keys} == {k: t[k] for k in keys}
         assert t2["step_us"] == 0.0          # taken from the cache, not measured
         with pytest.raises(sf.SFError):
             sim2.set_tuning(100, 0, 4, 16)
         sim2.close()
+
+
+def test_grid_cells_leave_results_unchanged(torch):
+    """Rebuilding a handle's grids with other cell sizes changes only the
+    cost: the exact kNN and the wheel rays give bitwise the same states,
+    events and observations; a captured graph, which holds the old grids, is
+    dropped."""
+    from paper_2605_08528_amd import sf
+    w = I.workload("cross64x8")
+    dt, S = I.TIMING["cross64x8"]
+    out = []
+    for gc, tc in ((8.0, 0.5), (4.0, 1.0), (16.0, 0.25), (2.0, 0.5)):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            sim = sf.Sim(w, mkparams(), flags=sf.SF_AUTO_RESET, stream=stream)
+            sim.policy_load(*I.mlp_params([256, 256, 256, 2], seed=3))
+            sim.graph_capture(2, dt, S)
+            t = sim.tuning()
+            sim.set_tuning(t["step_block"], t["step_grid"], t["obs_waves"], t["policy_rows"], gc, tc)
+            t2 = sim.tuning()
+            assert (t2["grid_cell"], t2["tri_cell"]) == (gc, tc)
+            if (gc, tc) != (8.0, 0.5):
+                with pytest.raises(sf.SFError):
+                    sim.graph_launch()
+            for step in range(8):
+                sim.step(cuda(torch, I.actions(31, step, sim.N)), dt, S)
+            obs, rew, done, ev = sim.observe()
+            torch.cuda.synchronize()
+            f, k = sim.get_state()
+            out.append((f.view(np.uint32).copy(), k.copy(), obs.cpu().numpy().view(np.uint32),
+                        ev.cpu().numpy(), sim.debug_obs_indices()))
+            sim.close()
+    names = ("state", "integer state", "observation", "events", "kNN indices")
+    cfgs = ((8.0, 0.5), (4.0, 1.0), (16.0, 0.25), (2.0, 0.5))
+    bad = []
+    for c, o in zip(cfgs[1:], out[1:]):
+        for nm, a, b in zip(names, out[0], o):
+            if not np.array_equal(a, b):
+                cols = np.nonzero((a != b).reshape(a.shape[0], -1).any(axis=0) if nm == "state"
+                                  else (a != b).reshape(a.shape[0], -1).any(axis=1))[0]
+                bad.append((c, nm, len(cols), cols[:8].tolist()))
+    assert not bad, bad
