@@ -164,6 +164,9 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     t_train = time.perf_counter() - t0
     n_adam = sum(k for _, k in sf.SUR_SCHEDULE)
     err_mean, err_p95 = sim.sur_evaluate(test)
+    errs = sim.sur_errors(test).cpu().numpy().astype(np.float64)
+    err_q = {"p50": float(np.percentile(errs, 50)), "p99": float(np.percentile(errs, 99)),
+             "max": float(errs.max())}
     log(f"surrogate: {M} samples logged in {t_log:.1f} s, {n_adam} Adam steps in {t_train:.1f} s, "
         f"held-out force error mean {err_mean:.4f} p95 {err_p95:.4f} (untrained {untrained[0]:.4f})")
     del data, train, test
@@ -192,7 +195,9 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
         "value": casps, "unit": "controlled-agent steps/s", "ms_per_step": ms / steps,
         "step_kernel_us": 1e3 * prof["step"][0] / max(1, prof["step"][1]),
         "network_share": used / max(1, used + fb), "wheel_substeps_in_domain": used + fb,
-        "force_error_mean": err_mean, "force_error_p95": err_p95, "force_error_untrained": untrained[0],
+        "force_error_mean": err_mean, "force_error_p50": err_q["p50"], "force_error_p95": err_p95,
+        "force_error_p99": err_q["p99"], "force_error_max": err_q["max"], "force_error_untrained": untrained[0],
+        "fallback_rate": fb / max(1, used + fb),
         "train_samples": int(split), "test_samples": int(M - split), "adam_steps": n_adam,
         "batch": 8192, "train_seconds": t_train, "last_loss": loss,
         "trajectory_error_200": traj,
@@ -304,7 +309,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--sur-log-steps", type=int, default=200)
+    ap.add_argument("--sur-log-steps", type=int, default=600)
     ap.add_argument("--grid-cell", type=float, default=0.0)
     ap.add_argument("--obs-waves", type=int, default=0)
     ap.add_argument("--step-block", type=int, default=0)

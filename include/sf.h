@@ -333,6 +333,10 @@ sf_status sf_sur_predict(sf_sim *sim, const float *d_data, int64_t M, float *d_p
  * |(dF_x, dF_y)| / max(|(F_x, F_y)|, 0.05) in units of mu F_z against the
  * stored targets; mean and 95th percentile.  Synchronises. */
 sf_status sf_sur_evaluate(sf_sim *sim, const float *d_data, int64_t M, float *h_mean, float *h_p95);
+/* The same relative force error per sample, d_err [M] (device float32,
+ * caller-owned), for any statistic the caller wants.  Enqueued on the
+ * handle's stream. */
+sf_status sf_sur_errors(sf_sim *sim, const float *d_data, int64_t M, float *d_err);
 /* Load (h_params, h_lo, h_hi: 35587, 16, 16 host floats) or read back the
  * network and its envelope.  Loading clears the Adam moments. */
 sf_status sf_sur_set(sf_sim *sim, const float *h_params, const float *h_lo, const float *h_hi);

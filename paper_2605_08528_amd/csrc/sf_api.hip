@@ -987,6 +987,19 @@ sf_status sf_sur_evaluate(sf_sim *sim, const float *d_data, int64_t M, float *h_
     return SF_OK;
 }
 
+sf_status sf_sur_errors(sf_sim *sim, const float *d_data, int64_t M, float *d_err) {
+    CHECK_SIM(sim);
+    sf_status r;
+    if ((r = sur_check_data(d_data, M, 1ll << 28)) != SF_OK) return r;
+    if (!d_err) return fail(SF_E_INVALID_ARG, "NULL output");
+    if (!sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    if ((r = sur_pred_buf(sim, M)) != SF_OK) return r;
+    launch_sur_eval(d_data, (int)M, sim->sur_P, sim->sur_Wb, sim->sur_pred, sim->stream);
+    launch_sur_errors(d_data, (int)M, sim->sur_pred, d_err, sim->stream);
+    LAUNCHED();
+    return SF_OK;
+}
+
 sf_status sf_sur_set(sf_sim *sim, const float *h_params, const float *h_lo, const float *h_hi) {
     CHECK_SIM(sim);
     if (!h_params || !h_lo || !h_hi) return fail(SF_E_INVALID_ARG, "NULL input");

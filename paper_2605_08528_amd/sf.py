@@ -135,6 +135,7 @@ def lib():
         L.sf_sur_gradient.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(C.c_float)]
         L.sf_sur_predict.argtypes = [vp, vp, C.c_int64, vp]
         L.sf_sur_evaluate.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.sf_sur_errors.argtypes = [vp, vp, C.c_int64, vp]
         L.sf_sur_set.argtypes = [vp, vp, vp, vp]
         L.sf_sur_get.argtypes = [vp, vp, vp, vp]
         L.sf_sur_enable.argtypes = [vp, i32]
@@ -150,7 +151,8 @@ def lib():
                      "sf_set_state", "sf_get_contacts", "sf_debug_raycast", "sf_debug_obs_indices",
                      "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
                      "sf_graph_launch", "sf_profile", "sf_profile_read", "sf_sur_log", "sf_sur_collect",
-                     "sf_sur_train", "sf_sur_gradient", "sf_sur_predict", "sf_sur_evaluate", "sf_sur_set",
+                     "sf_sur_train", "sf_sur_gradient", "sf_sur_predict", "sf_sur_evaluate", "sf_sur_errors",
+                     "sf_sur_set",
                      "sf_sur_get", "sf_sur_enable", "sf_sur_counts", "sf_get_tuning", "sf_set_tuning",
                      "sf_autotune"):
             getattr(L, name).restype = st
@@ -418,6 +420,13 @@ class Sim:
         check(lib().sf_sur_evaluate(self.h, _tptr(data), data.shape[0], C.byref(m), C.byref(p)),
               "sf_sur_evaluate")
         return m.value, p.value
+
+    def sur_errors(self, data):
+        """Per-sample relative force error of the network on data [M][20] (CUDA tensor [M])."""
+        t = self.torch
+        e = t.empty(data.shape[0], dtype=t.float32, device=data.device)
+        check(lib().sf_sur_errors(self.h, _tptr(data), data.shape[0], _tptr(e)), "sf_sur_errors")
+        return e
 
     def sur_set(self, params, lo, hi) -> None:
         self._sur_keep = [np.ascontiguousarray(a, np.float32) for a in (params, lo, hi)]

@@ -202,6 +202,26 @@ def test_predict_matches_oracle(O, torch):
     sim.close()
 
 
+def test_errors_per_sample(torch):
+    """Per-sample relative force errors equal |d(F_x, F_y)| / max(|(F_x, F_y)|,
+    0.05) of the network's predictions against the stored targets (both in
+    units of mu F_z), and their mean is the evaluation's mean."""
+    sim = fresh_sim(torch)
+    d = random_data(777, 13)
+    dd = cuda(torch, d)
+    sim.sur_train(dd, steps=20, batch=0, lr=1e-3, init_seed=5)
+    y = sim.sur_predict(dd).cpu().numpy().astype(np.float64)
+    e = sim.sur_errors(dd).cpu().numpy().astype(np.float64)
+    t = d[:, 16:18].astype(np.float64)
+    ref = np.hypot(y[:, 0] - t[:, 0], y[:, 1] - t[:, 1]) / np.maximum(np.hypot(t[:, 0], t[:, 1]), 0.05)
+    assert e.shape == (777,)
+    assert np.allclose(e, ref, rtol=1e-5, atol=1e-6)
+    m, p95 = sim.sur_evaluate(dd)
+    assert abs(m - e.mean()) <= 1e-5 * max(1.0, m)
+    assert np.sum(e <= p95) >= 0.95 * len(e)
+    sim.close()
+
+
 # ------------------------------------------------------------ accuracy
 @pytest.fixture(scope="module")
 def trained(torch):
