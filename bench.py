@@ -39,6 +39,10 @@ STEP_BYTES_PER_AGENT = 2 * 112 + 8 + 6        # state read + write, actions, rew
 OBS_BYTES_PER_AGENT = 1024 + 64               # observation row write + own state read
 POLICY_FLOP_PER_AGENT = 2 * (256 * 256 * 2 + 256 * 2)
 POLICY_WEIGHT_BYTES = 132098 * 2              # bf16 copies of the three layers read once per launch
+# learned tire network 16 -> 128 -> 128 -> 128 -> 3: multiply-adds per evaluation,
+# and forward + backward (weight and input gradients) per training sample
+SUR_FLOP_PER_EVAL = 2 * (16 * 128 + 128 * 128 * 2 + 128 * 3)
+SUR_TRAIN_FLOP_PER_SAMPLE = 3 * SUR_FLOP_PER_EVAL
 ACT_BYTES_PER_AGENT = 8                       # two float actions written
 
 
@@ -188,12 +192,17 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     used, fb = sim.sur_counts(reset=True)
     sim.sur_enable(False)
     casps = N * steps / (ms / 1e3)
+    step_us = 1e3 * prof["step"][0] / max(1, prof["step"][1])
+    # the network runs on every in-domain wheel-substep (fallback decided after)
+    net_tflops = (used + fb) * SUR_FLOP_PER_EVAL / (steps * step_us * 1e-6) / 1e12
+    train_tflops = n_adam * 8192 * SUR_TRAIN_FLOP_PER_SAMPLE / t_train / 1e12
     traj = trajectory_error(sim, torch, sf, dt, S, 200)
     log(f"surrogate step: {ms / steps:.4f} ms/step, {casps:.4g} CASPS, network on "
         f"{used / max(1, used + fb):.3f} of in-domain wheel-substeps")
     return {
         "value": casps, "unit": "controlled-agent steps/s", "ms_per_step": ms / steps,
-        "step_kernel_us": 1e3 * prof["step"][0] / max(1, prof["step"][1]),
+        "step_kernel_us": step_us,
+        "network_tflops_in_step": net_tflops, "train_tflops": train_tflops,
         "network_share": used / max(1, used + fb), "wheel_substeps_in_domain": used + fb,
         "force_error_mean": err_mean, "force_error_p50": err_q["p50"], "force_error_p95": err_p95,
         "force_error_p99": err_q["p99"], "force_error_max": err_q["max"], "force_error_untrained": untrained[0],

@@ -17,15 +17,32 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
     return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
-// ascending bitonic sort of one u64 key per lane across the wavefront
+// ascending bitonic sort of one u64 key per lane within each group of
+// WIDTH lanes (32: the two halves of the wavefront sorted separately)
+template <int WIDTH>
 __device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long key) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= WIDTH; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            unsigned long long o = shfl_xor_u64(key, j);
+            bool up = (lane & k) == 0, lower = (lane & j) == 0;
+            key = (lower == up) ? (key < o ? key : o) : (key > o ? key : o);
+        }
+    return key;
+}
+
+// the same for one u32 key per lane across the whole wavefront (one
+// exchange per stage instead of two)
+__device__ __forceinline__ unsigned wave_sort_u32(unsigned key) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1)
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            unsigned long long o = shfl_xor_u64(key, j);
-            bool up = (lane & k) == 0, lower = (lane & j) == 0;
+            const unsigned o = (unsigned)__shfl_xor((int)key, j, 64);
+            const bool up = (lane & k) == 0, lower = (lane & j) == 0;
             key = (lower == up) ? (key < o ? key : o) : (key > o ? key : o);
         }
     return key;
@@ -297,7 +314,9 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
                 key = ((unsigned long long)sat_key(dx * dx + dy * dy) << 8) | (unsigned)lane;
             }
         }
-        key = wave_sort_u64(key);
+        // every key sits in a lane below A: with A <= 32 the first half of
+        // the wavefront holds them all
+        key = A <= 32 ? wave_sort_u64<32>(key) : wave_sort_u64<64>(key);
         int jn = key == ~0ull ? -1 : (int)(key & 0xFF);
         if (dbg && lane < 8) dbg[(size_t)n * 72 + 64 + lane] = jn;
         // the state of the neighbour of rank `lane`, from lane jn
@@ -460,8 +479,7 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
         if (lane == 0)
             hint[n] = make_float4(px, py, nc >= 64 ? sqrtf((float)(kthr >> 20) * (1.f / 1048576.f)) : NAN, 0.f);
         // point-index order: sort the member indices across lanes
-        unsigned long long sk = wave_sort_u64((unsigned long long)(unsigned)my_idx);
-        my_idx = (int)sk;
+        my_idx = (int)wave_sort_u32((unsigned)my_idx);
     }
     if (dbg) dbg[(size_t)n * 72 + lane] = my_idx == 0x7fffffff ? -1 : my_idx;
     if (my_idx != 0x7fffffff) {
