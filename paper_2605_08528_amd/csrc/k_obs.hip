@@ -11,9 +11,31 @@ __device__ __forceinline__ unsigned long long lane_lt() {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+// the value of lane (lane ^ m): lane distances 1 and 2 as quad permutes,
+// 4 and 8 as a row shift in either direction chosen per lane (data-parallel
+// moves, no trip through the LDS crossbar), larger ones by permute
+__device__ __forceinline__ int lane_xor(int v, int m) {
+    const int lane = threadIdx.x & 63;
+    switch (m) {
+        case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 4: {
+            const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0xF, false);  // row_shl:4
+            const int dn = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+            return (lane & 4) ? dn : up;
+        }
+        case 8: {
+            const int up = __builtin_amdgcn_update_dpp(0, v, 0x108, 0xF, 0xF, false);  // row_shl:8
+            const int dn = __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+            return (lane & 8) ? dn : up;
+        }
+        default: return __shfl_xor(v, m, 64);
+    }
+}
+
 __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
-    int lo = __shfl_xor((int)(unsigned)v, m, 64);
-    int hi = __shfl_xor((int)(unsigned)(v >> 32), m, 64);
+    int lo = lane_xor((int)(unsigned)v, m);
+    int hi = lane_xor((int)(unsigned)(v >> 32), m);
     return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
@@ -41,7 +63,7 @@ __device__ __forceinline__ unsigned wave_sort_u32(unsigned key) {
     for (int k = 2; k <= 64; k <<= 1)
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const unsigned o = (unsigned)__shfl_xor((int)key, j, 64);
+            const unsigned o = (unsigned)lane_xor((int)key, j);
             const bool up = (lane & k) == 0, lower = (lane & j) == 0;
             key = (lower == up) ? (key < o ? key : o) : (key > o ? key : o);
         }
