@@ -11,28 +11,6 @@ __device__ __forceinline__ unsigned long long lane_lt() {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-// the value of lane (lane ^ m): lane distances 1 and 2 as quad permutes,
-// 4 and 8 as a row shift in either direction chosen per lane (data-parallel
-// moves, no trip through the LDS crossbar), larger ones by permute
-__device__ __forceinline__ int lane_xor(int v, int m) {
-    const int lane = threadIdx.x & 63;
-    switch (m) {
-        case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-        case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-        case 4: {
-            const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0xF, false);  // row_shl:4
-            const int dn = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
-            return (lane & 4) ? dn : up;
-        }
-        case 8: {
-            const int up = __builtin_amdgcn_update_dpp(0, v, 0x108, 0xF, 0xF, false);  // row_shl:8
-            const int dn = __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
-            return (lane & 8) ? dn : up;
-        }
-        default: return __shfl_xor(v, m, 64);
-    }
-}
-
 __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
     int lo = lane_xor((int)(unsigned)v, m);
     int hi = lane_xor((int)(unsigned)(v >> 32), m);
@@ -618,7 +596,7 @@ __global__ __launch_bounds__(1024) void k_obs_policy(DevParams P, DevWorld Wd, c
 #pragma unroll
         for (int k = 0; k < 8; ++k) a += bf2f(h[k]) * bf2f(w[k]);
 #pragma unroll
-        for (int m = 16; m > 0; m >>= 1) a += __shfl_xor(a, m, 64);
+        for (int m = 16; m > 0; m >>= 1) a += lane_xor_f(a, m);
         if (part == 0 && n0 + row < Wd.N) {
             const float z = tanhf(a + b3[o]);
             act[2 * (size_t)(n0 + row) + o] = o == 0 ? z : steer_max * z;

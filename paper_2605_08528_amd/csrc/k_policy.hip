@@ -94,7 +94,7 @@ __device__ __forceinline__ void policy_head(const uint16_t *__restrict__ s_h, co
 #pragma unroll 8
     for (int k = 0; k < KP; ++k) acc += bf2f(h[k]) * bf2f(w[k]);
 #pragma unroll
-    for (int m = G / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    for (int m = G / 2; m > 0; m >>= 1) acc += lane_xor_f(acc, m);
     if (part == 0 && r0 + row < N) {
         const float z = tanhf(acc + b3[o]);
         act[2 * (size_t)(r0 + row) + o] = o == 0 ? z : steer_max * z;

@@ -892,11 +892,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             }
 #pragma unroll
                             for (int m = 2; m > 0; m >>= 1) {
-                                jx += __shfl_xor(jx, m, 64);
-                                jy += __shfl_xor(jy, m, 64);
-                                tx += __shfl_xor(tx, m, 64);
-                                ty += __shfl_xor(ty, m, 64);
-                                tz += __shfl_xor(tz, m, 64);
+                                jx += lane_xor_f(jx, m);
+                                jy += lane_xor_f(jy, m);
+                                tx += lane_xor_f(tx, m);
+                                ty += lane_xor_f(ty, m);
+                                tz += lane_xor_f(tz, m);
                             }
                             if (cnt > 0 && g == 0) {
                                 s_v[0][b] += jx * P.inv_mass;

@@ -194,6 +194,32 @@ __device__ __forceinline__ long long sat_key(long long d2) {
     return d2 < SF_KEY_CAP ? d2 : SF_KEY_CAP - 1;
 }
 
+// ------------------------------------------------------------ lane exchange
+// the value of lane (lane ^ m): lane distances 1 and 2 as quad permutes,
+// 4 and 8 as a row shift in either direction chosen per lane (data-parallel
+// moves, no trip through the LDS crossbar), larger ones by permute
+__device__ __forceinline__ int lane_xor(int v, int m) {
+    const int lane = threadIdx.x & 63;
+    switch (m) {
+        case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 4: {
+            const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0xF, false);  // row_shl:4
+            const int dn = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+            return (lane & 4) ? dn : up;
+        }
+        case 8: {
+            const int up = __builtin_amdgcn_update_dpp(0, v, 0x108, 0xF, 0xF, false);  // row_shl:8
+            const int dn = __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+            return (lane & 8) ? dn : up;
+        }
+        default: return __shfl_xor(v, m, 64);
+    }
+}
+__device__ __forceinline__ float lane_xor_f(float v, int m) {
+    return __int_as_float(lane_xor(__float_as_int(v), m));
+}
+
 // ------------------------------------------------------------ small math
 struct f3 { float x, y, z; };
 __device__ __forceinline__ f3 mk3(float x, float y, float z) { return {x, y, z}; }
