@@ -385,7 +385,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                                                 float h, int S, float *__restrict__ reward,
                                                 uint8_t *__restrict__ done, uint8_t *__restrict__ events,
                                                 uint32_t *__restrict__ rec, int *__restrict__ rec_cnt,
-                                                int rec_cap, const int *__restrict__ order,
+                                                int rec_cap, const int4 *__restrict__ items,
                                                 int *__restrict__ queue) {
     constexpr int NWV = BLOCK / 64;
     const int N = Wd.N;
@@ -456,20 +456,21 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                       : e < 384 ? Su.P[SF_SUR_B3 + e - 256] : e < 387 ? Su.P[SF_SUR_B4 + e - 384] : 0.f;
     }
 
-    // Worlds in longest-first order.  Without a queue, block b takes world
-    // order[b]; with one (a persistent grid smaller than W), a block that
-    // finishes a world takes the next unclaimed one from an atomic counter.
+    // Worlds in longest-first order, one descriptor each (world, first
+    // agent, agents, any road triangles), so that the world's loads follow
+    // a single read.  Without a queue, block b takes item b; with one (a
+    // persistent grid smaller than W), a block that finishes a world takes
+    // the next unclaimed item from an atomic counter.
     __shared__ int s_item;
     int item = blockIdx.x;
     while (item < Wd.W) {
         do {
-            const int w = order ? order[item] : item;
-            const int a0 = Wd.aoff[w];
-            const int A = Wd.aoff[w + 1] - a0;
+            const int4 it = items[item];
+            const int w = it.x, a0 = it.y, A = it.z;
             if (A <= 0) break;
             if (tid == 0) {
                 s_tgrid = Wd.tgrid[w];
-                s_anytri = Wd.toff[w + 1] > Wd.toff[w];
+                s_anytri = it.w != 0;
             }
             if (tid < Wd.S) s_mu[tid] = Wd.mu[w * Wd.S + tid];
             // ---- load the world's agents; decode actions (Sec. "Action Space Details")
@@ -1019,7 +1020,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
 
 void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
                  const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
-                 int *rec_cnt, int rec_cap, const int *order, int block, int grid, int *queue, hipStream_t s) {
+                 int *rec_cnt, int rec_cap, const int4 *items, int block, int grid, int *queue, hipStream_t s) {
     if (Wd.W == 0) return;
     // a persistent grid pulls worlds from the queue; a full grid needs none
     if (grid <= 0 || grid >= Wd.W) {
@@ -1032,10 +1033,10 @@ void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool 
     do {                                                                                                      \
         if (use_sur)                                                                                          \
             k_step<B, true><<<grid, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,       \
-                                               rec_cnt, rec_cap, order, queue);                               \
+                                               rec_cnt, rec_cap, items, queue);                               \
         else                                                                                                  \
             k_step<B, false><<<grid, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,      \
-                                                rec_cnt, rec_cap, order, queue);                              \
+                                                rec_cnt, rec_cap, items, queue);                              \
     } while (0)
     if (block <= 64) SF_STEP_LAUNCH(64);
     else if (block <= 128) SF_STEP_LAUNCH(128);
@@ -1043,7 +1044,7 @@ void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool 
     else if (block <= 256 || use_sur) SF_STEP_LAUNCH(256);
     else
         k_step<320, false><<<grid, 320, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec, rec_cnt,
-                                                rec_cap, order, queue);
+                                                rec_cap, items, queue);
 #undef SF_STEP_LAUNCH
 }
 

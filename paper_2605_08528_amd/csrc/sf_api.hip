@@ -47,7 +47,7 @@ struct sf_sim {
     int *ist = nullptr;        // [NI][N] (same allocation, after st)
     float *obs = nullptr, *reward = nullptr;
     uint8_t *done = nullptr, *events = nullptr;
-    int *order = nullptr;
+    int4 *items = nullptr;         // [W] (world, first agent, agents, any triangles), longest first
     uint32_t *rec = nullptr;
     int *rec_cnt = nullptr;
     int rec_cap = 0;
@@ -556,8 +556,14 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
         return a * (8 + a);
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    ALLOC(sim->order, int, W);
-    H2D(sim->order, ord.data(), sizeof(int) * W);
+    std::vector<int4> its(W);
+    for (int k = 0; k < W; ++k) {
+        const int w = ord[k];
+        its[k] = make_int4(w, d->agent_offsets[w], d->agent_offsets[w + 1] - d->agent_offsets[w],
+                           d->tri_offsets[w + 1] > d->tri_offsets[w] ? 1 : 0);
+    }
+    ALLOC(sim->items, int4, W);
+    H2D(sim->items, its.data(), sizeof(int4) * W);
     ALLOC(sim->queue, int, 2);
     DEV(hipMemsetAsync(sim->queue, 0, 2 * sizeof(int), st));
     if (opts.flags & SF_RECORD_CONTACTS) {
@@ -641,7 +647,7 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         Su.log_cap = sim->sur_log_cap;
         Su.log_base = sim->sur_log_base;
         launch_step(sim->P_dev, sim->Wd, Su, sim->sur_on, sim->st, sim->ist, d_actions, h, substeps, sim->reward,
-                    sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->order, sim->step_block,
+                    sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->items, sim->step_block,
                     sim->step_grid, sim->queue, sim->stream);
         if (sim->sur_log)
             sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;

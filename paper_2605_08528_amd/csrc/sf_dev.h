@@ -291,7 +291,7 @@ void launch_reset(const DevParams &P, const DevWorld &Wd, float *st, int *ist, c
                   int bump_episode, hipStream_t s);
 void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
                  const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
-                 int *rec_cnt, int rec_cap, const int *order, int block, int grid, int *queue, hipStream_t s);
+                 int *rec_cnt, int rec_cap, const int4 *items, int block, int grid, int *queue, hipStream_t s);
 void launch_sur_reduce(const float *grad, int tiles, float *out, hipStream_t s);
 void launch_sur_grad_seq(const float *data, int M, const float *P, const uint16_t *Wb, float *grad, float *loss,
                          hipStream_t s);
