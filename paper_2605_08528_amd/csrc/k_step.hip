@@ -411,6 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ float s_mu[SF_MAX_SURFACES];  // the world's friction per surface
     __shared__ bool s_anytri;
     __shared__ int s_bn[SF_MAXA];
+    __shared__ int s_poff[BLOCK];        // first contact slot of each pair of a chunk
     __shared__ int s_scan[NWV];
     __shared__ int s_np;
     constexpr int NSW = NWV == 1 ? 1 : NWV - 1;  // waves that run wheels
@@ -746,32 +747,38 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                         if (v < wave) off += s_scan[v];
                         tot += s_scan[v];
                     }
-                    int pos = nc + off + x - cnt;
-                    if (cnt) {
-                        const int i = pr & 0xFF, j = (pr >> 8) & 0xFF;
-                        const uint32_t mask = pr >> 16;
-                        for (int a = 0; a < 3; ++a)
-                            for (int b = 0; b < 3; ++b) {
-                                if (!(mask & (1u << (3 * a + b)))) continue;
-                                if (pos < SF_CCAP) {
-                                    const float cix = s_p[0][i] + (float)(a - 1) * P.cd * s_hx[i];
-                                    const float ciy = s_p[1][i] + (float)(a - 1) * P.cd * s_hy[i];
-                                    const float cjx = s_p[0][j] + (float)(b - 1) * P.cd * s_hx[j];
-                                    const float cjy = s_p[1][j] + (float)(b - 1) * P.cd * s_hy[j];
-                                    const float dx = cjx - cix, dy = cjy - ciy;
-                                    const float L = sqrtf(dx * dx + dy * dy);
-                                    s_cn[0][pos] = L > 0.f ? dx / L : 1.f;
-                                    s_cn[1][pos] = L > 0.f ? dy / L : 0.f;
-                                    s_cpc[0][pos] = 0.5f * (cix + cjx);
-                                    s_cpc[1][pos] = 0.5f * (ciy + cjy);
-                                    s_cpc[2][pos] = 0.5f * (s_p[2][i] + s_p[2][j]);
-                                    const float pen = 2.f * P.cr - L - P.slop;
-                                    s_cb[pos] = pen > 0.f ? (P.baumgarte / h) * pen : 0.f;
-                                    s_clam[pos] = 0.f;
-                                    s_cij[pos] = i | (j << 8);
-                                }
-                                ++pos;
-                            }
+                    // first contact slot of each pair of this chunk
+                    if (k < np) s_poff[tid] = nc + off + x - cnt;
+                    __syncthreads();
+                    // one thread per (pair, circle combination) present in the
+                    // pair's mask; its slot is the pair's first plus the number
+                    // of the mask's lower bits (the list order is unchanged)
+                    const int npk = min(np - base, BLOCK);
+                    for (int t = tid; t < 9 * npk; t += BLOCK) {
+                        const int kk = t / 9, ab = t - 9 * kk;
+                        const uint32_t prk = s_pairs[base + kk];
+                        const uint32_t mask = prk >> 16;
+                        if (!(mask & (1u << ab))) continue;
+                        const int pos = s_poff[kk] + __popc(mask & ((1u << ab) - 1u));
+                        if (pos < SF_CCAP) {
+                            const int i = prk & 0xFF, j = (prk >> 8) & 0xFF;
+                            const int a = ab / 3, b = ab - 3 * a;
+                            const float cix = s_p[0][i] + (float)(a - 1) * P.cd * s_hx[i];
+                            const float ciy = s_p[1][i] + (float)(a - 1) * P.cd * s_hy[i];
+                            const float cjx = s_p[0][j] + (float)(b - 1) * P.cd * s_hx[j];
+                            const float cjy = s_p[1][j] + (float)(b - 1) * P.cd * s_hy[j];
+                            const float dx = cjx - cix, dy = cjy - ciy;
+                            const float L = sqrtf(dx * dx + dy * dy);
+                            s_cn[0][pos] = L > 0.f ? dx / L : 1.f;
+                            s_cn[1][pos] = L > 0.f ? dy / L : 0.f;
+                            s_cpc[0][pos] = 0.5f * (cix + cjx);
+                            s_cpc[1][pos] = 0.5f * (ciy + cjy);
+                            s_cpc[2][pos] = 0.5f * (s_p[2][i] + s_p[2][j]);
+                            const float pen = 2.f * P.cr - L - P.slop;
+                            s_cb[pos] = pen > 0.f ? (P.baumgarte / h) * pen : 0.f;
+                            s_clam[pos] = 0.f;
+                            s_cij[pos] = i | (j << 8);
+                        }
                     }
                     nc += tot;
                     __syncthreads();
