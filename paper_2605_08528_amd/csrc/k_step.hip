@@ -884,7 +884,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             const int cnt = b < A ? s_bn[b] : 0;
                             if (cnt > 0) {
                                 const float pbx = s_p[0][b], pby = s_p[1][b], pbz = s_p[2][b];
-#pragma unroll 2
+#pragma unroll 4
                                 for (int q = g; q < cnt; q += 4) {
                                     const int c = s_bl[b][q];
                                     const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? s_cdl[c] : -s_cdl[c];
