@@ -215,6 +215,66 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     }
 
 
+def config_leg(name, torch, sf, I, stream, steps, sur_params, tune_steps):
+    """Context for the other workload sizes: graph-replay CASPS of the plain
+    control step, per-kernel durations from a profiled eager pass, and the
+    step with the learned tire model trained in the main leg (wheels outside
+    its training envelope fall back to the plain model)."""
+    w = I.workload(name)
+    dt, S = I.TIMING[name]
+    with torch.cuda.stream(stream):
+        sim = sf.Sim(w, dict(I.VEHICLE_DEFAULTS), flags=sf.SF_AUTO_RESET, stream=stream)
+        sim.policy_load(*I.mlp_params([256, 256, 256, 2], seed=0))
+        N = sim.N
+        for _ in range(100):
+            sim.step_policy(dt, S)
+        tuning = sim.autotune(dt, S, steps=tune_steps)
+        sim.profile(True)
+        for _ in range(steps):
+            sim.step_policy(dt, S)
+        torch.cuda.synchronize()
+        prof = sim.profile_read()
+        sim.profile(False)
+        G = graph_len(steps)
+        sim.graph_capture(G, dt, S)
+        sim.graph_launch()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(steps // G):
+            sim.graph_launch()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        ms = g0.elapsed_time(g1)
+        out = {"worlds": w.num_worlds, "agents": N, "steps": steps, "casps": N * steps / (ms / 1e3),
+               "ms_per_step": ms / steps,
+               "launch_shapes": {k: tuning[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows",
+                                                          "grid_cell", "tri_cell")},
+               "kernels_us": {k: 1e3 * t / c for k, (t, c) in prof.items() if c}}
+        if "step" in out["kernels_us"]:
+            out["step_algorithmic_gbs"] = STEP_BYTES_PER_AGENT * N / (out["kernels_us"]["step"] * 1e-6) / 1e9
+        if sur_params is not None:
+            sim.sur_set(*sur_params)
+            sim.sur_enable(True)
+            for _ in range(20):
+                sim.step_policy(dt, S)
+            sim.sur_counts(reset=True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(steps):
+                sim.step_policy(dt, S)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            used, fb = sim.sur_counts(reset=True)
+            out["surrogate"] = {"casps_eager": N * steps / (e0.elapsed_time(e1) / 1e3),
+                                "network_share": used / max(1, used + fb)}
+        sim.close()
+    log(f"{name}: {N} agents, graph {out['ms_per_step']:.4f} ms/step, {out['casps']:.4g} CASPS"
+        + (f"; surrogate eager {out['surrogate']['casps_eager']:.4g} CASPS" if "surrogate" in out else ""))
+    return out
+
+
 def graph_len(steps: int) -> int:
     """Control steps per captured graph: the largest divisor of the timed
     step count up to 16, so that whole replays cover exactly that count."""
@@ -325,6 +385,9 @@ def main():
     ap.add_argument("--policy-rows", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune-steps", type=int, default=20)
+    ap.add_argument("--configs", default="cross1024x16,dense4096x32",
+                    help="other workload sizes reported as context (empty: none)")
+    ap.add_argument("--config-steps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step would shard by "
@@ -355,6 +418,17 @@ def main():
         with torch.cuda.stream(stream):
             sur = surrogate_leg(sim, torch, sf, stream, dt, S, args.steps, min(args.warmup, 300),
                                 args.sur_log_steps)
+
+    # ---- the other workload sizes (context, not the headline value)
+    others = {}
+    if args.configs:
+        sur_params = None
+        if sur is not None:
+            with torch.cuda.stream(stream):
+                sur_params = sim.sur_get()
+        for name in [c for c in args.configs.split(",") if c]:
+            others[name] = config_leg(name, torch, sf, I, stream, args.config_steps, sur_params,
+                                      max(4, args.tune_steps // 2))
 
     kernels = {}
     for name, (tot, cnt) in prof.items():
@@ -431,6 +505,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "surrogate": sur,
+        "other_configs": others,
         "paper_context": {"casps": 19250, "hardware": "RTX PRO 6000 Blackwell, PhysX, 256x16"},
     }
     print(json.dumps(out))
