@@ -1358,13 +1358,20 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
     }
     sim->sur_log = log_keep;
     sim->prof = prof_keep;
-    if (r == SF_OK) r = tuning_apply(sim, best);
-    if (r == SF_OK) r = restore();
     if (r == SF_OK) {
-        DEV(hipStreamSynchronize(st));
-        dev_free(sim, snap);
-        dev_free(sim, zero_act);
+        r = tuning_apply(sim, best);
+        if (r == SF_OK) r = restore();
+    } else if (!sim->bad) {
+        // a failed trial (e.g. no memory for other grid cells) leaves the
+        // shapes and the state the handle had before the search
+        const std::string why = sf_last_error();
+        if (tuning_apply(sim, *out) == SF_OK) (void)restore();
+        fail(r, why);
     }
+    // the snapshot is read by the restore on the stream: free it once drained
+    if (!sim->bad) (void)hipStreamSynchronize(st);
+    dev_free(sim, snap);
+    dev_free(sim, zero_act);
     if (r != SF_OK) return r;
     best.step_us = (float)(1e3 * best_ms[1]);
     best.obs_us = (float)(1e3 * best_ms[2]);
