@@ -649,7 +649,7 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         launch_step(sim->P_dev, sim->Wd, Su, sim->sur_on, sim->st, sim->ist, d_actions, h, substeps, sim->reward,
                     sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->items, sim->step_block,
                     sim->step_grid, sim->queue, sim->stream);
-        if (sim->sur_log)
+        if (sim->sur_log && sim->sur_log_cap > 0)
             sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;
     }
     enqueue_obs(sim);
@@ -850,8 +850,15 @@ sf_status sf_sur_log(sf_sim *sim, int64_t capacity) {
     sim->sur_flag = (int *)dev_alloc(sim, sizeof(int) * (size_t)capacity);
     sim->sur_pos = (int *)dev_alloc(sim, sizeof(int) * ((size_t)capacity + 1));
     sim->sur_scan = (int *)dev_alloc(sim, sizeof(int) * ((size_t)capacity / 1024 + 2));
-    if (!sim->sur_log || !sim->sur_flag || !sim->sur_pos || !sim->sur_scan)
+    if (!sim->sur_log || !sim->sur_flag || !sim->sur_pos || !sim->sur_scan) {
+        // no partial ring: the step logs only while all of it exists
+        dev_free(sim, sim->sur_log);
+        dev_free(sim, sim->sur_flag);
+        dev_free(sim, sim->sur_pos);
+        dev_free(sim, sim->sur_scan);
+        sim->sur_log = nullptr; sim->sur_flag = sim->sur_pos = sim->sur_scan = nullptr;
         return fail(SF_E_OUT_OF_MEMORY, "sample ring");
+    }
     DEV(hipMemsetAsync(sim->sur_log, 0, sizeof(float) * SF_SUR_SAMPLE * (size_t)capacity, sim->stream));
     sim->sur_log_cap = capacity;
     return SF_OK;
