@@ -374,3 +374,23 @@ void launch_world_of(const int *aoff, int W, int *world_of, hipStream_t st) {
     if (W == 0) return;
     k_world_of<<<(W + 255) / 256, 256, 0, st>>>(aoff, W, world_of);
 }
+
+// per agent, what the observation needs of its world (one read instead of
+// world index then world arrays)
+__global__ void k_agent_desc(const int *aoff, const int *roff, const GridHdr *grid, int W, int4 *agent_world,
+                             GridHdr *agent_grid) {
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W) return;
+    const int4 d = make_int4(aoff[w], aoff[w + 1] - aoff[w], roff[w], roff[w + 1] - roff[w]);
+    const GridHdr g = grid[w];
+    for (int n = aoff[w]; n < aoff[w + 1]; ++n) {
+        agent_world[n] = d;
+        agent_grid[n] = g;
+    }
+}
+
+void launch_agent_desc(const int *aoff, const int *roff, const GridHdr *grid, int W, int4 *agent_world,
+                       GridHdr *agent_grid, hipStream_t st) {
+    if (W == 0) return;
+    k_agent_desc<<<(W + 255) / 256, 256, 0, st>>>(aoff, roff, grid, W, agent_world, agent_grid);
+}

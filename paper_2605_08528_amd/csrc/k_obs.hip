@@ -231,10 +231,10 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
     const int N = Wd.N;
     float4 *dst = reinterpret_cast<float4 *>(obs + (size_t)n * SF_OBS_DIM);
 
-    // the loads that depend only on the agent go out together, then the
-    // world's (each group is one memory round trip)
+    // every load that depends only on the agent goes out together, its
+    // world's offsets and road grid header included (per-agent copies), so
+    // the first group is one memory round trip
     const int active = ist[SF_I_ACTIVE * N + n];
-    const int w = Wd.world_of[n];
     const float px = st[SF_F_PX * N + n], py = st[SF_F_PY * N + n];
     const float qw = st[SF_F_QW * N + n], qx = st[SF_F_QX * N + n];
     const float qy = st[SF_F_QY * N + n], qz = st[SF_F_QZ * N + n];
@@ -242,9 +242,9 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
     const float goal_x = st[SF_F_GOAL_X * N + n], goal_y = st[SF_F_GOAL_Y * N + n];
     const float mu_seen = st[SF_F_MU * N + n];
     const float4 hv = hint[n];
-    const int a0 = Wd.aoff[w], A = Wd.aoff[w + 1] - a0;
-    const int r0 = Wd.roff[w], PW = Wd.roff[w + 1] - r0;
-    const GridHdr g = Wd.grid[w];
+    const int4 aw = Wd.agent_world[n];
+    const int a0 = aw.x, A = aw.y, r0 = aw.z, PW = aw.w;
+    const GridHdr g = Wd.agent_grid[n];
     if (!active) {
         dst[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (dbg) dbg[(size_t)n * 72 + lane] = -1;

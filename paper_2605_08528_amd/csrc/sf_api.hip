@@ -40,6 +40,8 @@ struct sf_sim {
     float grid_cell = 8.f, tri_cell = 0.5f;
     const float *verts = nullptr;  // [T][3][3] triangle vertices
     const float4 *bbox = nullptr;  // [W] road bounding boxes
+    int4 *agent_world = nullptr;   // [N] per-agent copies of its world's offsets
+    GridHdr *agent_grid = nullptr; // [N] and road-point grid header
     std::vector<void *> grid_bufs;
     DevParams P_dev{};
     DevWorld Wd{};
@@ -320,6 +322,8 @@ static sf_status build_grids(sf_sim *sim, float grid_cell, float tri_cell) {
     for (void *p : tmp) dev_free(sim, p);
     for (void *p : sim->grid_bufs) dev_free(sim, p);
     sim->grid_bufs = keep;
+    launch_agent_desc(Wn.aoff, Wn.roff, Wn.grid, W, sim->agent_world, sim->agent_grid, st);
+    LAUNCHED();
     sim->Wd = Wn;
     sim->C = (int)CP;
     sim->grid_cell = grid_cell;
@@ -487,6 +491,8 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     float4 *bbox;
     ALLOC(aoff, int, W + 1); ALLOC(roff, int, W + 1); ALLOC(toff, int, W + 1); ALLOC(soff, int, W + 1);
     ALLOC(world_of, int, N);
+    ALLOC(sim->agent_world, int4, N);
+    ALLOC(sim->agent_grid, GridHdr, N);
     ALLOC(road_xy, float2, P); ALLOC(road_q, int2, P); ALLOC(road_type, uint8_t, P);
     ALLOC(verts, float, 9 * (size_t)T); ALLOC(tsurf, uint8_t, T); ALLOC(tri, float4, 4 * (size_t)T);
     ALLOC(mu_class, float, (size_t)W * sim->S); ALLOC(mu, float, (size_t)W * sim->S);
@@ -511,6 +517,8 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     Wd.W = W; Wd.N = N; Wd.S = sim->S;
     Wd.aoff = aoff; Wd.roff = roff; Wd.toff = toff; Wd.soff = soff;
     Wd.world_of = world_of;
+    Wd.agent_world = sim->agent_world;
+    Wd.agent_grid = sim->agent_grid;
     Wd.road_xy = road_xy; Wd.road_q = road_q; Wd.road_type = road_type;
     Wd.tri = tri; Wd.mu = mu; Wd.spawn = spawn;
     Wd.seed = d->seed;

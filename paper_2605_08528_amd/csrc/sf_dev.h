@@ -94,6 +94,8 @@ struct DevWorld {
     const float *mu;                     // [W][S]
     const float *spawn;                  // [E][5]
     const GridHdr *grid;                 // [W] road-point grid
+    const int4 *agent_world;             // [N] world's first agent, agents, first road point, road points
+    const GridHdr *agent_grid;           // [N] the agent's world's road-point grid header
     const GridHdr *tgrid;                // [W] triangle grid (its own cell size)
     const int *tri_cell_start;           // [CT+1]
     const float4 *tri_rec;               // [items][3] (v0, id bits) (e1, surface) (e2, 0), cell order
@@ -287,6 +289,8 @@ void launch_grid_finish(const DevWorld &Wd, int CT, int CP, int *tri_items, int 
                         float4 *tri_rec, int4 *pt_cell, int *pt_occ, hipStream_t st);
 void launch_scan(const int *in, int *out, int n, int *tmp, hipStream_t st);  // exclusive, out[n]
 void launch_world_of(const int *aoff, int W, int *world_of, hipStream_t st);
+void launch_agent_desc(const int *aoff, const int *roff, const GridHdr *grid, int W, int4 *agent_world,
+                       GridHdr *agent_grid, hipStream_t st);
 void launch_reset(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const uint8_t *mask,
                   int bump_episode, hipStream_t s);
 void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
