@@ -815,3 +815,187 @@ def test_surrogate_fallback_rules(oracle_mod):
     # disabled: counts stay at zero and the step is the plain one
     f, cnt = _one_step(O, _net([0.1, 0.0, 0.0]), WIDE, enable=False)
     assert cnt == (0, 0) and np.array_equal(f, plain)
+
+
+# ------------------------------------------------- gyroscopic term (O7)
+def _quat_mul(a, b):
+    aw, ax, ay, az = a
+    bw, bx, by, bz = b
+    return np.array([aw * bw - ax * bx - ay * by - az * bz, aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx, aw * bz + ax * by - ay * bx + az * bw])
+
+
+def _R(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _tilted_quat():
+    """yaw 0.3, then pitch 0.2, then roll 0.1 (a general attitude)."""
+    qz = np.array([math.cos(0.15), 0, 0, math.sin(0.15)])
+    qy = np.array([math.cos(0.1), 0, math.sin(0.1), 0])
+    qx = np.array([math.cos(0.05), math.sin(0.05), 0, 0])
+    return _quat_mul(_quat_mul(qz, qy), qx)
+
+
+def _spinning_body(O, prm, w_body):
+    """An airborne chassis without gravity at a general attitude, spinning
+    at body-frame rate w_body: no wheel, contact or spring acts on it."""
+    o, p = mk(O, [(0, 0, 0.0, 300, 0)], prm)
+    f, k = o.get_state()
+    q = _tilted_quat()
+    f[PZ, 0] = 50.0
+    f[QW:QZ + 1, 0] = q
+    f[WX:WZ + 1, 0] = _R(q) @ np.asarray(w_body, np.float64)
+    o.set_state(f, k)
+    return o, p
+
+
+def _body_rate(o):
+    f, _ = o.get_state()
+    q = f[QW:QZ + 1, 0]
+    return _R(q).T @ f[WX:WZ + 1, 0], q
+
+
+def test_symmetric_top_precession_discrete_closed_form(oracle_mod):
+    """Torque-free symmetric top (roll inertia = pitch inertia I1, yaw I3):
+    Euler's equations turn the body-frame rate (w1, w2) about the symmetry
+    axis at Omega = (I3 - I1) / I1 * w3, counter-clockwise for I3 > I1, with
+    w3 constant.  The explicit gyroscopic update is one forward-Euler step of
+    that rotation per substep, so after n steps the pair has turned by
+    n atan(h Omega) and grown by (1 + h^2 Omega^2)^(n/2); the quaternion
+    update turns the body about the new rate itself, which leaves the
+    body-frame rate unchanged.  A sign slip in the gyroscopic term turns the
+    precession the other way; a body/world frame mix-up breaks the closed
+    form at any attitude other than the identity."""
+    O = oracle_mod
+    I1, I3 = 1500.0, 2800.0
+    prm = params(inertia=(I1, I1, I3), gravity=0.0)
+    w0 = np.array([0.6, 0.0, 2.0])
+    o, _ = _spinning_body(O, prm, w0)
+    Om = (I3 - I1) / I1 * w0[2]
+    for n in range(1, 241):
+        o.step(zeros(1), H, 1)
+        wb, _ = _body_rate(o)
+        amp = w0[0] * (1.0 + (H * Om) ** 2) ** (n / 2)
+        ph = n * math.atan(H * Om)
+        expect = np.array([amp * math.cos(ph), amp * math.sin(ph), w0[2]])
+        assert np.max(np.abs(wb - expect)) < 1e-10, (n, wb, expect)
+        if n == 100:
+            # 1.44 rad of precession after 100 steps: counter-clockwise
+            assert wb[1] > 0.59 and abs(wb[0]) < 0.1
+
+
+def test_angular_momentum_conserved_first_order(oracle_mod):
+    """Torque-free spin about a non-principal axis of the asymmetric body
+    (600, 2500, 2800): the world-frame angular momentum R I R^T w is
+    constant in the continuous dynamics; the semi-implicit scheme with the
+    explicit gyroscopic term keeps it to first order in h (the drift halves
+    when h halves).  Dropping the term, flipping its sign or evaluating it in
+    the wrong frame leaves an O(1) drift that does not shrink with h."""
+    O = oracle_mod
+    prm = params(gravity=0.0)
+    Ib = np.diag([f32(x) for x in prm["inertia"]])
+    w0 = np.array([0.4, 0.9, 0.7])
+    T = 1.0
+    errs = []
+    for S in (2, 4, 8):
+        h = H / S
+        o, _ = _spinning_body(O, prm, w0)
+        wb, q = _body_rate(o)
+        L0 = _R(q) @ Ib @ wb
+        for _ in range(int(round(T / H))):
+            o.step(zeros(1), H, S)
+        wb, q = _body_rate(o)
+        L = _R(q) @ Ib @ wb
+        errs.append(np.linalg.norm(L - L0) / np.linalg.norm(L0))
+    assert errs[-1] < 5e-3, errs
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3, errs
+
+
+# ------------------------------------------------- spawn rotation (O12)
+_MASK64 = (1 << 64) - 1
+
+
+def _splitmix64(x):
+    """SplitMix64 (Steele, Lea and Flood 2014): add the golden gamma, then
+    two xor-shift-multiply rounds and a final xor-shift."""
+    z = (x + 0x9E3779B97F4A7C15) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def test_splitmix64_published_outputs():
+    """The generator reproduces the published first outputs of SplitMix64
+    seeded with 0 (state advanced by the golden gamma before each draw)."""
+    g = 0x9E3779B97F4A7C15
+    got = [_splitmix64((k * g) & _MASK64) for k in range(4)]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+
+
+def _two_worlds_three_entries(seed):
+    from paper_2605_08528_amd import inputs as I
+    tris = []
+    for cx in (0.0, 2000.0):
+        t = np.zeros((2, 3, 3), np.float32)
+        t[0, :, :2] = [(cx - 500, -500), (cx + 500, -500), (cx + 500, 500)]
+        t[1, :, :2] = [(cx - 500, -500), (cx + 500, 500), (cx - 500, 500)]
+        tris.append(t)
+    ent = []
+    for cx in (0.0, 2000.0):
+        for e in range(3):
+            ent.append((cx + 30.0 * e, 7.0 * e, 0.1 * e, cx + 30.0 * e + 200.0, 7.0 * e))
+    return I.Worlds(
+        num_worlds=2, agent_offsets=np.array([0, 2, 4], np.int32),
+        road_offsets=np.zeros(3, np.int32), road_xy=np.zeros((0, 2), np.float32),
+        road_type=np.zeros(0, np.uint8), tri_offsets=np.array([0, 2, 4], np.int32),
+        tri_verts=np.concatenate(tris), tri_surface=np.ones(4, np.uint8), num_surfaces=2,
+        mu_class=np.full((2, 2), 0.9, np.float32), film_mm=np.zeros(2, np.float32),
+        pavement=np.zeros(2, np.uint8), spawn_offsets=np.array([0, 3, 6], np.int32),
+        spawn=np.array(ent, np.float32), seed=seed, name="spawn-rotation")
+
+
+@pytest.mark.parametrize("seed", [0, 0x9E3779B97F4A7C15, 12345])
+def test_spawn_entry_rotation(oracle_mod, seed):
+    """Agent slot j of world w in episode e starts at entry
+    (j + SplitMix64(seed ^ w << 32 ^ e) mod M) mod M of its world's M-entry
+    table.  Seed 0 in world 0, episode 0 draws the published first output
+    0xE220A8397B1DCDAF (entry offset 1 of 3); seed = gamma draws the second.
+    Episodes 0..7 are checked in both worlds (the world index enters the
+    key in its upper half)."""
+    O = oracle_mod
+    w = _two_worlds_three_entries(seed)
+    o = O.Oracle(w, params())
+    if seed == 0:
+        assert 0xE220A8397B1DCDAF % 3 == 1
+    for e in range(8):
+        f, k = o.get_state()
+        for n in range(4):
+            wd, j = n // 2, n % 2
+            assert k[EPISODE, n] == e
+            off = _splitmix64(seed ^ (wd << 32) ^ e) % 3
+            ent = w.spawn[3 * wd + (j + off) % 3]
+            assert f[SX, n] == f32(ent[0]) and f[SY, n] == f32(ent[1]), (e, n)
+            assert f[PX, n] == f32(ent[0]) and f[GX, n] == f32(ent[3]), (e, n)
+            assert abs(2 * math.atan2(f[QZ, n], f[QW, n]) - f32(ent[2])) < 1e-12
+        o.reset(np.ones(4, np.uint8))
+
+
+# ------------------------------------------- hydroplaning end of the curve
+def test_friction_curve_past_the_printed_range(oracle_mod):
+    """Past the printed curve (0..0.8 mm) the paper gives near-complete
+    hydroplaning from 1.0 mm and a floor of 1e-3.  The reading joins the two
+    continuously: mu is continuous at 0.8 mm, non-increasing in h, and sits
+    at the floor from 1.0 mm on, for each pavement."""
+    O = oracle_mod
+    for pav in range(3):
+        hs = np.linspace(0.0, 1.3, 1301)
+        mus = np.array([O.weather_mu(0.9, h, pav) for h in hs])
+        assert np.all(np.diff(mus) <= 1e-15), pav
+        assert abs(O.weather_mu(0.9, 0.8 + 1e-9, pav) - O.weather_mu(0.9, 0.8, pav)) < 1e-6
+        assert O.weather_mu(0.9, 0.8, pav) > 0.5
+        assert O.weather_mu(0.9, 1.0, pav) == 1e-3
+        assert 1e-3 < O.weather_mu(0.9, 0.99, pav) < 0.1
