@@ -52,6 +52,10 @@ typedef enum {
 #define SF_MAX_SURFACES 16          /* friction surfaces per world           */
 #define SF_MAX_SUBSTEPS 16          /* physics substeps per control step     */
 #define SF_MAX_ROAD_POINTS_PER_WORLD (1 << 20)
+/* contact points (overlapping circle pairs) one world's solve holds per
+ * substep; points past it are left out of the solve for both of their
+ * vehicles and reported (SF_EV_CONTACT_OVERFLOW, sf_contact_overflows) */
+#define SF_MAX_CONTACTS_PER_WORLD 512
 
 /* observation layout (floats per agent), see sf_observe */
 #define SF_OBS_DIM 256
@@ -65,6 +69,10 @@ typedef enum {
 #define SF_EV_TIMEOUT 8u     /* episode reached max_episode_steps            */
 #define SF_EV_NUMERIC 16u    /* non-finite state (also sets SF_EV_CRASH)     */
 #define SF_EV_NAN_ACTION 32u /* a NaN action was replaced by 0               */
+#define SF_EV_CONTACT_OVERFLOW 64u /* the agent's world had more contact points
+                                      than SF_MAX_CONTACTS_PER_WORLD in some
+                                      substep of the step (the excess was left
+                                      out of the solve for both vehicles)    */
 
 /* sf_options.flags */
 #define SF_INVINCIBLE 1u       /* events are reported but do not terminate   */
@@ -197,6 +205,13 @@ sf_status sf_observe(sf_sim *sim, float *d_obs, float *d_reward, uint8_t *d_done
 /* Device pointers of the handle's own output buffers (valid until destroy). */
 sf_status sf_output_ptrs(sf_sim *sim, float **obs, float **reward, uint8_t **done,
                          uint8_t **events);
+
+/* Number of (world, substep) solves since the last reset of the counter in
+ * which a world had more than SF_MAX_CONTACTS_PER_WORLD contact points (the
+ * points past it were left out of the solve for both vehicles; the agents of
+ * that world also carry SF_EV_CONTACT_OVERFLOW for the step).  reset != 0
+ * clears the counter after reading.  Synchronises the stream. */
+sf_status sf_contact_overflows(sf_sim *sim, uint64_t *out, int32_t reset);
 
 /* Teleport reset (Sec. "Teleport-only reset"): agents whose d_mask byte is
  * non-zero start a new episode at a spawn entry of their world at rest;
@@ -347,6 +362,26 @@ sf_status sf_sur_enable(sf_sim *sim, int32_t on);
  * network (out[0]) or fell back (out[1]); reset != 0 clears them after
  * reading.  Synchronises. */
 sf_status sf_sur_counts(sf_sim *sim, uint64_t *out, int32_t reset);
+
+/* ---- measuring the road data the kernels read.
+ * Throughput against the memory roofline needs the bytes a control step
+ * must move, and the road data is part of them: the triangle records under
+ * the wheels' rays and the road points the observation visits (the paper
+ * counts throughput per control step, Sec. "Throughput Analysis Details").
+ * While on (enable != 0), every sf_step / sf_step_policy marks each road
+ * item its physics-step kernel and its observation kernel read in a bitmap
+ * and adds, per kernel, the number of distinct items read during that
+ * step; graph capture is refused meanwhile (the marking is for measuring,
+ * not for timing).  enable = 0 switches it off; enabling again clears the
+ * counts.  Synchronises. */
+sf_status sf_road_touch(sf_sim *sim, int32_t enable);
+/* items [2][6]: distinct items read, summed over the counted steps, by the
+ * step kernel ([0][*]) and the observation kernel ([1][*]), per array:
+ * triangle records (48 B), triangle-cell ranges (4 B), road-point records
+ * (16 B), road-point cell ranges (4 B), cell occupancy (4 B), selected road
+ * points (position and type, 9 B); bytes [2]: the same weighted by the item
+ * sizes, per kernel; *steps: the steps counted.  Synchronises. */
+sf_status sf_road_touch_read(sf_sim *sim, uint64_t *items, uint64_t *bytes, int32_t *steps);
 
 /* ---- launch shapes and their autotuner.
  * The paper measures throughput per configuration (Sec. "Throughput

@@ -4,6 +4,8 @@
 // point-index order), and the 8 nearest active neighbours with swept-circle
 // time to collision.  The row is staged in LDS and written as one coalesced
 // 1 KB store per wave.
+#include <algorithm>
+
 #include "sf_dev.h"
 
 __device__ __forceinline__ unsigned long long lane_lt() {
@@ -154,7 +156,8 @@ __device__ __forceinline__ unsigned long long hint_key(float r) {
 // batches of BATCH points per lane; a full buffer is first cut to its 64
 // best, which also lowers kthr.
 template <class SEG>
-__device__ __forceinline__ void gather(int nseg, SEG seg, const int4 *__restrict__ pts, int QX, int QY,
+__device__ __forceinline__ void gather(const DevWorld &Wd, int nseg, SEG seg, const int4 *__restrict__ pts, int QX,
+                                       int QY,
                                        unsigned long long *cand, int *segs, int *segp, int &nc,
                                        unsigned long long &kthr) {
     const int lane = threadIdx.x & 63;
@@ -190,6 +193,7 @@ __device__ __forceinline__ void gather(int nseg, SEG seg, const int4 *__restrict
                         if (segp[mid] <= f) lo = mid; else hi = mid - 1;
                     }
                     pq[t] = pts[segs[lo] + (f - segp[lo])];
+                    if (Wd.touch) touch(Wd, SF_T_PT, segs[lo] + (f - segp[lo]));
                 }
             }
 #pragma unroll
@@ -257,6 +261,7 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
     cx = max(0, min(cx, g.nx - 1));
     cy = max(0, min(cy, g.ny - 1));
     const int rr_first = PW > 0 ? Wd.pt_occ[g.cbase + cy * g.nx + cx] : 0;
+    if (PW > 0) touch(Wd, SF_T_PT_OCC, g.cbase + cy * g.nx + cx);
     float hx = 1.f - 2.f * (qy * qy + qz * qz), hy = 2.f * (qx * qy + qw * qz);
     {
         float L = sqrtf(hx * hx + hy * hy);
@@ -394,7 +399,7 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
             // widest chord of the disk in that row spans
             kthr = hint_key(rhint);
             const int k = (int)(rhint * g.inv_cell) + 1;
-            gather(2 * k + 1, [&](int j, int &s, int &e) {
+            gather(Wd, 2 * k + 1, [&](int j, int &s, int &e) {
                 const int y = cy - k + j;
                 if (y < 0 || y >= g.ny) return;
                 const float ry0 = g.y0 + (float)y * g.cell, ry1 = ry0 + g.cell;
@@ -407,6 +412,8 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
                 const int c0 = g.cbase + y * g.nx;
                 s = Wd.pt_cell_start[c0 + xa];
                 e = Wd.pt_cell_start[c0 + xb + 1];
+                touch(Wd, SF_T_PT_START, c0 + xa);
+                touch(Wd, SF_T_PT_START, c0 + xb + 1);
             }, pts, QX, QY, cand, segs, segp, nc, kthr);
             if (nc >= 64) {
                 settle();
@@ -422,7 +429,7 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
             // the ring's cells as contiguous row segments (top row, bottom
             // row, single cells of the left and right columns), one segment
             // per lane, their points flattened across the wave
-            gather(rr == 0 ? 1 : 4 * rr, [&](int j, int &s, int &e) {
+            gather(Wd, rr == 0 ? 1 : 4 * rr, [&](int j, int &s, int &e) {
                 int y, xa, xb;
                 if (rr == 0) { y = cy; xa = xb = cx; }
                 else if (j == 0) { y = cy - rr; xa = cx - rr; xb = cx + rr; }
@@ -444,6 +451,8 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
                 const int c0 = g.cbase + y * g.nx;
                 s = Wd.pt_cell_start[c0 + xa];
                 e = Wd.pt_cell_start[c0 + xb + 1];
+                touch(Wd, SF_T_PT_START, c0 + xa);
+                touch(Wd, SF_T_PT_START, c0 + xb + 1);
             }, pts, QX, QY, cand, segs, segp, nc, kthr);
             if (nc >= 64) settle();
             // lower bound on the distance to any point outside the visited square
@@ -483,6 +492,7 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
     }
     if (dbg) dbg[(size_t)n * 72 + lane] = my_idx == 0x7fffffff ? -1 : my_idx;
     if (my_idx != 0x7fffffff) {
+        touch(Wd, SF_T_ROAD, r0 + my_idx);
         const float2 rp = Wd.road_xy[r0 + my_idx];
         const float dx = rp.x - px, dy = rp.y - py;
         float *o = row + 8 + 3 * lane;
@@ -632,4 +642,32 @@ __global__ void k_hint_clear(float4 *hint, int n) {
 
 void launch_hint_clear(float4 *hint, int n, hipStream_t s) {
     if (n > 0) k_hint_clear<<<(n + 255) / 256, 256, 0, s>>>(hint, n);
+}
+
+// ------------------------------------------------------------ measuring
+// items set in each of the SF_T_N bit ranges, added to acc[k]
+__global__ void k_touch_count(const unsigned *__restrict__ bits, long long b0, long long b1,
+                              unsigned long long *acc) {
+    unsigned long long c = 0;
+    const long long w0 = b0 >> 5, w1 = (b1 + 31) >> 5;
+    for (long long wd = w0 + blockIdx.x * (long long)blockDim.x + threadIdx.x; wd < w1;
+         wd += (long long)gridDim.x * blockDim.x) {
+        unsigned v = bits[wd];
+        // only the bits inside [b0, b1)
+        if (wd == w0) v &= ~0u << (unsigned)(b0 & 31);
+        if (wd == w1 - 1 && (b1 & 31)) v &= ~0u >> (32u - (unsigned)(b1 & 31));
+        c += __popc(v);
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(acc, c);
+}
+
+void launch_touch_count(const unsigned *bits, const long long *off, unsigned long long *acc, hipStream_t s) {
+    for (int k = 0; k < SF_T_N; ++k) {
+        if (off[k + 1] <= off[k]) continue;
+        const long long words = ((off[k + 1] + 31) >> 5) - (off[k] >> 5);
+        const int blocks = (int)std::min<long long>((words + 255) / 256, 1024);
+        k_touch_count<<<blocks, 256, 0, s>>>(bits, off[k], off[k + 1], acc + k);
+    }
 }

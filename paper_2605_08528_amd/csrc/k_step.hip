@@ -5,8 +5,6 @@
 // chassis, and to agent pairs for contact detection.
 #include "sf_dev.h"
 
-__device__ int g_sf_overflow;  // contact-capacity overflows (diagnostic)
-
 // ---------------------------------------------------------------- raycast
 // body-frame mount point of wheel wh: selects between the four (uniform)
 // parameter entries rather than an indexed read of the argument block,
@@ -107,6 +105,15 @@ __device__ __forceinline__ RayHit raycast(const DevParams &P, const DevWorld &Wd
         const int sA = Wd.tri_cell_start[ca + cx0], eA = Wd.tri_cell_start[ca + cx1 + 1];
         const int sB = Wd.tri_cell_start[cb + cx0], eB = Wd.tri_cell_start[cb + cx1 + 1];
         const int nA = eA - sA, nAB = nA + (cy < cy1 ? eB - sB : 0);
+        if (Wd.touch) {
+            touch(Wd, SF_T_TRI_START, ca + cx0);
+            touch(Wd, SF_T_TRI_START, ca + cx1 + 1);
+            if (cy < cy1) {
+                touch(Wd, SF_T_TRI_START, cb + cx0);
+                touch(Wd, SF_T_TRI_START, cb + cx1 + 1);
+            }
+            for (int r = 0; r < nAB; ++r) touch(Wd, SF_T_TRI_REC, r < nA ? sA + r : sB + (r - nA));
+        }
         for (int rb = 0; rb < nAB; rb += 8) {
             float4 ra[8], rbv[8], rc[8];
 #pragma unroll
@@ -405,7 +412,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ float s_cn[2][SF_CCAP], s_cpc[3][SF_CCAP], s_cwk[SF_CCAP], s_cb[SF_CCAP];
     __shared__ float s_clam[SF_CCAP], s_cdl[SF_CCAP];
     __shared__ int s_cij[SF_CCAP];
-    __shared__ short s_bl[SF_MAXA][SF_BCAP];
+    __shared__ short s_bidx[2 * SF_CCAP];  // each body's contacts (CSR, list order)
+    __shared__ int s_boff[SF_MAXA];
+    __shared__ int s_ovf;                  // contact points past SF_CCAP in a substep
     __shared__ float s_iw[6][SF_MAXA];   // world-frame inverse inertia (xx xy xz yy yz zz)
     __shared__ GridHdr s_tgrid;          // the world's triangle grid
     __shared__ float s_mu[SF_MAX_SURFACES];  // the world's friction per surface
@@ -472,6 +481,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
             if (tid == 0) {
                 s_tgrid = Wd.tgrid[w];
                 s_anytri = it.w != 0;
+                s_ovf = 0;
             }
             if (tid < Wd.S) s_mu[tid] = Wd.mu[w * Wd.S + tid];
             // ---- load the world's agents; decode actions (Sec. "Action Space Details")
@@ -783,8 +793,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     nc += tot;
                     __syncthreads();
                 }
+                // points past the world's capacity are left out of the solve
+                // for both bodies (momentum stays exact) and reported
                 if (nc > SF_CCAP) {
-                    if (tid == 0) atomicAdd(&g_sf_overflow, 1);
+                    if (tid == 0) {
+                        s_ovf = 1;
+                        if (Wd.ovf) atomicAdd(Wd.ovf, 1ull);
+                    }
                     nc = SF_CCAP;
                 }
                 __syncthreads();
@@ -828,17 +843,35 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     int cnt = 0;
                     for (int c = 0; c < nc; ++c) {
                         const int ij = s_cij[c];
-                        if ((ij & 0xFF) == i || ((ij >> 8) & 0xFF) == i) {
-                            if (cnt < SF_BCAP) s_bl[i][cnt] = (short)c;
-                            ++cnt;
-                        }
+                        cnt += ((ij & 0xFF) == i) | (((ij >> 8) & 0xFF) == i);
                     }
-                    if (cnt > SF_BCAP) { atomicAdd(&g_sf_overflow, 1); cnt = SF_BCAP; }
                     s_bn[i] = cnt;
                 }
                 __syncthreads();
 
                 if (nc > 0) {
+                    // ---- each body's contacts as one range of a CSR list, in list
+                    //      order (every contact appears once for each of its bodies)
+                    if (wave == 0) {
+                        const int x = lane < A ? s_bn[lane] : 0;
+                        int incl = x;
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const int y = __shfl_up(incl, o, 64);
+                            if (lane >= o) incl += y;
+                        }
+                        if (lane < A) s_boff[lane] = incl - x;
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < A; i += BLOCK) {
+                        if (!s_bn[i]) continue;
+                        int k = s_boff[i];
+                        for (int c = 0; c < nc; ++c) {
+                            const int ij = s_cij[c];
+                            if ((ij & 0xFF) == i || ((ij >> 8) & 0xFF) == i) s_bidx[k++] = (short)c;
+                        }
+                    }
+                    __syncthreads();
                     // ---- F: effective mass along each normal, relaxed by the larger
                     //      contact count of the two bodies
                     for (int c = tid; c < nc; c += BLOCK) {
@@ -884,9 +917,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             const int cnt = b < A ? s_bn[b] : 0;
                             if (cnt > 0) {
                                 const float pbx = s_p[0][b], pby = s_p[1][b], pbz = s_p[2][b];
+                                const short *bl = s_bidx + s_boff[b];
 #pragma unroll 4
                                 for (int q = g; q < cnt; q += 4) {
-                                    const int c = s_bl[b][q];
+                                    const int c = bl[q];
                                     const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? s_cdl[c] : -s_cdl[c];
                                     const float Jx = dl * s_cn[0][c], Jy = dl * s_cn[1][c];
                                     const float rx = s_cpc[0][c] - pbx, ry = s_cpc[1][c] - pby,
@@ -981,6 +1015,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     if (crash) ev |= SF_EV_CRASH;
                 }
                 if (s_nan[i]) ev |= SF_EV_NAN_ACTION;
+                if (s_ovf) ev |= SF_EV_CONTACT_OVERFLOW;
                 const int ep = ist[SF_I_EP_STEP * N + n] + 1;
                 ist[SF_I_EP_STEP * N + n] = ep;
                 ist[SF_I_SINCE_SPAWN * N + n] += 1;

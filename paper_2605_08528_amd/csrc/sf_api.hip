@@ -34,6 +34,7 @@ struct sf_sim {
     int step_block = 128, obs_waves = 4;
     int step_grid = 0, cus = 256;  // persistent step: workgroups (0: one per world); compute units
     int *queue = nullptr;          // [2] world counter and finished-workgroup counter
+    unsigned long long *ovf = nullptr;  // world-substeps whose contact points exceeded the capacity
     float4 *hint = nullptr;        // [N] last observation's position and 64th road distance
     // grids: the road-point grid (observation kNN) and the triangle grid
     // (wheel rays) with their requested cell sizes, rebuilt when these change
@@ -82,6 +83,13 @@ struct sf_sim {
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // measuring the road data the kernels read (sf_road_touch)
+    bool touch_on = false;
+    unsigned *touch_bits = nullptr;
+    unsigned long long *touch_acc = nullptr;   // [2][SF_T_N] step, observation
+    long long touch_off[SF_T_N + 1] = {};
+    int touch_steps = 0;
+    int n_tri_items = 0;
     // profiling
     bool prof = false;
     struct Rec { int kind; hipEvent_t a, b; };
@@ -151,6 +159,13 @@ static void free_all(sf_sim *s) {
         else if (!s->alloc) (void)hipFree(p);
     }
     s->allocs.clear();
+}
+
+// A captured graph holds kernel arguments by value (grids, envelope, sample
+// ring, which step variant): every call that changes one of them drops it.
+static void drop_graph(sf_sim *s) {
+    if (s->graph_exec) { (void)hipGraphExecDestroy(s->graph_exec); s->graph_exec = nullptr; }
+    if (s->graph) { (void)hipGraphDestroy(s->graph); s->graph = nullptr; }
 }
 
 #define DEV(call)                                                                        \
@@ -326,11 +341,20 @@ static sf_status build_grids(sf_sim *sim, float grid_cell, float tri_cell) {
     LAUNCHED();
     sim->Wd = Wn;
     sim->C = (int)CP;
+    sim->n_tri_items = n_tri_items;
+    // bit ranges of the road-touch bitmaps (rebuilt grids have other sizes)
+    {
+        const long long n[SF_T_N] = {n_tri_items, CT + 1, P, CP + 1, CP, P};
+        sim->touch_off[0] = 0;
+        for (int k = 0; k < SF_T_N; ++k) sim->touch_off[k + 1] = sim->touch_off[k] + n[k];
+        if (sim->touch_bits) { dev_free(sim, sim->touch_bits); sim->touch_bits = nullptr; }
+        sim->touch_on = false;
+        sim->Wd.touch = nullptr;
+    }
     sim->grid_cell = grid_cell;
     sim->tri_cell = tri_cell;
     // a captured graph holds the previous grids
-    if (sim->graph_exec) { (void)hipGraphExecDestroy(sim->graph_exec); sim->graph_exec = nullptr; }
-    if (sim->graph) { (void)hipGraphDestroy(sim->graph); sim->graph = nullptr; }
+    drop_graph(sim);
     return SF_OK;
 }
 
@@ -574,6 +598,9 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     H2D(sim->items, its.data(), sizeof(int4) * W);
     ALLOC(sim->queue, int, 2);
     DEV(hipMemsetAsync(sim->queue, 0, 2 * sizeof(int), st));
+    ALLOC(sim->ovf, unsigned long long, 1);
+    DEV(hipMemsetAsync(sim->ovf, 0, sizeof(unsigned long long), st));
+    Wd.ovf = sim->ovf;
     if (opts.flags & SF_RECORD_CONTACTS) {
         sim->rec_cap = std::max(1, amax * (amax - 1) / 2);
         ALLOC(sim->rec, uint32_t, (size_t)SF_MAX_SUBSTEPS * W * sim->rec_cap);
@@ -637,6 +664,8 @@ static void enqueue_obs(sf_sim *sim) {
     }
 }
 
+static size_t touch_bytes(const sf_sim *s) { return (size_t)((s->touch_off[SF_T_N] + 31) >> 5) * 4; }
+
 sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substeps) {
     CHECK_SIM(sim);
     if (substeps < 1 || substeps > SF_MAX_SUBSTEPS) return fail(SF_E_INVALID_ARG, "substeps must be 1..16");
@@ -654,13 +683,22 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         Su.log = sim->sur_log;
         Su.log_cap = sim->sur_log_cap;
         Su.log_base = sim->sur_log_base;
+        if (sim->touch_on) DEV(hipMemsetAsync(sim->touch_bits, 0, touch_bytes(sim), sim->stream));
         launch_step(sim->P_dev, sim->Wd, Su, sim->sur_on, sim->st, sim->ist, d_actions, h, substeps, sim->reward,
                     sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->items, sim->step_block,
                     sim->step_grid, sim->queue, sim->stream);
         if (sim->sur_log && sim->sur_log_cap > 0)
             sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;
     }
+    if (sim->touch_on) {
+        launch_touch_count(sim->touch_bits, sim->touch_off, sim->touch_acc, sim->stream);
+        DEV(hipMemsetAsync(sim->touch_bits, 0, touch_bytes(sim), sim->stream));
+    }
     enqueue_obs(sim);
+    if (sim->touch_on) {
+        launch_touch_count(sim->touch_bits, sim->touch_off, sim->touch_acc + SF_T_N, sim->stream);
+        sim->touch_steps += 1;
+    }
     LAUNCHED();
     sim->last_substeps = substeps;
     return SF_OK;
@@ -696,8 +734,7 @@ sf_status sf_policy_load(sf_sim *sim, const float *h, size_t n) {
     sim->policy_loaded = true;
     sim->act_valid = false;
     // a captured graph may start from actions of the previous network
-    if (sim->graph_exec) { (void)hipGraphExecDestroy(sim->graph_exec); sim->graph_exec = nullptr; }
-    if (sim->graph) { (void)hipGraphDestroy(sim->graph); sim->graph = nullptr; }
+    drop_graph(sim);
     return SF_OK;
 }
 
@@ -729,13 +766,13 @@ sf_status sf_step_policy(sf_sim *sim, float dt, int32_t substeps) {
 
 sf_status sf_graph_capture(sf_sim *sim, int32_t K, float dt, int32_t substeps) {
     CHECK_SIM(sim);
+    if (sim->touch_on) return fail(SF_E_INVALID_ARG, "road-touch counting is on (sf_road_touch)");
     if (!sim->stream) return fail(SF_E_UNSUPPORTED, "graph capture needs a non-null stream");
     if (!sim->policy_loaded) return fail(SF_E_INVALID_ARG, "no policy loaded");
     if (K < 1 || K > 4096) return fail(SF_E_INVALID_ARG, "control_steps must be 1..4096");
     if (substeps < 1 || substeps > SF_MAX_SUBSTEPS || !(dt > 0.f))
         return fail(SF_E_INVALID_ARG, "bad dt or substeps");
-    if (sim->graph_exec) { (void)hipGraphExecDestroy(sim->graph_exec); sim->graph_exec = nullptr; }
-    if (sim->graph) { (void)hipGraphDestroy(sim->graph); sim->graph = nullptr; }
+    drop_graph(sim);
     const bool prof = sim->prof;
     sim->prof = false;
     // with the fused observation the actions of every later step come from
@@ -847,6 +884,8 @@ sf_status sf_sur_log(sf_sim *sim, int64_t capacity) {
     CHECK_SIM(sim);
     if (capacity < 0 || capacity > (1ll << 28)) return fail(SF_E_INVALID_ARG, "capacity must be in 0..2^28");
     DEV(hipStreamSynchronize(sim->stream));
+    // a captured graph writes into the ring it was captured with
+    drop_graph(sim);
     dev_free(sim, sim->sur_log);
     dev_free(sim, sim->sur_flag);
     dev_free(sim, sim->sur_pos);
@@ -916,6 +955,8 @@ sf_status sf_sur_train(sf_sim *sim, const float *d_data, int64_t M, const sf_sur
         sim->sur_t = 0;
     }
     if (o->set_envelope) {
+        // a captured graph tests wheels against the envelope it was captured with
+        drop_graph(sim);
         float *lo = sim->sur_env + 64 * SF_SUR_IN * 2, *hi = lo + SF_SUR_IN;
         launch_sur_envelope(d_data, (int)M, sim->sur_env, lo, hi, st);
         DEV(hipMemcpyAsync(sim->sur_lo, lo, sizeof(sim->sur_lo), hipMemcpyDeviceToHost, st));
@@ -1030,6 +1071,7 @@ sf_status sf_sur_set(sf_sim *sim, const float *h_params, const float *h_lo, cons
         if (!(h_lo[k] <= h_hi[k])) return fail(SF_E_INVALID_ARG, "envelope needs lo <= hi");
     sf_status r;
     if ((r = sur_alloc(sim)) != SF_OK) return r;
+    drop_graph(sim);  // the envelope is a kernel argument of a captured step
     DEV(hipMemcpyAsync(sim->sur_P, h_params, sizeof(float) * SF_SUR_PARAMS, hipMemcpyHostToDevice, sim->stream));
     DEV(hipMemsetAsync(sim->sur_m, 0, sizeof(float) * SF_SUR_PARAMS, sim->stream));
     DEV(hipMemsetAsync(sim->sur_v, 0, sizeof(float) * SF_SUR_PARAMS, sim->stream));
@@ -1058,6 +1100,7 @@ sf_status sf_sur_get(sf_sim *sim, float *h_params, float *h_lo, float *h_hi) {
 sf_status sf_sur_enable(sf_sim *sim, int32_t on) {
     CHECK_SIM(sim);
     if (on && !sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    if (sim->sur_on != (on != 0)) drop_graph(sim);  // a captured graph runs the other step variant
     sim->sur_on = on != 0;
     return SF_OK;
 }
@@ -1073,6 +1116,60 @@ sf_status sf_sur_counts(sf_sim *sim, uint64_t *out, int32_t reset) {
     DEV(hipStreamSynchronize(sim->stream));
     out[0] = c[0];
     out[1] = c[1];
+    return SF_OK;
+}
+
+sf_status sf_road_touch(sf_sim *sim, int32_t enable) {
+    CHECK_SIM(sim);
+    DEV(hipStreamSynchronize(sim->stream));
+    if (!enable) {
+        sim->touch_on = false;
+        sim->Wd.touch = nullptr;
+        return SF_OK;
+    }
+    if (!sim->touch_bits) {
+        sim->touch_bits = (unsigned *)dev_alloc(sim, touch_bytes(sim));
+        if (!sim->touch_bits) return fail(SF_E_OUT_OF_MEMORY, "road-touch bitmaps");
+    }
+    if (!sim->touch_acc) {
+        sim->touch_acc = (unsigned long long *)dev_alloc(sim, sizeof(unsigned long long) * 2 * SF_T_N);
+        if (!sim->touch_acc) return fail(SF_E_OUT_OF_MEMORY, "road-touch counters");
+    }
+    DEV(hipMemsetAsync(sim->touch_acc, 0, sizeof(unsigned long long) * 2 * SF_T_N, sim->stream));
+    drop_graph(sim);
+    sim->touch_on = true;
+    sim->touch_steps = 0;
+    sim->Wd.touch = sim->touch_bits;
+    std::memcpy(sim->Wd.touch_off, sim->touch_off, sizeof(sim->Wd.touch_off));
+    return SF_OK;
+}
+
+sf_status sf_road_touch_read(sf_sim *sim, uint64_t *items, uint64_t *bytes, int32_t *steps) {
+    CHECK_SIM(sim);
+    if (!items || !bytes || !steps) return fail(SF_E_INVALID_ARG, "NULL output");
+    unsigned long long c[2 * SF_T_N] = {};
+    if (sim->touch_acc) {
+        DEV(hipMemcpyAsync(c, sim->touch_acc, sizeof(c), hipMemcpyDeviceToHost, sim->stream));
+        DEV(hipStreamSynchronize(sim->stream));
+    }
+    const int sz[SF_T_N] = SF_T_BYTES;
+    bytes[0] = bytes[1] = 0;
+    for (int k = 0; k < 2 * SF_T_N; ++k) {
+        items[k] = c[k];
+        bytes[k / SF_T_N] += c[k] * (uint64_t)sz[k % SF_T_N];
+    }
+    *steps = sim->touch_steps;
+    return SF_OK;
+}
+
+sf_status sf_contact_overflows(sf_sim *sim, uint64_t *out, int32_t reset) {
+    CHECK_SIM(sim);
+    if (!out) return fail(SF_E_INVALID_ARG, "out is NULL");
+    unsigned long long c = 0;
+    DEV(hipMemcpyAsync(&c, sim->ovf, sizeof(c), hipMemcpyDeviceToHost, sim->stream));
+    if (reset) DEV(hipMemsetAsync(sim->ovf, 0, sizeof(c), sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    *out = c;
     return SF_OK;
 }
 
@@ -1153,13 +1250,18 @@ sf_status sf_debug_raycast(sf_sim *sim, float *h_out) {
     CHECK_SIM(sim);
     if (!h_out) return fail(SF_E_INVALID_ARG, "h_out is NULL");
     if (sim->N == 0) return SF_OK;
-    float *buf = nullptr;
-    DEV(hipMalloc(&buf, sizeof(float) * 16 * (size_t)sim->N));
+    float *buf = (float *)dev_alloc(sim, sizeof(float) * 16 * (size_t)sim->N);
+    if (!buf) return fail(SF_E_OUT_OF_MEMORY, "debug raycast buffer");
     launch_debug_raycast(sim->P_dev, sim->Wd, sim->st, buf, sim->stream);
-    LAUNCHED();
-    DEV(hipMemcpyAsync(h_out, buf, sizeof(float) * 16 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream));
-    DEV(hipStreamSynchronize(sim->stream));
-    DEV(hipFree(buf));
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h_out, buf, sizeof(float) * 16 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) {
+        sim->bad = true;   // the buffer stays with the handle until destroy
+        return fail(SF_E_DEVICE, std::string("debug raycast: ") + hipGetErrorString(e));
+    }
+    dev_free(sim, buf);
     return SF_OK;
 }
 
@@ -1167,14 +1269,19 @@ sf_status sf_debug_obs_indices(sf_sim *sim, int32_t *h_out) {
     CHECK_SIM(sim);
     if (!h_out) return fail(SF_E_INVALID_ARG, "h_out is NULL");
     if (sim->N == 0) return SF_OK;
-    int *buf = nullptr;
-    DEV(hipMalloc(&buf, sizeof(int) * 72 * (size_t)sim->N));
+    int *buf = (int *)dev_alloc(sim, sizeof(int) * 72 * (size_t)sim->N);
+    if (!buf) return fail(SF_E_OUT_OF_MEMORY, "debug index buffer");
     launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, buf, sim->hint,
                sim->obs_waves == 16 ? 4 : sim->obs_waves, sim->stream);
-    LAUNCHED();
-    DEV(hipMemcpyAsync(h_out, buf, sizeof(int) * 72 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream));
-    DEV(hipStreamSynchronize(sim->stream));
-    DEV(hipFree(buf));
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h_out, buf, sizeof(int) * 72 * (size_t)sim->N, hipMemcpyDeviceToHost, sim->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) {
+        sim->bad = true;   // the buffer stays with the handle until destroy
+        return fail(SF_E_DEVICE, std::string("debug obs indices: ") + hipGetErrorString(e));
+    }
+    dev_free(sim, buf);
     return SF_OK;
 }
 

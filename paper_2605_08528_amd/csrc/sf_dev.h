@@ -20,8 +20,7 @@
 #include "sf.h"
 
 #define SF_MAXA SF_MAX_AGENTS_PER_WORLD
-#define SF_CCAP 512      // contact points per world and substep
-#define SF_BCAP 32       // contact points per body and substep
+#define SF_CCAP SF_MAX_CONTACTS_PER_WORLD  // contact points per world and substep
 #define SF_PAIR_CAP (SF_MAXA * (SF_MAXA - 1) / 2)
 #define SF_KEY_CAP (1ll << 43)   // saturation of kNN squared distances
 #define SF_CAND_CAP 512           // road candidates kept per agent
@@ -102,8 +101,24 @@ struct DevWorld {
     const int *pt_cell_start;            // [CP+1]
     const int4 *pt_cell;                 // (qx, qy, local idx, 0) in cell order
     const int *pt_occ;                   // [CP] Chebyshev distance to the nearest non-empty cell
+    unsigned long long *ovf;             // world-substeps whose contact points exceeded SF_CCAP
     unsigned long long seed;
+    // measuring only (null otherwise): one bit per road item a kernel read,
+    // the items of array k at bits [touch_off[k], touch_off[k + 1])
+    unsigned *touch;
+    long long touch_off[7];
 };
+
+// road arrays whose reads the touch bitmaps record, and their item sizes
+enum { SF_T_TRI_REC, SF_T_TRI_START, SF_T_PT, SF_T_PT_START, SF_T_PT_OCC, SF_T_ROAD, SF_T_N };
+#define SF_T_BYTES {48, 4, 16, 4, 4, 9}
+
+__device__ __forceinline__ void touch(const DevWorld &Wd, int kind, long long idx) {
+    if (Wd.touch) {
+        const long long b = Wd.touch_off[kind] + idx;
+        atomicOr(Wd.touch + (b >> 5), 1u << (unsigned)(b & 31));
+    }
+}
 
 // ------------------------------------------------------------ quantisers
 // positions in units of 2^-10 m, nearest-even, saturating at 2^29
@@ -322,3 +337,5 @@ void launch_sur_adam(float *P, float *m, float *v, const float *grad, int tiles,
 void launch_sur_errors(const float *data, int M, const float *pred, float *err, hipStream_t s);
 void launch_debug_raycast(const DevParams &P, const DevWorld &Wd, const float *st, float *out,
                           hipStream_t s);
+void launch_touch_count(const unsigned *bits, const long long *off_host, unsigned long long *acc,
+                        hipStream_t s);

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libsf.so")
 
 SF_INVINCIBLE, SF_AUTO_RESET, SF_RECORD_CONTACTS = 1, 2, 4
 EV_GOAL, EV_COLLISION, EV_CRASH, EV_TIMEOUT, EV_NUMERIC, EV_NAN_ACTION = 1, 2, 4, 8, 16, 32
+EV_CONTACT_OVERFLOW = 64
+MAX_CONTACTS_PER_WORLD = 512
 NF, NI, OBS_DIM = 24, 4, 256
 FIELDS = ["px", "py", "pz", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
           "om0", "om1", "om2", "om3", "steer", "steer_rate", "mu", "goal_x", "goal_y",
@@ -115,6 +117,9 @@ def lib():
         L.sf_observe.argtypes = [vp, vp, vp, vp, vp]
         L.sf_output_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
         L.sf_reset.argtypes = [vp, vp]
+        L.sf_contact_overflows.argtypes = [vp, vp, i32]
+        L.sf_road_touch.argtypes = [vp, i32]
+        L.sf_road_touch_read.argtypes = [vp, vp, vp, C.POINTER(i32)]
         L.sf_state_bytes.argtypes = [vp]
         L.sf_state_bytes.restype = C.c_size_t
         L.sf_get_state.argtypes = [vp, vp, C.c_size_t]
@@ -147,7 +152,9 @@ def lib():
         L.sf_status_str.restype = C.c_char_p
         L.sf_last_error.restype = C.c_char_p
         for name in ("sf_default_params", "sf_default_options", "sf_create", "sf_destroy", "sf_info",
-                     "sf_step", "sf_observe", "sf_output_ptrs", "sf_reset", "sf_get_state",
+                     "sf_step", "sf_observe", "sf_output_ptrs", "sf_reset", "sf_contact_overflows",
+                     "sf_road_touch", "sf_road_touch_read",
+                     "sf_get_state",
                      "sf_set_state", "sf_get_contacts", "sf_debug_raycast", "sf_debug_obs_indices",
                      "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
                      "sf_graph_launch", "sf_profile", "sf_profile_read", "sf_sur_log", "sf_sur_collect",
@@ -300,6 +307,28 @@ class Sim:
         """mask: uint8 CUDA tensor [N]."""
         assert mask.is_cuda and mask.dtype == self.torch.uint8 and mask.numel() == self.N
         check(lib().sf_reset(self.h, _tptr(mask.contiguous())), "sf_reset")
+
+    def contact_overflows(self, reset: bool = False) -> int:
+        """(world, substep) solves that had more contact points than the
+        per-world capacity since the counter was last cleared."""
+        out = np.zeros(1, np.uint64)
+        check(lib().sf_contact_overflows(self.h, _ptr(out), int(bool(reset))), "sf_contact_overflows")
+        return int(out[0])
+
+    def road_touch(self, enable: bool) -> None:
+        """Count the distinct road items the step and observation kernels read
+        in each following eager step (for the roofline's algorithmic bytes)."""
+        check(lib().sf_road_touch(self.h, int(bool(enable))), "sf_road_touch")
+
+    def road_touch_read(self):
+        """(items [2, 6], bytes [2], steps): distinct road items read, summed over
+        the counted steps, by the step kernel and the observation kernel."""
+        items = np.zeros(12, np.uint64)
+        nbytes = np.zeros(2, np.uint64)
+        steps = C.c_int32()
+        check(lib().sf_road_touch_read(self.h, _ptr(items), _ptr(nbytes), C.byref(steps)),
+              "sf_road_touch_read")
+        return items.reshape(2, 6).astype(np.int64), nbytes.astype(np.int64), steps.value
 
     def state_bytes(self) -> int:
         return int(lib().sf_state_bytes(self.h))

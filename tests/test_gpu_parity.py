@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2605_08528_amd import inputs as I
+from tests import helpers as H
 from tests.helpers import params as mkparams
 
 pytestmark = pytest.mark.gpu
@@ -121,10 +122,34 @@ def test_spawn_matches_oracle(O, torch):
 
 # -------------------------------------------------------------- lockstep
 def test_lockstep_plane(O, torch):
+    """The single-world workload as configured: 1000 steps of seeded uniform
+    throttle/brake and steering."""
     w = I.workload("plane1x2")
     dt, S = I.TIMING["plane1x2"]
-    worst, _ = lockstep(O, torch, w, 300, dt, S)
+    worst, _ = lockstep(O, torch, w, 1000, dt, S)
     print("plane1x2 worst relative error", worst)
+
+
+def _at_speed(seed, lo=5.0, hi=25.0):
+    """Initial state: every vehicle moving along its heading at U[lo, hi]
+    m/s with rolling wheels (tests of the step at speed)."""
+    def init(f, k):
+        rng = np.random.default_rng(seed)
+        spd = rng.uniform(lo, hi, f.shape[1]).astype(np.float32)
+        hx = 1 - 2 * (f[5] ** 2 + f[6] ** 2)
+        hy = 2 * (f[4] * f[5] + f[3] * f[6])
+        f[7], f[8] = spd * hx, spd * hy
+        f[13:17] = spd / 0.35
+    return init
+
+
+def test_lockstep_roads_at_speed(O, torch):
+    """Intersection worlds with every vehicle moving at 5-25 m/s, seeded
+    throttle/brake and steering, dt 1/30 s with 4 substeps (the benchmark's
+    timing): vehicles cross road edges, brake, skid and meet."""
+    w = I.intersections(16, 8, seed=17)
+    worst, n_pairs = lockstep(O, torch, w, 60, 1.0 / 30.0, 4, init=_at_speed(17))
+    print("roads at speed worst relative error", worst, "pairs", n_pairs)
 
 
 def test_lockstep_cross_substeps(O, torch):
@@ -182,6 +207,89 @@ def test_freerun_plane_200_steps(O, torch):
     sim.close()
 
 
+def _driving(step, n, dt, amp):
+    """Driving actions: steady throttle 0.35 and one slow steering sine (3 s
+    period) shared by every vehicle, so vehicles that travel side by side
+    weave in step and never meet."""
+    a = np.empty((n, 2), np.float32)
+    a[:, 0] = 0.35
+    a[:, 1] = amp * math.sin(2.0 * math.pi * step * dt / 3.0)
+    return a
+
+
+def freerun_driving(O, torch, worlds, dt, S, v0, amp, steps=200, min_travel=50.0):
+    """Both implementations run free (each on its own state) for `steps`
+    control steps from one moving state under the driving actions; no
+    vehicle contact and no airborne wheel may occur (a non-chaotic run), and
+    the positions must agree within 1e-3 m after the last step."""
+    from paper_2605_08528_amd import sf
+    sim, orc = make_pair(O, torch, worlds, flags=sf.SF_RECORD_CONTACTS)
+    f, k = sim.get_state()
+    hx = 1 - 2 * (f[5] ** 2 + f[6] ** 2)
+    hy = 2 * (f[4] * f[5] + f[3] * f[6])
+    # roads are origin-centred: head away from the centre along the lane
+    # axis; vehicles near the centre are parked (inactive)
+    along = f[0] * hx + f[1] * hy
+    keep = (np.abs(along) > 12.0) if worlds.road_xy.shape[0] else np.ones(sim.N, bool)
+    sgn = np.where(along < 0, -1.0, 1.0) if worlds.road_xy.shape[0] else np.ones(sim.N)
+    yaw = np.arctan2(sgn * hy, sgn * hx)
+    f[3], f[4], f[5], f[6] = np.cos(yaw / 2), 0.0, 0.0, np.sin(yaw / 2)
+    f[7], f[8], f[9] = v0 * np.cos(yaw), v0 * np.sin(yaw), 0.0
+    f[10:13] = 0.0
+    f[13:17] = v0 / 0.35
+    f[17:19] = 0.0
+    f[20], f[21] = f[0] + 5000.0 * np.cos(yaw), f[1] + 5000.0 * np.sin(yaw)   # goals out of reach
+    k[0] = keep.astype(np.int32)
+    f[0, ~keep] = 1000.0 + 20.0 * np.arange((~keep).sum())
+    f[7:9, ~keep] = 0.0
+    f[13:17, ~keep] = 0.0
+    sim.set_state(f, k)
+    orc.set_state(f.astype(np.float64), k)
+    start = f[:2].astype(np.float64).copy()
+    mu_w = orc.mu_table()[:, 1]
+    wof = np.repeat(np.arange(sim.W), np.diff(worlds.agent_offsets))
+    for step in range(steps):
+        a = _driving(step, sim.N, dt, amp)
+        sim.step(cuda(torch, a), dt, S)
+        orc.step(a, float(np.float32(dt)), S)
+        for s_ in range(S):
+            cg, _ = sim.contacts(s_)
+            assert cg.sum() == 0, (step, s_)
+        fg, kg = sim.get_state()
+        assert np.array_equal(kg[0], k[0]), step
+        # every wheel of every active vehicle on the ground (mean mu seen = the world's mu)
+        assert np.all(np.abs(fg[19, keep] - mu_w[wof[keep]]) <= 1e-6), step
+    fg, kg = sim.get_state()
+    fo, ko = orc.get_state()
+    assert np.array_equal(kg, ko)
+    err = np.max(np.abs(fg[:3, keep].astype(np.float64) - fo[:3, keep]))
+    travel = np.hypot(fo[0, keep] - start[0, keep], fo[1, keep] - start[1, keep])
+    print(f"{worlds.name}: {int(keep.sum())} vehicles, {steps}-step position error {err:.3e} m, "
+          f"travelled {travel.min():.1f}-{travel.max():.1f} m")
+    assert travel.min() >= min_travel
+    assert err <= 1e-3
+    sim.close()
+
+
+def test_freerun_plane_driving_200_steps(O, torch):
+    """The single-world workload (dt 1/120 s) driven at 30 m/s: 200 free
+    steps travel over 50 m with position error <= 1e-3 m."""
+    w = I.workload("plane1x2")
+    dt, S = I.TIMING["plane1x2"]
+    freerun_driving(O, torch, w, dt, S, v0=30.0, amp=0.03)
+
+
+def test_freerun_cross_driving_200_steps(O, torch):
+    """The 64-world intersection workload (dt 1/60 s, 4 substeps) driven at
+    17 m/s away from the intersections (ground friction equal to the road's,
+    so leaving the mesh changes nothing): over 50 m in 200 free steps,
+    position error <= 1e-3 m."""
+    w = I.workload("cross64x8")
+    w.mu_class[:, 0] = w.mu_class[:, 1]
+    dt, S = I.TIMING["cross64x8"]
+    freerun_driving(O, torch, w, dt, S, v0=17.0, amp=0.02)
+
+
 # -------------------------------------------------------------- raycast
 @pytest.mark.parametrize("tri_cell", [0.5, 0.25, 1.0, 3.0])
 def test_raycast_grid_vs_brute_force(O, torch, tri_cell):
@@ -223,15 +331,19 @@ def test_raycast_grid_vs_brute_force(O, torch, tri_cell):
 
 # -------------------------------------------------------------- contacts
 def test_contact_pairs_bit_exact_random_dense(O, torch):
-    """Random poses packed into a small square: the compacted pair list of the
-    first substep equals the oracle's O(n^2) list, order and masks included."""
+    """10 240 worlds of 48 vehicles at random poses packed into squares of
+    16-40 m (10 % inactive): the compacted pair list of the first substep
+    equals the oracle's O(n^2) list, order and masks included."""
     from paper_2605_08528_amd import sf
-    w = I.intersections(32, 48, seed=6, min_sep=3.0, spawn_factor=1)
-    sim, orc = make_pair(O, torch, w, flags=sf.SF_RECORD_CONTACTS | sf.SF_INVINCIBLE)
+    W, A = 10240, 48
+    w = H.plain_worlds(W, A)
+    # 30 m triangle cells: each world's two triangles fill four cells
+    sim, orc = make_pair(O, torch, w, flags=sf.SF_RECORD_CONTACTS | sf.SF_INVINCIBLE, tri_cell=30.0)
     rng = np.random.default_rng(1)
     f, k = sim.get_state()
-    f[0] = rng.uniform(-12, 12, sim.N).astype(np.float32)
-    f[1] = rng.uniform(-12, 12, sim.N).astype(np.float32)
+    half = np.repeat(rng.uniform(8.0, 20.0, W), A)
+    f[0] = (rng.uniform(-1, 1, sim.N) * half).astype(np.float32)
+    f[1] = (rng.uniform(-1, 1, sim.N) * half).astype(np.float32)
     yaw = rng.uniform(-np.pi, np.pi, sim.N)
     f[3], f[4], f[5], f[6] = np.cos(yaw / 2), 0, 0, np.sin(yaw / 2)
     k[0] = (rng.uniform(size=sim.N) > 0.1).astype(np.int32)
@@ -242,20 +354,155 @@ def test_contact_pairs_bit_exact_random_dense(O, torch):
     total = 0
     for wd in range(sim.W):
         ref = orc.detect_pairs(wd)
-        assert cg[wd] == len(ref)
+        assert cg[wd] == len(ref), wd
         assert np.array_equal(pg[wd, :cg[wd]], ref), wd
         total += len(ref)
-    assert total > 100
+    print("random dense pair lists:", W, "worlds,", total, "pairs")
+    assert total > 100 * W
+    sim.close()
+
+
+def _heap(seed, radius, z=None):
+    """Vehicles of every world heaped within `radius` of the world origin at
+    random yaw, with random planar velocities (and optionally airborne)."""
+    def init(f, k):
+        rng = np.random.default_rng(seed)
+        n = f.shape[1]
+        r = radius * np.sqrt(rng.uniform(size=n))
+        a = rng.uniform(0, 2 * np.pi, n)
+        f[0], f[1] = (r * np.cos(a)).astype(np.float32), (r * np.sin(a)).astype(np.float32)
+        if z is not None:
+            f[2] = z
+        yaw = rng.uniform(-np.pi, np.pi, n)
+        f[3], f[4], f[5], f[6] = np.cos(yaw / 2), 0, 0, np.sin(yaw / 2)
+        f[7] = rng.uniform(-3, 3, n).astype(np.float32)
+        f[8] = rng.uniform(-3, 3, n).astype(np.float32)
+    return init
+
+
+def _contacts_per_body(orc, W, A):
+    """Contact points per body and per world of the oracle's pair lists."""
+    per_body, per_world = [], []
+    for wd in range(W):
+        cnt = np.zeros(A, int)
+        for pr in orc.detect_pairs(wd):
+            m = bin(int(pr) >> 16).count("1")
+            cnt[pr & 0xFF] += m
+            cnt[(pr >> 8) & 0xFF] += m
+        per_body.append(cnt.max())
+        per_world.append(cnt.sum() // 2)
+    return max(per_body), max(per_world)
+
+
+def test_lockstep_heaped_vehicles_many_contacts_per_body(O, torch):
+    """Ten vehicles heaped within 1.5 m: a body takes part in up to 81
+    contact points (more than a fixed per-body list of 32 could hold) while
+    the world stays under its 512-point capacity; the Jacobi solve over the
+    full per-body lists matches the oracle in lockstep, no overflow bit."""
+    w = H.plain_worlds(4, 10)
+    prm = mkparams(collision_warmup=0)
+    init = _heap(31, 1.5)
+    o = O.Oracle(w, prm, invincible=True)
+    f, k = o.get_state()
+    f32_ = f.astype(np.float32)
+    init(f32_, k)
+    o.set_state(f32_.astype(np.float64), k)
+    pb, pw = _contacts_per_body(o, 4, 10)
+    print("heap of 10: contact points per body up to", pb, "per world up to", pw)
+    assert pb > 32 and pw <= 512
+    worst, n_pairs = lockstep(O, torch, w, 4, 1.0 / 120.0, 1, prm=prm, flags=1, init=init)
+    print("heap of 10 worst relative error", worst)
+
+
+def test_contact_overflow_reported_and_momentum_conserved(O, torch):
+    """32 airborne vehicles heaped within 2 m (world 0, thousands of contact
+    points) beside a world of 32 well separated ones (world 1): the points
+    past the world's 512-point capacity are left out for both bodies, so
+    linear momentum and angular momentum about z stay exact; every agent of
+    world 0 carries the overflow bit, none of world 1, and the handle counts
+    one overflowing (world, substep) solve."""
+    from paper_2605_08528_amd import sf
+    w = H.plain_worlds(2, 32)
+    prm = mkparams(collision_warmup=0)
+    sim = sf.Sim(w, prm, flags=sf.SF_INVINCIBLE | sf.SF_RECORD_CONTACTS)
+    f, k = sim.get_state()
+    heap = _heap(33, 2.0, z=5.0)
+    f0 = f.copy()
+    heap(f0, k)
+    f[:, :32] = f0[:, :32]
+    f[2, 32:] = 5.0
+    sim.set_state(f, k)
+    assert sim.contact_overflows() == 0
+    sim.step(cuda(torch, np.zeros((sim.N, 2), np.float32)), 1.0 / 120.0, 1)
+    ev = sim.observe()[3].cpu().numpy()
+    fg, _ = sim.get_state()
+    cnt, pairs = sim.contacts(0)
+    pts = sum(bin(int(p) >> 16).count("1") for p in pairs[0, :cnt[0]])
+    print("heap of 32:", cnt[0], "pairs,", pts, "contact points")
+    assert pts > sf.MAX_CONTACTS_PER_WORLD and cnt[1] == 0
+    assert np.all(ev[:32] & sf.EV_CONTACT_OVERFLOW) and not np.any(ev[32:] & sf.EV_CONTACT_OVERFLOW)
+    assert sim.contact_overflows(reset=True) == 1 and sim.contact_overflows() == 0
+    m = float(np.float32(prm["mass"]))
+    Izz = float(np.float32(prm["inertia"][2]))
+    v0, v1 = f[7:9, :32].astype(np.float64), fg[7:9, :32].astype(np.float64)
+    scale = m * (np.abs(v0).sum() + np.abs(v1).sum())
+    assert np.abs(m * (v1.sum(axis=1) - v0.sum(axis=1))).max() <= 1e-5 * scale
+    # angular momentum about z with the positions before the step (the
+    # impulses act at shared contact points and the bodies stay level)
+    x, y = f[0, :32].astype(np.float64), f[1, :32].astype(np.float64)
+    L0 = np.sum(m * (x * v0[1] - y * v0[0]) + Izz * f[12, :32])
+    L1 = np.sum(m * (x * v1[1] - y * v1[0]) + Izz * fg[12, :32].astype(np.float64))
+    assert abs(L1 - L0) <= 1e-4 * (np.sum(m * np.hypot(x, y) * np.abs(v1).sum(axis=0)) + 1.0)
     sim.close()
 
 
 # ---------------------------------------------------------- observations
+HEAD_COLS = [200 + 7 * s + 4 for s in range(8)]
+TTC_COLS = [200 + 7 * s + 6 for s in range(8)]
+
+
+def obs_rows_check(obs_g, obs_o, f64, nidx, a0, prm, tag=""):
+    """Observation rows of agents a0.. of one world against the oracle's on
+    the same float state: every feature within 1e-4 (the relative heading
+    modulo 2: +-1 are the same angle), the time to collision included.  A
+    TTC entry may differ by more only where the GPU's value is the one the
+    definition gives with a decision within TTC_MARGIN of its threshold
+    (neighbour abeam, circles just touching, separating, grazing root),
+    recomputed in FP64 on the state: each such entry is checked and
+    counted.  nidx holds the world-local neighbour indices of the rows."""
+    cr, cd = _circle(prm)
+    d = np.abs(obs_g - obs_o)
+    for c in HEAD_COLS:
+        d[:, c] = np.minimum(d[:, c], 2.0 - d[:, c])
+    rest = d.copy()
+    rest[:, TTC_COLS] = 0
+    assert rest.max() <= 1e-4, (tag, rest.max(), np.unravel_index(rest.argmax(), rest.shape))
+    n_deg = 0
+    for r, s in np.argwhere(d[:, TTC_COLS] > 1e-4):
+        j = int(nidx[r, s])
+        assert j >= 0, (tag, r, s)
+        ok, m = H.ttc_explained(f64, a0 + r, a0 + j, cr, cd, 10.0 * float(obs_g[r, TTC_COLS[s]]))
+        assert ok, (tag, r, s, float(obs_g[r, TTC_COLS[s]]), float(obs_o[r, TTC_COLS[s]]), m)
+        n_deg += 1
+    return d, n_deg
+
+
+_CIRCLE = {}
+
+
+def _circle(prm):
+    key = (prm["length"], prm["width"], prm["wheelbase"])
+    if key not in _CIRCLE:
+        from oracle import oracle as O
+        _CIRCLE[key] = O.circle_model(prm)
+    return _CIRCLE[key]
+
+
 def obs_compare(O, orc, sim, obs_g):
-    """kNN membership/order exact; features within 1e-4 (angles modulo 2)."""
+    """kNN membership/order exact; features within 1e-4 (see obs_rows_check)."""
     idx = sim.debug_obs_indices()
     obs_o = orc.observe()
     f, k = sim.get_state()
-    bad = 0
     for n in range(sim.N):
         if not k[0, n]:
             assert np.all(obs_g[n] == 0)
@@ -264,21 +511,16 @@ def obs_compare(O, orc, sim, obs_g):
         no = orc.knn_neigh(n)
         assert np.array_equal(idx[n, :64], ro), n
         assert np.array_equal(idx[n, 64:], no), n
-    d = np.abs(obs_g - obs_o)
-    # relative heading: +-1 are the same angle
-    for s in range(8):
-        c = 200 + 7 * s + 4
-        d[:, c] = np.minimum(d[:, c], 2.0 - d[:, c])
-    # the time-to-collision feature is discontinuous where a swept circle only
-    # grazes another; accept a mismatch only where the oracle's own value is
-    # near-degenerate (recomputed discriminant margin, checked below)
-    ttc_cols = [200 + 7 * s + 6 for s in range(8)]
-    worst = d.copy()
-    worst[:, ttc_cols] = 0
-    assert worst.max() <= 1e-4, (worst.max(), np.unravel_index(worst.argmax(), worst.shape))
-    ttc_bad = np.argwhere(d[:, ttc_cols] > 1e-3)
-    assert len(ttc_bad) <= max(1, sim.N // 500), ttc_bad
-    return d
+    f64 = f.astype(np.float64)
+    n_deg = 0
+    ao = sim.worlds.agent_offsets
+    for w in range(sim.W):
+        a0, a1 = int(ao[w]), int(ao[w + 1])
+        if a1 > a0:
+            _, nd = obs_rows_check(obs_g[a0:a1], obs_o[a0:a1], f64, idx[a0:a1, 64:], a0, sim.params, w)
+            n_deg += nd
+    print("TTC entries explained by a near-threshold decision:", n_deg)
+    return n_deg
 
 
 def test_obs_parity_cross(O, torch):
@@ -436,12 +678,9 @@ def sampled_full_size(O, torch, name, shapes, n_sample=6, surrogate=None, init=N
             if kg[0, a0 + n]:
                 assert np.array_equal(idx[a0 + n, :64], orc.knn_road(n))
                 assert np.array_equal(idx[a0 + n, 64:], orc.knn_neigh(n))
-        d = np.abs(obs.cpu().numpy()[a0:a1] - orc.observe())
-        for s_ in range(8):
-            c = 200 + 7 * s_ + 4
-            d[:, c] = np.minimum(d[:, c], 2.0 - d[:, c])
-        d[:, [200 + 7 * s_ + 6 for s_ in range(8)]] = 0
-        assert d.max() <= 1e-4, (name, wd, d.max())
+        fo64 = fg.astype(np.float64)
+        obs_rows_check(obs.cpu().numpy()[a0:a1], orc.observe(), fo64, idx[a0:a1, 64:], a0, sim.params,
+                       (name, wd))
     sim.close()
 
 
@@ -479,8 +718,11 @@ def test_policy_mfma_matches_oracle(O, torch):
         a_g = sim.policy_act().cpu().numpy().astype(np.float64)
         a_o = O.policy(Ws, bs, obs.cpu().numpy(), steer_max=0.5)
         rel = np.linalg.norm(a_g - a_o) / np.linalg.norm(a_o)
-        print("policy rows", rows, "obs waves", waves, "relative error", rel, "max abs", np.abs(a_g - a_o).max())
+        mx = np.abs(a_g - a_o).max()
+        print("policy rows", rows, "obs waves", waves, "relative error", rel, "max abs", mx)
         assert rel <= 1e-2
+        # every action, not just the norm: tanh outputs within 1e-2
+        assert mx <= 1e-2, (rows, waves, mx, np.unravel_index(np.abs(a_g - a_o).argmax(), a_g.shape))
         assert np.abs(a_g[:, 1]).max() <= 0.5 + 1e-6
         sim.close()
 

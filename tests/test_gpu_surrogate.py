@@ -164,7 +164,11 @@ def test_gradient_matches_oracle(O, torch):
     for l in range(4):
         for a, b in ((gWg[l], gW[l]), (gbg[l], gb[l])):
             rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            mx = np.abs(a - b).max() / np.abs(b).max()
+            print("layer", l, "gradient relative norm error", rel, "max abs / max", mx)
             assert rel <= 1e-2, (l, rel)
+            # every entry: within 2 % of the tensor's largest gradient
+            assert mx <= 2e-2, (l, mx)
     sim.close()
 
 
@@ -374,3 +378,36 @@ def test_cross1024x16_surrogate_full_size_sampled(O, torch):
     sim.close()
     sampled_full_size(O, torch, "cross1024x16", {"step_grid": 512}, n_sample=4, surrogate=(P, lo, hi),
                       init=moving(seed=10))
+
+
+def test_captured_graph_dropped_by_surrogate_changes(torch):
+    """A captured graph holds the sample ring, the envelope and the step
+    variant as kernel arguments: logging on or off, switching the network
+    on or off, loading parameters and training with a new envelope each drop
+    it, so a replay can never write into a freed ring or run a stale
+    envelope (sf_graph_launch then reports that no graph is captured)."""
+    from paper_2605_08528_amd import sf
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = sf.Sim(I.intersections(2, 4, seed=3), mkparams(), flags=sf.SF_AUTO_RESET, stream=stream)
+        sim.policy_load(*I.mlp_params([256, 256, 256, 2], seed=1))
+        d = cuda(torch, random_data(256, 5))
+        sim.sur_train(d, steps=0, init_seed=3, set_envelope=True)
+        P, lo, hi = sim.sur_get()
+        changes = [("log on", lambda: sim.sur_log(4096)), ("log off", lambda: sim.sur_log(0)),
+                   ("network on", lambda: sim.sur_enable(True)), ("network off", lambda: sim.sur_enable(False)),
+                   ("set", lambda: sim.sur_set(P, lo, hi)),
+                   ("train with envelope", lambda: sim.sur_train(d, steps=1, set_envelope=True))]
+        for name, change in changes:
+            sim.graph_capture(2, 1.0 / 30.0, 4)
+            sim.graph_launch()
+            change()
+            with pytest.raises(sf.SFError, match="no graph captured"):
+                sim.graph_launch()
+        # training without a new envelope keeps the graph (weights are read
+        # from device memory by every replay)
+        sim.graph_capture(2, 1.0 / 30.0, 4)
+        sim.sur_train(d, steps=1)
+        sim.graph_launch()
+        torch.cuda.synchronize()
+        sim.close()
