@@ -13,7 +13,8 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# SF_ORACLE_LIBRARY names another build (the AddressSanitizer build)
+LIB_PATH = os.environ.get("SF_ORACLE_LIBRARY") or os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "sf_oracle.c")
 
 NF, NK, NDYN = 24, 4, 19
@@ -26,15 +27,19 @@ SUR_SIZES = [16, 128, 128, 128, 3]
 SUR_PARAMS = 16 * 128 + 128 + 2 * (128 * 128 + 128) + 3 * 128 + 3
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle into ``oracle/liboracle.so`` (gcc, -O2, OpenMP)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-D_GNU_SOURCE",
-           "-o", LIB_PATH + ".tmp", SRC, "-lm"]
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` (gcc, -O2, OpenMP);
+    sanitize=True builds ``oracle/liboracle_asan.so`` with AddressSanitizer
+    (load it with gcc's libasan preloaded)."""
+    out = os.path.join(HERE, "liboracle_asan.so") if sanitize else os.path.join(HERE, "liboracle.so")
+    san = ["-fsanitize=address", "-fno-omit-frame-pointer", "-g"] if sanitize else []
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-D_GNU_SOURCE", *san,
+           "-o", out + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 class OrParams(C.Structure):

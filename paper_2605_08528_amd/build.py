@@ -30,14 +30,25 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+# AddressSanitizer on the host half only (device code is never instrumented)
+HOST_ASAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+ASAN_LIB = os.path.join(HERE, "libsf_asan.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile libsf.so; sanitize=True builds libsf_asan.so, whose host code
+    carries AddressSanitizer checks (load it with clang's ASan runtime
+    preloaded; the CPU-side tests use it)."""
+    bdir = BUILD + ("_asan" if sanitize else "")
+    lib_out = ASAN_LIB if sanitize else LIB
+    extra = HOST_ASAN if sanitize else []
+    os.makedirs(bdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     cc = hipcc()
 
     def compile_one(src):
-        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        cmd = [cc, *FLAGS, "-c", src, "-o", obj]
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = [cc, *FLAGS, *extra, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,13 +60,22 @@ def build(verbose: bool = False) -> str:
 
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(compile_one, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    tmp = lib_out + ".tmp"
+    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *extra, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_out)
+    return lib_out
+
+
+def asan_runtime() -> str:
+    """clang's AddressSanitizer runtime matching hipcc (to preload)."""
+    for d in sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux"), reverse=True):
+        p = os.path.join(d, "libclang_rt.asan-x86_64.so")
+        if os.path.exists(p):
+            return p
+    raise RuntimeError("clang AddressSanitizer runtime not found")
 
 
 if __name__ == "__main__":

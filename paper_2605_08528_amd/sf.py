@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsf.so")
+# SF_LIBRARY names another build of the same library (the AddressSanitizer
+# build of the host code, for the CPU-side tests run under it)
+LIB_PATH = os.environ.get("SF_LIBRARY") or os.path.join(HERE, "libsf.so")
 
 SF_INVINCIBLE, SF_AUTO_RESET, SF_RECORD_CONTACTS = 1, 2, 4
 EV_GOAL, EV_COLLISION, EV_CRASH, EV_TIMEOUT, EV_NUMERIC, EV_NAN_ACTION = 1, 2, 4, 8, 16, 32
