@@ -352,6 +352,21 @@ sf_status sf_sur_evaluate(sf_sim *sim, const float *d_data, int64_t M, float *h_
  * caller-owned), for any statistic the caller wants.  Enqueued on the
  * handle's stream. */
 sf_status sf_sur_errors(sf_sim *sim, const float *d_data, int64_t M, float *d_err);
+
+/* For callers that cannot allocate device memory (code under stream or
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same per-sample errors as sf_sur_errors, with the network's
+ * predictions kept in a fixed scratch array inside the library (one copy
+ * per GPU, 3 * SF_NOALLOC_MAX_SAMPLES floats = 3 MiB, held until the
+ * process ends) instead of handle memory that may grow.  The call
+ * allocates nothing; the handle and its surrogate parameters must already
+ * exist.  M must lie in 1..SF_NOALLOC_MAX_SAMPLES (else SF_E_INVALID_ARG);
+ * the handle's GPU must be the current device.  Every handle on a GPU
+ * shares that GPU's scratch: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  Enqueued on the
+ * handle's stream; d_err [M] is caller-owned device float32. */
+#define SF_NOALLOC_MAX_SAMPLES (1 << 18)
+sf_status sf_sur_errors_noalloc(sf_sim *sim, const float *d_data, int64_t M, float *d_err);
 /* Load (h_params, h_lo, h_hi: 35587, 16, 16 host floats) or read back the
  * network and its envelope.  Loading clears the Adam moments. */
 sf_status sf_sur_set(sf_sim *sim, const float *h_params, const float *h_lo, const float *h_hi);

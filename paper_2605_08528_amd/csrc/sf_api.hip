@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,8 @@ static sf_status fail(sf_status s, const std::string &msg) {
 
 struct sf_sim {
     hipStream_t stream = nullptr;
+    int device = 0;                // the GPU current at sf_create
+    float *scratch = nullptr;      // that GPU's copy of the fixed scratch array
     sf_alloc_fn alloc = nullptr;
     sf_free_fn free_fn = nullptr;
     void *alloc_ctx = nullptr;
@@ -358,6 +361,33 @@ static sf_status build_grids(sf_sim *sim, float grid_cell, float tri_cell) {
     return SF_OK;
 }
 
+// ------------------------------------------------ fixed per-GPU scratch
+// Device memory of the allocation-free entry points: one array per GPU,
+// created with the code object and kept until the process ends.  Host code
+// never uses the array's name as an address: its device address is looked
+// up once per GPU (with that GPU current) and passed to kernels instead.
+static __device__ __align__(256) float scratch[3 * SF_NOALLOC_MAX_SAMPLES];
+#define SF_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[SF_MAX_DEVICES] = {};
+
+static sf_status scratch_of_current_device(int *dev_out, float **ptr_out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SF_MAX_DEVICES)
+        return fail(SF_E_DEVICE, "no usable current device for the fixed scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SF_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *dev_out = dev;
+    *ptr_out = g_scratch_ptr[dev];
+    return SF_OK;
+}
+
 sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf_options *o,
                     sf_sim **out) {
     if (!out) return fail(SF_E_INVALID_ARG, "out is NULL");
@@ -421,7 +451,14 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
         opts.policy_rows < 0 || opts.policy_rows > 64)
         return fail(SF_E_INVALID_ARG, "launch shape out of range");
 
+    // the library's set-up on this GPU: the device address of its copy of
+    // the fixed scratch array (once per GPU, with that GPU current)
+    int sdev = 0;
+    float *sptr = nullptr;
+    if ((s = scratch_of_current_device(&sdev, &sptr)) != SF_OK) return s;
     sf_sim *sim = new sf_sim();
+    sim->device = sdev;
+    sim->scratch = sptr;
     sim->stream = (hipStream_t)opts.stream;
     sim->alloc = opts.alloc;
     sim->free_fn = opts.free;
@@ -1058,6 +1095,24 @@ sf_status sf_sur_errors(sf_sim *sim, const float *d_data, int64_t M, float *d_er
     if ((r = sur_pred_buf(sim, M)) != SF_OK) return r;
     launch_sur_eval(d_data, (int)M, sim->sur_P, sim->sur_Wb, sim->sur_pred, sim->stream);
     launch_sur_errors(d_data, (int)M, sim->sur_pred, d_err, sim->stream);
+    LAUNCHED();
+    return SF_OK;
+}
+
+sf_status sf_sur_errors_noalloc(sf_sim *sim, const float *d_data, int64_t M, float *d_err) {
+    CHECK_SIM(sim);
+    if (M < 1 || M > SF_NOALLOC_MAX_SAMPLES)
+        return fail(SF_E_INVALID_ARG, "sample count out of range (1.." + std::to_string(SF_NOALLOC_MAX_SAMPLES) +
+                                          " for the allocation-free call)");
+    if (!d_data || !d_err) return fail(SF_E_INVALID_ARG, "NULL data or output");
+    if (!sim->sur_ready) return fail(SF_E_INVALID_ARG, "no surrogate parameters");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != sim->device)
+        return fail(SF_E_INVALID_ARG, "the handle's GPU must be current");
+    // predictions [M][3] go to this GPU's scratch; every one of them is
+    // written before it is read, so nothing needs clearing
+    launch_sur_eval(d_data, (int)M, sim->sur_P, sim->sur_Wb, sim->scratch, sim->stream);
+    launch_sur_errors(d_data, (int)M, sim->scratch, d_err, sim->stream);
     LAUNCHED();
     return SF_OK;
 }

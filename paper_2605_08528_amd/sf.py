@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SF_LIBRARY") or os.path.join(HERE, "libsf.so")
 
 SF_INVINCIBLE, SF_AUTO_RESET, SF_RECORD_CONTACTS = 1, 2, 4
+NOALLOC_MAX_SAMPLES = 1 << 18      # SF_NOALLOC_MAX_SAMPLES of include/sf.h
 EV_GOAL, EV_COLLISION, EV_CRASH, EV_TIMEOUT, EV_NUMERIC, EV_NAN_ACTION = 1, 2, 4, 8, 16, 32
 EV_CONTACT_OVERFLOW = 64
 MAX_CONTACTS_PER_WORLD = 512
@@ -143,6 +144,7 @@ def lib():
         L.sf_sur_predict.argtypes = [vp, vp, C.c_int64, vp]
         L.sf_sur_evaluate.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.sf_sur_errors.argtypes = [vp, vp, C.c_int64, vp]
+        L.sf_sur_errors_noalloc.argtypes = [vp, vp, C.c_int64, vp]
         L.sf_sur_set.argtypes = [vp, vp, vp, vp]
         L.sf_sur_get.argtypes = [vp, vp, vp, vp]
         L.sf_sur_enable.argtypes = [vp, i32]
@@ -161,7 +163,7 @@ def lib():
                      "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
                      "sf_graph_launch", "sf_profile", "sf_profile_read", "sf_sur_log", "sf_sur_collect",
                      "sf_sur_train", "sf_sur_gradient", "sf_sur_predict", "sf_sur_evaluate", "sf_sur_errors",
-                     "sf_sur_set",
+                     "sf_sur_errors_noalloc", "sf_sur_set",
                      "sf_sur_get", "sf_sur_enable", "sf_sur_counts", "sf_get_tuning", "sf_set_tuning",
                      "sf_autotune"):
             getattr(L, name).restype = st
@@ -458,6 +460,15 @@ class Sim:
         e = t.empty(data.shape[0], dtype=t.float32, device=data.device)
         check(lib().sf_sur_errors(self.h, _tptr(data), data.shape[0], _tptr(e)), "sf_sur_errors")
         return e
+
+    def sur_errors_noalloc(self, data, out):
+        """The same errors written into a caller-provided CUDA tensor out [M];
+        the library allocates nothing (its predictions use a fixed per-GPU
+        scratch of at most NOALLOC_MAX_SAMPLES samples)."""
+        assert out.is_cuda and out.dtype == self.torch.float32 and out.numel() >= data.shape[0]
+        check(lib().sf_sur_errors_noalloc(self.h, _tptr(data), data.shape[0], _tptr(out)),
+              "sf_sur_errors_noalloc")
+        return out
 
     def sur_set(self, params, lo, hi) -> None:
         self._sur_keep = [np.ascontiguousarray(a, np.float32) for a in (params, lo, hi)]
