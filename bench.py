@@ -33,12 +33,20 @@ sys.path.insert(0, ROOT)
 METRIC = "controlled-agent steps/s @256 worlds×16 agents; plain vs surrogate step"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
-# algorithmic bytes per agent and launch: state read + write, actions and
-# outputs for the step; the observation row and the state it reads
-STEP_BYTES_PER_AGENT = 2 * 112 + 8 + 6        # state read + write, actions, reward/done/events
-OBS_BYTES_PER_AGENT = 1024 + 64               # observation row write + own state read
+# Algorithmic bytes per controlled agent and control step (the state stays
+# in registers/LDS across substeps): the step kernel reads the state (76 B
+# dynamic + 8 B counters + 16 B start and goal) and the actions (8 B) and
+# writes the state (76 + 8 B) and reward, done and events (6 B); the
+# observation kernel writes the 1 KB observation row.  Road bytes come on
+# top: the distinct grid ranges, triangle records and road points each
+# kernel reads, counted in the kernels during a separate eager pass.
+STEP_BYTES_PER_AGENT = (76 + 8 + 16) + (76 + 8) + 8 + 6
+OBS_BYTES_PER_AGENT = 1024
+CONTROL_STEP_BYTES_PER_AGENT = STEP_BYTES_PER_AGENT + OBS_BYTES_PER_AGENT
 POLICY_FLOP_PER_AGENT = 2 * (256 * 256 * 2 + 256 * 2)
 POLICY_WEIGHT_BYTES = 132098 * 2              # bf16 copies of the three layers read once per launch
+TOUCH_STEPS = 20                              # eager steps of the road-touch counting pass
+SETTLE_STEPS = 300                            # control steps from spawn to the measured traffic state
 # learned tire network 16 -> 128 -> 128 -> 128 -> 3: multiply-adds per evaluation,
 # and forward + backward (weight and input gradients) per training sample
 SUR_FLOP_PER_EVAL = 2 * (16 * 128 + 128 * 128 * 2 + 128 * 3)
@@ -46,11 +54,17 @@ SUR_TRAIN_FLOP_PER_SAMPLE = 3 * SUR_FLOP_PER_EVAL
 ACT_BYTES_PER_AGENT = 8                       # two float actions written
 
 
-def obs_bytes(n_agents: int, fused: bool) -> int:
-    """Algorithmic bytes of one observation launch; the kernel that also
-    evaluates the policy reads the network once and writes the actions."""
-    b = OBS_BYTES_PER_AGENT * n_agents
+def obs_bytes(n_agents: int, fused: bool, road: float = 0.0) -> float:
+    """Algorithmic bytes of one observation launch: the rows written and the
+    road data read; the kernel that also evaluates the policy reads the
+    network once and writes the actions (the step reads them back)."""
+    b = OBS_BYTES_PER_AGENT * n_agents + road
     return b + (POLICY_WEIGHT_BYTES + ACT_BYTES_PER_AGENT * n_agents if fused else 0)
+
+
+def step_bytes(n_agents: int, road: float = 0.0) -> float:
+    """Algorithmic bytes of one step launch (state, actions, outputs, road)."""
+    return STEP_BYTES_PER_AGENT * n_agents + road
 
 
 def log(*a):
@@ -86,34 +100,54 @@ def recorded_traffic(kernel: str, launch_name: str, n_agents: int):
     return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(worlds, prm, dt, S, policy, seconds, max_worlds=16):
     """The FP64 oracle on the first worlds of the workload: observe -> policy
-    -> step, timed over >= 20 control steps after 2 warm-up steps."""
+    -> step, timed over >= 20 control steps after 2 warm-up steps, first on
+    one thread, then with OpenMP over worlds on every host thread (half of
+    the time budget each)."""
     from oracle import oracle as O
     sub = worlds.world_slice(0, min(max_worlds, worlds.num_worlds))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    orc = O.Oracle(sub, prm, auto_reset=True, threads=threads)
     Ws, bs = policy
 
-    def one():
-        obs = orc.observe()
-        act = O.policy(Ws, bs, obs, steer_max=prm["steer_max"]).astype(np.float32)
-        orc.step(act, dt, S)
+    def rate(threads, budget):
+        orc = O.Oracle(sub, prm, auto_reset=True, threads=threads)
 
-    for _ in range(2):
-        one()
-    t0 = time.perf_counter()
-    n = 0
-    while n < 20 or time.perf_counter() - t0 < seconds:
-        one()
-        n += 1
-        if time.perf_counter() - t0 > 3 * seconds:
-            break
-    el = time.perf_counter() - t0
-    return {"value": orc.N * n / el, "unit": "controlled-agent steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {sub.num_worlds} worlds ({orc.N} agents) of the same workload, "
-                      f"{n} control steps (observe, policy, step), FP64 brute force"}
+        def one():
+            obs = orc.observe()
+            act = O.policy(Ws, bs, obs, steer_max=prm["steer_max"]).astype(np.float32)
+            orc.step(act, dt, S)
+
+        for _ in range(2):
+            one()
+        t0 = time.perf_counter()
+        n = 0
+        while n < 20 or time.perf_counter() - t0 < budget:
+            one()
+            n += 1
+            if time.perf_counter() - t0 > 3 * budget:
+                break
+        el = time.perf_counter() - t0
+        return orc.N * n / el, n, orc.N
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one_t, n1, N = rate(1, 0.5 * seconds)
+    all_t, n, N = rate(threads, 0.5 * seconds)
+    return {"value": all_t, "unit": "controlled-agent steps/s", "cores": threads,
+            "kind": "oracle", "cpu": cpu_model(),
+            "single_thread": {"value": one_t, "cores": 1, "steps": n1},
+            "sample": f"first {sub.num_worlds} worlds ({N} agents) of the same workload, "
+                      f"{n} control steps (observe, policy, step) on {threads} threads, "
+                      f"{n1} on one thread; FP64 brute force"}
 
 
 def trajectory_error(sim, torch, sf, dt, S, steps):
@@ -177,20 +211,28 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     sim.sur_enable(True)
     for _ in range(warmup):
         sim.step_policy(dt, S)
+    # profiled eager pass (per-kernel events, wheel counts), then the timed
+    # region measured as the plain step is: replays of a captured graph
     sim.sur_counts(reset=True)
     sim.profile(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
     for _ in range(steps):
         sim.step_policy(dt, S)
-    e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
     prof = sim.profile_read()
     sim.profile(False)
     used, fb = sim.sur_counts(reset=True)
-    sim.sur_enable(False)
+    G = graph_len(steps)
+    sim.graph_capture(G, dt, S)
+    sim.graph_launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps // G):
+        sim.graph_launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sim.sur_enable(False)     # drops the graph
     casps = N * steps / (ms / 1e3)
     step_us = 1e3 * prof["step"][0] / max(1, prof["step"][1])
     # the network runs on every in-domain wheel-substep (fallback decided after)
@@ -201,6 +243,7 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
         f"{used / max(1, used + fb):.3f} of in-domain wheel-substeps")
     return {
         "value": casps, "unit": "controlled-agent steps/s", "ms_per_step": ms / steps,
+        "timed": f"{steps} control steps as replays of {G}-step hipGraphs (profiling off), seed of the main leg",
         "step_kernel_us": step_us,
         "network_tflops_in_step": net_tflops, "train_tflops": train_tflops,
         "network_share": used / max(1, used + fb), "wheel_substeps_in_domain": used + fb,
@@ -252,7 +295,7 @@ def config_leg(name, torch, sf, I, stream, steps, sur_params, tune_steps):
                                                           "grid_cell", "tri_cell")},
                "kernels_us": {k: 1e3 * t / c for k, (t, c) in prof.items() if c}}
         if "step" in out["kernels_us"]:
-            out["step_algorithmic_gbs"] = STEP_BYTES_PER_AGENT * N / (out["kernels_us"]["step"] * 1e-6) / 1e9
+            out["step_algorithmic_gbs"] = step_bytes(N) / (out["kernels_us"]["step"] * 1e-6) / 1e9
         if sur_params is not None:
             sim.sur_set(*sur_params)
             sim.sur_enable(True)
@@ -318,7 +361,10 @@ def measure(args, seed, torch, sf, I, stream, keep=False):
         N = sim.N
         log(f"seed {seed}: {args.workload}: {worlds.num_worlds} worlds, {N} agents, "
             f"{len(worlds.road_xy)} road points, {len(worlds.tri_verts)} triangles")
-        for _ in range(args.warmup):
+        # the measured state is traffic SETTLE_STEPS control steps after spawn
+        # (episodes running, contacts and resets in their steady mix), then
+        # the requested warm-up
+        for _ in range(SETTLE_STEPS + args.warmup):
             sim.step_policy(dt, S)
         torch.cuda.synchronize()
         tuning = sim.tuning()
@@ -339,6 +385,16 @@ def measure(args, seed, torch, sf, I, stream, keep=False):
         prof = sim.profile_read()
         sim.profile(False)
 
+        # road data each kernel reads: distinct items per launch, counted in
+        # the kernels over a separate eager pass (atomics on; not timed)
+        sim.road_touch(True)
+        for _ in range(TOUCH_STEPS):
+            sim.step_policy(dt, S)
+        items, tbytes, tsteps = sim.road_touch_read()
+        sim.road_touch(False)
+        road = {"step": float(tbytes[0]) / max(1, tsteps), "obs": float(tbytes[1]) / max(1, tsteps),
+                "steps": int(tsteps)}
+
         # ---- timed region: K control steps as replays of a G-step graph
         G = graph_len(K)
         sim.graph_capture(G, dt, S)
@@ -354,7 +410,16 @@ def measure(args, seed, torch, sf, I, stream, keep=False):
         ms = g0.elapsed_time(g1)
         f, k = sim.get_state()
         active = int(k[0].sum())
-    r = {"seed": seed, "casps": N * K / (ms / 1e3), "ms_per_step": ms / K, "graph_steps": G,
+        # contact load where the timed region ended: overlapping vehicle pairs
+        # in each substep of one more control step, taken by a second handle
+        # that records its pair lists (the timed handle records none)
+        probe = sf.Sim(worlds, prm, flags=sf.SF_AUTO_RESET | sf.SF_RECORD_CONTACTS, stream=stream)
+        probe.policy_load(*policy)
+        probe.set_state(f, k)
+        probe.step_policy(dt, S)
+        pairs = [int(probe.contacts(q)[0].sum()) for q in range(S)]
+        probe.close()
+    r = {"seed": seed, "road_bytes": road, "contact_pairs_per_substep": pairs, "casps": N * K / (ms / 1e3), "ms_per_step": ms / K, "graph_steps": G,
          "eager_casps": N * K / (eager_ms / 1e3), "eager_ms_per_step": eager_ms / K, "active": active,
          "N": N, "tuning": tuning, "prof": prof, "worlds": worlds, "prm": prm, "policy": policy,
          "dt": dt, "S": S}
@@ -437,28 +502,38 @@ def main():
     dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
     avg_s = kernels[dom]["avg_us"] * 1e-6
     fused = tuning["obs_waves"] == 16
+    road = r0["road_bytes"]
     if dom == "policy":
         flop = POLICY_FLOP_PER_AGENT * N
         roof = {"bound": "mfma", "achieved": flop / avg_s / 1e12, "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "traffic": None}
     else:
-        nbytes = STEP_BYTES_PER_AGENT * N if dom == "step" else obs_bytes(N, fused)
+        nbytes = step_bytes(N, road["step"]) if dom == "step" else obs_bytes(N, fused, road["obs"])
         roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "traffic": None, "measured_copy_gbs": copy_gbs}
+                "unit": "GB/s", "traffic": None, "algorithmic_bytes": nbytes,
+                "road_bytes": road["step"] if dom == "step" else road["obs"],
+                "measured_copy_gbs": copy_gbs}
     roof["frac"] = roof["achieved"] / roof["peak"]
     launch = {"policy": "k_policy_lds<16>" if tuning["policy_rows"] <= 16 else f"k_policy<{tuning['policy_rows']}>",
               "step": f"k_step<{tuning['step_block']}, false>",
               "obs": "k_obs_policy" if fused else f"k_obs<{tuning['obs_waves']}>"}
     roof["kernel"] = launch[dom]
+    roof["avg_us"] = kernels[dom]["avg_us"]
     roof["traffic"] = recorded_traffic({"policy": "k_policy", "step": "k_step", "obs": "k_obs"}[dom],
                                        launch[dom], N)
     roof["timing"] = ("mean HIP-event duration of the kernel over a profiled eager pass of the same "
                       "control steps, seed %d" % args.seed)
+    # the whole control step (policy, step, observation) against the same peak
+    whole = CONTROL_STEP_BYTES_PER_AGENT * N + POLICY_WEIGHT_BYTES + road["step"] + road["obs"]
+    roof["control_step"] = {"algorithmic_bytes": whole, "ms": r0["ms_per_step"],
+                            "achieved": whole / (r0["ms_per_step"] * 1e-3) / 1e9,
+                            "frac": whole / (r0["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     for name in kernels:
         if name == "policy":
             kernels[name]["tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
         elif name in ("step", "obs"):
-            nbytes = STEP_BYTES_PER_AGENT * N if name == "step" else obs_bytes(N, fused)
+            nbytes = step_bytes(N, road["step"]) if name == "step" else obs_bytes(N, fused, road["obs"])
+            kernels[name]["algorithmic_bytes"] = nbytes
             kernels[name]["algorithmic_gbs"] = nbytes / (kernels[name]["avg_us"] * 1e-6) / 1e9
             if name == "obs" and fused:
                 kernels[name]["policy_tflops"] = POLICY_FLOP_PER_AGENT * N / (kernels[name]["avg_us"] * 1e-6) / 1e12
@@ -491,6 +566,8 @@ def main():
             "timed": f"{args.steps} control steps as replays of {r0['graph_steps']}-step hipGraphs, "
                      f"mean over seeds {[r['seed'] for r in runs]}",
             "active_agents": r0["active"],
+            "settle_steps": SETTLE_STEPS,
+            "contact_pairs_per_substep_after_timed": r0["contact_pairs_per_substep"],
             "launch_shapes": {k: tuning[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows")},
         },
         "value_stdev": float(vals.std(ddof=1)) if len(runs) > 1 else 0.0,

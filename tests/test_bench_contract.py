@@ -18,11 +18,17 @@ def test_graph_len_divides_the_timed_steps(steps, g):
     assert steps % bench.graph_len(steps) == 0
 
 
-def test_obs_bytes_counts_weights_and_actions_when_fused():
+def test_byte_counts_follow_the_per_agent_budget():
     n = 4096
-    assert bench.obs_bytes(n, False) == 1088 * n
-    assert bench.obs_bytes(n, True) == 1088 * n + 132098 * 2 + 8 * n
-    assert bench.STEP_BYTES_PER_AGENT == 238
+    # step: state read 76 + 8 + 16, state write 76 + 8, actions 8, outputs 6
+    assert bench.STEP_BYTES_PER_AGENT == 198
+    assert bench.step_bytes(n) == 198 * n
+    assert bench.step_bytes(n, road=12345.0) == 198 * n + 12345.0
+    # observation: the 1 KB row, plus the network and the actions when fused
+    assert bench.obs_bytes(n, False) == 1024 * n
+    assert bench.obs_bytes(n, True) == 1024 * n + 132098 * 2 + 8 * n
+    assert bench.obs_bytes(n, False, road=7.0) == 1024 * n + 7.0
+    assert bench.CONTROL_STEP_BYTES_PER_AGENT == 1222
 
 
 def test_more_than_one_gpu_is_refused():
