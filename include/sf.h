@@ -218,6 +218,33 @@ sf_status sf_contact_overflows(sf_sim *sim, uint64_t *out, int32_t reset);
  * their observation rows are recomputed.  d_mask is [N] device u8. */
 sf_status sf_reset(sf_sim *sim, const uint8_t *d_mask);
 
+/* Step backend (Sec. "Vehicle Dynamics Ablation"; the paper switches it by
+ * a configuration field).  SF_DYNAMICS_PHYSICS (default): the articulated
+ * vehicle above, `substeps` physics substeps per control step.
+ * SF_DYNAMICS_BICYCLE: a kinematic single-track model advanced once per
+ * control step by forward Euler on (x, y, yaw, speed), with the same actions
+ * (positive a_long: front-drive force 2 tau_drive a / r_w; negative: brake
+ * force 2 (tau_brake_front + tau_brake_rear) |a| / r_w, stopping at speed 0),
+ * slip angle atan(l_r tan(steer) / (l_f + l_r)) and yaw rate
+ * speed sin(slip) / l_r, l_f and l_r the front and rear mount distances; no
+ * suspension, tires or contact forces, collisions from the circle pairs of
+ * the new poses (recorded as substep 0), and the same events, rewards,
+ * resets and observations.  The learned tire model and its sample log do
+ * nothing in this mode.  Changing the mode drops a captured graph. */
+#define SF_DYNAMICS_PHYSICS 0
+#define SF_DYNAMICS_BICYCLE 1
+sf_status sf_set_dynamics(sf_sim *sim, int32_t mode);
+
+/* Spatially varying friction (the paper applies one friction value per
+ * world; Appendix "Simulator Limitations and Sharp Edges", uniform friction
+ * surface): h_scale [T] host float32, one factor per road triangle (all
+ * worlds' triangles in order), multiplies the world's friction of the
+ * triangle's surface class for a wheel whose ray hits that triangle; the
+ * ground plane keeps the class value.  NULL sets every factor back to 1.
+ * Factors must be finite and >= 0 (else SF_E_INVALID_ARG, nothing changes).
+ * Rebuilds the road grids (synchronises; drops a captured graph). */
+sf_status sf_set_triangle_friction(sf_sim *sim, const float *h_scale);
+
 /* State snapshot / restore through host memory (synchronous).  The layout is
  * [SF_NUM_FFIELDS][N] float32 followed by [SF_NUM_IFIELDS][N] int32;
  * bytes must equal sf_state_bytes(). */

@@ -114,6 +114,9 @@ def lib():
         L.or_set_surrogate.argtypes = [vp, vp, vp, vp, ip]
         L.or_surrogate_counts.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.or_record_samples.argtypes = [vp, vp]
+        L.or_set_dynamics.argtypes = [vp, ip]
+        L.or_set_tri_friction.argtypes = [vp, vp]
+        L.or_set_tri_friction.restype = ip
         _lib = L
     return _lib
 
@@ -258,6 +261,19 @@ class Oracle:
     def reset(self, mask):
         m = np.ascontiguousarray(mask, np.uint8)
         lib().or_reset(self.h, _ptr(m))
+
+    def set_dynamics(self, mode: str):
+        """'physics' (the articulated vehicle) or 'bicycle' (kinematic model)."""
+        lib().or_set_dynamics(self.h, {"physics": 0, "bicycle": 1}[mode])
+
+    def set_tri_friction(self, scale):
+        """Friction factor per road triangle [T] (None clears it)."""
+        if scale is None:
+            lib().or_set_tri_friction(self.h, None)
+            return
+        self._tri_mu = np.ascontiguousarray(scale, np.float32)
+        if lib().or_set_tri_friction(self.h, _ptr(self._tri_mu)) != 0:
+            raise ValueError("triangle friction factors must be finite and >= 0")
 
     def set_surrogate(self, params, env_lo, env_hi, enable=True):
         self._sur = [np.ascontiguousarray(params, np.float32), np.ascontiguousarray(env_lo, np.float32),

@@ -53,6 +53,8 @@ struct or_sim {
     float env_lo[OR_SUR_IN], env_hi[OR_SUR_IN];
     long long sur_used, sur_fallback;
     float *sample_rec;          /* [N][4][OR_SAMPLE] of the last substep, or NULL */
+    int dynamics;               /* OR_DYN_PHYSICS or OR_DYN_BICYCLE */
+    double *tri_mu_scale;       /* [T] friction factor per road triangle, or NULL */
 };
 
 #define F(s, fld, i) ((s)->f[(size_t)(fld) * (s)->N + (i)])
@@ -223,6 +225,7 @@ void or_destroy(or_sim *s) {
     if (!s) return;
     free(s->aoff); free(s->roff); free(s->toff); free(s->soff);
     free(s->road_xy); free(s->road_type); free(s->tri); free(s->tri_surf);
+    free(s->tri_mu_scale);
     free(s->mu); free(s->spawn); free(s->world_of); free(s->f); free(s->k);
     free(s->sur);
     free(s);
@@ -571,6 +574,8 @@ static void substep_world(or_sim *s, int w, const float *actions, double h,
             int tire = 0;
             if (hit) {
                 mu = s->mu[(size_t)w * s->S + surf];
+                /* spatially varying friction: the hit triangle's own factor */
+                if (tri >= 0 && s->tri_mu_scale) mu *= s->tri_mu_scale[s->toff[w] + tri];
                 mu_acc += mu;
                 /* suspension: massless spring-damper along the ray */
                 double x = s->ell - t;
@@ -833,6 +838,84 @@ void or_events(const or_sim *s, const uint8_t *collided, uint8_t *events) {
         events[i] = K(s, OR_ACTIVE, i) ? (uint8_t)agent_events(s, i, collided[i]) : 0;
 }
 
+/* ------------------------------------------------- kinematic bicycle */
+/* The lightweight backend of Sec. "Vehicle Dynamics Ablation": the same
+ * actions drive a kinematic single-track ("bicycle") model, advanced once
+ * per control tick by forward Euler, without suspension, tires or contact
+ * forces.  Its state (x, y, yaw psi, speed v >= 0) lives in the shared
+ * state: position at ride height, yaw-only orientation, planar velocity
+ * along the direction of travel psi + beta, yaw rate, wheels rolling at
+ * v / r_w, steering angle equal to the clamped command.  With l_f, l_r the
+ * axle distances from the centre of mass, the slip angle at the centre of
+ * mass is beta = atan(l_r / (l_f + l_r) tan delta) and the yaw rate
+ * v sin(beta) / l_r.  A positive command gives the front wheels' drive
+ * force 2 tau_drive a / r_w, a negative one the four brakes' force
+ * 2 (tau_brake_front + tau_brake_rear) |a| / r_w (divided by the mass);
+ * braking stops the vehicle at v = 0, it never reverses.  No wheel touches
+ * a surface, so the friction seen is 0. */
+static void bicycle_world(or_sim *s, int w, const float *actions, double dt, uint8_t *nan_act) {
+    const or_params *p = &s->p;
+    const int a0 = s->aoff[w], a1 = s->aoff[w + 1];
+    const double lf = p->mount[0][0], lr = -p->mount[2][0];
+    for (int i = a0; i < a1; ++i) {
+        const int li = i - a0;
+        if (!K(s, OR_ACTIVE, i)) continue;
+        double al = actions[2 * i], st = actions[2 * i + 1];
+        if (isnan(al)) { al = 0.0; nan_act[li] = 1; }
+        if (isnan(st)) { st = 0.0; nan_act[li] = 1; }
+        if (al > 1.0) al = 1.0;
+        if (al < -1.0) al = -1.0;
+        double delta = st;
+        if (delta > p->steer_max) delta = p->steer_max;
+        if (delta < -p->steer_max) delta = -p->steer_max;
+        const double qw = F(s, OR_QW, i), qx = F(s, OR_QX, i), qy = F(s, OR_QY, i), qz = F(s, OR_QZ, i);
+        const double psi = atan2(2.0 * (qw * qz + qx * qy), 1.0 - 2.0 * (qy * qy + qz * qz));
+        const double v = hypot(F(s, OR_VX, i), F(s, OR_VY, i));
+        const double beta = atan(lr / (lf + lr) * tan(delta));
+        double acc = 0.0;
+        if (al > 0.0) acc = 2.0 * p->tau_drive * al / (p->wheel_radius * p->mass);
+        else if (al < 0.0) acc = -2.0 * (p->tau_brake_front + p->tau_brake_rear) * (-al) / (p->wheel_radius * p->mass);
+        const double x1 = F(s, OR_PX, i) + v * cos(psi + beta) * dt;
+        const double y1 = F(s, OR_PY, i) + v * sin(psi + beta) * dt;
+        const double psi1 = psi + v * sin(beta) / lr * dt;
+        double v1 = v + acc * dt;
+        if (v1 < 0.0) v1 = 0.0;
+        F(s, OR_PX, i) = x1;
+        F(s, OR_PY, i) = y1;
+        F(s, OR_PZ, i) = s->z_ride;
+        F(s, OR_QW, i) = cos(0.5 * psi1);
+        F(s, OR_QX, i) = 0.0;
+        F(s, OR_QY, i) = 0.0;
+        F(s, OR_QZ, i) = sin(0.5 * psi1);
+        F(s, OR_VX, i) = v1 * cos(psi1 + beta);
+        F(s, OR_VY, i) = v1 * sin(psi1 + beta);
+        F(s, OR_VZ, i) = 0.0;
+        F(s, OR_WX, i) = 0.0;
+        F(s, OR_WY, i) = 0.0;
+        F(s, OR_WZ, i) = v1 * sin(beta) / lr;
+        for (int wh = 0; wh < NW; ++wh) F(s, OR_OM0 + wh, i) = v1 / p->wheel_radius;
+        F(s, OR_TH, i) = delta;
+        F(s, OR_THD, i) = 0.0;
+        F(s, OR_MU, i) = 0.0;
+    }
+}
+
+void or_set_dynamics(or_sim *s, int mode) { s->dynamics = mode == OR_DYN_BICYCLE ? OR_DYN_BICYCLE : OR_DYN_PHYSICS; }
+
+int or_set_tri_friction(or_sim *s, const float *scale) {
+    const int T = s->toff[s->W];
+    if (!scale) {
+        free(s->tri_mu_scale);
+        s->tri_mu_scale = NULL;
+        return 0;
+    }
+    for (int k = 0; k < T; ++k)
+        if (!(scale[k] >= 0.0f) || !isfinite(scale[k])) return -1;
+    if (!s->tri_mu_scale) s->tri_mu_scale = (double *)malloc(sizeof(double) * (T + 1));
+    for (int k = 0; k < T; ++k) s->tri_mu_scale[k] = scale[k];
+    return 0;
+}
+
 void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
              uint8_t *done, uint8_t *events, uint32_t *pair_rec, int32_t *pair_cnt,
              int pair_cap) {
@@ -848,10 +931,29 @@ void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
         uint8_t *coll = (uint8_t *)calloc(A + 1, 1);
         uint8_t *was_active = (uint8_t *)calloc(A + 1, 1);
         for (int i = a0; i < a1; ++i) was_active[i - a0] = (uint8_t)K(s, OR_ACTIVE, i);
-        for (int sub = 0; sub < S; ++sub) {
-            uint32_t *rec = pair_rec ? pair_rec + ((size_t)sub * W + w) * pair_cap : NULL;
-            int32_t *rc = pair_cnt ? pair_cnt + (size_t)sub * W + w : NULL;
-            substep_world(s, w, actions, h, nan_act, coll, sub == S - 1, rec, rc, pair_cap);
+        if (s->dynamics == OR_DYN_BICYCLE) {
+            /* one update per control tick; collisions from the circle pairs
+             * of the tick's input poses (as the articulated step takes them
+             * on each substep's input poses) */
+            const int cap = A * (A - 1) / 2 + 1;
+            uint32_t *pairs = (uint32_t *)malloc(sizeof(uint32_t) * cap);
+            const int np = or_detect_pairs(s, w, pairs, cap);
+            for (int k = 0; k < np; ++k) {
+                coll[pairs[k] & 0xFF] = 1;
+                coll[(pairs[k] >> 8) & 0xFF] = 1;
+            }
+            if (pair_rec) {
+                for (int k = 0; k < np && k < pair_cap; ++k) pair_rec[(size_t)w * pair_cap + k] = pairs[k];
+                pair_cnt[w] = np;
+            }
+            free(pairs);
+            bicycle_world(s, w, actions, dt, nan_act);
+        } else {
+            for (int sub = 0; sub < S; ++sub) {
+                uint32_t *rec = pair_rec ? pair_rec + ((size_t)sub * W + w) * pair_cap : NULL;
+                int32_t *rc = pair_cnt ? pair_cnt + (size_t)sub * W + w : NULL;
+                substep_world(s, w, actions, h, nan_act, coll, sub == S - 1, rec, rc, pair_cap);
+            }
         }
         for (int i = a0; i < a1; ++i) {
             int li = i - a0;

@@ -162,6 +162,16 @@ void or_record_samples(or_sim *s, float *rec);
 
 void or_set_threads(int n);
 
+/* dynamics backend: the articulated vehicle (default) or the kinematic
+ * bicycle advanced once per control tick (Sec. "Vehicle Dynamics Ablation") */
+#define OR_DYN_PHYSICS 0
+#define OR_DYN_BICYCLE 1
+void or_set_dynamics(or_sim *s, int mode);
+/* per-triangle friction factor [T] (all worlds' triangles in order) applied
+ * to the class friction of a wheel hit on that triangle; NULL clears it.
+ * Returns -1 (and changes nothing) if a factor is negative or not finite. */
+int or_set_tri_friction(or_sim *s, const float *scale);
+
 #ifdef __cplusplus
 }
 #endif

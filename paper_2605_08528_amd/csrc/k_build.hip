@@ -80,8 +80,19 @@ __global__ void k_prep_tris(const float *v, const uint8_t *surf, float4 *tri, in
     n = L > 0.f ? mul3(n, 1.f / L) : mk3(0.f, 0.f, 1.f);
     tri[4 * (size_t)k + 0] = make_float4(a.x, a.y, a.z, (float)surf[k]);
     tri[4 * (size_t)k + 1] = make_float4(e1.x, e1.y, e1.z, 0.f);
-    tri[4 * (size_t)k + 2] = make_float4(e2.x, e2.y, e2.z, 0.f);
+    tri[4 * (size_t)k + 2] = make_float4(e2.x, e2.y, e2.z, 1.f);   // friction factor (1: the class value)
     tri[4 * (size_t)k + 3] = make_float4(n.x, n.y, n.z, 0.f);
+}
+
+// per-triangle friction factors into the triangles' fourth e2 component
+// (null: every factor back to 1)
+__global__ void k_tri_friction(const float *scale, float4 *tri, int T) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < T) tri[4 * (size_t)k + 2].w = scale ? scale[k] : 1.f;
+}
+
+void launch_tri_friction(const float *scale, float4 *tri, int T, hipStream_t st) {
+    if (T > 0) k_tri_friction<<<(T + 255) / 256, 256, 0, st>>>(scale, tri, T);
 }
 
 void launch_prep_tris(const float *verts, const uint8_t *surf, float4 *tri, int T, hipStream_t st) {
@@ -236,7 +247,7 @@ __global__ void k_pack_tris(DevWorld Wd, int C, const int *tri_items, float4 *re
         const float4 e = Wd.tri[4 * (size_t)(t0 + id) + 2];
         rec[3 * (size_t)k] = make_float4(a.x, a.y, a.z, __int_as_float(id));
         rec[3 * (size_t)k + 1] = make_float4(b.x, b.y, b.z, a.w);
-        rec[3 * (size_t)k + 2] = make_float4(e.x, e.y, e.z, 0.f);
+        rec[3 * (size_t)k + 2] = make_float4(e.x, e.y, e.z, e.w);
     }
 }
 

@@ -44,7 +44,7 @@ __device__ __forceinline__ float mt_rec(const float4 &a, const float4 &b, const 
 
 struct RayHit {
     int hit, surf, tri;
-    float t;
+    float t, mus;   // mus: the hit triangle's friction factor (1 on the ground)
     f3 n;
 };
 
@@ -85,6 +85,7 @@ __device__ __forceinline__ RayHit raycast(const DevParams &P, const DevWorld &Wd
     H.tri = -1;
     H.surf = 0;
     H.t = tg;
+    H.mus = 1.f;
     H.n = mk3(0.f, 0.f, 1.f);
     if (!any_tri) {
         H.hit = tg < INFINITY;
@@ -169,6 +170,7 @@ __device__ __forceinline__ RayHit raycast(const DevParams &P, const DevWorld &Wd
         H.t = bt;
         H.n = n;
         H.surf = (int)b.w;
+        H.mus = c.w;
         H.tri = best;
     }
     return H;
@@ -346,6 +348,135 @@ __device__ __forceinline__ void pair_of(int k, int A, int &i, int &j) {
     j = k - ii * (2 * A - ii - 1) / 2 + ii + 1;
 }
 
+// Quantised three-circle centres (rear, centre, front) of a pose, as
+// (x, y) pairs in units of 2^-10 m: the planar heading comes from the
+// quaternion quantised to 2^-14, so the pair predicate is exact integer
+// arithmetic on both sides of the parity contract.
+__device__ __forceinline__ void circle_centres_q(const DevParams &P, float px, float py, float fqw, float fqx,
+                                                 float fqy, float fqz, int (&cq)[6]) {
+    const long long X = qpos(px), Y = qpos(py);
+    const long long qw = qquat(fqw), qx = qquat(fqx), qy = qquat(fqy), qz = qquat(fqz);
+    const long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);
+    const long long hy = 2 * (qx * qy + qw * qz);
+    const long long nh = isqrt64(hx * hx + hy * hy);
+    long long ox = 0, oy = 0;
+    // |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to the
+    // exact integer quotient (cheaper than 64-bit division)
+    if (nh > 0) {
+        ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);
+        oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);
+    }
+    cq[0] = (int)(X - ox); cq[1] = (int)(Y - oy);
+    cq[2] = (int)X;        cq[3] = (int)Y;
+    cq[4] = (int)(X + ox); cq[5] = (int)(Y + oy);
+}
+
+// Overlapping circle pairs (i < j, both active) of one world's A vehicles
+// from their quantised centres, compacted by one wave with ballots into
+// `pairs` in canonical (i, j) order, packed i | j << 8 | mask << 16 (mask
+// bit 3a + b: circle a of i against circle b of j).  Every lane of the wave
+// returns the number of pairs.
+__device__ __forceinline__ int detect_pairs_wave(const DevParams &P, const int (*cq)[SF_MAXA], const int *act,
+                                                 int A, uint32_t *pairs) {
+    const int lane = threadIdx.x & 63;
+    const int npc = A * (A - 1) / 2;
+    const int pair_bound = (int)sqrtf((float)P.Qr2) + 2 + 2 * P.Qd;
+    int np = 0;
+    for (int base = 0; base < npc; base += 64) {
+        const int k = base + lane;
+        int flag = 0;
+        uint32_t packed = 0;
+        if (k < npc) {
+            int i, j;
+            pair_of(k, A, i, j);
+            // centres farther apart than 2 (r + d) on either axis cannot
+            // overlap; past that test every offset is below 2^13 units and
+            // the squares fit 32-bit integers
+            const int dX = cq[2][i] - cq[2][j], dY = cq[3][i] - cq[3][j];
+            if (act[i] && act[j] && abs(dX) < pair_bound && abs(dY) < pair_bound) {
+                uint32_t mask = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const int dx = cq[2 * a][i] - cq[2 * b][j];
+                        const int dy = cq[2 * a + 1][i] - cq[2 * b + 1][j];
+                        if (dx * dx + dy * dy < P.Qr2) mask |= 1u << (3 * a + b);
+                    }
+                if (mask) {
+                    flag = 1;
+                    packed = (uint32_t)i | ((uint32_t)j << 8) | (mask << 16);
+                }
+            }
+        }
+        const unsigned long long bal = __ballot(flag);
+        if (flag) pairs[np + __popcll(bal & lanemask_lt())] = packed;
+        np += __popcll(bal);
+    }
+    return np;
+}
+
+// End of a control step for active agent n (slot i of world w): writes its
+// new dynamic state dyn and friction seen, takes the sparse events on the
+// quantised pose (Sec. "Reward Design Details": goal within 3 m, collision
+// after the spawn warm-up, crash on falling, drifting or tilting), the
+// time-out, reward and termination, then respawns or parks it
+// (Sec. "Termination and time-out").
+__device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld &Wd, float *st, int *ist, int N,
+                                             int n, int w, int i, const float (&dyn)[SF_F_MU], float mu_seen,
+                                             bool coll, bool nan_act, bool ovf, float *reward, uint8_t *done,
+                                             uint8_t *events) {
+    bool finite = true;
+    for (int c = 0; c < SF_F_MU; ++c) {
+        st[c * N + n] = dyn[c];
+        finite = finite && isfinite(dyn[c]);
+    }
+    st[SF_F_MU * N + n] = mu_seen;
+    uint32_t ev = 0;
+    if (!finite) {
+        ev = SF_EV_CRASH | SF_EV_NUMERIC;
+    } else {
+        const long long X = qpos(dyn[SF_F_PX]), Y = qpos(dyn[SF_F_PY]), Z = qpos(dyn[SF_F_PZ]);
+        const long long gx = X - qpos(st[SF_F_GOAL_X * N + n]), gy = Y - qpos(st[SF_F_GOAL_Y * N + n]);
+        if (gx * gx + gy * gy <= 3072ll * 3072ll) ev |= SF_EV_GOAL;
+        if (coll && ist[SF_I_SINCE_SPAWN * N + n] >= P.warmup) ev |= SF_EV_COLLISION;
+        const long long sx = X - qpos(st[SF_F_START_X * N + n]), sy = Y - qpos(st[SF_F_START_Y * N + n]);
+        bool crash = sx * sx + sy * sy > 102400ll * 102400ll || Z < 0;
+        const long long qx = qquat(dyn[SF_F_QX]), qy = qquat(dyn[SF_F_QY]);
+        crash = crash || ((1ll << 28) - 2 * (qx * qx + qy * qy) < 40265318ll);
+        if (crash) ev |= SF_EV_CRASH;
+    }
+    if (nan_act) ev |= SF_EV_NAN_ACTION;
+    if (ovf) ev |= SF_EV_CONTACT_OVERFLOW;
+    const int ep = ist[SF_I_EP_STEP * N + n] + 1;
+    ist[SF_I_EP_STEP * N + n] = ep;
+    ist[SF_I_SINCE_SPAWN * N + n] += 1;
+    if (ep >= P.max_ep) ev |= SF_EV_TIMEOUT;
+    const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f : 0.f;
+    const bool term = (ev & (SF_EV_GOAL | SF_EV_COLLISION | SF_EV_CRASH)) != 0;
+    const bool dn = (term && !(P.flags & SF_INVINCIBLE)) || (ev & (SF_EV_TIMEOUT | SF_EV_NUMERIC));
+    reward[n] = r;
+    done[n] = dn;
+    events[n] = (uint8_t)ev;
+    if (dn) {
+        if (P.flags & SF_AUTO_RESET) {
+            ist[SF_I_EPISODE * N + n] += 1;
+            spawn_agent(P, Wd, st, ist, N, n, w, i);
+        } else {
+            // parked off-stage at x = 1000 m at rest (Sec. "Termination and time-out")
+            st[SF_F_PX * N + n] = 1000.f;
+            st[SF_F_PY * N + n] = 0.f;
+            st[SF_F_PZ * N + n] = P.z_ride;
+            st[SF_F_QW * N + n] = 1.f;
+            st[SF_F_QX * N + n] = 0.f;
+            st[SF_F_QY * N + n] = 0.f;
+            st[SF_F_QZ * N + n] = 0.f;
+            for (int c = SF_F_VX; c <= SF_F_MU; ++c) st[c * N + n] = 0.f;
+            ist[SF_I_ACTIVE * N + n] = 0;
+        }
+    }
+}
+
 // ---- A: steering PD (Eq. steer PD, implicit in the rate), rotation, planar
 //      heading and the quantised three-circle centres of active agent i
 //      (run for the first substep after the load, and for each later one
@@ -368,22 +499,10 @@ __device__ __forceinline__ void pair_of(int k, int A, int &i, int &j) {
         float L = sqrtf(R[0] * R[0] + R[3] * R[3]);                                  \
         s_hx[i] = L < 1e-12f ? 1.f : R[0] / L;                                       \
         s_hy[i] = L < 1e-12f ? 0.f : R[3] / L;                                       \
-        long long X = qpos(s_p[0][i]), Y = qpos(s_p[1][i]);                          \
-        long long qw = qquat(s_q[0][i]), qx = qquat(s_q[1][i]);                      \
-        long long qy = qquat(s_q[2][i]), qz = qquat(s_q[3][i]);                      \
-        long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);                        \
-        long long hy = 2 * (qx * qy + qw * qz);                                      \
-        long long nh = isqrt64(hx * hx + hy * hy);                                   \
-        long long ox = 0, oy = 0;                                                    \
-        /* |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to */        \
-        /* the exact integer quotient (cheaper than 64-bit division) */              \
-        if (nh > 0) {                                                                \
-            ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);           \
-            oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);           \
-        }                                                                            \
-        s_cq[0][i] = (int)(X - ox); s_cq[1][i] = (int)(Y - oy);                      \
-        s_cq[2][i] = (int)X;        s_cq[3][i] = (int)Y;                             \
-        s_cq[4][i] = (int)(X + ox); s_cq[5][i] = (int)(Y + oy);                      \
+        int cq_[6];                                                                  \
+        circle_centres_q(P, s_p[0][i], s_p[1][i], s_q[0][i], s_q[1][i], s_q[2][i],  \
+                         s_q[3][i], cq_);                                            \
+        for (int c = 0; c < 6; ++c) s_cq[c][i] = cq_[c];                             \
     } while (0)
 
 template <int BLOCK, bool SUR>
@@ -513,7 +632,6 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
             }
             __syncthreads();
 
-            const int npc = A * (A - 1) / 2;
             for (int sub = 0; sub < S; ++sub) {
                 const bool last = sub == S - 1;
                 if (sub == 0) {
@@ -528,39 +646,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 //      wheels: raycast, suspension, tire, spin.  B and C overlap.
                 const bool pair_wave = NWV == 1 || wave == NWV - 1;
                 if (pair_wave) {
-                    const int pair_bound = (int)sqrtf((float)P.Qr2) + 2 + 2 * P.Qd;
-                    int np_w = 0;
-                    for (int base = 0; base < npc; base += 64) {
-                        const int k = base + lane;
-                        int flag = 0;
-                        uint32_t packed = 0;
-                        if (k < npc) {
-                            int i, j;
-                            pair_of(k, A, i, j);
-                            // centres farther apart than 2 (r + d) on either axis
-                            // cannot overlap; past that test every offset is below
-                            // 2^13 units and the squares fit 32-bit integers
-                            const int dX = s_cq[2][i] - s_cq[2][j], dY = s_cq[3][i] - s_cq[3][j];
-                            if (s_act[i] && s_act[j] && abs(dX) < pair_bound && abs(dY) < pair_bound) {
-                                uint32_t mask = 0;
-#pragma unroll
-                                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                                    for (int b = 0; b < 3; ++b) {
-                                        const int dx = s_cq[2 * a][i] - s_cq[2 * b][j];
-                                        const int dy = s_cq[2 * a + 1][i] - s_cq[2 * b + 1][j];
-                                        if (dx * dx + dy * dy < P.Qr2) mask |= 1u << (3 * a + b);
-                                    }
-                                if (mask) {
-                                    flag = 1;
-                                    packed = (uint32_t)i | ((uint32_t)j << 8) | (mask << 16);
-                                }
-                            }
-                        }
-                        const unsigned long long bal = __ballot(flag);
-                        if (flag) s_pairs[np_w + __popcll(bal & lanemask_lt())] = packed;
-                        np_w += __popcll(bal);
-                    }
+                    const int np_w = detect_pairs_wave(P, s_cq, s_act, A, s_pairs);
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     if (rec) {
@@ -604,7 +690,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             hit = H.hit;
                             if (hit) {
                                 n = H.n;
-                                mu = s_mu[H.surf];
+                                mu = s_mu[H.surf] * H.mus;
                                 mu_seen = mu;
                                 // massless spring-damper along the ray
                                 x = P.ell - H.t;
@@ -994,55 +1080,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 }
                 dyn[SF_F_STEER] = s_th[i];
                 dyn[SF_F_STEER_RATE] = s_thd[i];
-                bool finite = true;
-                for (int c = 0; c < SF_F_MU; ++c) {
-                    st[c * N + n] = dyn[c];
-                    finite = finite && isfinite(dyn[c]);
-                }
-                st[SF_F_MU * N + n] = s_muo[i];
-                uint32_t ev = 0;
-                if (!finite) {
-                    ev = SF_EV_CRASH | SF_EV_NUMERIC;
-                } else {
-                    const long long X = qpos(dyn[SF_F_PX]), Y = qpos(dyn[SF_F_PY]), Z = qpos(dyn[SF_F_PZ]);
-                    const long long gx = X - qpos(st[SF_F_GOAL_X * N + n]), gy = Y - qpos(st[SF_F_GOAL_Y * N + n]);
-                    if (gx * gx + gy * gy <= 3072ll * 3072ll) ev |= SF_EV_GOAL;
-                    if (s_coll[i] && ist[SF_I_SINCE_SPAWN * N + n] >= P.warmup) ev |= SF_EV_COLLISION;
-                    const long long sx = X - qpos(st[SF_F_START_X * N + n]), sy = Y - qpos(st[SF_F_START_Y * N + n]);
-                    bool crash = sx * sx + sy * sy > 102400ll * 102400ll || Z < 0;
-                    const long long qx = qquat(dyn[SF_F_QX]), qy = qquat(dyn[SF_F_QY]);
-                    crash = crash || ((1ll << 28) - 2 * (qx * qx + qy * qy) < 40265318ll);
-                    if (crash) ev |= SF_EV_CRASH;
-                }
-                if (s_nan[i]) ev |= SF_EV_NAN_ACTION;
-                if (s_ovf) ev |= SF_EV_CONTACT_OVERFLOW;
-                const int ep = ist[SF_I_EP_STEP * N + n] + 1;
-                ist[SF_I_EP_STEP * N + n] = ep;
-                ist[SF_I_SINCE_SPAWN * N + n] += 1;
-                if (ep >= P.max_ep) ev |= SF_EV_TIMEOUT;
-                const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f : 0.f;
-                const bool term = (ev & (SF_EV_GOAL | SF_EV_COLLISION | SF_EV_CRASH)) != 0;
-                const bool dn = (term && !(P.flags & SF_INVINCIBLE)) || (ev & (SF_EV_TIMEOUT | SF_EV_NUMERIC));
-                reward[n] = r;
-                done[n] = dn;
-                events[n] = (uint8_t)ev;
-                if (dn) {
-                    if (P.flags & SF_AUTO_RESET) {
-                        ist[SF_I_EPISODE * N + n] += 1;
-                        spawn_agent(P, Wd, st, ist, N, n, w, i);
-                    } else {
-                        // parked off-stage at x = 1000 m at rest (Sec. "Termination and time-out")
-                        st[SF_F_PX * N + n] = 1000.f;
-                        st[SF_F_PY * N + n] = 0.f;
-                        st[SF_F_PZ * N + n] = P.z_ride;
-                        st[SF_F_QW * N + n] = 1.f;
-                        st[SF_F_QX * N + n] = 0.f;
-                        st[SF_F_QY * N + n] = 0.f;
-                        st[SF_F_QZ * N + n] = 0.f;
-                        for (int c = SF_F_VX; c <= SF_F_MU; ++c) st[c * N + n] = 0.f;
-                        ist[SF_I_ACTIVE * N + n] = 0;
-                    }
-                }
+                finish_agent(P, Wd, st, ist, N, n, w, i, dyn, s_muo[i], s_coll[i] != 0, s_nan[i] != 0, s_ovf != 0,
+                             reward, done, events);
             }
         } while (0);
         if (!queue) break;
@@ -1088,6 +1127,108 @@ void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool 
         k_step<320, false><<<grid, 320, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec, rec_cnt,
                                                 rec_cap, items, queue);
 #undef SF_STEP_LAUNCH
+}
+
+// ------------------------------------------------------ kinematic bicycle
+// The lightweight backend (Sec. "Vehicle Dynamics Ablation"): the same
+// actions drive a kinematic single-track model, advanced once per control
+// tick by forward Euler, with no suspension, tires or contact forces.  Slip
+// angle at the centre of mass beta = atan(l_r tan(delta) / (l_f + l_r)),
+// yaw rate v sin(beta) / l_r; front-drive force 2 tau_drive a / r_w, brake
+// force 2 (tau_bf + tau_br) |a| / r_w, and braking stops at v = 0 (no
+// reversing).  Vehicle pairs whose circles overlap on the tick's input
+// poses count as collisions (the articulated step takes them on each
+// substep's input poses).  One wave per world, one lane per vehicle; the state keeps
+// its shared layout (level chassis at ride height, yaw-only orientation,
+// planar velocity along the direction of travel, rolling wheels, steering
+// angle = command, no friction seen).
+__global__ __launch_bounds__(64) void k_step_bicycle(DevParams P, DevWorld Wd, float *__restrict__ st,
+                                                     int *__restrict__ ist, const float *__restrict__ act, float dt,
+                                                     float *__restrict__ reward, uint8_t *__restrict__ done,
+                                                     uint8_t *__restrict__ events, uint32_t *__restrict__ rec,
+                                                     int *__restrict__ rec_cnt, int rec_cap,
+                                                     const int4 *__restrict__ items) {
+    __shared__ int s_cq[6][SF_MAXA];
+    __shared__ int s_act[SF_MAXA];
+    __shared__ uint8_t s_coll[SF_MAXA];
+    __shared__ uint32_t s_pairs[SF_PAIR_CAP];
+    const int4 it = items[blockIdx.x];
+    const int w = it.x, a0 = it.y, A = it.z, N = Wd.N, i = threadIdx.x, n = a0 + i;
+    if (A <= 0) return;
+    const bool mine = i < A;
+    const bool on = mine && ist[SF_I_ACTIVE * N + n] != 0;
+    if (mine) {
+        s_act[i] = on;
+        s_coll[i] = 0;
+    }
+    if (on) {
+        int cq[6];
+        circle_centres_q(P, st[SF_F_PX * N + n], st[SF_F_PY * N + n], st[SF_F_QW * N + n], st[SF_F_QX * N + n],
+                         st[SF_F_QY * N + n], st[SF_F_QZ * N + n], cq);
+        for (int c = 0; c < 6; ++c) s_cq[c][i] = cq[c];
+    }
+    wave_sync();
+    const int np = detect_pairs_wave(P, s_cq, s_act, A, s_pairs);
+    wave_sync();
+    if (rec) {
+        for (int k = i; k < np && k < rec_cap; k += 64) rec[(size_t)w * rec_cap + k] = s_pairs[k];
+        if (i == 0) rec_cnt[w] = np;
+    }
+    for (int k = i; k < np; k += 64) {
+        s_coll[s_pairs[k] & 0xFF] = 1;
+        s_coll[(s_pairs[k] >> 8) & 0xFF] = 1;
+    }
+    wave_sync();
+    if (!mine) return;
+    if (!on) {
+        reward[n] = 0.f;
+        done[n] = 0;
+        events[n] = 0;
+        return;
+    }
+    float dyn[SF_F_MU];
+    bool bad = false;
+    {
+        float al = act[2 * (size_t)n], sa = act[2 * (size_t)n + 1];
+        if (al != al) { al = 0.f; bad = true; }
+        if (sa != sa) { sa = 0.f; bad = true; }
+        al = fminf(fmaxf(al, -1.f), 1.f);
+        const float delta = fminf(fmaxf(sa, -P.steer_max), P.steer_max);
+        const float qw = st[SF_F_QW * N + n], qx = st[SF_F_QX * N + n];
+        const float qy = st[SF_F_QY * N + n], qz = st[SF_F_QZ * N + n];
+        const float psi = atan2f(2.f * (qw * qz + qx * qy), 1.f - 2.f * (qy * qy + qz * qz));
+        const float v = hypotf(st[SF_F_VX * N + n], st[SF_F_VY * N + n]);
+        const float lf = P.mount[0][0], lr = -P.mount[2][0];
+        const float beta = atanf(lr / (lf + lr) * tanf(delta));
+        const float acc = al > 0.f ? 2.f * P.tau_drive * al / (P.rw * P.mass)
+                        : al < 0.f ? -2.f * (P.tau_bf + P.tau_br) * (-al) / (P.rw * P.mass) : 0.f;
+        const float psi1 = psi + v * sinf(beta) / lr * dt;
+        const float v1 = fmaxf(v + acc * dt, 0.f);
+        dyn[SF_F_PX] = st[SF_F_PX * N + n] + v * cosf(psi + beta) * dt;
+        dyn[SF_F_PY] = st[SF_F_PY * N + n] + v * sinf(psi + beta) * dt;
+        dyn[SF_F_PZ] = P.z_ride;
+        dyn[SF_F_QW] = cosf(0.5f * psi1);
+        dyn[SF_F_QX] = 0.f;
+        dyn[SF_F_QY] = 0.f;
+        dyn[SF_F_QZ] = sinf(0.5f * psi1);
+        dyn[SF_F_VX] = v1 * cosf(psi1 + beta);
+        dyn[SF_F_VY] = v1 * sinf(psi1 + beta);
+        dyn[SF_F_VZ] = 0.f;
+        dyn[SF_F_WX] = 0.f;
+        dyn[SF_F_WY] = 0.f;
+        dyn[SF_F_WZ] = v1 * sinf(beta) / lr;
+        for (int c = 0; c < 4; ++c) dyn[SF_F_OM0 + c] = v1 / P.rw;
+        dyn[SF_F_STEER] = delta;
+        dyn[SF_F_STEER_RATE] = 0.f;
+    }
+    finish_agent(P, Wd, st, ist, N, n, w, i, dyn, 0.f, s_coll[i] != 0, bad, false, reward, done, events);
+}
+
+void launch_step_bicycle(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act, float dt,
+                         float *reward, uint8_t *done, uint8_t *events, uint32_t *rec, int *rec_cnt, int rec_cap,
+                         const int4 *items, hipStream_t s) {
+    if (Wd.W == 0) return;
+    k_step_bicycle<<<Wd.W, 64, 0, s>>>(P, Wd, st, ist, act, dt, reward, done, events, rec, rec_cnt, rec_cap, items);
 }
 
 // ------------------------------------------------------------------ reset

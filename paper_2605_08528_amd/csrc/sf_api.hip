@@ -58,6 +58,7 @@ struct sf_sim {
     int *rec_cnt = nullptr;
     int rec_cap = 0;
     int last_substeps = 0;
+    int dynamics = SF_DYNAMICS_PHYSICS;   // step backend (sf_set_dynamics)
     // policy
     int policy_rows = 64;
     float steer_max = 0.5f;
@@ -721,11 +722,18 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         Su.log_cap = sim->sur_log_cap;
         Su.log_base = sim->sur_log_base;
         if (sim->touch_on) DEV(hipMemsetAsync(sim->touch_bits, 0, touch_bytes(sim), sim->stream));
-        launch_step(sim->P_dev, sim->Wd, Su, sim->sur_on, sim->st, sim->ist, d_actions, h, substeps, sim->reward,
-                    sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->items, sim->step_block,
-                    sim->step_grid, sim->queue, sim->stream);
-        if (sim->sur_log && sim->sur_log_cap > 0)
-            sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;
+        if (sim->dynamics == SF_DYNAMICS_BICYCLE) {
+            // one kinematic update per control tick (no substeps, no tires,
+            // nothing logged for the learned tire model)
+            launch_step_bicycle(sim->P_dev, sim->Wd, sim->st, sim->ist, d_actions, dt, sim->reward, sim->done,
+                                sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->items, sim->stream);
+        } else {
+            launch_step(sim->P_dev, sim->Wd, Su, sim->sur_on, sim->st, sim->ist, d_actions, h, substeps,
+                        sim->reward, sim->done, sim->events, sim->rec, sim->rec_cnt, sim->rec_cap, sim->items,
+                        sim->step_block, sim->step_grid, sim->queue, sim->stream);
+            if (sim->sur_log && sim->sur_log_cap > 0)
+                sim->sur_log_base = (sim->sur_log_base + (long long)substeps * 4 * sim->N) % sim->sur_log_cap;
+        }
     }
     if (sim->touch_on) {
         launch_touch_count(sim->touch_bits, sim->touch_off, sim->touch_acc, sim->stream);
@@ -737,8 +745,39 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         sim->touch_steps += 1;
     }
     LAUNCHED();
-    sim->last_substeps = substeps;
+    sim->last_substeps = sim->dynamics == SF_DYNAMICS_BICYCLE ? 1 : substeps;
     return SF_OK;
+}
+
+sf_status sf_set_dynamics(sf_sim *sim, int32_t mode) {
+    CHECK_SIM(sim);
+    if (mode != SF_DYNAMICS_PHYSICS && mode != SF_DYNAMICS_BICYCLE)
+        return fail(SF_E_INVALID_ARG, "dynamics mode must be SF_DYNAMICS_PHYSICS or SF_DYNAMICS_BICYCLE");
+    if (mode != sim->dynamics) drop_graph(sim);   // a captured graph runs the other backend
+    sim->dynamics = mode;
+    return SF_OK;
+}
+
+sf_status sf_set_triangle_friction(sf_sim *sim, const float *h_scale) {
+    CHECK_SIM(sim);
+    const int T = sim->T;
+    if (h_scale)
+        for (int k = 0; k < T; ++k)
+            if (!(h_scale[k] >= 0.f) || !std::isfinite(h_scale[k]))
+                return fail(SF_E_INVALID_ARG, "triangle friction factors must be finite and >= 0");
+    float *d = nullptr;
+    if (h_scale && T > 0) {
+        d = (float *)dev_alloc(sim, sizeof(float) * (size_t)T);
+        if (!d) return fail(SF_E_OUT_OF_MEMORY, "triangle friction factors");
+        DEV(hipMemcpyAsync(d, h_scale, sizeof(float) * (size_t)T, hipMemcpyHostToDevice, sim->stream));
+    }
+    launch_tri_friction(d, const_cast<float4 *>(sim->Wd.tri), T, sim->stream);
+    LAUNCHED();
+    // the grid's triangle records carry the factors: pack them again
+    const sf_status r = build_grids(sim, sim->grid_cell, sim->tri_cell);
+    DEV(hipStreamSynchronize(sim->stream));
+    dev_free(sim, d);
+    return r;
 }
 
 static void enqueue_policy(sf_sim *sim, float *d_act) {

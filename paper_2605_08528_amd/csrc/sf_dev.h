@@ -5,7 +5,8 @@
 //             (structure of arrays: lane-contiguous loads per field)
 //   worlds  : CSR offsets [W+1] for agents, road points, triangles, spawns
 //   roads   : float2 xy [P], int2 quantised xy [P], u8 type [P]
-//   tris    : float4 [T][4] = (v0, surface) (e1, 0) (e2, 0) (unit normal, 0)
+//   tris    : float4 [T][4] = (v0, surface) (e1, 0) (e2, friction factor)
+//             (unit normal, 0)
 //   grids   : per world two uniform xy grids (road points; triangles, finer);
 //             cells of all worlds are numbered globally (world w owns
 //             [cbase, cbase + nx*ny)); CSR over cells with the items stored
@@ -97,7 +98,7 @@ struct DevWorld {
     const GridHdr *agent_grid;           // [N] the agent's world's road-point grid header
     const GridHdr *tgrid;                // [W] triangle grid (its own cell size)
     const int *tri_cell_start;           // [CT+1]
-    const float4 *tri_rec;               // [items][3] (v0, id bits) (e1, surface) (e2, 0), cell order
+    const float4 *tri_rec;               // [items][3] (v0, id bits) (e1, surface) (e2, friction factor), cell order
     const int *pt_cell_start;            // [CP+1]
     const int4 *pt_cell;                 // (qx, qy, local idx, 0) in cell order
     const int *pt_occ;                   // [CP] Chebyshev distance to the nearest non-empty cell
@@ -294,6 +295,7 @@ void launch_weather_mu(const float *mu_class, const float *film, const uint8_t *
                        float *mu_out, hipStream_t st);
 void launch_quantise_roads(const float2 *xy, int2 *q, int P, hipStream_t st);
 void launch_prep_tris(const float *verts, const uint8_t *surf, float4 *tri, int T, hipStream_t st);
+void launch_tri_friction(const float *scale, float4 *tri, int T, hipStream_t st);
 void launch_world_bbox(const int *roff, const float2 *xy, const int *toff, const float *verts, int W,
                        float4 *bbox, hipStream_t st);
 void launch_grid_count(const DevWorld &Wd, const float *verts, int T, int P, int *tri_cnt,
@@ -311,6 +313,9 @@ void launch_reset(const DevParams &P, const DevWorld &Wd, float *st, int *ist, c
 void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool use_sur, float *st, int *ist,
                  const float *act, float h, int S, float *reward, uint8_t *done, uint8_t *events, uint32_t *rec,
                  int *rec_cnt, int rec_cap, const int4 *items, int block, int grid, int *queue, hipStream_t s);
+void launch_step_bicycle(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act, float dt,
+                         float *reward, uint8_t *done, uint8_t *events, uint32_t *rec, int *rec_cnt, int rec_cap,
+                         const int4 *items, hipStream_t s);
 void launch_sur_reduce(const float *grad, int tiles, float *out, hipStream_t s);
 void launch_sur_grad_seq(const float *data, int M, const float *P, const uint16_t *Wb, float *grad, float *loss,
                          hipStream_t s);

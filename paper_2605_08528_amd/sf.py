@@ -123,6 +123,8 @@ def lib():
         L.sf_contact_overflows.argtypes = [vp, vp, i32]
         L.sf_road_touch.argtypes = [vp, i32]
         L.sf_road_touch_read.argtypes = [vp, vp, vp, C.POINTER(i32)]
+        L.sf_set_dynamics.argtypes = [vp, i32]
+        L.sf_set_triangle_friction.argtypes = [vp, vp]
         L.sf_state_bytes.argtypes = [vp]
         L.sf_state_bytes.restype = C.c_size_t
         L.sf_get_state.argtypes = [vp, vp, C.c_size_t]
@@ -157,7 +159,7 @@ def lib():
         L.sf_last_error.restype = C.c_char_p
         for name in ("sf_default_params", "sf_default_options", "sf_create", "sf_destroy", "sf_info",
                      "sf_step", "sf_observe", "sf_output_ptrs", "sf_reset", "sf_contact_overflows",
-                     "sf_road_touch", "sf_road_touch_read",
+                     "sf_road_touch", "sf_road_touch_read", "sf_set_dynamics", "sf_set_triangle_friction",
                      "sf_get_state",
                      "sf_set_state", "sf_get_contacts", "sf_debug_raycast", "sf_debug_obs_indices",
                      "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
@@ -333,6 +335,19 @@ class Sim:
         check(lib().sf_road_touch_read(self.h, _ptr(items), _ptr(nbytes), C.byref(steps)),
               "sf_road_touch_read")
         return items.reshape(2, 6).astype(np.int64), nbytes.astype(np.int64), steps.value
+
+    def set_dynamics(self, mode: str) -> None:
+        """'physics' (the articulated vehicle) or 'bicycle' (kinematic model)."""
+        check(lib().sf_set_dynamics(self.h, {"physics": 0, "bicycle": 1}[mode]), "sf_set_dynamics")
+
+    def set_triangle_friction(self, scale) -> None:
+        """Friction factor per road triangle [T] (None: back to 1)."""
+        if scale is None:
+            check(lib().sf_set_triangle_friction(self.h, None), "sf_set_triangle_friction")
+            return
+        a = np.ascontiguousarray(scale, np.float32)
+        assert a.size == len(self.worlds.tri_surface)
+        check(lib().sf_set_triangle_friction(self.h, _ptr(a)), "sf_set_triangle_friction")
 
     def state_bytes(self) -> int:
         return int(lib().sf_state_bytes(self.h))

@@ -999,3 +999,166 @@ def test_friction_curve_past_the_printed_range(oracle_mod):
         assert O.weather_mu(0.9, 0.8, pav) > 0.5
         assert O.weather_mu(0.9, 1.0, pav) == 1e-3
         assert 1e-3 < O.weather_mu(0.9, 0.99, pav) < 0.1
+
+
+# ------------------------------------------------------ kinematic bicycle
+DT = 1.0 / 30.0
+
+
+def _bicycle(O, spawns, prm=None, **kw):
+    o, p = mk(O, spawns, prm, **kw)
+    o.set_dynamics("bicycle")
+    return o, p
+
+
+def test_bicycle_straight_acceleration_closed_form(oracle_mod):
+    """Full throttle from rest, straight: forward Euler on (x, v) with the
+    front-drive acceleration a = 2 tau_drive / (r_w m) gives v_n = n a dt and
+    x_n = a dt^2 n (n - 1) / 2; the vehicle stays level at ride height with
+    rolling wheels."""
+    O = oracle_mod
+    o, p = _bicycle(O, [(0, 0, 0.4, 3000, 0)], invincible=True)
+    f, k = o.get_state()
+    z0 = f[PZ, 0]
+    acc = 2 * f32(p["tau_drive"]) / (f32(p["wheel_radius"]) * f32(p["mass"]))
+    assert abs(acc - 2.2884) < 1e-4
+    a = np.array([[1.0, 0.0]], np.float32)
+    dt = f32(DT)
+    for n in range(1, 61):
+        o.step(a, dt, 4)
+        f, _ = o.get_state()
+        s = acc * dt * dt * n * (n - 1) / 2
+        yaw = f32(0.4)                              # the spawn table holds float32
+        assert abs(f[PX, 0] - s * math.cos(yaw)) < 1e-9 and abs(f[PY, 0] - s * math.sin(yaw)) < 1e-9
+        assert abs(math.hypot(f[VX, 0], f[VY, 0]) - n * acc * dt) < 1e-9
+        assert abs(f[OM0, 0] - n * acc * dt / f32(p["wheel_radius"])) < 1e-9
+        assert f[PZ, 0] == z0 and f[WZ, 0] == 0.0
+    assert abs(2 * math.atan2(f[QZ, 0], f[QW, 0]) - f32(0.4)) < 1e-12
+
+
+def test_bicycle_braking_stops_without_reversing(oracle_mod):
+    """Full brake from 15 m/s: v drops by a_b dt per tick with a_b = 2 (tau_bf
+    + tau_br) / (r_w m), stops at exactly zero and stays there; the distance
+    is the discrete sum, which tends to v0^2 / (2 a_b)."""
+    O = oracle_mod
+    o, p = _bicycle(O, [(0, 0, 0.0, 3000, 0)], invincible=True)
+    f, k = o.get_state()
+    v0 = 15.0
+    f[VX, 0] = v0
+    o.set_state(f, k)
+    ab = 2 * (f32(p["tau_brake_front"]) + f32(p["tau_brake_rear"])) / (f32(p["wheel_radius"]) * f32(p["mass"]))
+    a = np.array([[-1.0, 0.0]], np.float32)
+    dt = f32(DT)
+    v, x = v0, 0.0
+    for n in range(120):
+        o.step(a, dt, 4)
+        x += v * dt
+        v = max(0.0, v - ab * dt)
+        f, _ = o.get_state()
+        assert abs(f[PX, 0] - x) < 1e-9 and abs(f[VX, 0] - v) < 1e-12
+        assert f[VX, 0] >= 0.0
+    assert v == 0.0 and f[VX, 0] == 0.0
+    assert abs(x - v0 * v0 / (2 * ab)) < v0 * dt          # within one tick of travel
+
+
+@pytest.mark.parametrize("front,rear", [(1.3, 1.3), (1.6, 1.0)])
+def test_bicycle_constant_steer_polygon_on_circle(oracle_mod, front, rear):
+    """Constant speed and steering angle: each tick advances the yaw by
+    omega dt with omega = v sin(beta) / l_r, beta = atan(l_r tan(delta) /
+    (l_f + l_r)); forward Euler then puts every position on one circle of
+    radius v dt / (2 sin(omega dt / 2)) (a regular polygon's vertices)."""
+    O = oracle_mod
+    mounts = ((front, 0.8, -0.2), (front, -0.8, -0.2), (-rear, 0.8, -0.2), (-rear, -0.8, -0.2))
+    o, p = _bicycle(O, [(0, 0, 0.0, 3000, 0)], params(mount=mounts), invincible=True)
+    f, k = o.get_state()
+    v = 8.0
+    f[VX, 0] = v
+    o.set_state(f, k)
+    delta = 0.3
+    lf, lr = f32(p["mount"][0][0]), -f32(p["mount"][2][0])
+    beta = math.atan(lr / (lf + lr) * math.tan(f32(delta)))
+    om = v * math.sin(beta) / lr
+    dt = f32(DT)
+    R = v * dt / (2 * math.sin(om * dt / 2))
+    a = np.array([[0.0, delta]], np.float32)
+    pts = []
+    for n in range(90):
+        o.step(a, dt, 4)
+        f, _ = o.get_state()
+        pts.append((f[PX, 0], f[PY, 0]))
+        assert abs(f[WZ, 0] - om) < 1e-12 and abs(f[TH, 0] - f32(delta)) < 1e-15
+    pts = np.array([(0.0, 0.0)] + pts)
+    # centre from three of the points, then every point on the circle
+    (x1, y1), (x2, y2), (x3, y3) = pts[0], pts[30], pts[60]
+    d = 2 * (x1 * (y2 - y3) + x2 * (y3 - y1) + x3 * (y1 - y2))
+    cx = ((x1 * x1 + y1 * y1) * (y2 - y3) + (x2 * x2 + y2 * y2) * (y3 - y1) + (x3 * x3 + y3 * y3) * (y1 - y2)) / d
+    cy = ((x1 * x1 + y1 * y1) * (x3 - x2) + (x2 * x2 + y2 * y2) * (x1 - x3) + (x3 * x3 + y3 * y3) * (x2 - x1)) / d
+    r = np.hypot(pts[:, 0] - cx, pts[:, 1] - cy)
+    assert np.max(np.abs(r - R)) < 1e-9
+    # turning left (positive steer) puts the centre on the left of the start heading
+    assert cy > 0
+
+
+def test_bicycle_collision_event_and_pair_list(oracle_mod):
+    """Two bicycles driving head-on meet: a tick's pair list holds the pair
+    exactly when its input poses overlap (head-on, the front circles overlap
+    once the centres are closer than 2 d + 2 r), and the collision event
+    follows in that tick once the warm-up has passed."""
+    O = oracle_mod
+    o, p = _bicycle(O, [(0, 0, 0.0, 3000, 0), (20, 0, math.pi, -3000, 0)], invincible=True)
+    r, d = O.circle_model(p)
+    f, k = o.get_state()
+    f[VX, 0], f[VX, 1] = 6.0, 6.0              # speeds; the bicycle moves along its heading
+    k[SINCE] = 100
+    o.set_state(f, k)
+    a = np.zeros((2, 2), np.float32)
+    dt = f32(DT)
+    seen = 0
+    for n in range(60):
+        f, _ = o.get_state()
+        gap = abs(f[PX, 1] - f[PX, 0])          # (the spawn rotation may swap the two entries)
+        if abs(gap - (2 * d + 2 * r)) < 2e-3:
+            continue                             # quantisation decides at the threshold itself
+        overlap = gap < 2 * d + 2 * r
+        rew, done, ev, (rec, cnt) = o.step(a, dt, 4, record_pairs=True)
+        assert cnt[0, 0] == int(overlap), n
+        if overlap:
+            seen += 1
+            assert rec[0, 0, 0] & 0xFFFF == (0 | 1 << 8)
+            if seen == 1:                                     # first contact: front against front only
+                assert rec[0, 0, 0] >> 16 == 1 << (3 * 2 + 2)
+            assert ev[0] & O.EV_COLLISION and ev[1] & O.EV_COLLISION and rew[0] == -6.0
+        else:
+            assert not (ev[0] & O.EV_COLLISION)
+    assert seen > 0
+
+
+def test_triangle_friction_factor_scales_the_stopping_distance(oracle_mod):
+    """A per-triangle friction factor s multiplies the class friction of
+    wheels on that triangle: the locked-wheel stop from 20 m/s on triangles
+    with s = 0.5 and class mu = 0.9 matches v0^2 / (2 s mu g) - v0 h / 2, as
+    the plain mu = 0.45 world does."""
+    O = oracle_mod
+    prm = params(tau_brake_front=1e4, tau_brake_rear=1e4, max_episode_steps=10**6)
+    stops = []
+    for mu, scale in ((0.9, 0.5), (0.45, None)):
+        o, p = mk(O, [(0, 0, 0.0, 3000, 0)], prm, mu=mu, invincible=True)
+        if scale is not None:
+            o.set_tri_friction(np.full(2, scale, np.float32))
+        f, k = o.get_state()
+        f[VX, 0] = 20.0
+        f[OM0:OM0 + 4, 0] = 20.0 / f32(p["wheel_radius"])
+        o.set_state(f, k)
+        a = np.array([[-1.0, 0.0]], np.float32)
+        for n in range(20000):
+            o.step(a, H, 1)
+            f, _ = o.get_state()
+            if abs(f[VX, 0]) < 1e-4:
+                break
+        stops.append(f[PX, 0])
+        closed = 400.0 / (2 * f32(0.9) * 0.5 * f32(p["gravity"])) - 20.0 * H / 2
+        assert abs(f[PX, 0] - closed) / closed < 5e-3
+        assert abs(f[MU, 0] - f32(0.9) * 0.5) < 2e-7 if scale else True
+    assert abs(stops[0] - stops[1]) < 1e-3
+    with pytest.raises(ValueError):
+        o.set_tri_friction(np.array([1.0, -0.5], np.float32))
