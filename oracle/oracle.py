@@ -22,9 +22,16 @@ FIELDS = ["px", "py", "pz", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy"
           "om0", "om1", "om2", "om3", "th", "thd", "mu", "gx", "gy", "sx", "sy"]
 IFIELDS = ["active", "ep_step", "since", "episode"]
 EV_GOAL, EV_COLLISION, EV_CRASH, EV_TIMEOUT, EV_NUMERIC, EV_NAN_ACTION = 1, 2, 4, 8, 16, 32
+EV_LANE_FORBIDDEN = 128
 SUR_IN, SUR_HID, SAMPLE = 16, 128, 20
 SUR_SIZES = [16, 128, 128, 128, 3]
 SUR_PARAMS = 16 * 128 + 128 + 2 * (128 * 128 + 128) + 3 * 128 + 3
+# the paper's observation and the late-fusion actor-critic
+FULL_EGO, FULL_ROAD_K, FULL_NEIGH_K = 11, 350, 24
+FULL_DIM = FULL_EGO + 5 * FULL_ROAD_K + 7 * FULL_NEIGH_K
+AC_BODY = (11 * 64 + 64 + 64 * 64 + 64 + 5 * 96 + 96 + 96 * 96 + 96 + 7 * 96 + 96 + 96 * 96 + 96
+           + 256 * 128 + 128 + 128 * 64 + 64)
+AC_PARAMS = 2 * AC_BODY + 3 * 64 + 3 + 3 + 64 + 1
 
 
 def build(verbose: bool = False, sanitize: bool = False) -> str:
@@ -70,6 +77,7 @@ class OrWorld(C.Structure):
         ("film_mm", C.c_void_p), ("pavement", C.c_void_p),
         ("spawn_offsets", C.c_void_p), ("spawn", C.c_void_p),
         ("seed", C.c_uint64),
+        ("road_dir", C.c_void_p),
     ]
 
 
@@ -115,6 +123,15 @@ def lib():
         L.or_surrogate_counts.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.or_record_samples.argtypes = [vp, vp]
         L.or_set_dynamics.argtypes = [vp, ip]
+        L.or_observe_full.argtypes = [vp, vp, vp]
+        L.or_set_shaping.argtypes = [vp, ip]
+        L.or_shaping_terms.argtypes = [vp, ip, C.c_double, C.c_double, vp]
+        L.or_lane_forbidden.argtypes = [vp, ip]
+        L.or_lane_forbidden.restype = ip
+        L.or_road_within.argtypes = [vp, ip, ip, vp]
+        L.or_road_within.restype = ip
+        L.or_knn_neigh_k.argtypes = [vp, ip, ip, vp]
+        L.or_actor_critic.argtypes = [vp, ip, vp, vp, vp, vp]
         L.or_set_tri_friction.argtypes = [vp, vp]
         L.or_set_tri_friction.restype = ip
         _lib = L
@@ -201,6 +218,8 @@ class Oracle:
         w.spawn_offsets = arr(worlds.spawn_offsets, np.int32)
         w.spawn = arr(worlds.spawn, np.float32)
         w.seed = int(worlds.seed)
+        if getattr(worlds, "road_dir", None) is not None:
+            w.road_dir = arr(worlds.road_dir, np.float32)
         self._p = make_params(params, invincible, auto_reset)
         self.h = L.or_create(C.byref(w), C.byref(self._p))
         self._keep = []
@@ -261,6 +280,37 @@ class Oracle:
     def reset(self, mask):
         m = np.ascontiguousarray(mask, np.uint8)
         lib().or_reset(self.h, _ptr(m))
+
+    def set_shaping(self, on: bool):
+        """Dense shaping rewards and the lane-forbidden event on or off."""
+        lib().or_set_shaping(self.h, int(bool(on)))
+
+    def shaping_terms(self, i, dx, dy):
+        """(progress, lane keeping, off-road, idle, vehicle TTC, road-edge TTC)
+        of agent i on the current pose after a displacement (dx, dy)."""
+        t = np.zeros(6, np.float64)
+        lib().or_shaping_terms(self.h, int(i), float(dx), float(dy), _ptr(t))
+        return t
+
+    def lane_forbidden(self, i) -> bool:
+        return bool(lib().or_lane_forbidden(self.h, int(i)))
+
+    def observe_full(self):
+        """The paper's observation [N, 1929] and valid (road, neighbour) slot counts [N, 2]."""
+        obs = np.zeros((self.N, FULL_DIM), np.float32)
+        cnt = np.zeros((self.N, 2), np.int32)
+        lib().or_observe_full(self.h, _ptr(obs), _ptr(cnt))
+        return obs, cnt
+
+    def road_within(self, i, K=FULL_ROAD_K):
+        out = np.zeros(K, np.int32)
+        n = lib().or_road_within(self.h, int(i), int(K), _ptr(out))
+        return out, n
+
+    def knn_neigh_k(self, i, K=FULL_NEIGH_K):
+        out = np.zeros(K, np.int32)
+        lib().or_knn_neigh_k(self.h, int(i), int(K), _ptr(out))
+        return out
 
     def set_dynamics(self, mode: str):
         """'physics' (the articulated vehicle) or 'bicycle' (kinematic model)."""
@@ -371,3 +421,17 @@ def adam(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     assert w.dtype == np.float32 and m.dtype == np.float64 and v.dtype == np.float64
     g = np.ascontiguousarray(g, np.float64)
     lib().or_adam(w.size, _ptr(w), _ptr(g), _ptr(m), _ptr(v), int(step), lr, b1, b2, eps)
+
+
+def actor_critic(params, obs, counts):
+    """Late-fusion actor-critic forward in FP64 (bf16 rounding points as set
+    by set_bf16): mean [M, 3] and value [M]."""
+    params = np.ascontiguousarray(params, np.float32)
+    assert params.size == AC_PARAMS
+    obs = np.ascontiguousarray(obs, np.float32).reshape(-1, FULL_DIM)
+    counts = np.ascontiguousarray(counts, np.int32).reshape(-1, 2)
+    M = obs.shape[0]
+    mean = np.zeros((M, 3), np.float64)
+    value = np.zeros(M, np.float64)
+    lib().or_actor_critic(_ptr(params), M, _ptr(obs), _ptr(counts), _ptr(mean), _ptr(value))
+    return mean, value

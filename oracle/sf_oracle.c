@@ -38,8 +38,11 @@ struct or_sim {
     int W, N, S;
     int *aoff, *roff, *toff, *soff;
     double *road_xy; uint8_t *road_type;
+    double *road_dir;   /* [P][2] polyline direction per point (0 if not given) */
     double *tri; uint8_t *tri_surf;
     double *mu;      /* [W][S] effective */
+    double *film;    /* [W] water film depth [mm] */
+    int *pav;        /* [W] pavement (0 AC, 1 SMA, 2 OGFC) */
     double *spawn;   /* [E][5] */
     uint64_t seed;
     int *world_of;   /* [N] */
@@ -54,6 +57,7 @@ struct or_sim {
     long long sur_used, sur_fallback;
     float *sample_rec;          /* [N][4][OR_SAMPLE] of the last substep, or NULL */
     int dynamics;               /* OR_DYN_PHYSICS or OR_DYN_BICYCLE */
+    int shaping;                /* dense rewards and the lane-forbidden event */
     double *tri_mu_scale;       /* [T] friction factor per road triangle, or NULL */
 };
 
@@ -190,10 +194,18 @@ or_sim *or_create(const or_world_desc *d, const or_params *prm) {
     s->road_type = (uint8_t *)malloc(P + 1);
     for (int i = 0; i < 2 * P; ++i) s->road_xy[i] = d->road_xy[i];
     for (int i = 0; i < P; ++i) s->road_type[i] = d->road_type[i];
+    s->road_dir = (double *)malloc(sizeof(double) * 2 * (P + 1));
+    for (int i = 0; i < 2 * P; ++i) s->road_dir[i] = d->road_dir ? d->road_dir[i] : 0.0;
     s->tri = (double *)malloc(sizeof(double) * 9 * (T + 1));
     s->tri_surf = (uint8_t *)malloc(T + 1);
     for (int i = 0; i < 9 * T; ++i) s->tri[i] = d->tri_verts[i];
     for (int i = 0; i < T; ++i) s->tri_surf[i] = d->tri_surface[i];
+    s->film = (double *)malloc(sizeof(double) * (W + 1));
+    s->pav = (int *)malloc(sizeof(int) * (W + 1));
+    for (int w = 0; w < W; ++w) {
+        s->film[w] = d->film_mm ? d->film_mm[w] : 0.0;
+        s->pav[w] = d->pavement ? d->pavement[w] : 0;
+    }
     s->mu = (double *)malloc(sizeof(double) * W * s->S);
     for (int w = 0; w < W; ++w)
         for (int j = 0; j < s->S; ++j) {
@@ -224,7 +236,7 @@ or_sim *or_create(const or_world_desc *d, const or_params *prm) {
 void or_destroy(or_sim *s) {
     if (!s) return;
     free(s->aoff); free(s->roff); free(s->toff); free(s->soff);
-    free(s->road_xy); free(s->road_type); free(s->tri); free(s->tri_surf);
+    free(s->road_xy); free(s->road_type); free(s->road_dir); free(s->film); free(s->pav); free(s->tri); free(s->tri_surf);
     free(s->tri_mu_scale);
     free(s->mu); free(s->spawn); free(s->world_of); free(s->f); free(s->k);
     free(s->sur);
@@ -916,6 +928,154 @@ int or_set_tri_friction(or_sim *s, const float *scale) {
     return 0;
 }
 
+/* ------------------------------------------------- shaping rewards */
+/* Appendix "Reward Design Details": six dense terms at every active step
+ * and the lane-forbidden event.  Readings: the road context of both is the
+ * observation's 64 nearest road points; every road point stands for the
+ * 0.5 m segment of its polyline centred on it along its direction; the
+ * decisions (which point is nearest, which side, off-road, idle, which
+ * edges lie ahead, overlap) are integer predicates on quantised values
+ * (positions 2^-10 m, directions and headings 2^-14). */
+void or_set_shaping(or_sim *s, int on) { s->shaping = on != 0; }
+
+static int64_t sat_key(int64_t d2);
+static double ttc_pair(const or_sim *s, int i, int j);
+
+/* circle of quantised centre (cx, cy) and radius r against the segment of
+ * global road point q: exact squared distance from the centre to the
+ * segment below r^2 */
+static int circle_hits_segment(const or_sim *s, int64_t cx, int64_t cy, int q) {
+    const int64_t px = Qp(s->road_xy[2 * q]), py = Qp(s->road_xy[2 * q + 1]);
+    const int64_t hx = Qp(0.25 * s->road_dir[2 * q]), hy = Qp(0.25 * s->road_dir[2 * q + 1]);
+    const int64_t ax = px - hx, ay = py - hy, vx = 2 * hx, vy = 2 * hy;
+    const int64_t wx = cx - ax, wy = cy - ay;
+    if (wx > 4096 || wx < -4096 || wy > 4096 || wy < -4096) return 0;   /* farther than 4 m: no overlap */
+    const int64_t R = Qp(s->cr), R2 = R * R;
+    const int64_t len2 = vx * vx + vy * vy, t = wx * vx + wy * vy;
+    if (len2 == 0 || t <= 0) return wx * wx + wy * wy < R2;
+    if (t >= len2) {
+        const int64_t ex = wx - vx, ey = wy - vy;
+        return ex * ex + ey * ey < R2;
+    }
+    return (wx * wx + wy * wy) * len2 - t * t < R2 * len2;
+}
+
+static int is_edge(int type) { return type == 15 || type == 16; }
+static int is_lane(int type) { return type == 1 || type == 2; }
+
+int or_lane_forbidden(const or_sim *s, int i) {
+    int32_t idx[OR_ROAD_K];
+    or_knn_road(s, i, idx);
+    int64_t C[3][2];
+    circle_centres_q(s, i, C);
+    const int r0 = s->roff[s->world_of[i]];
+    for (int k = 0; k < OR_ROAD_K; ++k) {
+        if (idx[k] < 0) break;
+        const int q = r0 + idx[k];
+        if (!is_edge(s->road_type[q])) continue;
+        for (int a = 0; a < 3; ++a)
+            if (circle_hits_segment(s, C[a][0], C[a][1], q)) return 1;
+    }
+    return 0;
+}
+
+static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+void or_shaping_terms(const or_sim *s, int i, double dx, double dy, double *terms) {
+    const or_params *p = &s->p;
+    for (int k = 0; k < 6; ++k) terms[k] = 0.0;
+    const int w = s->world_of[i], r0 = s->roff[w];
+    int32_t idx[OR_ROAD_K];
+    or_knn_road(s, i, idx);
+    const double px = F(s, OR_PX, i), py = F(s, OR_PY, i);
+    const int64_t X = Qp(px), Y = Qp(py);
+    double hx, hy;
+    heading_fp(s, i, &hx, &hy);
+    /* the nearest driving-lane point (types 1-2) among the 64 */
+    int best = -1;
+    int64_t bkey = 0;
+    for (int k = 0; k < OR_ROAD_K; ++k) {
+        if (idx[k] < 0) break;
+        const int q = r0 + idx[k];
+        if (!is_lane(s->road_type[q])) continue;
+        const int64_t ex = Qp(s->road_xy[2 * q]) - X, ey = Qp(s->road_xy[2 * q + 1]) - Y;
+        const int64_t key = sat_key(ex * ex + ey * ey);
+        if (best < 0 || key < bkey) { best = q; bkey = key; }   /* index order: ties keep the lower */
+    }
+    int off = 1;
+    if (best >= 0) {
+        /* lane tangent oriented toward the goal (integer sign; 0 keeps it) */
+        double tx = s->road_dir[2 * best], ty = s->road_dir[2 * best + 1];
+        const int64_t gdx = Qp(F(s, OR_GX, i)) - X, gdy = Qp(F(s, OR_GY, i)) - Y;
+        if (Qq(tx) * gdx + Qq(ty) * gdy < 0) { tx = -tx; ty = -ty; }
+        /* route progress: displacement along the tangent, clamped to +-2 m */
+        terms[0] = 2.0 * clampd(dx * tx + dy * ty, -2.0, 2.0);
+        /* lane keeping: lateral offset and heading alignment */
+        const double qx = s->road_xy[2 * best], qy = s->road_xy[2 * best + 1];
+        const double lat = (px - qx) * (-ty) + (py - qy) * tx;
+        const double align = hx * tx + hy * ty;
+        terms[1] = 0.08 * exp(-(lat / 1.75) * (lat / 1.75)) * (0.2 + 0.8 * (align > 0.0 ? align : 0.0));
+        /* off the road: lateral offset beyond 3.25 m or the lane point
+         * farther than 6 m (integers: lateral in 2^-24 m) */
+        const int64_t ox = X - Qp(qx), oy = Y - Qp(qy);
+        int64_t latq = ox * (-Qq(ty)) + oy * Qq(tx);
+        if (latq < 0) latq = -latq;
+        off = latq > (int64_t)(3.25 * 16777216.0) || bkey > (int64_t)6144 * 6144;
+    }
+    if (off) terms[2] = -0.5;
+    /* idle: speed below 1 m/s (quantised velocity) */
+    {
+        const int64_t vx = Qp(F(s, OR_VX, i)), vy = Qp(F(s, OR_VY, i));
+        if (vx * vx + vy * vy < (int64_t)1024 * 1024) terms[3] = -0.05;
+    }
+    /* inter-vehicle TTC: the smallest over the observation's neighbours */
+    {
+        int32_t nidx[OR_NEIGH_K];
+        or_knn_neigh(s, i, nidx);
+        double tau = 10.0;
+        const int a0 = s->aoff[w];
+        for (int k = 0; k < OR_NEIGH_K; ++k) {
+            if (nidx[k] < 0) break;
+            const int j = a0 + nidx[k];
+            const double bx = hx * (F(s, OR_PX, j) - px) + hy * (F(s, OR_PY, j) - py);
+            const double t = bx < 0.0 ? 10.0 : ttc_pair(s, i, j);
+            if (t < tau) tau = t;
+        }
+        const double pen = 0.10 / (tau > 0.5 ? tau : 0.5);
+        terms[4] = -(pen < 0.35 ? pen : 0.35);
+    }
+    /* road-edge TTC: edge points ahead in the vehicle's corridor (|lateral|
+     * <= W / 2 + r), reached by the front circle at the forward speed; the
+     * side decisions use the planar heading of the quantised quaternion
+     * (unnormalised, exact integers, as the circle model does) */
+    {
+        const double vf = hx * F(s, OR_VX, i) + hy * F(s, OR_VY, i);
+        const int64_t qw = Qq(F(s, OR_QW, i)), qx = Qq(F(s, OR_QX, i));
+        const int64_t qy = Qq(F(s, OR_QY, i)), qz = Qq(F(s, OR_QZ, i));
+        const int64_t ihx = ((int64_t)1 << 28) - 2 * (qy * qy + qz * qz), ihy = 2 * (qx * qy + qw * qz);
+        const int64_t nh = (int64_t)isqrt_u64((uint64_t)(ihx * ihx + ihy * ihy));
+        const int64_t half = (int64_t)nearbyint((0.5 * p->width + s->cr) * 1024.0);
+        double tau = INFINITY;
+        for (int k = 0; k < OR_ROAD_K && vf > 0.0; ++k) {
+            if (idx[k] < 0) break;
+            const int q = r0 + idx[k];
+            if (!is_edge(s->road_type[q])) continue;
+            const int64_t ex = Qp(s->road_xy[2 * q]) - X, ey = Qp(s->road_xy[2 * q + 1]) - Y;
+            if (ex > (1 << 20) || ex < -(1 << 20) || ey > (1 << 20) || ey < -(1 << 20)) continue;
+            const int64_t along = ex * ihx + ey * ihy, side = -ex * ihy + ey * ihx;
+            if (along <= 0 || side > half * nh || side < -half * nh) continue;
+            const double xb = hx * (s->road_xy[2 * q] - px) + hy * (s->road_xy[2 * q + 1] - py);
+            const double gap = xb - (s->cd + s->cr);
+            const double t = (gap > 0.0 ? gap : 0.0) / vf;
+            if (t < tau) tau = t;
+        }
+        if (tau < INFINITY) {
+            const double pen = 0.07 / (tau > 0.5 ? tau : 0.5);
+            terms[5] = -(pen < 0.40 ? pen : 0.40);
+        }
+    }
+}
+
 void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
              uint8_t *done, uint8_t *events, uint32_t *pair_rec, int32_t *pair_cnt,
              int pair_cap) {
@@ -930,7 +1090,17 @@ void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
         uint8_t *nan_act = (uint8_t *)calloc(A + 1, 1);
         uint8_t *coll = (uint8_t *)calloc(A + 1, 1);
         uint8_t *was_active = (uint8_t *)calloc(A + 1, 1);
-        for (int i = a0; i < a1; ++i) was_active[i - a0] = (uint8_t)K(s, OR_ACTIVE, i);
+        uint8_t *forbid = (uint8_t *)calloc(A + 1, 1);
+        double *p0 = (double *)calloc(2 * (A + 1), sizeof(double));
+        double *sparse = (double *)calloc(A + 1, sizeof(double));
+        uint8_t *carry = (uint8_t *)calloc(A + 1, 1);
+        for (int i = a0; i < a1; ++i) {
+            was_active[i - a0] = (uint8_t)K(s, OR_ACTIVE, i);
+            /* lane-forbidden is decided on the control step's input pose */
+            if (s->shaping && was_active[i - a0]) forbid[i - a0] = (uint8_t)or_lane_forbidden(s, i);
+            p0[2 * (i - a0)] = F(s, OR_PX, i);
+            p0[2 * (i - a0) + 1] = F(s, OR_PY, i);
+        }
         if (s->dynamics == OR_DYN_BICYCLE) {
             /* one update per control tick; collisions from the circle pairs
              * of the tick's input poses (as the articulated step takes them
@@ -964,6 +1134,7 @@ void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
                 continue;
             }
             uint32_t ev = agent_events(s, i, coll[li]);
+            if (forbid[li] && !(ev & OR_EV_NUMERIC)) ev |= OR_EV_LANE_FORBIDDEN;
             if (nan_act[li]) ev |= OR_EV_NAN_ACTION;
             K(s, OR_EPSTEP, i) += 1;
             K(s, OR_SINCE, i) += 1;
@@ -972,8 +1143,11 @@ void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
             if (ev & OR_EV_GOAL) r = 45.0;
             else if (ev & OR_EV_COLLISION) r = -6.0;
             else if (ev & OR_EV_CRASH) r = -10.0;
-            int term = (ev & (OR_EV_GOAL | OR_EV_COLLISION | OR_EV_CRASH)) != 0;
+            else if (ev & OR_EV_LANE_FORBIDDEN) r = -20.0;
+            int term = (ev & (OR_EV_GOAL | OR_EV_COLLISION | OR_EV_CRASH | OR_EV_LANE_FORBIDDEN)) != 0;
             int dn = (term && !p->invincible) || (ev & (OR_EV_TIMEOUT | OR_EV_NUMERIC)) != 0;
+            sparse[li] = r;
+            carry[li] = !dn;
             reward[i] = (float)r;
             done[i] = (uint8_t)dn;
             events[i] = (uint8_t)ev;
@@ -986,7 +1160,21 @@ void or_step(or_sim *s, const float *actions, double dt, int S, float *reward,
                 }
             }
         }
-        free(nan_act); free(coll); free(was_active);
+        /* dense terms on the new pose of every agent that carries on (a
+         * terminating step delivers its sparse reward only), with the world
+         * as the step leaves it: agents that ended this step are already at
+         * their new spawn or parked */
+        if (s->shaping)
+            for (int i = a0; i < a1; ++i) {
+                const int li = i - a0;
+                if (!was_active[li] || !carry[li]) continue;
+                double terms[6];
+                or_shaping_terms(s, i, F(s, OR_PX, i) - p0[2 * li], F(s, OR_PY, i) - p0[2 * li + 1], terms);
+                double r = sparse[li];
+                for (int k = 0; k < 6; ++k) r += terms[k];
+                reward[i] = (float)r;
+            }
+        free(nan_act); free(coll); free(was_active); free(forbid); free(p0); free(sparse); free(carry);
     }
 }
 
@@ -1135,6 +1323,121 @@ void or_observe(const or_sim *s, float *obs) {
     }
 }
 
+/* ------------------------------------------- the paper's observation */
+/* Appendix "Observation Space Details", at the paper's shape: per agent
+ * OR_FULL_DIM = 11 + 350 x 5 + 24 x 7 = 1929 floats, zero where a slot is
+ * empty, and the numbers of valid road and neighbour slots (the slots the
+ * network's masked max-pool reads).
+ *   ego 11: goal in the body frame / 100 (2), sin and cos of the goal
+ *     bearing, goal distance / 100, body-frame velocity / 10 (2), then the
+ *     weather token of Eq. weather_obs: film depth / 1 mm and the one-hot
+ *     pavement (AC, SMA, OGFC);
+ *   road 350 x 5: every road point within 10 m (quantised squared distance,
+ *     inclusive), in point-index order, the first 350: body-frame offset / 10
+ *     (2), type / 20, body-frame polyline direction (2);
+ *   neighbours 24 x 7: the 24 nearest other active agents (quantised key,
+ *     ties by lower index), ascending, with the features of the
+ *     8-neighbour observation. */
+void or_knn_neigh_k(const or_sim *s, int i, int K, int32_t *out) {
+    int w = s->world_of[i];
+    int a0 = s->aoff[w], A = s->aoff[w + 1] - a0;
+    kv_t *kv = (kv_t *)malloc(sizeof(kv_t) * (A + 1));
+    int64_t X = Qp(F(s, OR_PX, i)), Y = Qp(F(s, OR_PY, i));
+    int n = 0;
+    for (int j = a0; j < a0 + A; ++j) {
+        if (j == i || !K(s, OR_ACTIVE, j)) continue;
+        int64_t dx = Qp(F(s, OR_PX, j)) - X, dy = Qp(F(s, OR_PY, j)) - Y;
+        kv[n].key = sat_key(dx * dx + dy * dy);
+        kv[n].idx = j - a0;
+        ++n;
+    }
+    qsort(kv, n, sizeof(kv_t), kv_cmp);
+    for (int k = 0; k < K; ++k) out[k] = k < n ? kv[k].idx : -1;
+    free(kv);
+}
+
+int or_road_within(const or_sim *s, int i, int K, int32_t *out) {
+    int w = s->world_of[i];
+    int r0 = s->roff[w], P = s->roff[w + 1] - r0;
+    int64_t X = Qp(F(s, OR_PX, i)), Y = Qp(F(s, OR_PY, i));
+    const int64_t R = (int64_t)10 * 1024;
+    int n = 0;
+    for (int k = 0; k < P && n < K; ++k) {
+        int64_t dx = Qp(s->road_xy[2 * (r0 + k)]) - X, dy = Qp(s->road_xy[2 * (r0 + k) + 1]) - Y;
+        if (dx * dx + dy * dy <= R * R) out[n++] = k;
+    }
+    for (int k = n; k < K; ++k) out[k] = -1;
+    return n;
+}
+
+void or_observe_full(const or_sim *s, float *obs, int32_t *counts) {
+    const or_params *p = &s->p;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < s->N; ++i) {
+        float *o = obs + (size_t)OR_FULL_DIM * i;
+        for (int k = 0; k < OR_FULL_DIM; ++k) o[k] = 0.0f;
+        counts[2 * i] = counts[2 * i + 1] = 0;
+        if (!K(s, OR_ACTIVE, i)) continue;
+        int w = s->world_of[i];
+        double hx, hy;
+        heading_fp(s, i, &hx, &hy);
+        double px = F(s, OR_PX, i), py = F(s, OR_PY, i);
+        double gx = F(s, OR_GX, i) - px, gy = F(s, OR_GY, i) - py;
+        double gbx = hx * gx + hy * gy, gby = -hy * gx + hx * gy;
+        double dist = sqrt(gx * gx + gy * gy);
+        double vx = F(s, OR_VX, i), vy = F(s, OR_VY, i);
+        o[0] = (float)(gbx / 100.0);
+        o[1] = (float)(gby / 100.0);
+        o[2] = (float)(dist > 0 ? gby / dist : 0.0);
+        o[3] = (float)(dist > 0 ? gbx / dist : 1.0);
+        o[4] = (float)(dist / 100.0);
+        o[5] = (float)((hx * vx + hy * vy) / 10.0);
+        o[6] = (float)((-hy * vx + hx * vy) / 10.0);
+        o[7] = (float)(s->film[w] / 1.0);
+        o[8 + (s->pav[w] >= 0 && s->pav[w] <= 2 ? s->pav[w] : 0)] = 1.0f;
+        int32_t ridx[OR_FULL_ROAD_K];
+        const int nr = or_road_within(s, i, OR_FULL_ROAD_K, ridx);
+        int r0 = s->roff[w];
+        for (int k = 0; k < nr; ++k) {
+            const int q = r0 + ridx[k];
+            double dx = s->road_xy[2 * q] - px, dy = s->road_xy[2 * q + 1] - py;
+            double ux = s->road_dir[2 * q], uy = s->road_dir[2 * q + 1];
+            float *r = o + OR_FULL_EGO + 5 * k;
+            r[0] = (float)((hx * dx + hy * dy) / 10.0);
+            r[1] = (float)((-hy * dx + hx * dy) / 10.0);
+            r[2] = (float)(s->road_type[q] / 20.0);
+            r[3] = (float)(hx * ux + hy * uy);
+            r[4] = (float)(-hy * ux + hx * uy);
+        }
+        int32_t nidx[OR_FULL_NEIGH_K];
+        or_knn_neigh_k(s, i, OR_FULL_NEIGH_K, nidx);
+        int a0 = s->aoff[w], nv = 0;
+        for (int k = 0; k < OR_FULL_NEIGH_K; ++k) {
+            if (nidx[k] < 0) break;
+            int j = a0 + nidx[k];
+            double dx = F(s, OR_PX, j) - px, dy = F(s, OR_PY, j) - py;
+            double bx = hx * dx + hy * dy, by = -hy * dx + hx * dy;
+            double hjx, hjy;
+            heading_fp(s, j, &hjx, &hjy);
+            double dpsi = atan2(hx * hjy - hy * hjx, hx * hjx + hy * hjy);
+            if (dpsi == -M_PI) dpsi = M_PI;
+            double ttc = bx < 0.0 ? 10.0 : ttc_pair(s, i, j);
+            double vjx = F(s, OR_VX, j), vjy = F(s, OR_VY, j);
+            float *q = o + OR_FULL_EGO + 5 * OR_FULL_ROAD_K + 7 * k;
+            q[0] = (float)(bx / 100.0);
+            q[1] = (float)(by / 100.0);
+            q[2] = (float)(p->length / 100.0);
+            q[3] = (float)(p->width / 100.0);
+            q[4] = (float)(dpsi / M_PI);
+            q[5] = (float)(sqrt(vjx * vjx + vjy * vjy) / 10.0);
+            q[6] = (float)(ttc / 10.0);
+            ++nv;
+        }
+        counts[2 * i] = nr;
+        counts[2 * i + 1] = nv;
+    }
+}
+
 /* ----------------------------------------------------------- networks */
 /* round to bfloat16 (8 significant bits), nearest-even, from the value;
  * switched off only for finite-difference checks of the gradients */
@@ -1179,6 +1482,67 @@ void or_mlp_forward(int L, const int *sz, const float *const *W, const float *co
         mlp_fwd_keep(L, sz, W, b, act, x + (size_t)r * sz[0], a, z);
         for (int o = 0; o < sz[L]; ++o) y[(size_t)r * sz[L] + o] = a[L][o];
         for (int l = 0; l <= L; ++l) { free(a[l]); free(z[l]); }
+    }
+}
+
+/* The late-fusion actor-critic of appendix "Network Architecture Details"
+ * on the paper's observation: per network (actor, then critic; no shared
+ * weights) an ego encoder 11 -> 64 -> 64, a road encoder 5 -> 96 -> 96 on
+ * every valid road slot and a vehicle encoder 7 -> 96 -> 96 on every valid
+ * neighbour slot, each followed by a max over its valid slots (the masked
+ * max-pool; an empty set pools to 0), the 64 + 96 + 96 embedding through a
+ * trunk 256 -> 128 -> 64, ELU after every hidden layer, then the actor's
+ * 3-dim mean or the critic's value.  bf16 rounding points as in the other
+ * networks: the layers' inputs, weights and hidden activations.
+ * Parameter block (float32): for each network, ego W1[64][11] b1 W2[64][64]
+ * b2, road W1[96][5] b1 W2[96][96] b2, vehicle W1[96][7] b1 W2[96][96] b2,
+ * trunk W1[128][256] b1 W2[64][128] b2, then the actor's head W[3][64] b[3]
+ * and log sigma[3], or the critic's W[1][64] b[1]. */
+static const float *ac_dense(const float *P, int in, int out, double *xin, double *y, int act) {
+    const float *W = P, *b = P + (size_t)in * out;
+    for (int o = 0; o < out; ++o) {
+        double acc = b[o];
+        for (int k = 0; k < in; ++k) acc += bf16r(W[(size_t)o * in + k]) * xin[k];
+        y[o] = act ? bf16r(elu(acc)) : acc;
+    }
+    return b + out;
+}
+
+static const float *ac_encoder_pool(const float *P, int in, int rows, const float *x, int stride, double *pool) {
+    double h[96], z[96], xin[16];
+    const float *end = P;
+    for (int c = 0; c < 96; ++c) pool[c] = rows > 0 ? -INFINITY : 0.0;
+    for (int r = 0; r < rows; ++r) {
+        for (int k = 0; k < in; ++k) xin[k] = bf16r(x[(size_t)r * stride + k]);
+        const float *P2 = ac_dense(P, in, 96, xin, h, 1);
+        end = ac_dense(P2, 96, 96, h, z, 1);
+        for (int c = 0; c < 96; ++c) if (z[c] > pool[c]) pool[c] = z[c];
+    }
+    if (rows == 0) end = P + (size_t)in * 96 + 96 + 96 * 96 + 96;
+    return end;
+}
+
+/* one network on one agent's observation; returns the parameters after it */
+static const float *ac_net(const float *P, const float *o, int nr, int nv, int nout, double *out) {
+    double xin[OR_FULL_EGO], e1[64], emb[256], t1[128], t2[64];
+    for (int k = 0; k < OR_FULL_EGO; ++k) xin[k] = bf16r(o[k]);
+    P = ac_dense(P, OR_FULL_EGO, 64, xin, e1, 1);
+    P = ac_dense(P, 64, 64, e1, emb, 1);
+    P = ac_encoder_pool(P, 5, nr, o + OR_FULL_EGO, 5, emb + 64);
+    P = ac_encoder_pool(P, 7, nv, o + OR_FULL_EGO + 5 * OR_FULL_ROAD_K, 7, emb + 160);
+    P = ac_dense(P, 256, 128, emb, t1, 1);
+    P = ac_dense(P, 128, 64, t1, t2, 1);
+    return ac_dense(P, 64, nout, t2, out, 0);
+}
+
+void or_actor_critic(const float *params, int M, const float *obs, const int32_t *counts, double *mean,
+                     double *value) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int r = 0; r < M; ++r) {
+        const float *o = obs + (size_t)OR_FULL_DIM * r;
+        const int nr = counts[2 * r], nv = counts[2 * r + 1];
+        const float *critic = ac_net(params, o, nr, nv, 3, mean + 3 * (size_t)r) + 3;   /* skip log sigma */
+        ac_net(critic, o, nr, nv, 1, value + r);
     }
 }
 

@@ -38,6 +38,7 @@ enum { OR_ACTIVE, OR_EPSTEP, OR_SINCE, OR_EPISODE, OR_NK };
 #define OR_EV_TIMEOUT 8u
 #define OR_EV_NUMERIC 16u
 #define OR_EV_NAN_ACTION 32u
+#define OR_EV_LANE_FORBIDDEN 128u
 
 #define OR_SUR_IN 16
 #define OR_SUR_HID 128
@@ -46,6 +47,15 @@ enum { OR_ACTIVE, OR_EPSTEP, OR_SINCE, OR_EPISODE, OR_NK };
 #define OR_OBS_DIM 256
 #define OR_ROAD_K 64
 #define OR_NEIGH_K 8
+/* the paper's observation (appendix "Observation Space Details") */
+#define OR_FULL_EGO 11
+#define OR_FULL_ROAD_K 350
+#define OR_FULL_NEIGH_K 24
+#define OR_FULL_DIM (OR_FULL_EGO + 5 * OR_FULL_ROAD_K + 7 * OR_FULL_NEIGH_K)
+/* late-fusion actor-critic parameter count (appendix "Network Architecture Details") */
+#define OR_AC_BODY (11 * 64 + 64 + 64 * 64 + 64 + 5 * 96 + 96 + 96 * 96 + 96 + 7 * 96 + 96 + 96 * 96 + 96 + \
+                    256 * 128 + 128 + 128 * 64 + 64)
+#define OR_AC_PARAMS (2 * OR_AC_BODY + 3 * 64 + 3 + 3 + 64 + 1)
 
 typedef struct {
     double mass, inertia[3];               /* body (roll, pitch, yaw)          */
@@ -70,6 +80,7 @@ typedef struct {
     const float *film_mm; const uint8_t *pavement;    /* [W] or NULL     */
     const int32_t *spawn_offsets; const float *spawn; /* [E][5]          */
     uint64_t seed;
+    const float *road_dir;                            /* [P][2] or NULL  */
 } or_world_desc;
 
 typedef struct or_sim or_sim;
@@ -162,11 +173,31 @@ void or_record_samples(or_sim *s, float *rec);
 
 void or_set_threads(int n);
 
+/* the paper's observation [N][OR_FULL_DIM] and valid road / neighbour slot
+ * counts [N][2] of the current state */
+void or_observe_full(const or_sim *s, float *obs, int32_t *counts);
+/* the road points within 10 m in index order (at most K; -1 padded), and
+ * the K nearest other active agents; returns the number of road points */
+int or_road_within(const or_sim *s, int agent, int K, int32_t *out);
+void or_knn_neigh_k(const or_sim *s, int agent, int K, int32_t *out);
+/* late-fusion actor-critic forward: mean [M][3] and value [M] */
+void or_actor_critic(const float *params, int M, const float *obs, const int32_t *counts, double *mean,
+                     double *value);
+
 /* dynamics backend: the articulated vehicle (default) or the kinematic
  * bicycle advanced once per control tick (Sec. "Vehicle Dynamics Ablation") */
 #define OR_DYN_PHYSICS 0
 #define OR_DYN_BICYCLE 1
 void or_set_dynamics(or_sim *s, int mode);
+/* dense shaping rewards and the lane-forbidden event (appendix "Reward
+ * Design Details"); off by default */
+void or_set_shaping(or_sim *s, int on);
+/* the six dense terms of agent i on the current pose with displacement
+ * (dx, dy) since the previous control step: progress, lane keeping,
+ * off-road, idle, vehicle TTC, road-edge TTC (rewards, signs included) */
+void or_shaping_terms(const or_sim *s, int i, double dx, double dy, double *terms);
+/* whether a vehicle circle of agent i overlaps a road-edge segment */
+int or_lane_forbidden(const or_sim *s, int i);
 /* per-triangle friction factor [T] (all worlds' triangles in order) applied
  * to the class friction of a wheel hit on that triangle; NULL clears it.
  * Returns -1 (and changes nothing) if a factor is negative or not finite. */

@@ -67,6 +67,9 @@ VEHICLE_DEFAULTS: dict = dict(
 
 #: friction classes of the workloads (dry, wet, snow, ice)
 MU_CLASSES = np.array([0.9, 0.6, 0.3, 0.1], dtype=np.float32)
+#: friction classes of the tire-sampling workload (the four above plus the
+#: hydroplaning floor's order of magnitude, for coverage of the network)
+MU_SAMPLING = np.array([0.9, 0.6, 0.3, 0.1, 0.001], dtype=np.float32)
 
 ROAD_LANE = 2
 ROAD_EDGE_LEFT = 15
@@ -97,6 +100,7 @@ class Worlds:
     seed: int = 0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    road_dir: np.ndarray = None          # float32 [P,2] unit direction of each point's polyline
 
     @property
     def num_agents(self) -> int:
@@ -108,13 +112,15 @@ class Worlds:
             a, b = int(off[w0]), int(off[w1])
             return (off[w0:w1 + 1] - off[w0]).astype(np.int32), [x[a:b] for x in arrs]
         ao, _ = sub(self.agent_offsets)
-        ro, (rxy, rty) = sub(self.road_offsets, self.road_xy, self.road_type)
+        rdir = self.road_dir if self.road_dir is not None else np.zeros_like(self.road_xy)
+        ro, (rxy, rty, rdr) = sub(self.road_offsets, self.road_xy, self.road_type, rdir)
         to, (tv, ts) = sub(self.tri_offsets, self.tri_verts, self.tri_surface)
         so, (sp,) = sub(self.spawn_offsets, self.spawn)
         return Worlds(w1 - w0, ao, ro, rxy.copy(), rty.copy(), to, tv.copy(), ts.copy(),
                       self.num_surfaces, self.mu_class[w0:w1].copy(),
                       self.film_mm[w0:w1].copy(), self.pavement[w0:w1].copy(),
-                      so, sp.copy(), self.seed, self.name + f"[{w0}:{w1}]", dict(self.meta))
+                      so, sp.copy(), self.seed, self.name + f"[{w0}:{w1}]", dict(self.meta),
+                      rdr.copy() if self.road_dir is not None else None)
 
 
 # --------------------------------------------------------------------------
@@ -127,6 +133,7 @@ class _Road:
     def __init__(self):
         self.xy: list = []
         self.ty: list = []
+        self.dr: list = []           # unit direction of each polyline point
         self.tris: list = []
         self.lanes: list = []        # (start_xy, unit travel dir, length)
 
@@ -142,11 +149,14 @@ class _Road:
         n_pts = int(math.floor(length / SPACING + 1e-9)) + 1
         s = np.arange(n_pts) * SPACING
         emitted = 0
-        # polylines: right edge, right lanes, left lanes, left edge
+        # polylines: right edge, right lanes, left lanes, left edge; lane
+        # centres point along their travel direction (right-hand traffic),
+        # each edge along the lane next to it
         offsets = [(-2 * LANE_W, ROAD_EDGE_RIGHT), (-1.5 * LANE_W, ROAD_LANE),
                    (-0.5 * LANE_W, ROAD_LANE), (0.5 * LANE_W, ROAD_LANE),
                    (1.5 * LANE_W, ROAD_LANE), (2 * LANE_W, ROAD_EDGE_LEFT)]
         for off, ty in offsets:
+            travel = d if off < 0 else -d
             pts = a[None, :] + s[:, None] * d[None, :] + off * left[None, :]
             if max_points is not None:
                 room = max_points - emitted
@@ -155,6 +165,7 @@ class _Road:
                 pts = pts[:room]
             self.xy.append(pts)
             self.ty.append(np.full(len(pts), ty, np.uint8))
+            self.dr.append(np.tile(travel, (len(pts), 1)))
             emitted += len(pts)
         # lane quads (flat, z = 0)
         n_q = int(math.floor(length / QUAD_LEN + 1e-9))
@@ -179,13 +190,14 @@ class _Road:
     def arrays(self):
         xy = np.concatenate(self.xy).astype(np.float32) if self.xy else np.zeros((0, 2), np.float32)
         ty = np.concatenate(self.ty) if self.ty else np.zeros((0,), np.uint8)
+        dr = np.concatenate(self.dr).astype(np.float32) if self.dr else np.zeros((0, 2), np.float32)
         if self.tris:
             t = np.array(self.tris, np.float64)                  # [T,3,2]
             tv = np.zeros((len(t), 3, 3), np.float32)
             tv[:, :, :2] = t
         else:
             tv = np.zeros((0, 3, 3), np.float32)
-        return xy, ty, tv
+        return xy, ty, tv, dr
 
 
 def _rot(v, ang):
@@ -297,7 +309,7 @@ def _manhattan(rng, n_points, block=100.0):
 
 def _pack(name, seed, roads, agents, spawns, mu_class, film, pavement):
     W = len(roads)
-    xy, ty, tv = zip(*[r.arrays() for r in roads])
+    xy, ty, tv, dr = zip(*[r.arrays() for r in roads])
     off = lambda sizes: np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
     return Worlds(
         num_worlds=W,
@@ -316,6 +328,7 @@ def _pack(name, seed, roads, agents, spawns, mu_class, film, pavement):
         spawn=np.concatenate(spawns).reshape(-1, 5).astype(np.float32),
         seed=int(seed),
         name=name,
+        road_dir=np.concatenate(dr).reshape(-1, 2).astype(np.float32),
     )
 
 
@@ -400,6 +413,21 @@ def uneven_manhattan(num_worlds=256, agents=(4, 32), points=(1000, 20000), seed=
     mu = MU_CLASSES[rng.integers(0, 4, size=(num_worlds, 2))]
     return _pack(f"uneven-manhattan {num_worlds}w", seed, roads, counts, spawns, mu,
                  np.zeros(num_worlds), np.zeros(num_worlds, np.uint8))
+
+
+def tire_sampling(num_worlds=1024, agents=16, seed=0) -> Worlds:
+    """The intersection worlds of the learned tire model's sample logging:
+    friction per (world, surface) drawn from MU_SAMPLING."""
+    w = intersections(num_worlds, agents, seed=seed, name=f"tire sampling {num_worlds}x{agents}")
+    rng = np.random.default_rng([int(seed), 0x7E])
+    w.mu_class = MU_SAMPLING[rng.integers(0, len(MU_SAMPLING), size=w.mu_class.shape)]
+    return w
+
+
+def speeds(seed: int, step: int, n: int, lo: float = 3.0, hi: float = 30.0) -> np.ndarray:
+    """Seeded forward speeds U[lo, hi] m/s (re-initialisation of the sample logging)."""
+    rng = np.random.default_rng([int(seed), int(step), 0x5B])
+    return rng.uniform(lo, hi, n).astype(np.float32)
 
 
 def workload(name: str, seed: int = 0) -> Worlds:
