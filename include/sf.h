@@ -69,6 +69,9 @@ typedef enum {
 #define SF_EV_TIMEOUT 8u     /* episode reached max_episode_steps            */
 #define SF_EV_NUMERIC 16u    /* non-finite state (also sets SF_EV_CRASH)     */
 #define SF_EV_NAN_ACTION 32u /* a NaN action was replaced by 0               */
+#define SF_EV_LANE_FORBIDDEN 128u /* a vehicle circle overlapped a road-edge
+                                     segment (types 15, 16) at the start of
+                                     the control step (with shaping on)     */
 #define SF_EV_CONTACT_OVERFLOW 64u /* the agent's world had more contact points
                                       than SF_MAX_CONTACTS_PER_WORLD in some
                                       substep of the step (the excess was left
@@ -143,6 +146,8 @@ typedef struct {
     const int32_t *spawn_offsets;  /* spawn entries per world (>= 1 if agents)*/
     const float *spawn;            /* [E][5] x, y, yaw, goal_x, goal_y        */
     uint64_t seed;                 /* spawn-entry rotation seed               */
+    const float *road_dir;         /* [P][2] unit direction of each point's
+                                      polyline, or NULL (all zero)            */
 } sf_world_desc;
 
 typedef void *(*sf_alloc_fn)(size_t bytes, void *ctx);
@@ -228,12 +233,43 @@ sf_status sf_reset(sf_sim *sim, const uint8_t *d_mask);
  * slip angle atan(l_r tan(steer) / (l_f + l_r)) and yaw rate
  * speed sin(slip) / l_r, l_f and l_r the front and rear mount distances; no
  * suspension, tires or contact forces, collisions from the circle pairs of
- * the new poses (recorded as substep 0), and the same events, rewards,
+ * the tick's input poses (recorded as substep 0), and the same events, rewards,
  * resets and observations.  The learned tire model and its sample log do
  * nothing in this mode.  Changing the mode drops a captured graph. */
 #define SF_DYNAMICS_PHYSICS 0
 #define SF_DYNAMICS_BICYCLE 1
 sf_status sf_set_dynamics(sf_sim *sim, int32_t mode);
+
+/* Dense shaping rewards and the lane-forbidden termination (Appendix
+ * "Reward Design Details").  on = 1: every step of an agent that carries on
+ * (not done) adds to its sparse reward six terms taken on its new pose,
+ * with the road context of its observation (the 64 nearest road points and
+ * the 8 nearest vehicles); each road point stands for the 0.5 m segment of
+ * its polyline centred on it along its direction.  With t the direction of
+ * the nearest lane point (types 1, 2) turned toward the goal, lat the
+ * signed lateral offset from it and h the vehicle heading:
+ *   progress      2 clamp(d . t, -2, 2), d the step's displacement (m)
+ *   lane keeping  0.08 exp(-(lat / 1.75)^2) (0.2 + 0.8 max(0, h . t))
+ *   off road      -0.5 if |lat| > 3.25 m, the lane point is farther than
+ *                 6 m, or there is none
+ *   idle          -0.05 if the speed is below 1 m/s
+ *   vehicle TTC   -min(0.10 / max(tau, 0.5), 0.35), tau the smallest time to
+ *                 collision of the observation's neighbours (10 s if none)
+ *   road-edge TTC -min(0.07 / max(tau_e, 0.5), 0.40), tau_e the smallest
+ *                 time for the front circle to reach a road-edge point
+ *                 (types 15, 16) ahead of the vehicle within W / 2 + r of
+ *                 its centre line at the forward speed (no term if none)
+ * and a step that starts with a vehicle circle overlapping a road-edge
+ * segment sets SF_EV_LANE_FORBIDDEN, terminates with reward -20 (after goal,
+ * collision and crash in precedence) and carries no dense terms.  The
+ * nearest-point, side, off-road, idle, corridor and overlap decisions are
+ * integer predicates on quantised positions (2^-10 m) and directions
+ * (2^-14).  on = 0 (default): sparse rewards only.  Switching recomputes the
+ * current observation (and so the flags) and drops a captured graph; on
+ * first use it allocates 9 bytes per agent.  With shaping on, the step of
+ * sf_step_actor_critic also runs the 256-float observation, which carries
+ * the shaping terms. */
+sf_status sf_set_shaping(sf_sim *sim, int32_t on);
 
 /* Spatially varying friction (the paper applies one friction value per
  * world; Appendix "Simulator Limitations and Sharp Edges", uniform friction
@@ -298,13 +334,80 @@ sf_status sf_step_policy(sf_sim *sim, float dt, int32_t substeps);
 sf_status sf_graph_capture(sf_sim *sim, int32_t control_steps, float dt, int32_t substeps);
 sf_status sf_graph_launch(sf_sim *sim);
 
+/* ---- the paper's observation and network at their own shapes.
+ * sf_observe_full: the observation of appendix "Observation Space Details"
+ * for the current state, [N][SF_FULL_DIM] float32 per agent:
+ *   ego 11: goal in the body frame / 100 (2), sine and cosine of the goal
+ *     bearing, goal distance / 100, body velocity / 10 (2), then the weather
+ *     token of Eq. weather_obs: film depth / 1 mm and the one-hot pavement
+ *     (AC, SMA, OGFC) of the agent's world;
+ *   road 350 x 5: every road point within 10 m (quantised squared distance,
+ *     inclusive) in point-index order, the first 350: body-frame offset / 10
+ *     (2), type / 20, body-frame polyline direction (2);
+ *   neighbours 24 x 7: the 24 nearest other active agents, ascending, with
+ *     the features of the 8-neighbour observation (time to collision too);
+ * slots past the valid ones are zero; d_counts [N][2] int32 receives the
+ * numbers of valid road and neighbour slots (the network's masks).  With
+ * both pointers NULL the handle's own buffers receive them
+ * (sf_actor_critic_outputs).  Inactive agents: zero rows, counts 0.
+ * Enqueued on the handle's stream. */
+#define SF_FULL_EGO 11
+#define SF_FULL_ROAD_K 350
+#define SF_FULL_NEIGH_K 24
+#define SF_FULL_DIM (SF_FULL_EGO + 5 * SF_FULL_ROAD_K + 7 * SF_FULL_NEIGH_K)
+sf_status sf_observe_full(sf_sim *sim, float *d_obs, int32_t *d_counts);
+
+/* The late-fusion actor-critic of appendix "Network Architecture Details".
+ * Parameters: SF_AC_PARAMS float32 (host), for the actor and then the
+ * critic (no shared weights), each: ego W1[64][11] b1[64] W2[64][64] b2[64],
+ * road W1[96][5] b1[96] W2[96][96] b2[96], vehicle W1[96][7] b1[96]
+ * W2[96][96] b2[96], trunk W1[128][256] b1[128] W2[64][128] b2[64]
+ * (SF_AC_BODY floats), then the actor's head W[3][64] b[3] and its
+ * state-independent log sigma[3], or the critic's head W[1][64] b[1]
+ * (row-major [out][in]).  ELU after every hidden layer; each set encoder is
+ * followed by a max over the valid slots (the masked max-pool; an empty set
+ * gives 0); embeddings concatenate as ego 64 | road 96 | vehicle 96.  bf16
+ * inputs, weights and hidden activations, fp32 accumulation and biases.
+ * sf_actor_critic: d_obs [M][SF_FULL_DIM], d_counts [M][2] -> d_mean [M][3]
+ * (the actor's mean) and d_value [M] (the critic), device float32.
+ * sf_step_actor_critic: the paper's observation of the current state, the
+ * network, actions from its mean (throttle and brake rectified to [0, 1],
+ * steering clamped to [-1, 1]; a_long = throttle - brake, steer =
+ * steer_max * steering; appendix "Action Space Details"), then sf_step's
+ * physics and outputs -- the 256-float observation of sf_observe is NOT
+ * refreshed by this call. */
+#define SF_AC_BODY (11 * 64 + 64 + 64 * 64 + 64 + 5 * 96 + 96 + 96 * 96 + 96 + 7 * 96 + 96 + 96 * 96 + 96 + \
+                    256 * 128 + 128 + 128 * 64 + 64)
+#define SF_AC_PARAMS (2 * SF_AC_BODY + 3 * 64 + 3 + 3 + 64 + 1)
+sf_status sf_actor_critic_load(sf_sim *sim, const float *h_params, size_t n);
+sf_status sf_actor_critic(sf_sim *sim, const float *d_obs, const int32_t *d_counts, int64_t M, float *d_mean,
+                          float *d_value);
+sf_status sf_step_actor_critic(sf_sim *sim, float dt, int32_t substeps);
+/* Copies (enqueued on the handle's stream) of the handle's buffers of the
+ * last sf_step_actor_critic (observation and counts also of the last
+ * sf_observe_full without outputs) into caller device arrays: mean [N][3],
+ * value [N], actions [N][2], observation [N][SF_FULL_DIM], counts [N][2];
+ * a NULL destination is skipped. */
+sf_status sf_actor_critic_read(sf_sim *sim, float *d_mean, float *d_value, float *d_actions, float *d_obs,
+                               int32_t *d_counts);
+
 /* ---- per-kernel timing of eagerly enqueued work (hipEvents on the
  * handle's stream).  sf_profile(sim, 1) starts (and clears) the record;
  * sf_profile_read synchronises and returns total milliseconds and launch
- * counts per kernel: [0] policy, [1] step, [2] observation, [3] reset. */
-#define SF_PROF_KERNELS 4
+ * counts per kernel: [0] policy, [1] step, [2] observation, [3] reset,
+ * [4] the paper's observation, [5] the actor-critic, [6] the clock kernels
+ * of sf_profile_calibrate.  Each event pair is bound to its kernel's
+ * dispatch (hipExtLaunchKernelGGL); an interval still holds a fixed cost of
+ * the pair beside the kernel's execution. */
+#define SF_PROF_KERNELS 7
 sf_status sf_profile(sf_sim *sim, int32_t enable);
 sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches);
+/* Enqueues n (1..10000) launches of a one-wave kernel that runs for `us`
+ * microseconds (1..10000) of the GPU's constant-rate wall clock, timed as
+ * the kernels above are (profiling must be on): its mean interval less `us`
+ * is the fixed cost of an event pair and a dispatch, to be taken off the
+ * other kernels' means.  Not for graph capture. */
+sf_status sf_profile_calibrate(sf_sim *sim, int32_t n, double us);
 
 /* ---- learned tire surrogate.
  * The paper replaces a validated but expensive vehicle model (its teacher)
@@ -319,8 +422,9 @@ sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches);
  * v_eps), slip angle atan(v_y / max(|v_x|, v_eps)), F_z / 4000, mu,
  * r Omega / 30, camber asin(axle . n), v_x / 30, v_y / 5, steer angle,
  * compression / 0.2, compression rate / 2, tau_drive / tau_drive_max,
- * tau_brake / tau_brake_front, body roll atan2(R21, R22), pitch asin(-R20),
- * yaw rate / 2.  Outputs (F_x, F_y, M_z / trail) / (mu F_z).
+ * tau_brake / tau_brake_front, the slip vector over mu (slip ratio / mu,
+ * (v_y / max(|v_x|, v_eps)) / mu) shortened to length 2 if longer, yaw
+ * rate / 2.  Outputs (F_x, F_y, M_z / trail) / (mu F_z).
  * A wheel uses the network only if every input lies inside the training
  * envelope [lo, hi] and the prediction passes two residual checks (force
  * inside 1.02 mu F_z, and F_x along the slip when |slip ratio| > 0.02);
@@ -362,8 +466,10 @@ typedef struct {
 } sf_sur_train_opts;
 
 /* Train on d_data [M][20] (device, valid samples) with the batch-mean
- * squared error over the three outputs; *loss_out (may be NULL) receives
- * the last step's loss.  Enqueued on the handle's stream; synchronises. */
+ * weighted squared error over the three outputs, a sample weighted by
+ * 1 / max(|(t_x, t_y)|, 0.05)^2 of its targets (so that the loss is the mean
+ * squared relative force error); *loss_out (may be NULL) receives the last
+ * step's loss.  Enqueued on the handle's stream; synchronises. */
 sf_status sf_sur_train(sf_sim *sim, const float *d_data, int64_t M, const sf_sur_train_opts *opts,
                        float *loss_out);
 /* Gradient of that loss over all M samples (at most 262144) at the current

@@ -114,7 +114,7 @@ def lib():
         L.or_circle_model.argtypes = [C.POINTER(OrParams), dp, dp]
         L.or_mlp_forward.argtypes = [ip, vp, vp, vp, ip, ip, vp, vp]
         L.or_policy.argtypes = [ip, vp, vp, vp, C.c_double, vp]
-        L.or_mlp_mse_grad.argtypes = [ip, vp, vp, vp, ip, vp, vp, vp, vp]
+        L.or_mlp_mse_grad.argtypes = [ip, vp, vp, vp, ip, vp, vp, vp, vp, vp]
         L.or_mlp_mse_grad.restype = C.c_double
         L.or_adam.argtypes = [ip, vp, vp, vp, vp, ip, C.c_double, C.c_double, C.c_double, C.c_double]
         L.or_tire.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 8 + [dp] * 4
@@ -403,7 +403,16 @@ def policy(Ws, bs, obs, steer_max=0.5):
     return act
 
 
-def mlp_mse_grad(Ws, bs, x, target):
+def force_weights(target):
+    """Training weight of a tire-model sample: 1 / max(|(F_x, F_y)|, 0.05)^2
+    of its targets (in units of mu F_z), the squared denominator of the
+    relative force error, so that the weighted squared error is the squared
+    relative error that metric measures."""
+    t = np.asarray(target, np.float64)
+    return 1.0 / np.maximum(np.hypot(t[:, 0], t[:, 1]), 0.05) ** 2
+
+
+def mlp_mse_grad(Ws, bs, x, target, row_weight=None):
     sizes = np.array([Ws[0].shape[1]] + [w.shape[0] for w in Ws], np.int32)
     Wc, bc, Wp, bp = _layer_ptrs(Ws, bs)
     gW = [np.zeros(w.shape, np.float64) for w in Ws]
@@ -412,7 +421,8 @@ def mlp_mse_grad(Ws, bs, x, target):
     gbp = (C.c_void_p * len(gb))(*[_ptr(g) for g in gb])
     x = np.ascontiguousarray(x, np.float32)
     t = np.ascontiguousarray(target, np.float32)
-    loss = lib().or_mlp_mse_grad(len(Ws), _ptr(sizes), Wp, bp, x.shape[0], _ptr(x), _ptr(t), gWp, gbp)
+    w = None if row_weight is None else np.ascontiguousarray(row_weight, np.float64)
+    loss = lib().or_mlp_mse_grad(len(Ws), _ptr(sizes), Wp, bp, x.shape[0], _ptr(x), _ptr(t), _ptr(w), gWp, gbp)
     return loss, gW, gb
 
 

@@ -391,21 +391,29 @@ int or_raycast(const or_sim *s, int i, int wh, double *t, double *n, int *surf, 
 /* Inputs of the learned tire model for one wheel, each scaled to order one:
  * slip ratio, slip angle, load, friction, rim speed, camber, then the
  * longitudinal and lateral contact speeds, the wheel's steer angle, spring
- * compression and rate, drive and brake torque fractions, body roll and
- * pitch and yaw rate.  Rounded to float (the form in which both the logged
- * training samples and the inference inputs exist). */
+ * compression and rate, drive and brake torque fractions, the slip vector
+ * over the friction coefficient (slip ratio / mu, tan(slip angle) / mu)
+ * shortened to length 2 if longer, and the yaw rate.  The outputs are forces
+ * over mu F_z, so that pair is the scale on which they vary at any mu.
+ * Rounded to float (the form in which both the logged training samples and
+ * the inference inputs exist). */
 static void sur_features(const or_sim *s, double Fz, double mu, double vx, double vy, double Om,
                          double td, double tb, double x, double xd, double delta, double gamma,
-                         double R[3][3], const double *om, float *f) {
+                         const double *om, float *f) {
     const or_params *p = &s->p;
     double D = fabs(vx) > p->v_eps ? fabs(vx) : p->v_eps;
-    double pitch_s = -R[2][0];
-    if (pitch_s > 1.0) pitch_s = 1.0;
-    if (pitch_s < -1.0) pitch_s = -1.0;
+    const double kap = (p->wheel_radius * Om - vx) / D;
+    double sx = 0.0, sy = 0.0;
+    if (mu > 0.0) {
+        sx = kap / mu;
+        sy = vy / D / mu;
+        const double L = sqrt(sx * sx + sy * sy);
+        if (L > 2.0) { sx *= 2.0 / L; sy *= 2.0 / L; }
+    }
     double v[OR_SUR_IN] = {
-        (p->wheel_radius * Om - vx) / D, atan(vy / D), Fz / 4000.0, mu, p->wheel_radius * Om / 30.0,
+        kap, atan(vy / D), Fz / 4000.0, mu, p->wheel_radius * Om / 30.0,
         gamma, vx / 30.0, vy / 5.0, delta, x / 0.2, xd / 2.0, td / p->tau_drive,
-        tb / p->tau_brake_front, atan2(R[2][1], R[2][2]), asin(pitch_s), om[2] / 2.0};
+        tb / p->tau_brake_front, sx, sy, om[2] / 2.0};
     for (int k = 0; k < OR_SUR_IN; ++k) f[k] = (float)v[k];
 }
 
@@ -621,7 +629,7 @@ static void substep_world(or_sim *s, int w, const float *actions, double h,
                         double g = dot3(axle, n);
                         if (g > 1.0) g = 1.0;
                         if (g < -1.0) g = -1.0;
-                        sur_features(s, Fz, mu, vx, vy, Omega, td, tb, x, xd, dl, asin(g), R, om, feat);
+                        sur_features(s, Fz, mu, vx, vy, Omega, td, tb, x, xd, dl, asin(g), om, feat);
                     }
                     if (in_domain && s->sur_on) {
                         int inside = 1;
@@ -1559,8 +1567,8 @@ void or_policy(int M, const float *obs, const float *const *W, const float *cons
 }
 
 double or_mlp_mse_grad(int L, const int *sz, const float *const *W, const float *const *b,
-                       int M, const float *x, const float *target, double *const *gW,
-                       double *const *gb) {
+                       int M, const float *x, const float *target, const double *row_weight,
+                       double *const *gW, double *const *gb) {
     int mx = 0;
     for (int l = 0; l <= L; ++l) if (sz[l] > mx) mx = sz[l];
     for (int l = 0; l < L; ++l) {
@@ -1573,10 +1581,11 @@ double or_mlp_mse_grad(int L, const int *sz, const float *const *W, const float 
     for (int l = 0; l <= L; ++l) { a[l] = (double *)malloc(sizeof(double) * mx); z[l] = (double *)malloc(sizeof(double) * mx); }
     for (int r = 0; r < M; ++r) {
         mlp_fwd_keep(L, sz, W, b, 1, x + (size_t)r * sz[0], a, z);
+        const double wr = row_weight ? row_weight[r] : 1.0;
         for (int o = 0; o < sz[L]; ++o) {
             double e = a[L][o] - target[(size_t)r * sz[L] + o];
-            loss += e * e * scale;
-            d0[o] = 2.0 * e * scale;
+            loss += wr * e * e * scale;
+            d0[o] = 2.0 * wr * e * scale;
         }
         for (int l = L - 1; l >= 0; --l) {
             for (int o = 0; o < sz[l + 1]; ++o) {

@@ -137,12 +137,14 @@ void or_mlp_forward(int L, const int *sizes, const float *const *W,
 void or_policy(int M, const float *obs, const float *const *W,
                const float *const *b, double steer_max, double *act);
 /* Mean-squared-error loss of the surrogate net and its gradients in FP64
- * (no bf16 rounding of gradients; forward uses the bf16 rounding points).
- * gW/gb laid out like W/b (double).  Returns the loss. */
+ * (no bf16 rounding of gradients; forward uses the bf16 rounding points):
+ * (1 / (M n_out)) sum_r w_r sum_o (y_ro - t_ro)^2 with row weights w_r
+ * (row_weight NULL: all 1).  gW/gb laid out like W/b (double).  Returns the
+ * loss. */
 double or_mlp_mse_grad(int L, const int *sizes, const float *const *W,
                        const float *const *b, int M, const float *x,
-                       const float *target, double *const *gW,
-                       double *const *gb);
+                       const float *target, const double *row_weight,
+                       double *const *gW, double *const *gb);
 /* Switch the bf16 rounding points off (1 = on, the default); used only by
  * finite-difference gradient checks, which need a smooth function. */
 void or_set_bf16(int on);

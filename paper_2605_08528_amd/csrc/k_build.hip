@@ -202,15 +202,39 @@ void launch_grid_fill(const DevWorld &Wd, const float *verts, int T, int P, int 
     if (P) k_grid_pts<1><<<(P + 255) / 256, 256, 0, st>>>(Wd, P, pt_cursor, pt_items);
 }
 
-// order each cell's items by index (the scatter order is not deterministic)
-__global__ void k_cell_sort(const int *start, int C, int *items) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+// order each cell's items by index (the scatter order is not
+// deterministic): one wave per cell; up to 64 items by a bitonic sort across
+// the lanes, up to CELL_SORT_LDS by ranks counted against a copy in LDS
+// (items of a cell are distinct), larger cells by an insertion sort on one
+// lane
+#define CELL_SORT_LDS 2048
+__global__ __launch_bounds__(256) void k_cell_sort(const int *start, int C, int *items) {
+    __shared__ int buf[4][CELL_SORT_LDS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = blockIdx.x * 4 + wv;
     if (c >= C) return;
-    int a = start[c], b = start[c + 1];
-    for (int i = a + 1; i < b; ++i) {
-        int v = items[i], j = i - 1;
-        while (j >= a && items[j] > v) { items[j + 1] = items[j]; --j; }
-        items[j + 1] = v;
+    const int a = start[c], n = start[c + 1] - a;
+    if (n <= 1) return;
+    if (n <= 64) {
+        unsigned v = lane < n ? (unsigned)items[a + lane] : 0xffffffffu;
+        v = wave_sort_u32(v);
+        if (lane < n) items[a + lane] = (int)v;
+    } else if (n <= CELL_SORT_LDS) {
+        int *b = buf[wv];
+        for (int i = lane; i < n; i += 64) b[i] = items[a + i];
+        wave_sync();
+        for (int i = lane; i < n; i += 64) {
+            const int v = b[i];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) rank += b[j] < v;
+            items[a + rank] = v;
+        }
+    } else if (lane == 0) {
+        for (int i = a + 1; i < a + n; ++i) {
+            int v = items[i], j = i - 1;
+            while (j >= a && items[j] > v) { items[j + 1] = items[j]; --j; }
+            items[j + 1] = v;
+        }
     }
 }
 
@@ -289,11 +313,11 @@ __global__ __launch_bounds__(256) void k_occ(DevWorld Wd, int *occ) {
 void launch_grid_finish(const DevWorld &Wd, int CT, int CP, int *tri_items, int *pt_items,
                         float4 *tri_rec, int4 *pt_cell, int *pt_occ, hipStream_t st) {
     if (CT) {
-        k_cell_sort<<<(CT + 255) / 256, 256, 0, st>>>(Wd.tri_cell_start, CT, tri_items);
+        k_cell_sort<<<(CT + 3) / 4, 256, 0, st>>>(Wd.tri_cell_start, CT, tri_items);
         k_pack_tris<<<(CT + 255) / 256, 256, 0, st>>>(Wd, CT, tri_items, tri_rec);
     }
     if (CP) {
-        k_cell_sort<<<(CP + 255) / 256, 256, 0, st>>>(Wd.pt_cell_start, CP, pt_items);
+        k_cell_sort<<<(CP + 3) / 4, 256, 0, st>>>(Wd.pt_cell_start, CP, pt_items);
         k_pack_pts<<<(CP + 255) / 256, 256, 0, st>>>(Wd, CP, pt_items, pt_cell);
     }
     if (Wd.W) k_occ<<<Wd.W, 256, 0, st>>>(Wd, pt_occ);

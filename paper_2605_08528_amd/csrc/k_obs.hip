@@ -13,43 +13,6 @@ __device__ __forceinline__ unsigned long long lane_lt() {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
-    int lo = lane_xor((int)(unsigned)v, m);
-    int hi = lane_xor((int)(unsigned)(v >> 32), m);
-    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
-}
-
-// ascending bitonic sort of one u64 key per lane within each group of
-// WIDTH lanes (32: the two halves of the wavefront sorted separately)
-template <int WIDTH>
-__device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long key) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 2; k <= WIDTH; k <<= 1)
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            unsigned long long o = shfl_xor_u64(key, j);
-            bool up = (lane & k) == 0, lower = (lane & j) == 0;
-            key = (lower == up) ? (key < o ? key : o) : (key > o ? key : o);
-        }
-    return key;
-}
-
-// the same for one u32 key per lane across the whole wavefront (one
-// exchange per stage instead of two)
-__device__ __forceinline__ unsigned wave_sort_u32(unsigned key) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1)
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const unsigned o = (unsigned)lane_xor((int)key, j);
-            const bool up = (lane & k) == 0, lower = (lane & j) == 0;
-            key = (lower == up) ? (key < o ? key : o) : (key > o ? key : o);
-        }
-    return key;
-}
-
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) {
@@ -224,6 +187,110 @@ __device__ __forceinline__ int xcd_agent(int waves) {
     return (x * q + min(x, r) + (b >> 3)) * waves;
 }
 
+// Appendix "Reward Design Details" on the pose this observation sees, from
+// the road points it selected (one per lane, my_idx) and the neighbours'
+// times to collision (nb_ttc, 10 s in lanes without one): whether a
+// vehicle circle overlaps a road-edge segment (read by the next step), and
+// after a step the six dense terms added to that step's reward of an agent
+// that carries on.  Every road point stands for the 0.5 m segment of its
+// polyline centred on it; the decisions are integer predicates on
+// quantised values, so that they match the oracle's bit for bit.
+__device__ __forceinline__ bool circle_hits_segment(long long cx, long long cy, int2 pq, float2 dir, long long R2) {
+    const long long hx = qpos(0.25f * dir.x), hy = qpos(0.25f * dir.y);
+    const long long ax = pq.x - hx, ay = pq.y - hy, vx = 2 * hx, vy = 2 * hy;
+    const long long wx = cx - ax, wy = cy - ay;
+    if (wx > 4096 || wx < -4096 || wy > 4096 || wy < -4096) return false;
+    const long long len2 = vx * vx + vy * vy, t = wx * vx + wy * vy;
+    if (len2 == 0 || t <= 0) return wx * wx + wy * wy < R2;
+    if (t >= len2) {
+        const long long ex = wx - vx, ey = wy - vy;
+        return ex * ex + ey * ey < R2;
+    }
+    return (wx * wx + wy * wy) * len2 - t * t < R2 * len2;
+}
+
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = fminf(v, lane_xor_f(v, m));
+    return v;
+}
+
+__device__ void shaping(const DevParams &P, const DevWorld &Wd, int n, int r0, int my_idx, float px, float py,
+                        float qw, float qx, float qy, float qz, float hx, float hy, float vx, float vy, float goal_x,
+                        float goal_y, float nb_ttc) {
+    const int lane = threadIdx.x & 63;
+    const long long QX = qpos(px), QY = qpos(py);
+    int cq[6];
+    circle_centres_q(P, px, py, qw, qx, qy, qz, cq);
+    const long long R2 = (long long)(P.Qr2 >> 2);   // Qr2 = (2 round(r 2^10))^2
+    // planar heading of the quantised quaternion (unnormalised integers)
+    const long long iqw = qquat(qw), iqx = qquat(qx), iqy = qquat(qy), iqz = qquat(qz);
+    const long long ihx = (1ll << 28) - 2 * (iqy * iqy + iqz * iqz), ihy = 2 * (iqx * iqy + iqw * iqz);
+    const long long nh = isqrt64(ihx * ihx + ihy * ihy);
+    const float vf = hx * vx + hy * vy;
+    bool forbid = false;
+    unsigned long long lkey = ~0ull;
+    float etau = INFINITY;
+    if (my_idx != 0x7fffffff) {
+        const int q = r0 + my_idx;
+        const int ty = Wd.road_type[q];
+        const int2 pq = Wd.road_q[q];
+        const long long ex = (long long)pq.x - QX, ey = (long long)pq.y - QY;
+        if (ty == 15 || ty == 16) {
+            const float2 rd = Wd.road_dir[q];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) forbid = forbid || circle_hits_segment(cq[2 * a], cq[2 * a + 1], pq, rd, R2);
+            // road-edge time to collision: edge points ahead in the corridor
+            if (vf > 0.f && ex <= (1 << 20) && ex >= -(1 << 20) && ey <= (1 << 20) && ey >= -(1 << 20)) {
+                const long long along = ex * ihx + ey * ihy, side = -ex * ihy + ey * ihx;
+                if (along > 0 && side <= Wd.edge_half_q * nh && side >= -Wd.edge_half_q * nh) {
+                    const float2 rp = Wd.road_xy[q];
+                    const float xb = hx * (rp.x - px) + hy * (rp.y - py);
+                    etau = fmaxf(xb - (P.cd + P.cr), 0.f) / vf;
+                }
+            }
+        }
+        if (ty == 1 || ty == 2) lkey = ((unsigned long long)sat_key(ex * ex + ey * ey) << 20) | (unsigned)my_idx;
+    }
+    forbid = __ballot(forbid) != 0ull;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const unsigned long long o = shfl_xor_u64(lkey, m);
+        lkey = o < lkey ? o : lkey;
+    }
+    etau = wave_min_f(etau);
+    const float tau = wave_min_f(lane < 8 ? nb_ttc : 10.f);
+    if (lane != 0) return;
+    Wd.forbid[n] = forbid;
+    if (!Wd.shape_add || Wd.done_out[n]) return;
+    float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f, t4, t5 = 0.f;
+    bool off = true;
+    if (lkey != ~0ull) {
+        const int q = r0 + (int)(lkey & 0xFFFFF);
+        const float2 rd = Wd.road_dir[q];
+        float tx = rd.x, ty = rd.y;
+        // the lane's direction turned toward the goal (integer sign)
+        const long long gdx = (long long)qpos(goal_x) - QX, gdy = (long long)qpos(goal_y) - QY;
+        if ((long long)qquat(tx) * gdx + (long long)qquat(ty) * gdy < 0) { tx = -tx; ty = -ty; }
+        const float2 d = Wd.disp[n];
+        t0 = 2.f * fminf(fmaxf(d.x * tx + d.y * ty, -2.f), 2.f);
+        const float2 rp = Wd.road_xy[q];
+        const float lat = (px - rp.x) * (-ty) + (py - rp.y) * tx;
+        const float al = hx * tx + hy * ty;
+        t1 = 0.08f * expf(-(lat / 1.75f) * (lat / 1.75f)) * (0.2f + 0.8f * fmaxf(al, 0.f));
+        const int2 pq = Wd.road_q[q];
+        long long latq = (QX - pq.x) * (-(long long)qquat(ty)) + (QY - pq.y) * (long long)qquat(tx);
+        if (latq < 0) latq = -latq;
+        off = latq > 54525952ll /* 3.25 m in 2^-24 m */ || (long long)(lkey >> 20) > 6144ll * 6144ll;
+    }
+    if (off) t2 = -0.5f;
+    const long long qvx = qpos(vx), qvy = qpos(vy);
+    if (qvx * qvx + qvy * qvy < 1024ll * 1024ll) t3 = -0.05f;
+    t4 = -fminf(0.10f / fmaxf(tau, 0.5f), 0.35f);
+    if (etau < INFINITY) t5 = -fminf(0.07f / fmaxf(etau, 0.5f), 0.40f);
+    Wd.reward_out[n] += ((((t0 + t1) + t2) + t3) + t4) + t5;
+}
+
 // One agent's observation row (one wave): written to obs and left in the
 // wave's LDS row; returns false for an inactive agent (row of zeros in
 // memory, LDS row untouched).
@@ -250,6 +317,7 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
     const int a0 = aw.x, A = aw.y, r0 = aw.z, PW = aw.w;
     const GridHdr g = Wd.agent_grid[n];
     if (!active) {
+        if (Wd.forbid && lane == 0) Wd.forbid[n] = 0;
         dst[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (dbg) dbg[(size_t)n * 72 + lane] = -1;
         if (dbg && lane < 8) dbg[(size_t)n * 72 + 64 + lane] = -1;
@@ -295,6 +363,8 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
         row[lane] = e;
     }
     const int QX = qpos(px), QY = qpos(py);
+    float nb_ttc = 10.f;     // time to collision of this lane's neighbour (10 s: none)
+    int nb_ttc_lane = 1;
 
     // ---- neighbours: 8 nearest other active agents of the world
     {
@@ -332,6 +402,7 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
         const float mvx = __shfl(ovx, src, 64), mvy = __shfl(ovy, src, 64);
         if (lane < 8 && jn >= 0) {
             float jx = 1.f - 2.f * (mqy * mqy + mqz * mqz), jy = 2.f * (mqx * mqy + mqw * mqz);
+            nb_ttc_lane = 0;   // this lane holds a neighbour (its time to collision below)
             float L = sqrtf(jx * jx + jy * jy);
             if (L < 1e-12f) { jx = 1.f; jy = 0.f; } else { jx /= L; jy /= L; }
             const float dx = mx - px, dy = my - py;
@@ -339,28 +410,8 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
             float dpsi = atan2f(hx * jy - hy * jx, hx * jx + hy * jy);
             if (dpsi == -3.14159265358979f) dpsi = 3.14159265358979f;
             // swept circles, constant planar velocities; 0 if touching
-            float ttc = 10.f;
-            if (bx >= 0.f) {
-                const float dvx = mvx - vx, dvy = mvy - vy;
-                const float R2 = 4.f * P.cr * P.cr;
-                for (int a = 0; a < 3; ++a)
-                    for (int c = 0; c < 3; ++c) {
-                        const float cx = (mx + (float)(c - 1) * P.cd * jx) - (px + (float)(a - 1) * P.cd * hx);
-                        const float cy = (my + (float)(c - 1) * P.cd * jy) - (py + (float)(a - 1) * P.cd * hy);
-                        const float c0 = cx * cx + cy * cy - R2;
-                        float t;
-                        if (c0 <= 0.f) t = 0.f;
-                        else {
-                            const float bq = 2.f * (cx * dvx + cy * dvy);
-                            if (bq >= 0.f) continue;
-                            const float aq = dvx * dvx + dvy * dvy;
-                            const float disc = bq * bq - 4.f * aq * c0;
-                            if (disc < 0.f) continue;
-                            t = 2.f * c0 / (-bq + sqrtf(disc));
-                        }
-                        ttc = fminf(ttc, t);
-                    }
-            }
+            const float ttc = bx >= 0.f ? ttc_swept(P, px, py, hx, hy, vx, vy, mx, my, jx, jy, mvx, mvy, 10.f) : 10.f;
+            nb_ttc = ttc;
             float *o = row + 200 + 7 * lane;
             o[0] = bx / 100.f;
             o[1] = by / 100.f;
@@ -500,6 +551,8 @@ __device__ bool obs_agent(const DevParams &P, const DevWorld &Wd, const float *_
         o[1] = (-hy * dx + hx * dy) / 10.f;
         o[2] = (float)Wd.road_type[r0 + my_idx] / 20.f;
     }
+    (void)nb_ttc_lane;
+    if (Wd.forbid) shaping(P, Wd, n, r0, my_idx, px, py, qw, qx, qy, qz, hx, hy, vx, vy, goal_x, goal_y, nb_ttc);
     wave_sync();
     dst[lane] = reinterpret_cast<const float4 *>(row)[lane];
     return true;
@@ -531,12 +584,6 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_obs(DevParams P, DevWorld Wd,
 // workgroup waits for its slowest agent.
 #define OP_LD (SF_OBS_DIM + 8)  // padded bf16 activation row
 #define OP_KS (SF_OBS_DIM / 32)  // k-steps of 32 per layer
-
-__device__ __forceinline__ float elu_fast(float x) {
-    if (x > 0.f) return x;
-    if (x > -0.25f) return x * (1.f + x * (0.5f + x * (1.f / 6.f + x * (1.f / 24.f))));
-    return __expf(x) - 1.f;
-}
 
 // this lane's B fragments of wave w's 16 columns, all k-steps
 __device__ __forceinline__ void op_fetch(const uint16_t *__restrict__ W, bf16x8 (&f)[OP_KS]) {
@@ -618,19 +665,19 @@ void launch_obs_policy(const DevParams &P, const DevWorld &Wd, const float *st, 
                        float4 *hint, const uint16_t *W1, const float *b1, const uint16_t *W2, const float *b2,
                        const uint16_t *W3, const float *b3, float steer_max, float *act, hipStream_t s) {
     if (Wd.N == 0) return;
-    k_obs_policy<<<(Wd.N + 15) / 16, 1024, 0, s>>>(P, Wd, st, ist, obs, hint, W1, b1, W2, b2, W3, b3, steer_max,
-                                                   act);
+    sf_launch(k_obs_policy, dim3((Wd.N + 15) / 16), dim3(1024), 0, s, P, Wd, st, ist, obs, hint, W1, b1, W2, b2, W3,
+              b3, steer_max, act);
 }
 
 void launch_obs(const DevParams &P, const DevWorld &Wd, const float *st, const int *ist, float *obs,
                 int *dbg_idx, float4 *hint, int waves, hipStream_t s) {
     if (Wd.N == 0) return;
     if (waves <= 1) {
-        k_obs<1><<<Wd.N, 64, 0, s>>>(P, Wd, st, ist, obs, dbg_idx, hint);
+        sf_launch(k_obs<1>, dim3(Wd.N), dim3(64), 0, s, P, Wd, st, ist, obs, dbg_idx, hint);
     } else if (waves <= 2) {
-        k_obs<2><<<(Wd.N + 1) / 2, 128, 0, s>>>(P, Wd, st, ist, obs, dbg_idx, hint);
+        sf_launch(k_obs<2>, dim3((Wd.N + 1) / 2), dim3(128), 0, s, P, Wd, st, ist, obs, dbg_idx, hint);
     } else {
-        k_obs<4><<<(Wd.N + 3) / 4, 256, 0, s>>>(P, Wd, st, ist, obs, dbg_idx, hint);
+        sf_launch(k_obs<4>, dim3((Wd.N + 3) / 4), dim3(256), 0, s, P, Wd, st, ist, obs, dbg_idx, hint);
     }
 }
 

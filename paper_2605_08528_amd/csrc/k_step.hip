@@ -348,29 +348,6 @@ __device__ __forceinline__ void pair_of(int k, int A, int &i, int &j) {
     j = k - ii * (2 * A - ii - 1) / 2 + ii + 1;
 }
 
-// Quantised three-circle centres (rear, centre, front) of a pose, as
-// (x, y) pairs in units of 2^-10 m: the planar heading comes from the
-// quaternion quantised to 2^-14, so the pair predicate is exact integer
-// arithmetic on both sides of the parity contract.
-__device__ __forceinline__ void circle_centres_q(const DevParams &P, float px, float py, float fqw, float fqx,
-                                                 float fqy, float fqz, int (&cq)[6]) {
-    const long long X = qpos(px), Y = qpos(py);
-    const long long qw = qquat(fqw), qx = qquat(fqx), qy = qquat(fqy), qz = qquat(fqz);
-    const long long hx = (1ll << 28) - 2 * (qy * qy + qz * qz);
-    const long long hy = 2 * (qx * qy + qw * qz);
-    const long long nh = isqrt64(hx * hx + hy * hy);
-    long long ox = 0, oy = 0;
-    // |Qd h| < 2^39 and nh < 2^29: the double quotient truncates to the
-    // exact integer quotient (cheaper than 64-bit division)
-    if (nh > 0) {
-        ox = (long long)((double)((long long)P.Qd * hx) / (double)nh);
-        oy = (long long)((double)((long long)P.Qd * hy) / (double)nh);
-    }
-    cq[0] = (int)(X - ox); cq[1] = (int)(Y - oy);
-    cq[2] = (int)X;        cq[3] = (int)Y;
-    cq[4] = (int)(X + ox); cq[5] = (int)(Y + oy);
-}
-
 // Overlapping circle pairs (i < j, both active) of one world's A vehicles
 // from their quantised centres, compacted by one wave with ballots into
 // `pairs` in canonical (i, j) order, packed i | j << 8 | mask << 16 (mask
@@ -424,8 +401,8 @@ __device__ __forceinline__ int detect_pairs_wave(const DevParams &P, const int (
 // (Sec. "Termination and time-out").
 __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld &Wd, float *st, int *ist, int N,
                                              int n, int w, int i, const float (&dyn)[SF_F_MU], float mu_seen,
-                                             bool coll, bool nan_act, bool ovf, float *reward, uint8_t *done,
-                                             uint8_t *events) {
+                                             bool coll, bool nan_act, bool ovf, bool forbid, float2 p0,
+                                             float *reward, uint8_t *done, uint8_t *events) {
     bool finite = true;
     for (int c = 0; c < SF_F_MU; ++c) {
         st[c * N + n] = dyn[c];
@@ -446,14 +423,18 @@ __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld 
         crash = crash || ((1ll << 28) - 2 * (qx * qx + qy * qy) < 40265318ll);
         if (crash) ev |= SF_EV_CRASH;
     }
+    // road edge touched at the start of the step (shaping on)
+    if (forbid && !(ev & SF_EV_NUMERIC)) ev |= SF_EV_LANE_FORBIDDEN;
     if (nan_act) ev |= SF_EV_NAN_ACTION;
     if (ovf) ev |= SF_EV_CONTACT_OVERFLOW;
+    if (Wd.disp) Wd.disp[n] = make_float2(dyn[SF_F_PX] - p0.x, dyn[SF_F_PY] - p0.y);
     const int ep = ist[SF_I_EP_STEP * N + n] + 1;
     ist[SF_I_EP_STEP * N + n] = ep;
     ist[SF_I_SINCE_SPAWN * N + n] += 1;
     if (ep >= P.max_ep) ev |= SF_EV_TIMEOUT;
-    const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f : 0.f;
-    const bool term = (ev & (SF_EV_GOAL | SF_EV_COLLISION | SF_EV_CRASH)) != 0;
+    const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f
+                  : (ev & SF_EV_LANE_FORBIDDEN) ? -20.f : 0.f;
+    const bool term = (ev & (SF_EV_GOAL | SF_EV_COLLISION | SF_EV_CRASH | SF_EV_LANE_FORBIDDEN)) != 0;
     const bool dn = (term && !(P.flags & SF_INVINCIBLE)) || (ev & (SF_EV_TIMEOUT | SF_EV_NUMERIC));
     reward[n] = r;
     done[n] = dn;
@@ -523,7 +504,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ float s_hx[SF_MAXA], s_hy[SF_MAXA], s_muo[SF_MAXA];
     __shared__ int s_cq[6][SF_MAXA];
     __shared__ int s_act[SF_MAXA];
-    __shared__ uint8_t s_coll[SF_MAXA], s_nan[SF_MAXA];
+    __shared__ uint8_t s_coll[SF_MAXA], s_nan[SF_MAXA], s_forbid[SF_MAXA];
+    __shared__ float2 s_p0[SF_MAXA];     // positions at the start of the control step
     __shared__ float s_om[4 * SF_MAXA];
     __shared__ float s_wf[6][4 * SF_MAXA];
     __shared__ float s_wmu[4 * SF_MAXA];
@@ -546,6 +528,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ __attribute__((aligned(16))) uint16_t s_sur[SUR ? NSW * SUR_ROWS * SUR_LD : 8];
     __shared__ __attribute__((aligned(16))) uint16_t s_surw[SUR ? SURW_BF16 : 8];
     __shared__ __attribute__((aligned(16))) float s_surb[SUR ? SURW_NB : 4];
+    // wheels on the network / on the fallback in this workgroup (one global
+    // update per workgroup at the end instead of one per wave and substep)
+    __shared__ unsigned s_sur_cnt[2];
+    if (SUR && tid < 2) s_sur_cnt[tid] = 0u;
 
     if (SUR) {
         // the network's weights and biases, once per block for all substeps;
@@ -629,6 +615,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 s_tgt[i] = fminf(fmaxf(sa, -P.steer_max), P.steer_max);
                 s_nan[i] = bad;
                 s_coll[i] = 0;
+                s_forbid[i] = Wd.forbid ? Wd.forbid[n] : 0;
+                s_p0[i] = make_float2(s_p[0][i], s_p[1][i]);
             }
             __syncthreads();
 
@@ -735,8 +723,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                                 feat[10] = xd / 2.f;
                                 feat[11] = td / P.tau_drive;
                                 feat[12] = tb / P.tau_bf;
-                                feat[13] = atan2f(R[7], R[8]);
-                                feat[14] = asinf(fminf(fmaxf(-R[6], -1.f), 1.f));
+                                // the slip vector over mu, at most 2 long
+                                float sx = 0.f, sy = 0.f;
+                                if (mu > 0.f) {
+                                    sx = feat[0] / mu;
+                                    sy = vy / D / mu;
+                                    const float L = sqrtf(sx * sx + sy * sy);
+                                    if (L > 2.f) { sx *= 2.f / L; sy *= 2.f / L; }
+                                }
+                                feat[13] = sx;
+                                feat[14] = sy;
                                 feat[15] = om.z / 2.f;
                             } else {
 #pragma unroll
@@ -767,8 +763,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             }
                             // one counter update per wave, not per wheel
                             const unsigned long long bu = __ballot(dom && use), bf = __ballot(dom && !use);
-                            if (lane == 0 && bu) atomicAdd(Su.counts, (unsigned long long)__popcll(bu));
-                            if (lane == 0 && bf) atomicAdd(Su.counts + 1, (unsigned long long)__popcll(bf));
+                            if (lane == 0 && bu) atomicAdd(&s_sur_cnt[0], (unsigned)__popcll(bu));
+                            if (lane == 0 && bf) atomicAdd(&s_sur_cnt[1], (unsigned)__popcll(bf));
                         }
                         if (live) {
                             float Fx = 0.f, Fy = 0.f, Mz = 0.f, om1;
@@ -1081,7 +1077,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 dyn[SF_F_STEER] = s_th[i];
                 dyn[SF_F_STEER_RATE] = s_thd[i];
                 finish_agent(P, Wd, st, ist, N, n, w, i, dyn, s_muo[i], s_coll[i] != 0, s_nan[i] != 0, s_ovf != 0,
-                             reward, done, events);
+                             s_forbid[i] != 0, s_p0[i], reward, done, events);
             }
         } while (0);
         if (!queue) break;
@@ -1089,6 +1085,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
         if (tid == 0) s_item = atomicAdd(queue, 1) + (int)gridDim.x;
         __syncthreads();
         item = s_item;
+    }
+    if (SUR) {
+        __syncthreads();
+        if (tid == 0 && s_sur_cnt[0]) atomicAdd(Su.counts, (unsigned long long)s_sur_cnt[0]);
+        if (tid == 1 && s_sur_cnt[1]) atomicAdd(Su.counts + 1, (unsigned long long)s_sur_cnt[1]);
     }
     // the last block out re-arms the queue for the next launch
     if (queue && tid == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
@@ -1113,19 +1114,19 @@ void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool 
 #define SF_STEP_LAUNCH(B)                                                                                     \
     do {                                                                                                      \
         if (use_sur)                                                                                          \
-            k_step<B, true><<<grid, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,       \
-                                               rec_cnt, rec_cap, items, queue);                               \
+            sf_launch(k_step<B, true>, dim3(grid), dim3(B), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done,  \
+                      events, rec, rec_cnt, rec_cap, items, queue);                                           \
         else                                                                                                  \
-            k_step<B, false><<<grid, B, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec,      \
-                                                rec_cnt, rec_cap, items, queue);                              \
+            sf_launch(k_step<B, false>, dim3(grid), dim3(B), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done, \
+                      events, rec, rec_cnt, rec_cap, items, queue);                                           \
     } while (0)
     if (block <= 64) SF_STEP_LAUNCH(64);
     else if (block <= 128) SF_STEP_LAUNCH(128);
     else if (block <= 192) SF_STEP_LAUNCH(192);
     else if (block <= 256 || use_sur) SF_STEP_LAUNCH(256);
     else
-        k_step<320, false><<<grid, 320, 0, s>>>(P, Wd, Su, st, ist, act, h, S, reward, done, events, rec, rec_cnt,
-                                                rec_cap, items, queue);
+        sf_launch(k_step<320, false>, dim3(grid), dim3(320), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done,
+                  events, rec, rec_cnt, rec_cap, items, queue);
 #undef SF_STEP_LAUNCH
 }
 
@@ -1188,6 +1189,7 @@ __global__ __launch_bounds__(64) void k_step_bicycle(DevParams P, DevWorld Wd, f
     }
     float dyn[SF_F_MU];
     bool bad = false;
+    const float2 p0 = make_float2(st[SF_F_PX * N + n], st[SF_F_PY * N + n]);
     {
         float al = act[2 * (size_t)n], sa = act[2 * (size_t)n + 1];
         if (al != al) { al = 0.f; bad = true; }
@@ -1221,14 +1223,16 @@ __global__ __launch_bounds__(64) void k_step_bicycle(DevParams P, DevWorld Wd, f
         dyn[SF_F_STEER] = delta;
         dyn[SF_F_STEER_RATE] = 0.f;
     }
-    finish_agent(P, Wd, st, ist, N, n, w, i, dyn, 0.f, s_coll[i] != 0, bad, false, reward, done, events);
+    finish_agent(P, Wd, st, ist, N, n, w, i, dyn, 0.f, s_coll[i] != 0, bad, false, Wd.forbid && Wd.forbid[n],
+                 p0, reward, done, events);
 }
 
 void launch_step_bicycle(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act, float dt,
                          float *reward, uint8_t *done, uint8_t *events, uint32_t *rec, int *rec_cnt, int rec_cap,
                          const int4 *items, hipStream_t s) {
     if (Wd.W == 0) return;
-    k_step_bicycle<<<Wd.W, 64, 0, s>>>(P, Wd, st, ist, act, dt, reward, done, events, rec, rec_cnt, rec_cap, items);
+    sf_launch(k_step_bicycle, dim3(Wd.W), dim3(64), 0, s, P, Wd, st, ist, act, dt, reward, done, events, rec, rec_cnt,
+              rec_cap, items);
 }
 
 // ------------------------------------------------------------------ reset

@@ -278,14 +278,18 @@ __global__ __launch_bounds__(256) void k_sur_tile(const float *__restrict__ data
         }
         return;
     }
-    // ---- loss and its gradient dY = 2 (y - t) / (3 batch), kept in L.y
+    // ---- loss and its gradient dY = 2 w (y - t) / (3 batch), kept in L.y;
+    // a sample's weight w = 1 / max(|(t_x, t_y)|, 0.05)^2 makes its squared
+    // error the squared relative force error
     float* g = grad + (size_t)tile * SF_SUR_PARAMS;
     float d2 = 0.f;
     if (tid < TILE * 3) {
         const int r = tid / 3, o = tid % 3;
+        const float den = fmaxf(sqrtf(L.t[r][0] * L.t[r][0] + L.t[r][1] * L.t[r][1]), 0.05f);
+        const float w = 1.f / (den * den);
         const float d = L.t[r][3] != 0.f ? L.y[r][o] - L.t[r][o] : 0.f;
-        d2 = d * d;
-        L.y[r][o] = 2.f * d / (3.f * (float)batch);
+        d2 = w * d * d;
+        L.y[r][o] = 2.f * w * d / (3.f * (float)batch);
     }
     for (int o = 32; o > 0; o >>= 1) d2 += __shfl_xor(d2, o, 64);
     if (lane == 0) L.loss[wv] = d2;

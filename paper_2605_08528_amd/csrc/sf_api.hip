@@ -59,6 +59,18 @@ struct sf_sim {
     int rec_cap = 0;
     int last_substeps = 0;
     int dynamics = SF_DYNAMICS_PHYSICS;   // step backend (sf_set_dynamics)
+    // the paper's observation and late-fusion actor-critic
+    const float *film_dev = nullptr;      // [W] water film depth, or null
+    const uint8_t *pav_dev = nullptr;     // [W] pavement, or null
+    float *full_obs = nullptr;            // [N][SF_FULL_DIM]
+    int *full_counts = nullptr;           // [N][2]
+    float *ac_f32 = nullptr;              // [SF_AC_PARAMS] masters as loaded
+    uint16_t *ac_bf16 = nullptr;          // bf16 weight copies (padded layout)
+    float *ac_mean = nullptr, *ac_value = nullptr, *ac_act = nullptr;  // [N][3], [N], [N][2]
+    bool ac_loaded = false;
+    // dense shaping rewards and the lane-forbidden event (sf_set_shaping)
+    uint8_t *forbid = nullptr;            // [N]
+    float2 *disp = nullptr;               // [N]
     // policy
     int policy_rows = 64;
     float steer_max = 0.5f;
@@ -112,27 +124,38 @@ static hipEvent_t ev_get(sf_sim *s) {
     return e;
 }
 
-// bracket one enqueued kernel with events when profiling
+thread_local LaunchEvents g_launch_ev;
+
+// Time one enqueued kernel when profiling: its launch records the event
+// pair itself (sf_launch); a scope whose launcher enqueued nothing records
+// an empty interval.
 struct ProfScope {
     sf_sim *s;
     int kind;
-    hipEvent_t a = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
     ProfScope(sf_sim *s_, int k) : s(s_), kind(k) {
         if (s->prof) {
             a = ev_get(s);
-            if (a) (void)hipEventRecord(a, s->stream);
+            b = ev_get(s);
+            if (a && b) {
+                g_launch_ev.start = a;
+                g_launch_ev.stop = b;
+            }
         }
     }
     ~ProfScope() {
-        if (s->prof && a) {
-            hipEvent_t b = ev_get(s);
-            if (b) {
-                (void)hipEventRecord(b, s->stream);
-                s->recs.push_back({kind, a, b});
-            } else {
-                s->pool.push_back(a);
-            }
+        if (!a || !b) {
+            if (a) s->pool.push_back(a);
+            if (b) s->pool.push_back(b);
+            return;
         }
+        if (g_launch_ev.start == a) {
+            // not consumed: nothing was launched
+            g_launch_ev = LaunchEvents{};
+            (void)hipEventRecord(a, s->stream);
+            (void)hipEventRecord(b, s->stream);
+        }
+        s->recs.push_back({kind, a, b});
     }
 };
 
@@ -430,6 +453,9 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
             return fail(SF_E_INVALID_ARG, "tri_surface out of range");
     for (int k = 0; k < 2 * P; ++k)
         if (!std::isfinite(d->road_xy[k])) return fail(SF_E_INVALID_ARG, "road_xy not finite");
+    if (d->road_dir)
+        for (long long k = 0; k < 2ll * P; ++k)
+            if (!std::isfinite(d->road_dir[k])) return fail(SF_E_INVALID_ARG, "road_dir not finite");
     for (int k = 0; k < 9 * T; ++k)
         if (!std::isfinite(d->tri_verts[k])) return fail(SF_E_INVALID_ARG, "tri_verts not finite");
     for (int k = 0; k < 5 * E; ++k)
@@ -546,7 +572,7 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     } while (0)
 
     int *aoff, *roff, *toff, *soff, *world_of;
-    float2 *road_xy; int2 *road_q; uint8_t *road_type;
+    float2 *road_xy, *road_dir; int2 *road_q; uint8_t *road_type;
     float *verts; uint8_t *tsurf; float4 *tri;
     float *mu_class, *film = nullptr, *mu; uint8_t *pav = nullptr;
     float *spawn;
@@ -556,6 +582,7 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     ALLOC(sim->agent_world, int4, N);
     ALLOC(sim->agent_grid, GridHdr, N);
     ALLOC(road_xy, float2, P); ALLOC(road_q, int2, P); ALLOC(road_type, uint8_t, P);
+    ALLOC(road_dir, float2, P);
     ALLOC(verts, float, 9 * (size_t)T); ALLOC(tsurf, uint8_t, T); ALLOC(tri, float4, 4 * (size_t)T);
     ALLOC(mu_class, float, (size_t)W * sim->S); ALLOC(mu, float, (size_t)W * sim->S);
     if (d->film_mm) ALLOC(film, float, W);
@@ -568,11 +595,15 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     H2D(soff, d->spawn_offsets, sizeof(int) * (W + 1));
     H2D(road_xy, d->road_xy, sizeof(float) * 2 * (size_t)P);
     H2D(road_type, d->road_type, (size_t)P);
+    if (d->road_dir) H2D(road_dir, d->road_dir, sizeof(float) * 2 * (size_t)P);
+    else if (P) DEV(hipMemsetAsync(road_dir, 0, sizeof(float2) * (size_t)P, st));
     H2D(verts, d->tri_verts, sizeof(float) * 9 * (size_t)T);
     H2D(tsurf, d->tri_surface, (size_t)T);
     H2D(mu_class, d->mu_class, sizeof(float) * (size_t)W * sim->S);
     if (film) H2D(film, d->film_mm, sizeof(float) * W);
     if (pav) H2D(pav, d->pavement, (size_t)W);
+    sim->film_dev = film;
+    sim->pav_dev = pav;
     H2D(spawn, d->spawn, sizeof(float) * 5 * (size_t)E);
 
     DevWorld &Wd = sim->Wd;
@@ -581,7 +612,7 @@ sf_status sf_create(const sf_world_desc *d, const sf_vehicle_params *p, const sf
     Wd.world_of = world_of;
     Wd.agent_world = sim->agent_world;
     Wd.agent_grid = sim->agent_grid;
-    Wd.road_xy = road_xy; Wd.road_q = road_q; Wd.road_type = road_type;
+    Wd.road_xy = road_xy; Wd.road_q = road_q; Wd.road_type = road_type; Wd.road_dir = road_dir;
     Wd.tri = tri; Wd.mu = mu; Wd.spawn = spawn;
     Wd.seed = d->seed;
 
@@ -687,16 +718,20 @@ sf_status sf_info(const sf_sim *sim, int32_t *W, int32_t *N, int32_t *amax) {
 
 // The observation of the current state; with a loaded policy and 16 agents
 // per workgroup, the fused kernel also leaves the next actions in pol_act.
-static void enqueue_obs(sf_sim *sim) {
+// With shaping on it also sets the lane-forbidden flags the next step reads
+// and, right after a step (after_step), adds the dense terms to its rewards.
+static void enqueue_obs(sf_sim *sim, bool after_step = false) {
     ProfScope ps(sim, 2);
+    DevWorld Wd = sim->Wd;
+    Wd.shape_add = after_step && Wd.forbid ? 1 : 0;
     if (sim->policy_loaded && sim->obs_waves == 16) {
         const uint16_t *W1 = sim->pol_bf16, *W2 = W1 + 256 * 256, *W3 = W2 + 256 * 256;
         const float *b1 = sim->pol_f32 + 256 * 256, *b2 = b1 + 256 + 256 * 256, *b3 = b2 + 256 + 2 * 256;
-        launch_obs_policy(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, sim->hint, W1, b1, W2, b2, W3, b3,
+        launch_obs_policy(sim->P_dev, Wd, sim->st, sim->ist, sim->obs, sim->hint, W1, b1, W2, b2, W3, b3,
                           sim->steer_max, sim->pol_act, sim->stream);
         sim->act_valid = true;
     } else {
-        launch_obs(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint,
+        launch_obs(sim->P_dev, Wd, sim->st, sim->ist, sim->obs, nullptr, sim->hint,
                    sim->obs_waves == 16 ? 4 : sim->obs_waves, sim->stream);
         sim->act_valid = false;
     }
@@ -704,7 +739,13 @@ static void enqueue_obs(sf_sim *sim) {
 
 static size_t touch_bytes(const sf_sim *s) { return (size_t)((s->touch_off[SF_T_N] + 31) >> 5) * 4; }
 
+static sf_status enqueue_step(sf_sim *sim, const float *d_actions, float dt, int32_t substeps, bool small_obs);
+
 sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substeps) {
+    return enqueue_step(sim, d_actions, dt, substeps, true);
+}
+
+static sf_status enqueue_step(sf_sim *sim, const float *d_actions, float dt, int32_t substeps, bool small_obs) {
     CHECK_SIM(sim);
     if (substeps < 1 || substeps > SF_MAX_SUBSTEPS) return fail(SF_E_INVALID_ARG, "substeps must be 1..16");
     if (!(dt > 0.f) || !std::isfinite(dt)) return fail(SF_E_INVALID_ARG, "dt must be finite and > 0");
@@ -739,13 +780,148 @@ sf_status sf_step(sf_sim *sim, const float *d_actions, float dt, int32_t substep
         launch_touch_count(sim->touch_bits, sim->touch_off, sim->touch_acc, sim->stream);
         DEV(hipMemsetAsync(sim->touch_bits, 0, touch_bytes(sim), sim->stream));
     }
-    enqueue_obs(sim);
+    if (small_obs || sim->Wd.forbid) {
+        // with shaping on, the actor-critic path runs it too: the dense
+        // rewards and the lane-forbidden flags come from this kernel
+        enqueue_obs(sim, true);
+    } else {
+        sim->act_valid = false;   // the fused kernel's actions belong to the previous state
+    }
     if (sim->touch_on) {
         launch_touch_count(sim->touch_bits, sim->touch_off, sim->touch_acc + SF_T_N, sim->stream);
         sim->touch_steps += 1;
     }
     LAUNCHED();
     sim->last_substeps = sim->dynamics == SF_DYNAMICS_BICYCLE ? 1 : substeps;
+    return SF_OK;
+}
+
+// ------------------------------------------ the paper's observation and network
+static sf_status full_buffers(sf_sim *sim) {
+    if (sim->full_obs) return SF_OK;
+    const size_t N = std::max(sim->N, 1);
+    sim->full_obs = (float *)dev_alloc(sim, sizeof(float) * SF_FULL_DIM * N);
+    sim->full_counts = (int *)dev_alloc(sim, sizeof(int) * 2 * N);
+    if (!sim->full_obs || !sim->full_counts) return fail(SF_E_OUT_OF_MEMORY, "full observation buffers");
+    return SF_OK;
+}
+
+sf_status sf_observe_full(sf_sim *sim, float *d_obs, int32_t *d_counts) {
+    CHECK_SIM(sim);
+    if (sim->N == 0) return SF_OK;
+    if ((d_obs == nullptr) != (d_counts == nullptr)) return fail(SF_E_INVALID_ARG, "give both outputs or neither");
+    sf_status r;
+    if (!d_obs && (r = full_buffers(sim)) != SF_OK) return r;
+    {
+        ProfScope ps(sim, 4);
+        launch_obs_full(sim->P_dev, sim->Wd, sim->st, sim->ist, sim->film_dev, sim->pav_dev,
+                        d_obs ? d_obs : sim->full_obs, d_counts ? d_counts : sim->full_counts, sim->stream);
+    }
+    LAUNCHED();
+    return SF_OK;
+}
+
+sf_status sf_actor_critic_load(sf_sim *sim, const float *h_params, size_t n) {
+    CHECK_SIM(sim);
+    if (!h_params || n != SF_AC_PARAMS) return fail(SF_E_INVALID_ARG, "actor-critic parameters must be SF_AC_PARAMS floats");
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(h_params[k])) return fail(SF_E_INVALID_ARG, "actor-critic parameters must be finite");
+    if (!sim->ac_f32) {
+        const size_t N = std::max(sim->N, 1);
+        sim->ac_f32 = (float *)dev_alloc(sim, sizeof(float) * SF_AC_PARAMS);
+        sim->ac_bf16 = (uint16_t *)dev_alloc(sim, sizeof(uint16_t) * SF_AC_BF16);
+        sim->ac_mean = (float *)dev_alloc(sim, sizeof(float) * 3 * N);
+        sim->ac_value = (float *)dev_alloc(sim, sizeof(float) * N);
+        sim->ac_act = (float *)dev_alloc(sim, sizeof(float) * 2 * N);
+        if (!sim->ac_f32 || !sim->ac_bf16 || !sim->ac_mean || !sim->ac_value || !sim->ac_act)
+            return fail(SF_E_OUT_OF_MEMORY, "actor-critic buffers");
+    }
+    DEV(hipMemcpyAsync(sim->ac_f32, h_params, sizeof(float) * n, hipMemcpyHostToDevice, sim->stream));
+    launch_ac_pack(sim->ac_f32, sim->ac_bf16, sim->stream);
+    LAUNCHED();
+    DEV(hipStreamSynchronize(sim->stream));
+    sim->ac_loaded = true;
+    return SF_OK;
+}
+
+sf_status sf_actor_critic(sf_sim *sim, const float *d_obs, const int32_t *d_counts, int64_t M, float *d_mean,
+                          float *d_value) {
+    CHECK_SIM(sim);
+    if (!sim->ac_loaded) return fail(SF_E_INVALID_ARG, "no actor-critic loaded");
+    if (M < 0 || M > INT32_MAX) return fail(SF_E_INVALID_ARG, "bad row count");
+    if (M > 0 && (!d_obs || !d_counts || !d_mean || !d_value)) return fail(SF_E_INVALID_ARG, "NULL argument");
+    {
+        ProfScope ps(sim, 5);
+        launch_actor_critic(d_obs, d_counts, (int)M, sim->ac_f32, sim->ac_bf16, d_mean, d_value, nullptr,
+                            sim->steer_max, sim->stream);
+    }
+    LAUNCHED();
+    return SF_OK;
+}
+
+sf_status sf_step_actor_critic(sf_sim *sim, float dt, int32_t substeps) {
+    CHECK_SIM(sim);
+    if (!sim->ac_loaded) return fail(SF_E_INVALID_ARG, "no actor-critic loaded");
+    if (substeps < 1 || substeps > SF_MAX_SUBSTEPS || !(dt > 0.f) || !std::isfinite(dt))
+        return fail(SF_E_INVALID_ARG, "bad dt or substeps");
+    sf_status r;
+    if ((r = sf_observe_full(sim, nullptr, nullptr)) != SF_OK) return r;
+    {
+        ProfScope ps(sim, 5);
+        launch_actor_critic(sim->full_obs, sim->full_counts, sim->N, sim->ac_f32, sim->ac_bf16, sim->ac_mean,
+                            sim->ac_value, sim->ac_act, sim->steer_max, sim->stream);
+    }
+    LAUNCHED();
+    return enqueue_step(sim, sim->ac_act, dt, substeps, false);
+}
+
+sf_status sf_actor_critic_read(sf_sim *sim, float *d_mean, float *d_value, float *d_actions, float *d_obs,
+                               int32_t *d_counts) {
+    CHECK_SIM(sim);
+    const size_t N = sim->N;
+    if (N == 0) return SF_OK;
+    if ((d_mean || d_value || d_actions) && !sim->ac_loaded) return fail(SF_E_INVALID_ARG, "no actor-critic loaded");
+    if ((d_obs || d_counts) && !sim->full_obs) return fail(SF_E_INVALID_ARG, "no full observation computed");
+    hipStream_t st = sim->stream;
+    if (d_mean) DEV(hipMemcpyAsync(d_mean, sim->ac_mean, sizeof(float) * 3 * N, hipMemcpyDeviceToDevice, st));
+    if (d_value) DEV(hipMemcpyAsync(d_value, sim->ac_value, sizeof(float) * N, hipMemcpyDeviceToDevice, st));
+    if (d_actions) DEV(hipMemcpyAsync(d_actions, sim->ac_act, sizeof(float) * 2 * N, hipMemcpyDeviceToDevice, st));
+    if (d_obs) DEV(hipMemcpyAsync(d_obs, sim->full_obs, sizeof(float) * SF_FULL_DIM * N, hipMemcpyDeviceToDevice, st));
+    if (d_counts) DEV(hipMemcpyAsync(d_counts, sim->full_counts, sizeof(int) * 2 * N, hipMemcpyDeviceToDevice, st));
+    return SF_OK;
+}
+
+sf_status sf_set_shaping(sf_sim *sim, int32_t on) {
+    CHECK_SIM(sim);
+    if (on != 0 && on != 1) return fail(SF_E_INVALID_ARG, "shaping switch must be 0 or 1");
+    drop_graph(sim);   // a captured graph runs the other observation variant
+    if (!on) {
+        sim->Wd.forbid = nullptr;
+        sim->Wd.disp = nullptr;
+        return SF_OK;
+    }
+    const size_t N = std::max(sim->N, 1);
+    if (!sim->forbid) {
+        sim->forbid = (uint8_t *)dev_alloc(sim, N);
+        sim->disp = (float2 *)dev_alloc(sim, sizeof(float2) * N);
+        if (!sim->forbid || !sim->disp) return fail(SF_E_OUT_OF_MEMORY, "shaping buffers");
+        DEV(hipMemsetAsync(sim->forbid, 0, N, sim->stream));
+        DEV(hipMemsetAsync(sim->disp, 0, sizeof(float2) * N, sim->stream));
+    }
+    DevWorld &Wd = sim->Wd;
+    Wd.forbid = sim->forbid;
+    Wd.disp = sim->disp;
+    Wd.reward_out = sim->reward;
+    Wd.done_out = sim->done;
+    // corridor half-width W / 2 + r of the road-edge time to collision, in
+    // 2^-10 m, from the circle radius r = max(0.45, 0.55 W) in double
+    const double width = sim->P_dev.width;
+    const double cr = std::max(0.45, 0.55 * width);
+    Wd.edge_half_q = (long long)std::nearbyint((0.5 * width + cr) * 1024.0);
+    // the flags of the current state (no rewards added)
+    enqueue_obs(sim);
+    LAUNCHED();
+    DEV(hipStreamSynchronize(sim->stream));
     return SF_OK;
 }
 
@@ -909,6 +1085,32 @@ sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches) {
         total_ms[r.kind] += ms;
         launches[r.kind] += 1;
     }
+    return SF_OK;
+}
+
+// one wave that polls the constant-rate wall clock until `ticks` have passed
+// (at most max_polls reads, so that it ends whatever the clock does)
+__global__ void k_busy(long long ticks, long long max_polls) {
+    const long long t0 = wall_clock64();
+    long long polls = 0;
+    while (wall_clock64() - t0 < ticks && ++polls < max_polls) {
+    }
+}
+
+sf_status sf_profile_calibrate(sf_sim *sim, int32_t n, double us) {
+    CHECK_SIM(sim);
+    if (!sim->prof) return fail(SF_E_INVALID_ARG, "profiling is off");
+    if (n < 1 || n > 10000) return fail(SF_E_INVALID_ARG, "n must be 1..10000");
+    if (!(us >= 1.0 && us <= 10000.0)) return fail(SF_E_INVALID_ARG, "duration must be 1..10000 us");
+    int khz = 0;
+    DEV(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, sim->device));
+    if (khz <= 0) return fail(SF_E_UNSUPPORTED, "no wall clock rate");
+    const long long ticks = (long long)std::llround(us * 1e-3 * (double)khz);
+    for (int k = 0; k < n; ++k) {
+        ProfScope ps(sim, 6);
+        sf_launch(k_busy, dim3(1), dim3(64), 0, sim->stream, ticks, 64 * ticks + 1000);
+    }
+    LAUNCHED();
     return SF_OK;
 }
 
@@ -1519,18 +1721,31 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
     };
     sf_tuning best = *out;
     double ms[3], best_ms[3] = {1e30, 1e30, 1e30};
+    // another step shape or triangle cell replaces the current one only when
+    // its median is this much faster: shapes within timing noise of each
+    // other leave the choice where it was, so that runs repeat it
+    const double margin = 0.97;
     sf_status r = SF_OK;
-    // step shapes (a persistent grid matters only when it is smaller than W)
+    // step shapes (a persistent grid matters only when it is smaller than W),
+    // the handle's current shape first
+    const int g_now = sim->step_grid > 0 && sim->step_grid < sim->W ? sim->step_grid : 0;
+    {
+        sf_tuning t = best;
+        t.step_grid = g_now;
+        r = trial(t, ms);
+        if (r == SF_OK) { best_ms[1] = ms[1]; best.step_grid = g_now; }
+    }
     for (int b : k_step_blocks) {
+        if (r != SF_OK) break;
         for (int g : {0, 1, 2, 4}) {
             if (g > 0 && g * sim->cus >= sim->W) continue;
+            if (b == out->step_block && g * sim->cus == g_now) continue;
             sf_tuning t = best;
             t.step_block = b;
             t.step_grid = g * sim->cus;
             if ((r = trial(t, ms)) != SF_OK) break;
-            if (ms[1] < best_ms[1]) { best_ms[1] = ms[1]; best.step_block = b; best.step_grid = t.step_grid; }
+            if (ms[1] < margin * best_ms[1]) { best_ms[1] = ms[1]; best.step_block = b; best.step_grid = t.step_grid; }
         }
-        if (r != SF_OK) break;
     }
     // policy tiles first (with a plain observation), then the observation
     // shapes, each scored with the policy time it leaves per step (none when
@@ -1570,7 +1785,7 @@ sf_status sf_autotune(sf_sim *sim, float dt, int32_t substeps, int32_t steps, co
         sf_tuning t = best;
         t.tri_cell = tc;
         if ((r = trial(t, ms)) != SF_OK) break;
-        if (ms[1] < best_ms[1]) { best_ms[1] = ms[1]; best.tri_cell = tc; }
+        if (ms[1] < margin * best_ms[1]) { best_ms[1] = ms[1]; best.tri_cell = tc; }
     }
     sim->sur_log = log_keep;
     sim->prof = prof_keep;

@@ -19,8 +19,14 @@ LIB_PATH = os.environ.get("SF_LIBRARY") or os.path.join(HERE, "libsf.so")
 
 SF_INVINCIBLE, SF_AUTO_RESET, SF_RECORD_CONTACTS = 1, 2, 4
 NOALLOC_MAX_SAMPLES = 1 << 18      # SF_NOALLOC_MAX_SAMPLES of include/sf.h
+FULL_EGO, FULL_ROAD_K, FULL_NEIGH_K = 11, 350, 24
+FULL_DIM = FULL_EGO + 5 * FULL_ROAD_K + 7 * FULL_NEIGH_K
+AC_BODY = (11 * 64 + 64 + 64 * 64 + 64 + 5 * 96 + 96 + 96 * 96 + 96 + 7 * 96 + 96 + 96 * 96 + 96
+           + 256 * 128 + 128 + 128 * 64 + 64)
+AC_PARAMS = 2 * AC_BODY + 3 * 64 + 3 + 3 + 64 + 1
 EV_GOAL, EV_COLLISION, EV_CRASH, EV_TIMEOUT, EV_NUMERIC, EV_NAN_ACTION = 1, 2, 4, 8, 16, 32
 EV_CONTACT_OVERFLOW = 64
+EV_LANE_FORBIDDEN = 128
 MAX_CONTACTS_PER_WORLD = 512
 NF, NI, OBS_DIM = 24, 4, 256
 FIELDS = ["px", "py", "pz", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "wx", "wy", "wz",
@@ -55,6 +61,7 @@ class WorldDesc(C.Structure):
         ("film_mm", C.c_void_p), ("pavement", C.c_void_p),
         ("spawn_offsets", C.c_void_p), ("spawn", C.c_void_p),
         ("seed", C.c_uint64),
+        ("road_dir", C.c_void_p),
     ]
 
 
@@ -75,7 +82,7 @@ class Options(C.Structure):
 SUR_INPUTS, SUR_PARAMS, SUR_SAMPLE = 16, 35587, 20
 # piecewise-constant Adam learning rates (lr, steps) used to fit the tire
 # network; 40k steps of 8192 samples take about 3 s on one MI355X
-SUR_SCHEDULE = ((2e-3, 15000), (1e-3, 10000), (3e-4, 10000), (1e-4, 5000))
+SUR_SCHEDULE = ((2e-3, 40000), (1e-3, 30000), (3e-4, 20000), (1e-4, 10000))
 
 
 class SurTrainOpts(C.Structure):
@@ -124,6 +131,13 @@ def lib():
         L.sf_road_touch.argtypes = [vp, i32]
         L.sf_road_touch_read.argtypes = [vp, vp, vp, C.POINTER(i32)]
         L.sf_set_dynamics.argtypes = [vp, i32]
+        L.sf_set_shaping.argtypes = [vp, i32]
+        L.sf_profile_calibrate.argtypes = [vp, i32, C.c_double]
+        L.sf_observe_full.argtypes = [vp, vp, vp]
+        L.sf_actor_critic_load.argtypes = [vp, vp, C.c_size_t]
+        L.sf_actor_critic.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        L.sf_step_actor_critic.argtypes = [vp, C.c_float, i32]
+        L.sf_actor_critic_read.argtypes = [vp, vp, vp, vp, vp, vp]
         L.sf_set_triangle_friction.argtypes = [vp, vp]
         L.sf_state_bytes.argtypes = [vp]
         L.sf_state_bytes.restype = C.c_size_t
@@ -159,7 +173,9 @@ def lib():
         L.sf_last_error.restype = C.c_char_p
         for name in ("sf_default_params", "sf_default_options", "sf_create", "sf_destroy", "sf_info",
                      "sf_step", "sf_observe", "sf_output_ptrs", "sf_reset", "sf_contact_overflows",
-                     "sf_road_touch", "sf_road_touch_read", "sf_set_dynamics", "sf_set_triangle_friction",
+                     "sf_road_touch", "sf_road_touch_read", "sf_set_dynamics", "sf_set_shaping", "sf_profile_calibrate", "sf_set_triangle_friction",
+                     "sf_observe_full", "sf_actor_critic_load", "sf_actor_critic", "sf_step_actor_critic",
+                     "sf_actor_critic_read",
                      "sf_get_state",
                      "sf_set_state", "sf_get_contacts", "sf_debug_raycast", "sf_debug_obs_indices",
                      "sf_policy_load", "sf_policy_act", "sf_step_policy", "sf_graph_capture",
@@ -237,6 +253,8 @@ class Sim:
         d.spawn_offsets = arr(worlds.spawn_offsets, np.int32)
         d.spawn = arr(worlds.spawn, np.float32)
         d.seed = int(worlds.seed)
+        if getattr(worlds, "road_dir", None) is not None:
+            d.road_dir = arr(worlds.road_dir, np.float32)
         o = Options()
         check(L.sf_default_options(C.byref(o)), "sf_default_options")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -336,9 +354,55 @@ class Sim:
               "sf_road_touch_read")
         return items.reshape(2, 6).astype(np.int64), nbytes.astype(np.int64), steps.value
 
+    # the paper's observation and network ---------------------------------
+    def observe_full(self):
+        """(obs [N, 1929], counts [N, 2]) CUDA tensors of the current state."""
+        t = self.torch
+        dev = t.device("cuda", t.cuda.current_device())
+        obs = t.empty((self.N, FULL_DIM), dtype=t.float32, device=dev)
+        cnt = t.empty((self.N, 2), dtype=t.int32, device=dev)
+        check(lib().sf_observe_full(self.h, _tptr(obs), _tptr(cnt)), "sf_observe_full")
+        return obs, cnt
+
+    def actor_critic_load(self, params) -> None:
+        a = np.ascontiguousarray(params, np.float32)
+        assert a.size == AC_PARAMS
+        check(lib().sf_actor_critic_load(self.h, _ptr(a), a.size), "sf_actor_critic_load")
+
+    def actor_critic(self, obs, counts):
+        """(mean [M, 3], value [M]) for CUDA rows obs [M, 1929], counts [M, 2]."""
+        t = self.torch
+        M = obs.shape[0]
+        mean = t.empty((M, 3), dtype=t.float32, device=obs.device)
+        value = t.empty(M, dtype=t.float32, device=obs.device)
+        check(lib().sf_actor_critic(self.h, _tptr(obs.contiguous()), _tptr(counts.contiguous()), M, _tptr(mean),
+                                    _tptr(value)), "sf_actor_critic")
+        return mean, value
+
+    def step_actor_critic(self, dt: float, substeps: int) -> None:
+        check(lib().sf_step_actor_critic(self.h, float(dt), int(substeps)), "sf_step_actor_critic")
+
+    def actor_critic_read(self):
+        """Copies of the handle's last actor-critic outputs and observation:
+        (mean [N, 3], value [N], actions [N, 2], obs [N, 1929], counts [N, 2])."""
+        t = self.torch
+        dev = t.device("cuda", t.cuda.current_device())
+        mean = t.empty((self.N, 3), dtype=t.float32, device=dev)
+        value = t.empty(self.N, dtype=t.float32, device=dev)
+        act = t.empty((self.N, 2), dtype=t.float32, device=dev)
+        obs = t.empty((self.N, FULL_DIM), dtype=t.float32, device=dev)
+        cnt = t.empty((self.N, 2), dtype=t.int32, device=dev)
+        check(lib().sf_actor_critic_read(self.h, _tptr(mean), _tptr(value), _tptr(act), _tptr(obs), _tptr(cnt)),
+              "sf_actor_critic_read")
+        return mean, value, act, obs, cnt
+
     def set_dynamics(self, mode: str) -> None:
         """'physics' (the articulated vehicle) or 'bicycle' (kinematic model)."""
         check(lib().sf_set_dynamics(self.h, {"physics": 0, "bicycle": 1}[mode]), "sf_set_dynamics")
+
+    def set_shaping(self, on: bool) -> None:
+        """Dense shaping rewards and the lane-forbidden termination on or off."""
+        check(lib().sf_set_shaping(self.h, 1 if on else 0), "sf_set_shaping")
 
     def set_triangle_friction(self, scale) -> None:
         """Friction factor per road triangle [T] (None: back to 1)."""
@@ -412,11 +476,17 @@ class Sim:
         check(lib().sf_profile(self.h, int(bool(enable))), "sf_profile")
 
     def profile_read(self):
-        """{kernel: (total_ms, launches)} for policy, step, obs, reset."""
-        ms = np.zeros(4, np.float64)
-        n = np.zeros(4, np.int32)
+        """{kernel: (total_ms, launches)} for policy, step, obs, reset, the
+        paper-shaped observation, the actor-critic and the clock kernels."""
+        ms = np.zeros(7, np.float64)
+        n = np.zeros(7, np.int32)
         check(lib().sf_profile_read(self.h, _ptr(ms), _ptr(n)), "sf_profile_read")
-        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(("policy", "step", "obs", "reset"))}
+        return {k: (float(ms[i]), int(n[i]))
+                for i, k in enumerate(("policy", "step", "obs", "reset", "obs_full", "actor_critic", "clock"))}
+
+    def profile_calibrate(self, n: int = 20, us: float = 50.0) -> None:
+        """n wall-clock kernels of `us` microseconds timed like the others."""
+        check(lib().sf_profile_calibrate(self.h, int(n), float(us)), "sf_profile_calibrate")
 
     # learned tire surrogate --------------------------------------------
     def sur_log(self, capacity: int) -> None:

@@ -158,7 +158,7 @@ def test_gradient_matches_oracle(O, torch):
     assert np.array_equal(lo, d[:, :16].min(0)) and np.array_equal(hi, d[:, :16].max(0))
     loss_g, g = sim.sur_gradient(dd)
     Ws, bs = layers(P0)
-    loss_o, gW, gb = O.mlp_mse_grad(Ws, bs, d[:, :16], d[:, 16:19])
+    loss_o, gW, gb = O.mlp_mse_grad(Ws, bs, d[:, :16], d[:, 16:19], row_weight=O.force_weights(d[:, 16:19]))
     assert abs(loss_g - loss_o) <= 1e-4 * loss_o, (loss_g, loss_o)
     gWg, gbg = layers(g.astype(np.float64))
     for l in range(4):
@@ -201,8 +201,16 @@ def test_predict_matches_oracle(O, torch):
     O.set_bf16(True)
     yo = O.mlp_forward(Ws, bs, d[:, :16])
     err = np.abs(y - yo).max()
-    print(f"predict: worst |gpu - oracle| {err:.3g} over outputs of scale {np.abs(yo).max():.3g}")
-    assert err <= 1e-3 * max(1.0, float(np.abs(yo).max()))
+    scale = max(1.0, float(np.abs(yo).max()))
+    rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    print(f"predict: worst |gpu - oracle| {err:.3g} over outputs of scale {scale:.3g}, relative norm {rel:.3g}, "
+          f"{int(np.sum(np.abs(y - yo) > 1e-3 * scale))} of {y.size} outputs beyond 1e-3")
+    # both sides round inputs, weights and hidden activations to bf16 at the
+    # same points; a hidden value that lands on a rounding boundary under the
+    # fp32 (GPU) or fp64 (oracle) sum flips by one bf16 ulp (2^-8 relative),
+    # which moves an output by up to a few 2^-8 of its scale
+    assert rel <= 1e-3
+    assert err <= 4e-3 * scale
     sim.close()
 
 

@@ -618,6 +618,30 @@ def test_mlp_matches_torch_float64(oracle_mod):
     for l in range(3):
         assert np.allclose(gW[l], tW[l].grad.numpy(), rtol=1e-10, atol=1e-13)
         assert np.allclose(gb[l], tb[l].grad.numpy(), rtol=1e-10, atol=1e-13)
+    # row-weighted: (1 / (M n_out)) sum_r w_r sum_o (y - t)^2, the tire
+    # model's weights 1 / max(|(t_x, t_y)|, 0.05)^2 (targets near zero too)
+    t[:5, :2] = 0.01 * t[:5, :2]
+    wr = O.force_weights(t)
+    assert np.allclose(wr, 1.0 / np.maximum(np.hypot(t[:, 0].astype(np.float64), t[:, 1]), 0.05) ** 2)
+    assert wr[:5].max() <= 400.0 + 1e-9 and wr.min() > 0
+    O.set_bf16(False)
+    try:
+        lw, gWw, gbw = O.mlp_mse_grad(Ws, bs, x, t, row_weight=wr)
+    finally:
+        O.set_bf16(True)
+    for g in tW + tb:
+        g.grad = None
+    h = torch.tensor(x, dtype=torch.float64)
+    for l in range(3):
+        h = torch.nn.functional.linear(h, tW[l], tb[l])
+        if l < 2:
+            h = torch.relu(h)
+    Lw = torch.mean(torch.tensor(wr)[:, None] * (h - torch.tensor(t, dtype=torch.float64)) ** 2)
+    Lw.backward()
+    assert abs(lw - Lw.item()) <= 1e-12 * max(1.0, abs(Lw.item()))
+    for l in range(3):
+        assert np.allclose(gWw[l], tW[l].grad.numpy(), rtol=1e-10, atol=1e-12)
+        assert np.allclose(gbw[l], tb[l].grad.numpy(), rtol=1e-10, atol=1e-12)
 
 
 def test_mlp_bf16_rounding_points(oracle_mod):
@@ -721,8 +745,13 @@ def test_surrogate_features_closed_form(oracle_mod):
         wx_, wy_ = math.cos(d) * bx + math.sin(d) * by, -math.sin(d) * bx + math.cos(d) * by
         D = max(abs(wx_), p["v_eps"])
         td = 0.5 * p["tau_drive"] if wh < 2 else 0.0
-        want = [(r * (vx / r) - wx_) / D, math.atan(wy_ / D), mg4 / 4000.0, 0.9, vx / 30.0, 0.0,
-                wx_ / 30.0, wy_ / 5.0, d, sag / 0.2, 0.0, td / p["tau_drive"], 0.0, 0.0, 0.0, wz / 2.0]
+        kap = (r * (vx / r) - wx_) / D
+        sx, sy = kap / 0.9, wy_ / D / 0.9
+        L = math.hypot(sx, sy)
+        if L > 2.0:
+            sx, sy = 2.0 * sx / L, 2.0 * sy / L
+        want = [kap, math.atan(wy_ / D), mg4 / 4000.0, 0.9, vx / 30.0, 0.0,
+                wx_ / 30.0, wy_ / 5.0, d, sag / 0.2, 0.0, td / p["tau_drive"], 0.0, sx, sy, wz / 2.0]
         assert rec[wh, 19] == 1.0
         assert np.allclose(rec[wh, :16], want, rtol=2e-6, atol=2e-6), (wh, rec[wh, :16], want)
         Fx, Fy, Mz, _ = O.tire(p, H, mg4, 0.9, wx_, wy_, vx / r, td, 0.0)
@@ -731,9 +760,40 @@ def test_surrogate_features_closed_form(oracle_mod):
     assert rec[0, 0] != rec[1, 0] and rec[0, 7] != rec[2, 7]   # wheels are told apart
 
 
+def test_surrogate_features_normalised_slip_clipped(oracle_mod):
+    """On ice (mu 0.1), sliding sideways at 0.3 m/s with the rear wheels spinning
+    30 % fast:
+    the friction-normalised slip vector is longer than 2 and is shortened to
+    length 2 along its own direction; on a dry road the same kinematics give
+    the unclipped vector (slip ratio / mu, tan(slip angle) / mu)."""
+    O = oracle_mod
+    for mu in (0.1, 0.9):
+        o, p = _settled(O, 0.0, mu=mu)
+        r = f32(p["wheel_radius"])
+        _drive(o, 0.0, 10.0, 0.3, 0.0, 10.0 / r)
+        f, k = o.get_state()
+        f[OM0 + 2:OM0 + 4, 0] = 13.0 / r
+        o.set_state(f, k)
+        o.record_samples(True)
+        o.step(zeros(1), H, 1)
+        rec = o.samples()[0]
+        for wh in range(4):
+            assert rec[wh, 19] == 1.0
+            kap, tan_a = float(rec[wh, 0]), math.tan(float(rec[wh, 1]))
+            raw = np.array([kap / mu, tan_a / mu])
+            L = float(np.hypot(*raw))
+            want = raw if L <= 2.0 else 2.0 * raw / L
+            assert np.allclose(rec[wh, 13:15], want, atol=2e-6), (mu, wh, rec[wh, 13:15], want)
+            if mu == 0.1 and wh >= 2:
+                assert L > 2.0 and abs(math.hypot(*rec[wh, 13:15]) - 2.0) < 1e-6
+            if mu == 0.9:
+                assert L < 2.0
+
+
 def test_surrogate_features_attitude(oracle_mod):
-    """Rolled and pitched body: the roll, pitch and camber inputs are the
-    body's Euler angles and asin(axle . n) of the tilted axle."""
+    """Rolled and pitched body: the camber input is asin(axle . n) of the
+    tilted axle; the friction-normalised slip inputs are the slip ratio and
+    tan(slip angle) over mu, shortened to length 2."""
     O = oracle_mod
     o, p = _settled(O, 0.0)
     roll, pitch = 0.03, -0.02
@@ -748,7 +808,12 @@ def test_surrogate_features_attitude(oracle_mod):
     loaded = rec[:, 19] == 1.0
     assert loaded.sum() >= 2
     for wh in np.nonzero(loaded)[0]:
-        assert abs(rec[wh, 13] - roll) < 1e-6 and abs(rec[wh, 14] - pitch) < 1e-6
+        kap, tan_a = float(rec[wh, 0]), math.tan(float(rec[wh, 1]))
+        sx, sy = kap / 0.9, tan_a / 0.9
+        L = math.hypot(sx, sy)
+        if L > 2.0:
+            sx, sy = 2.0 * sx / L, 2.0 * sy / L
+        assert abs(rec[wh, 13] - sx) < 1e-6 and abs(rec[wh, 14] - sy) < 1e-6
         assert abs(rec[wh, 5] - math.asin(math.cos(pitch) * math.sin(roll))) < 1e-6
 
 
