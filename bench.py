@@ -71,19 +71,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(kernel: str) -> str:
-    """Hash of the sources a kernel is built from (its .hip file and the
-    shared device header): recorded traffic counters only count while this
-    matches."""
-    import hashlib
-    csrc = os.path.join(ROOT, "paper_2605_08528_amd", "csrc")
-    files = {"k_obs": "k_obs.hip", "k_step": "k_step.hip", "k_policy": "k_policy.hip"}[kernel]
-    h = hashlib.sha256()
-    for f in (files, "sf_dev.h"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def recorded_traffic(kernel: str, launch_name: str, n_agents: int):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     record (scaled by the copy-kernel calibration), or None when the kernel
@@ -94,6 +81,7 @@ def recorded_traffic(kernel: str, launch_name: str, n_agents: int):
         return None
     rec = json.load(open(path))
     k = rec.get("launches", {}).get(launch_name)
+    from paper_2605_08528_amd.profile_summary import kernel_source_hash
     if not k or k.get("kernel") != kernel or k.get("source_hash") != kernel_source_hash(kernel) \
             or k.get("agents") != n_agents:
         return None
@@ -150,13 +138,34 @@ def cpu_baseline(worlds, prm, dt, S, policy, seconds, max_worlds=16):
                       f"{n1} on one thread; FP64 brute force"}
 
 
-def trajectory_error(sim, torch, sf, dt, S, steps):
+def _heading(f):
+    hx = 1 - 2 * (f[5] ** 2 + f[6] ** 2)
+    hy = 2 * (f[4] * f[5] + f[3] * f[6])
+    L = np.maximum(np.hypot(hx, hy), 1e-6)
+    return hx / L, hy / L
+
+
+def trajectory_error(sim, torch, sf, dt, S, steps, v0=None, driving=False):
     """Position difference between the plain and the network step after
-    `steps` control steps from the same state under the same seeded
-    open-loop actions, over agents that neither run reset."""
+    `steps` control steps from the same state, over agents that neither
+    run reset.  Optionally every vehicle first moves along its heading at
+    v0 m/s; actions are the seeded random ones, or with `driving` a steady
+    throttle of 0.35 and a slow steering sine (3 s period)."""
     from paper_2605_08528_amd import inputs as I
     f0, k0 = sim.get_state()
-    acts = [torch.from_numpy(I.actions(7, t, sim.N)).cuda() for t in range(steps)]
+    if v0 is not None:
+        hx, hy = _heading(f0)
+        f0[7], f0[8] = v0 * hx, v0 * hy
+        f0[13:17] = v0 / 0.35
+    if driving:
+        acts = []
+        for t in range(steps):
+            a = np.empty((sim.N, 2), np.float32)
+            a[:, 0] = 0.35
+            a[:, 1] = 0.1 * np.sin(2.0 * np.pi * t * dt / 3.0)
+            acts.append(torch.from_numpy(a).cuda())
+    else:
+        acts = [torch.from_numpy(I.actions(7, t, sim.N)).cuda() for t in range(steps)]
     ends = []
     for on in (False, True):
         sim.set_state(f0, k0)
@@ -166,48 +175,87 @@ def trajectory_error(sim, torch, sf, dt, S, steps):
         torch.cuda.synchronize()
         ends.append(sim.get_state())
     sim.sur_enable(False)
-    sim.set_state(f0, k0)
     (fa, ka), (fb, kb) = ends
     same = (ka[3] == k0[3]) & (kb[3] == k0[3]) & (k0[0] == 1)   # same episode, active at the start
     d = np.hypot(fa[0] - fb[0], fa[1] - fb[1])[same]
     moved = np.hypot(fa[0] - f0[0], fa[1] - f0[1])[same]
-    return {"agents": int(same.sum()), "mean_m": float(d.mean()), "p95_m": float(np.percentile(d, 95)),
-            "max_m": float(d.max()), "mean_path_m": float(moved.mean())}
+    return {"agents": int(same.sum()), "of": int(sim.N), "mean_m": float(d.mean()),
+            "p95_m": float(np.percentile(d, 95)), "max_m": float(d.max()), "mean_path_m": float(moved.mean()),
+            "actions": "throttle 0.35, steering 0.1 sin(2 pi t / 3 s)" if driving else "seeded uniform random",
+            "initial_speed": v0}
 
 
-def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
-    """Log training samples from the plain policy-driven step, train the
-    tire network on the GPU, then time the same control step with the
-    network inside (wheels outside its envelope or failing the residual
-    checks fall back to the plain tire model)."""
+def log_tire_samples(torch, sf, I, worlds, steps, seed, reinit=40, dt=1.0 / 30.0, S=4):
+    """Samples of the plain tire model (inputs and outputs of every loaded
+    wheel at |v_x| >= 3 m/s) from `steps` control steps of seeded random
+    actions on `worlds`; every `reinit` steps every vehicle is launched
+    again along its heading at U[3, 30] m/s with its wheels rolling."""
+    sim = sf.Sim(worlds, dict(I.VEHICLE_DEFAULTS), flags=sf.SF_INVINCIBLE | sf.SF_AUTO_RESET)
     N = sim.N
-    cap = log_steps * S * 4 * N
-    t0 = time.perf_counter()
+    cap = steps * S * 4 * N
     sim.sur_log(cap)
-    for _ in range(log_steps):
-        sim.step_policy(dt, S)
+    for t in range(steps):
+        if t % reinit == 0:
+            f, k = sim.get_state()
+            spd = I.speeds(seed, t, N)
+            hx, hy = _heading(f)
+            f[7], f[8] = spd * hx, spd * hy
+            f[13:17] = spd / 0.35
+            sim.set_state(f, k)
+        sim.step(torch.from_numpy(I.actions(seed, t, N)).cuda(), dt, S)
     data, n = sim.sur_collect(cap)
     sim.sur_log(0)
     torch.cuda.synchronize()
-    t_log = time.perf_counter() - t0
-    M = data.shape[0]
-    split = int(0.9 * M)
-    train, test = data[:split], data[split:]
+    sim.close()
+    return data
+
+
+def force_errors(sim, data):
+    """Relative force error statistics of the current network on `data`."""
+    e = sim.sur_errors(data).cpu().numpy().astype(np.float64)
+    y = sim.sur_predict(data).cpu().numpy().astype(np.float64)
+    t = data[:, 16:18].cpu().numpy().astype(np.float64)
+    F = np.hypot(t[:, 0], t[:, 1])
+    dF = np.hypot(y[:, 0] - t[:, 0], y[:, 1] - t[:, 1])
+    return {"mean": float(e.mean()), "p50": float(np.percentile(e, 50)), "p95": float(np.percentile(e, 95)),
+            "p99": float(np.percentile(e, 99)), "max": float(e.max()),
+            "aggregate": float(dF.sum() / max(F.sum(), 1e-30)), "samples": int(len(e))}
+
+
+def surrogate_leg(sim, torch, sf, I, stream, dt, S, steps, warmup, train_samples, main_log_steps):
+    """The learned tire model: trained on samples of the plain step logged
+    from the tire-sampling workload (1024 worlds x 16 agents, friction
+    classes down to 0.001, random actions, launches at 3-30 m/s), judged on
+    1 M samples of another run of it and on samples of the benchmark's own
+    policy-driven workload; then the same control step with the network
+    inside (wheels outside its envelope or failing the residual checks fall
+    back to the plain tire model), timed like the plain step."""
+    N = sim.N
     t0 = time.perf_counter()
+    train = log_tire_samples(torch, sf, I, I.tire_sampling(seed=101), 80, 101)[:train_samples]
+    held = log_tire_samples(torch, sf, I, I.tire_sampling(seed=202), 10, 202)[:1_000_000]
+    cap = main_log_steps * S * 4 * N
+    sim.sur_log(cap)
+    for _ in range(main_log_steps):
+        sim.step_policy(dt, S)
+    held_main, _ = sim.sur_collect(cap)
+    sim.sur_log(0)
+    torch.cuda.synchronize()
+    t_log = time.perf_counter() - t0
     sim.sur_train(train, steps=0, init_seed=1, set_envelope=True)
-    untrained = sim.sur_evaluate(test)
+    untrained = force_errors(sim, held)
     t0 = time.perf_counter()
     loss = sim.sur_fit(train)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     n_adam = sum(k for _, k in sf.SUR_SCHEDULE)
-    err_mean, err_p95 = sim.sur_evaluate(test)
-    errs = sim.sur_errors(test).cpu().numpy().astype(np.float64)
-    err_q = {"p50": float(np.percentile(errs, 50)), "p99": float(np.percentile(errs, 99)),
-             "max": float(errs.max())}
-    log(f"surrogate: {M} samples logged in {t_log:.1f} s, {n_adam} Adam steps in {t_train:.1f} s, "
-        f"held-out force error mean {err_mean:.4f} p95 {err_p95:.4f} (untrained {untrained[0]:.4f})")
-    del data, train, test
+    err = force_errors(sim, held)
+    err_main = force_errors(sim, held_main)
+    log(f"surrogate: {train.shape[0]} training samples ({t_log:.1f} s of logging), {n_adam} Adam steps in "
+        f"{t_train:.1f} s; held-out force error mean {err['mean']:.4f} p99 {err['p99']:.4f}; on the "
+        f"benchmark workload mean {err_main['mean']:.4f} (untrained {untrained['mean']:.3f})")
+    n_train = int(train.shape[0])
+    del train, held, held_main
     sim.sur_enable(True)
     for _ in range(warmup):
         sim.step_policy(dt, S)
@@ -218,8 +266,7 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     for _ in range(steps):
         sim.step_policy(dt, S)
     torch.cuda.synchronize()
-    prof = sim.profile_read()
-    sim.profile(False)
+    ev, fixed = read_profile(sim)
     used, fb = sim.sur_counts(reset=True)
     G = graph_len(steps)
     sim.graph_capture(G, dt, S)
@@ -234,7 +281,7 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
     ms = e0.elapsed_time(e1)
     sim.sur_enable(False)     # drops the graph
     casps = N * steps / (ms / 1e3)
-    step_us = 1e3 * prof["step"][0] / max(1, prof["step"][1])
+    step_us = kernel_us(ev, fixed)["step"]
     # the network runs on every in-domain wheel-substep (fallback decided after)
     net_tflops = (used + fb) * SUR_FLOP_PER_EVAL / (steps * step_us * 1e-6) / 1e12
     train_tflops = n_adam * 8192 * SUR_TRAIN_FLOP_PER_SAMPLE / t_train / 1e12
@@ -247,14 +294,14 @@ def surrogate_leg(sim, torch, sf, stream, dt, S, steps, warmup, log_steps):
         "step_kernel_us": step_us,
         "network_tflops_in_step": net_tflops, "train_tflops": train_tflops,
         "network_share": used / max(1, used + fb), "wheel_substeps_in_domain": used + fb,
-        "force_error_mean": err_mean, "force_error_p50": err_q["p50"], "force_error_p95": err_p95,
-        "force_error_p99": err_q["p99"], "force_error_max": err_q["max"], "force_error_untrained": untrained[0],
-        "fallback_rate": fb / max(1, used + fb),
-        "train_samples": int(split), "test_samples": int(M - split), "adam_steps": n_adam,
-        "batch": 8192, "train_seconds": t_train, "last_loss": loss,
+        "force_error_heldout": err, "force_error_benchmark_workload": err_main,
+        "force_error_untrained": untrained["mean"],
+        "fallback_rate": fb / max(1, used + fb), "train_samples": n_train,
+        "adam_steps": n_adam, "batch": 8192, "train_seconds": t_train, "last_loss": loss,
         "trajectory_error_200": traj,
-        "note": "force error = |d(Fx,Fy)| / max(|(Fx,Fy)|, 0.05 mu Fz) against the plain tire model "
-                "on held-out samples (the last 10% of the logged steps)",
+        "note": "force error = |d(Fx,Fy)| / max(|(Fx,Fy)|, 0.05 mu Fz) per sample against the plain tire "
+                "model; aggregate = sum |d(Fx,Fy)| / sum |(Fx,Fy)|; training: samples of 80 control steps "
+                "of the tire-sampling workload (seed 101), held out: 1 M samples of another run (seed 202)",
     }
 
 
@@ -276,8 +323,7 @@ def config_leg(name, torch, sf, I, stream, steps, sur_params, tune_steps):
         for _ in range(steps):
             sim.step_policy(dt, S)
         torch.cuda.synchronize()
-        prof = sim.profile_read()
-        sim.profile(False)
+        ev, fixed = read_profile(sim)
         G = graph_len(steps)
         sim.graph_capture(G, dt, S)
         sim.graph_launch()
@@ -293,28 +339,93 @@ def config_leg(name, torch, sf, I, stream, steps, sur_params, tune_steps):
                "ms_per_step": ms / steps,
                "launch_shapes": {k: tuning[k] for k in ("step_block", "step_grid", "obs_waves", "policy_rows",
                                                           "grid_cell", "tri_cell")},
-               "kernels_us": {k: 1e3 * t / c for k, (t, c) in prof.items() if c}}
+               "kernels_us": kernel_us(ev, fixed), "event_fixed_us": fixed}
         if "step" in out["kernels_us"]:
             out["step_algorithmic_gbs"] = step_bytes(N) / (out["kernels_us"]["step"] * 1e-6) / 1e9
         if sur_params is not None:
+            # the same control step with the network inside, timed the same way
             sim.sur_set(*sur_params)
             sim.sur_enable(True)
             for _ in range(20):
                 sim.step_policy(dt, S)
             sim.sur_counts(reset=True)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            sim.graph_capture(G, dt, S)
+            sim.graph_launch()
             torch.cuda.synchronize()
-            e0.record(stream)
-            for _ in range(steps):
-                sim.step_policy(dt, S)
-            e1.record(stream)
+            g0.record(stream)
+            for _ in range(steps // G):
+                sim.graph_launch()
+            g1.record(stream)
             torch.cuda.synchronize()
+            ms_s = g0.elapsed_time(g1)
             used, fb = sim.sur_counts(reset=True)
-            out["surrogate"] = {"casps_eager": N * steps / (e0.elapsed_time(e1) / 1e3),
+            sim.sur_enable(False)
+            out["surrogate"] = {"casps": N * steps / (ms_s / 1e3), "ms_per_step": ms_s / steps,
                                 "network_share": used / max(1, used + fb)}
+            if name == "dense4096x32":
+                # 200 control steps of driving from 10 m/s: plain against network
+                out["surrogate"]["trajectory_error_200"] = trajectory_error(sim, torch, sf, dt, S, 200, v0=10.0,
+                                                                            driving=True)
         sim.close()
     log(f"{name}: {N} agents, graph {out['ms_per_step']:.4f} ms/step, {out['casps']:.4g} CASPS"
-        + (f"; surrogate eager {out['surrogate']['casps_eager']:.4g} CASPS" if "surrogate" in out else ""))
+        + (f"; surrogate {out['surrogate']['casps']:.4g} CASPS" if "surrogate" in out else ""))
+    return out
+
+
+def ac_flop(counts: np.ndarray) -> float:
+    """Algorithmic FLOP of the late-fusion actor-critic on rows with these
+    valid (road, neighbour) counts: both networks, every layer, no padding."""
+    nr = counts[:, 0].astype(np.float64)
+    nv = counts[:, 1].astype(np.float64)
+    per_net = (11 * 64 + 64 * 64 + nr * (5 * 96 + 96 * 96) + nv * (7 * 96 + 96 * 96) + 256 * 128 + 128 * 64)
+    return float(2.0 * (2 * per_net.sum() + len(nr) * 64 * (3 + 1)))
+
+
+def full_obs_leg(torch, sf, I, stream, workload, steps, seed=0):
+    """The paper-shaped observation (1929 floats per agent) and the
+    late-fusion actor-critic (seeded random weights) driving the physics
+    step: control steps timed with HIP events around the whole sequence
+    (eager launches), per-kernel durations from a profiled pass, the
+    network's rate in algorithmic FLOP against the bf16 matrix-core peak and
+    the observation's in algorithmic bytes against the HBM peak."""
+    w = I.workload(workload, seed=seed)
+    dt, S = I.TIMING[workload]
+    with torch.cuda.stream(stream):
+        sim = sf.Sim(w, dict(I.VEHICLE_DEFAULTS), flags=sf.SF_AUTO_RESET, stream=stream)
+        rng = np.random.default_rng(seed)
+        sim.actor_critic_load((rng.standard_normal(sf.AC_PARAMS) * 0.1).astype(np.float32))
+        N = sim.N
+        for _ in range(20):
+            sim.step_actor_critic(dt, S)
+        sim.profile(True)
+        for _ in range(steps):
+            sim.step_actor_critic(dt, S)
+        torch.cuda.synchronize()
+        ev, fixed = read_profile(sim)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            sim.step_actor_critic(dt, S)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        _, cnt = sim.observe_full()
+        torch.cuda.synchronize()
+        counts = cnt.cpu().numpy()
+        sim.close()
+    us = kernel_us(ev, fixed)
+    flop = ac_flop(counts)
+    obs_bytes_ = N * (sf.FULL_DIM * 4 + 8)
+    out = {"workload": workload, "agents": N, "steps": steps, "casps_eager": N * steps / (ms / 1e3),
+           "ms_per_step": ms / steps, "kernels_us": us,
+           "road_slots_mean": float(counts[:, 0].mean()), "neighbour_slots_mean": float(counts[:, 1].mean()),
+           "actor_critic_flop": flop,
+           "actor_critic_tflops": flop / (us["actor_critic"] * 1e-6) / 1e12 if "actor_critic" in us else None,
+           "actor_critic_frac_of_bf16_peak": (flop / (us["actor_critic"] * 1e-6) / 1e12 / BF16_PEAK_TFLOPS
+                                              if "actor_critic" in us else None),
+           "obs_full_gbs": obs_bytes_ / (us["obs_full"] * 1e-6) / 1e9 if "obs_full" in us else None}
+    log(f"full observation + actor-critic on {workload}: {N} agents, {ms / steps:.4f} ms/step eager, "
+        f"{out['casps_eager']:.4g} CASPS; kernels {us}")
     return out
 
 
@@ -341,6 +452,28 @@ def copy_bandwidth(torch, stream) -> float:
         gbs = 10 * 2 * x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del x, y
     return gbs
+
+
+CLOCK_US = 50.0
+
+
+def read_profile(sim, n_clock=20):
+    """The handle's per-kernel event record, closed by `n_clock` kernels that
+    run CLOCK_US of the GPU's constant-rate wall clock, timed the same way;
+    returns ({kernel: (mean event us, launches)}, fixed us): an event pair
+    bound to a dispatch still holds a fixed cost beside the kernel's
+    execution, which the clock kernels measure (their mean less CLOCK_US)."""
+    sim.profile_calibrate(n_clock, CLOCK_US)
+    prof = sim.profile_read()
+    sim.profile(False)
+    t, c = prof.pop("clock")
+    fixed = 1e3 * t / c - CLOCK_US if c else 0.0
+    return {k: (1e3 * t / c, c) for k, (t, c) in prof.items() if c}, fixed
+
+
+def kernel_us(ev, fixed):
+    """Kernel means less the event pair's fixed cost."""
+    return {k: us - fixed for k, (us, c) in ev.items()}
 
 
 def measure(args, seed, torch, sf, I, stream, keep=False):
@@ -382,8 +515,7 @@ def measure(args, seed, torch, sf, I, stream, keep=False):
         e1.record(stream)
         torch.cuda.synchronize()
         eager_ms = e0.elapsed_time(e1)
-        prof = sim.profile_read()
-        sim.profile(False)
+        prof = read_profile(sim)
 
         # road data each kernel reads: distinct items per launch, counted in
         # the kernels over a separate eager pass (atomics on; not timed)
@@ -443,7 +575,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--sur-log-steps", type=int, default=600)
+    ap.add_argument("--sur-log-steps", type=int, default=50,
+                    help="control steps of the benchmark workload logged as a second held-out set")
+    ap.add_argument("--sur-train-samples", type=int, default=10_000_000)
     ap.add_argument("--grid-cell", type=float, default=0.0)
     ap.add_argument("--obs-waves", type=int, default=0)
     ap.add_argument("--step-block", type=int, default=0)
@@ -453,6 +587,8 @@ def main():
     ap.add_argument("--configs", default="cross1024x16,dense4096x32",
                     help="other workload sizes reported as context (empty: none)")
     ap.add_argument("--config-steps", type=int, default=300)
+    ap.add_argument("--full-obs-steps", type=int, default=100,
+                    help="control steps of the paper-shaped observation + actor-critic leg (0: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step would shard by "
@@ -481,11 +617,14 @@ def main():
     sur = None
     if not args.no_surrogate:
         with torch.cuda.stream(stream):
-            sur = surrogate_leg(sim, torch, sf, stream, dt, S, args.steps, min(args.warmup, 300),
-                                args.sur_log_steps)
+            sur = surrogate_leg(sim, torch, sf, I, stream, dt, S, args.steps, min(args.warmup, 300),
+                                args.sur_train_samples, args.sur_log_steps)
 
     # ---- the other workload sizes (context, not the headline value)
     others = {}
+    if args.full_obs_steps > 0:
+        others["full_obs_" + args.workload] = full_obs_leg(torch, sf, I, stream, args.workload,
+                                                           args.full_obs_steps, args.seed)
     if args.configs:
         sur_params = None
         if sur is not None:
@@ -495,10 +634,8 @@ def main():
             others[name] = config_leg(name, torch, sf, I, stream, args.config_steps, sur_params,
                                       max(4, args.tune_steps // 2))
 
-    kernels = {}
-    for name, (tot, cnt) in prof.items():
-        if cnt:
-            kernels[name] = {"avg_us": 1e3 * tot / cnt, "launches": cnt}
+    ev, fixed = prof
+    kernels = {name: {"avg_us": us - fixed, "event_us": us, "launches": cnt} for name, (us, cnt) in ev.items()}
     dom = max(kernels, key=lambda n: kernels[n]["avg_us"])
     avg_s = kernels[dom]["avg_us"] * 1e-6
     fused = tuning["obs_waves"] == 16
@@ -521,8 +658,12 @@ def main():
     roof["avg_us"] = kernels[dom]["avg_us"]
     roof["traffic"] = recorded_traffic({"policy": "k_policy", "step": "k_step", "obs": "k_obs"}[dom],
                                        launch[dom], N)
-    roof["timing"] = ("mean HIP-event duration of the kernel over a profiled eager pass of the same "
-                      "control steps, seed %d" % args.seed)
+    roof["event_us"] = kernels[dom]["event_us"]
+    roof["event_fixed_us"] = fixed
+    roof["timing"] = ("mean HIP-event duration of the kernel (the event pair bound to its dispatch) over a "
+                      "profiled eager pass of the same control steps, seed %d, less the event pair's fixed "
+                      "cost: the mean event duration of a kernel that runs %.0f us of the GPU's wall clock, "
+                      "less %.0f us" % (args.seed, CLOCK_US, CLOCK_US))
     # the whole control step (policy, step, observation) against the same peak
     whole = CONTROL_STEP_BYTES_PER_AGENT * N + POLICY_WEIGHT_BYTES + road["step"] + road["obs"]
     roof["control_step"] = {"algorithmic_bytes": whole, "ms": r0["ms_per_step"],

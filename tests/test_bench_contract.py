@@ -46,7 +46,8 @@ def test_traffic_record_needs_matching_source_and_size():
     assert bench.recorded_traffic(k["kernel"], name, k["agents"] + 1) is None
     assert bench.recorded_traffic(k["kernel"], "no such launch", k["agents"]) is None
     v = bench.recorded_traffic(k["kernel"], name, k["agents"])
-    if k["source_hash"] == bench.kernel_source_hash(k["kernel"]):
+    from paper_2605_08528_amd.profile_summary import kernel_source_hash
+    if k["source_hash"] == kernel_source_hash(k["kernel"]):
         assert v == pytest.approx((k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024)
     else:
         assert v is None
