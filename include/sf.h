@@ -391,15 +391,86 @@ sf_status sf_step_actor_critic(sf_sim *sim, float dt, int32_t substeps);
 sf_status sf_actor_critic_read(sf_sim *sim, float *d_mean, float *d_value, float *d_actions, float *d_obs,
                                int32_t *d_counts);
 
+/* ---- on-device PPO (Algorithm "SceneFactory Pipeline": T rollout steps,
+ * then a PPO update on the N x T transitions; appendix "PPO
+ * Hyperparameters").  The policy is a diagonal Gaussian over the 3-dim
+ * action (throttle, steering, brake) with the actor's mean and its
+ * state-independent log sigma (the parameter block's); the environment
+ * takes the sample's decode of sf_step_actor_critic (throttle and brake
+ * rectified, steering clamped).  Random numbers come in from the caller:
+ * the standard normals of the rollout and the minibatch permutations. */
+typedef struct {
+    int32_t horizon;        /* T rollout steps per iteration (128) */
+    int32_t epochs;         /* 5 */
+    int32_t minibatches;    /* 16; must divide N T */
+    float gamma, lam;       /* discount 0.99, GAE lambda 0.98 */
+    float clip;             /* 0.15 */
+    float value_coef;       /* 1.0 */
+    float entropy_coef;     /* 3e-5 */
+    float max_grad_norm;    /* 1.0 (global norm over the parameter block) */
+    float lr;               /* initial learning rate 2.09e-4 */
+    float kl_target;        /* 0.01: the rate halves above 2x, doubles below 0.5x */
+    float lr_min, lr_max;   /* 1e-5, 1e-2 */
+    float beta1, beta2, eps; /* Adam 0.9, 0.999, 1e-8 */
+} sf_ppo_opts;
+
+typedef struct {
+    float lr;               /* the learning rate after the update */
+    float kl;               /* mean over the update's minibatches */
+    float surrogate, value_loss, entropy, clip_fraction, grad_norm;   /* means */
+    int32_t steps;          /* optimizer steps taken (epochs x minibatches) */
+} sf_ppo_stats;
+
+sf_status sf_ppo_default_opts(sf_ppo_opts *o);
+/* Rollout and update buffers for horizon T (about 7.8 KB per agent and
+ * step, most of it the 1929-float observations) and fresh Adam moments.
+ * Needs a loaded actor-critic (sf_actor_critic_load) and a handle created
+ * with SF_AUTO_RESET (every agent acts at every step). */
+sf_status sf_ppo_init(sf_sim *sim, const sf_ppo_opts *o);
+/* T control steps: the paper's observation, the actor-critic, actions
+ * u = mean + exp(log sigma) eps with d_eps [T][N][3] device standard
+ * normals, their log-densities, the step; observations, counts, u,
+ * log-densities, means, values, rewards and done flags are kept, then the
+ * value of the state after the last step. */
+sf_status sf_ppo_rollout(sf_sim *sim, float dt, int32_t substeps, const float *d_eps);
+/* Generalised advantages and returns of the kept rollout (a done step
+ * cuts the bootstrap and the recursion), advantages then normalised to
+ * zero mean and unit (population) spread over the N T samples. */
+sf_status sf_ppo_advantages(sf_sim *sim);
+/* The PPO update: advantages, then for each epoch the permutation
+ * d_perm[e] (device int32 [epochs][N T], each a permutation of 0..N T-1,
+ * checked) cut into `minibatches` consecutive minibatches; per minibatch the
+ * actor-critic on its rows, the loss surrogate + c_v value_loss - c_e
+ * entropy (surrogate = mean max(-A r, -A clip(r, 1 - clip, 1 + clip)),
+ * value_loss = mean (V - R)^2), the KL to the rollout's policy, which sets
+ * the learning rate before the step, the gradient (bf16 rounding points of
+ * the forward pass, fp32 back-propagation), clipped to max_grad_norm, and
+ * an Adam step on the fp32 parameters.  Synchronises once per minibatch. */
+sf_status sf_ppo_update(sf_sim *sim, const int32_t *d_perm, sf_ppo_stats *out);
+/* The loss's gradient (h_grad [SF_AC_PARAMS] float, parameter block
+ * layout) and statistics (h_stats [8]: surrogate, value_loss, KL and
+ * clipped-fraction means, d/d log sigma[3] of the surrogate, rows) on the
+ * kept rollout's samples d_rows[0, M) (M <= N T / minibatches) at the
+ * current parameters, after sf_ppo_advantages; no step.  Synchronises. */
+sf_status sf_ppo_gradient(sf_sim *sim, const int32_t *d_rows, int32_t M, float *h_grad, double *h_stats);
+/* Copies of the kept rollout into caller device arrays (NULL skips):
+ * u, mean [T][N][3], logp, value (value has T + 1 rows), reward, adv,
+ * ret [T][N] float, done [T][N] u8, obs [T][N][SF_FULL_DIM], counts [T][N][2]. */
+sf_status sf_ppo_read(sf_sim *sim, float *d_u, float *d_mean, float *d_logp, float *d_value, float *d_reward,
+                      uint8_t *d_done, float *d_adv, float *d_ret, float *d_obs, int32_t *d_counts);
+/* The actor-critic's current parameters (h_params [SF_AC_PARAMS]). */
+sf_status sf_actor_critic_get(sf_sim *sim, float *h_params);
+
 /* ---- per-kernel timing of eagerly enqueued work (hipEvents on the
  * handle's stream).  sf_profile(sim, 1) starts (and clears) the record;
  * sf_profile_read synchronises and returns total milliseconds and launch
  * counts per kernel: [0] policy, [1] step, [2] observation, [3] reset,
- * [4] the paper's observation, [5] the actor-critic, [6] the clock kernels
- * of sf_profile_calibrate.  Each event pair is bound to its kernel's
+ * [4] the paper's observation, [5] the actor-critic (its forward pass in a
+ * PPO update included), [6] the clock kernels of sf_profile_calibrate, [7]
+ * the PPO backward pass.  Each event pair is bound to its kernel's
  * dispatch (hipExtLaunchKernelGGL); an interval still holds a fixed cost of
  * the pair beside the kernel's execution. */
-#define SF_PROF_KERNELS 7
+#define SF_PROF_KERNELS 8
 sf_status sf_profile(sf_sim *sim, int32_t enable);
 sf_status sf_profile_read(sf_sim *sim, double *total_ms, int32_t *launches);
 /* Enqueues n (1..10000) launches of a one-wave kernel that runs for `us`

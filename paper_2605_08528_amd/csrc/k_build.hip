@@ -203,39 +203,67 @@ void launch_grid_fill(const DevWorld &Wd, const float *verts, int T, int P, int 
 }
 
 // order each cell's items by index (the scatter order is not
-// deterministic): one wave per cell; up to 64 items by a bitonic sort across
-// the lanes, up to CELL_SORT_LDS by ranks counted against a copy in LDS
-// (items of a cell are distinct), larger cells by an insertion sort on one
-// lane
+// deterministic).  Small cells (most of them, many empty) are sorted by one
+// thread each in place; a cell with more than CELL_SORT_SMALL items goes to
+// a list that persistent waves then take one cell at a time: a bitonic sort
+// across the lanes up to 64 items, ranks counted against a copy in LDS up to
+// CELL_SORT_LDS (items of a cell are distinct), an insertion sort on one
+// lane beyond
+#define CELL_SORT_SMALL 16
 #define CELL_SORT_LDS 2048
-__global__ __launch_bounds__(256) void k_cell_sort(const int *start, int C, int *items) {
-    __shared__ int buf[4][CELL_SORT_LDS];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int c = blockIdx.x * 4 + wv;
+__global__ void k_cell_sort_small(const int *start, int C, int *items, int *big_count, int *big) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
     const int a = start[c], n = start[c + 1] - a;
-    if (n <= 1) return;
-    if (n <= 64) {
-        unsigned v = lane < n ? (unsigned)items[a + lane] : 0xffffffffu;
-        v = wave_sort_u32(v);
-        if (lane < n) items[a + lane] = (int)v;
-    } else if (n <= CELL_SORT_LDS) {
-        int *b = buf[wv];
-        for (int i = lane; i < n; i += 64) b[i] = items[a + i];
-        wave_sync();
-        for (int i = lane; i < n; i += 64) {
-            const int v = b[i];
-            int rank = 0;
-            for (int j = 0; j < n; ++j) rank += b[j] < v;
-            items[a + rank] = v;
-        }
-    } else if (lane == 0) {
-        for (int i = a + 1; i < a + n; ++i) {
-            int v = items[i], j = i - 1;
-            while (j >= a && items[j] > v) { items[j + 1] = items[j]; --j; }
-            items[j + 1] = v;
+    if (n > CELL_SORT_SMALL) {
+        big[atomicAdd(big_count, 1)] = c;
+        return;
+    }
+    for (int i = a + 1; i < a + n; ++i) {
+        int v = items[i], j = i - 1;
+        while (j >= a && items[j] > v) { items[j + 1] = items[j]; --j; }
+        items[j + 1] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_sort_big(const int *start, int *items, const int *big_count,
+                                                       const int *big) {
+    __shared__ int buf[4][CELL_SORT_LDS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nb = *big_count;
+    for (int q = blockIdx.x * 4 + wv; q < nb; q += gridDim.x * 4) {
+        const int c = big[q];
+        const int a = start[c], n = start[c + 1] - a;
+        if (n <= 64) {
+            unsigned v = lane < n ? (unsigned)items[a + lane] : 0xffffffffu;
+            v = wave_sort_u32(v);
+            if (lane < n) items[a + lane] = (int)v;
+        } else if (n <= CELL_SORT_LDS) {
+            int *b = buf[wv];
+            for (int i = lane; i < n; i += 64) b[i] = items[a + i];
+            wave_sync();
+            for (int i = lane; i < n; i += 64) {
+                const int v = b[i];
+                int rank = 0;
+                for (int j = 0; j < n; ++j) rank += b[j] < v;
+                items[a + rank] = v;
+            }
+            wave_sync();   // the copy is reused by this wave's next cell
+        } else if (lane == 0) {
+            for (int i = a + 1; i < a + n; ++i) {
+                int v = items[i], j = i - 1;
+                while (j >= a && items[j] > v) { items[j + 1] = items[j]; --j; }
+                items[j + 1] = v;
+            }
         }
     }
+}
+
+static void cell_sort(const int *start, int C, int *items, int *work, hipStream_t st) {
+    // work: [0] the count of large cells, [1..C] their list
+    (void)hipMemsetAsync(work, 0, sizeof(int), st);
+    k_cell_sort_small<<<(C + 255) / 256, 256, 0, st>>>(start, C, items, work, work + 1);
+    k_cell_sort_big<<<1024, 256, 0, st>>>(start, items, work, work + 1);
 }
 
 __device__ __forceinline__ int world_of_cell(const GridHdr *grid, int W, int c) {
@@ -311,13 +339,14 @@ __global__ __launch_bounds__(256) void k_occ(DevWorld Wd, int *occ) {
 }
 
 void launch_grid_finish(const DevWorld &Wd, int CT, int CP, int *tri_items, int *pt_items,
-                        float4 *tri_rec, int4 *pt_cell, int *pt_occ, hipStream_t st) {
+                        float4 *tri_rec, int4 *pt_cell, int *pt_occ, int *tri_work, int *pt_work,
+                        hipStream_t st) {
     if (CT) {
-        k_cell_sort<<<(CT + 3) / 4, 256, 0, st>>>(Wd.tri_cell_start, CT, tri_items);
+        cell_sort(Wd.tri_cell_start, CT, tri_items, tri_work, st);
         k_pack_tris<<<(CT + 255) / 256, 256, 0, st>>>(Wd, CT, tri_items, tri_rec);
     }
     if (CP) {
-        k_cell_sort<<<(CP + 3) / 4, 256, 0, st>>>(Wd.pt_cell_start, CP, pt_items);
+        cell_sort(Wd.pt_cell_start, CP, pt_items, pt_work, st);
         k_pack_pts<<<(CP + 255) / 256, 256, 0, st>>>(Wd, CP, pt_items, pt_cell);
     }
     if (Wd.W) k_occ<<<Wd.W, 256, 0, st>>>(Wd, pt_occ);

@@ -230,39 +230,7 @@ void launch_obs_full(const DevParams &P, const DevWorld &Wd, const float *st, co
 }
 
 // ------------------------------------------------------------ actor-critic
-// bf16 weight block per network (elements): ego W1 [64][12] (11 inputs,
-// zero-padded), ego W2 [64][64], road W1 [96][8] (5, padded), road W2
-// [96][96], vehicle W1 [96][8] (7, padded), vehicle W2 [96][96], trunk W1
-// [128][256], trunk W2 [64][128]; the heads and every bias come from the
-// float32 parameter block (the heads rounded to bf16 on the way).
-#define ACB_EW1 0
-#define ACB_EW2 (ACB_EW1 + 64 * 12)
-#define ACB_RW1 (ACB_EW2 + 64 * 64)
-#define ACB_RW2 (ACB_RW1 + 96 * 8)
-#define ACB_VW1 (ACB_RW2 + 96 * 96)
-#define ACB_VW2 (ACB_VW1 + 96 * 8)
-#define ACB_TW1 (ACB_VW2 + 96 * 96)
-#define ACB_TW2 (ACB_TW1 + 128 * 256)
-#define ACB_NET (ACB_TW2 + 64 * 128)
-// float32 parameter block offsets within one network (the order of the
-// C ABI's parameter block)
-#define ACF_EW1 0
-#define ACF_EB1 (ACF_EW1 + 64 * 11)
-#define ACF_EW2 (ACF_EB1 + 64)
-#define ACF_EB2 (ACF_EW2 + 64 * 64)
-#define ACF_RW1 (ACF_EB2 + 64)
-#define ACF_RB1 (ACF_RW1 + 96 * 5)
-#define ACF_RW2 (ACF_RB1 + 96)
-#define ACF_RB2 (ACF_RW2 + 96 * 96)
-#define ACF_VW1 (ACF_RB2 + 96)
-#define ACF_VB1 (ACF_VW1 + 96 * 7)
-#define ACF_VW2 (ACF_VB1 + 96)
-#define ACF_VB2 (ACF_VW2 + 96 * 96)
-#define ACF_TW1 (ACF_VB2 + 96)
-#define ACF_TB1 (ACF_TW1 + 128 * 256)
-#define ACF_TW2 (ACF_TB1 + 128)
-#define ACF_TB2 (ACF_TW2 + 64 * 128)
-#define ACF_HEAD (ACF_TB2 + 64)          // == SF_AC_BODY
+#include "ac_layout.h"
 
 // bf16 copies of the weight matrices in the padded layout above (one thread
 // per element of both networks' blocks)
@@ -301,16 +269,19 @@ __device__ __forceinline__ float bfr(float x) { return bf2f(f2bf(x)); }
 // pass, weights as the row operand so that a lane's results are four
 // consecutive features of one slot.  Returns this lane's pooled values for
 // features 16 ft + 4 (lane / 16) + j in pool[ft][j].
-template <int K1>
+template <int K1, bool ARG>
 __device__ __forceinline__ void set_encoder(const float *__restrict__ x, int rows, const bf16x8 (&w1)[6],
                                             const float *__restrict__ b1, const uint16_t *__restrict__ w2,
                                             const float *__restrict__ b2, uint16_t *__restrict__ h,
-                                            float (&pool)[6][4]) {
+                                            float (&pool)[6][4], int (&amax)[6][4]) {
     const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
     for (int ft = 0; ft < 6; ++ft)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) pool[ft][j] = -INFINITY;
+        for (int j = 0; j < 4; ++j) {
+            pool[ft][j] = -INFINITY;
+            amax[ft][j] = -1;
+        }
     for (int base = 0; base < rows; base += 32) {
         // layer 1: B fragments, slot = base + 16 g + r16, features k in [0, K1)
         bf16x8 xb[2];
@@ -357,33 +328,65 @@ __device__ __forceinline__ void set_encoder(const float *__restrict__ x, int row
 #pragma unroll
         for (int ft = 0; ft < 6; ++ft) {
             const float4 bb = *reinterpret_cast<const float4 *>(b2 + 16 * ft + 4 * kq);
+            const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
 #pragma unroll
             for (int gq = 0; gq < 2; ++gq) {
-                if (base + 16 * gq + r16 >= rows) continue;
-                pool[ft][0] = fmaxf(pool[ft][0], bfr(elu_fast(acc[ft][gq][0] + bb.x)));
-                pool[ft][1] = fmaxf(pool[ft][1], bfr(elu_fast(acc[ft][gq][1] + bb.y)));
-                pool[ft][2] = fmaxf(pool[ft][2], bfr(elu_fast(acc[ft][gq][2] + bb.z)));
-                pool[ft][3] = fmaxf(pool[ft][3], bfr(elu_fast(acc[ft][gq][3] + bb.w)));
+                const int slot = base + 16 * gq + r16;
+                if (slot >= rows) continue;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float v = bfr(elu_fast(acc[ft][gq][j] + bv[j]));
+                    if (ARG) {
+                        // a lane sees its slots in increasing order: the
+                        // first maximum is kept
+                        if (v > pool[ft][j]) {
+                            pool[ft][j] = v;
+                            amax[ft][j] = slot;
+                        }
+                    } else {
+                        pool[ft][j] = fmaxf(pool[ft][j], v);
+                    }
+                }
             }
         }
     }
-    // maximum over the 16 slot lanes of each group of four features
+    // maximum over the 16 slot lanes of each group of four features (with
+    // ARG: the lowest slot among equal maxima)
 #pragma unroll
     for (int ft = 0; ft < 6; ++ft)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             float v = pool[ft][j];
+            int a = amax[ft][j];
 #pragma unroll
-            for (int m = 1; m < 16; m <<= 1) v = fmaxf(v, lane_xor_f(v, m));
+            for (int m = 1; m < 16; m <<= 1) {
+                const float ov = lane_xor_f(v, m);
+                if (ARG) {
+                    const int oa = lane_xor(a, m);
+                    if (ov > v || (ov == v && (unsigned)oa < (unsigned)a)) {
+                        v = ov;
+                        a = oa;
+                    }
+                } else {
+                    v = fmaxf(v, ov);
+                }
+            }
             pool[ft][j] = rows > 0 ? v : 0.f;
+            amax[ft][j] = rows > 0 ? a : -1;
         }
 }
 
+// SAVE: row n also leaves, per network, what the backward pass needs (see
+// AC_SAVE_* in the header): the ego and trunk pre-activations, the
+// embedding, and for each pooled feature the slot it came from.  rows (or
+// null): row n reads the observation of sample rows[n].
+template <bool SAVE>
 __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ obs, const int *__restrict__ counts,
-                                                      int N, const float *__restrict__ Pf,
+                                                      const int *__restrict__ rows, int N,
+                                                      const float *__restrict__ Pf,
                                                       const uint16_t *__restrict__ Wb, float *__restrict__ mean,
                                                       float *__restrict__ value, float *__restrict__ act,
-                                                      float steer_max) {
+                                                      float steer_max, float *__restrict__ save) {
     __shared__ __attribute__((aligned(16))) uint16_t s_rw2[96 * AC_W2LD];
     __shared__ __attribute__((aligned(16))) uint16_t s_vw2[96 * AC_W2LD];
     __shared__ __attribute__((aligned(16))) uint16_t s_h[4][32 * AC_HLD];
@@ -420,8 +423,10 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
                 for (int k = lane; k < 256; k += 64) emb[k] = 0;
                 continue;
             }
-            const float *o = obs + (size_t)n * FULL_DIM;
-            const int nr = counts[2 * n], nv = counts[2 * n + 1];
+            const int src = rows ? rows[n] : n;
+            const float *o = obs + (size_t)src * FULL_DIM;
+            const int nr = counts[2 * src], nv = counts[2 * src + 1];
+            float *sv = SAVE ? save + (size_t)n * AC_SAVE_ROW + net * AC_SAVE : nullptr;
             // ego 11 -> 64 -> 64 (lane = feature)
             {
                 float acc = F[ACF_EB1 + lane];
@@ -432,23 +437,39 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
                 const uint16_t *w2 = B + ACB_EW2 + lane * 64;
                 for (int k = 0; k < 64; ++k) acc2 += bf2f(w2[k]) * s_ego[wv][k];
                 emb[lane] = f2bf(elu_fast(acc2));
+                if (SAVE) {
+                    sv[AC_SAVE_ZE1 + lane] = acc;
+                    sv[AC_SAVE_ZE2 + lane] = acc2;
+                }
                 wave_sync();
             }
             float pool[6][4];
-            set_encoder<5>(o + FULL_EGO, min(nr, FULL_RK), rw1, F + ACF_RB1, s_rw2, F + ACF_RB2, s_h[wv], pool);
+            int amax[6][4];
+            set_encoder<5, SAVE>(o + FULL_EGO, min(nr, FULL_RK), rw1, F + ACF_RB1, s_rw2, F + ACF_RB2, s_h[wv], pool,
+                                 amax);
             if (r16 == 0) {
 #pragma unroll
                 for (int ft = 0; ft < 6; ++ft)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) emb[64 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
+                    for (int j = 0; j < 4; ++j) {
+                        emb[64 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
+                        if (SAVE) sv[AC_SAVE_AR + 16 * ft + 4 * kq + j] = __int_as_float(amax[ft][j]);
+                    }
             }
-            set_encoder<7>(o + FULL_EGO + 5 * FULL_RK, min(nv, FULL_VK), vw1, F + ACF_VB1, s_vw2, F + ACF_VB2,
-                           s_h[wv], pool);
+            set_encoder<7, SAVE>(o + FULL_EGO + 5 * FULL_RK, min(nv, FULL_VK), vw1, F + ACF_VB1, s_vw2, F + ACF_VB2,
+                                 s_h[wv], pool, amax);
             if (r16 == 0) {
 #pragma unroll
                 for (int ft = 0; ft < 6; ++ft)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) emb[160 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
+                    for (int j = 0; j < 4; ++j) {
+                        emb[160 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
+                        if (SAVE) sv[AC_SAVE_AV + 16 * ft + 4 * kq + j] = __int_as_float(amax[ft][j]);
+                    }
+            }
+            if (SAVE) {
+                wave_sync();
+                for (int k = lane; k < 256; k += 64) sv[AC_SAVE_EMB + k] = bf2f(emb[k]);
             }
         }
         __syncthreads();
@@ -470,7 +491,11 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
                 const int col = 32 * wv + 16 * c + r16;
                 const float bb = F[ACF_TB1 + col];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) s_t1[(4 * kq + j) * AC_TLD + col] = f2bf(elu_fast(acc[c][j] + bb));
+                for (int j = 0; j < 4; ++j) {
+                    s_t1[(4 * kq + j) * AC_TLD + col] = f2bf(elu_fast(acc[c][j] + bb));
+                    if (SAVE && n0 + 4 * kq + j < N)
+                        save[(size_t)(n0 + 4 * kq + j) * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZT1 + col] = acc[c][j] + bb;
+                }
             }
         }
         __syncthreads();
@@ -487,7 +512,11 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
             const int col = 16 * wv + r16;
             const float bb = F[ACF_TB2 + col];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) s_t2[(4 * kq + j) * 72 + col] = f2bf(elu_fast(acc[j] + bb));
+            for (int j = 0; j < 4; ++j) {
+                s_t2[(4 * kq + j) * 72 + col] = f2bf(elu_fast(acc[j] + bb));
+                if (SAVE && n0 + 4 * kq + j < N)
+                    save[(size_t)(n0 + 4 * kq + j) * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZT2 + col] = acc[j] + bb;
+            }
         }
         __syncthreads();
         // ---- heads: actor mean (3 per agent), critic value (1 per agent)
@@ -523,6 +552,13 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
 void launch_actor_critic(const float *obs, const int *counts, int N, const float *Pf, const uint16_t *Wb,
                          float *mean, float *value, float *act, float steer_max, hipStream_t s) {
     if (N == 0) return;
-    sf_launch(k_actor_critic, dim3((N + AC_AGENTS - 1) / AC_AGENTS), dim3(256), 0, s, obs, counts, N, Pf, Wb, mean,
-              value, act, steer_max);
+    sf_launch(k_actor_critic<false>, dim3((N + AC_AGENTS - 1) / AC_AGENTS), dim3(256), 0, s, obs, counts,
+              (const int *)nullptr, N, Pf, Wb, mean, value, act, steer_max, (float *)nullptr);
+}
+
+void launch_actor_critic_save(const float *obs, const int *counts, const int *rows, int M, const float *Pf,
+                              const uint16_t *Wb, float *mean, float *value, float *save, hipStream_t s) {
+    if (M == 0) return;
+    sf_launch(k_actor_critic<true>, dim3((M + AC_AGENTS - 1) / AC_AGENTS), dim3(256), 0, s, obs, counts, rows, M, Pf,
+              Wb, mean, value, (float *)nullptr, 0.f, save);
 }

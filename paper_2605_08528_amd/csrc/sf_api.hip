@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "sf_dev.h"
+#include "ac_layout.h"
 
 static thread_local std::string g_err;
 
@@ -68,6 +69,23 @@ struct sf_sim {
     uint16_t *ac_bf16 = nullptr;          // bf16 weight copies (padded layout)
     float *ac_mean = nullptr, *ac_value = nullptr, *ac_act = nullptr;  // [N][3], [N], [N][2]
     bool ac_loaded = false;
+    // on-device PPO
+    bool ppo_ready = false;
+    sf_ppo_opts ppo{};
+    int ppo_B = 0;                        // rows per minibatch
+    long long ppo_TN = 0;
+    float *ro_obs = nullptr, *ro_u = nullptr, *ro_mu = nullptr, *ro_logp = nullptr, *ro_val = nullptr;
+    float *ro_rew = nullptr, *ro_adv = nullptr, *ro_ret = nullptr;
+    int *ro_cnt = nullptr;
+    uint8_t *ro_done = nullptr;
+    bool ro_full = false, adv_ready = false;
+    float ls_old[3] = {};                 // log sigma during the kept rollout
+    float *ppo_m = nullptr, *ppo_v = nullptr, *ppo_grad = nullptr, *ppo_part = nullptr, *ppo_save = nullptr;
+    float *ppo_mean = nullptr, *ppo_value = nullptr, *ppo_dout = nullptr, *ppo_lpart = nullptr, *ppo_norm = nullptr;
+    double *ppo_stats = nullptr, *ppo_mom = nullptr, *ppo_sq = nullptr;
+    int *ppo_flag = nullptr;
+    long long ppo_t = 0;                  // Adam steps taken
+    float ppo_lr = 0.f;
     // dense shaping rewards and the lane-forbidden event (sf_set_shaping)
     uint8_t *forbid = nullptr;            // [N]
     float2 *disp = nullptr;               // [N]
@@ -358,7 +376,9 @@ static sf_status build_grids(sf_sim *sim, float grid_cell, float tri_cell) {
     Wn.tri_cell_start = tri_start; Wn.tri_rec = tri_rec;
     Wn.pt_cell_start = pt_start; Wn.pt_cell = pt_cell; Wn.pt_occ = pt_occ;
     launch_grid_fill(Wn, sim->verts, T, P, tri_cursor, pt_cursor, tri_items, pt_items, st);
-    launch_grid_finish(Wn, (int)CT, (int)CP, tri_items, pt_items, tri_rec, pt_cell, pt_occ, st);
+    // the cursors are spent after the fill: work space of the cell sorts
+    launch_grid_finish(Wn, (int)CT, (int)CP, tri_items, pt_items, tri_rec, pt_cell, pt_occ, tri_cursor, pt_cursor,
+                       st);
     LAUNCHED();
     DEV(hipStreamSynchronize(st));
     for (void *p : tmp) dev_free(sim, p);
@@ -888,6 +908,293 @@ sf_status sf_actor_critic_read(sf_sim *sim, float *d_mean, float *d_value, float
     if (d_actions) DEV(hipMemcpyAsync(d_actions, sim->ac_act, sizeof(float) * 2 * N, hipMemcpyDeviceToDevice, st));
     if (d_obs) DEV(hipMemcpyAsync(d_obs, sim->full_obs, sizeof(float) * SF_FULL_DIM * N, hipMemcpyDeviceToDevice, st));
     if (d_counts) DEV(hipMemcpyAsync(d_counts, sim->full_counts, sizeof(int) * 2 * N, hipMemcpyDeviceToDevice, st));
+    return SF_OK;
+}
+
+// ------------------------------------------------------------ on-device PPO
+sf_status sf_ppo_default_opts(sf_ppo_opts *o) {
+    if (!o) return fail(SF_E_INVALID_ARG, "opts is NULL");
+    o->horizon = 128;
+    o->epochs = 5;
+    o->minibatches = 16;
+    o->gamma = 0.99f;
+    o->lam = 0.98f;
+    o->clip = 0.15f;
+    o->value_coef = 1.f;
+    o->entropy_coef = 3e-5f;
+    o->max_grad_norm = 1.f;
+    o->lr = 2.09e-4f;
+    o->kl_target = 0.01f;
+    o->lr_min = 1e-5f;
+    o->lr_max = 1e-2f;
+    o->beta1 = 0.9f;
+    o->beta2 = 0.999f;
+    o->eps = 1e-8f;
+    return SF_OK;
+}
+
+sf_status sf_ppo_init(sf_sim *sim, const sf_ppo_opts *o) {
+    CHECK_SIM(sim);
+    if (!o) return fail(SF_E_INVALID_ARG, "opts is NULL");
+    if (!sim->ac_loaded) return fail(SF_E_INVALID_ARG, "no actor-critic loaded");
+    if (!(sim->flags & SF_AUTO_RESET)) return fail(SF_E_INVALID_ARG, "PPO needs a handle created with SF_AUTO_RESET");
+    if (sim->N == 0) return fail(SF_E_INVALID_ARG, "no agents");
+    if (o->horizon < 1 || o->horizon > 4096 || o->epochs < 1 || o->epochs > 100 || o->minibatches < 1)
+        return fail(SF_E_INVALID_ARG, "horizon 1..4096, epochs 1..100, minibatches >= 1");
+    const long long TN = (long long)o->horizon * sim->N;
+    if (TN % o->minibatches != 0) return fail(SF_E_INVALID_ARG, "minibatches must divide N x horizon");
+    if (TN > INT32_MAX / 2) return fail(SF_E_INVALID_ARG, "N x horizon too large");
+    const float fs[] = {o->gamma, o->lam, o->clip, o->value_coef, o->entropy_coef, o->max_grad_norm, o->lr,
+                        o->kl_target, o->lr_min, o->lr_max, o->beta1, o->beta2, o->eps};
+    for (float f : fs)
+        if (!std::isfinite(f) || f < 0.f) return fail(SF_E_INVALID_ARG, "PPO options must be finite and >= 0");
+    if (!(o->lr_min <= o->lr && o->lr <= o->lr_max) || o->beta1 >= 1.f || o->beta2 >= 1.f || !(o->eps > 0.f))
+        return fail(SF_E_INVALID_ARG, "need lr_min <= lr <= lr_max, betas < 1, eps > 0");
+    const int B = (int)(TN / o->minibatches);
+    if (sim->ppo_ready && (sim->ppo.horizon != o->horizon || sim->ppo_B != B))
+        return fail(SF_E_INVALID_ARG, "PPO buffers exist for another horizon or minibatch size");
+    if (!sim->ppo_ready) {
+        const size_t N = sim->N, T = o->horizon;
+        auto A = [&](size_t bytes) { return dev_alloc(sim, bytes); };
+        sim->ro_obs = (float *)A(sizeof(float) * SF_FULL_DIM * T * N);
+        sim->ro_cnt = (int *)A(sizeof(int) * 2 * T * N);
+        sim->ro_u = (float *)A(sizeof(float) * 3 * T * N);
+        sim->ro_mu = (float *)A(sizeof(float) * 3 * T * N);
+        sim->ro_logp = (float *)A(sizeof(float) * T * N);
+        sim->ro_val = (float *)A(sizeof(float) * (T + 1) * N);
+        sim->ro_rew = (float *)A(sizeof(float) * T * N);
+        sim->ro_adv = (float *)A(sizeof(float) * T * N);
+        sim->ro_ret = (float *)A(sizeof(float) * T * N);
+        sim->ro_done = (uint8_t *)A(T * N);
+        const int tiles = ppo_tiles(B);
+        sim->ppo_m = (float *)A(sizeof(float) * SF_AC_PARAMS);
+        sim->ppo_v = (float *)A(sizeof(float) * SF_AC_PARAMS);
+        sim->ppo_grad = (float *)A(sizeof(float) * SF_AC_PARAMS);
+        sim->ppo_part = (float *)A(sizeof(float) * SF_AC_PARAMS * (size_t)tiles);
+        sim->ppo_save = (float *)A(sizeof(float) * AC_SAVE_ROW * (size_t)B);
+        sim->ppo_mean = (float *)A(sizeof(float) * 3 * (size_t)B);
+        sim->ppo_value = (float *)A(sizeof(float) * (size_t)B);
+        sim->ppo_dout = (float *)A(sizeof(float) * 4 * (size_t)B);
+        sim->ppo_lpart = (float *)A(sizeof(float) * 8 * (size_t)((B + 255) / 256));
+        sim->ppo_norm = (float *)A(sizeof(float) * 4);
+        sim->ppo_stats = (double *)A(sizeof(double) * 8);
+        sim->ppo_mom = (double *)A(sizeof(double) * 2 * (size_t)ppo_moment_blocks(TN));
+        sim->ppo_sq = (double *)A(sizeof(double) * 64);
+        sim->ppo_flag = (int *)A(sizeof(int));
+        if (!sim->ro_obs || !sim->ro_cnt || !sim->ro_u || !sim->ro_mu || !sim->ro_logp || !sim->ro_val ||
+            !sim->ro_rew || !sim->ro_adv || !sim->ro_ret || !sim->ro_done || !sim->ppo_m || !sim->ppo_v ||
+            !sim->ppo_grad || !sim->ppo_part || !sim->ppo_save || !sim->ppo_mean || !sim->ppo_value ||
+            !sim->ppo_dout || !sim->ppo_lpart || !sim->ppo_norm || !sim->ppo_stats || !sim->ppo_mom ||
+            !sim->ppo_sq || !sim->ppo_flag)
+            return fail(SF_E_OUT_OF_MEMORY, "PPO buffers");
+        sf_status r;
+        if ((r = full_buffers(sim)) != SF_OK) return r;
+    }
+    DEV(hipMemsetAsync(sim->ppo_m, 0, sizeof(float) * SF_AC_PARAMS, sim->stream));
+    DEV(hipMemsetAsync(sim->ppo_v, 0, sizeof(float) * SF_AC_PARAMS, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    sim->ppo = *o;
+    sim->ppo_B = B;
+    sim->ppo_TN = TN;
+    sim->ppo_t = 0;
+    sim->ppo_lr = o->lr;
+    sim->ro_full = sim->adv_ready = false;
+    sim->ppo_ready = true;
+    return SF_OK;
+}
+
+sf_status sf_ppo_rollout(sf_sim *sim, float dt, int32_t substeps, const float *d_eps) {
+    CHECK_SIM(sim);
+    if (!sim->ppo_ready) return fail(SF_E_INVALID_ARG, "sf_ppo_init first");
+    if (!d_eps) return fail(SF_E_INVALID_ARG, "eps is NULL");
+    if (substeps < 1 || substeps > SF_MAX_SUBSTEPS || !(dt > 0.f) || !std::isfinite(dt))
+        return fail(SF_E_INVALID_ARG, "bad dt or substeps");
+    const size_t N = sim->N, T = sim->ppo.horizon;
+    hipStream_t st = sim->stream;
+    // log sigma of the policy that acts (the KL reference of the update)
+    DEV(hipMemcpyAsync(sim->ls_old, sim->ac_f32 + ACF_LOGSTD, sizeof(float) * 3, hipMemcpyDeviceToHost, st));
+    DEV(hipStreamSynchronize(st));
+    sf_status r;
+    for (size_t t = 0; t < T; ++t) {
+        float *obs_t = sim->ro_obs + t * N * SF_FULL_DIM;
+        int *cnt_t = sim->ro_cnt + t * N * 2;
+        if ((r = sf_observe_full(sim, obs_t, cnt_t)) != SF_OK) return r;
+        {
+            ProfScope ps(sim, 5);
+            launch_actor_critic(obs_t, cnt_t, (int)N, sim->ac_f32, sim->ac_bf16, sim->ac_mean, sim->ro_val + t * N,
+                                nullptr, sim->steer_max, st);
+        }
+        launch_ppo_sample(sim->ac_mean, sim->ac_f32, d_eps + t * N * 3, (int)N, sim->ro_u + t * N * 3,
+                          sim->ro_logp + t * N, sim->ro_mu + t * N * 3, sim->ac_act, sim->steer_max, st);
+        LAUNCHED();
+        if ((r = enqueue_step(sim, sim->ac_act, dt, substeps, false)) != SF_OK) return r;
+        DEV(hipMemcpyAsync(sim->ro_rew + t * N, sim->reward, sizeof(float) * N, hipMemcpyDeviceToDevice, st));
+        DEV(hipMemcpyAsync(sim->ro_done + t * N, sim->done, N, hipMemcpyDeviceToDevice, st));
+    }
+    // the value of the state after the last step
+    if ((r = sf_observe_full(sim, nullptr, nullptr)) != SF_OK) return r;
+    {
+        ProfScope ps(sim, 5);
+        launch_actor_critic(sim->full_obs, sim->full_counts, (int)N, sim->ac_f32, sim->ac_bf16, sim->ac_mean,
+                            sim->ro_val + T * N, nullptr, sim->steer_max, st);
+    }
+    LAUNCHED();
+    sim->ro_full = true;
+    sim->adv_ready = false;
+    return SF_OK;
+}
+
+sf_status sf_ppo_advantages(sf_sim *sim) {
+    CHECK_SIM(sim);
+    if (!sim->ppo_ready || !sim->ro_full) return fail(SF_E_INVALID_ARG, "no rollout kept");
+    launch_ppo_advantages(sim->ro_rew, sim->ro_done, sim->ro_val, sim->ppo.horizon, sim->N, sim->ppo.gamma,
+                          sim->ppo.lam, sim->ro_adv, sim->ro_ret, sim->ppo_mom, sim->stream);
+    LAUNCHED();
+    sim->adv_ready = true;
+    return SF_OK;
+}
+
+// forward pass, loss and gradient of rows[0, M) into ppo_grad; stats to
+// ppo_stats (the loss statistics are read by the caller)
+static sf_status ppo_loss_stage(sf_sim *sim, const int32_t *rows, int M) {
+    hipStream_t st = sim->stream;
+    {
+        ProfScope ps(sim, 5);
+        launch_actor_critic_save(sim->ro_obs, sim->ro_cnt, rows, M, sim->ac_f32, sim->ac_bf16, sim->ppo_mean,
+                                 sim->ppo_value, sim->ppo_save, st);
+    }
+    launch_ppo_loss(rows, M, sim->ppo_mean, sim->ppo_value, sim->ro_u, sim->ro_logp, sim->ro_mu, sim->ro_adv,
+                    sim->ro_ret, sim->ac_f32, sim->ls_old, sim->ppo.clip, sim->ppo.value_coef, sim->ppo_dout,
+                    sim->ppo_lpart, sim->ppo_stats, st);
+    LAUNCHED();
+    return SF_OK;
+}
+
+static sf_status ppo_grad_stage(sf_sim *sim, const int32_t *rows, int M) {
+    hipStream_t st = sim->stream;
+    {
+        ProfScope ps(sim, 7);
+        launch_ppo_backward(sim->ro_obs, rows, M, sim->ppo_save, sim->ppo_dout, sim->ac_f32, sim->ac_bf16,
+                            sim->ppo_part, st);
+    }
+    launch_ppo_reduce(sim->ppo_part, ppo_tiles(M), sim->ppo_stats, sim->ppo.entropy_coef, sim->ppo_grad, sim->ppo_sq,
+                      st);
+    LAUNCHED();
+    return SF_OK;
+}
+
+static sf_status ppo_check_rows(sf_sim *sim, const int32_t *rows, long long n) {
+    DEV(hipMemsetAsync(sim->ppo_flag, 0, sizeof(int), sim->stream));
+    launch_ppo_check_rows(rows, n, (int)sim->ppo_TN, sim->ppo_flag, sim->stream);
+    LAUNCHED();
+    int bad = 0;
+    DEV(hipMemcpyAsync(&bad, sim->ppo_flag, sizeof(int), hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    if (bad) return fail(SF_E_INVALID_ARG, "row index outside the rollout");
+    return SF_OK;
+}
+
+sf_status sf_ppo_gradient(sf_sim *sim, const int32_t *d_rows, int32_t M, float *h_grad, double *h_stats) {
+    CHECK_SIM(sim);
+    if (!sim->ppo_ready || !sim->adv_ready) return fail(SF_E_INVALID_ARG, "sf_ppo_advantages first");
+    if (!d_rows || M < 1 || M > sim->ppo_B) return fail(SF_E_INVALID_ARG, "rows NULL or M outside 1..rows per minibatch");
+    sf_status r;
+    if ((r = ppo_check_rows(sim, d_rows, M)) != SF_OK) return r;
+    if ((r = ppo_loss_stage(sim, d_rows, M)) != SF_OK) return r;
+    if ((r = ppo_grad_stage(sim, d_rows, M)) != SF_OK) return r;
+    if (h_grad) DEV(hipMemcpyAsync(h_grad, sim->ppo_grad, sizeof(float) * SF_AC_PARAMS, hipMemcpyDeviceToHost, sim->stream));
+    if (h_stats) DEV(hipMemcpyAsync(h_stats, sim->ppo_stats, sizeof(double) * 8, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
+    return SF_OK;
+}
+
+sf_status sf_ppo_update(sf_sim *sim, const int32_t *d_perm, sf_ppo_stats *out) {
+    CHECK_SIM(sim);
+    if (!sim->ppo_ready || !sim->ro_full) return fail(SF_E_INVALID_ARG, "no rollout kept");
+    if (!d_perm) return fail(SF_E_INVALID_ARG, "perm is NULL");
+    const sf_ppo_opts &o = sim->ppo;
+    sf_status r;
+    if ((r = ppo_check_rows(sim, d_perm, (long long)o.epochs * sim->ppo_TN)) != SF_OK) return r;
+    if ((r = sf_ppo_advantages(sim)) != SF_OK) return r;
+    hipStream_t st = sim->stream;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int steps = 0;
+    for (int e = 0; e < o.epochs; ++e) {
+        for (int mb = 0; mb < o.minibatches; ++mb) {
+            const int32_t *rows = d_perm + (size_t)e * sim->ppo_TN + (size_t)mb * sim->ppo_B;
+            if ((r = ppo_loss_stage(sim, rows, sim->ppo_B)) != SF_OK) return r;
+            double stats[8];
+            DEV(hipMemcpyAsync(stats, sim->ppo_stats, sizeof(stats), hipMemcpyDeviceToHost, st));
+            DEV(hipStreamSynchronize(st));
+            // the learning rate follows the KL of this minibatch, before its step
+            const double kl = stats[2];
+            if (kl > 2.0 * o.kl_target) sim->ppo_lr = std::max(o.lr_min, sim->ppo_lr * 0.5f);
+            else if (kl < 0.5 * o.kl_target) sim->ppo_lr = std::min(o.lr_max, sim->ppo_lr * 2.f);
+            if ((r = ppo_grad_stage(sim, rows, sim->ppo_B)) != SF_OK) return r;
+            sim->ppo_t += 1;
+            const double c1 = 1.0 / (1.0 - std::pow((double)o.beta1, (double)sim->ppo_t));
+            const double c2 = 1.0 / (1.0 - std::pow((double)o.beta2, (double)sim->ppo_t));
+            launch_ppo_adam(sim->ac_f32, sim->ppo_m, sim->ppo_v, sim->ppo_grad, sim->ppo_sq, o.max_grad_norm,
+                            sim->ppo_lr, o.beta1, o.beta2, o.eps, (float)c1, (float)c2, sim->ppo_norm, st);
+            launch_ac_pack(sim->ac_f32, sim->ac_bf16, st);
+            LAUNCHED();
+            float norm = 0.f;
+            DEV(hipMemcpyAsync(&norm, sim->ppo_norm, sizeof(float), hipMemcpyDeviceToHost, st));
+            DEV(hipStreamSynchronize(st));
+            acc[0] += stats[0];
+            acc[1] += stats[1];
+            acc[2] += kl;
+            acc[3] += stats[3];
+            acc[4] += norm;
+            ++steps;
+        }
+    }
+    if (out) {
+        float ls[3];
+        DEV(hipMemcpyAsync(ls, sim->ac_f32 + ACF_LOGSTD, sizeof(ls), hipMemcpyDeviceToHost, st));
+        DEV(hipStreamSynchronize(st));
+        out->lr = sim->ppo_lr;
+        out->surrogate = (float)(acc[0] / steps);
+        out->value_loss = (float)(acc[1] / steps);
+        out->kl = (float)(acc[2] / steps);
+        out->clip_fraction = (float)(acc[3] / steps);
+        out->grad_norm = (float)(acc[4] / steps);
+        out->entropy = (float)(ls[0] + ls[1] + ls[2] + 1.5 * (1.0 + std::log(2.0 * M_PI)));
+        out->steps = steps;
+    }
+    sim->act_valid = false;
+    return SF_OK;
+}
+
+sf_status sf_ppo_read(sf_sim *sim, float *d_u, float *d_mean, float *d_logp, float *d_value, float *d_reward,
+                      uint8_t *d_done, float *d_adv, float *d_ret, float *d_obs, int32_t *d_counts) {
+    CHECK_SIM(sim);
+    if (!sim->ppo_ready || !sim->ro_full) return fail(SF_E_INVALID_ARG, "no rollout kept");
+    const size_t TN = sim->ppo_TN, N = sim->N;
+    hipStream_t st = sim->stream;
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        return dst ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+    };
+    DEV(cp(d_u, sim->ro_u, sizeof(float) * 3 * TN));
+    DEV(cp(d_mean, sim->ro_mu, sizeof(float) * 3 * TN));
+    DEV(cp(d_logp, sim->ro_logp, sizeof(float) * TN));
+    DEV(cp(d_value, sim->ro_val, sizeof(float) * (TN + N)));
+    DEV(cp(d_reward, sim->ro_rew, sizeof(float) * TN));
+    DEV(cp(d_done, sim->ro_done, TN));
+    if ((d_adv || d_ret) && !sim->adv_ready) return fail(SF_E_INVALID_ARG, "sf_ppo_advantages first");
+    DEV(cp(d_adv, sim->ro_adv, sizeof(float) * TN));
+    DEV(cp(d_ret, sim->ro_ret, sizeof(float) * TN));
+    DEV(cp(d_obs, sim->ro_obs, sizeof(float) * SF_FULL_DIM * TN));
+    DEV(cp(d_counts, sim->ro_cnt, sizeof(int) * 2 * TN));
+    return SF_OK;
+}
+
+sf_status sf_actor_critic_get(sf_sim *sim, float *h_params) {
+    CHECK_SIM(sim);
+    if (!sim->ac_loaded) return fail(SF_E_INVALID_ARG, "no actor-critic loaded");
+    if (!h_params) return fail(SF_E_INVALID_ARG, "h_params is NULL");
+    DEV(hipMemcpyAsync(h_params, sim->ac_f32, sizeof(float) * SF_AC_PARAMS, hipMemcpyDeviceToHost, sim->stream));
+    DEV(hipStreamSynchronize(sim->stream));
     return SF_OK;
 }
 

@@ -117,8 +117,8 @@ def counter_table(path: str, last: int = 20):
     return out
 
 
-KERNEL_SOURCES = {"k_obs": "k_obs.hip", "k_step": "k_step.hip", "k_policy": "k_policy.hip",
-                  "k_full": "k_full.hip"}
+KERNEL_SOURCES = {"k_obs": ("k_obs.hip",), "k_step": ("k_step.hip",), "k_policy": ("k_policy.hip",),
+                  "k_full": ("k_full.hip", "ac_layout.h"), "k_ppo": ("k_ppo.hip", "ac_layout.h")}
 
 
 def kernel_family(launch: str) -> str:
@@ -126,6 +126,8 @@ def kernel_family(launch: str) -> str:
     k_obs.hip, k_step<...> from k_step.hip, and so on."""
     if launch.startswith("k_obs_full") or launch.startswith("k_actor_critic"):
         return "k_full"
+    if launch.startswith("k_ppo"):
+        return "k_ppo"
     for fam in ("k_obs", "k_step", "k_policy"):
         if launch.startswith(fam):
             return fam
@@ -133,13 +135,14 @@ def kernel_family(launch: str) -> str:
 
 
 def kernel_source_hash(family: str) -> str:
-    """Hash of the sources a kernel family is built from (its .hip file and
-    the shared device header)."""
+    """Hash of the sources a kernel family is built from (its .hip file, the
+    layout header it reads and the shared device header; the host-side launch
+    declarations are not part of it)."""
     import hashlib
     import os
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
-    for f in (KERNEL_SOURCES[family], "sf_dev.h"):
+    for f in KERNEL_SOURCES[family] + ("sf_dev.h",):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

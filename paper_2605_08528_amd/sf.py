@@ -93,6 +93,24 @@ class SurTrainOpts(C.Structure):
     ]
 
 
+class PPOOpts(C.Structure):
+    _fields_ = [
+        ("horizon", C.c_int32), ("epochs", C.c_int32), ("minibatches", C.c_int32),
+        ("gamma", C.c_float), ("lam", C.c_float), ("clip", C.c_float), ("value_coef", C.c_float),
+        ("entropy_coef", C.c_float), ("max_grad_norm", C.c_float), ("lr", C.c_float), ("kl_target", C.c_float),
+        ("lr_min", C.c_float), ("lr_max", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+    ]
+
+
+class PPOStats(C.Structure):
+    _fields_ = [("lr", C.c_float), ("kl", C.c_float), ("surrogate", C.c_float), ("value_loss", C.c_float),
+                ("entropy", C.c_float), ("clip_fraction", C.c_float), ("grad_norm", C.c_float),
+                ("steps", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Tuning(C.Structure):
     _fields_ = [("step_block", C.c_int32), ("step_grid", C.c_int32), ("obs_waves", C.c_int32),
                 ("policy_rows", C.c_int32), ("step_us", C.c_float), ("obs_us", C.c_float),
@@ -138,6 +156,14 @@ def lib():
         L.sf_actor_critic.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.sf_step_actor_critic.argtypes = [vp, C.c_float, i32]
         L.sf_actor_critic_read.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.sf_ppo_default_opts.argtypes = [C.POINTER(PPOOpts)]
+        L.sf_ppo_init.argtypes = [vp, C.POINTER(PPOOpts)]
+        L.sf_ppo_rollout.argtypes = [vp, C.c_float, i32, vp]
+        L.sf_ppo_advantages.argtypes = [vp]
+        L.sf_ppo_update.argtypes = [vp, vp, C.POINTER(PPOStats)]
+        L.sf_ppo_gradient.argtypes = [vp, vp, i32, vp, vp]
+        L.sf_ppo_read.argtypes = [vp] + [vp] * 10
+        L.sf_actor_critic_get.argtypes = [vp, vp]
         L.sf_set_triangle_friction.argtypes = [vp, vp]
         L.sf_state_bytes.argtypes = [vp]
         L.sf_state_bytes.restype = C.c_size_t
@@ -173,7 +199,8 @@ def lib():
         L.sf_last_error.restype = C.c_char_p
         for name in ("sf_default_params", "sf_default_options", "sf_create", "sf_destroy", "sf_info",
                      "sf_step", "sf_observe", "sf_output_ptrs", "sf_reset", "sf_contact_overflows",
-                     "sf_road_touch", "sf_road_touch_read", "sf_set_dynamics", "sf_set_shaping", "sf_profile_calibrate", "sf_set_triangle_friction",
+                     "sf_road_touch", "sf_road_touch_read", "sf_set_dynamics", "sf_set_shaping", "sf_ppo_default_opts", "sf_ppo_init", "sf_ppo_rollout",
+                     "sf_ppo_advantages", "sf_ppo_update", "sf_ppo_gradient", "sf_ppo_read", "sf_actor_critic_get", "sf_profile_calibrate", "sf_set_triangle_friction",
                      "sf_observe_full", "sf_actor_critic_load", "sf_actor_critic", "sf_step_actor_critic",
                      "sf_actor_critic_read",
                      "sf_get_state",
@@ -396,6 +423,68 @@ class Sim:
               "sf_actor_critic_read")
         return mean, value, act, obs, cnt
 
+    def actor_critic_get(self):
+        P = np.zeros(AC_PARAMS, np.float32)
+        check(lib().sf_actor_critic_get(self.h, _ptr(P)), "sf_actor_critic_get")
+        return P
+
+    # on-device PPO -------------------------------------------------------
+    @staticmethod
+    def ppo_default_opts() -> dict:
+        o = PPOOpts()
+        check(lib().sf_ppo_default_opts(C.byref(o)), "sf_ppo_default_opts")
+        return {k: getattr(o, k) for k, _ in PPOOpts._fields_}
+
+    def ppo_init(self, **over) -> dict:
+        d = self.ppo_default_opts()
+        d.update(over)
+        o = PPOOpts(**d)
+        check(lib().sf_ppo_init(self.h, C.byref(o)), "sf_ppo_init")
+        self.ppo_opts = d
+        return d
+
+    def ppo_rollout(self, eps, dt: float, substeps: int) -> None:
+        """eps: CUDA float32 [T, N, 3] standard normals."""
+        T = self.ppo_opts["horizon"]
+        assert tuple(eps.shape) == (T, self.N, 3) and eps.dtype == self.torch.float32
+        check(lib().sf_ppo_rollout(self.h, float(dt), int(substeps), _tptr(eps.contiguous())), "sf_ppo_rollout")
+
+    def ppo_advantages(self) -> None:
+        check(lib().sf_ppo_advantages(self.h), "sf_ppo_advantages")
+
+    def ppo_update(self, perm) -> dict:
+        """perm: CUDA int32 [epochs, N T], each row a permutation."""
+        o = self.ppo_opts
+        assert tuple(perm.shape) == (o["epochs"], o["horizon"] * self.N) and perm.dtype == self.torch.int32
+        st = PPOStats()
+        check(lib().sf_ppo_update(self.h, _tptr(perm.contiguous()), C.byref(st)), "sf_ppo_update")
+        return st.as_dict()
+
+    def ppo_gradient(self, rows):
+        """(grad [AC_PARAMS] float32, stats [8] float64) on CUDA int32 rows."""
+        g = np.zeros(AC_PARAMS, np.float32)
+        st = np.zeros(8, np.float64)
+        check(lib().sf_ppo_gradient(self.h, _tptr(rows.contiguous()), int(rows.numel()), _ptr(g), _ptr(st)),
+              "sf_ppo_gradient")
+        return g, st
+
+    def ppo_read(self, advantages: bool = True) -> dict:
+        """CUDA copies of the kept rollout."""
+        t = self.torch
+        dev = t.device("cuda", t.cuda.current_device())
+        T, N = self.ppo_opts["horizon"], self.N
+        f = lambda *shape: t.empty(shape, dtype=t.float32, device=dev)
+        out = {"u": f(T, N, 3), "mean": f(T, N, 3), "logp": f(T, N), "value": f(T + 1, N), "reward": f(T, N),
+               "done": t.empty((T, N), dtype=t.uint8, device=dev), "obs": f(T, N, FULL_DIM),
+               "counts": t.empty((T, N, 2), dtype=t.int32, device=dev)}
+        if advantages:
+            out["adv"], out["ret"] = f(T, N), f(T, N)
+        check(lib().sf_ppo_read(self.h, _tptr(out["u"]), _tptr(out["mean"]), _tptr(out["logp"]),
+                                _tptr(out["value"]), _tptr(out["reward"]), _tptr(out["done"]),
+                                _tptr(out["adv"]) if advantages else None, _tptr(out["ret"]) if advantages else None,
+                                _tptr(out["obs"]), _tptr(out["counts"])), "sf_ppo_read")
+        return out
+
     def set_dynamics(self, mode: str) -> None:
         """'physics' (the articulated vehicle) or 'bicycle' (kinematic model)."""
         check(lib().sf_set_dynamics(self.h, {"physics": 0, "bicycle": 1}[mode]), "sf_set_dynamics")
@@ -477,12 +566,14 @@ class Sim:
 
     def profile_read(self):
         """{kernel: (total_ms, launches)} for policy, step, obs, reset, the
-        paper-shaped observation, the actor-critic and the clock kernels."""
-        ms = np.zeros(7, np.float64)
-        n = np.zeros(7, np.int32)
+        paper-shaped observation, the actor-critic, the clock kernels and the PPO
+        backward pass."""
+        ms = np.zeros(8, np.float64)
+        n = np.zeros(8, np.int32)
         check(lib().sf_profile_read(self.h, _ptr(ms), _ptr(n)), "sf_profile_read")
         return {k: (float(ms[i]), int(n[i]))
-                for i, k in enumerate(("policy", "step", "obs", "reset", "obs_full", "actor_critic", "clock"))}
+                for i, k in enumerate(("policy", "step", "obs", "reset", "obs_full", "actor_critic", "clock",
+                                       "ppo_backward"))}
 
     def profile_calibrate(self, n: int = 20, us: float = 50.0) -> None:
         """n wall-clock kernels of `us` microseconds timed like the others."""
