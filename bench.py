@@ -381,6 +381,62 @@ def ac_flop(counts: np.ndarray) -> float:
     return float(2.0 * (2 * per_net.sum() + len(nr) * 64 * (3 + 1)))
 
 
+def ppo_leg(torch, sf, I, stream, workload, horizon, iters, seed=0):
+    """On-device PPO with the paper's hyperparameters (horizon, 5 epochs x 16
+    minibatches, dense shaping rewards on): `iters` iterations after one
+    untimed, each a rollout of `horizon` control steps and the update, timed
+    with HIP events; training CASPS = agents x horizon / iteration time, the
+    quantity the paper's throughput is (it measures during PPO training).
+    Per-kernel durations from a profiled iteration."""
+    w = I.workload(workload, seed=seed)
+    dt, S = I.TIMING[workload]
+    with torch.cuda.stream(stream):
+        sim = sf.Sim(w, dict(I.VEHICLE_DEFAULTS), flags=sf.SF_AUTO_RESET, stream=stream)
+        rng = np.random.default_rng(seed)
+        P = (rng.standard_normal(sf.AC_PARAMS) * 0.1).astype(np.float32)
+        sim.actor_critic_load(P)
+        sim.set_shaping(True)
+        opts = sim.ppo_init(horizon=horizon)
+        N, TN = sim.N, horizon * sim.N
+        g = torch.Generator(device="cuda").manual_seed(seed)
+
+        def iteration():
+            eps = torch.randn((horizon, N, 3), generator=g, device="cuda", dtype=torch.float32)
+            perm = torch.stack([torch.randperm(TN, generator=g, device="cuda") for _ in range(opts["epochs"])])
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            sim.ppo_rollout(eps, dt, S)
+            e1.record(stream)
+            st = sim.ppo_update(perm.to(torch.int32))
+            e2.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1), e1.elapsed_time(e2), st
+
+        iteration()                                   # untimed
+        sim.profile(True)
+        iteration()
+        torch.cuda.synchronize()
+        ev, fixed = read_profile(sim)
+        times = [iteration() for _ in range(iters)]
+        sim.close()
+    roll = float(np.mean([t[0] for t in times]))
+    upd = float(np.mean([t[1] for t in times]))
+    us = kernel_us(ev, fixed)
+    last = times[-1][2]
+    return {"workload": workload, "agents": N, "horizon": horizon, "epochs": opts["epochs"],
+            "minibatches": opts["minibatches"], "rows_per_minibatch": TN // opts["minibatches"],
+            "iterations_timed": iters, "rollout_ms": roll, "update_ms": upd,
+            "training_casps": TN / ((roll + upd) * 1e-3), "rollout_casps": TN / (roll * 1e-3),
+            "kernels_us": us,
+            "per_minibatch_us": {"forward_with_save": us.get("actor_critic", 0.0),
+                                 "backward": us.get("ppo_backward", 0.0)},
+            "last_update": last,
+            "note": "rollout: observation, actor-critic, sampling, physics step per control step (eager); update: "
+                    "advantages, then per minibatch the forward pass with saved activations, loss, backward, "
+                    "reduction, clip and Adam; one host synchronisation per minibatch (the KL-adaptive rate); "
+                    "actor_critic in kernels_us mixes rollout (4096 rows) and update (32768 rows) launches"}
+
+
 def full_obs_leg(torch, sf, I, stream, workload, steps, seed=0):
     """The paper-shaped observation (1929 floats per agent) and the
     late-fusion actor-critic (seeded random weights) driving the physics
@@ -587,6 +643,9 @@ def main():
     ap.add_argument("--configs", default="cross1024x16,dense4096x32",
                     help="other workload sizes reported as context (empty: none)")
     ap.add_argument("--config-steps", type=int, default=300)
+    ap.add_argument("--ppo-iters", type=int, default=2,
+                    help="timed PPO iterations on the workload (0: no PPO leg)")
+    ap.add_argument("--ppo-horizon", type=int, default=128)
     ap.add_argument("--full-obs-steps", type=int, default=100,
                     help="control steps of the paper-shaped observation + actor-critic leg (0: none)")
     args = ap.parse_args()
@@ -622,6 +681,12 @@ def main():
 
     # ---- the other workload sizes (context, not the headline value)
     others = {}
+    if args.ppo_iters > 0:
+        others["ppo_" + args.workload] = ppo_leg(torch, sf, I, stream, args.workload, args.ppo_horizon,
+                                                 args.ppo_iters, args.seed)
+        log(f"ppo on {args.workload}: {others['ppo_' + args.workload]['training_casps']:.4g} training CASPS "
+            f"(rollout {others['ppo_' + args.workload]['rollout_ms']:.1f} ms, update "
+            f"{others['ppo_' + args.workload]['update_ms']:.1f} ms per iteration)")
     if args.full_obs_steps > 0:
         others["full_obs_" + args.workload] = full_obs_leg(torch, sf, I, stream, args.workload,
                                                            args.full_obs_steps, args.seed)

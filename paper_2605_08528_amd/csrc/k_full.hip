@@ -255,7 +255,8 @@ void launch_ac_pack(const float *Pf, uint16_t *Wb, hipStream_t s) {
     k_ac_pack<<<(2 * ACB_NET + 255) / 256, 256, 0, s>>>(Pf, Wb);
 }
 
-#define AC_AGENTS 16          // agents per workgroup (4 waves, 4 agents each)
+#define AC_AGENTS 8           // agents per workgroup (4 waves, 2 agents each; two workgroups per CU)
+#define AC_ROWS 16            // rows of the trunk's matrix tiles (those past AC_AGENTS are zero)
 #define AC_W2LD 104           // padded LDS row of a 96-wide bf16 matrix
 #define AC_HLD 104            // padded row of the 32-point activation tile
 #define AC_ELD 264            // padded embedding row (256)
@@ -381,18 +382,17 @@ __device__ __forceinline__ void set_encoder(const float *__restrict__ x, int row
 // embedding, and for each pooled feature the slot it came from.  rows (or
 // null): row n reads the observation of sample rows[n].
 template <bool SAVE>
-__global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ obs, const int *__restrict__ counts,
+__device__ __forceinline__ void actor_critic_body(const float *__restrict__ obs, const int *__restrict__ counts,
                                                       const int *__restrict__ rows, int N,
                                                       const float *__restrict__ Pf,
                                                       const uint16_t *__restrict__ Wb, float *__restrict__ mean,
                                                       float *__restrict__ value, float *__restrict__ act,
                                                       float steer_max, float *__restrict__ save) {
-    __shared__ __attribute__((aligned(16))) uint16_t s_rw2[96 * AC_W2LD];
-    __shared__ __attribute__((aligned(16))) uint16_t s_vw2[96 * AC_W2LD];
+    __shared__ __attribute__((aligned(16))) uint16_t s_w2[96 * AC_W2LD];   // one set encoder's W2 at a time
     __shared__ __attribute__((aligned(16))) uint16_t s_h[4][32 * AC_HLD];
-    __shared__ __attribute__((aligned(16))) uint16_t s_emb[AC_AGENTS * AC_ELD];
-    __shared__ __attribute__((aligned(16))) uint16_t s_t1[AC_AGENTS * AC_TLD];
-    __shared__ __attribute__((aligned(16))) uint16_t s_t2[AC_AGENTS * 72];
+    __shared__ __attribute__((aligned(16))) uint16_t s_emb[AC_ROWS * AC_ELD];
+    __shared__ __attribute__((aligned(16))) uint16_t s_t1[AC_ROWS * AC_TLD];
+    __shared__ __attribute__((aligned(16))) uint16_t s_t2[AC_ROWS * 72];
     __shared__ float s_ego[4][64];
     __shared__ float s_mean[AC_AGENTS][3];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, kq = lane >> 4;
@@ -400,76 +400,100 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
     for (int net = 0; net < 2; ++net) {
         const float *F = Pf + (size_t)net * (SF_AC_BODY + 3 * 64 + 3 + 3);
         const uint16_t *B = Wb + (size_t)net * ACB_NET;
-        // the encoders' 96 x 96 matrices into LDS (padded rows)
+        // the road encoder's 96 x 96 matrix into LDS (padded rows); the
+        // vehicle encoder's takes its place after the road pass
         for (int e = tid; e < 96 * 12; e += 256) {
             const int r = e / 12, c = (e % 12) * 8;
-            *reinterpret_cast<uint4 *>(s_rw2 + r * AC_W2LD + c) = *reinterpret_cast<const uint4 *>(B + ACB_RW2 + r * 96 + c);
-            *reinterpret_cast<uint4 *>(s_vw2 + r * AC_W2LD + c) = *reinterpret_cast<const uint4 *>(B + ACB_VW2 + r * 96 + c);
+            *reinterpret_cast<uint4 *>(s_w2 + r * AC_W2LD + c) = *reinterpret_cast<const uint4 *>(B + ACB_RW2 + r * 96 + c);
         }
-        // first-layer fragments of both set encoders (rows 16 ft + r16,
-        // inputs 0..7 in the first quarter of the lanes, zero elsewhere)
-        bf16x8 rw1[6], vw1[6];
+        // the trunk tiles' rows past the workgroup's agents stay zero
+        for (int e = tid; e < (AC_ROWS - AC_AGENTS) * AC_ELD; e += 256) s_emb[AC_AGENTS * AC_ELD + e] = 0;
+        __syncthreads();
+        // ---- ego and road encoders: wave wv, its agents one after the other
+        {
+            // first-layer fragments (rows 16 ft + r16, inputs 0..7 in the
+            // first quarter of the lanes, zero elsewhere)
+            bf16x8 rw1[6];
 #pragma unroll
-        for (int ft = 0; ft < 6; ++ft) {
-            rw1[ft] = kq == 0 ? ld8(B + ACB_RW1 + (16 * ft + r16) * 8) : zero8();
-            vw1[ft] = kq == 0 ? ld8(B + ACB_VW1 + (16 * ft + r16) * 8) : zero8();
+            for (int ft = 0; ft < 6; ++ft) rw1[ft] = kq == 0 ? ld8(B + ACB_RW1 + (16 * ft + r16) * 8) : zero8();
+            for (int t = 0; t < AC_AGENTS / 4; ++t) {
+                const int a = wv * (AC_AGENTS / 4) + t, n = n0 + a;
+                uint16_t *emb = s_emb + a * AC_ELD;
+                if (n >= N) {
+                    for (int k = lane; k < 256; k += 64) emb[k] = 0;
+                    continue;
+                }
+                const int src = rows ? rows[n] : n;
+                const float *o = obs + (size_t)src * FULL_DIM;
+                const int nr = counts[2 * src];
+                float *sv = SAVE ? save + (size_t)n * AC_SAVE_ROW + net * AC_SAVE : nullptr;
+                // ego 11 -> 64 -> 64 (lane = feature)
+                {
+                    float acc = F[ACF_EB1 + lane];
+                    for (int k = 0; k < 11; ++k) acc += bf2f(B[ACB_EW1 + lane * 12 + k]) * bfr(o[k]);
+                    s_ego[wv][lane] = bfr(elu_fast(acc));
+                    wave_sync();
+                    float acc2 = F[ACF_EB2 + lane];
+                    const uint16_t *w2 = B + ACB_EW2 + lane * 64;
+                    for (int k = 0; k < 64; ++k) acc2 += bf2f(w2[k]) * s_ego[wv][k];
+                    emb[lane] = f2bf(elu_fast(acc2));
+                    if (SAVE) {
+                        sv[AC_SAVE_ZE1 + lane] = acc;
+                        sv[AC_SAVE_ZE2 + lane] = acc2;
+                    }
+                    wave_sync();
+                }
+                float pool[6][4];
+                int amax[6][4];
+                set_encoder<5, SAVE>(o + FULL_EGO, min(nr, FULL_RK), rw1, F + ACF_RB1, s_w2, F + ACF_RB2, s_h[wv],
+                                     pool, amax);
+                if (r16 == 0) {
+#pragma unroll
+                    for (int ft = 0; ft < 6; ++ft)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            emb[64 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
+                            if (SAVE) sv[AC_SAVE_AR + 16 * ft + 4 * kq + j] = __int_as_float(amax[ft][j]);
+                        }
+                }
+            }
         }
         __syncthreads();
-        // ---- encoders: wave wv, its four agents one after the other
-        for (int t = 0; t < 4; ++t) {
-            const int a = wv * 4 + t, n = n0 + a;
-            uint16_t *emb = s_emb + a * AC_ELD;
-            if (n >= N) {
-                for (int k = lane; k < 256; k += 64) emb[k] = 0;
-                continue;
-            }
-            const int src = rows ? rows[n] : n;
-            const float *o = obs + (size_t)src * FULL_DIM;
-            const int nr = counts[2 * src], nv = counts[2 * src + 1];
-            float *sv = SAVE ? save + (size_t)n * AC_SAVE_ROW + net * AC_SAVE : nullptr;
-            // ego 11 -> 64 -> 64 (lane = feature)
-            {
-                float acc = F[ACF_EB1 + lane];
-                for (int k = 0; k < 11; ++k) acc += bf2f(B[ACB_EW1 + lane * 12 + k]) * bfr(o[k]);
-                s_ego[wv][lane] = bfr(elu_fast(acc));
-                wave_sync();
-                float acc2 = F[ACF_EB2 + lane];
-                const uint16_t *w2 = B + ACB_EW2 + lane * 64;
-                for (int k = 0; k < 64; ++k) acc2 += bf2f(w2[k]) * s_ego[wv][k];
-                emb[lane] = f2bf(elu_fast(acc2));
-                if (SAVE) {
-                    sv[AC_SAVE_ZE1 + lane] = acc;
-                    sv[AC_SAVE_ZE2 + lane] = acc2;
+        for (int e = tid; e < 96 * 12; e += 256) {
+            const int r = e / 12, c = (e % 12) * 8;
+            *reinterpret_cast<uint4 *>(s_w2 + r * AC_W2LD + c) = *reinterpret_cast<const uint4 *>(B + ACB_VW2 + r * 96 + c);
+        }
+        __syncthreads();
+        // ---- vehicle encoder
+        {
+            bf16x8 vw1[6];
+#pragma unroll
+            for (int ft = 0; ft < 6; ++ft) vw1[ft] = kq == 0 ? ld8(B + ACB_VW1 + (16 * ft + r16) * 8) : zero8();
+            for (int t = 0; t < AC_AGENTS / 4; ++t) {
+                const int a = wv * (AC_AGENTS / 4) + t, n = n0 + a;
+                if (n >= N) continue;
+                uint16_t *emb = s_emb + a * AC_ELD;
+                const int src = rows ? rows[n] : n;
+                const float *o = obs + (size_t)src * FULL_DIM;
+                const int nv = counts[2 * src + 1];
+                float *sv = SAVE ? save + (size_t)n * AC_SAVE_ROW + net * AC_SAVE : nullptr;
+                float pool[6][4];
+                int amax[6][4];
+                set_encoder<7, SAVE>(o + FULL_EGO + 5 * FULL_RK, min(nv, FULL_VK), vw1, F + ACF_VB1, s_w2, F + ACF_VB2,
+                                     s_h[wv], pool, amax);
+                if (r16 == 0) {
+#pragma unroll
+                    for (int ft = 0; ft < 6; ++ft)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            emb[160 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
+                            if (SAVE) sv[AC_SAVE_AV + 16 * ft + 4 * kq + j] = __int_as_float(amax[ft][j]);
+                        }
                 }
-                wave_sync();
-            }
-            float pool[6][4];
-            int amax[6][4];
-            set_encoder<5, SAVE>(o + FULL_EGO, min(nr, FULL_RK), rw1, F + ACF_RB1, s_rw2, F + ACF_RB2, s_h[wv], pool,
-                                 amax);
-            if (r16 == 0) {
-#pragma unroll
-                for (int ft = 0; ft < 6; ++ft)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        emb[64 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
-                        if (SAVE) sv[AC_SAVE_AR + 16 * ft + 4 * kq + j] = __int_as_float(amax[ft][j]);
-                    }
-            }
-            set_encoder<7, SAVE>(o + FULL_EGO + 5 * FULL_RK, min(nv, FULL_VK), vw1, F + ACF_VB1, s_vw2, F + ACF_VB2,
-                                 s_h[wv], pool, amax);
-            if (r16 == 0) {
-#pragma unroll
-                for (int ft = 0; ft < 6; ++ft)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        emb[160 + 16 * ft + 4 * kq + j] = f2bf(pool[ft][j]);
-                        if (SAVE) sv[AC_SAVE_AV + 16 * ft + 4 * kq + j] = __int_as_float(amax[ft][j]);
-                    }
-            }
-            if (SAVE) {
-                wave_sync();
-                for (int k = lane; k < 256; k += 64) sv[AC_SAVE_EMB + k] = bf2f(emb[k]);
+                if (SAVE) {
+                    wave_sync();
+                    for (int k = lane; k < 256; k += 64) sv[AC_SAVE_EMB + k] = bf2f(emb[k]);
+                }
             }
         }
         __syncthreads();
@@ -493,7 +517,7 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     s_t1[(4 * kq + j) * AC_TLD + col] = f2bf(elu_fast(acc[c][j] + bb));
-                    if (SAVE && n0 + 4 * kq + j < N)
+                    if (SAVE && 4 * kq + j < AC_AGENTS && n0 + 4 * kq + j < N)
                         save[(size_t)(n0 + 4 * kq + j) * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZT1 + col] = acc[c][j] + bb;
                 }
             }
@@ -514,7 +538,7 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 s_t2[(4 * kq + j) * 72 + col] = f2bf(elu_fast(acc[j] + bb));
-                if (SAVE && n0 + 4 * kq + j < N)
+                if (SAVE && 4 * kq + j < AC_AGENTS && n0 + 4 * kq + j < N)
                     save[(size_t)(n0 + 4 * kq + j) * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZT2 + col] = acc[j] + bb;
             }
         }
@@ -549,16 +573,36 @@ __global__ __launch_bounds__(256) void k_actor_critic(const float *__restrict__ 
     }
 }
 
+// inference: two workgroups per CU (the registers fit without spilling)
+__global__ __launch_bounds__(256, 2) void k_actor_critic(const float *__restrict__ obs,
+                                                         const int *__restrict__ counts, int N,
+                                                         const float *__restrict__ Pf,
+                                                         const uint16_t *__restrict__ Wb, float *__restrict__ mean,
+                                                         float *__restrict__ value, float *__restrict__ act,
+                                                         float steer_max) {
+    actor_critic_body<false>(obs, counts, nullptr, N, Pf, Wb, mean, value, act, steer_max, nullptr);
+}
+
+// the training forward pass (pooled slots in registers: one workgroup per CU)
+__global__ __launch_bounds__(256) void k_actor_critic_save(const float *__restrict__ obs,
+                                                           const int *__restrict__ counts,
+                                                           const int *__restrict__ rows, int M,
+                                                           const float *__restrict__ Pf,
+                                                           const uint16_t *__restrict__ Wb, float *__restrict__ mean,
+                                                           float *__restrict__ value, float *__restrict__ save) {
+    actor_critic_body<true>(obs, counts, rows, M, Pf, Wb, mean, value, nullptr, 0.f, save);
+}
+
 void launch_actor_critic(const float *obs, const int *counts, int N, const float *Pf, const uint16_t *Wb,
                          float *mean, float *value, float *act, float steer_max, hipStream_t s) {
     if (N == 0) return;
-    sf_launch(k_actor_critic<false>, dim3((N + AC_AGENTS - 1) / AC_AGENTS), dim3(256), 0, s, obs, counts,
-              (const int *)nullptr, N, Pf, Wb, mean, value, act, steer_max, (float *)nullptr);
+    sf_launch(k_actor_critic, dim3((N + AC_AGENTS - 1) / AC_AGENTS), dim3(256), 0, s, obs, counts, N, Pf, Wb, mean,
+              value, act, steer_max);
 }
 
 void launch_actor_critic_save(const float *obs, const int *counts, const int *rows, int M, const float *Pf,
                               const uint16_t *Wb, float *mean, float *value, float *save, hipStream_t s) {
     if (M == 0) return;
-    sf_launch(k_actor_critic<true>, dim3((M + AC_AGENTS - 1) / AC_AGENTS), dim3(256), 0, s, obs, counts, rows, M, Pf,
-              Wb, mean, value, (float *)nullptr, 0.f, save);
+    sf_launch(k_actor_critic_save, dim3((M + AC_AGENTS - 1) / AC_AGENTS), dim3(256), 0, s, obs, counts, rows, M, Pf,
+              Wb, mean, value, save);
 }

@@ -272,32 +272,41 @@ __device__ __forceinline__ void sur_layer32(uint16_t *buf, const uint16_t *W, in
     wave_sync();
 }
 
-// The learned tire model on the 64 wheels of one wave, in two passes of 32
-// rows (a pass is skipped when none of its wheels is inside the envelope):
-// bf16 inputs and weights on the matrix cores, fp32 accumulation.  The
-// 3-wide output layer is a product against W4 padded to 16 rows; its fp32
-// results go to the row's padding columns, where the row's lane reads them.
-// Lanes outside the domain run with zero inputs and ignore y.
+// The learned tire model on the wheels of one wave that are inside its
+// domain, compacted: the k-th such wheel (in lane order) takes row k % 32 of
+// pass k / 32, so that a wave runs one 32-row pass per 32 wheels that use
+// the network (none when no wheel does) and a row's result does not depend
+// on the pass it lands in; bf16 inputs and weights on the matrix cores,
+// fp32 accumulation.  The 3-wide output layer is a product against W4
+// padded to 16 rows; its fp32 results go to the row's padding columns,
+// where the row's lane reads them.  Lanes outside the domain ignore y.
 __device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool inside, const uint16_t *Wl,
                              const float *bl, float (&y)[3]) {
-    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4, row = lane & 31;
+    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
     const unsigned long long any = __ballot(inside);
+    const int cnt = __popcll(any);
+    const int pos = __popcll(any & ((1ull << lane) - 1ull));    // rank among the inside lanes
     y[0] = y[1] = y[2] = 0.f;
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) {
-        if (!(half ? (any >> 32) : (any & 0xFFFFFFFFull))) continue;
-        if ((lane >> 5) == half) {
+        const int rows = min(cnt - 32 * half, 32);
+        if (rows <= 0) break;
+        if (inside && (pos >> 5) == half) {
             bf16x8 v0, v1;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                v0[q] = (__bf16)(inside ? feat[q] : 0.f);
-                v1[q] = (__bf16)(inside ? feat[8 + q] : 0.f);
+                v0[q] = (__bf16)feat[q];
+                v1[q] = (__bf16)feat[8 + q];
             }
-            bf16x8 *d = reinterpret_cast<bf16x8 *>(buf + row * SUR_LD);
+            bf16x8 *d = reinterpret_cast<bf16x8 *>(buf + (pos & 31) * SUR_LD);
             d[0] = v0;
             d[1] = v1;
             d[2] = zero8();
             d[3] = zero8();
+        } else if (lane < 32 && lane >= rows) {
+            // rows no wheel takes in this pass: zero inputs
+            bf16x8 *d = reinterpret_cast<bf16x8 *>(buf + lane * SUR_LD);
+            d[0] = d[1] = d[2] = d[3] = zero8();
         }
         wave_sync();
         sur_layer32<1>(buf, Wl, SURW_LD1, bl);
@@ -322,8 +331,8 @@ __device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool
             }
         }
         wave_sync();
-        if ((lane >> 5) == half) {
-            const float *yo = reinterpret_cast<const float *>(buf + row * SUR_LD + 128);
+        if (inside && (pos >> 5) == half) {
+            const float *yo = reinterpret_cast<const float *>(buf + (pos & 31) * SUR_LD + 128);
             y[0] = yo[0];
             y[1] = yo[1];
             y[2] = yo[2];
