@@ -236,10 +236,13 @@ void launch_ppo_loss(const int *rows, int B, const float *mean_new, const float 
 
 // ----------------------------------------------------------------- backward
 // LDS of one tile (floats).  Dense phase: the 16 rows' output gradients,
-// activations and back-propagated vectors; encoder phase: per channel the
-// layer-1 activations of the slot it pooled from (bf16), their ELU
-// derivatives, the slot's inputs and the channel's layer-2 gradient.  The
-// embedding gradient stays at the front through both.
+// activations and back-propagated vectors; encoder phase: the encoder's
+// weights (bf16, W2 rows padded to 98 so that the lanes of a wave read
+// different banks) and biases, per channel the layer-1 activations of the
+// slot it pooled from (bf16), their ELU derivatives, the slot's inputs and
+// the channel's layer-2 gradient.  The embedding gradient stays at the
+// front through both.
+#define W2P 98
 #define BW_DEMB 0
 #define BW_DENSE (BW_DEMB + PPO_TILE * 256)
 #define BW_DO (BW_DENSE)
@@ -253,10 +256,19 @@ void launch_ppo_loss(const int *rows, int B, const float *mean_new, const float 
 #define BW_DZE1 (BW_DZE2 + PPO_TILE * 64)
 #define BW_XEGO (BW_DZE1 + PPO_TILE * 64)
 #define BW_DENSE_END (BW_XEGO + PPO_TILE * 12)
-#define BW_H (BW_DENSE)                       // 96 x 96 bf16 = 4608 floats
-#define BW_D1 (BW_H + 96 * 96 / 2)
-#define BW_X (BW_D1 + 96 * 96)
-#define BW_DZ (BW_X + 96 * 8)
+#define BW_W2 (BW_DENSE)                      // 96 x 98 bf16 = 4704 floats
+#define BW_W1 (BW_W2 + 96 * W2P / 2)          // 96 x 8 bf16 = 384 floats
+#define BW_B1 (BW_W1 + 96 * 8 / 2)
+#define BW_B2 (BW_B1 + 96)
+// per-channel rows padded to odd word pitches, so that the 64 lanes of a
+// wave, one channel each, write their rows through different banks
+#define HP 98                                 // bf16 per H row (49 words)
+#define DP 97                                 // floats per D1 row
+#define XP 9                                  // floats per X row
+#define BW_H (BW_B2 + 96)                     // 96 x 98 bf16 = 4704 floats
+#define BW_D1 (BW_H + 96 * HP / 2)
+#define BW_X (BW_D1 + 96 * DP)
+#define BW_DZ (BW_X + 96 * XP)
 #define BW_ENC_END (BW_DZ + 96)
 #define BW_FLOATS (BW_DENSE_END > BW_ENC_END ? BW_DENSE_END : BW_ENC_END)
 
@@ -270,8 +282,17 @@ __device__ void encoder_backward(float *sm, const float *__restrict__ obs, const
                                  const uint16_t *__restrict__ bw1, const uint16_t *__restrict__ bw2,
                                  float *__restrict__ g) {
     const int tid = threadIdx.x;
+    uint16_t *W2 = reinterpret_cast<uint16_t *>(sm + BW_W2), *W1 = reinterpret_cast<uint16_t *>(sm + BW_W1);
     uint16_t *H = reinterpret_cast<uint16_t *>(sm + BW_H);
-    float *D1 = sm + BW_D1, *X = sm + BW_X, *DZ = sm + BW_DZ;
+    float *B1 = sm + BW_B1, *B2 = sm + BW_B2, *D1 = sm + BW_D1, *X = sm + BW_X, *DZ = sm + BW_DZ;
+    // the encoder's weights and biases into LDS
+    for (int e = tid; e < 96 * 96; e += 256) W2[(e / 96) * W2P + e % 96] = bw2[e];
+    for (int e = tid; e < 96 * 8; e += 256) W1[e] = bw1[e];
+    if (tid < 96) {
+        B1[tid] = F[fb1 + tid];
+        B2[tid] = F[fb2 + tid];
+    }
+    __syncthreads();
     float acc2[36];
 #pragma unroll
     for (int i = 0; i < 36; ++i) acc2[i] = 0.f;
@@ -279,67 +300,66 @@ __device__ void encoder_backward(float *sm, const float *__restrict__ obs, const
     float acc1[(N1 + 255) / 256];
 #pragma unroll
     for (int i = 0; i < (N1 + 255) / 256; ++i) acc1[i] = 0.f;
+    __shared__ int s_slot[96];
     for (int s = 0; s < PPO_TILE; ++s) {
         const int r = r0 + s;
         if (r >= B) break;
+        // the slot each channel pooled from and that slot's inputs
         if (tid < 96) {
             const int c = tid;
             const int slot = __float_as_int(save[(size_t)r * AC_SAVE_ROW + net * AC_SAVE + soff + c]);
-            float dz = 0.f;
-            if (slot < 0) {
-                // an empty set: no gradient, and no stale values in its rows
-                for (int j = 0; j < 96; ++j) {
-                    H[c * 96 + j] = 0;
-                    D1[c * 96 + j] = 0.f;
-                }
-                for (int k = 0; k < 8; ++k) X[c * 8 + k] = 0.f;
-            } else {
-                const float *xs = obs + (size_t)rows[r] * SF_FULL_DIM + xoff + (size_t)slot * K1;
-                float x[K1];
+            s_slot[c] = slot;
+            const float *xs = obs + (size_t)rows[r] * SF_FULL_DIM + xoff + (size_t)(slot < 0 ? 0 : slot) * K1;
 #pragma unroll
-                for (int k = 0; k < K1; ++k) {
-                    x[k] = bfr1(xs[k]);
-                    X[c * 8 + k] = x[k];
-                }
-                float z2 = F[fb2 + c];
-                const uint16_t *w2r = bw2 + c * 96;
-                for (int j = 0; j < 96; ++j) {
-                    float z1 = F[fb1 + j];
-#pragma unroll
-                    for (int k = 0; k < K1; ++k) z1 += bf2f(bw1[j * 8 + k]) * x[k];
-                    const uint16_t h = f2bf(eluf(z1));
-                    H[c * 96 + j] = h;
-                    D1[c * 96 + j] = elu_d(z1);
-                    z2 += bf2f(w2r[j]) * bf2f(h);
-                }
-                dz = sm[BW_DEMB + s * 256 + eoff + c] * elu_d(z2);
-            }
-            DZ[c] = dz;
+            for (int k = 0; k < K1; ++k) X[c * XP + k] = slot < 0 ? 0.f : bfr1(xs[k]);
         }
         __syncthreads();
-        // layer 2 weights: thread-owned entries e = tid + 256 i (c = e / 96)
+        // layer 1 of channel c's slot, feature j, for every (c, j)
+#pragma unroll 4
+        for (int i = 0; i < 36; ++i) {
+            const int e = tid + 256 * i, c = e / 96, j = e - 96 * c;
+            float z1 = B1[j];
+#pragma unroll
+            for (int k = 0; k < K1; ++k) z1 += bf2f(W1[j * 8 + k]) * X[c * XP + k];
+            H[c * HP + j] = f2bf(eluf(z1));
+            D1[c * DP + j] = elu_d(z1);
+        }
+        __syncthreads();
+        // channel c's layer-2 pre-activation and gradient
+        if (tid < 96) {
+            const int c = tid;
+            float z2 = B2[c];
+            const uint16_t *w2r = W2 + c * W2P;
+            for (int j = 0; j < 96; ++j) z2 += bf2f(w2r[j]) * bf2f(H[c * HP + j]);
+            DZ[c] = s_slot[c] < 0 ? 0.f : sm[BW_DEMB + s * 256 + eoff + c] * elu_d(z2);
+        }
+        __syncthreads();
+        // layer 2 weights (thread-owned entries), and v_c[j] = dz_c W2[c][j]
+        // ELU'(z1_c[j]) in place of the derivative
 #pragma unroll
         for (int i = 0; i < 36; ++i) {
             const int e = tid + 256 * i, c = e / 96, j = e - 96 * c;
-            acc2[i] += DZ[c] * bf2f(H[c * 96 + j]);
+            const float dz = DZ[c];
+            acc2[i] += dz * bf2f(H[c * HP + j]);
+            D1[c * DP + j] = dz * bf2f(W2[c * W2P + j]) * D1[c * DP + j];
         }
-        // layer 1 weights and both biases: v_c[j] = dz_c W2[c][j] ELU'(z1_c[j])
+        __syncthreads();
+        // layer 1 weights and both biases
 #pragma unroll
         for (int i = 0; i < (N1 + 255) / 256; ++i) {
             const int e = tid + 256 * i;
             if (e >= N1) break;
-            if (e < 96 * K1 + 96) {
-                const int j = e < 96 * K1 ? e / K1 : e - 96 * K1;
-                const int k = e < 96 * K1 ? e - K1 * j : -1;
-                float a = 0.f;
-                for (int c = 0; c < 96; ++c) {
-                    const float v = DZ[c] * bf2f(bw2[c * 96 + j]) * D1[c * 96 + j];
-                    a += k >= 0 ? v * X[c * 8 + k] : v;
-                }
-                acc1[i] += a;
+            float a = 0.f;
+            if (e < 96 * K1) {
+                const int j = e / K1, k = e - K1 * j;
+                for (int c = 0; c < 96; ++c) a += D1[c * DP + j] * X[c * XP + k];
+            } else if (e < 96 * K1 + 96) {
+                const int j = e - 96 * K1;
+                for (int c = 0; c < 96; ++c) a += D1[c * DP + j];
             } else {
-                acc1[i] += DZ[e - 96 * K1 - 96];
+                a = DZ[e - 96 * K1 - 96];
             }
+            acc1[i] += a;
         }
         __syncthreads();
     }
@@ -352,6 +372,35 @@ __device__ void encoder_backward(float *sm, const float *__restrict__ obs, const
         if (e < 96 * K1) g[fw1 + e] = acc1[i];
         else if (e < 96 * K1 + 96) g[fb1 + e - 96 * K1] = acc1[i];
         else g[fb2 + e - 96 * K1 - 96] = acc1[i];
+    }
+    __syncthreads();   // the encoder buffers are reused next
+}
+
+// y[s][k] = sum_i x[s][i] W[i][k] for the tile's rows, W row-major [n_in][ld]
+// (bf16): thread k keeps the 16 rows' sums, so each weight is read once
+__device__ __forceinline__ void tile_matvec_t(const float *x, int xld, const uint16_t *__restrict__ W, int ld,
+                                              int n_in, int k, float (&acc)[PPO_TILE]) {
+#pragma unroll
+    for (int s = 0; s < PPO_TILE; ++s) acc[s] = 0.f;
+    for (int i = 0; i < n_in; ++i) {
+        const float w = bf2f(W[(size_t)i * ld + k]);
+#pragma unroll
+        for (int s = 0; s < PPO_TILE; ++s) acc[s] += x[s * xld + i] * w;
+    }
+}
+
+// G[i][k] = sum_s dz[s][i] a[s][k] (+ bias column: sum_s dz[s][i]) for
+// thread k: the 16 activations of column k stay in registers
+__device__ __forceinline__ void tile_outer(const float *dz, int dzld, int n_out, const float *a, int ald, int k,
+                                           float *__restrict__ G, int gld) {
+    float ak[PPO_TILE];
+#pragma unroll
+    for (int s = 0; s < PPO_TILE; ++s) ak[s] = a[s * ald + k];
+    for (int i = 0; i < n_out; ++i) {
+        float v = 0.f;
+#pragma unroll
+        for (int s = 0; s < PPO_TILE; ++s) v += dz[s * dzld + i] * ak[s];
+        G[(size_t)i * gld + k] = v;
     }
 }
 
@@ -385,46 +434,49 @@ __global__ __launch_bounds__(256) void k_ppo_backward(const float *__restrict__ 
                                                   : 0.f;
         }
         __syncthreads();
+        const float *svb = save + (size_t)r0 * AC_SAVE_ROW + net * AC_SAVE;   // row s at svb + s * AC_SAVE_ROW
+        auto zsave = [&](int s, int off) -> float { return r0 + s < B ? svb[(size_t)s * AC_SAVE_ROW + off] : 0.f; };
         // ---- head -> trunk 2: dz_t2 = (W_head^T d_out) ELU'(z_t2)
-        for (int e = tid; e < PPO_TILE * 64; e += 256) {
-            const int s = e >> 6, k = e & 63, r = r0 + s;
-            float a = 0.f;
-            for (int o = 0; o < nout; ++o) a += sm[BW_DO + s * 4 + o] * bfr1(F[ACF_HEAD + o * 64 + k]);
-            sm[BW_DZT2 + e] = r < B ? a * elu_d(save[(size_t)r * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZT2 + k]) : 0.f;
+        if (tid < 64) {
+            const int k = tid;
+            float w[3];
+            for (int o = 0; o < nout; ++o) w[o] = bfr1(F[ACF_HEAD + o * 64 + k]);
+            for (int s = 0; s < PPO_TILE; ++s) {
+                float a = 0.f;
+                for (int o = 0; o < nout; ++o) a += sm[BW_DO + s * 4 + o] * w[o];
+                sm[BW_DZT2 + s * 64 + k] = r0 + s < B ? a * elu_d(zsave(s, AC_SAVE_ZT2 + k)) : 0.f;
+            }
         }
         __syncthreads();
+        float acc[PPO_TILE];
         // ---- trunk 2 -> trunk 1: dz_t1 = (W_t2^T dz_t2) ELU'(z_t1)
-        for (int e = tid; e < PPO_TILE * 128; e += 256) {
-            const int s = e >> 7, k = e & 127, r = r0 + s;
-            float a = 0.f;
-            for (int j = 0; j < 64; ++j) a += sm[BW_DZT2 + s * 64 + j] * bf2f(Bw[ACB_TW2 + j * 128 + k]);
-            sm[BW_DZT1 + e] = r < B ? a * elu_d(save[(size_t)r * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZT1 + k]) : 0.f;
+        if (tid < 128) {
+            tile_matvec_t(sm + BW_DZT2, 64, Bw + ACB_TW2, 128, 64, tid, acc);
+#pragma unroll
+            for (int s = 0; s < PPO_TILE; ++s)
+                sm[BW_DZT1 + s * 128 + tid] = r0 + s < B ? acc[s] * elu_d(zsave(s, AC_SAVE_ZT1 + tid)) : 0.f;
         }
         __syncthreads();
         // ---- trunk 1 -> embedding
-        for (int e = tid; e < PPO_TILE * 256; e += 256) {
-            const int s = e >> 8, k = e & 255;
-            float a = 0.f;
-            for (int i = 0; i < 128; ++i) a += sm[BW_DZT1 + s * 128 + i] * bf2f(Bw[ACB_TW1 + i * 256 + k]);
-            sm[BW_DEMB + e] = a;
-        }
+        tile_matvec_t(sm + BW_DZT1, 128, Bw + ACB_TW1, 256, 128, tid, acc);
+#pragma unroll
+        for (int s = 0; s < PPO_TILE; ++s) sm[BW_DEMB + s * 256 + tid] = acc[s];
         __syncthreads();
         // ---- ego encoder: dz_e2 = d_emb[0:64] ELU'(z_e2); dz_e1 = (W_e2^T dz_e2) ELU'(z_e1)
-        for (int e = tid; e < PPO_TILE * 64; e += 256) {
-            const int s = e >> 6, k = e & 63, r = r0 + s;
-            sm[BW_DZE2 + e] = r < B ? sm[BW_DEMB + s * 256 + k] *
-                                          elu_d(save[(size_t)r * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZE2 + k])
-                                    : 0.f;
+        if (tid < 64) {
+#pragma unroll
+            for (int s = 0; s < PPO_TILE; ++s)
+                sm[BW_DZE2 + s * 64 + tid] = r0 + s < B ? sm[BW_DEMB + s * 256 + tid] * elu_d(zsave(s, AC_SAVE_ZE2 + tid)) : 0.f;
         }
         __syncthreads();
-        for (int e = tid; e < PPO_TILE * 64; e += 256) {
-            const int s = e >> 6, k = e & 63, r = r0 + s;
-            float a = 0.f;
-            for (int j = 0; j < 64; ++j) a += sm[BW_DZE2 + s * 64 + j] * bf2f(Bw[ACB_EW2 + j * 64 + k]);
-            sm[BW_DZE1 + e] = r < B ? a * elu_d(save[(size_t)r * AC_SAVE_ROW + net * AC_SAVE + AC_SAVE_ZE1 + k]) : 0.f;
+        if (tid < 64) {
+            tile_matvec_t(sm + BW_DZE2, 64, Bw + ACB_EW2, 64, 64, tid, acc);
+#pragma unroll
+            for (int s = 0; s < PPO_TILE; ++s)
+                sm[BW_DZE1 + s * 64 + tid] = r0 + s < B ? acc[s] * elu_d(zsave(s, AC_SAVE_ZE1 + tid)) : 0.f;
         }
         __syncthreads();
-        // ---- dense weight gradients: sum over the tile's rows
+        // ---- dense weight gradients: sums over the tile's rows
         // head W[o][k], b[o]
         for (int e = tid; e < nout * 65; e += 256) {
             const int o = e / 65, k = e - 65 * o;
@@ -434,29 +486,24 @@ __global__ __launch_bounds__(256) void k_ppo_backward(const float *__restrict__ 
             else g[ACF_HEAD + nout * 64 + o] = a;
         }
         if (net == 0 && tid < 3) g[ACF_LOGSTD + tid] = 0.f;     // from the loss partials
-        // trunk 2: W[j][k] (64 x 128), b[j]
-        for (int e = tid; e < 64 * 129; e += 256) {
-            const int j = e / 129, k = e - 129 * j;
+        // trunk 1: W[i][k] (128 x 256), column k per thread
+        tile_outer(sm + BW_DZT1, 128, 128, sm + BW_EMB, 256, tid, g + ACF_TW1, 256);
+        // trunk 2: W[j][k] (64 x 128); ego 2: W[j][k] (64 x 64)
+        if (tid < 128) tile_outer(sm + BW_DZT2, 64, 64, sm + BW_T1, 128, tid, g + ACF_TW2, 128);
+        else if (tid < 192) tile_outer(sm + BW_DZE2, 64, 64, sm + BW_E1, 64, tid - 128, g + ACF_EW2, 64);
+        // biases of trunk 1, trunk 2, ego 2
+        if (tid < 128) {
             float a = 0.f;
-            for (int s = 0; s < PPO_TILE; ++s) a += sm[BW_DZT2 + s * 64 + j] * (k < 128 ? sm[BW_T1 + s * 128 + k] : 1.f);
-            if (k < 128) g[ACF_TW2 + j * 128 + k] = a;
-            else g[ACF_TB2 + j] = a;
-        }
-        // trunk 1: W[i][k] (128 x 256), b[i]
-        for (int e = tid; e < 128 * 257; e += 256) {
-            const int i = e / 257, k = e - 257 * i;
-            float a = 0.f;
-            for (int s = 0; s < PPO_TILE; ++s) a += sm[BW_DZT1 + s * 128 + i] * (k < 256 ? sm[BW_EMB + s * 256 + k] : 1.f);
-            if (k < 256) g[ACF_TW1 + i * 256 + k] = a;
-            else g[ACF_TB1 + i] = a;
-        }
-        // ego 2: W[j][k] (64 x 64), b[j]
-        for (int e = tid; e < 64 * 65; e += 256) {
-            const int j = e / 65, k = e - 65 * j;
-            float a = 0.f;
-            for (int s = 0; s < PPO_TILE; ++s) a += sm[BW_DZE2 + s * 64 + j] * (k < 64 ? sm[BW_E1 + s * 64 + k] : 1.f);
-            if (k < 64) g[ACF_EW2 + j * 64 + k] = a;
-            else g[ACF_EB2 + j] = a;
+            for (int s = 0; s < PPO_TILE; ++s) a += sm[BW_DZT1 + s * 128 + tid];
+            g[ACF_TB1 + tid] = a;
+        } else if (tid < 192) {
+            float a = 0.f, b = 0.f;
+            for (int s = 0; s < PPO_TILE; ++s) {
+                a += sm[BW_DZT2 + s * 64 + tid - 128];
+                b += sm[BW_DZE2 + s * 64 + tid - 128];
+            }
+            g[ACF_TB2 + tid - 128] = a;
+            g[ACF_EB2 + tid - 128] = b;
         }
         // ego 1: W[j][k] (64 x 11), b[j]
         for (int e = tid; e < 64 * 12; e += 256) {
@@ -472,7 +519,6 @@ __global__ __launch_bounds__(256) void k_ppo_backward(const float *__restrict__ 
                             ACF_RW2, ACF_RB2, Bw + ACB_RW1, Bw + ACB_RW2, g);
         encoder_backward<7>(sm, obs, rows, B, r0, save, net, AC_SAVE_AV, SF_FULL_EGO + 5 * SF_FULL_ROAD_K, 160, F,
                             ACF_VW1, ACF_VB1, ACF_VW2, ACF_VB2, Bw + ACB_VW1, Bw + ACB_VW2, g);
-        __syncthreads();
     }
 }
 
@@ -486,17 +532,32 @@ void launch_ppo_backward(const float *obs, const int *rows, int B, const float *
 int ppo_tiles(int B) { return (B + PPO_TILE - 1) / PPO_TILE; }
 
 // ------------------------------------------------------------ reduce, Adam
-// grad[p] = sum over tiles (in order) + the log sigma terms of the loss
-// (stats[4..6]) less the entropy coefficient
-__global__ void k_ppo_reduce(const float *__restrict__ part, int tiles, const double *__restrict__ stats, float c_e,
+// two-level sum of the tile partials, each level in a fixed order: group
+// g of the tiles into gpart[g] (grid y = group), then the groups in order
+// into grad plus the log sigma terms of the loss (stats[4..6]) less the
+// entropy coefficient
+#define RED_GROUPS 16
+__global__ void k_ppo_reduce_groups(const float *__restrict__ part, int tiles, float *__restrict__ gpart) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= SF_AC_PARAMS) return;
+    const int per = (tiles + RED_GROUPS - 1) / RED_GROUPS;
+    const int t0 = blockIdx.y * per, t1 = min(tiles, t0 + per);
+    float g = 0.f;
+    for (int t = t0; t < t1; ++t) g += part[(size_t)t * SF_AC_PARAMS + p];
+    gpart[(size_t)blockIdx.y * SF_AC_PARAMS + p] = g;
+}
+
+__global__ void k_ppo_reduce(const float *__restrict__ gpart, const double *__restrict__ stats, float c_e,
                              float *__restrict__ grad) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= SF_AC_PARAMS) return;
     float g = 0.f;
-    for (int t = 0; t < tiles; ++t) g += part[(size_t)t * SF_AC_PARAMS + p];
+    for (int q = 0; q < RED_GROUPS; ++q) g += gpart[(size_t)q * SF_AC_PARAMS + p];
     if (p >= ACF_LOGSTD && p < ACF_LOGSTD + 3) g += (float)stats[4 + p - ACF_LOGSTD] - c_e;
     grad[p] = g;
 }
+
+int ppo_reduce_groups() { return RED_GROUPS; }
 
 #define SQ_BLOCK 256
 __global__ __launch_bounds__(SQ_BLOCK) void k_ppo_sqnorm(const float *__restrict__ grad, double *__restrict__ part) {
@@ -536,9 +597,10 @@ __global__ void k_ppo_adam(float *__restrict__ P, float *__restrict__ m, float *
 }
 
 #define SQ_BLOCKS 64
-void launch_ppo_reduce(const float *part, int tiles, const double *stats, float c_e, float *grad, double *sq,
-                       hipStream_t s) {
-    k_ppo_reduce<<<(SF_AC_PARAMS + 255) / 256, 256, 0, s>>>(part, tiles, stats, c_e, grad);
+void launch_ppo_reduce(const float *part, int tiles, float *gpart, const double *stats, float c_e, float *grad,
+                       double *sq, hipStream_t s) {
+    k_ppo_reduce_groups<<<dim3((SF_AC_PARAMS + 255) / 256, RED_GROUPS), 256, 0, s>>>(part, tiles, gpart);
+    k_ppo_reduce<<<(SF_AC_PARAMS + 255) / 256, 256, 0, s>>>(gpart, stats, c_e, grad);
     k_ppo_sqnorm<<<SQ_BLOCKS, SQ_BLOCK, 0, s>>>(grad, sq);
 }
 

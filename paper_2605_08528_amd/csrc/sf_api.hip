@@ -81,6 +81,7 @@ struct sf_sim {
     bool ro_full = false, adv_ready = false;
     float ls_old[3] = {};                 // log sigma during the kept rollout
     float *ppo_m = nullptr, *ppo_v = nullptr, *ppo_grad = nullptr, *ppo_part = nullptr, *ppo_save = nullptr;
+    float *ppo_gpart = nullptr;           // [groups][SF_AC_PARAMS] partial sums of the tile partials
     float *ppo_mean = nullptr, *ppo_value = nullptr, *ppo_dout = nullptr, *ppo_lpart = nullptr, *ppo_norm = nullptr;
     double *ppo_stats = nullptr, *ppo_mom = nullptr, *ppo_sq = nullptr;
     int *ppo_flag = nullptr;
@@ -971,6 +972,7 @@ sf_status sf_ppo_init(sf_sim *sim, const sf_ppo_opts *o) {
         sim->ppo_v = (float *)A(sizeof(float) * SF_AC_PARAMS);
         sim->ppo_grad = (float *)A(sizeof(float) * SF_AC_PARAMS);
         sim->ppo_part = (float *)A(sizeof(float) * SF_AC_PARAMS * (size_t)tiles);
+        sim->ppo_gpart = (float *)A(sizeof(float) * SF_AC_PARAMS * (size_t)ppo_reduce_groups());
         sim->ppo_save = (float *)A(sizeof(float) * AC_SAVE_ROW * (size_t)B);
         sim->ppo_mean = (float *)A(sizeof(float) * 3 * (size_t)B);
         sim->ppo_value = (float *)A(sizeof(float) * (size_t)B);
@@ -983,7 +985,7 @@ sf_status sf_ppo_init(sf_sim *sim, const sf_ppo_opts *o) {
         sim->ppo_flag = (int *)A(sizeof(int));
         if (!sim->ro_obs || !sim->ro_cnt || !sim->ro_u || !sim->ro_mu || !sim->ro_logp || !sim->ro_val ||
             !sim->ro_rew || !sim->ro_adv || !sim->ro_ret || !sim->ro_done || !sim->ppo_m || !sim->ppo_v ||
-            !sim->ppo_grad || !sim->ppo_part || !sim->ppo_save || !sim->ppo_mean || !sim->ppo_value ||
+            !sim->ppo_grad || !sim->ppo_part || !sim->ppo_gpart || !sim->ppo_save || !sim->ppo_mean || !sim->ppo_value ||
             !sim->ppo_dout || !sim->ppo_lpart || !sim->ppo_norm || !sim->ppo_stats || !sim->ppo_mom ||
             !sim->ppo_sq || !sim->ppo_flag)
             return fail(SF_E_OUT_OF_MEMORY, "PPO buffers");
@@ -1077,8 +1079,8 @@ static sf_status ppo_grad_stage(sf_sim *sim, const int32_t *rows, int M) {
         launch_ppo_backward(sim->ro_obs, rows, M, sim->ppo_save, sim->ppo_dout, sim->ac_f32, sim->ac_bf16,
                             sim->ppo_part, st);
     }
-    launch_ppo_reduce(sim->ppo_part, ppo_tiles(M), sim->ppo_stats, sim->ppo.entropy_coef, sim->ppo_grad, sim->ppo_sq,
-                      st);
+    launch_ppo_reduce(sim->ppo_part, ppo_tiles(M), sim->ppo_gpart, sim->ppo_stats, sim->ppo.entropy_coef,
+                      sim->ppo_grad, sim->ppo_sq, st);
     LAUNCHED();
     return SF_OK;
 }

@@ -101,8 +101,9 @@ void launch_ppo_loss(const int *rows, int B, const float *mean_new, const float 
 void launch_ppo_backward(const float *obs, const int *rows, int B, const float *save, const float *dout,
                          const float *Pf, const uint16_t *Wb, float *part, hipStream_t s);
 int ppo_tiles(int B);
-void launch_ppo_reduce(const float *part, int tiles, const double *stats, float c_e, float *grad, double *sq,
-                       hipStream_t s);
+void launch_ppo_reduce(const float *part, int tiles, float *gpart, const double *stats, float c_e, float *grad,
+                       double *sq, hipStream_t s);
+int ppo_reduce_groups();
 void launch_ppo_adam(float *P, float *m, float *v, const float *grad, const double *sq, float max_norm, float lr,
                      float b1, float b2, float eps, float c1, float c2, float *norm_out, hipStream_t s);
 void launch_ppo_check_rows(const int *rows, long long n, int limit, int *flag, hipStream_t s);

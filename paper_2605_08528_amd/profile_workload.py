@@ -11,7 +11,8 @@ with the policy, step and observation kernels launched separately, a learned tir
 from the plain step (``--train-steps`` Adam steps of the training kernels),
 ``--steps`` control steps with the network inside the step, and ``--steps``
 control steps driven by the paper-shaped observation and the late-fusion
-actor-critic (seeded random weights), and last ``--steps`` fused control
+actor-critic (seeded random weights), one short PPO iteration (a 4-step
+rollout, one epoch of two minibatches), and last ``--steps`` fused control
 steps at each step workgroup shape of ``--step-blocks``.  Launch shapes are
 fixed (no autotuning) so that the kernels are the ones named on the command
 line.
@@ -85,6 +86,15 @@ def main():
         sim.actor_critic_load((rng.standard_normal(sf.AC_PARAMS) * 0.1).astype(np.float32))
         for _ in range(args.steps):
             sim.step_actor_critic(dt, S)
+        torch.cuda.synchronize()
+        # one short PPO iteration: a 4-step rollout, one epoch of two
+        # minibatches (training forward pass, loss, backward pass, Adam)
+        opts = sim.ppo_init(horizon=4, epochs=1, minibatches=2)
+        g = torch.Generator(device="cuda").manual_seed(args.seed)
+        eps = torch.randn((4, sim.N, 3), generator=g, device="cuda", dtype=torch.float32)
+        perm = torch.randperm(4 * sim.N, generator=g, device="cuda").to(torch.int32)[None]
+        sim.ppo_rollout(eps, dt, S)
+        sim.ppo_update(perm)
         torch.cuda.synchronize()
         # last: the fused policy-driven step at every step workgroup shape, so
         # that each shape's last dispatches are its own control steps
