@@ -19,7 +19,11 @@ __device__ __forceinline__ f3 mount_of(const DevParams &P, int wh) {
 // Ray-triangle test (Moller-Trumbore) on a packed record: v0, edges e1 and
 // e2.  Every product-sum is an explicit fused multiply-add and the compiler
 // may fuse nothing else, so a call rounds the same wherever it is inlined
-// (the records of a ray sit at layout-dependent places in its batch).
+// (the records of a ray sit at layout-dependent places in its batch).  The
+// determinant's reciprocal is the hardware's (one ulp), and the barycentric
+// and distance tests are taken together without branches: a wave runs the
+// test for every record up to its lanes' longest list, so its cost is the
+// instruction count.
 __device__ __forceinline__ float mt_rec(const float4 &a, const float4 &b, const float4 &c, f3 m, f3 u,
                                         float ell) {
 #pragma clang fp contract(off)
@@ -27,19 +31,18 @@ __device__ __forceinline__ float mt_rec(const float4 &a, const float4 &b, const 
     const float pvy = fmaf(u.z, c.x, -(u.x * c.z));
     const float pvz = fmaf(u.x, c.y, -(u.y * c.x));
     const float det = fmaf(b.x, pvx, fmaf(b.y, pvy, b.z * pvz));
-    if (fabsf(det) < 1e-12f) return INFINITY;
-    const float inv = 1.f / det;
+    const float inv = __builtin_amdgcn_rcpf(det);
     const float tx = m.x - a.x, ty = m.y - a.y, tz = m.z - a.z;
     const float bu = fmaf(tx, pvx, fmaf(ty, pvy, tz * pvz)) * inv;
-    if (bu < 0.f || bu > 1.f) return INFINITY;
     const float qx = fmaf(ty, b.z, -(tz * b.y));
     const float qy = fmaf(tz, b.x, -(tx * b.z));
     const float qz = fmaf(tx, b.y, -(ty * b.x));
     const float bv = fmaf(u.x, qx, fmaf(u.y, qy, u.z * qz)) * inv;
-    if (bv < 0.f || bu + bv > 1.f) return INFINITY;
     const float t = fmaf(c.x, qx, fmaf(c.y, qy, c.z * qz)) * inv;
-    if (t < 0.f || t > ell) return INFINITY;
-    return t;
+    // NaN (a degenerate record) fails every comparison
+    const bool ok = fabsf(det) >= 1e-12f && bu >= 0.f && bu <= 1.f && bv >= 0.f && bu + bv <= 1.f &&
+                    t >= 0.f && t <= ell;
+    return ok ? t : INFINITY;
 }
 
 struct RayHit {
@@ -50,18 +53,24 @@ struct RayHit {
 
 // record hit (t, id) of record k: the nearest distance so far and up to 4
 // distinct triangle hits, in separate registers (an indexed array here
-// would be placed in scratch memory)
-#define RAY_HIT(t_, id_, k_)                                                        \
+// would be placed in scratch memory), and the first hit's edge records
+#define RAY_HIT(t_, id_, k_, b_, c_)                                                \
     do {                                                                            \
-        tmin = fminf(tmin, (t_));                                                   \
-        const int idh = (id_);                                                      \
-        if (idh != i0 && idh != i1 && idh != i2 && idh != i3) {                     \
-            if (nh == 0) { t0 = (t_); i0 = idh; k0 = (k_); }                        \
-            else if (nh == 1) { t1 = (t_); i1 = idh; k1 = (k_); }                   \
-            else if (nh == 2) { t2 = (t_); i2 = idh; k2 = (k_); }                   \
-            else if (nh == 3) { t3 = (t_); i3 = idh; k3 = (k_); }                   \
-            ++nh;                                                                   \
-        }                                                                           \
+        const float th = (t_);                                                      \
+        const int idh = (id_), kh = (k_);                                           \
+        const bool nw = th < INFINITY && idh != i0 && idh != i1 && idh != i2 && idh != i3; \
+        const bool s0 = nw && nh == 0, s1 = nw && nh == 1, s2 = nw && nh == 2,     \
+                   s3 = nw && nh == 3;                                              \
+        tmin = fminf(tmin, th);                                                     \
+        t0 = s0 ? th : t0; i0 = s0 ? idh : i0; k0 = s0 ? kh : k0;                   \
+        const float4 bh = (b_), ch = (c_);                                          \
+        fb0 = s0 ? bh.x : fb0; fb1 = s0 ? bh.y : fb1; fb2 = s0 ? bh.z : fb2;        \
+        fb3 = s0 ? bh.w : fb3; fc0 = s0 ? ch.x : fc0; fc1 = s0 ? ch.y : fc1;        \
+        fc2 = s0 ? ch.z : fc2; fc3 = s0 ? ch.w : fc3;                               \
+        t1 = s1 ? th : t1; i1 = s1 ? idh : i1; k1 = s1 ? kh : k1;                   \
+        t2 = s2 ? th : t2; i2 = s2 ? idh : i2; k2 = s2 ? kh : k2;                   \
+        t3 = s3 ? th : t3; i3 = s3 ? idh : i3; k3 = s3 ? kh : k3;                   \
+        nh += nw ? 1 : 0;                                                           \
     } while (0)
 
 // Nearest hit of the wheel ray against the ground plane z = 0 and the road
@@ -100,12 +109,19 @@ __device__ __forceinline__ RayHit raycast(const DevParams &P, const DevWorld &Wd
     cy0 = max(0, min(cy0, g.ny - 1)); cy1 = max(0, min(cy1, g.ny - 1));
     float tmin = tg, t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
     int nh = 0, i0 = -1, i1 = -1, i2 = -1, i3 = -1, k0 = -1, k1 = -1, k2 = -1, k3 = -1;
+    // edge records of the first hit (scalars: a selected float4 would be
+    // placed in scratch memory)
+    float fb0 = 0.f, fb1 = 0.f, fb2 = 0.f, fb3 = 0.f, fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fc3 = 0.f;
     // two cell rows at a time (the second empty unless the footprint spans it)
     for (int cy = cy0; cy <= cy1; cy += 2) {
         const int ca = g.cbase + cy * g.nx, cb = g.cbase + min(cy + 1, g.ny - 1) * g.nx;
         const int sA = Wd.tri_cell_start[ca + cx0], eA = Wd.tri_cell_start[ca + cx1 + 1];
-        const int sB = Wd.tri_cell_start[cb + cx0], eB = Wd.tri_cell_start[cb + cx1 + 1];
-        const int nA = eA - sA, nAB = nA + (cy < cy1 ? eB - sB : 0);
+        int sB = 0, eB = 0;
+        if (cy < cy1) {
+            sB = Wd.tri_cell_start[cb + cx0];
+            eB = Wd.tri_cell_start[cb + cx1 + 1];
+        }
+        const int nA = eA - sA, nAB = nA + eB - sB;
         if (Wd.touch) {
             touch(Wd, SF_T_TRI_START, ca + cx0);
             touch(Wd, SF_T_TRI_START, ca + cx1 + 1);
@@ -130,9 +146,10 @@ __device__ __forceinline__ RayHit raycast(const DevParams &P, const DevWorld &Wd
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int r = rb + q;
-                if (r >= nAB) break;
-                const float t = mt_rec(ra[q], rbv[q], rc[q], m, u, ell);
-                if (t < INFINITY) RAY_HIT(t, __float_as_int(ra[q].w), r < nA ? sA + r : sB + (r - nA));
+                if (r < nAB) {
+                    const float t = mt_rec(ra[q], rbv[q], rc[q], m, u, ell);
+                    RAY_HIT(t, __float_as_int(ra[q].w), r < nA ? sA + r : sB + (r - nA), rbv[q], rc[q]);
+                }
             }
         }
     }
@@ -162,7 +179,12 @@ __device__ __forceinline__ RayHit raycast(const DevParams &P, const DevWorld &Wd
         }
     }
     if (bk >= 0) {
-        const float4 b = Wd.tri_rec[3 * (size_t)bk + 1], c = Wd.tri_rec[3 * (size_t)bk + 2];
+        // the first hit wins in the common case: its records are at hand
+        float4 b = make_float4(fb0, fb1, fb2, fb3), c = make_float4(fc0, fc1, fc2, fc3);
+        if (bk != k0) {
+            b = Wd.tri_rec[3 * (size_t)bk + 1];
+            c = Wd.tri_rec[3 * (size_t)bk + 2];
+        }
         f3 n = cross3(mk3(b.x, b.y, b.z), mk3(c.x, c.y, c.z));
         const float L = sqrtf(dot3(n, n));
         n = L > 0.f ? mul3(n, 1.f / L) : mk3(0.f, 0.f, 1.f);
@@ -243,16 +265,23 @@ __device__ __forceinline__ void sur_layer32(uint16_t *buf, const uint16_t *W, in
     f32x4 acc[8][2];
 #pragma unroll
     for (int n = 0; n < 8; ++n) acc[n][0] = acc[n][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // every fragment of a 32-deep slice is read before its products are
+    // issued, so that the LDS reads overlap one another
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k0 = ks * 32 + kq * 8;
         const bf16x8 x0 = ld8(buf + r16 * SUR_LD + k0), x1 = ld8(buf + (16 + r16) * SUR_LD + k0);
+        bf16x8 w[8];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) w[n] = ld8(W + (n * 16 + r16) * ldw + k0);
 #pragma unroll
         for (int n = 0; n < 8; ++n) {
-            const bf16x8 w = ld8(W + (n * 16 + r16) * ldw + k0);
-            acc[n][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x0, acc[n][0], 0, 0, 0);
-            acc[n][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x1, acc[n][1], 0, 0, 0);
+            acc[n][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[n], x0, acc[n][0], 0, 0, 0);
+            acc[n][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[n], x1, acc[n][1], 0, 0, 0);
         }
+        // scheduling hint: the slice's ten LDS reads, then its sixteen products
+        __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
     }
     wave_sync();
     // lane holds out[row 16 t + lane % 16][16 n + 4 (lane / 16) + j]
@@ -341,6 +370,44 @@ __device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool
     }
 }
 
+// Contact point of circle a of body i against circle b of body j (ab = 3a + b,
+// the pair's mask bit): unit normal from i to j, midpoint of the two circle
+// centres (height: mean of the bodies'), Baumgarte bias on the penetration
+// past the slop.
+struct CPoint {
+    float nx, ny, px, py, pz, b;
+};
+__device__ __forceinline__ CPoint contact_point(const DevParams &P, float h, const float (*p)[SF_MAXA],
+                                               const float *hx, const float *hy, int i, int j, int ab) {
+    const int a = ab / 3, b = ab - 3 * a;
+    const float cix = p[0][i] + (float)(a - 1) * P.cd * hx[i];
+    const float ciy = p[1][i] + (float)(a - 1) * P.cd * hy[i];
+    const float cjx = p[0][j] + (float)(b - 1) * P.cd * hx[j];
+    const float cjy = p[1][j] + (float)(b - 1) * P.cd * hy[j];
+    const float dx = cjx - cix, dy = cjy - ciy;
+    const float L = sqrtf(dx * dx + dy * dy);
+    CPoint c;
+    c.nx = L > 0.f ? dx / L : 1.f;
+    c.ny = L > 0.f ? dy / L : 0.f;
+    c.px = 0.5f * (cix + cjx);
+    c.py = 0.5f * (ciy + cjy);
+    c.pz = 0.5f * (p[2][i] + p[2][j]);
+    const float pen = 2.f * P.cr - L - P.slop;
+    c.b = pen > 0.f ? (P.baumgarte / h) * pen : 0.f;
+    return c;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
 __device__ __forceinline__ unsigned long long lanemask_lt() {
     unsigned lane = threadIdx.x & 63;
     return lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -408,10 +475,28 @@ __device__ __forceinline__ int detect_pairs_wave(const DevParams &P, const int (
 // after the spawn warm-up, crash on falling, drifting or tilting), the
 // time-out, reward and termination, then respawns or parks it
 // (Sec. "Termination and time-out").
+// Goal, start and step counters of an agent, read with its state at the
+// start of the control step.
+struct AgentTail {
+    float gx, gy, sx, sy;
+    int since, ep;
+};
+__device__ __forceinline__ AgentTail load_tail(const float *st, const int *ist, int N, int n) {
+    AgentTail a;
+    a.gx = st[SF_F_GOAL_X * N + n];
+    a.gy = st[SF_F_GOAL_Y * N + n];
+    a.sx = st[SF_F_START_X * N + n];
+    a.sy = st[SF_F_START_Y * N + n];
+    a.since = ist[SF_I_SINCE_SPAWN * N + n];
+    a.ep = ist[SF_I_EP_STEP * N + n];
+    return a;
+}
+
 __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld &Wd, float *st, int *ist, int N,
                                              int n, int w, int i, const float (&dyn)[SF_F_MU], float mu_seen,
                                              bool coll, bool nan_act, bool ovf, bool forbid, float2 p0,
-                                             float *reward, uint8_t *done, uint8_t *events) {
+                                             const AgentTail &tl, float *reward, uint8_t *done,
+                                             uint8_t *events) {
     bool finite = true;
     for (int c = 0; c < SF_F_MU; ++c) {
         st[c * N + n] = dyn[c];
@@ -423,10 +508,10 @@ __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld 
         ev = SF_EV_CRASH | SF_EV_NUMERIC;
     } else {
         const long long X = qpos(dyn[SF_F_PX]), Y = qpos(dyn[SF_F_PY]), Z = qpos(dyn[SF_F_PZ]);
-        const long long gx = X - qpos(st[SF_F_GOAL_X * N + n]), gy = Y - qpos(st[SF_F_GOAL_Y * N + n]);
+        const long long gx = X - qpos(tl.gx), gy = Y - qpos(tl.gy);
         if (gx * gx + gy * gy <= 3072ll * 3072ll) ev |= SF_EV_GOAL;
-        if (coll && ist[SF_I_SINCE_SPAWN * N + n] >= P.warmup) ev |= SF_EV_COLLISION;
-        const long long sx = X - qpos(st[SF_F_START_X * N + n]), sy = Y - qpos(st[SF_F_START_Y * N + n]);
+        if (coll && tl.since >= P.warmup) ev |= SF_EV_COLLISION;
+        const long long sx = X - qpos(tl.sx), sy = Y - qpos(tl.sy);
         bool crash = sx * sx + sy * sy > 102400ll * 102400ll || Z < 0;
         const long long qx = qquat(dyn[SF_F_QX]), qy = qquat(dyn[SF_F_QY]);
         crash = crash || ((1ll << 28) - 2 * (qx * qx + qy * qy) < 40265318ll);
@@ -437,9 +522,9 @@ __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld 
     if (nan_act) ev |= SF_EV_NAN_ACTION;
     if (ovf) ev |= SF_EV_CONTACT_OVERFLOW;
     if (Wd.disp) Wd.disp[n] = make_float2(dyn[SF_F_PX] - p0.x, dyn[SF_F_PY] - p0.y);
-    const int ep = ist[SF_I_EP_STEP * N + n] + 1;
+    const int ep = tl.ep + 1;
     ist[SF_I_EP_STEP * N + n] = ep;
-    ist[SF_I_SINCE_SPAWN * N + n] += 1;
+    ist[SF_I_SINCE_SPAWN * N + n] = tl.since + 1;
     if (ep >= P.max_ep) ev |= SF_EV_TIMEOUT;
     const float r = (ev & SF_EV_GOAL) ? 45.f : (ev & SF_EV_COLLISION) ? -6.f : (ev & SF_EV_CRASH) ? -10.f
                   : (ev & SF_EV_LANE_FORBIDDEN) ? -20.f : 0.f;
@@ -515,6 +600,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ int s_act[SF_MAXA];
     __shared__ uint8_t s_coll[SF_MAXA], s_nan[SF_MAXA], s_forbid[SF_MAXA];
     __shared__ float2 s_p0[SF_MAXA];     // positions at the start of the control step
+    __shared__ AgentTail s_tail[SF_MAXA];
     __shared__ float s_om[4 * SF_MAXA];
     __shared__ float s_wf[6][4 * SF_MAXA];
     __shared__ float s_wmu[4 * SF_MAXA];
@@ -524,6 +610,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     __shared__ int s_cij[SF_CCAP];
     __shared__ short s_bidx[2 * SF_CCAP];  // each body's contacts (CSR, list order)
     __shared__ int s_boff[SF_MAXA];
+    __shared__ unsigned long long s_bmask[SF_MAXA];  // one-wave path: each body's contacts
     __shared__ int s_ovf;                  // contact points past SF_CCAP in a substep
     __shared__ float s_iw[6][SF_MAXA];   // world-frame inverse inertia (xx xy xz yy yz zz)
     __shared__ GridHdr s_tgrid;          // the world's triangle grid
@@ -541,43 +628,67 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     // update per workgroup at the end instead of one per wave and substep)
     __shared__ unsigned s_sur_cnt[2];
     if (SUR && tid < 2) s_sur_cnt[tid] = 0u;
+    // wheel mount points (an indexed read of the argument block per wheel
+    // would be a memory gather on every substep)
+    __shared__ float s_mount[12];
+    if (tid < 12) s_mount[tid] = P.mount[tid / 3][tid % 3];
 
     if (SUR) {
         // the network's weights and biases, once per block for all substeps;
         // each block starts at its own offset so that the blocks' copies do
-        // not all hit the same memory lines at once
+        // not all hit the same memory lines at once, and each thread keeps
+        // its 16-byte loads in flight (up to 24) before it stores them
         constexpr int NCH = 128 * 4 + 2 * 128 * 16 + 3 * 16;
+        constexpr int PER = (NCH + BLOCK - 1) / BLOCK;
+        constexpr int NB = PER < 24 ? PER : 24;
         const int rot = (int)(blockIdx.x % 64) * 64;
-        for (int e0 = tid; e0 < NCH; e0 += BLOCK) {
-            const int e = e0 + rot < NCH ? e0 + rot : e0 + rot - NCH;
-            const uint16_t *src;
-            uint16_t *dst;
-            if (e < 512) {
-                // W1 rows: 16 inputs then 16 zeros
-                dst = s_surw + (e >> 2) * SURW_LD1 + (e & 3) * 8;
-                if ((e & 3) >= 2) {
-                    *reinterpret_cast<uint4 *>(dst) = make_uint4(0u, 0u, 0u, 0u);
-                    continue;
+        for (int k0 = 0; k0 < PER; k0 += NB) {
+            uint4 v[NB];
+            int dofs[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e0 = tid + (k0 + q) * BLOCK;
+                dofs[q] = -1;
+                v[q] = make_uint4(0u, 0u, 0u, 0u);
+                if (e0 < NCH) {
+                    const int e = e0 + rot < NCH ? e0 + rot : e0 + rot - NCH;
+                    const uint16_t *src = nullptr;
+                    if (e < 512) {
+                        // W1 rows: 16 inputs then 16 zeros
+                        dofs[q] = (e >> 2) * SURW_LD1 + (e & 3) * 8;
+                        if ((e & 3) < 2) src = Su.Wb + SF_SURB_W1 + (e >> 2) * SF_SUR_IN + (e & 3) * 8;
+                    } else if (e < 512 + 2048) {
+                        const int r = e - 512;
+                        src = Su.Wb + SF_SURB_W2 + (r >> 4) * SF_SUR_HID + (r & 15) * 8;
+                        dofs[q] = SURW_W2 + (r >> 4) * SUR_LD + (r & 15) * 8;
+                    } else if (e < 512 + 4096) {
+                        const int r = e - 512 - 2048;
+                        src = Su.Wb + SF_SURB_W3 + (r >> 4) * SF_SUR_HID + (r & 15) * 8;
+                        dofs[q] = SURW_W3 + (r >> 4) * SUR_LD + (r & 15) * 8;
+                    } else {
+                        const int r = e - 512 - 4096;
+                        src = Su.Wb + SF_SURB_W4 + (r >> 4) * SF_SUR_HID + (r & 15) * 8;
+                        dofs[q] = SURW_W4 + (r >> 4) * SUR_LD + (r & 15) * 8;
+                    }
+                    if (src) v[q] = *reinterpret_cast<const uint4 *>(src);
                 }
-                src = Su.Wb + SF_SURB_W1 + (e >> 2) * SF_SUR_IN + (e & 3) * 8;
-            } else if (e < 512 + 2048) {
-                const int q = e - 512;
-                src = Su.Wb + SF_SURB_W2 + (q >> 4) * SF_SUR_HID + (q & 15) * 8;
-                dst = s_surw + SURW_W2 + (q >> 4) * SUR_LD + (q & 15) * 8;
-            } else if (e < 512 + 4096) {
-                const int q = e - 512 - 2048;
-                src = Su.Wb + SF_SURB_W3 + (q >> 4) * SF_SUR_HID + (q & 15) * 8;
-                dst = s_surw + SURW_W3 + (q >> 4) * SUR_LD + (q & 15) * 8;
-            } else {
-                const int q = e - 512 - 4096;
-                src = Su.Wb + SF_SURB_W4 + (q >> 4) * SF_SUR_HID + (q & 15) * 8;
-                dst = s_surw + SURW_W4 + (q >> 4) * SUR_LD + (q & 15) * 8;
             }
-            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (dofs[q] >= 0) *reinterpret_cast<uint4 *>(s_surw + dofs[q]) = v[q];
         }
-        for (int e = tid; e < SURW_NB; e += BLOCK)
-            s_surb[e] = e < 128 ? Su.P[SF_SUR_B1 + e] : e < 256 ? Su.P[SF_SUR_B2 + e - 128]
+        {
+            float bv[(SURW_NB + BLOCK - 1) / BLOCK];
+#pragma unroll
+            for (int q = 0; q < (SURW_NB + BLOCK - 1) / BLOCK; ++q) {
+                const int e = tid + q * BLOCK;
+                bv[q] = e < 128 ? Su.P[SF_SUR_B1 + e] : e < 256 ? Su.P[SF_SUR_B2 + e - 128]
                       : e < 384 ? Su.P[SF_SUR_B3 + e - 256] : e < 387 ? Su.P[SF_SUR_B4 + e - 384] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < (SURW_NB + BLOCK - 1) / BLOCK; ++q)
+                if (tid + q * BLOCK < SURW_NB) s_surb[tid + q * BLOCK] = bv[q];
+        }
     }
 
     // Worlds in longest-first order, one descriptor each (world, first
@@ -626,6 +737,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 s_coll[i] = 0;
                 s_forbid[i] = Wd.forbid ? Wd.forbid[n] : 0;
                 s_p0[i] = make_float2(s_p[0][i], s_p[1][i]);
+                s_tail[i] = load_tail(st, ist, N, n);
             }
             __syncthreads();
 
@@ -678,7 +790,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             const f3 pos = mk3(s_p[0][i], s_p[1][i], s_p[2][i]);
                             v = mk3(s_v[0][i], s_v[1][i], s_v[2][i]);
                             om = mk3(s_w[0][i], s_w[1][i], s_w[2][i]);
-                            rm = Rmul(R, mount_of(P, wh));
+                            rm = Rmul(R, mk3(s_mount[3 * wh], s_mount[3 * wh + 1], s_mount[3 * wh + 2]));
                             u = mk3(-R[2], -R[5], -R[8]);
                             const RayHit H = raycast(P, Wd, s_tgrid, s_anytri, add3(pos, rm), u);
                             Om = s_om[wi];
@@ -748,6 +860,25 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                                 for (int q = 0; q < SF_SUR_IN; ++q) feat[q] = 0.f;
                             }
                         }
+                        // ---- training samples: inputs and the plain model's outputs (before the
+                        //      network, so that the features are not kept across it)
+                        if (Su.log && valid) {
+                            const long long slot = (Su.log_base + (long long)sub * 4 * N + 4ll * (a0 + i) + wh) % Su.log_cap;
+                            float *dst = Su.log + slot * SF_SUR_SAMPLE;
+                            if (dom) {
+                                float Fxp, Fyp, omp;
+                                tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fxp, Fyp, omp);
+                                const float lim = mu * Fz;
+#pragma unroll
+                                for (int q = 0; q < SF_SUR_IN; ++q) dst[q] = feat[q];
+                                dst[SF_SUR_IN] = lim > 0.f ? Fxp / lim : 0.f;
+                                dst[SF_SUR_IN + 1] = lim > 0.f ? Fyp / lim : 0.f;
+                                dst[SF_SUR_IN + 2] = lim > 0.f ? -Fyp / lim : 0.f;
+                                dst[SF_SUR_IN + 3] = 1.f;
+                            } else {
+                                dst[SF_SUR_IN + 3] = 0.f;
+                            }
+                        }
                         // ---- learned tire model for the wave's wheels, if enabled
                         bool use = false;
                         float Fxs = 0.f, Fys = 0.f, Mzs = 0.f;
@@ -801,24 +932,6 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                             }
                             s_om[wi] = om1;
                         }
-                        // ---- training samples: inputs and the plain model's outputs
-                        if (Su.log && valid) {
-                            const long long slot = (Su.log_base + (long long)sub * 4 * N + 4ll * (a0 + i) + wh) % Su.log_cap;
-                            float *dst = Su.log + slot * SF_SUR_SAMPLE;
-                            if (dom) {
-                                float Fxp, Fyp, omp;
-                                tire(P, h, Fz, mu, vx, vy, Om, td, tb, Fxp, Fyp, omp);
-                                const float lim = mu * Fz;
-#pragma unroll
-                                for (int q = 0; q < SF_SUR_IN; ++q) dst[q] = feat[q];
-                                dst[SF_SUR_IN] = lim > 0.f ? Fxp / lim : 0.f;
-                                dst[SF_SUR_IN + 1] = lim > 0.f ? Fyp / lim : 0.f;
-                                dst[SF_SUR_IN + 2] = lim > 0.f ? -Fyp / lim : 0.f;
-                                dst[SF_SUR_IN + 3] = 1.f;
-                            } else {
-                                dst[SF_SUR_IN + 3] = 0.f;
-                            }
-                        }
                         if (valid) {
 #pragma unroll
                             for (int c = 0; c < 6; ++c) s_wf[c][wi] = f[c];
@@ -829,9 +942,17 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
 
                 __syncthreads();
                 const int np = s_np;
+                // A world with at most 64 contact points (one a lane) solves them on
+                // wave 0, which holds every agent, with wave-level ordering only
+                // (phases D to G below, then H, with no workgroup barrier); more
+                // points take the workgroup-wide path.  Every wave reaches the
+                // same choice from the pair list.
+                int nsw = 0;
+                if (np > 0 && np <= 64) nsw = wave_sum(lane < np ? __popc(s_pairs[lane] >> 16) : 0);
+                const bool sw = np > 0 && np <= 64 && nsw <= 64;
                 // ---- D: contact points of the compacted pairs, in list order
                 int nc = 0;
-                for (int base = 0; base < np; base += BLOCK) {
+                for (int base = 0; base < (sw ? 0 : np); base += BLOCK) {
                     const int k = base + tid;
                     uint32_t pr = k < np ? s_pairs[k] : 0u;
                     int cnt = __popc(pr >> 16);
@@ -863,20 +984,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                         const int pos = s_poff[kk] + __popc(mask & ((1u << ab) - 1u));
                         if (pos < SF_CCAP) {
                             const int i = prk & 0xFF, j = (prk >> 8) & 0xFF;
-                            const int a = ab / 3, b = ab - 3 * a;
-                            const float cix = s_p[0][i] + (float)(a - 1) * P.cd * s_hx[i];
-                            const float ciy = s_p[1][i] + (float)(a - 1) * P.cd * s_hy[i];
-                            const float cjx = s_p[0][j] + (float)(b - 1) * P.cd * s_hx[j];
-                            const float cjy = s_p[1][j] + (float)(b - 1) * P.cd * s_hy[j];
-                            const float dx = cjx - cix, dy = cjy - ciy;
-                            const float L = sqrtf(dx * dx + dy * dy);
-                            s_cn[0][pos] = L > 0.f ? dx / L : 1.f;
-                            s_cn[1][pos] = L > 0.f ? dy / L : 0.f;
-                            s_cpc[0][pos] = 0.5f * (cix + cjx);
-                            s_cpc[1][pos] = 0.5f * (ciy + cjy);
-                            s_cpc[2][pos] = 0.5f * (s_p[2][i] + s_p[2][j]);
-                            const float pen = 2.f * P.cr - L - P.slop;
-                            s_cb[pos] = pen > 0.f ? (P.baumgarte / h) * pen : 0.f;
+                            const CPoint cp = contact_point(P, h, s_p, s_hx, s_hy, i, j, ab);
+                            s_cn[0][pos] = cp.nx;
+                            s_cn[1][pos] = cp.ny;
+                            s_cpc[0][pos] = cp.px;
+                            s_cpc[1][pos] = cp.py;
+                            s_cpc[2][pos] = cp.pz;
+                            s_cb[pos] = cp.b;
                             s_clam[pos] = 0.f;
                             s_cij[pos] = i | (j << 8);
                         }
@@ -893,7 +1007,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     }
                     nc = SF_CCAP;
                 }
-                __syncthreads();
+                // (np, nc and sw are the same in every thread: without pairs, or on
+                //  the one-wave path, D wrote nothing)
+                if (np > 0 && !sw) __syncthreads();
 
                 // ---- E: chassis velocities (semi-implicit Euler, explicit gyroscopic
                 //      term) and each body's contact list in list order
@@ -938,9 +1054,171 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     }
                     s_bn[i] = cnt;
                 }
-                __syncthreads();
 
-                if (nc > 0) {
+                if (sw) {
+                    if (wave == 0) {
+                        // ---- D on one wave: pair k (lane k) takes contact slots from
+                        //      the prefix sum of its mask's bits, in list order
+                        wave_sync();
+                        const uint32_t pr = lane < np ? s_pairs[lane] : 0u;
+                        const int pcnt = __popc(pr >> 16);
+                        int incl = pcnt;
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const int y = __shfl_up(incl, o, 64);
+                            if (lane >= o) incl += y;
+                        }
+                        const int poff = incl - pcnt;
+                        for (int q = 0; q < pcnt; ++q) s_poff[poff + q] = lane;
+                        if (lane < A) s_bmask[lane] = 0ull;
+                        wave_sync();
+                        const bool own = lane < nsw;
+                        const int kq = own ? s_poff[lane] : 0;
+                        const int koff = __shfl(poff, kq, 64);
+                        const uint32_t kpr = __shfl((int)pr, kq, 64);
+                        int ci = 0, cj = 0;
+                        float cnx = 0.f, cny = 0.f, cbb = 0.f, cwk = 0.f, clam = 0.f;
+                        f3 cri = mk3(0.f, 0.f, 0.f), crj = cri;
+                        if (own) {
+                            // the (lane - koff)-th set bit of the pair's mask
+                            uint32_t m = kpr >> 16;
+                            for (int r = lane - koff; r > 0; --r) m &= m - 1u;
+                            ci = kpr & 0xFF;
+                            cj = (kpr >> 8) & 0xFF;
+                            const CPoint cp = contact_point(P, h, s_p, s_hx, s_hy, ci, cj, __ffs(m) - 1);
+                            cnx = cp.nx;
+                            cny = cp.ny;
+                            cbb = cp.b;
+                            s_cn[0][lane] = cp.nx;
+                            s_cn[1][lane] = cp.ny;
+                            s_cpc[0][lane] = cp.px;
+                            s_cpc[1][lane] = cp.py;
+                            s_cpc[2][lane] = cp.pz;
+                            s_cij[lane] = ci | (cj << 8);
+                            cri = sub3(mk3(cp.px, cp.py, cp.pz), mk3(s_p[0][ci], s_p[1][ci], s_p[2][ci]));
+                            crj = sub3(mk3(cp.px, cp.py, cp.pz), mk3(s_p[0][cj], s_p[1][cj], s_p[2][cj]));
+                            // each body's contacts as a bit set over the list
+                            atomicOr(&s_bmask[ci], 1ull << lane);
+                            atomicOr(&s_bmask[cj], 1ull << lane);
+                        }
+                        wave_sync();
+                        // ---- F: effective mass, relaxed by the larger contact count
+                        if (own) {
+                            float Ri[9], Rj[9];
+#pragma unroll
+                            for (int q = 0; q < 9; ++q) { Ri[q] = s_R[q][ci]; Rj[q] = s_R[q][cj]; }
+                            const f3 n = mk3(cnx, cny, 0.f);
+                            const f3 xi = cross3(cri, n), xj = cross3(crj, n);
+                            const float keff = 2.f * P.inv_mass + dot3(xi, inv_inertia(P, Ri, xi)) +
+                                               dot3(xj, inv_inertia(P, Rj, xj));
+                            const int nmax = max(__popcll(s_bmask[ci]), __popcll(s_bmask[cj]));
+                            cwk = 1.f / ((float)nmax * keff);
+                        }
+                        // body lane b: its first SW_K contacts in list order with their
+                        // normals (signed toward the body: the sign flip is exact) and
+                        // lever arms, its velocities and inertia
+                        constexpr int SW_K = 9;
+                        const int b = lane;
+                        unsigned long long bm = b < A ? s_bmask[b] : 0ull;
+                        const int bcnt = __popcll(bm);
+                        const int kmax = wave_max(min(bcnt, SW_K));
+                        int kc[SW_K];
+                        float kx[SW_K], ky[SW_K], krx[SW_K], kry[SW_K], krz[SW_K];
+                        const float pbx = b < A ? s_p[0][b] : 0.f, pby = b < A ? s_p[1][b] : 0.f,
+                                    pbz = b < A ? s_p[2][b] : 0.f;
+#pragma unroll
+                        for (int u = 0; u < SW_K; ++u) {
+                            kc[u] = 0;
+                            kx[u] = ky[u] = krx[u] = kry[u] = krz[u] = 0.f;
+                            if (u < kmax && bm) {
+                                const int c = __ffsll((long long)bm) - 1;
+                                bm &= bm - 1ull;
+                                kc[u] = c;
+                                const bool toward = ((s_cij[c] >> 8) & 0xFF) == b;
+                                kx[u] = toward ? s_cn[0][c] : -s_cn[0][c];
+                                ky[u] = toward ? s_cn[1][c] : -s_cn[1][c];
+                                krx[u] = s_cpc[0][c] - pbx;
+                                kry[u] = s_cpc[1][c] - pby;
+                                krz[u] = s_cpc[2][c] - pbz;
+                            }
+                        }
+                        // bm now holds the contacts past the first SW_K
+                        float ev0 = 0.f, ev1 = 0.f, ew0 = 0.f, ew1 = 0.f, ew2 = 0.f;
+                        float iw0 = 0.f, iw1 = 0.f, iw2 = 0.f, iw3 = 0.f, iw4 = 0.f, iw5 = 0.f;
+                        if (bcnt > 0) {
+                            ev0 = s_v[0][b];
+                            ev1 = s_v[1][b];
+                            ew0 = s_w[0][b];
+                            ew1 = s_w[1][b];
+                            ew2 = s_w[2][b];
+                            iw0 = s_iw[0][b];
+                            iw1 = s_iw[1][b];
+                            iw2 = s_iw[2][b];
+                            iw3 = s_iw[3][b];
+                            iw4 = s_iw[4][b];
+                            iw5 = s_iw[5][b];
+                        }
+                        // ---- G: Jacobi sweeps; a body adds its contacts in list order
+                        for (int it = 0; it < P.jacobi_iters; ++it) {
+                            if (own) {
+                                // every load first, then the arithmetic
+                                const float wix = s_w[0][ci], wiy = s_w[1][ci], wiz = s_w[2][ci];
+                                const float wjx = s_w[0][cj], wjy = s_w[1][cj], wjz = s_w[2][cj];
+                                const float vix = s_v[0][ci], viy = s_v[1][ci];
+                                const float vjx = s_v[0][cj], vjy = s_v[1][cj];
+                                const f3 wi = cross3(mk3(wix, wiy, wiz), cri);
+                                const f3 wj = cross3(mk3(wjx, wjy, wjz), crj);
+                                const float vn = ((vjx + wj.x) - (vix + wi.x)) * cnx + ((vjy + wj.y) - (viy + wi.y)) * cny;
+                                const float lam1 = fmaxf(clam + cwk * (-vn + cbb), 0.f);
+                                s_cdl[lane] = lam1 - clam;
+                                clam = lam1;
+                            }
+                            wave_sync();
+                            if (bcnt > 0) {
+                                float d[SW_K];
+#pragma unroll
+                                for (int u = 0; u < SW_K; ++u) d[u] = u < kmax ? s_cdl[kc[u]] : 0.f;
+                                float jx = 0.f, jy = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
+#pragma unroll
+                                for (int u = 0; u < SW_K; ++u) {
+                                    if (u < kmax && u < bcnt) {
+                                        const float Jx = d[u] * kx[u], Jy = d[u] * ky[u];
+                                        jx += Jx;
+                                        jy += Jy;
+                                        tx -= krz[u] * Jy;
+                                        ty += krz[u] * Jx;
+                                        tz += krx[u] * Jy - kry[u] * Jx;
+                                    }
+                                }
+                                for (unsigned long long rest = bm; rest; rest &= rest - 1ull) {
+                                    const int c = __ffsll((long long)rest) - 1;
+                                    const float cd = s_cdl[c];
+                                    const float dl = ((s_cij[c] >> 8) & 0xFF) == b ? cd : -cd;
+                                    const float Jx = dl * s_cn[0][c], Jy = dl * s_cn[1][c];
+                                    const float rx = s_cpc[0][c] - pbx, ry = s_cpc[1][c] - pby,
+                                                rz = s_cpc[2][c] - pbz;
+                                    jx += Jx;
+                                    jy += Jy;
+                                    tx -= rz * Jy;
+                                    ty += rz * Jx;
+                                    tz += rx * Jy - ry * Jx;
+                                }
+                                ev0 += jx * P.inv_mass;
+                                ev1 += jy * P.inv_mass;
+                                ew0 += iw0 * tx + iw1 * ty + iw2 * tz;
+                                ew1 += iw1 * tx + iw3 * ty + iw4 * tz;
+                                ew2 += iw2 * tx + iw4 * ty + iw5 * tz;
+                                s_v[0][b] = ev0;
+                                s_v[1][b] = ev1;
+                                s_w[0][b] = ew0;
+                                s_w[1][b] = ew1;
+                                s_w[2][b] = ew2;
+                            }
+                            wave_sync();
+                        }
+                    }
+                } else if (nc > 0) {
+                    __syncthreads();
                     // ---- each body's contacts as one range of a CSR list, in list
                     //      order (every contact appears once for each of its bodies)
                     if (wave == 0) {
@@ -1043,7 +1321,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     }
                 }
 
-                // ---- H: positions and orientations
+                // ---- H: positions and orientations (agent i is on the thread that ran its
+                //      E, so without contacts no barrier separates the two)
                 for (int i = tid; i < A; i += BLOCK) {
                     if (!s_act[i]) continue;
                     const float vx = s_v[0][i], vy = s_v[1][i], vz = s_v[2][i];
@@ -1086,7 +1365,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                 dyn[SF_F_STEER] = s_th[i];
                 dyn[SF_F_STEER_RATE] = s_thd[i];
                 finish_agent(P, Wd, st, ist, N, n, w, i, dyn, s_muo[i], s_coll[i] != 0, s_nan[i] != 0, s_ovf != 0,
-                             s_forbid[i] != 0, s_p0[i], reward, done, events);
+                             s_forbid[i] != 0, s_p0[i], s_tail[i], reward, done, events);
             }
         } while (0);
         if (!queue) break;
@@ -1233,7 +1512,7 @@ __global__ __launch_bounds__(64) void k_step_bicycle(DevParams P, DevWorld Wd, f
         dyn[SF_F_STEER_RATE] = 0.f;
     }
     finish_agent(P, Wd, st, ist, N, n, w, i, dyn, 0.f, s_coll[i] != 0, bad, false, Wd.forbid && Wd.forbid[n],
-                 p0, reward, done, events);
+                 p0, load_tail(st, ist, N, n), reward, done, events);
 }
 
 void launch_step_bicycle(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act, float dt,
