@@ -255,33 +255,37 @@ __device__ __forceinline__ f3 inv_inertia(const DevParams &P, const float R[9], 
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-// One hidden layer for the tile's 32 rows, written back over its input.
-// The product is taken transposed, out^T = W in^T (weights as the row
-// operand), so that each lane ends up with four consecutive outputs of one
-// row: bias, ReLU, one packed bf16 conversion and one 8-byte store.
-template <int KS>
-__device__ __forceinline__ void sur_layer32(uint16_t *buf, const uint16_t *W, int ldw, const float *bias) {
+// One hidden layer for the tile's 16 RT rows (RT = 1 or 2), written back
+// over its input.  The product is taken transposed, out^T = W in^T (weights
+// as the row operand), so that each lane ends up with four consecutive
+// outputs of one row: bias, ReLU, one packed bf16 conversion and one 8-byte
+// store.
+template <int KS, int RT>
+__device__ __forceinline__ void sur_layer(uint16_t *buf, const uint16_t *W, int ldw, const float *bias) {
     const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
-    f32x4 acc[8][2];
+    f32x4 acc[8][RT];
 #pragma unroll
-    for (int n = 0; n < 8; ++n) acc[n][0] = acc[n][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int n = 0; n < 8; ++n)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[n][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     // every fragment of a 32-deep slice is read before its products are
     // issued, so that the LDS reads overlap one another
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k0 = ks * 32 + kq * 8;
-        const bf16x8 x0 = ld8(buf + r16 * SUR_LD + k0), x1 = ld8(buf + (16 + r16) * SUR_LD + k0);
+        bf16x8 x[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) x[t] = ld8(buf + (16 * t + r16) * SUR_LD + k0);
         bf16x8 w[8];
 #pragma unroll
         for (int n = 0; n < 8; ++n) w[n] = ld8(W + (n * 16 + r16) * ldw + k0);
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            acc[n][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[n], x0, acc[n][0], 0, 0, 0);
-            acc[n][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[n], x1, acc[n][1], 0, 0, 0);
-        }
-        // scheduling hint: the slice's ten LDS reads, then its sixteen products
-        __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+        for (int n = 0; n < 8; ++n)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) acc[n][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[n], x[t], acc[n][t], 0, 0, 0);
+        // scheduling hint: the slice's LDS reads, then its products
+        __builtin_amdgcn_sched_group_barrier(0x100, 8 + RT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 8 * RT, 0);
     }
     wave_sync();
     // lane holds out[row 16 t + lane % 16][16 n + 4 (lane / 16) + j]
@@ -289,7 +293,7 @@ __device__ __forceinline__ void sur_layer32(uint16_t *buf, const uint16_t *W, in
     for (int n = 0; n < 8; ++n) {
         const float4 bb = *reinterpret_cast<const float4 *>(bias + n * 16 + kq * 4);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < RT; ++t) {
             bf16x4 o;
             o[0] = (__bf16)fmaxf(acc[n][t][0] + bb.x, 0.f);
             o[1] = (__bf16)fmaxf(acc[n][t][1] + bb.y, 0.f);
@@ -301,17 +305,49 @@ __device__ __forceinline__ void sur_layer32(uint16_t *buf, const uint16_t *W, in
     wave_sync();
 }
 
+// The three hidden layers and the 3-wide output layer for 16 RT rows of the
+// tile.  The output is a product against W4 padded to 16 rows; its fp32
+// results go to the row's padding columns, where the row's lane reads them.
+template <int RT>
+__device__ __forceinline__ void sur_pass(uint16_t *buf, const uint16_t *Wl, const float *bl) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+    sur_layer<1, RT>(buf, Wl, SURW_LD1, bl);
+    sur_layer<4, RT>(buf, Wl + SURW_W2, SUR_LD, bl + 128);
+    sur_layer<4, RT>(buf, Wl + SURW_W3, SUR_LD, bl + 256);
+    f32x4 o[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) o[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const int k0 = ks * 32 + kq * 8;
+        const bf16x8 w = ld8(Wl + SURW_W4 + (r16 < 3 ? r16 : 0) * SUR_LD + k0);
+        const bf16x8 wz = r16 < 3 ? w : zero8();
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+            o[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(buf + (16 * t + r16) * SUR_LD + k0), wz, o[t], 0, 0, 0);
+    }
+    wave_sync();
+    if (r16 < 3) {
+        const float b4 = bl[384 + r16];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                reinterpret_cast<float *>(buf + (16 * t + kq * 4 + j) * SUR_LD + 128)[r16] = o[t][j] + b4;
+    }
+    wave_sync();
+}
+
 // The learned tire model on the wheels of one wave that are inside its
 // domain, compacted: the k-th such wheel (in lane order) takes row k % 32 of
-// pass k / 32, so that a wave runs one 32-row pass per 32 wheels that use
-// the network (none when no wheel does) and a row's result does not depend
-// on the pass it lands in; bf16 inputs and weights on the matrix cores,
-// fp32 accumulation.  The 3-wide output layer is a product against W4
-// padded to 16 rows; its fp32 results go to the row's padding columns,
-// where the row's lane reads them.  Lanes outside the domain ignore y.
+// pass k / 32, so that a wave runs one pass per 32 wheels that use the
+// network (none when no wheel does; a pass of at most 16 rows runs one
+// 16-row tile) and a row's result does not depend on the pass or tile it
+// lands in; bf16 inputs and weights on the matrix cores, fp32 accumulation.
+// Lanes outside the domain ignore y.
 __device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool inside, const uint16_t *Wl,
                              const float *bl, float (&y)[3]) {
-    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+    const int lane = threadIdx.x & 63;
     const unsigned long long any = __ballot(inside);
     const int cnt = __popcll(any);
     const int pos = __popcll(any & ((1ull << lane) - 1ull));    // rank among the inside lanes
@@ -320,6 +356,7 @@ __device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool
     for (int half = 0; half < 2; ++half) {
         const int rows = min(cnt - 32 * half, 32);
         if (rows <= 0) break;
+        const int tile_rows = rows > 16 ? 32 : 16;
         if (inside && (pos >> 5) == half) {
             bf16x8 v0, v1;
 #pragma unroll
@@ -332,34 +369,14 @@ __device__ void sur_mlp_wave(uint16_t *buf, const float (&feat)[SF_SUR_IN], bool
             d[1] = v1;
             d[2] = zero8();
             d[3] = zero8();
-        } else if (lane < 32 && lane >= rows) {
+        } else if (lane < tile_rows && lane >= rows) {
             // rows no wheel takes in this pass: zero inputs
             bf16x8 *d = reinterpret_cast<bf16x8 *>(buf + lane * SUR_LD);
             d[0] = d[1] = d[2] = d[3] = zero8();
         }
         wave_sync();
-        sur_layer32<1>(buf, Wl, SURW_LD1, bl);
-        sur_layer32<4>(buf, Wl + SURW_W2, SUR_LD, bl + 128);
-        sur_layer32<4>(buf, Wl + SURW_W3, SUR_LD, bl + 256);
-        f32x4 o0 = f32x4{0.f, 0.f, 0.f, 0.f}, o1 = o0;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k0 = ks * 32 + kq * 8;
-            const bf16x8 w = ld8(Wl + SURW_W4 + (r16 < 3 ? r16 : 0) * SUR_LD + k0);
-            const bf16x8 wz = r16 < 3 ? w : zero8();
-            o0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(buf + r16 * SUR_LD + k0), wz, o0, 0, 0, 0);
-            o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(buf + (16 + r16) * SUR_LD + k0), wz, o1, 0, 0, 0);
-        }
-        wave_sync();
-        if (r16 < 3) {
-            const float b4 = bl[384 + r16];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                reinterpret_cast<float *>(buf + (kq * 4 + j) * SUR_LD + 128)[r16] = o0[j] + b4;
-                reinterpret_cast<float *>(buf + (16 + kq * 4 + j) * SUR_LD + 128)[r16] = o1[j] + b4;
-            }
-        }
-        wave_sync();
+        if (tile_rows == 32) sur_pass<2>(buf, Wl, bl);
+        else sur_pass<1>(buf, Wl, bl);
         if (inside && (pos >> 5) == half) {
             const float *yo = reinterpret_cast<const float *>(buf + (pos & 31) * SUR_LD + 128);
             y[0] = yo[0];
@@ -628,6 +645,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     // update per workgroup at the end instead of one per wave and substep)
     __shared__ unsigned s_sur_cnt[2];
     if (SUR && tid < 2) s_sur_cnt[tid] = 0u;
+    // the learned tire model's input envelope (lo then hi), read as vectors
+    __shared__ __attribute__((aligned(16))) float s_env[SUR ? 2 * SF_SUR_IN : 4];
+    if (SUR && tid < 2 * SF_SUR_IN) s_env[tid] = tid < SF_SUR_IN ? Su.lo[tid] : Su.hi[tid - SF_SUR_IN];
     // wheel mount points (an indexed read of the argument block per wheel
     // would be a memory gather on every substep)
     __shared__ float s_mount[12];
@@ -829,32 +849,33 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                         float feat[SF_SUR_IN];
                         if (SUR || Su.log) {
                             if (dom) {
-                                const float D = fmaxf(fabsf(vx), P.v_eps);
+                                const float D = fmaxf(fabsf(vx), P.v_eps), iD = 1.f / D;
                                 const f3 axle = Rmul(R, mk3(-sinf(dl), cosf(dl), 0.f));
-                                feat[0] = (P.rw * Om - vx) / D;
-                                feat[1] = atanf(vy / D);
-                                feat[2] = Fz / 4000.f;
+                                feat[0] = (P.rw * Om - vx) * iD;
+                                feat[1] = atanf(vy * iD);
+                                feat[2] = Fz * (1.f / 4000.f);
                                 feat[3] = mu;
-                                feat[4] = P.rw * Om / 30.f;
+                                feat[4] = P.rw * Om * (1.f / 30.f);
                                 feat[5] = asinf(fminf(fmaxf(dot3(axle, n), -1.f), 1.f));
-                                feat[6] = vx / 30.f;
-                                feat[7] = vy / 5.f;
+                                feat[6] = vx * (1.f / 30.f);
+                                feat[7] = vy * 0.2f;
                                 feat[8] = dl;
-                                feat[9] = x / 0.2f;
-                                feat[10] = xd / 2.f;
+                                feat[9] = x * 5.f;
+                                feat[10] = xd * 0.5f;
                                 feat[11] = td / P.tau_drive;
                                 feat[12] = tb / P.tau_bf;
                                 // the slip vector over mu, at most 2 long
                                 float sx = 0.f, sy = 0.f;
                                 if (mu > 0.f) {
-                                    sx = feat[0] / mu;
-                                    sy = vy / D / mu;
+                                    const float imu = 1.f / mu;
+                                    sx = feat[0] * imu;
+                                    sy = vy * iD * imu;
                                     const float L = sqrtf(sx * sx + sy * sy);
                                     if (L > 2.f) { sx *= 2.f / L; sy *= 2.f / L; }
                                 }
                                 feat[13] = sx;
                                 feat[14] = sy;
-                                feat[15] = om.z / 2.f;
+                                feat[15] = om.z * 0.5f;
                             } else {
 #pragma unroll
                                 for (int q = 0; q < SF_SUR_IN; ++q) feat[q] = 0.f;
@@ -885,7 +906,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                         if (SUR) {
                             bool inside = dom;
 #pragma unroll
-                            for (int q = 0; q < SF_SUR_IN; ++q) inside = inside && feat[q] >= Su.lo[q] && feat[q] <= Su.hi[q];
+                            for (int q = 0; q < SF_SUR_IN; q += 4) {
+                                const float4 lo = *reinterpret_cast<const float4 *>(s_env + q);
+                                const float4 hi = *reinterpret_cast<const float4 *>(s_env + SF_SUR_IN + q);
+                                inside = inside && feat[q] >= lo.x && feat[q] <= hi.x && feat[q + 1] >= lo.y &&
+                                         feat[q + 1] <= hi.y && feat[q + 2] >= lo.z && feat[q + 2] <= hi.z &&
+                                         feat[q + 3] >= lo.w && feat[q + 3] <= hi.w;
+                            }
                             if (__ballot(inside)) {
                                 float y[3];
                                 sur_mlp_wave(s_sur + wave * SUR_ROWS * SUR_LD, feat, inside, s_surw, s_surb, y);
