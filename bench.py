@@ -259,6 +259,18 @@ def surrogate_leg(sim, torch, sf, I, stream, dt, S, steps, warmup, train_samples
     sim.sur_enable(True)
     for _ in range(warmup):
         sim.step_policy(dt, S)
+    # the plain step's kernel over the same control steps from the same
+    # state, so that the two kernels are compared on one load
+    f0, k0 = sim.get_state()
+    sim.sur_enable(False)
+    sim.profile(True)
+    for _ in range(steps):
+        sim.step_policy(dt, S)
+    torch.cuda.synchronize()
+    ev_p, fixed_p = read_profile(sim)
+    plain_us = kernel_us(ev_p, fixed_p)["step"]
+    sim.set_state(f0, k0)
+    sim.sur_enable(True)
     # profiled eager pass (per-kernel events, wheel counts), then the timed
     # region measured as the plain step is: replays of a captured graph
     sim.sur_counts(reset=True)
@@ -292,6 +304,8 @@ def surrogate_leg(sim, torch, sf, I, stream, dt, S, steps, warmup, train_samples
         "value": casps, "unit": "controlled-agent steps/s", "ms_per_step": ms / steps,
         "timed": f"{steps} control steps as replays of {G}-step hipGraphs (profiling off), seed of the main leg",
         "step_kernel_us": step_us,
+        "plain_step_kernel_us_same_steps": plain_us,
+        "step_kernel_ratio": step_us / plain_us,
         "network_tflops_in_step": net_tflops, "train_tflops": train_tflops,
         "network_share": used / max(1, used + fb), "wheel_substeps_in_domain": used + fb,
         "force_error_heldout": err, "force_error_benchmark_workload": err_main,

@@ -148,7 +148,34 @@ __device__ __forceinline__ int cell_y(const GridHdr &g, float y) {
     return c < 0 ? 0 : (c >= g.ny ? g.ny - 1 : c);
 }
 
-// mode 0: count, mode 1: scatter through cursors
+// Whether triangle (a, b, c), projected on the ground plane, may meet the
+// cell [x0, x1] x [y0, y1]: false only when one of its edges separates the
+// two, with the cell widened by 1 mm (far above the rounding of these
+// coordinates), so no cell that a point of the triangle lies in is ever
+// left out.  A degenerate projection keeps its whole bounding box.
+__device__ __forceinline__ bool tri_meets_cell(const float *p, float x0, float y0, float x1, float y1) {
+    const float ax = p[0], ay = p[1], bx = p[3], by = p[4], cx = p[6], cy = p[7];
+    const float area2 = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+    if (fabsf(area2) < 1e-6f) return true;
+    const float s = area2 > 0.f ? 1.f : -1.f;
+    const float m = 1e-3f;
+    x0 -= m; y0 -= m; x1 += m; y1 += m;
+    const float vx[3] = {ax, bx, cx}, vy[3] = {ay, by, cy};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const float px = vx[e], py = vy[e];
+        const float ex = vx[(e + 1) % 3] - px, ey = vy[(e + 1) % 3] - py;
+        // s * cross(edge, q - p) >= 0 inside; the cell's corner that
+        // maximises it
+        const float nx = -s * ey, ny = s * ex;
+        const float qx = nx > 0.f ? x1 : x0, qy = ny > 0.f ? y1 : y0;
+        if (nx * (qx - px) + ny * (qy - py) < 0.f) return false;
+    }
+    return true;
+}
+
+// mode 0: count, mode 1: scatter through cursors (both take the same cells:
+// those of the triangle's bounding box that the triangle itself meets)
 template <int MODE>
 __global__ void k_grid_tris(DevWorld Wd, const float *verts, int T, int *cnt_or_cursor, int *items) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -165,8 +192,15 @@ __global__ void k_grid_tris(DevWorld Wd, const float *verts, int T, int *cnt_or_
     float xa = fminf(p[0], fminf(p[3], p[6])), xb = fmaxf(p[0], fmaxf(p[3], p[6]));
     float ya = fminf(p[1], fminf(p[4], p[7])), yb = fmaxf(p[1], fmaxf(p[4], p[7]));
     int cx0 = cell_x(g, xa), cx1 = cell_x(g, xb), cy0 = cell_y(g, ya), cy1 = cell_y(g, yb);
+    const bool one = cx0 == cx1 && cy0 == cy1;
     for (int cy = cy0; cy <= cy1; ++cy)
         for (int cx = cx0; cx <= cx1; ++cx) {
+            // cells at the grid's clamped border reach to infinity
+            const float x0 = cx == 0 ? -INFINITY : g.x0 + (float)cx * g.cell;
+            const float x1 = cx == g.nx - 1 ? INFINITY : g.x0 + (float)(cx + 1) * g.cell;
+            const float y0 = cy == 0 ? -INFINITY : g.y0 + (float)cy * g.cell;
+            const float y1 = cy == g.ny - 1 ? INFINITY : g.y0 + (float)(cy + 1) * g.cell;
+            if (!one && !tri_meets_cell(p, x0, y0, x1, y1)) continue;
             int c = g.cbase + cy * g.nx + cx;
             if (MODE == 0) atomicAdd(&cnt_or_cursor[c], 1);
             else items[atomicAdd(&cnt_or_cursor[c], 1)] = k - Wd.toff[w];

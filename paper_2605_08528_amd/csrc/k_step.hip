@@ -654,48 +654,46 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
     if (tid < 12) s_mount[tid] = P.mount[tid / 3][tid % 3];
 
     if (SUR) {
-        // the network's weights and biases, once per block for all substeps;
-        // each block starts at its own offset so that the blocks' copies do
-        // not all hit the same memory lines at once, and each thread keeps
-        // its 16-byte loads in flight (up to 24) before it stores them
-        constexpr int NCH = 128 * 4 + 2 * 128 * 16 + 3 * 16;
-        constexpr int PER = (NCH + BLOCK - 1) / BLOCK;
-        constexpr int NB = PER < 24 ? PER : 24;
+        // the network's weights, once per block for all substeps: each matrix
+        // as 16-byte chunks with shift-and-mask addressing (no per-chunk
+        // branching), each block starting at its own chunk offset so that the
+        // blocks' copies do not all hit the same memory lines at once, and
+        // each thread's loads in flight before its stores
         const int rot = (int)(blockIdx.x % 64) * 64;
-        for (int k0 = 0; k0 < PER; k0 += NB) {
-            uint4 v[NB];
-            int dofs[NB];
+        // W2 and W3: 128 rows of 16 chunks, into rows of SUR_LD
+        constexpr int N23 = (2048 + BLOCK - 1) / BLOCK;
+        constexpr int B23 = N23 < 8 ? N23 : 8;
+#pragma unroll 1
+        for (int q0 = 0; q0 < N23; q0 += B23) {
+            uint4 v2[B23], v3[B23];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int e0 = tid + (k0 + q) * BLOCK;
-                dofs[q] = -1;
-                v[q] = make_uint4(0u, 0u, 0u, 0u);
-                if (e0 < NCH) {
-                    const int e = e0 + rot < NCH ? e0 + rot : e0 + rot - NCH;
-                    const uint16_t *src = nullptr;
-                    if (e < 512) {
-                        // W1 rows: 16 inputs then 16 zeros
-                        dofs[q] = (e >> 2) * SURW_LD1 + (e & 3) * 8;
-                        if ((e & 3) < 2) src = Su.Wb + SF_SURB_W1 + (e >> 2) * SF_SUR_IN + (e & 3) * 8;
-                    } else if (e < 512 + 2048) {
-                        const int r = e - 512;
-                        src = Su.Wb + SF_SURB_W2 + (r >> 4) * SF_SUR_HID + (r & 15) * 8;
-                        dofs[q] = SURW_W2 + (r >> 4) * SUR_LD + (r & 15) * 8;
-                    } else if (e < 512 + 4096) {
-                        const int r = e - 512 - 2048;
-                        src = Su.Wb + SF_SURB_W3 + (r >> 4) * SF_SUR_HID + (r & 15) * 8;
-                        dofs[q] = SURW_W3 + (r >> 4) * SUR_LD + (r & 15) * 8;
-                    } else {
-                        const int r = e - 512 - 4096;
-                        src = Su.Wb + SF_SURB_W4 + (r >> 4) * SF_SUR_HID + (r & 15) * 8;
-                        dofs[q] = SURW_W4 + (r >> 4) * SUR_LD + (r & 15) * 8;
-                    }
-                    if (src) v[q] = *reinterpret_cast<const uint4 *>(src);
-                }
+            for (int q = 0; q < B23; ++q) {
+                const int r = ((q0 + q) * BLOCK + tid + rot) & 2047;
+                const int so = (r >> 4) * SF_SUR_HID + (r & 15) * 8;
+                v2[q] = *reinterpret_cast<const uint4 *>(Su.Wb + SF_SURB_W2 + so);
+                v3[q] = *reinterpret_cast<const uint4 *>(Su.Wb + SF_SURB_W3 + so);
             }
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (dofs[q] >= 0) *reinterpret_cast<uint4 *>(s_surw + dofs[q]) = v[q];
+            for (int q = 0; q < B23; ++q) {
+                const int r = ((q0 + q) * BLOCK + tid + rot) & 2047;
+                const int d = (r >> 4) * SUR_LD + (r & 15) * 8;
+                *reinterpret_cast<uint4 *>(s_surw + SURW_W2 + d) = v2[q];
+                *reinterpret_cast<uint4 *>(s_surw + SURW_W3 + d) = v3[q];
+            }
+        }
+        // W1: 128 rows of 16 inputs (2 chunks) then 16 zeros; W4: 3 rows of
+        // 16 chunks
+        for (int r = tid; r < 256 + 48; r += BLOCK) {
+            if (r < 256) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(Su.Wb + SF_SURB_W1 + (r >> 1) * SF_SUR_IN + (r & 1) * 8);
+                const int d = (r >> 1) * SURW_LD1 + (r & 1) * 8;
+                *reinterpret_cast<uint4 *>(s_surw + d) = v;
+                *reinterpret_cast<uint4 *>(s_surw + d + 16) = make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                const int k = r - 256;
+                const uint4 v = *reinterpret_cast<const uint4 *>(Su.Wb + SF_SURB_W4 + (k >> 4) * SF_SUR_HID + (k & 15) * 8);
+                *reinterpret_cast<uint4 *>(s_surw + SURW_W4 + (k >> 4) * SUR_LD + (k & 15) * 8) = v;
+            }
         }
         {
             float bv[(SURW_NB + BLOCK - 1) / BLOCK];
@@ -790,12 +788,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur
                     if (lane == 0) s_np = np_w;
                 }
                 const int wheel_threads = NWV == 1 ? BLOCK : BLOCK - 64;
+                // the world's wheels spread evenly over the wheel waves (per_wave
+                // consecutive wheels a wave and pass), so that a wave holds as
+                // few wheels as the world allows: its ray test runs to the
+                // longest record list of fewer lanes, and the learned tire model
+                // runs fewer row passes
+                const int npass = (4 * A + wheel_threads - 1) / wheel_threads;
+                const int per_wave = (4 * A + npass * NSW - 1) / (npass * NSW);
                 if (tid < wheel_threads) {
                     // the loop bound is the same for every lane of a wave (the
                     // surrogate's matrix products need the whole wave)
-                    for (int base = 0; base < 4 * A; base += wheel_threads) {
-                        const int wi = base + tid;
-                        const bool valid = wi < 4 * A;
+                    for (int pass = 0; pass < npass; ++pass) {
+                        const int wi = (pass * NSW + wave) * per_wave + lane;
+                        const bool valid = lane < per_wave && wi < 4 * A;
                         const int i = valid ? (wi >> 2) : 0, wh = wi & 3;
                         const bool live = valid && s_act[i];
                         float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};

@@ -20,10 +20,14 @@ def torch():
 
 
 def test_road_touch_counts_known_cases(torch):
-    """One vehicle at rest on a flat world of two triangles (0.5 m triangle
-    cells, each holding both triangles): its four vertical wheel rays read
-    one cell each, so the step reads 4 x 2 triangle records and 4 x 2 cell
-    range entries in every substep, 8 and 8 distinct per step.  With a road
+    """One vehicle at rest at the centre of a flat square of two triangles
+    split along the diagonal y = x (0.5 m triangle cells, a triangle listed
+    in the cells it meets, within 1 mm): its four vertical wheel rays read
+    one cell each.  The front-left wheel's cell [1.0, 1.5] x [0.5, 1.0] and
+    the rear-right one's [-1.5, -1.0] x [-1.0, -0.5] touch the diagonal at a
+    corner and hold both triangles, the other two cells one each, so the
+    step reads 2 + 1 + 1 + 2 = 6 triangle records and 4 x 2 cell range
+    entries, distinct per step.  With a road
     of polylines the observation reads exactly 64 distinct road points for
     its one agent, the occupancy of its cell once, and at least 64 point
     records.  Bytes are the item counts weighted by the item sizes; graph
@@ -38,7 +42,7 @@ def test_road_touch_counts_known_cases(torch):
             sim.step(act, 1.0 / 30.0, 4)
         items, nbytes, steps = sim.road_touch_read()
         assert steps == 3
-        assert items[0].tolist() == [24, 24, 0, 0, 0, 0], items
+        assert items[0].tolist() == [18, 24, 0, 0, 0, 0], items
         assert items[1].tolist() == [0] * 6, items
         assert nbytes.tolist() == (items * SIZES).sum(axis=1).tolist()
         sim.policy_load(*I.mlp_params([256, 256, 256, 2], seed=0))
