@@ -597,8 +597,12 @@ __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld 
         for (int c = 0; c < 6; ++c) s_cq[c][i] = cq_[c];                             \
     } while (0)
 
+// Two waves a SIMD for the plain step with more than one wave (its
+// registers then stay within 256, so several worlds share a compute unit
+// when the grid has more worlds than units); the learned tire model's LDS
+// copy leaves room for one workgroup a unit anyway.
 template <int BLOCK, bool SUR>
-__global__ __launch_bounds__(BLOCK) void k_step(DevParams P, DevWorld Wd, DevSur Su, float *__restrict__ st,
+__global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevParams P, DevWorld Wd, DevSur Su, float *__restrict__ st,
                                                 int *__restrict__ ist, const float *__restrict__ act,
                                                 float h, int S, float *__restrict__ reward,
                                                 uint8_t *__restrict__ done, uint8_t *__restrict__ events,
