@@ -179,6 +179,51 @@ def test_lockstep_dense_contacts(O, torch):
     assert n_pairs > 0
 
 
+def test_lockstep_cluster_long_contact_lists(O, torch):
+    """Five vehicles at rest in a cluster on a flat world (three abreast 1.5 m
+    apart, two more overlapping their front): the middle vehicle touches its
+    neighbours with more contact points than the one-wave solve keeps in
+    registers (nine), while the world's points fit one wave (at most 64), so
+    the solve takes its list-order tail; the step matches the oracle while
+    the overlaps push the vehicles apart."""
+    from paper_2605_08528_amd import sf
+    w = H.plain_worlds(2, 5)
+    prm = mkparams(collision_warmup=0)
+    xs = [0.0, 0.0, 0.0, 3.4, 3.4]
+    ys = [-1.5, 0.0, 1.5, -0.75, 0.75]
+
+    def cluster(f, k):
+        for wi in range(2):
+            for a in range(5):
+                n = 5 * wi + a
+                f[0, n], f[1, n] = xs[a], ys[a]
+                f[3, n], f[4, n], f[5, n], f[6, n] = 1.0, 0.0, 0.0, 0.0
+                f[7:13, n] = 0.0
+                f[13:17, n] = 0.0
+
+    # the scenario: contact points per body and per world from the pair masks
+    sim = sf.Sim(w, prm, flags=sf.SF_INVINCIBLE | sf.SF_RECORD_CONTACTS)
+    f, k = sim.get_state()
+    cluster(f, k)
+    sim.set_state(f, k)
+    sim.step(cuda(torch, np.zeros((sim.N, 2), np.float32)), 1.0 / 120.0, 1)
+    cnt, pairs = sim.contacts(0)
+    sim.close()
+    for wi in range(2):
+        per_body = np.zeros(5, int)
+        for p in pairs[wi, :cnt[wi]]:
+            m = bin(int(p) >> 16).count("1")
+            per_body[int(p) & 0xFF] += m
+            per_body[(int(p) >> 8) & 0xFF] += m
+        total = per_body.sum() // 2
+        print("contact points per body", per_body.tolist(), "world", total)
+        assert per_body.max() > 9 and total <= 64
+
+    worst, n_pairs = lockstep(O, torch, w, 12, 1.0 / 120.0, 1, prm=prm, flags=sf.SF_INVINCIBLE, init=cluster)
+    print("cluster worst relative error", worst, "pairs", n_pairs)
+    assert n_pairs > 0
+
+
 def test_lockstep_auto_reset(O, torch):
     """Short episodes force timeouts and respawns inside the step."""
     from paper_2605_08528_amd import sf
