@@ -498,6 +498,10 @@ struct AgentTail {
     float gx, gy, sx, sy;
     int since, ep;
 };
+// A world's spawn entries [s0, s0 + M), read with its header.
+struct SpawnRange {
+    int s0, M;
+};
 __device__ __forceinline__ AgentTail load_tail(const float *st, const int *ist, int N, int n) {
     AgentTail a;
     a.gx = st[SF_F_GOAL_X * N + n];
@@ -512,8 +516,8 @@ __device__ __forceinline__ AgentTail load_tail(const float *st, const int *ist, 
 __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld &Wd, float *st, int *ist, int N,
                                              int n, int w, int i, const float (&dyn)[SF_F_MU], float mu_seen,
                                              bool coll, bool nan_act, bool ovf, bool forbid, float2 p0,
-                                             const AgentTail &tl, float *reward, uint8_t *done,
-                                             uint8_t *events) {
+                                             const AgentTail &tl, SpawnRange sr, float *reward,
+                                             uint8_t *done, uint8_t *events) {
     bool finite = true;
     for (int c = 0; c < SF_F_MU; ++c) {
         st[c * N + n] = dyn[c];
@@ -553,7 +557,7 @@ __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld 
     if (dn) {
         if (P.flags & SF_AUTO_RESET) {
             ist[SF_I_EPISODE * N + n] += 1;
-            spawn_agent(P, Wd, st, ist, N, n, w, i);
+            spawn_agent(P, Wd, st, ist, N, n, w, i, sr.s0, sr.M);
         } else {
             // parked off-stage at x = 1000 m at rest (Sec. "Termination and time-out")
             st[SF_F_PX * N + n] = 1000.f;
@@ -622,6 +626,7 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
     __shared__ uint8_t s_coll[SF_MAXA], s_nan[SF_MAXA], s_forbid[SF_MAXA];
     __shared__ float2 s_p0[SF_MAXA];     // positions at the start of the control step
     __shared__ AgentTail s_tail[SF_MAXA];
+    __shared__ SpawnRange s_spawn;
     __shared__ float s_om[4 * SF_MAXA];
     __shared__ float s_wf[6][4 * SF_MAXA];
     __shared__ float s_wmu[4 * SF_MAXA];
@@ -729,6 +734,8 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                 s_tgrid = Wd.tgrid[w];
                 s_anytri = it.w != 0;
                 s_ovf = 0;
+                const int s0 = Wd.soff[w];
+                s_spawn = SpawnRange{s0, Wd.soff[w + 1] - s0};
             }
             if (tid < Wd.S) s_mu[tid] = Wd.mu[w * Wd.S + tid];
             // ---- load the world's agents; decode actions (Sec. "Action Space Details")
@@ -1401,7 +1408,7 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                 dyn[SF_F_STEER] = s_th[i];
                 dyn[SF_F_STEER_RATE] = s_thd[i];
                 finish_agent(P, Wd, st, ist, N, n, w, i, dyn, s_muo[i], s_coll[i] != 0, s_nan[i] != 0, s_ovf != 0,
-                             s_forbid[i] != 0, s_p0[i], s_tail[i], reward, done, events);
+                             s_forbid[i] != 0, s_p0[i], s_tail[i], s_spawn, reward, done, events);
             }
         } while (0);
         if (!queue) break;
@@ -1548,7 +1555,8 @@ __global__ __launch_bounds__(64) void k_step_bicycle(DevParams P, DevWorld Wd, f
         dyn[SF_F_STEER_RATE] = 0.f;
     }
     finish_agent(P, Wd, st, ist, N, n, w, i, dyn, 0.f, s_coll[i] != 0, bad, false, Wd.forbid && Wd.forbid[n],
-                 p0, load_tail(st, ist, N, n), reward, done, events);
+                 p0, load_tail(st, ist, N, n), SpawnRange{Wd.soff[w], Wd.soff[w + 1] - Wd.soff[w]}, reward, done,
+                 events);
 }
 
 void launch_step_bicycle(const DevParams &P, const DevWorld &Wd, float *st, int *ist, const float *act, float dt,

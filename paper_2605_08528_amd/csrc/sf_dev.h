@@ -377,9 +377,9 @@ __device__ __forceinline__ float ttc_swept(const DevParams &P, float px, float p
 
 // Spawn of agent n (world w, world-local slot j) for its current episode:
 // the world's spawn entries rotated by SplitMix64(seed ^ w << 32 ^ episode).
+// spawn entries [s0, s0 + M) of world w
 __device__ __forceinline__ void spawn_agent(const DevParams &P, const DevWorld &Wd, float *st,
-                                            int *ist, int N, int n, int w, int j) {
-    int s0 = Wd.soff[w], M = Wd.soff[w + 1] - s0;
+                                            int *ist, int N, int n, int w, int j, int s0, int M) {
     unsigned long long e = (unsigned long long)(unsigned)ist[SF_I_EPISODE * N + n];
     unsigned long long key = Wd.seed ^ ((unsigned long long)(unsigned)w << 32) ^ e;
     int off = (int)(splitmix64(key) % (unsigned long long)M);
@@ -400,6 +400,10 @@ __device__ __forceinline__ void spawn_agent(const DevParams &P, const DevWorld &
     ist[SF_I_ACTIVE * N + n] = 1;
     ist[SF_I_EP_STEP * N + n] = 0;
     ist[SF_I_SINCE_SPAWN * N + n] = 0;
+}
+__device__ __forceinline__ void spawn_agent(const DevParams &P, const DevWorld &Wd, float *st,
+                                            int *ist, int N, int n, int w, int j) {
+    spawn_agent(P, Wd, st, ist, N, n, w, j, Wd.soff[w], Wd.soff[w + 1] - Wd.soff[w]);
 }
 
 // what the actor-critic's forward pass keeps per row and network for the
