@@ -1169,21 +1169,33 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                         float kx[SW_K], ky[SW_K], krx[SW_K], kry[SW_K], krz[SW_K];
                         const float pbx = b < A ? s_p[0][b] : 0.f, pby = b < A ? s_p[1][b] : 0.f,
                                     pbz = b < A ? s_p[2][b] : 0.f;
+                        // the slots' contact indices first (bit operations only),
+                        // then every slot's reads at once (a slot past the body's
+                        // count reads contact 0 and is zeroed)
 #pragma unroll
                         for (int u = 0; u < SW_K; ++u) {
-                            kc[u] = 0;
-                            kx[u] = ky[u] = krx[u] = kry[u] = krz[u] = 0.f;
-                            if (u < kmax && bm) {
-                                const int c = __ffsll((long long)bm) - 1;
-                                bm &= bm - 1ull;
-                                kc[u] = c;
-                                const bool toward = ((s_cij[c] >> 8) & 0xFF) == b;
-                                kx[u] = toward ? s_cn[0][c] : -s_cn[0][c];
-                                ky[u] = toward ? s_cn[1][c] : -s_cn[1][c];
-                                krx[u] = s_cpc[0][c] - pbx;
-                                kry[u] = s_cpc[1][c] - pby;
-                                krz[u] = s_cpc[2][c] - pbz;
-                            }
+                            kc[u] = bm ? __ffsll((long long)bm) - 1 : 0;
+                            bm &= bm - 1ull;
+                        }
+                        int kij[SW_K];
+#pragma unroll
+                        for (int u = 0; u < SW_K; ++u) {
+                            kij[u] = s_cij[kc[u]];
+                            kx[u] = s_cn[0][kc[u]];
+                            ky[u] = s_cn[1][kc[u]];
+                            krx[u] = s_cpc[0][kc[u]];
+                            kry[u] = s_cpc[1][kc[u]];
+                            krz[u] = s_cpc[2][kc[u]];
+                        }
+                        __builtin_amdgcn_sched_group_barrier(0x100, 6 * SW_K, 0);
+#pragma unroll
+                        for (int u = 0; u < SW_K; ++u) {
+                            const bool in = u < bcnt, toward = ((kij[u] >> 8) & 0xFF) == b;
+                            kx[u] = in ? (toward ? kx[u] : -kx[u]) : 0.f;
+                            ky[u] = in ? (toward ? ky[u] : -ky[u]) : 0.f;
+                            krx[u] = in ? krx[u] - pbx : 0.f;
+                            kry[u] = in ? kry[u] - pby : 0.f;
+                            krz[u] = in ? krz[u] - pbz : 0.f;
                         }
                         // bm now holds the contacts past the first SW_K
                         float ev0 = 0.f, ev1 = 0.f, ew0 = 0.f, ew1 = 0.f, ew2 = 0.f;
@@ -1218,14 +1230,17 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                             }
                             wave_sync();
                             if (bcnt > 0) {
+                                // no branches: a slot past the body's count adds zero
+                                // (its delta is selected to 0, its normal is 0)
                                 float d[SW_K];
 #pragma unroll
-                                for (int u = 0; u < SW_K; ++u) d[u] = u < kmax ? s_cdl[kc[u]] : 0.f;
+                                for (int u = 0; u < SW_K; ++u) d[u] = s_cdl[kc[u]];
                                 float jx = 0.f, jy = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
 #pragma unroll
                                 for (int u = 0; u < SW_K; ++u) {
-                                    if (u < kmax && u < bcnt) {
-                                        const float Jx = d[u] * kx[u], Jy = d[u] * ky[u];
+                                    if (u < kmax) {
+                                        const float du = u < bcnt ? d[u] : 0.f;
+                                        const float Jx = du * kx[u], Jy = du * ky[u];
                                         jx += Jx;
                                         jy += Jy;
                                         tx -= krz[u] * Jy;
