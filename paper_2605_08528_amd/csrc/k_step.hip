@@ -1103,22 +1103,28 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                         // ---- D on one wave: pair k (lane k) takes contact slots from
                         //      the prefix sum of its mask's bits, in list order
                         wave_sync();
-                        const uint32_t pr = lane < np ? s_pairs[lane] : 0u;
-                        const int pcnt = __popc(pr >> 16);
-                        int incl = pcnt;
-#pragma unroll
-                        for (int o = 1; o < 64; o <<= 1) {
-                            const int y = __shfl_up(incl, o, 64);
-                            if (lane >= o) incl += y;
-                        }
-                        const int poff = incl - pcnt;
-                        for (int q = 0; q < pcnt; ++q) s_poff[poff + q] = lane;
-                        if (lane < A) s_bmask[lane] = 0ull;
-                        wave_sync();
                         const bool own = lane < nsw;
-                        const int kq = own ? s_poff[lane] : 0;
-                        const int koff = __shfl(poff, kq, 64);
-                        const uint32_t kpr = __shfl((int)pr, kq, 64);
+                        // all contacts of one pair: the short solve below
+                        const bool one_pair = np == 1 && nsw <= 16;   // a pair has at most 16 points
+                        uint32_t kpr = s_pairs[0];
+                        int koff = 0;
+                        if (!one_pair) {
+                            const uint32_t pr = lane < np ? s_pairs[lane] : 0u;
+                            const int pcnt = __popc(pr >> 16);
+                            int incl = pcnt;
+#pragma unroll
+                            for (int o = 1; o < 64; o <<= 1) {
+                                const int y = __shfl_up(incl, o, 64);
+                                if (lane >= o) incl += y;
+                            }
+                            const int poff = incl - pcnt;
+                            for (int q = 0; q < pcnt; ++q) s_poff[poff + q] = lane;
+                            if (lane < A) s_bmask[lane] = 0ull;
+                            wave_sync();
+                            const int kq = own ? s_poff[lane] : 0;
+                            koff = __shfl(poff, kq, 64);
+                            kpr = __shfl((int)pr, kq, 64);
+                        }
                         int ci = 0, cj = 0;
                         float cnx = 0.f, cny = 0.f, cbb = 0.f, cwk = 0.f, clam = 0.f;
                         f3 cri = mk3(0.f, 0.f, 0.f), crj = cri;
@@ -1132,18 +1138,87 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                             cnx = cp.nx;
                             cny = cp.ny;
                             cbb = cp.b;
-                            s_cn[0][lane] = cp.nx;
-                            s_cn[1][lane] = cp.ny;
-                            s_cpc[0][lane] = cp.px;
-                            s_cpc[1][lane] = cp.py;
-                            s_cpc[2][lane] = cp.pz;
-                            s_cij[lane] = ci | (cj << 8);
                             cri = sub3(mk3(cp.px, cp.py, cp.pz), mk3(s_p[0][ci], s_p[1][ci], s_p[2][ci]));
                             crj = sub3(mk3(cp.px, cp.py, cp.pz), mk3(s_p[0][cj], s_p[1][cj], s_p[2][cj]));
-                            // each body's contacts as a bit set over the list
-                            atomicOr(&s_bmask[ci], 1ull << lane);
-                            atomicOr(&s_bmask[cj], 1ull << lane);
+                            if (!one_pair) {
+                                s_cn[0][lane] = cp.nx;
+                                s_cn[1][lane] = cp.ny;
+                                s_cpc[0][lane] = cp.px;
+                                s_cpc[1][lane] = cp.py;
+                                s_cpc[2][lane] = cp.pz;
+                                s_cij[lane] = ci | (cj << 8);
+                                // each body's contacts as a bit set over the list
+                                atomicOr(&s_bmask[ci], 1ull << lane);
+                                atomicOr(&s_bmask[cj], 1ull << lane);
+                            }
                         }
+                        if (one_pair) {
+                            // ---- F and G for one pair (bodies bi, bj): every contact
+                            //      belongs to both, so the contact lanes keep both
+                            //      bodies' velocities themselves and sum the contacts'
+                            //      impulses across the row, with no trip through LDS
+                            const int bi = s_pairs[0] & 0xFF, bj = (s_pairs[0] >> 8) & 0xFF;
+                            if (own) {
+                                float Ri[9], Rj[9];
+#pragma unroll
+                                for (int q = 0; q < 9; ++q) { Ri[q] = s_R[q][ci]; Rj[q] = s_R[q][cj]; }
+                                const f3 n = mk3(cnx, cny, 0.f);
+                                const f3 xi = cross3(cri, n), xj = cross3(crj, n);
+                                const float keff = 2.f * P.inv_mass + dot3(xi, inv_inertia(P, Ri, xi)) +
+                                                   dot3(xj, inv_inertia(P, Rj, xj));
+                                cwk = 1.f / ((float)nsw * keff);
+                            }
+                            float vix = s_v[0][bi], viy = s_v[1][bi], wix = s_w[0][bi], wiy = s_w[1][bi],
+                                  wiz = s_w[2][bi];
+                            float vjx = s_v[0][bj], vjy = s_v[1][bj], wjx = s_w[0][bj], wjy = s_w[1][bj],
+                                  wjz = s_w[2][bj];
+                            float ii[6], ij[6];
+#pragma unroll
+                            for (int q = 0; q < 6; ++q) { ii[q] = s_iw[q][bi]; ij[q] = s_iw[q][bj]; }
+                            for (int it = 0; it < P.jacobi_iters; ++it) {
+                                float dl = 0.f;
+                                if (own) {
+                                    const f3 wi = cross3(mk3(wix, wiy, wiz), cri);
+                                    const f3 wj = cross3(mk3(wjx, wjy, wjz), crj);
+                                    const float vn = ((vjx + wj.x) - (vix + wi.x)) * cnx + ((vjy + wj.y) - (viy + wi.y)) * cny;
+                                    const float lam1 = fmaxf(clam + cwk * (-vn + cbb), 0.f);
+                                    dl = lam1 - clam;
+                                    clam = lam1;
+                                }
+                                // this contact's impulse on bj (along +n) and on bi (-n),
+                                // with their torques, summed over the pair's contacts
+                                // (at most 16, lanes 0-15: one DPP row) and handed to
+                                // every lane
+                                const float Jx = dl * cnx, Jy = dl * cny;
+                                float sm[8] = {Jx, Jy, -(crj.z * Jy), crj.z * Jx, crj.x * Jy - crj.y * Jx,
+                                               cri.z * Jy, -(cri.z * Jx), -(cri.x * Jy - cri.y * Jx)};
+#pragma unroll
+                                for (int q = 0; q < 8; ++q) sm[q] = row0_sum(sm[q]);
+                                vix -= sm[0] * P.inv_mass;
+                                viy -= sm[1] * P.inv_mass;
+                                wix += ii[0] * sm[5] + ii[1] * sm[6] + ii[2] * sm[7];
+                                wiy += ii[1] * sm[5] + ii[3] * sm[6] + ii[4] * sm[7];
+                                wiz += ii[2] * sm[5] + ii[4] * sm[6] + ii[5] * sm[7];
+                                vjx += sm[0] * P.inv_mass;
+                                vjy += sm[1] * P.inv_mass;
+                                wjx += ij[0] * sm[2] + ij[1] * sm[3] + ij[2] * sm[4];
+                                wjy += ij[1] * sm[2] + ij[3] * sm[3] + ij[4] * sm[4];
+                                wjz += ij[2] * sm[2] + ij[4] * sm[3] + ij[5] * sm[4];
+                            }
+                            if (lane == 0) {
+                                s_v[0][bi] = vix;
+                                s_v[1][bi] = viy;
+                                s_w[0][bi] = wix;
+                                s_w[1][bi] = wiy;
+                                s_w[2][bi] = wiz;
+                                s_v[0][bj] = vjx;
+                                s_v[1][bj] = vjy;
+                                s_w[0][bj] = wjx;
+                                s_w[1][bj] = wjy;
+                                s_w[2][bj] = wjz;
+                            }
+                            wave_sync();
+                        } else {
                         wave_sync();
                         // ---- F: effective mass, relaxed by the larger contact count
                         if (own) {
@@ -1273,6 +1348,7 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                                 s_w[2][b] = ew2;
                             }
                             wave_sync();
+                        }
                         }
                     }
                 } else if (nc > 0) {
@@ -1455,24 +1531,23 @@ void launch_step(const DevParams &P, const DevWorld &Wd, const DevSur &Su, bool 
         grid = Wd.W;
         queue = nullptr;
     }
-    // the network's LDS copy leaves room for at most three wheel waves
-    if (use_sur && block > 256) block = 256;
-#define SF_STEP_LAUNCH(B)                                                                                     \
-    do {                                                                                                      \
-        if (use_sur)                                                                                          \
-            sf_launch(k_step<B, true>, dim3(grid), dim3(B), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done,  \
-                      events, rec, rec_cnt, rec_cap, items, queue);                                           \
-        else                                                                                                  \
-            sf_launch(k_step<B, false>, dim3(grid), dim3(B), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done, \
-                      events, rec, rec_cnt, rec_cap, items, queue);                                           \
-    } while (0)
+    // the surrogate step always takes 256 threads: the network's LDS copy
+    // leaves room for at most three wheel waves, and with fewer a wave's
+    // wheels fill more 32-row network passes (each a chain of products on
+    // one SIMD)
+    if (use_sur) {
+        sf_launch(k_step<256, true>, dim3(grid), dim3(256), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done,
+                  events, rec, rec_cnt, rec_cap, items, queue);
+        return;
+    }
+#define SF_STEP_LAUNCH(B)                                                                                   \
+    sf_launch(k_step<B, false>, dim3(grid), dim3(B), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done, events, \
+              rec, rec_cnt, rec_cap, items, queue)
     if (block <= 64) SF_STEP_LAUNCH(64);
     else if (block <= 128) SF_STEP_LAUNCH(128);
     else if (block <= 192) SF_STEP_LAUNCH(192);
-    else if (block <= 256 || use_sur) SF_STEP_LAUNCH(256);
-    else
-        sf_launch(k_step<320, false>, dim3(grid), dim3(320), 0, s, P, Wd, Su, st, ist, act, h, S, reward, done,
-                  events, rec, rec_cnt, rec_cap, items, queue);
+    else if (block <= 256) SF_STEP_LAUNCH(256);
+    else SF_STEP_LAUNCH(320);
 #undef SF_STEP_LAUNCH
 }
 

@@ -224,6 +224,42 @@ def test_lockstep_cluster_long_contact_lists(O, torch):
     assert n_pairs > 0
 
 
+def test_lockstep_single_pair_many_points(O, torch):
+    """Worlds of two overlapping vehicles at rest (side by side 1.5 m apart,
+    nose to tail 3.4 m apart, and offset on the diagonal): each world's
+    contacts all belong to one pair, with several points, which the solve
+    takes as one pair summed across lanes; the step matches the oracle while
+    the overlaps push the vehicles apart."""
+    from paper_2605_08528_amd import sf
+    w = H.plain_worlds(3, 2)
+    prm = mkparams(collision_warmup=0)
+    second = [(0.0, 1.5), (3.4, 0.0), (3.4, 0.75)]
+
+    def overlap(f, k):
+        for wi in range(3):
+            for a in range(2):
+                n = 2 * wi + a
+                f[0, n], f[1, n] = (0.0, 0.0) if a == 0 else second[wi]
+                f[3, n], f[4, n], f[5, n], f[6, n] = 1.0, 0.0, 0.0, 0.0
+                f[7:13, n] = 0.0
+                f[13:17, n] = 0.0
+
+    sim = sf.Sim(w, prm, flags=sf.SF_INVINCIBLE | sf.SF_RECORD_CONTACTS)
+    f, k = sim.get_state()
+    overlap(f, k)
+    sim.set_state(f, k)
+    sim.step(cuda(torch, np.zeros((sim.N, 2), np.float32)), 1.0 / 120.0, 1)
+    cnt, pairs = sim.contacts(0)
+    sim.close()
+    pts = [bin(int(pairs[wi, 0]) >> 16).count("1") for wi in range(3)]
+    print("pairs per world", cnt[:3].tolist(), "points", pts)
+    assert list(cnt[:3]) == [1, 1, 1] and max(pts) > 4
+
+    worst, n_pairs = lockstep(O, torch, w, 12, 1.0 / 120.0, 1, prm=prm, flags=sf.SF_INVINCIBLE, init=overlap)
+    print("single pair worst relative error", worst, "pairs", n_pairs)
+    assert n_pairs > 0
+
+
 def test_lockstep_auto_reset(O, torch):
     """Short episodes force timeouts and respawns inside the step."""
     from paper_2605_08528_amd import sf
