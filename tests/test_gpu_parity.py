@@ -260,6 +260,42 @@ def test_lockstep_single_pair_many_points(O, torch):
     assert n_pairs > 0
 
 
+def test_lockstep_few_pairs_sharing_bodies(O, torch):
+    """Vehicles at rest abreast 1.5 m apart, each overlapping the next: a
+    chain of three (two pairs sharing the middle vehicle, two more vehicles
+    far off) and a chain of five (four pairs): the solve takes each pair on
+    its own lane row and adds a shared body's rows in order; the step
+    matches the oracle while the overlaps push the vehicles apart."""
+    from paper_2605_08528_amd import sf
+    w = H.plain_worlds(2, 5)
+    prm = mkparams(collision_warmup=0)
+    layout = [[(0.0, 0.0), (0.0, 1.5), (0.0, 3.0), (30.0, 0.0), (60.0, 0.0)],
+              [(0.0, 1.5 * a) for a in range(5)]]
+
+    def chains(f, k):
+        for wi in range(2):
+            for a in range(5):
+                n = 5 * wi + a
+                f[0, n], f[1, n] = layout[wi][a]
+                f[3, n], f[4, n], f[5, n], f[6, n] = 1.0, 0.0, 0.0, 0.0
+                f[7:13, n] = 0.0
+                f[13:17, n] = 0.0
+
+    sim = sf.Sim(w, prm, flags=sf.SF_INVINCIBLE | sf.SF_RECORD_CONTACTS)
+    f, k = sim.get_state()
+    chains(f, k)
+    sim.set_state(f, k)
+    sim.step(cuda(torch, np.zeros((sim.N, 2), np.float32)), 1.0 / 120.0, 1)
+    cnt, pairs = sim.contacts(0)
+    sim.close()
+    print("pairs per world", cnt[:2].tolist())
+    assert list(cnt[:2]) == [2, 4]
+
+    worst, n_pairs = lockstep(O, torch, w, 12, 1.0 / 120.0, 1, prm=prm, flags=sf.SF_INVINCIBLE, init=chains)
+    print("few pairs worst relative error", worst, "pairs", n_pairs)
+    assert n_pairs > 0
+
+
 def test_lockstep_auto_reset(O, torch):
     """Short episodes force timeouts and respawns inside the step."""
     from paper_2605_08528_amd import sf
