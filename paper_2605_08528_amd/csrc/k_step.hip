@@ -605,26 +605,6 @@ __device__ __forceinline__ void finish_agent(const DevParams &P, const DevWorld 
 // registers then stay within 256, so several worlds share a compute unit
 // when the grid has more worlds than units); the learned tire model's LDS
 // copy leaves room for one workgroup a unit anyway.
-// one pair's row sums S (impulse x, y on its second body b; torques about
-// b; torques about its first body a) added to the sums of body x, which
-// takes the impulse with sign -1 as a, +1 as b, nothing otherwise
-__device__ __forceinline__ void pair_sums_add(float (&acc)[5], int x, int a, int b, const float (&S)[8]) {
-    acc[0] += x == a ? -S[0] : x == b ? S[0] : 0.f;
-    acc[1] += x == a ? -S[1] : x == b ? S[1] : 0.f;
-    acc[2] += x == a ? S[5] : x == b ? S[2] : 0.f;
-    acc[3] += x == a ? S[6] : x == b ? S[3] : 0.f;
-    acc[4] += x == a ? S[7] : x == b ? S[4] : 0.f;
-}
-// a body's velocities (v_x, v_y, w_x, w_y, w_z) after the impulse sums s:
-// 1/m on the impulse, the world-frame inverse inertia on the torque
-__device__ __forceinline__ void body_kick(float (&v)[5], const float (&iw)[6], const float (&s)[5], float inv_mass) {
-    v[0] += s[0] * inv_mass;
-    v[1] += s[1] * inv_mass;
-    v[2] += iw[0] * s[2] + iw[1] * s[3] + iw[2] * s[4];
-    v[3] += iw[1] * s[2] + iw[3] * s[3] + iw[4] * s[4];
-    v[4] += iw[2] * s[2] + iw[4] * s[3] + iw[5] * s[4];
-}
-
 template <int BLOCK, bool SUR>
 __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevParams P, DevWorld Wd, DevSur Su, float *__restrict__ st,
                                                 int *__restrict__ ist, const float *__restrict__ act,
@@ -1123,14 +1103,12 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                         // ---- D on one wave: pair k (lane k) takes contact slots from
                         //      the prefix sum of its mask's bits, in list order
                         wave_sync();
-                        // at most four pairs: pair k on DPP row k (lanes 16k..16k+15;
-                        // a pair has at most 16 points), the short solve below
-                        const bool few = np <= 4;
-                        uint32_t kpr = s_pairs[min(lane >> 4, np - 1)];
-                        int koff = lane & ~15;
-                        bool own = (lane >> 4) < np && lane - koff < __popc(kpr >> 16);
-                        if (!few) {
-                            own = lane < nsw;
+                        const bool own = lane < nsw;
+                        // all contacts of one pair: the short solve below
+                        const bool one_pair = np == 1 && nsw <= 16;   // a pair has at most 16 points
+                        uint32_t kpr = s_pairs[0];
+                        int koff = 0;
+                        if (!one_pair) {
                             const uint32_t pr = lane < np ? s_pairs[lane] : 0u;
                             const int pcnt = __popc(pr >> 16);
                             int incl = pcnt;
@@ -1162,7 +1140,7 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                             cbb = cp.b;
                             cri = sub3(mk3(cp.px, cp.py, cp.pz), mk3(s_p[0][ci], s_p[1][ci], s_p[2][ci]));
                             crj = sub3(mk3(cp.px, cp.py, cp.pz), mk3(s_p[0][cj], s_p[1][cj], s_p[2][cj]));
-                            if (!few) {
+                            if (!one_pair) {
                                 s_cn[0][lane] = cp.nx;
                                 s_cn[1][lane] = cp.ny;
                                 s_cpc[0][lane] = cp.px;
@@ -1174,7 +1152,7 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                                 atomicOr(&s_bmask[cj], 1ull << lane);
                             }
                         }
-                        if (few && np == 1) {
+                        if (one_pair) {
                             // ---- F and G for one pair (bodies bi, bj): every contact
                             //      belongs to both, so the contact lanes keep both
                             //      bodies' velocities themselves and sum the contacts'
@@ -1215,7 +1193,7 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                                 float sm[8] = {Jx, Jy, -(crj.z * Jy), crj.z * Jx, crj.x * Jy - crj.y * Jx,
                                                cri.z * Jy, -(cri.z * Jx), -(cri.x * Jy - cri.y * Jx)};
 #pragma unroll
-                                for (int q = 0; q < 8; ++q) sm[q] = rdlane_f(row_scan(sm[q]), 15);
+                                for (int q = 0; q < 8; ++q) sm[q] = row0_sum(sm[q]);
                                 vix -= sm[0] * P.inv_mass;
                                 viy -= sm[1] * P.inv_mass;
                                 wix += ii[0] * sm[5] + ii[1] * sm[6] + ii[2] * sm[7];
@@ -1238,78 +1216,6 @@ __global__ __launch_bounds__(BLOCK, SUR || BLOCK == 64 ? 1 : 2) void k_step(DevP
                                 s_w[0][bj] = wjx;
                                 s_w[1][bj] = wjy;
                                 s_w[2][bj] = wjz;
-                            }
-                            wave_sync();
-                        } else if (few) {
-                            // ---- F and G for two to four pairs: a contact lane keeps
-                            //      its two bodies' velocities itself; a sweep sums each
-                            //      row's impulses and torques by a row scan, and every
-                            //      lane adds the rows that touch its bodies in row order
-                            //      (a body of two pairs gets the same sums on both rows),
-                            //      with no trip through LDS
-                            int ni = 0, nj = 0;
-                            for (int q = 0; q < np; ++q) {
-                                const uint32_t pq = (uint32_t)__builtin_amdgcn_readlane((int)kpr, 16 * q);
-                                const int a = pq & 0xFF, b = (pq >> 8) & 0xFF, cq = __popc(pq >> 16);
-                                ni += (a == ci || b == ci) ? cq : 0;
-                                nj += (a == cj || b == cj) ? cq : 0;
-                            }
-                            if (own) {
-                                float Ri[9], Rj[9];
-#pragma unroll
-                                for (int q = 0; q < 9; ++q) { Ri[q] = s_R[q][ci]; Rj[q] = s_R[q][cj]; }
-                                const f3 n = mk3(cnx, cny, 0.f);
-                                const f3 xi = cross3(cri, n), xj = cross3(crj, n);
-                                const float keff = 2.f * P.inv_mass + dot3(xi, inv_inertia(P, Ri, xi)) +
-                                                   dot3(xj, inv_inertia(P, Rj, xj));
-                                cwk = 1.f / ((float)max(ni, nj) * keff);
-                            }
-                            float vi[5] = {s_v[0][ci], s_v[1][ci], s_w[0][ci], s_w[1][ci], s_w[2][ci]};
-                            float vj[5] = {s_v[0][cj], s_v[1][cj], s_w[0][cj], s_w[1][cj], s_w[2][cj]};
-                            float ii[6], ij[6];
-#pragma unroll
-                            for (int q = 0; q < 6; ++q) { ii[q] = s_iw[q][ci]; ij[q] = s_iw[q][cj]; }
-                            for (int it = 0; it < P.jacobi_iters; ++it) {
-                                float dl = 0.f;
-                                if (own) {
-                                    const f3 wi = cross3(mk3(vi[2], vi[3], vi[4]), cri);
-                                    const f3 wj = cross3(mk3(vj[2], vj[3], vj[4]), crj);
-                                    const float vn = ((vj[0] + wj.x) - (vi[0] + wi.x)) * cnx + ((vj[1] + wj.y) - (vi[1] + wi.y)) * cny;
-                                    const float lam1 = fmaxf(clam + cwk * (-vn + cbb), 0.f);
-                                    dl = lam1 - clam;
-                                    clam = lam1;
-                                }
-                                // this contact's impulse on cj (along +n) and on ci (-n)
-                                // with their torques; lane 16k + 15 ends with row k's sums
-                                const float Jx = dl * cnx, Jy = dl * cny;
-                                float sm[8] = {Jx, Jy, -(crj.z * Jy), crj.z * Jx, crj.x * Jy - crj.y * Jx,
-                                               cri.z * Jy, -(cri.z * Jx), -(cri.x * Jy - cri.y * Jx)};
-#pragma unroll
-                                for (int q = 0; q < 8; ++q) sm[q] = row_scan(sm[q]);
-                                float ai[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, aj[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-                                for (int q = 0; q < np; ++q) {
-                                    const uint32_t pq = (uint32_t)__builtin_amdgcn_readlane((int)kpr, 16 * q);
-                                    const int a = pq & 0xFF, b = (pq >> 8) & 0xFF;
-                                    float S[8];
-#pragma unroll
-                                    for (int k = 0; k < 8; ++k) S[k] = rdlane_f(sm[k], 16 * q + 15);
-                                    pair_sums_add(ai, ci, a, b, S);
-                                    pair_sums_add(aj, cj, a, b, S);
-                                }
-                                body_kick(vi, ii, ai, P.inv_mass);
-                                body_kick(vj, ij, aj, P.inv_mass);
-                            }
-                            if (own && (lane & 15) == 0) {
-                                s_v[0][ci] = vi[0];
-                                s_v[1][ci] = vi[1];
-                                s_w[0][ci] = vi[2];
-                                s_w[1][ci] = vi[3];
-                                s_w[2][ci] = vi[4];
-                                s_v[0][cj] = vj[0];
-                                s_v[1][cj] = vj[1];
-                                s_w[0][cj] = vj[2];
-                                s_w[1][cj] = vj[3];
-                                s_w[2][cj] = vj[4];
                             }
                             wave_sync();
                         } else {

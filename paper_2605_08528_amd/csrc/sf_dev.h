@@ -247,19 +247,15 @@ __device__ __forceinline__ int lane_xor(int v, int m) {
 __device__ __forceinline__ float lane_xor_f(float v, int m) {
     return __int_as_float(lane_xor(__float_as_int(v), m));
 }
-// inclusive prefix sum of v along each 16-lane row: shifts of 1, 2, 4 and 8
-// lanes (a lane with no source adds 0), so lane 16k + 15 ends with row k's
-// total (one fixed order of additions)
-__device__ __forceinline__ float row_scan(float v) {
+// the sum of v over lanes 0-15, in every lane: an inclusive scan along the
+// row by shifts of 1, 2, 4 and 8 lanes (a lane with no source adds 0), then
+// lane 15's total read out (one fixed order of additions)
+__device__ __forceinline__ float row0_sum(float v) {
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));  // row_shr:1
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, false));  // row_shr:2
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, false));  // row_shr:4
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, false));  // row_shr:8
-    return v;
-}
-// the value of v in lane l (l the same in every lane of the wave)
-__device__ __forceinline__ float rdlane_f(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 15));
 }
 
 // ------------------------------------------------------------ activations

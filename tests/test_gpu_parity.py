@@ -263,9 +263,9 @@ def test_lockstep_single_pair_many_points(O, torch):
 def test_lockstep_few_pairs_sharing_bodies(O, torch):
     """Vehicles at rest abreast 1.5 m apart, each overlapping the next: a
     chain of three (two pairs sharing the middle vehicle, two more vehicles
-    far off) and a chain of five (four pairs): the solve takes each pair on
-    its own lane row and adds a shared body's rows in order; the step
-    matches the oracle while the overlaps push the vehicles apart."""
+    far off) and a chain of five (four pairs): the one-wave solve with
+    bodies that hold contacts of two pairs; the step matches the oracle
+    while the overlaps push the vehicles apart."""
     from paper_2605_08528_amd import sf
     w = H.plain_worlds(2, 5)
     prm = mkparams(collision_warmup=0)
